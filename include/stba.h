@@ -1,0 +1,221 @@
+/*
+ * stba.h - C ABI of the MI355X (gfx950) hot path of Stochastic Bundle Adjustment.
+ *
+ * Method: L. Zhou et al., "Stochastic Bundle Adjustment for Efficient and Scalable
+ * 3D Reconstruction", ECCV 2020 (arXiv 2008.00446).  One LM iteration of STBA
+ * (Alg. 1) is: residuals and Jacobian (Sec. 3), the sampled constraint set as
+ * point segments (Sec. 4.1-4.2), the optional steepest-descent correction
+ * (Sec. 4.3), one reduced camera system per camera cluster from the clustered
+ * Schur complement S' = B - E' C'^-1 E'^T (Eq. 10, 13), independent dense
+ * Cholesky solves per cluster (Eq. 13), the physical point update (Eq. 15) and
+ * the accept/reject rule on the FP64 cost (Alg. 1).
+ *
+ * Conventions shared by every entry point
+ *  - Pointers are DEVICE pointers unless the comment says (host).  The caller
+ *    owns all memory; the library never allocates or frees and keeps no global
+ *    state.  Everything it needs between calls lives in the caller's workspace.
+ *  - Calls that take a stream only enqueue work on it and return; they do not
+ *    synchronise (stba_analyze is the one exception and says so).
+ *  - Host-detectable argument errors return an error code before anything is
+ *    enqueued.  Conditions only the device can see (bad ids, unsorted input,
+ *    a cluster matrix that is not positive definite, non-finite values) are
+ *    written to device status words and seen at the caller's next sync.
+ *  - Camera parameters: 9 doubles (w0 w1 w2 t0 t1 t2 f k1 k2): rotation vector,
+ *    translation, focal length, radial distortion.  A point X projects to
+ *    P = R(w) X + t, (x, y) = (P_x, P_y)/P_z, r2 = x^2 + y^2,
+ *    pixel = f (1 + k1 r2 + k2 r2^2)(x, y) (image-centred).  The residual is
+ *    f_o = pixel - observed and the cost F = sum ||f_o||^2 (Sec. 3, no 1/2).
+ *  - Observations are sorted by (point, camera) with at most one observation
+ *    per (camera, point); every point has at least one observation.
+ *  - Per-observation Jacobian blocks are stored observation-major:
+ *    f [q][2], Jc [q][2][9], Jp [q][2][3] (row-major inside an observation).
+ *  - Every call after stba_prepare takes the same (dims, precision, ws, ws_bytes)
+ *    that sized and prepared the workspace; the layout is derived from them.
+ */
+#ifndef STBA_H
+#define STBA_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* precision of residuals, Jacobians and Schur assembly */
+#define STBA_FP64  0   /* everything in FP64 */
+#define STBA_MIXED 1   /* f, J, Hessian blocks and Schur assembly in FP32 with FP32
+                          accumulation; Cholesky, one refinement step of every
+                          cluster solve, point update and cost in FP64 */
+
+/* status codes (int32) */
+#define STBA_OK          0
+#define STBA_EINVAL     -1   /* bad argument (host) or bad id / size (device) */
+#define STBA_ENOTPD     -2   /* a cluster matrix S_k is not positive definite */
+#define STBA_ENONFINITE -3   /* NaN / Inf in a step or cost */
+#define STBA_EWORKSPACE -4   /* workspace too small */
+#define STBA_EHIP       -5   /* a HIP runtime call failed */
+#define STBA_EDATA      -6   /* observations not sorted / duplicated / point unseen */
+
+/* Bundle-adjustment problem: the visibility graph and x = [c; p] (Sec. 3). */
+typedef struct stba_problem {
+    int32_t m;                 /* cameras, >= 1 */
+    int32_t n;                 /* points, >= 1 */
+    int64_t q;                 /* observations, 1 <= q < 2^31 */
+    double *cam;               /* [m][9] FP64 master copy; stba_lm_step updates it on accept */
+    double *pt;                /* [n][3] FP64 master copy; stba_lm_step updates it on accept */
+    const int32_t *obs_cam;    /* [q] camera of each observation */
+    const int32_t *obs_pt;     /* [q] point of each observation, (obs_pt, obs_cam) increasing */
+    const double *obs_uv;      /* [q][2] observed pixel, image-centred */
+} stba_problem;
+
+/* Data-dependent sizes, filled by stba_analyze (host struct). */
+typedef struct stba_dims {
+    int64_t n_pairs;           /* sum over points of v (v + 1) / 2, v = observations of the point */
+    int32_t max_track;         /* largest v */
+    int32_t gamma_max;         /* largest cluster (cameras) the workspace must hold */
+} stba_dims;
+
+/* One draw of the constraint sampler Theta(alpha) (Sec. 4.2). */
+typedef struct stba_sample {
+    const int32_t *cam_cluster; /* [m] cluster of each camera, values in [0, l) */
+    int32_t l;                  /* number of clusters, 1 <= l <= m */
+    int32_t pad0;
+    double alpha;               /* confidence level in (0, 1]; 1 keeps every intra-cluster link */
+    uint64_t seed;              /* Philox4x64-10 key word 0 */
+    uint64_t iter;              /* LM iteration t, Philox counter word 0 */
+} stba_sample;
+
+/* Damping for the standalone assembly call (Eq. 1-4, Sec. 4.3). */
+typedef struct stba_damping {
+    double lambda;              /* LM damping, > 0 */
+    double lambda_corr;         /* correction threshold: correct iff lambda >= lambda_corr (paper: 0.1) */
+} stba_damping;
+
+/* Device-resident LM state updated by stba_lm_step (Alg. 1). */
+typedef struct stba_lm_state {
+    double lambda;              /* current damping */
+    double lambda_corr;         /* correction threshold */
+    double F;                   /* cost at the current x (valid once have_F = 1) */
+    double F_new;               /* cost at the last candidate x + dx (NaN if the step failed) */
+    int32_t accepted;           /* 1 if the last step was accepted */
+    int32_t status;             /* sticky: first device-side error (STBA_* code), 0 if none */
+    int32_t need_jac;           /* 1 if f and J must be evaluated at the current x */
+    int32_t have_F;             /* 1 once F holds the cost at x */
+    int32_t last_status;        /* status of the last step only (0, STBA_ENOTPD, STBA_ENONFINITE) */
+    int32_t pad0;
+    int64_t n_jac;              /* Jacobian evaluations */
+    int64_t n_rcs;              /* RCS builds / solves */
+    int64_t n_accept;           /* accepted steps */
+} stba_lm_state;
+
+/* Views into the workspace written by stba_build_cluster_rcs (read-only for
+ * the caller, valid until the workspace is reused).  All device pointers. */
+typedef struct stba_rcs {
+    const double *S;            /* concatenated cluster matrices, column-major, padded to Np_k */
+    const int64_t *S_off;       /* [l+1] offset (doubles) of cluster k's matrix in S */
+    const int32_t *cl_n;        /* [l] cameras in cluster k */
+    const int32_t *cl_Np;       /* [l] padded order of S_k (multiple of 32, >= 9 cl_n[k]) */
+    const int32_t *cl_start;    /* [l+1] offset of cluster k in cl_cams */
+    const int32_t *cl_cams;     /* [m] cameras grouped by cluster, ascending id inside a cluster */
+    const int32_t *cam_local;   /* [m] index of each camera inside its cluster */
+    const double *b;            /* [m][9] right-hand side b' = v' - E' C'^-1 w' (Eq. 13) */
+    const int32_t *seg_head;    /* [q] sampled segment of each observation, named by its first
+                                   observation (smallest camera) - the bound virtual point */
+    int32_t l;
+    int32_t precision;
+} stba_rcs;
+
+/* ---- set-up ------------------------------------------------------------ */
+
+/* Size of the device scratch buffer stba_analyze needs (bytes, host, pure). */
+size_t stba_analyze_scratch_bytes(void);
+
+/* Check the observation arrays and measure the data-dependent sizes (Sec. 3's
+ * visibility graph).  SYNCHRONISES `stream`.  d_scratch: device buffer of at
+ * least stba_analyze_scratch_bytes().  dims (host) receives n_pairs and
+ * max_track; dims->gamma_max is left untouched.  Returns STBA_EDATA if the
+ * observations are unsorted, duplicated, out of range or a point is unseen. */
+int stba_analyze(const stba_problem *p, void *d_scratch, stba_dims *dims, hipStream_t stream);
+
+/* Workspace bytes for a problem, its dims (dims->gamma_max = largest cluster
+ * that will be passed) and a precision.  Host, pure; 0 on bad arguments. */
+size_t stba_workspace_bytes(const stba_problem *p, const stba_dims *dims, int precision);
+
+/* Build the static plan in the workspace: per-point offsets and the list of
+ * observation pairs (same point) grouped by camera pair, which is the sparsity
+ * of E C^-1 E^T (Eq. 5).  Must be called once before the per-iteration calls;
+ * asynchronous.  ws must be 256-byte aligned. */
+int stba_prepare(const stba_problem *p, const stba_dims *dims, int precision, void *ws,
+                 size_t ws_bytes, hipStream_t stream);
+
+/* ---- per-iteration calls (all asynchronous, graph-capturable) ---------- */
+
+/* Residuals f and Jacobian blocks J_c, J_p of every observation (Sec. 3, Alg. 1).
+ * precision selects the element type of f, Jc, Jp (double or float).  Jc and Jp
+ * may both be NULL (residuals only).  cost (nullable, device double) receives
+ * F = sum ||f||^2 computed in FP64.  Uses the workspace for partial sums. */
+int stba_residual_jacobian(const stba_problem *p, const stba_dims *dims, int precision, void *f, void *Jc,
+                           void *Jp, double *cost, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Assemble one reduced camera system per cluster (Eq. 10, 13; Alg. 1): draw the
+ * sampled constraints as point segments, form the segment blocks C', E', the
+ * corrected gradient when lambda >= lambda_corr (Sec. 4.3), then
+ * S_k = B_k - E'_k C'^-1 E'_k^T (lower triangle, FP64 storage) and
+ * b' = v' - E' C'^-1 w'.  f, Jc, Jp are the outputs of stba_residual_jacobian in
+ * the same precision.  out (host) receives views into the workspace.  The
+ * per-point blocks needed by stba_solve_clusters are kept in the workspace. */
+int stba_build_cluster_rcs(const stba_problem *p, const stba_dims *dims, const stba_sample *s,
+                           const stba_damping *d, int precision, const void *f, const void *Jc, const void *Jp,
+                           stba_rcs *out, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Solve every S_k dc_k = b_k by dense FP64 Cholesky (Eq. 13; plus one FP64
+ * refinement step in STBA_MIXED), then the point step
+ * dp_j = C_j^-1 (w_j - sum_o W_o^T dc) with the physical blocks (Eq. 15).
+ * Jc, Jp: the Jacobian passed to stba_build_cluster_rcs.  dcam [m][9], dpt [n][3]
+ * (device, FP64).  cluster_status (device int32 [l], nullable): STBA_OK or
+ * STBA_ENOTPD per cluster.  The factorisation overwrites S in the workspace. */
+int stba_solve_clusters(const stba_problem *p, const stba_dims *dims, const stba_rcs *rcs, int precision,
+                        const void *Jc, const void *Jp, double *dcam, double *dpt,
+                        int32_t *cluster_status, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Initialise a device stba_lm_state (lambda0, lambda_corr, need_jac = 1). */
+int stba_lm_init(stba_lm_state *st, double lambda0, double lambda_corr, hipStream_t stream);
+
+/* One full STBA LM iteration (Alg. 1, one pass of the loop) for the given
+ * cluster map: residuals/Jacobian (only when x changed), cluster RCS, solves,
+ * point update, candidate cost, accept iff F(x+dx) < F(x) strictly, the step is
+ * finite and every S_k factorised; then lambda /= 3 and x += dx, else lambda *= 3.
+ * Every decision is taken on the device; no host synchronisation. */
+int stba_lm_step(const stba_problem *p, const stba_dims *dims, const stba_sample *s, stba_lm_state *st,
+                 int precision, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Same as stba_lm_step, recording events[k] before phase k and events[STBA_NUM_PHASES]
+ * after the last (host array of STBA_NUM_PHASES + 1 created hipEvent_t) so that a
+ * caller can time each kernel of the iteration on `stream`. */
+#define STBA_NUM_PHASES 9
+int stba_lm_step_profiled(const stba_problem *p, const stba_dims *dims, const stba_sample *s,
+                          stba_lm_state *st, int precision, void *ws, size_t ws_bytes, hipStream_t stream,
+                          hipEvent_t *events);
+
+/* Name of phase k of stba_lm_step_profiled (static string, host). */
+const char *stba_phase_name(int k);
+
+/* ---- differentiation (residuals as a differentiable function) ----------- */
+
+/* J^T v for a cotangent v [q][2] of the residuals (FP32 or FP64 per precision):
+ * grad_cam[m][9] = sum_o J_c,o^T v_o, grad_pt[n][3] = sum_o J_p,o^T v_o and
+ * grad_uv[q][2] = -v_o.  J is recomputed from cam and pt (nothing stored).
+ * Outputs are written (not accumulated) in the same precision as v; the per-camera
+ * and per-point sums use fixed-order segmented reductions.  Requires stba_prepare. */
+int stba_residual_vjp(const stba_problem *p, const stba_dims *dims, int precision, const void *v,
+                      void *grad_cam, void *grad_pt, void *grad_uv, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Library version string (host). */
+const char *stba_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STBA_H */

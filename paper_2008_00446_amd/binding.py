@@ -1,0 +1,242 @@
+"""ctypes binding of libstba.so: the C ABI in include/stba.h under the same names.
+
+Argument marshalling only: every call passes device pointers (torch CUDA/HIP
+tensors' data_ptr()) and the current HIP stream to the library.  There is no
+fallback: if the shared library is missing or a call fails, an exception is
+raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libstba.so")
+
+STBA_FP64 = 0
+STBA_MIXED = 1
+STBA_NUM_PHASES = 9
+STATUS_NAMES = {0: "STBA_OK", -1: "STBA_EINVAL", -2: "STBA_ENOTPD", -3: "STBA_ENONFINITE",
+                -4: "STBA_EWORKSPACE", -5: "STBA_EHIP", -6: "STBA_EDATA"}
+
+
+class StbaError(RuntimeError):
+    def __init__(self, fn, code):
+        super().__init__(f"{fn} returned {code} ({STATUS_NAMES.get(code, '?')})")
+        self.code = code
+
+
+class StbaProblem(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("n", ctypes.c_int32), ("q", ctypes.c_int64),
+                ("cam", ctypes.c_void_p), ("pt", ctypes.c_void_p), ("obs_cam", ctypes.c_void_p),
+                ("obs_pt", ctypes.c_void_p), ("obs_uv", ctypes.c_void_p)]
+
+
+class StbaDims(ctypes.Structure):
+    _fields_ = [("n_pairs", ctypes.c_int64), ("max_track", ctypes.c_int32), ("gamma_max", ctypes.c_int32)]
+
+
+class StbaSample(ctypes.Structure):
+    _fields_ = [("cam_cluster", ctypes.c_void_p), ("l", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("alpha", ctypes.c_double), ("seed", ctypes.c_uint64), ("iter", ctypes.c_uint64)]
+
+
+class StbaDamping(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_double), ("lambda_corr", ctypes.c_double)]
+
+
+class StbaLmState(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_double), ("lambda_corr", ctypes.c_double), ("F", ctypes.c_double),
+                ("F_new", ctypes.c_double), ("accepted", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("need_jac", ctypes.c_int32), ("have_F", ctypes.c_int32), ("last_status", ctypes.c_int32),
+                ("pad0", ctypes.c_int32), ("n_jac", ctypes.c_int64), ("n_rcs", ctypes.c_int64),
+                ("n_accept", ctypes.c_int64)]
+
+
+class StbaRcs(ctypes.Structure):
+    _fields_ = [("S", ctypes.c_void_p), ("S_off", ctypes.c_void_p), ("cl_n", ctypes.c_void_p),
+                ("cl_Np", ctypes.c_void_p), ("cl_start", ctypes.c_void_p), ("cl_cams", ctypes.c_void_p),
+                ("cam_local", ctypes.c_void_p), ("b", ctypes.c_void_p), ("seg_head", ctypes.c_void_p),
+                ("l", ctypes.c_int32),
+                ("precision", ctypes.c_int32)]
+
+
+_P = ctypes.c_void_p
+_SIGS = {
+    "stba_version": (ctypes.c_char_p, []),
+    "stba_phase_name": (ctypes.c_char_p, [ctypes.c_int]),
+    "stba_analyze_scratch_bytes": (ctypes.c_size_t, []),
+    "stba_analyze": (ctypes.c_int, [_P, _P, _P, _P]),
+    "stba_workspace_bytes": (ctypes.c_size_t, [_P, _P, ctypes.c_int]),
+    "stba_prepare": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, ctypes.c_size_t, _P]),
+    "stba_residual_jacobian": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "stba_build_cluster_rcs": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, _P, _P, _P, _P, _P,
+                                              ctypes.c_size_t, _P]),
+    "stba_solve_clusters": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "stba_lm_init": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double, _P]),
+    "stba_lm_step": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, _P, ctypes.c_size_t, _P]),
+    "stba_lm_step_profiled": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, _P, ctypes.c_size_t, _P, _P]),
+    "stba_residual_vjp": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libstba.so (built by paper_2008_00446_amd.build); raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libstba.so not found at {path}; build it with `python -m paper_2008_00446_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(fn, rc):
+    if rc != 0:
+        raise StbaError(fn, rc)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("STBA calls take device tensors")
+    if not t.is_contiguous():
+        raise ValueError("STBA calls take contiguous tensors")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ref(struct):
+    return ctypes.byref(struct)
+
+
+# ---------------------------------------------------------------------------
+# argument structs from tensors
+# ---------------------------------------------------------------------------
+
+def make_problem(cam, pt, obs_cam, obs_pt, obs_uv) -> StbaProblem:
+    """stba_problem from device tensors: cam [m,9] f64, pt [n,3] f64, obs_cam/obs_pt [q] int32, obs_uv [q,2] f64."""
+    assert cam.dtype == torch.float64 and pt.dtype == torch.float64 and obs_uv.dtype == torch.float64
+    assert obs_cam.dtype == torch.int32 and obs_pt.dtype == torch.int32
+    assert cam.shape[1] == 9 and pt.shape[1] == 3 and obs_uv.shape[1] == 2
+    p = StbaProblem(cam.shape[0], pt.shape[0], obs_cam.shape[0], _ptr(cam), _ptr(pt), _ptr(obs_cam),
+                    _ptr(obs_pt), _ptr(obs_uv))
+    p._keep = (cam, pt, obs_cam, obs_pt, obs_uv)
+    return p
+
+
+def make_sample(cam_cluster, l, alpha=1.0, seed=0, it=0) -> StbaSample:
+    assert cam_cluster.dtype == torch.int32
+    s = StbaSample(_ptr(cam_cluster), int(l), 0, float(alpha), int(seed), int(it))
+    s._keep = cam_cluster
+    return s
+
+
+# ---------------------------------------------------------------------------
+# the ABI under its own names
+# ---------------------------------------------------------------------------
+
+def stba_version() -> str:
+    return load_library().stba_version().decode()
+
+
+def stba_phase_name(k: int) -> str:
+    return load_library().stba_phase_name(k).decode()
+
+
+def stba_analyze_scratch_bytes() -> int:
+    return int(load_library().stba_analyze_scratch_bytes())
+
+
+def stba_analyze(problem: StbaProblem, stream=None) -> StbaDims:
+    lib = load_library()
+    scratch = torch.empty(stba_analyze_scratch_bytes(), dtype=torch.uint8, device="cuda")
+    dims = StbaDims(0, 0, 0)
+    _check("stba_analyze", lib.stba_analyze(_ref(problem), _ptr(scratch), _ref(dims), _stream(stream)))
+    return dims
+
+
+def stba_workspace_bytes(problem: StbaProblem, dims: StbaDims, precision: int) -> int:
+    n = load_library().stba_workspace_bytes(_ref(problem), _ref(dims), precision)
+    if n == 0:
+        raise StbaError("stba_workspace_bytes", -1)
+    return int(n)
+
+
+def alloc_workspace(nbytes: int) -> torch.Tensor:
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + nbytes]
+
+
+def stba_prepare(problem, dims, precision, ws, stream=None):
+    _check("stba_prepare", load_library().stba_prepare(_ref(problem), _ref(dims), precision, _ptr(ws),
+                                                       ws.numel(), _stream(stream)))
+
+
+def stba_residual_jacobian(problem, dims, precision, f, Jc, Jp, cost, ws, stream=None):
+    _check("stba_residual_jacobian", load_library().stba_residual_jacobian(
+        _ref(problem), _ref(dims), precision, _ptr(f), _ptr(Jc), _ptr(Jp), _ptr(cost), _ptr(ws), ws.numel(),
+        _stream(stream)))
+
+
+def stba_build_cluster_rcs(problem, dims, sample, damping, precision, f, Jc, Jp, ws, stream=None) -> StbaRcs:
+    out = StbaRcs()
+    _check("stba_build_cluster_rcs", load_library().stba_build_cluster_rcs(
+        _ref(problem), _ref(dims), _ref(sample), _ref(damping), precision, _ptr(f), _ptr(Jc), _ptr(Jp),
+        _ref(out), _ptr(ws), ws.numel(), _stream(stream)))
+    return out
+
+
+def stba_solve_clusters(problem, dims, rcs, precision, Jc, Jp, dcam, dpt, cluster_status, ws, stream=None):
+    _check("stba_solve_clusters", load_library().stba_solve_clusters(
+        _ref(problem), _ref(dims), _ref(rcs), precision, _ptr(Jc), _ptr(Jp), _ptr(dcam), _ptr(dpt),
+        _ptr(cluster_status), _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def stba_lm_init(state, lambda0, lambda_corr=0.1, stream=None):
+    _check("stba_lm_init", load_library().stba_lm_init(_ptr(state), float(lambda0), float(lambda_corr),
+                                                       _stream(stream)))
+
+
+def stba_lm_step(problem, dims, sample, state, precision, ws, stream=None):
+    _check("stba_lm_step", load_library().stba_lm_step(_ref(problem), _ref(dims), _ref(sample), _ptr(state),
+                                                       precision, _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def stba_lm_step_profiled(problem, dims, sample, state, precision, ws, events, stream=None):
+    """events: a ctypes array of STBA_NUM_PHASES + 1 hipEvent_t handles."""
+    _check("stba_lm_step_profiled", load_library().stba_lm_step_profiled(
+        _ref(problem), _ref(dims), _ref(sample), _ptr(state), precision, _ptr(ws), ws.numel(),
+        _stream(stream), ctypes.cast(events, ctypes.c_void_p)))
+
+
+def stba_residual_vjp(problem, dims, precision, v, grad_cam, grad_pt, grad_uv, ws, stream=None):
+    _check("stba_residual_vjp", load_library().stba_residual_vjp(
+        _ref(problem), _ref(dims), precision, _ptr(v), _ptr(grad_cam), _ptr(grad_pt), _ptr(grad_uv), _ptr(ws),
+        ws.numel(), _stream(stream)))
+
+
+def read_state(state: torch.Tensor) -> dict:
+    """Copy a device stba_lm_state to the host (synchronising) as a dict."""
+    raw = state.cpu().numpy().tobytes()
+    s = StbaLmState.from_buffer_copy(raw[:ctypes.sizeof(StbaLmState)])
+    return {name: getattr(s, name) for name, _ in StbaLmState._fields_ if not name.startswith("pad")}
+
+
+def new_state(device="cuda") -> torch.Tensor:
+    return torch.zeros(ctypes.sizeof(StbaLmState), dtype=torch.uint8, device=device)

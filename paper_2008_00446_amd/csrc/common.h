@@ -1,0 +1,44 @@
+// Shared device/host definitions of the STBA gfx950 library (internal header).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <math.h>
+
+#include "stba.h"
+
+namespace stba {
+
+constexpr int kNB = 32;            // Cholesky tile order (FP64)
+constexpr int kObsRec = 32;        // per-observation record written by the point kernel:
+                                   //   Y[9][3] (27), M (m00 m01 m11), r (2)
+constexpr int kMaxCamsForClusters = 16384;   // single-workgroup cluster layout limit (LDS keys)
+
+// Status words kept in the workspace (int32[16]).
+enum StatusWord : int {
+    kStSticky = 0,       // first device-side data error (STBA_EINVAL / STBA_EDATA)
+    kStJacRan = 1,       // 1 if the residual/Jacobian kernel ran in this iteration
+    kStPointBad = 2,     // a segment block V*_s failed to factorise
+    kStCount = 16,
+};
+
+__host__ __device__ inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+__device__ inline void set_status(int32_t *w, int code) {
+    atomicCAS(reinterpret_cast<int *>(w), 0, code);
+}
+
+// Deterministic fixed-order sum over a 256-thread block (LDS tree).
+__device__ inline double block_sum_256(double v, double *sh) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s) sh[t] += sh[t + s];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+}  // namespace stba

@@ -1,0 +1,838 @@
+// Per-iteration kernels of one STBA LM iteration (Alg. 1) on gfx950, except the
+// cluster Cholesky (chol.hip).  Every kernel reads its sizes and the LM state
+// from device memory so an iteration can be captured in a HIP graph.
+#include "camera.h"
+#include "kernels.h"
+#include "philox.h"
+
+namespace stba {
+
+namespace {
+
+inline unsigned grid_for(int64_t count, int bs = 256) { return (unsigned)((count + bs - 1) / bs); }
+
+// ---------------------------------------------------------------------------
+// cluster layout: cameras grouped by cluster (ascending id inside a cluster),
+// per-cluster sizes, padded orders and offsets of S_k (Eq. 13).
+// One 1024-thread workgroup; bitonic sort of (cluster, camera) keys in LDS.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_clusters(const int32_t *cam_cluster, int32_t m, int32_t l,
+                                                   int32_t gamma_max, int32_t *cl_n, int32_t *cl_Np,
+                                                   int32_t *cl_start, int32_t *cl_cams, int32_t *cam_local,
+                                                   int64_t *S_off, int32_t *status) {
+    __shared__ uint32_t keys[kMaxCamsForClusters];
+    __shared__ int64_t part[1024];
+    __shared__ int bad;
+    const int tid = threadIdx.x;
+    int P = 1;
+    while (P < m) P <<= 1;
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    for (int i = tid; i < P; i += 1024) {
+        uint32_t key = 0xFFFFFFFFu;
+        if (i < m) {
+            int k = cam_cluster[i];
+            if (k < 0 || k >= l) {
+                bad = 1;
+                k = 0;
+            }
+            key = ((uint32_t)k << 15) | (uint32_t)i;
+        }
+        keys[i] = key;
+    }
+    __syncthreads();
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = tid; i < (P >> 1); i += 1024) {
+                const int lo = 2 * stride * (i / stride) + (i % stride);
+                const int hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const uint32_t a = keys[lo], b = keys[hi];
+                if ((a > b) == up) {
+                    keys[lo] = b;
+                    keys[hi] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int k = tid; k <= l; k += 1024) {
+        int lo = 0, hi = m;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if ((int)(keys[mid] >> 15) < k) lo = mid + 1; else hi = mid;
+        }
+        cl_start[k] = lo;
+    }
+    for (int p = tid; p < m; p += 1024) cl_cams[p] = (int32_t)(keys[p] & 0x7FFFu);
+    __syncthreads();
+    for (int p = tid; p < m; p += 1024) {
+        const int32_t cam = (int32_t)(keys[p] & 0x7FFFu);
+        cam_local[cam] = p - cl_start[keys[p] >> 15];
+    }
+    for (int k = tid; k < l; k += 1024) {
+        const int nk = cl_start[k + 1] - cl_start[k];
+        if (nk > gamma_max) bad = 2;
+        cl_n[k] = nk;
+        cl_Np[k] = (int32_t)round_up(9 * (int64_t)nk, kNB);
+    }
+    __syncthreads();
+    if (bad) {
+        // nothing is assembled or solved for an invalid map; the step is rejected
+        for (int k = tid; k < l; k += 1024) {
+            cl_n[k] = 0;
+            cl_Np[k] = 0;
+        }
+        if (tid == 0) set_status(status + kStSticky, STBA_EINVAL);
+    }
+    __syncthreads();
+    // exclusive scan of Np^2 over clusters
+    const int chunk = (l + 1023) / 1024;
+    const int k0 = tid * chunk, k1 = min(l, k0 + chunk);
+    int64_t s = 0;
+    for (int k = k0; k < k1; ++k) s += (int64_t)cl_Np[k] * cl_Np[k];
+    part[tid] = s;
+    __syncthreads();
+    if (tid == 0) {
+        int64_t run = 0;
+        for (int t = 0; t < 1024; ++t) {
+            const int64_t v = part[t];
+            part[t] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    s = part[tid];
+    for (int k = k0; k < k1; ++k) {
+        S_off[k] = s;
+        s += (int64_t)cl_Np[k] * cl_Np[k];
+    }
+    if (k0 < l && k1 == l) S_off[l] = s;
+}
+
+__global__ void k_reset_status(int32_t *status) {
+    if (threadIdx.x < kStCount) status[threadIdx.x] = 0;
+}
+
+__global__ void k_lm_init(stba_lm_state *st, double lambda0, double lambda_corr) {
+    st->lambda = lambda0;
+    st->lambda_corr = lambda_corr;
+    st->F = 0.0;
+    st->F_new = __builtin_nan("");
+    st->accepted = 0;
+    st->status = 0;
+    st->need_jac = 1;
+    st->have_F = 0;
+    st->last_status = 0;
+    st->pad0 = 0;
+    st->n_jac = 0;
+    st->n_rcs = 0;
+    st->n_accept = 0;
+}
+
+// ---------------------------------------------------------------------------
+// a1: residuals and Jacobian blocks, one thread per observation (Sec. 3).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_rj(int64_t q, const double *__restrict__ cam, const double *__restrict__ pt,
+                                            const int32_t *__restrict__ oc, const int32_t *__restrict__ op,
+                                            const double *__restrict__ uv, T *__restrict__ f, T *__restrict__ Jc,
+                                            T *__restrict__ Jp, double *__restrict__ partials,
+                                            const int32_t *need_jac, int32_t *jac_ran) {
+    __shared__ double sh[256];
+    if (need_jac != nullptr && need_jac[0] == 0) return;
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double sq = 0.0;
+    if (o < q) {
+        const int32_t i = oc[o], j = op[o];
+        double c[9], X[3];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) c[k] = cam[9 * (int64_t)i + k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) X[k] = pt[3 * (int64_t)j + k];
+        double pix[2], jc[2][9], jp[2][3];
+        camera_project_jac(c, X, pix, jc, jp);
+        const double f0 = pix[0] - uv[2 * o], f1 = pix[1] - uv[2 * o + 1];
+        f[2 * o] = (T)f0;
+        f[2 * o + 1] = (T)f1;
+        sq = f0 * f0 + f1 * f1;
+        if (Jc != nullptr) {
+            T *dc = Jc + 18 * o;
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+#pragma unroll
+                for (int k = 0; k < 9; ++k) dc[9 * r + k] = (T)jc[r][k];
+        }
+        if (Jp != nullptr) {
+            T *dp = Jp + 6 * o;
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) dp[3 * r + k] = (T)jp[r][k];
+        }
+    }
+    if (partials != nullptr) {
+        const double s = block_sum_256(sq, sh);
+        if (threadIdx.x == 0) partials[blockIdx.x] = s;
+    }
+    if (jac_ran != nullptr && blockIdx.x == 0 && threadIdx.x == 0) jac_ran[0] = 1;
+}
+
+// Fixed-order sum of per-block partials (one 256-thread block).
+__global__ __launch_bounds__(256) void k_sum_partials(const double *partials, int64_t count, double *out) {
+    __shared__ double sh[256];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < count; i += 256) s += partials[i];
+    s = block_sum_256(s, sh);
+    if (threadIdx.x == 0) out[0] = s;
+}
+
+__global__ __launch_bounds__(256) void k_init_cost(const double *partials, int64_t count, stba_lm_state *st) {
+    __shared__ double sh[256];
+    if (!(st->need_jac && !st->have_F)) return;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < count; i += 256) s += partials[i];
+    s = block_sum_256(s, sh);
+    if (threadIdx.x == 0) {
+        st->F = s;
+        st->have_F = 1;
+    }
+}
+
+__global__ void k_set_damping(double *slot, double lambda, double lambda_corr) {
+    slot[0] = lambda;
+    slot[1] = lambda_corr;
+}
+
+// ---------------------------------------------------------------------------
+// 3x3 symmetric positive definite helpers (upper Cholesky V = R^T R)
+// packed symmetric order: 00 01 02 11 12 22
+// ---------------------------------------------------------------------------
+struct Chol3 {
+    double R00, R01, R02, R11, R12, R22;   // R
+    double I00, I01, I02, I11, I12, I22;   // R^-1 (upper)
+    bool ok;
+};
+
+__device__ inline Chol3 chol3(const double V[6]) {
+    Chol3 c;
+    c.ok = true;
+    double d = V[0];
+    if (!(d > 0.0)) { c.ok = false; d = 1.0; }
+    c.R00 = sqrt(d);
+    c.R01 = V[1] / c.R00;
+    c.R02 = V[2] / c.R00;
+    d = V[3] - c.R01 * c.R01;
+    if (!(d > 0.0)) { c.ok = false; d = 1.0; }
+    c.R11 = sqrt(d);
+    c.R12 = (V[4] - c.R01 * c.R02) / c.R11;
+    d = V[5] - c.R02 * c.R02 - c.R12 * c.R12;
+    if (!(d > 0.0)) { c.ok = false; d = 1.0; }
+    c.R22 = sqrt(d);
+    c.I00 = 1.0 / c.R00;
+    c.I11 = 1.0 / c.R11;
+    c.I22 = 1.0 / c.R22;
+    c.I01 = -c.R01 * c.I00 * c.I11;
+    c.I12 = -c.R12 * c.I11 * c.I22;
+    c.I02 = -(c.R01 * c.I12 + c.R02 * c.I22) * c.I00;
+    return c;
+}
+
+// V^-1 = R^-1 R^-T, packed
+__device__ inline void chol3_inverse(const Chol3 &c, double Vi[6]) {
+    Vi[0] = c.I00 * c.I00 + c.I01 * c.I01 + c.I02 * c.I02;
+    Vi[1] = c.I01 * c.I11 + c.I02 * c.I12;
+    Vi[2] = c.I02 * c.I22;
+    Vi[3] = c.I11 * c.I11 + c.I12 * c.I12;
+    Vi[4] = c.I12 * c.I22;
+    Vi[5] = c.I22 * c.I22;
+}
+
+__device__ inline void sym3_mul(const double S[6], const double x[3], double y[3]) {
+    y[0] = S[0] * x[0] + S[1] * x[1] + S[2] * x[2];
+    y[1] = S[1] * x[0] + S[3] * x[1] + S[4] * x[2];
+    y[2] = S[2] * x[0] + S[4] * x[1] + S[5] * x[2];
+}
+
+template <typename T>
+__device__ inline void load_jp(const T *Jp, int64_t o, double jp[6]) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) jp[k] = (double)Jp[6 * o + k];
+}
+
+// ---------------------------------------------------------------------------
+// a0 + a2 + a3: per point, the sampled segments (point splitting and binding,
+// Sec. 4.1-4.2), segment blocks V_s = sum J_p^T J_p and w'_s = -sum J_p^T f,
+// the steepest-descent correction when lambda >= lambda_corr (Sec. 4.3), and
+// the per-observation record used by the Schur assembly:
+//   Y_o = W_o R_s^-1 (W_o = J_c,o^T J_p,o, R_s^T R_s = V*_s), so that
+//   W_o V*_s^-1 W_o'^T = Y_o Y_o'^T (Eq. 10),
+//   M_o = I - J_p,o V*_s^-1 J_p,o^T and r_o = f_o + J_p,o V*_s^-1 w'_s, so that
+//   S_ii = sum J_c^T M J_c + lambda diag(U_i) and b_i = -sum J_c^T r.
+// Also the physical damped V*_j^-1 and w_j for the point update (Eq. 15).
+// One thread per point.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_points(int32_t n, const int64_t *__restrict__ pt_off,
+                                                const int32_t *__restrict__ obs_cam,
+                                                const int32_t *__restrict__ cam_cluster, const T *__restrict__ f,
+                                                const T *__restrict__ Jc, const T *__restrict__ Jp,
+                                                const double *__restrict__ lam2, uint64_t seed, uint64_t t,
+                                                uint64_t thr, int32_t *__restrict__ seg_head, T *__restrict__ obsd,
+                                                double *__restrict__ Vinv, double *__restrict__ wph,
+                                                int32_t *status) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const double lam = lam2[0];
+    const bool corr = lam >= lam2[1];
+    const int64_t p0 = pt_off[j], p1 = pt_off[j + 1];
+    // segment heads: the chain of a cluster follows camera order, which is storage order
+    for (int64_t a = p0; a < p1; ++a) {
+        const int32_t ca = obs_cam[a];
+        const int32_t ka = cam_cluster[ca];
+        int64_t pred = -1;
+        for (int64_t b = a - 1; b >= p0; --b) {
+            if (cam_cluster[obs_cam[b]] == ka) {
+                pred = b;
+                break;
+            }
+        }
+        int32_t h = (int32_t)a;
+        if (pred >= 0 && keep_link(seed, t, (uint64_t)j, (uint64_t)ca, thr)) h = seg_head[pred];
+        seg_head[a] = h;
+    }
+    // physical blocks
+    double V[6] = {0, 0, 0, 0, 0, 0}, w[3] = {0, 0, 0};
+    for (int64_t a = p0; a < p1; ++a) {
+        double jp[6];
+        load_jp(Jp, a, jp);
+        const double f0 = (double)f[2 * a], f1 = (double)f[2 * a + 1];
+        V[0] += jp[0] * jp[0] + jp[3] * jp[3];
+        V[1] += jp[0] * jp[1] + jp[3] * jp[4];
+        V[2] += jp[0] * jp[2] + jp[3] * jp[5];
+        V[3] += jp[1] * jp[1] + jp[4] * jp[4];
+        V[4] += jp[1] * jp[2] + jp[4] * jp[5];
+        V[5] += jp[2] * jp[2] + jp[5] * jp[5];
+        w[0] -= jp[0] * f0 + jp[3] * f1;
+        w[1] -= jp[1] * f0 + jp[4] * f1;
+        w[2] -= jp[2] * f0 + jp[5] * f1;
+    }
+    bool ok = true;
+    {
+        double Vd[6] = {V[0] * (1.0 + lam), V[1], V[2], V[3] * (1.0 + lam), V[4], V[5] * (1.0 + lam)};
+        const Chol3 c = chol3(Vd);
+        ok &= c.ok;
+        double Vi[6];
+        chol3_inverse(c, Vi);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) Vinv[6 * j + k] = Vi[k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) wph[3 * j + k] = w[k];
+    }
+    for (int64_t h = p0; h < p1; ++h) {
+        if (seg_head[h] != (int32_t)h) continue;
+        double Vs[6] = {0, 0, 0, 0, 0, 0}, ws[3] = {0, 0, 0};
+        for (int64_t a = h; a < p1; ++a) {
+            if (seg_head[a] != (int32_t)h) continue;
+            double jp[6];
+            load_jp(Jp, a, jp);
+            const double f0 = (double)f[2 * a], f1 = (double)f[2 * a + 1];
+            Vs[0] += jp[0] * jp[0] + jp[3] * jp[3];
+            Vs[1] += jp[0] * jp[1] + jp[3] * jp[4];
+            Vs[2] += jp[0] * jp[2] + jp[3] * jp[5];
+            Vs[3] += jp[1] * jp[1] + jp[4] * jp[4];
+            Vs[4] += jp[1] * jp[2] + jp[4] * jp[5];
+            Vs[5] += jp[2] * jp[2] + jp[5] * jp[5];
+            ws[0] -= jp[0] * f0 + jp[3] * f1;
+            ws[1] -= jp[1] * f0 + jp[4] * f1;
+            ws[2] -= jp[2] * f0 + jp[5] * f1;
+        }
+        if (corr) {
+            // g'_s = h_s (sum_s g_s) / (sum_s h_s), h_s = (1 + lambda) diag(V_s);
+            // sum_s g_s = w_j and sum_s diag(V_s) = diag(V_j)
+            ws[0] = Vs[0] * w[0] / V[0];
+            ws[1] = Vs[3] * w[1] / V[3];
+            ws[2] = Vs[5] * w[2] / V[5];
+        }
+        const double Vd[6] = {Vs[0] * (1.0 + lam), Vs[1], Vs[2], Vs[3] * (1.0 + lam), Vs[4], Vs[5] * (1.0 + lam)};
+        const Chol3 c = chol3(Vd);
+        ok &= c.ok;
+        double Vi[6];
+        chol3_inverse(c, Vi);
+        double u[3];
+        sym3_mul(Vi, ws, u);   // V*_s^-1 w'_s
+        for (int64_t a = h; a < p1; ++a) {
+            if (seg_head[a] != (int32_t)h) continue;
+            double jp[6], jc[18];
+            load_jp(Jp, a, jp);
+#pragma unroll
+            for (int k = 0; k < 18; ++k) jc[k] = (double)Jc[18 * a + k];
+            T *rec = obsd + (int64_t)kObsRec * a;
+#pragma unroll
+            for (int e = 0; e < 9; ++e) {
+                const double W0 = jc[e] * jp[0] + jc[9 + e] * jp[3];
+                const double W1 = jc[e] * jp[1] + jc[9 + e] * jp[4];
+                const double W2 = jc[e] * jp[2] + jc[9 + e] * jp[5];
+                rec[3 * e + 0] = (T)(W0 * c.I00);
+                rec[3 * e + 1] = (T)(W0 * c.I01 + W1 * c.I11);
+                rec[3 * e + 2] = (T)(W0 * c.I02 + W1 * c.I12 + W2 * c.I22);
+            }
+            double G0[3], G1[3];
+            const double r0v[3] = {jp[0], jp[1], jp[2]}, r1v[3] = {jp[3], jp[4], jp[5]};
+            sym3_mul(Vi, r0v, G0);
+            sym3_mul(Vi, r1v, G1);
+            rec[27] = (T)(1.0 - (G0[0] * jp[0] + G0[1] * jp[1] + G0[2] * jp[2]));
+            rec[28] = (T)(-(G0[0] * jp[3] + G0[1] * jp[4] + G0[2] * jp[5]));
+            rec[29] = (T)(1.0 - (G1[0] * jp[3] + G1[1] * jp[4] + G1[2] * jp[5]));
+            rec[30] = (T)((double)f[2 * a] + jp[0] * u[0] + jp[1] * u[1] + jp[2] * u[2]);
+            rec[31] = (T)((double)f[2 * a + 1] + jp[3] * u[0] + jp[4] * u[1] + jp[5] * u[2]);
+        }
+    }
+    if (!ok) set_status(status + kStPointBad, STBA_ENOTPD);
+}
+
+// zero S (all clusters) and b; identity on the padded tail of each S_k
+__global__ __launch_bounds__(256) void k_zero_S(double *S, double *b, int32_t m, const int64_t *S_off, int32_t l,
+                                                int64_t S_cap) {
+    int64_t total = S_off[l];
+    if (total > S_cap) total = S_cap;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) S[i] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 9 * (int64_t)m; i += stride) b[i] = 0.0;
+}
+
+__global__ __launch_bounds__(64) void k_pad_S(double *S, const int64_t *S_off, const int32_t *cl_n,
+                                              const int32_t *cl_Np) {
+    const int k = blockIdx.x;
+    const int64_t Np = cl_Np[k];
+    double *A = S + S_off[k];
+    for (int64_t i = 9 * (int64_t)cl_n[k] + threadIdx.x; i < Np; i += 64) A[i + i * Np] = 1.0;
+}
+
+// ---------------------------------------------------------------------------
+// a4: Schur assembly.  One wavefront per camera pair (r, c), r >= c, of the
+// static pair list; lanes (g, e): g in 0..6 takes every 7th observation pair,
+// e in 0..8 the row of the 9x9 block.  Off-diagonal blocks
+// S_rc = -sum Y_u Y_w^T over pairs in the same segment (Eq. 10); diagonal blocks
+// S_rr = sum J_c^T M J_c + lambda diag(U_r) and b_r = -sum J_c^T r (Eq. 13).
+// Blocks of cameras in different clusters are dropped (S' is cluster-diagonal).
+// The 7 partial sums per row are combined in a fixed order (deterministic).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_schur(const int64_t *__restrict__ n_blocks_p, const int2 *__restrict__ blk_key,
+                                               const int64_t *__restrict__ blk_start,
+                                               const uint64_t *__restrict__ pairs,
+                                               const int32_t *__restrict__ cam_cluster, int32_t l,
+                                               const int32_t *__restrict__ cam_local,
+                                               const int32_t *__restrict__ cl_Np, const int64_t *__restrict__ S_off,
+                                               const int32_t *__restrict__ seg_head, const T *__restrict__ Jc,
+                                               const T *__restrict__ obsd, const double *__restrict__ lam2,
+                                               double *__restrict__ S, double *__restrict__ b) {
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int g = lane / 9;
+    const int e = lane - 9 * g;
+    const bool act = lane < 63;
+    const int64_t nb = n_blocks_p[0];
+    const double lam = lam2[0];
+    const int64_t wstride = (int64_t)gridDim.x * 4;
+    for (int64_t blk = (int64_t)blockIdx.x * 4 + wv; blk < nb; blk += wstride) {
+        const int2 key = blk_key[blk];
+        const int32_t r = key.x, c = key.y;
+        const int32_t kr = cam_cluster[r];
+        if (kr < 0 || kr >= l || cam_cluster[c] != kr) continue;
+        const int64_t Np = cl_Np[kr];
+        if (Np == 0) continue;   // the map was rejected by the cluster layout
+        const int64_t s0 = blk_start[blk], s1 = blk_start[blk + 1];
+        T acc[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) acc[k] = (T)0;
+        T du = (T)0, rb = (T)0;
+        if (r == c) {
+            if (act) {
+                for (int64_t p = s0 + g; p < s1; p += 7) {
+                    const int64_t bo = (int64_t)(pairs[p] >> 32);
+                    const T *jc = Jc + 18 * bo;
+                    const T *od = obsd + (int64_t)kObsRec * bo;
+                    const T j0e = jc[e], j1e = jc[9 + e];
+                    const T m00 = od[27], m01 = od[28], m11 = od[29];
+                    const T t0 = j0e * m00 + j1e * m01;
+                    const T t1 = j0e * m01 + j1e * m11;
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) acc[k] += t0 * jc[k] + t1 * jc[9 + k];
+                    du += j0e * j0e + j1e * j1e;
+                    rb += j0e * od[30] + j1e * od[31];
+                }
+            }
+        } else {
+            if (act) {
+                for (int64_t p = s0 + g; p < s1; p += 7) {
+                    const uint64_t pr = pairs[p];
+                    const int64_t u = (int64_t)(pr >> 32), w = (int64_t)(pr & 0xFFFFFFFFull);
+                    if (seg_head[u] != seg_head[w]) continue;
+                    const T *yu = obsd + (int64_t)kObsRec * u + 3 * e;
+                    const T *yw = obsd + (int64_t)kObsRec * w;
+                    const T y0 = yu[0], y1 = yu[1], y2 = yu[2];
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) acc[k] += y0 * yw[3 * k] + y1 * yw[3 * k + 1] + y2 * yw[3 * k + 2];
+                }
+            }
+        }
+        // fixed-order sum over the 7 pair slots g of each row e: g += g+4, g += g+2, g += g+1
+#pragma unroll
+        for (int d = 36; d >= 9; d >>= 1) {
+            const bool take = lane + d < 63;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                const T o = __shfl_down(acc[k], d, 64);
+                if (take) acc[k] += o;
+            }
+            const T od = __shfl_down(du, d, 64);
+            const T orb = __shfl_down(rb, d, 64);
+            if (take) {
+                du += od;
+                rb += orb;
+            }
+        }
+        if (lane < 9) {
+            double *A = S + S_off[kr];
+            const int64_t lr = cam_local[r];
+            const int64_t row = 9 * lr + e;
+            if (r == c) {
+#pragma unroll
+                for (int k = 0; k < 9; ++k) {
+                    double v = (double)acc[k];
+                    if (k == e) v += lam * (double)du;
+                    A[row + (9 * lr + k) * Np] = v;
+                }
+                b[9 * (int64_t)r + e] = -(double)rb;
+            } else {
+                const int64_t lc = cam_local[c];
+#pragma unroll
+                for (int k = 0; k < 9; ++k) A[row + (9 * lc + k) * Np] = -(double)acc[k];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a6: point update with the physical blocks (Eq. 15):
+//   dp_j = V*_j^-1 (w_j - sum_o J_p,o^T J_c,o dc_{i_o}).  One thread per point.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_backsub(int32_t n, const int64_t *__restrict__ pt_off,
+                                                 const int32_t *__restrict__ obs_cam, const T *__restrict__ Jc,
+                                                 const T *__restrict__ Jp, const double *__restrict__ Vinv,
+                                                 const double *__restrict__ wph, const double *__restrict__ dcam,
+                                                 double *__restrict__ dpt) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double g[3] = {wph[3 * j], wph[3 * j + 1], wph[3 * j + 2]};
+    for (int64_t o = pt_off[j]; o < pt_off[j + 1]; ++o) {
+        const double *dc = dcam + 9 * (int64_t)obs_cam[o];
+        const T *jc = Jc + 18 * o;
+        double t0 = 0.0, t1 = 0.0;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            t0 += (double)jc[k] * dc[k];
+            t1 += (double)jc[9 + k] * dc[k];
+        }
+        const T *jp = Jp + 6 * o;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) g[k] -= (double)jp[k] * t0 + (double)jp[3 + k] * t1;
+    }
+    double Vi[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) Vi[k] = Vinv[6 * j + k];
+    double d[3];
+    sym3_mul(Vi, g, d);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dpt[3 * j + k] = d[k];
+}
+
+// a7: cost at the candidate x + dx in FP64 (block partial sums).
+__global__ __launch_bounds__(256) void k_cost_at(int64_t q, const double *__restrict__ cam,
+                                                 const double *__restrict__ pt, const int32_t *__restrict__ oc,
+                                                 const int32_t *__restrict__ op, const double *__restrict__ uv,
+                                                 const double *__restrict__ dcam, const double *__restrict__ dpt,
+                                                 double *__restrict__ partials) {
+    __shared__ double sh[256];
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double sq = 0.0;
+    if (o < q) {
+        const int64_t i = oc[o], j = op[o];
+        double c[9], X[3];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) c[k] = cam[9 * i + k] + dcam[9 * i + k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) X[k] = pt[3 * j + k] + dpt[3 * j + k];
+        double pix[2];
+        camera_project(c, X, pix);
+        const double f0 = pix[0] - uv[2 * o], f1 = pix[1] - uv[2 * o + 1];
+        sq = f0 * f0 + f1 * f1;
+    }
+    const double s = block_sum_256(sq, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// a7: accept iff F(x + dx) < F(x), the step is finite and every S_k factorised
+// (Alg. 1); lambda /= 3 on accept, *= 3 otherwise.
+__global__ __launch_bounds__(256) void k_accept(const double *partials, int64_t count, const int32_t *cl_status,
+                                                int32_t l, const int32_t *status, stba_lm_state *st) {
+    __shared__ double sh[256];
+    __shared__ int bad_pd;
+    if (threadIdx.x == 0) bad_pd = 0;
+    __syncthreads();
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < count; i += 256) s += partials[i];
+    for (int k = threadIdx.x; k < l; k += 256)
+        if (cl_status[k] != STBA_OK) bad_pd = 1;
+    s = block_sum_256(s, sh);
+    if (threadIdx.x == 0) {
+        const double Fn = s;
+        const bool pd = !bad_pd && status[kStPointBad] == 0;
+        const bool fin = isfinite(Fn);
+        const bool valid = pd && fin && status[kStSticky] == 0;
+        const bool acc = valid && (Fn < st->F);
+        st->F_new = Fn;
+        st->accepted = acc ? 1 : 0;
+        st->lambda = acc ? st->lambda / 3.0 : st->lambda * 3.0;
+        if (acc) st->F = Fn;
+        st->need_jac = acc ? 1 : 0;
+        st->n_rcs += 1;
+        st->n_accept += acc ? 1 : 0;
+        st->n_jac += status[kStJacRan] ? 1 : 0;
+        st->last_status = !pd ? STBA_ENOTPD : (!fin ? STBA_ENONFINITE : status[kStSticky]);
+        if (st->status == 0 && status[kStSticky] != 0) st->status = status[kStSticky];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_update(int32_t m, int32_t n, const stba_lm_state *st, double *cam,
+                                                double *pt, const double *dcam, const double *dpt) {
+    if (!st->accepted) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 9 * (int64_t)m) cam[i] += dcam[i];
+    else if (i < 9 * (int64_t)m + 3 * (int64_t)n) pt[i - 9 * (int64_t)m] += dpt[i - 9 * (int64_t)m];
+}
+
+// ---------------------------------------------------------------------------
+// J^T v (differentiation of the residuals): the Jacobian is recomputed.
+// Cameras: one wavefront per camera over its observations (fixed order);
+// points: one thread per point; observed pixels: -v.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_vjp_cam(int32_t m, const double *__restrict__ cam,
+                                                 const double *__restrict__ pt, const int32_t *__restrict__ op,
+                                                 const int64_t *__restrict__ diag_blk,
+                                                 const int64_t *__restrict__ blk_start,
+                                                 const uint64_t *__restrict__ pairs, const T *__restrict__ v,
+                                                 T *__restrict__ grad_cam) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= m) return;
+    double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const int64_t kb = diag_blk[r];
+    if (kb >= 0) {
+        double c[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) c[k] = cam[9 * r + k];
+        for (int64_t p = blk_start[kb] + lane; p < blk_start[kb + 1]; p += 64) {
+            const int64_t o = (int64_t)(pairs[p] >> 32);
+            const int64_t j = op[o];
+            const double X[3] = {pt[3 * j], pt[3 * j + 1], pt[3 * j + 2]};
+            double pix[2], jc[2][9], jp[2][3];
+            camera_project_jac(c, X, pix, jc, jp);
+            const double v0 = (double)v[2 * o], v1 = (double)v[2 * o + 1];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) acc[k] += jc[0][k] * v0 + jc[1][k] * v1;
+        }
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1)
+#pragma unroll
+        for (int k = 0; k < 9; ++k) acc[k] += __shfl_xor(acc[k], d, 64);
+    if (lane < 9) grad_cam[9 * r + lane] = (T)acc[lane];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_vjp_pt(int32_t n, int64_t q, const double *__restrict__ cam,
+                                                const double *__restrict__ pt, const int32_t *__restrict__ oc,
+                                                const int64_t *__restrict__ pt_off, const T *__restrict__ v,
+                                                T *__restrict__ grad_pt) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const double X[3] = {pt[3 * j], pt[3 * j + 1], pt[3 * j + 2]};
+    double acc[3] = {0, 0, 0};
+    for (int64_t o = pt_off[j]; o < pt_off[j + 1]; ++o) {
+        double c[9];
+        const int64_t i = oc[o];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) c[k] = cam[9 * i + k];
+        double pix[2], jc[2][9], jp[2][3];
+        camera_project_jac(c, X, pix, jc, jp);
+        const double v0 = (double)v[2 * o], v1 = (double)v[2 * o + 1];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) acc[k] += jp[0][k] * v0 + jp[1][k] * v1;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) grad_pt[3 * j + k] = (T)acc[k];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_neg(int64_t len, const T *v, T *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) out[i] = -v[i];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+hipError_t launch_reset_status(int32_t *status, hipStream_t st) {
+    k_reset_status<<<1, 64, 0, st>>>(status);
+    return hipGetLastError();
+}
+
+hipError_t launch_lm_init(stba_lm_state *s, double lambda0, double lambda_corr, hipStream_t st) {
+    k_lm_init<<<1, 1, 0, st>>>(s, lambda0, lambda_corr);
+    return hipGetLastError();
+}
+
+hipError_t launch_clusters(const int32_t *cam_cluster, int32_t m, int32_t l, int32_t gamma_max, int32_t *cl_n,
+                           int32_t *cl_Np, int32_t *cl_start, int32_t *cl_cams, int32_t *cam_local,
+                           int64_t *S_off, int32_t *status, hipStream_t st) {
+    k_clusters<<<1, 1024, 0, st>>>(cam_cluster, m, l, gamma_max, cl_n, cl_Np, cl_start, cl_cams, cam_local, S_off,
+                                   status);
+    return hipGetLastError();
+}
+
+int64_t rj_blocks(int64_t q) { return (q + 255) / 256; }
+
+template <typename T>
+hipError_t launch_rj(const stba_problem &p, T *f, T *Jc, T *Jp, double *partials, const int32_t *need_jac,
+                     int32_t *jac_ran, hipStream_t st) {
+    k_rj<T><<<grid_for(p.q), 256, 0, st>>>(p.q, p.cam, p.pt, p.obs_cam, p.obs_pt, p.obs_uv, f, Jc, Jp, partials,
+                                           need_jac, jac_ran);
+    return hipGetLastError();
+}
+template hipError_t launch_rj<double>(const stba_problem &, double *, double *, double *, double *,
+                                      const int32_t *, int32_t *, hipStream_t);
+template hipError_t launch_rj<float>(const stba_problem &, float *, float *, float *, double *, const int32_t *,
+                                     int32_t *, hipStream_t);
+
+hipError_t launch_sum_partials(const double *partials, int64_t count, double *out, hipStream_t st) {
+    k_sum_partials<<<1, 256, 0, st>>>(partials, count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_cost(const double *partials, int64_t count, stba_lm_state *s, hipStream_t st) {
+    k_init_cost<<<1, 256, 0, st>>>(partials, count, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_damping(double *slot, double lambda, double lambda_corr, hipStream_t st) {
+    k_set_damping<<<1, 1, 0, st>>>(slot, lambda, lambda_corr);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_points(const stba_problem &p, const int64_t *pt_off, const int32_t *cam_cluster, int32_t l,
+                         const T *f, const T *Jc, const T *Jp, const double *lam2, uint64_t seed, uint64_t t,
+                         uint64_t thr, int32_t *seg_head, T *obsd, double *Vinv, double *wph, int32_t *status,
+                         hipStream_t st) {
+    (void)l;
+    k_points<T><<<grid_for(p.n), 256, 0, st>>>(p.n, pt_off, p.obs_cam, cam_cluster, f, Jc, Jp, lam2, seed, t, thr,
+                                               seg_head, obsd, Vinv, wph, status);
+    return hipGetLastError();
+}
+template hipError_t launch_points<double>(const stba_problem &, const int64_t *, const int32_t *, int32_t,
+                                          const double *, const double *, const double *, const double *, uint64_t,
+                                          uint64_t, uint64_t, int32_t *, double *, double *, double *, int32_t *,
+                                          hipStream_t);
+template hipError_t launch_points<float>(const stba_problem &, const int64_t *, const int32_t *, int32_t,
+                                         const float *, const float *, const float *, const double *, uint64_t,
+                                         uint64_t, uint64_t, int32_t *, float *, double *, double *, int32_t *,
+                                         hipStream_t);
+
+hipError_t launch_fill_S(double *S, double *b, int32_t m, const int64_t *S_off, int32_t l, int64_t S_cap,
+                         const int32_t *cl_n, const int32_t *cl_Np, hipStream_t st) {
+    int64_t blocks = (S_cap + 1023) / 1024;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    k_zero_S<<<(unsigned)blocks, 256, 0, st>>>(S, b, m, S_off, l, S_cap);
+    k_pad_S<<<(unsigned)l, 64, 0, st>>>(S, S_off, cl_n, cl_Np);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_schur(const int64_t *n_blocks, int64_t n_blocks_cap, const int2 *blk_key,
+                        const int64_t *blk_start, const uint64_t *pairs, const int32_t *cam_cluster, int32_t l,
+                        const int32_t *cam_local, const int32_t *cl_Np, const int64_t *S_off,
+                        const int32_t *seg_head, const T *Jc, const T *obsd, const double *lam2, double *S,
+                        double *b, hipStream_t st) {
+    int64_t wgs = (n_blocks_cap + 3) / 4;
+    if (wgs > 16384) wgs = 16384;
+    if (wgs < 1) wgs = 1;
+    k_schur<T><<<(unsigned)wgs, 256, 0, st>>>(n_blocks, blk_key, blk_start, pairs, cam_cluster, l, cam_local, cl_Np,
+                                              S_off, seg_head, Jc, obsd, lam2, S, b);
+    return hipGetLastError();
+}
+template hipError_t launch_schur<double>(const int64_t *, int64_t, const int2 *, const int64_t *, const uint64_t *,
+                                         const int32_t *, int32_t, const int32_t *, const int32_t *,
+                                         const int64_t *, const int32_t *, const double *, const double *,
+                                         const double *, double *, double *, hipStream_t);
+template hipError_t launch_schur<float>(const int64_t *, int64_t, const int2 *, const int64_t *, const uint64_t *,
+                                        const int32_t *, int32_t, const int32_t *, const int32_t *, const int64_t *,
+                                        const int32_t *, const float *, const float *, const double *, double *,
+                                        double *, hipStream_t);
+
+template <typename T>
+hipError_t launch_backsub(const stba_problem &p, const int64_t *pt_off, const T *Jc, const T *Jp,
+                          const double *Vinv, const double *wph, const double *dcam, double *dpt, hipStream_t st) {
+    k_backsub<T><<<grid_for(p.n), 256, 0, st>>>(p.n, pt_off, p.obs_cam, Jc, Jp, Vinv, wph, dcam, dpt);
+    return hipGetLastError();
+}
+template hipError_t launch_backsub<double>(const stba_problem &, const int64_t *, const double *, const double *,
+                                           const double *, const double *, const double *, double *, hipStream_t);
+template hipError_t launch_backsub<float>(const stba_problem &, const int64_t *, const float *, const float *,
+                                          const double *, const double *, const double *, double *, hipStream_t);
+
+hipError_t launch_cost_at(const stba_problem &p, const double *dcam, const double *dpt, double *partials,
+                          hipStream_t st) {
+    k_cost_at<<<grid_for(p.q), 256, 0, st>>>(p.q, p.cam, p.pt, p.obs_cam, p.obs_pt, p.obs_uv, dcam, dpt, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_accept(const double *partials, int64_t count, const int32_t *cl_status, int32_t l,
+                         const int32_t *status, stba_lm_state *s, hipStream_t st) {
+    k_accept<<<1, 256, 0, st>>>(partials, count, cl_status, l, status, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_update(const stba_problem &p, const stba_lm_state *s, const double *dcam, const double *dpt,
+                         hipStream_t st) {
+    k_update<<<grid_for(9 * (int64_t)p.m + 3 * (int64_t)p.n), 256, 0, st>>>(p.m, p.n, s, p.cam, p.pt, dcam, dpt);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_vjp(const stba_problem &p, const int64_t *pt_off, const int64_t *diag_blk, const int2 *blk_key,
+                      const int64_t *blk_start, const uint64_t *pairs, const T *v, T *grad_cam, T *grad_pt,
+                      T *grad_uv, hipStream_t st) {
+    (void)blk_key;
+    k_vjp_cam<T><<<grid_for(p.m, 4), 256, 0, st>>>(p.m, p.cam, p.pt, p.obs_pt, diag_blk, blk_start, pairs, v,
+                                                   grad_cam);
+    k_vjp_pt<T><<<grid_for(p.n), 256, 0, st>>>(p.n, p.q, p.cam, p.pt, p.obs_cam, pt_off, v, grad_pt);
+    k_neg<T><<<grid_for(2 * p.q), 256, 0, st>>>(2 * p.q, v, grad_uv);
+    return hipGetLastError();
+}
+template hipError_t launch_vjp<double>(const stba_problem &, const int64_t *, const int64_t *, const int2 *,
+                                       const int64_t *, const uint64_t *, const double *, double *, double *,
+                                       double *, hipStream_t);
+template hipError_t launch_vjp<float>(const stba_problem &, const int64_t *, const int64_t *, const int2 *,
+                                      const int64_t *, const uint64_t *, const float *, float *, float *, float *,
+                                      hipStream_t);
+
+}  // namespace stba

@@ -1,0 +1,84 @@
+// Launchers of the gfx950 kernels (internal header).  Each launcher enqueues on
+// `st` and returns the launch status; shapes are checked by the caller.
+#pragma once
+#include "common.h"
+
+namespace stba {
+
+// --- set-up (prepare.hip) ---------------------------------------------------
+hipError_t launch_analyze(const stba_problem &p, int64_t *d_scratch, hipStream_t st);
+struct PrepBufs {
+    int64_t *pt_off;      // [n+1] first observation of each point
+    int64_t *pair_off;    // [n+1] first pair of each point (generation order)
+    int64_t *scratch_a;   // [n_pairs] pair counts / head flags
+    uint64_t *keys_in;    // [n_pairs] (row camera) * m + (column camera)
+    uint64_t *keys_out;   // [n_pairs] sorted keys
+    uint64_t *vals_in;    // [n_pairs] (row obs << 32) | column obs
+    uint64_t *pairs;      // [n_pairs] sorted values: the pair list grouped by camera pair
+    int64_t *blk_of;      // [n_pairs] block index of each sorted pair (exclusive scan of heads)
+    int2 *blk_key;        // [n_pairs] (row camera, column camera) of each block (first n_blocks used)
+    int64_t *blk_start;   // [n_pairs + 1] first pair of each block
+    int64_t *n_blocks;    // [1]
+    int64_t *diag_blk;    // [m] block index of camera pair (i, i)
+    void *tmp;            // rocPRIM temporary storage
+    size_t tmp_bytes;
+};
+size_t prepare_tmp_bytes(int64_t n_pairs, int32_t m, hipStream_t st);
+hipError_t launch_prepare(const stba_problem &p, int64_t n_pairs, const PrepBufs &b, int32_t *status,
+                          hipStream_t st);
+
+// --- per iteration ----------------------------------------------------------
+hipError_t launch_reset_status(int32_t *status, hipStream_t st);
+hipError_t launch_lm_init(stba_lm_state *s, double lambda0, double lambda_corr, hipStream_t st);
+hipError_t launch_clusters(const int32_t *cam_cluster, int32_t m, int32_t l, int32_t gamma_max,
+                           int32_t *cl_n, int32_t *cl_Np, int32_t *cl_start, int32_t *cl_cams,
+                           int32_t *cam_local, int64_t *S_off, int32_t *status, hipStream_t st);
+
+template <typename T>
+hipError_t launch_rj(const stba_problem &p, T *f, T *Jc, T *Jp, double *partials, const int32_t *need_jac,
+                     int32_t *jac_ran, hipStream_t st);
+int64_t rj_blocks(int64_t q);
+
+hipError_t launch_sum_partials(const double *partials, int64_t count, double *out, hipStream_t st);
+hipError_t launch_init_cost(const double *partials, int64_t count, stba_lm_state *s, hipStream_t st);
+hipError_t launch_set_damping(double *slot, double lambda, double lambda_corr, hipStream_t st);
+
+template <typename T>
+hipError_t launch_points(const stba_problem &p, const int64_t *pt_off, const int32_t *cam_cluster, int32_t l,
+                         const T *f, const T *Jc, const T *Jp, const double *lam2, uint64_t seed, uint64_t t,
+                         uint64_t thr, int32_t *seg_head, T *obsd, double *Vinv, double *wph, int32_t *status,
+                         hipStream_t st);
+
+hipError_t launch_fill_S(double *S, double *b, int32_t m, const int64_t *S_off, int32_t l, int64_t S_cap,
+                         const int32_t *cl_n, const int32_t *cl_Np, hipStream_t st);
+
+template <typename T>
+hipError_t launch_schur(const int64_t *n_blocks, int64_t n_blocks_cap, const int2 *blk_key,
+                        const int64_t *blk_start, const uint64_t *pairs, const int32_t *cam_cluster, int32_t l,
+                        const int32_t *cam_local, const int32_t *cl_Np, const int64_t *S_off,
+                        const int32_t *seg_head, const T *Jc, const T *obsd, const double *lam2, double *S,
+                        double *b, hipStream_t st);
+
+hipError_t launch_chol(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, const int64_t *S_off,
+                       const int32_t *cl_start, const int32_t *cl_cams, double *S, const double *b,
+                       double *dcam, int32_t *cl_status, int32_t max_Np, hipStream_t st);
+
+template <typename T>
+hipError_t launch_backsub(const stba_problem &p, const int64_t *pt_off, const T *Jc, const T *Jp,
+                          const double *Vinv, const double *wph, const double *dcam, double *dpt, hipStream_t st);
+
+hipError_t launch_cost_at(const stba_problem &p, const double *dcam, const double *dpt, double *partials,
+                          hipStream_t st);
+
+hipError_t launch_accept(const double *partials, int64_t count, const int32_t *cl_status, int32_t l,
+                         const int32_t *status, stba_lm_state *s, hipStream_t st);
+
+hipError_t launch_update(const stba_problem &p, const stba_lm_state *s, const double *dcam, const double *dpt,
+                         hipStream_t st);
+
+template <typename T>
+hipError_t launch_vjp(const stba_problem &p, const int64_t *pt_off, const int64_t *diag_blk,
+                      const int2 *blk_key, const int64_t *blk_start, const uint64_t *pairs, const T *v,
+                      T *grad_cam, T *grad_pt, T *grad_uv, hipStream_t st);
+
+}  // namespace stba

@@ -1,0 +1,382 @@
+// C ABI of the STBA hot path: argument checks, the workspace layout and the
+// order in which one LM iteration (Alg. 1) enqueues its kernels.
+#include <math.h>
+#include <string.h>
+
+#include "kernels.h"
+
+namespace stba {
+namespace {
+
+struct Layout {
+    size_t status, lam2;
+    // static plan (stba_prepare)
+    size_t pt_off, pair_off, scratch_a, keys_in, keys_out, vals_in, pairs, blk_of, blk_key, blk_start, n_blocks,
+        diag_blk, tmp;
+    size_t tmp_bytes;
+    // per iteration
+    size_t cl_n, cl_Np, cl_start, cl_cams, cam_local, cl_status, S_off;
+    size_t f, Jc, Jp, seg_head, obsd, Vinv, wph, S, b, dcam, dpt, partials;
+    int64_t S_cap, n_partials;
+    int32_t max_Np;
+    size_t total;
+};
+
+inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int check_problem(const stba_problem *p) {
+    if (!p || p->m < 1 || p->n < 1 || p->q < 1 || p->q >= (int64_t(1) << 31)) return STBA_EINVAL;
+    if (!p->cam || !p->pt || !p->obs_cam || !p->obs_pt || !p->obs_uv) return STBA_EINVAL;
+    if (p->m > kMaxCamsForClusters) return STBA_EINVAL;
+    return STBA_OK;
+}
+
+int check_dims(const stba_problem *p, const stba_dims *d) {
+    if (!d || d->n_pairs < p->n || d->n_pairs < p->q || d->gamma_max < 1 || d->gamma_max > p->m)
+        return STBA_EINVAL;
+    return STBA_OK;
+}
+
+int check_precision(int precision) {
+    return (precision == STBA_FP64 || precision == STBA_MIXED) ? STBA_OK : STBA_EINVAL;
+}
+
+int check_sample(const stba_problem *p, const stba_sample *s) {
+    if (!s || !s->cam_cluster || s->l < 1 || s->l > p->m) return STBA_EINVAL;
+    if (!(s->alpha > 0.0 && s->alpha <= 1.0)) return STBA_EINVAL;
+    return STBA_OK;
+}
+
+// Largest sum of padded S_k sizes over any map with clusters of at most gamma
+// cameras: sum_k Np(n_k)^2 = sum_k n_k (Np(n_k)^2 / n_k) <= m max_n Np(n)^2 / n.
+int64_t s_capacity(int32_t m, int32_t gamma) {
+    double best = 0.0;
+    for (int32_t nk = 1; nk <= gamma; ++nk) {
+        const double np = (double)round_up(9 * (int64_t)nk, kNB);
+        best = fmax(best, np * np / nk);
+    }
+    return (int64_t)ceil(best * m);
+}
+
+bool make_layout(const stba_problem *p, const stba_dims *d, int precision, Layout &L) {
+    const size_t es = precision == STBA_MIXED ? sizeof(float) : sizeof(double);
+    const size_t m = (size_t)p->m, n = (size_t)p->n, q = (size_t)p->q, np = (size_t)d->n_pairs;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + (bytes ? bytes : 1));
+        return o;
+    };
+    L.status = take(sizeof(int32_t) * kStCount);
+    L.lam2 = take(2 * sizeof(double));
+    L.pt_off = take(8 * (n + 1));
+    L.pair_off = take(8 * (n + 1));
+    L.scratch_a = take(8 * np);
+    L.keys_in = take(8 * np);
+    L.keys_out = take(8 * np);
+    L.vals_in = take(8 * np);
+    L.pairs = take(8 * np);
+    L.blk_of = take(8 * np);
+    L.blk_key = take(8 * np);
+    L.blk_start = take(8 * (np + 1));
+    L.n_blocks = take(8);
+    L.diag_blk = take(8 * m);
+    L.tmp_bytes = prepare_tmp_bytes(d->n_pairs, p->m, 0);
+    L.tmp = take(L.tmp_bytes);
+    L.cl_n = take(4 * m);
+    L.cl_Np = take(4 * m);
+    L.cl_start = take(4 * (m + 1));
+    L.cl_cams = take(4 * m);
+    L.cam_local = take(4 * m);
+    L.cl_status = take(4 * m);
+    L.S_off = take(8 * (m + 1));
+    L.f = take(es * 2 * q);
+    L.Jc = take(es * 18 * q);
+    L.Jp = take(es * 6 * q);
+    L.seg_head = take(4 * q);
+    L.obsd = take(es * kObsRec * q);
+    L.Vinv = take(8 * 6 * n);
+    L.wph = take(8 * 3 * n);
+    L.S_cap = s_capacity(p->m, d->gamma_max);
+    L.S = take(8 * (size_t)L.S_cap);
+    L.b = take(8 * 9 * m);
+    L.dcam = take(8 * 9 * m);
+    L.dpt = take(8 * 3 * n);
+    L.n_partials = rj_blocks(p->q);
+    L.partials = take(8 * (size_t)L.n_partials);
+    L.max_Np = (int32_t)round_up(9 * (int64_t)d->gamma_max, kNB);
+    L.total = off;
+    return true;
+}
+
+template <typename P>
+P *at(void *ws, size_t off) {
+    return reinterpret_cast<P *>(static_cast<char *>(ws) + off);
+}
+
+int check_ws(const Layout &L, void *ws, size_t bytes) {
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) != 0) return STBA_EINVAL;
+    if (bytes < L.total) return STBA_EWORKSPACE;
+    return STBA_OK;
+}
+
+#define STBA_TRY(expr)                          \
+    do {                                        \
+        const int _rc = (expr);                 \
+        if (_rc != STBA_OK) return _rc;         \
+    } while (0)
+
+#define STBA_HIP(expr)                          \
+    do {                                        \
+        if ((expr) != hipSuccess) return STBA_EHIP; \
+    } while (0)
+
+uint64_t keep_threshold(double alpha) { return (uint64_t)ceil(alpha * 9007199254740992.0); }
+
+// Common front end of every per-iteration call.
+int front(const stba_problem *p, const stba_dims *d, int precision, void *ws, size_t ws_bytes, Layout &L) {
+    STBA_TRY(check_problem(p));
+    STBA_TRY(check_dims(p, d));
+    STBA_TRY(check_precision(precision));
+    make_layout(p, d, precision, L);
+    return check_ws(L, ws, ws_bytes);
+}
+
+template <typename T>
+int build_rcs_impl(const stba_problem *p, const stba_dims *d, const stba_sample *s, const double *lam2,
+                   const T *f, const T *Jc, const T *Jp, const Layout &L, void *ws, hipStream_t st) {
+    int32_t *status = at<int32_t>(ws, L.status);
+    STBA_HIP(launch_clusters(s->cam_cluster, p->m, s->l, d->gamma_max, at<int32_t>(ws, L.cl_n),
+                             at<int32_t>(ws, L.cl_Np), at<int32_t>(ws, L.cl_start), at<int32_t>(ws, L.cl_cams),
+                             at<int32_t>(ws, L.cam_local), at<int64_t>(ws, L.S_off), status, st));
+    STBA_HIP(launch_points<T>(*p, at<int64_t>(ws, L.pt_off), s->cam_cluster, s->l, f, Jc, Jp, lam2, s->seed, s->iter,
+                              keep_threshold(s->alpha), at<int32_t>(ws, L.seg_head), at<T>(ws, L.obsd),
+                              at<double>(ws, L.Vinv), at<double>(ws, L.wph), status, st));
+    STBA_HIP(launch_fill_S(at<double>(ws, L.S), at<double>(ws, L.b), p->m, at<int64_t>(ws, L.S_off), s->l, L.S_cap,
+                           at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np), st));
+    STBA_HIP(launch_schur<T>(at<int64_t>(ws, L.n_blocks), d->n_pairs, at<int2>(ws, L.blk_key),
+                             at<int64_t>(ws, L.blk_start), at<uint64_t>(ws, L.pairs), s->cam_cluster, s->l,
+                             at<int32_t>(ws, L.cam_local), at<int32_t>(ws, L.cl_Np), at<int64_t>(ws, L.S_off),
+                             at<int32_t>(ws, L.seg_head), Jc, at<T>(ws, L.obsd), lam2, at<double>(ws, L.S),
+                             at<double>(ws, L.b), st));
+    return STBA_OK;
+}
+
+template <typename T>
+int solve_impl(const stba_problem *p, const stba_dims *d, int32_t l, const T *Jc, const T *Jp, double *dcam,
+               double *dpt, int32_t *cl_status, const Layout &L, void *ws, hipStream_t st) {
+    (void)d;
+    STBA_HIP(launch_chol(l, at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np), at<int64_t>(ws, L.S_off),
+                         at<int32_t>(ws, L.cl_start), at<int32_t>(ws, L.cl_cams), at<double>(ws, L.S),
+                         at<double>(ws, L.b), dcam, cl_status, L.max_Np, st));
+    STBA_HIP(launch_backsub<T>(*p, at<int64_t>(ws, L.pt_off), Jc, Jp, at<double>(ws, L.Vinv), at<double>(ws, L.wph),
+                               dcam, dpt, st));
+    return STBA_OK;
+}
+
+template <typename T>
+int lm_step_impl(const stba_problem *p, const stba_dims *d, const stba_sample *s, stba_lm_state *stt,
+                 const Layout &L, void *ws, hipStream_t st, hipEvent_t *ev) {
+    int32_t *status = at<int32_t>(ws, L.status);
+    const double *lam2 = &stt->lambda;   // lambda and lambda_corr are adjacent
+    T *f = at<T>(ws, L.f), *Jc = at<T>(ws, L.Jc), *Jp = at<T>(ws, L.Jp);
+    auto mark = [&](int k) -> int {
+        if (ev) STBA_HIP(hipEventRecord(ev[k], st));
+        return STBA_OK;
+    };
+    STBA_TRY(mark(0));
+    STBA_HIP(launch_reset_status(status, st));
+    STBA_HIP(launch_clusters(s->cam_cluster, p->m, s->l, d->gamma_max, at<int32_t>(ws, L.cl_n),
+                             at<int32_t>(ws, L.cl_Np), at<int32_t>(ws, L.cl_start), at<int32_t>(ws, L.cl_cams),
+                             at<int32_t>(ws, L.cam_local), at<int64_t>(ws, L.S_off), status, st));
+    STBA_TRY(mark(1));
+    STBA_HIP(launch_rj<T>(*p, f, Jc, Jp, at<double>(ws, L.partials), &stt->need_jac, status + kStJacRan, st));
+    STBA_HIP(launch_init_cost(at<double>(ws, L.partials), L.n_partials, stt, st));
+    STBA_TRY(mark(2));
+    STBA_HIP(launch_points<T>(*p, at<int64_t>(ws, L.pt_off), s->cam_cluster, s->l, f, Jc, Jp, lam2, s->seed, s->iter,
+                              keep_threshold(s->alpha), at<int32_t>(ws, L.seg_head), at<T>(ws, L.obsd),
+                              at<double>(ws, L.Vinv), at<double>(ws, L.wph), status, st));
+    STBA_TRY(mark(3));
+    STBA_HIP(launch_fill_S(at<double>(ws, L.S), at<double>(ws, L.b), p->m, at<int64_t>(ws, L.S_off), s->l, L.S_cap,
+                           at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np), st));
+    STBA_TRY(mark(4));
+    STBA_HIP(launch_schur<T>(at<int64_t>(ws, L.n_blocks), d->n_pairs, at<int2>(ws, L.blk_key),
+                             at<int64_t>(ws, L.blk_start), at<uint64_t>(ws, L.pairs), s->cam_cluster, s->l,
+                             at<int32_t>(ws, L.cam_local), at<int32_t>(ws, L.cl_Np), at<int64_t>(ws, L.S_off),
+                             at<int32_t>(ws, L.seg_head), Jc, at<T>(ws, L.obsd), lam2, at<double>(ws, L.S),
+                             at<double>(ws, L.b), st));
+    STBA_TRY(mark(5));
+    double *dcam = at<double>(ws, L.dcam), *dpt = at<double>(ws, L.dpt);
+    STBA_HIP(launch_chol(s->l, at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np), at<int64_t>(ws, L.S_off),
+                         at<int32_t>(ws, L.cl_start), at<int32_t>(ws, L.cl_cams), at<double>(ws, L.S),
+                         at<double>(ws, L.b), dcam, at<int32_t>(ws, L.cl_status), L.max_Np, st));
+    STBA_TRY(mark(6));
+    STBA_HIP(launch_backsub<T>(*p, at<int64_t>(ws, L.pt_off), Jc, Jp, at<double>(ws, L.Vinv), at<double>(ws, L.wph),
+                               dcam, dpt, st));
+    STBA_TRY(mark(7));
+    STBA_HIP(launch_cost_at(*p, dcam, dpt, at<double>(ws, L.partials), st));
+    STBA_TRY(mark(8));
+    STBA_HIP(launch_accept(at<double>(ws, L.partials), L.n_partials, at<int32_t>(ws, L.cl_status), s->l, status, stt,
+                           st));
+    STBA_HIP(launch_update(*p, stt, dcam, dpt, st));
+    STBA_TRY(mark(9));
+    return STBA_OK;
+}
+
+const char *const kPhaseNames[STBA_NUM_PHASES] = {
+    "clusters", "residual_jacobian", "points_segments", "fill_S", "schur_assembly",
+    "cluster_cholesky", "point_backsub", "candidate_cost", "accept_update"};
+
+}  // namespace
+}  // namespace stba
+
+using namespace stba;
+
+extern "C" {
+
+const char *stba_version(void) { return "stba-gfx950 0.1"; }
+
+const char *stba_phase_name(int k) { return (k >= 0 && k < STBA_NUM_PHASES) ? kPhaseNames[k] : ""; }
+
+size_t stba_analyze_scratch_bytes(void) { return 64; }
+
+int stba_analyze(const stba_problem *p, void *d_scratch, stba_dims *dims, hipStream_t stream) {
+    STBA_TRY(check_problem(p));
+    if (!d_scratch || !dims) return STBA_EINVAL;
+    STBA_HIP(launch_analyze(*p, static_cast<int64_t *>(d_scratch), stream));
+    int64_t h[4] = {0, 0, 0, 0};
+    STBA_HIP(hipMemcpyAsync(h, d_scratch, sizeof(h), hipMemcpyDeviceToHost, stream));
+    STBA_HIP(hipStreamSynchronize(stream));
+    if (h[2] != 0) return STBA_EDATA;
+    dims->n_pairs = h[0];
+    dims->max_track = (int32_t)h[1];
+    return STBA_OK;
+}
+
+size_t stba_workspace_bytes(const stba_problem *p, const stba_dims *dims, int precision) {
+    if (check_problem(p) != STBA_OK || check_dims(p, dims) != STBA_OK || check_precision(precision) != STBA_OK)
+        return 0;
+    Layout L;
+    make_layout(p, dims, precision, L);
+    return L.total;
+}
+
+int stba_prepare(const stba_problem *p, const stba_dims *dims, int precision, void *ws, size_t ws_bytes,
+                 hipStream_t stream) {
+    Layout L;
+    STBA_TRY(front(p, dims, precision, ws, ws_bytes, L));
+    PrepBufs b;
+    b.pt_off = at<int64_t>(ws, L.pt_off);
+    b.pair_off = at<int64_t>(ws, L.pair_off);
+    b.scratch_a = at<int64_t>(ws, L.scratch_a);
+    b.keys_in = at<uint64_t>(ws, L.keys_in);
+    b.keys_out = at<uint64_t>(ws, L.keys_out);
+    b.vals_in = at<uint64_t>(ws, L.vals_in);
+    b.pairs = at<uint64_t>(ws, L.pairs);
+    b.blk_of = at<int64_t>(ws, L.blk_of);
+    b.blk_key = at<int2>(ws, L.blk_key);
+    b.blk_start = at<int64_t>(ws, L.blk_start);
+    b.n_blocks = at<int64_t>(ws, L.n_blocks);
+    b.diag_blk = at<int64_t>(ws, L.diag_blk);
+    b.tmp = at<void>(ws, L.tmp);
+    b.tmp_bytes = L.tmp_bytes;
+    STBA_HIP(launch_reset_status(at<int32_t>(ws, L.status), stream));
+    STBA_HIP(launch_prepare(*p, dims->n_pairs, b, at<int32_t>(ws, L.status), stream));
+    return STBA_OK;
+}
+
+int stba_residual_jacobian(const stba_problem *p, const stba_dims *dims, int precision, void *f, void *Jc, void *Jp,
+                           double *cost, void *ws, size_t ws_bytes, hipStream_t stream) {
+    Layout L;
+    STBA_TRY(front(p, dims, precision, ws, ws_bytes, L));
+    if (!f || ((Jc == nullptr) != (Jp == nullptr))) return STBA_EINVAL;
+    double *partials = cost ? at<double>(ws, L.partials) : nullptr;
+    if (precision == STBA_FP64)
+        STBA_HIP(launch_rj<double>(*p, (double *)f, (double *)Jc, (double *)Jp, partials, nullptr, nullptr, stream));
+    else
+        STBA_HIP(launch_rj<float>(*p, (float *)f, (float *)Jc, (float *)Jp, partials, nullptr, nullptr, stream));
+    if (cost) STBA_HIP(launch_sum_partials(partials, L.n_partials, cost, stream));
+    return STBA_OK;
+}
+
+int stba_build_cluster_rcs(const stba_problem *p, const stba_dims *dims, const stba_sample *s, const stba_damping *d,
+                           int precision, const void *f, const void *Jc, const void *Jp, stba_rcs *out, void *ws,
+                           size_t ws_bytes, hipStream_t stream) {
+    Layout L;
+    STBA_TRY(front(p, dims, precision, ws, ws_bytes, L));
+    STBA_TRY(check_sample(p, s));
+    if (!d || !(d->lambda > 0.0) || !(d->lambda_corr >= 0.0) || !f || !Jc || !Jp || !out) return STBA_EINVAL;
+    double *lam2 = at<double>(ws, L.lam2);
+    STBA_HIP(launch_set_damping(lam2, d->lambda, d->lambda_corr, stream));
+    STBA_HIP(launch_reset_status(at<int32_t>(ws, L.status), stream));
+    if (precision == STBA_FP64)
+        STBA_TRY(build_rcs_impl<double>(p, dims, s, lam2, (const double *)f, (const double *)Jc, (const double *)Jp, L,
+                                        ws, stream));
+    else
+        STBA_TRY(build_rcs_impl<float>(p, dims, s, lam2, (const float *)f, (const float *)Jc, (const float *)Jp, L, ws,
+                                       stream));
+    out->S = at<double>(ws, L.S);
+    out->S_off = at<int64_t>(ws, L.S_off);
+    out->cl_n = at<int32_t>(ws, L.cl_n);
+    out->cl_Np = at<int32_t>(ws, L.cl_Np);
+    out->cl_start = at<int32_t>(ws, L.cl_start);
+    out->cl_cams = at<int32_t>(ws, L.cl_cams);
+    out->cam_local = at<int32_t>(ws, L.cam_local);
+    out->b = at<double>(ws, L.b);
+    out->seg_head = at<int32_t>(ws, L.seg_head);
+    out->l = s->l;
+    out->precision = precision;
+    return STBA_OK;
+}
+
+int stba_solve_clusters(const stba_problem *p, const stba_dims *dims, const stba_rcs *rcs, int precision,
+                        const void *Jc, const void *Jp, double *dcam, double *dpt, int32_t *cluster_status, void *ws,
+                        size_t ws_bytes, hipStream_t stream) {
+    Layout L;
+    STBA_TRY(front(p, dims, precision, ws, ws_bytes, L));
+    if (!rcs || rcs->l < 1 || rcs->l > p->m || rcs->precision != precision || !Jc || !Jp || !dcam || !dpt)
+        return STBA_EINVAL;
+    int32_t *cs = cluster_status ? cluster_status : at<int32_t>(ws, L.cl_status);
+    if (precision == STBA_FP64)
+        return solve_impl<double>(p, dims, rcs->l, (const double *)Jc, (const double *)Jp, dcam, dpt, cs, L, ws, stream);
+    return solve_impl<float>(p, dims, rcs->l, (const float *)Jc, (const float *)Jp, dcam, dpt, cs, L, ws, stream);
+}
+
+int stba_lm_init(stba_lm_state *st, double lambda0, double lambda_corr, hipStream_t stream) {
+    if (!st || !(lambda0 > 0.0) || !(lambda_corr >= 0.0)) return STBA_EINVAL;
+    STBA_HIP(launch_lm_init(st, lambda0, lambda_corr, stream));
+    return STBA_OK;
+}
+
+int stba_lm_step_profiled(const stba_problem *p, const stba_dims *dims, const stba_sample *s, stba_lm_state *st,
+                          int precision, void *ws, size_t ws_bytes, hipStream_t stream, hipEvent_t *events) {
+    Layout L;
+    STBA_TRY(front(p, dims, precision, ws, ws_bytes, L));
+    STBA_TRY(check_sample(p, s));
+    if (!st) return STBA_EINVAL;
+    if (precision == STBA_FP64) return lm_step_impl<double>(p, dims, s, st, L, ws, stream, events);
+    return lm_step_impl<float>(p, dims, s, st, L, ws, stream, events);
+}
+
+int stba_lm_step(const stba_problem *p, const stba_dims *dims, const stba_sample *s, stba_lm_state *st, int precision,
+                 void *ws, size_t ws_bytes, hipStream_t stream) {
+    return stba_lm_step_profiled(p, dims, s, st, precision, ws, ws_bytes, stream, nullptr);
+}
+
+int stba_residual_vjp(const stba_problem *p, const stba_dims *dims, int precision, const void *v, void *grad_cam,
+                      void *grad_pt, void *grad_uv, void *ws, size_t ws_bytes, hipStream_t stream) {
+    Layout L;
+    STBA_TRY(front(p, dims, precision, ws, ws_bytes, L));
+    if (!v || !grad_cam || !grad_pt || !grad_uv) return STBA_EINVAL;
+    if (precision == STBA_FP64)
+        STBA_HIP(launch_vjp<double>(*p, at<int64_t>(ws, L.pt_off), at<int64_t>(ws, L.diag_blk), at<int2>(ws, L.blk_key),
+                                    at<int64_t>(ws, L.blk_start), at<uint64_t>(ws, L.pairs), (const double *)v,
+                                    (double *)grad_cam, (double *)grad_pt, (double *)grad_uv, stream));
+    else
+        STBA_HIP(launch_vjp<float>(*p, at<int64_t>(ws, L.pt_off), at<int64_t>(ws, L.diag_blk), at<int2>(ws, L.blk_key),
+                                   at<int64_t>(ws, L.blk_start), at<uint64_t>(ws, L.pairs), (const float *)v,
+                                   (float *)grad_cam, (float *)grad_pt, (float *)grad_uv, stream));
+    return STBA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,137 @@
+"""Python conveniences over the C ABI: a solver object that owns the workspace
+and the device LM state, and residuals as a differentiable function.
+
+Both only marshal arguments; every step of the method runs in libstba.so.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+
+class StbaSolver:
+    """One bundle-adjustment problem resident on the GPU.
+
+    cam [m,9], pt [n,3] (FP64, copied to the device and updated in place on
+    accepted steps), obs_cam / obs_pt [q] int32 sorted by (point, camera),
+    obs_uv [q,2] FP64.  gamma_max bounds the cluster sizes of every map later
+    passed to `step`."""
+
+    def __init__(self, cam, pt, obs_cam, obs_pt, obs_uv, gamma_max, precision=B.STBA_FP64,
+                 lambda0=1e-4, lambda_corr=0.1, device="cuda"):
+        as_dev = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(device)  # noqa: E731
+        self.cam = as_dev(cam, torch.float64).clone()
+        self.pt = as_dev(pt, torch.float64).clone()
+        self.obs_cam = as_dev(obs_cam, torch.int32)
+        self.obs_pt = as_dev(obs_pt, torch.int32)
+        self.obs_uv = as_dev(obs_uv, torch.float64)
+        self.precision = int(precision)
+        self.problem = B.make_problem(self.cam, self.pt, self.obs_cam, self.obs_pt, self.obs_uv)
+        self.dims = B.stba_analyze(self.problem)
+        self.dims.gamma_max = int(gamma_max)
+        self.ws = B.alloc_workspace(B.stba_workspace_bytes(self.problem, self.dims, self.precision))
+        B.stba_prepare(self.problem, self.dims, self.precision, self.ws)
+        self.state = B.new_state(device)
+        B.stba_lm_init(self.state, lambda0, lambda_corr)
+        self._events = None
+
+    @property
+    def m(self):
+        return self.problem.m
+
+    @property
+    def q(self):
+        return self.problem.q
+
+    def sample(self, cam_cluster, alpha=1.0, seed=0, it=0, l=None):
+        cc = cam_cluster if torch.is_tensor(cam_cluster) else torch.as_tensor(
+            np.asarray(cam_cluster, dtype=np.int32)).to(self.cam.device)
+        if l is None:
+            l = int(np.asarray(cam_cluster.cpu() if torch.is_tensor(cam_cluster) else cam_cluster).max()) + 1
+        return B.make_sample(cc, l, alpha, seed, it)
+
+    def step(self, sample, events=None):
+        """One LM iteration (asynchronous)."""
+        if events is None:
+            B.stba_lm_step(self.problem, self.dims, sample, self.state, self.precision, self.ws)
+        else:
+            B.stba_lm_step_profiled(self.problem, self.dims, sample, self.state, self.precision, self.ws, events)
+
+    def read_state(self):
+        return B.read_state(self.state)
+
+
+class ResidualPlan:
+    """Static structure (visibility graph) for repeated residual / J^T v calls."""
+
+    def __init__(self, obs_cam, obs_pt, m, n, precision=B.STBA_FP64, device="cuda"):
+        self.obs_cam = torch.as_tensor(obs_cam, dtype=torch.int32).to(device).contiguous()
+        self.obs_pt = torch.as_tensor(obs_pt, dtype=torch.int32).to(device).contiguous()
+        self.m, self.n, self.q = int(m), int(n), int(self.obs_cam.shape[0])
+        self.precision = int(precision)
+        self.dtype = torch.float64 if self.precision == B.STBA_FP64 else torch.float32
+        cam = torch.zeros((self.m, 9), dtype=torch.float64, device=device)
+        pt = torch.zeros((self.n, 3), dtype=torch.float64, device=device)
+        uv = torch.zeros((self.q, 2), dtype=torch.float64, device=device)
+        prob = B.make_problem(cam, pt, self.obs_cam, self.obs_pt, uv)
+        self.dims = B.stba_analyze(prob)
+        self.dims.gamma_max = 1
+        self.ws = B.alloc_workspace(B.stba_workspace_bytes(prob, self.dims, self.precision))
+        B.stba_prepare(prob, self.dims, self.precision, self.ws)
+
+    def problem(self, cam, pt, uv):
+        return B.make_problem(cam.contiguous(), pt.contiguous(), self.obs_cam, self.obs_pt, uv.contiguous())
+
+
+class _Residuals(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, cam, pt, obs_uv, plan):
+        cam_d, pt_d, uv_d = cam.detach(), pt.detach(), obs_uv.detach()
+        prob = plan.problem(cam_d, pt_d, uv_d)
+        f = torch.empty((plan.q, 2), dtype=plan.dtype, device=cam.device)
+        B.stba_residual_jacobian(prob, plan.dims, plan.precision, f, None, None, None, plan.ws)
+        ctx.save_for_backward(cam_d, pt_d, uv_d)
+        ctx.plan = plan
+        return f
+
+    @staticmethod
+    def backward(ctx, grad_f):
+        cam, pt, uv = ctx.saved_tensors
+        plan = ctx.plan
+        prob = plan.problem(cam, pt, uv)
+        v = grad_f.to(plan.dtype).contiguous()
+        gc = torch.empty((plan.m, 9), dtype=plan.dtype, device=cam.device)
+        gp = torch.empty((plan.n, 3), dtype=plan.dtype, device=cam.device)
+        gu = torch.empty((plan.q, 2), dtype=plan.dtype, device=cam.device)
+        B.stba_residual_vjp(prob, plan.dims, plan.precision, v, gc, gp, gu, plan.ws)
+        return gc.to(cam.dtype), gp.to(pt.dtype), gu.to(uv.dtype), None
+
+
+def residuals(cam, pt, obs_uv, plan: ResidualPlan):
+    """Reprojection residuals f (pixel - observed) as a differentiable function of
+    cam, pt and obs_uv; the backward pass is J^T v with J recomputed on the GPU."""
+    return _Residuals.apply(cam, pt, obs_uv, plan)
+
+
+def hip_events(count):
+    """Create `count` timing events through the HIP runtime (for stba_lm_step_profiled)."""
+    hip = ctypes.CDLL("libamdhip64.so")
+    arr = (ctypes.c_void_p * count)()
+    for i in range(count):
+        rc = hip.hipEventCreate(ctypes.byref(arr, i * ctypes.sizeof(ctypes.c_void_p)))
+        if rc != 0:
+            raise RuntimeError(f"hipEventCreate failed: {rc}")
+    return arr
+
+
+def event_ms(start, stop) -> float:
+    hip = ctypes.CDLL("libamdhip64.so")
+    ms = ctypes.c_float(0.0)
+    rc = hip.hipEventElapsedTime(ctypes.byref(ms), ctypes.c_void_p(start), ctypes.c_void_p(stop))
+    if rc != 0:
+        raise RuntimeError(f"hipEventElapsedTime failed: {rc}")
+    return float(ms.value)
