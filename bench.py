@@ -1,0 +1,251 @@
+"""Benchmark of the STBA hot path on one MI355X.
+
+Workload (default): the 200-camera ring scene (3 rings around a 20 x 20 x 5 box,
+50k points, 8 views per point, q = 400k observations, 1 px noise), camera
+clusters of at most 50 from stochastic graph clustering redrawn every LM
+iteration, lambda0 = 1e-4, alpha = 1, FP64: 10 LM iterations.  One step = one
+full LM iteration of STBA (cluster layout, residuals/Jacobian when x changed,
+segments and correction, Schur assembly, cluster Cholesky, point update,
+candidate cost, accept).  Inputs are resident in HBM before the timed region;
+the cluster maps of all timed iterations are drawn and uploaded beforehand.
+
+Prints ONE JSON line.  `value` is LM iterations per second; `obs_per_s` is
+q x iterations/s.  `roofline` describes the kernel with the largest time per
+iteration, timed with HIP events on the library's stream; `cpu_baseline` times
+the FP64 oracle on the host for the first iterations of the same run.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+
+
+def source_hash() -> str:
+    csrc = os.path.join(ROOT, "paper_2008_00446_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    h.update(open(os.path.join(ROOT, "include", "stba.h"), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def parse_args():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--gamma", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=2, help="oracle iterations timed for cpu_baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 1 GiB (to scale HBM counters)")
+    return ap.parse_args()
+
+
+def copy_calibration():
+    import torch
+    x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")     # 1 GiB
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": x.numel() * 8, "copy_bytes_written": y.numel() * 8, "launches": 3}))
+
+
+def algorithmic_model(scene, maps, es):
+    """Algorithmic bytes / flops per launch of each phase (averaged over `maps`).
+
+    es: bytes per element of f/J/Schur data (8 FP64, 4 mixed)."""
+    q, n, m = scene.q, scene.n, scene.m
+    counts = np.bincount(scene.obs_pt, minlength=n)
+    chol_flops, schur_pairs, S_entries = [], [], []
+    for lab in maps:
+        sizes = np.bincount(lab)
+        N = 9 * sizes.astype(np.float64)
+        chol_flops.append(float(np.sum(N ** 3 / 3.0 + 2.0 * N ** 2)))
+        S_entries.append(float(np.sum(N * (N + 1) / 2)))
+        # same-cluster observation pairs of each point (alpha = 1: one segment per point and cluster)
+        key = scene.obs_pt.astype(np.int64) * (lab.max() + 1) + lab[scene.obs_cam]
+        _, c = np.unique(key, return_counts=True)
+        schur_pairs.append(float(np.sum(c * (c + 1) / 2)))
+    chol_flops, schur_pairs, S_entries = map(np.mean, (chol_flops, schur_pairs, S_entries))
+    diag_pairs = float(q)
+    off_pairs = schur_pairs - diag_pairs
+    model = {
+        # reads ids (8) + uv (16) + gathered cam/pt; writes f, Jc, Jp (26 elements)
+        "residual_jacobian": dict(bound="hbm", bytes=q * (24 + 26 * es) + m * 72 + n * 24),
+        # reads f, Jp, Jc (26 el.) + ids; writes segment record (32 el.) + head; point blocks (72 B)
+        "points_segments": dict(bound="hbm", bytes=q * (26 * es + 32 * es + 12) + n * (72 + 16)),
+        # zero the lower-triangle storage of S (counted as written once)
+        "fill_S": dict(bound="hbm", bytes=8 * S_entries),
+        # 486 flop per off-diagonal pair (Y_u Y_w^T), 400 per diagonal pair; each record read once
+        "schur_assembly": dict(bound="alu", flops=486 * off_pairs + 400 * diag_pairs,
+                               bytes=q * (32 + 18) * es + 8 * S_entries + 8 * schur_pairs),
+        "cluster_cholesky": dict(bound="mfma", flops=chol_flops, bytes=8 * 2 * S_entries),
+        # reads Jc, Jp (24 el.) + dc gathers; point blocks (72 B); writes dp
+        "point_backsub": dict(bound="hbm", bytes=q * (24 * es + 4) + n * (72 + 24 + 16)),
+        # reads ids, uv, gathered x and dx
+        "candidate_cost": dict(bound="hbm", bytes=q * 24 + (m * 72 + n * 24) * 2),
+    }
+    return model, dict(chol_flops=chol_flops, schur_pairs=schur_pairs, S_lower_entries=S_entries,
+                       counts_mean=float(counts.mean()))
+
+
+def load_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it was
+    measured on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.strip().split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_hash") != source_hash():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(scene, maps, lam0, iters):
+    import psutil
+    import oracle as O
+    proc = psutil.Process()
+    cam, pt, lam = scene.cam0.copy(), scene.pt0.copy(), lam0
+    F = O.cost(O.residuals(cam, pt, scene.obs_cam, scene.obs_pt, scene.obs_uv))
+    c0 = proc.cpu_times()
+    t0 = time.perf_counter()
+    for t in range(iters):
+        r = O.lm_iteration(cam, pt, scene.obs_cam, scene.obs_pt, scene.obs_uv, maps[t], lam, 1.0, 0, t, F=F)
+        cam, pt, lam, F = r.cam, r.pt, r.lam, r.F
+    wall = time.perf_counter() - t0
+    c1 = proc.cpu_times()
+    cpu = (c1.user - c0.user) + (c1.system - c0.system)
+    try:
+        from threadpoolctl import threadpool_info
+        blas = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        blas = 1
+    return {"value": iters / wall, "unit": "iter/s", "cores": int(round(max(1.0, cpu / wall))),
+            "kind": "oracle",
+            "sample": f"first {iters} LM iterations of the same workload, same maps and seeds "
+                      f"(FP64 NumPy/SciPy, {wall:.1f} s wall, {cpu:.1f} s CPU; BLAS threads available {blas}, "
+                      f"host cpus {len(os.sched_getaffinity(0))})",
+            "F_after": F}
+
+
+def main():
+    args = parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is not built",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    import torch
+    import paper_2008_00446_amd as S
+    import synth
+
+    precision = S.STBA_FP64 if args.precision == "fp64" else S.STBA_MIXED
+    es = 8 if precision == S.STBA_FP64 else 4
+    scene = synth.ring(m=200, n=50_000, views=8, seed=0)
+    workload = f"ring_m{scene.m}_n{scene.n}_q{scene.q}"
+    e, w = synth.camera_graph(scene.obs_cam, scene.obs_pt, scene.m)
+    total = max(args.steps, args.warmup, args.cpu_iters)
+    maps = [synth.sgc_map(e, w, scene.m, args.gamma, 10.0, 0, t) for t in range(total)]
+    lam0 = 1e-4
+    sol = S.StbaSolver(scene.cam0, scene.pt0, scene.obs_cam, scene.obs_pt, scene.obs_uv,
+                       gamma_max=args.gamma, precision=precision, lambda0=lam0)
+    samples = [sol.sample(maps[t], alpha=1.0, seed=0, it=t) for t in range(total)]
+    cam0 = sol.cam.clone()
+    pt0 = sol.pt.clone()
+    # warm-up iterations, then restart from x0 so the timed steps are iterations 0..K-1
+    for t in range(args.warmup):
+        sol.step(samples[t])
+    torch.cuda.synchronize()
+    sol.cam.copy_(cam0)
+    sol.pt.copy_(pt0)
+    S.stba_lm_init(sol.state, lam0, 0.1)
+    P = S.STBA_NUM_PHASES
+    evs = [S.hip_events(P + 1) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(args.steps):
+        sol.step(samples[t], events=evs[t])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = sol.read_state()
+    phase_ms = np.zeros(P)
+    for ev in evs:
+        for k in range(P):
+            phase_ms[k] += S.event_ms(ev[k], ev[k + 1])
+    phase_ms /= args.steps
+    names = [S.stba_phase_name(k) for k in range(P)]
+    model, stats = algorithmic_model(scene, maps[:args.steps], es)
+    ms_per_step = 1e3 * elapsed / args.steps
+    dom = max((nm for nm in names if nm in model), key=lambda nm: phase_ms[names.index(nm)])
+    dur_s = phase_ms[names.index(dom)] * 1e-3
+    mdl = model[dom]
+    if mdl["bound"] == "hbm":
+        achieved, peak, unit = mdl["bytes"] / dur_s / 1e9, HBM_PEAK_GBS, "GB/s"
+    else:
+        achieved = mdl["flops"] / dur_s / 1e12
+        peak = FP64_PEAK_TFLOPS if (precision == S.STBA_FP64 or dom == "cluster_cholesky") else FP32_PEAK_TFLOPS
+        unit = "TFLOP/s"
+    roofline = {"kernel": dom, "bound": mdl["bound"], "achieved": achieved, "peak": peak, "unit": unit,
+                "frac": achieved / peak, "traffic": load_traffic(dom, workload),
+                "duration_ms": phase_ms[names.index(dom)]}
+    per_phase = {}
+    for k, nm in enumerate(names):
+        entry = {"ms": round(float(phase_ms[k]), 4)}
+        if nm in model:
+            mm = model[nm]
+            if "bytes" in mm:
+                entry["GB/s"] = round(mm["bytes"] / (phase_ms[k] * 1e-3) / 1e9, 1)
+            if "flops" in mm:
+                entry["TFLOP/s"] = round(mm["flops"] / (phase_ms[k] * 1e-3) / 1e12, 3)
+        per_phase[nm] = entry
+    out = {
+        "metric": "STBA LM iterations/s (and observations/s)", "value": args.steps / elapsed, "unit": "iter/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if precision == S.STBA_FP64 else "f32+f64", "data": "synthetic",
+        "config": {"workload": workload, "cameras": scene.m, "points": scene.n, "observations": scene.q,
+                   "views_per_point": 8, "cluster_cap": args.gamma, "clusters_mean": float(
+                       np.mean([mp.max() + 1 for mp in maps[:args.steps]])), "lambda0": lam0, "alpha": 1.0,
+                   "lm_iterations": args.steps, "precision": args.precision},
+        "obs_per_s": scene.q * args.steps / elapsed,
+        "roofline": roofline,
+        "phases": per_phase,
+        "lm": {"F_final": st["F"], "accepted": st["n_accept"], "jacobian_evals": st["n_jac"],
+               "rcs_builds": st["n_rcs"], "lambda_final": st["lambda_"], "status": st["status"]},
+        "model": stats, "source_hash": source_hash(),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(scene, maps, lam0, args.cpu_iters)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()
