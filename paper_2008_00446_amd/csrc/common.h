@@ -11,6 +11,9 @@ namespace stba {
 constexpr int kNB = 32;            // Cholesky tile order (FP64)
 constexpr int kObsRec = 32;        // per-observation record written by the point kernel:
                                    //   Y[9][3] (27), M (m00 m01 m11), r (2)
+constexpr int kSegRec = 16;        // per-segment record at the head observation: R^-1 (6), V*^-1 (6), V*^-1 w' (3)
+constexpr int kSchurChunk = 512;   // observation pairs per Schur work item (16 rounds of 32 pair slots)
+constexpr int kSchurPart = 100;    // doubles per partial sum: 81 block entries, 9 diag(U), 9 rhs, pad
 constexpr int kMaxCamsForClusters = 16384;   // single-workgroup cluster layout limit (LDS keys)
 
 // Status words kept in the workspace (int32[16]).

@@ -273,14 +273,13 @@ __device__ inline void load_jp(const T *Jp, int64_t o, double jp[6]) {
 // One thread per point.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_points(int32_t n, const int64_t *__restrict__ pt_off,
-                                                const int32_t *__restrict__ obs_cam,
-                                                const int32_t *__restrict__ cam_cluster, const T *__restrict__ f,
-                                                const T *__restrict__ Jc, const T *__restrict__ Jp,
-                                                const double *__restrict__ lam2, uint64_t seed, uint64_t t,
-                                                uint64_t thr, int32_t *__restrict__ seg_head, T *__restrict__ obsd,
-                                                double *__restrict__ Vinv, double *__restrict__ wph,
-                                                int32_t *status) {
+__global__ __launch_bounds__(64) void k_points(int32_t n, const int64_t *__restrict__ pt_off,
+                                               const int32_t *__restrict__ obs_cam,
+                                               const int32_t *__restrict__ cam_cluster, const T *__restrict__ f,
+                                               const T *__restrict__ Jp, const double *__restrict__ lam2,
+                                               uint64_t seed, uint64_t t, uint64_t thr, int32_t *__restrict__ seg_head,
+                                               double *__restrict__ seg_rec, double *__restrict__ Vinv,
+                                               double *__restrict__ wph, int32_t *status) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     const double lam = lam2[0];
@@ -361,34 +360,60 @@ __global__ __launch_bounds__(256) void k_points(int32_t n, const int64_t *__rest
         chol3_inverse(c, Vi);
         double u[3];
         sym3_mul(Vi, ws, u);   // V*_s^-1 w'_s
-        for (int64_t a = h; a < p1; ++a) {
-            if (seg_head[a] != (int32_t)h) continue;
-            double jp[6], jc[18];
-            load_jp(Jp, a, jp);
+        double *rec = seg_rec + (int64_t)kSegRec * h;
+        rec[0] = c.I00;
+        rec[1] = c.I01;
+        rec[2] = c.I02;
+        rec[3] = c.I11;
+        rec[4] = c.I12;
+        rec[5] = c.I22;
 #pragma unroll
-            for (int k = 0; k < 18; ++k) jc[k] = (double)Jc[18 * a + k];
-            T *rec = obsd + (int64_t)kObsRec * a;
+        for (int k = 0; k < 6; ++k) rec[6 + k] = Vi[k];
 #pragma unroll
-            for (int e = 0; e < 9; ++e) {
-                const double W0 = jc[e] * jp[0] + jc[9 + e] * jp[3];
-                const double W1 = jc[e] * jp[1] + jc[9 + e] * jp[4];
-                const double W2 = jc[e] * jp[2] + jc[9 + e] * jp[5];
-                rec[3 * e + 0] = (T)(W0 * c.I00);
-                rec[3 * e + 1] = (T)(W0 * c.I01 + W1 * c.I11);
-                rec[3 * e + 2] = (T)(W0 * c.I02 + W1 * c.I12 + W2 * c.I22);
-            }
-            double G0[3], G1[3];
-            const double r0v[3] = {jp[0], jp[1], jp[2]}, r1v[3] = {jp[3], jp[4], jp[5]};
-            sym3_mul(Vi, r0v, G0);
-            sym3_mul(Vi, r1v, G1);
-            rec[27] = (T)(1.0 - (G0[0] * jp[0] + G0[1] * jp[1] + G0[2] * jp[2]));
-            rec[28] = (T)(-(G0[0] * jp[3] + G0[1] * jp[4] + G0[2] * jp[5]));
-            rec[29] = (T)(1.0 - (G1[0] * jp[3] + G1[1] * jp[4] + G1[2] * jp[5]));
-            rec[30] = (T)((double)f[2 * a] + jp[0] * u[0] + jp[1] * u[1] + jp[2] * u[2]);
-            rec[31] = (T)((double)f[2 * a + 1] + jp[3] * u[0] + jp[4] * u[1] + jp[5] * u[2]);
-        }
+        for (int k = 0; k < 3; ++k) rec[12 + k] = u[k];
     }
     if (!ok) set_status(status + kStPointBad, STBA_ENOTPD);
+}
+
+// Per observation o of segment s: Y_o = W_o R_s^-1, M_o = I - J_p,o V*_s^-1 J_p,o^T,
+// r_o = f_o + J_p,o V*_s^-1 w'_s (see k_points).  One thread per observation.
+template <typename T>
+__global__ __launch_bounds__(256) void k_obs_rec(int64_t q, const int32_t *__restrict__ seg_head,
+                                                 const double *__restrict__ seg_rec, const T *__restrict__ f,
+                                                 const T *__restrict__ Jc, const T *__restrict__ Jp,
+                                                 T *__restrict__ obsd) {
+    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= q) return;
+    const double *sr = seg_rec + (int64_t)kSegRec * seg_head[a];
+    const double I00 = sr[0], I01 = sr[1], I02 = sr[2], I11 = sr[3], I12 = sr[4], I22 = sr[5];
+    double Vi[6], u[3];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) Vi[k] = sr[6 + k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) u[k] = sr[12 + k];
+    double jp[6], jc[18];
+    load_jp(Jp, a, jp);
+#pragma unroll
+    for (int k = 0; k < 18; ++k) jc[k] = (double)Jc[18 * a + k];
+    T *rec = obsd + (int64_t)kObsRec * a;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        const double W0 = jc[e] * jp[0] + jc[9 + e] * jp[3];
+        const double W1 = jc[e] * jp[1] + jc[9 + e] * jp[4];
+        const double W2 = jc[e] * jp[2] + jc[9 + e] * jp[5];
+        rec[3 * e + 0] = (T)(W0 * I00);
+        rec[3 * e + 1] = (T)(W0 * I01 + W1 * I11);
+        rec[3 * e + 2] = (T)(W0 * I02 + W1 * I12 + W2 * I22);
+    }
+    double G0[3], G1[3];
+    const double r0v[3] = {jp[0], jp[1], jp[2]}, r1v[3] = {jp[3], jp[4], jp[5]};
+    sym3_mul(Vi, r0v, G0);
+    sym3_mul(Vi, r1v, G1);
+    rec[27] = (T)(1.0 - (G0[0] * jp[0] + G0[1] * jp[1] + G0[2] * jp[2]));
+    rec[28] = (T)(-(G0[0] * jp[3] + G0[1] * jp[4] + G0[2] * jp[5]));
+    rec[29] = (T)(1.0 - (G1[0] * jp[3] + G1[1] * jp[4] + G1[2] * jp[5]));
+    rec[30] = (T)((double)f[2 * a] + jp[0] * u[0] + jp[1] * u[1] + jp[2] * u[2]);
+    rec[31] = (T)((double)f[2 * a + 1] + jp[3] * u[0] + jp[4] * u[1] + jp[5] * u[2]);
 }
 
 // zero S (all clusters) and b; identity on the padded tail of each S_k
@@ -410,16 +435,40 @@ __global__ __launch_bounds__(64) void k_pad_S(double *S, const int64_t *S_off, c
 }
 
 // ---------------------------------------------------------------------------
-// a4: Schur assembly.  One wavefront per camera pair (r, c), r >= c, of the
-// static pair list; lanes (g, e): g in 0..6 takes every 7th observation pair,
-// e in 0..8 the row of the 9x9 block.  Off-diagonal blocks
-// S_rc = -sum Y_u Y_w^T over pairs in the same segment (Eq. 10); diagonal blocks
-// S_rr = sum J_c^T M J_c + lambda diag(U_r) and b_r = -sum J_c^T r (Eq. 13).
-// Blocks of cameras in different clusters are dropped (S' is cluster-diagonal).
-// The 7 partial sums per row are combined in a fixed order (deterministic).
+// a4: Schur assembly.  Every camera pair (r, c), r >= c, of the static pair list
+// is cut into chunks of kSchurChunk observation pairs; one wavefront takes one
+// chunk.  Lane (s, h): s in 0..31 is the pair slot (every 32nd pair of the
+// chunk), h picks rows 0..4 or 5..8 of the 9x9 block, so each lane holds its
+// rows in registers and every observation record is read once per pair.
+// Off-diagonal blocks S_rc = -sum Y_u Y_w^T over pairs in the same segment
+// (Eq. 10); diagonal blocks S_rr = sum J_c^T M J_c + lambda diag(U_r) and
+// b_r = -sum J_c^T r (Eq. 13).  Blocks of cameras in different clusters are
+// dropped (S' is cluster-diagonal).  The 32 slots are summed by a butterfly
+// (bit-identical in every lane).  A block of one chunk is written directly; a
+// block of several chunks stores one partial sum per chunk and k_schur_reduce
+// adds them in chunk order, so the result does not depend on scheduling.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_schur(const int64_t *__restrict__ n_blocks_p, const int2 *__restrict__ blk_key,
+__device__ inline void schur_butterfly(T (&acc)[5][9], T (&du)[5], T (&rb)[5], bool diag) {
+#pragma unroll
+    for (int d = 2; d < 64; d <<= 1) {
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) acc[i][k] += __shfl_xor(acc[i][k], d, 64);
+        }
+        if (diag) {
+#pragma unroll
+            for (int i = 0; i < 5; ++i) {
+                du[i] += __shfl_xor(du[i], d, 64);
+                rb[i] += __shfl_xor(rb[i], d, 64);
+            }
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_schur(SchurChunks ch, const int2 *__restrict__ blk_key,
                                                const int64_t *__restrict__ blk_start,
                                                const uint64_t *__restrict__ pairs,
                                                const int32_t *__restrict__ cam_cluster, int32_t l,
@@ -430,87 +479,155 @@ __global__ __launch_bounds__(256) void k_schur(const int64_t *__restrict__ n_blo
                                                double *__restrict__ S, double *__restrict__ b) {
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const int g = lane / 9;
-    const int e = lane - 9 * g;
-    const bool act = lane < 63;
-    const int64_t nb = n_blocks_p[0];
+    const int slot = lane >> 1;
+    const int e0 = 5 * (lane & 1);   // rows e0..e0+4; row 9 of the upper half is computed and dropped
+    const int64_t nc = ch.n_chunks[0];
     const double lam = lam2[0];
     const int64_t wstride = (int64_t)gridDim.x * 4;
-    for (int64_t blk = (int64_t)blockIdx.x * 4 + wv; blk < nb; blk += wstride) {
-        const int2 key = blk_key[blk];
+    for (int64_t item = (int64_t)blockIdx.x * 4 + wv; item < nc; item += wstride) {
+        const int32_t bk = ch.chunk_blk[item];
+        const int2 key = blk_key[bk];
         const int32_t r = key.x, c = key.y;
         const int32_t kr = cam_cluster[r];
         if (kr < 0 || kr >= l || cam_cluster[c] != kr) continue;
         const int64_t Np = cl_Np[kr];
         if (Np == 0) continue;   // the map was rejected by the cluster layout
-        const int64_t s0 = blk_start[blk], s1 = blk_start[blk + 1];
-        T acc[9];
+        const int64_t c0 = ch.blk_chunk_off[bk];
+        const int64_t nch = ch.blk_chunk_off[bk + 1] - c0;
+        const int64_t s0 = blk_start[bk] + (item - c0) * kSchurChunk;
+        const int64_t s1 = min(s0 + (int64_t)kSchurChunk, blk_start[bk + 1]);
+        T acc[5][9], du[5], rb[5];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) acc[k] = (T)0;
-        T du = (T)0, rb = (T)0;
-        if (r == c) {
-            if (act) {
-                for (int64_t p = s0 + g; p < s1; p += 7) {
-                    const int64_t bo = (int64_t)(pairs[p] >> 32);
-                    const T *jc = Jc + 18 * bo;
-                    const T *od = obsd + (int64_t)kObsRec * bo;
-                    const T j0e = jc[e], j1e = jc[9 + e];
-                    const T m00 = od[27], m01 = od[28], m11 = od[29];
-                    const T t0 = j0e * m00 + j1e * m01;
-                    const T t1 = j0e * m01 + j1e * m11;
+        for (int i = 0; i < 5; ++i) {
+            du[i] = rb[i] = (T)0;
 #pragma unroll
-                    for (int k = 0; k < 9; ++k) acc[k] += t0 * jc[k] + t1 * jc[9 + k];
-                    du += j0e * j0e + j1e * j1e;
-                    rb += j0e * od[30] + j1e * od[31];
+            for (int k = 0; k < 9; ++k) acc[i][k] = (T)0;
+        }
+        const bool diag = r == c;
+        if (diag) {
+            // pairs of a diagonal block are (a, a): J_c^T M J_c, diag(J_c^T J_c), J_c^T r
+            for (int64_t p = s0 + slot; p < s1; p += 32) {
+                const int64_t a = (int64_t)(pairs[p] >> 32);
+                const T *jc = Jc + 18 * a;
+                const T *od = obsd + (int64_t)kObsRec * a;
+                T t0[9], t1[9];
+                const T m00 = od[27], m01 = od[28], m11 = od[29], r0 = od[30], r1 = od[31];
+#pragma unroll
+                for (int k = 0; k < 9; ++k) {
+                    const T j0 = jc[k], j1 = jc[9 + k];
+                    t0[k] = m00 * j0 + m01 * j1;
+                    t1[k] = m01 * j0 + m11 * j1;
+                }
+#pragma unroll
+                for (int i = 0; i < 5; ++i) {
+                    const int e = min(e0 + i, 8);
+                    const T je0 = jc[e], je1 = jc[9 + e];
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) acc[i][k] += je0 * t0[k] + je1 * t1[k];
+                    du[i] += je0 * je0 + je1 * je1;
+                    rb[i] += je0 * r0 + je1 * r1;
                 }
             }
         } else {
-            if (act) {
-                for (int64_t p = s0 + g; p < s1; p += 7) {
-                    const uint64_t pr = pairs[p];
-                    const int64_t u = (int64_t)(pr >> 32), w = (int64_t)(pr & 0xFFFFFFFFull);
-                    if (seg_head[u] != seg_head[w]) continue;
-                    const T *yu = obsd + (int64_t)kObsRec * u + 3 * e;
-                    const T *yw = obsd + (int64_t)kObsRec * w;
-                    const T y0 = yu[0], y1 = yu[1], y2 = yu[2];
+            for (int64_t p = s0 + slot; p < s1; p += 32) {
+                const uint64_t pr = pairs[p];
+                const int64_t u = (int64_t)(pr >> 32), w = (int64_t)(pr & 0xFFFFFFFFull);
+                if (seg_head[u] != seg_head[w]) continue;
+                const T *yw = obsd + (int64_t)kObsRec * w;
+                const T *yu = obsd + (int64_t)kObsRec * u + 3 * e0;   // rows e0.. (row 9: still inside the record)
+                T y[27];
 #pragma unroll
-                    for (int k = 0; k < 9; ++k) acc[k] += y0 * yw[3 * k] + y1 * yw[3 * k + 1] + y2 * yw[3 * k + 2];
+                for (int k = 0; k < 27; ++k) y[k] = yw[k];
+#pragma unroll
+                for (int i = 0; i < 5; ++i) {
+                    const T a0 = yu[3 * i], a1 = yu[3 * i + 1], a2 = yu[3 * i + 2];
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) acc[i][k] += a0 * y[3 * k] + a1 * y[3 * k + 1] + a2 * y[3 * k + 2];
                 }
             }
         }
-        // fixed-order sum over the 7 pair slots g of each row e: g += g+4, g += g+2, g += g+1
+        schur_butterfly<T>(acc, du, rb, diag);
+        // slot k < 9 of each half holds column k of its rows
+        T col[5];
 #pragma unroll
-        for (int d = 36; d >= 9; d >>= 1) {
-            const bool take = lane + d < 63;
+        for (int i = 0; i < 5; ++i) {
+            col[i] = acc[i][0];
 #pragma unroll
-            for (int k = 0; k < 9; ++k) {
-                const T o = __shfl_down(acc[k], d, 64);
-                if (take) acc[k] += o;
-            }
-            const T od = __shfl_down(du, d, 64);
-            const T orb = __shfl_down(rb, d, 64);
-            if (take) {
-                du += od;
-                rb += orb;
-            }
+            for (int k = 1; k < 9; ++k)
+                if (slot == k) col[i] = acc[i][k];
         }
-        if (lane < 9) {
+        if (slot >= 9) continue;
+        const int nrow = e0 == 0 ? 5 : 4;
+        if (nch == 1) {
             double *A = S + S_off[kr];
             const int64_t lr = cam_local[r];
-            const int64_t row = 9 * lr + e;
-            if (r == c) {
-#pragma unroll
-                for (int k = 0; k < 9; ++k) {
-                    double v = (double)acc[k];
-                    if (k == e) v += lam * (double)du;
-                    A[row + (9 * lr + k) * Np] = v;
+            const int64_t lc = cam_local[c];
+            double *colp = A + 9 * lr + (9 * lc + slot) * Np;
+            for (int i = 0; i < nrow; ++i) {
+                const int e = e0 + i;
+                double v = (double)col[i];
+                if (diag) {
+                    if (e == slot) v += lam * (double)du[i];
+                } else {
+                    v = -v;
                 }
-                b[9 * (int64_t)r + e] = -(double)rb;
-            } else {
-                const int64_t lc = cam_local[c];
-#pragma unroll
-                for (int k = 0; k < 9; ++k) A[row + (9 * lc + k) * Np] = -(double)acc[k];
+                colp[e] = v;
             }
+            if (diag && slot == 0)
+                for (int i = 0; i < nrow; ++i) b[9 * (int64_t)r + e0 + i] = -(double)rb[i];
+        } else {
+            double *mine = ch.part + item * kSchurPart;
+            for (int i = 0; i < nrow; ++i) mine[9 * (e0 + i) + slot] = (double)col[i];
+            if (diag && slot == 0)
+                for (int i = 0; i < nrow; ++i) {
+                    mine[81 + e0 + i] = (double)du[i];
+                    mine[90 + e0 + i] = (double)rb[i];
+                }
+        }
+    }
+}
+
+// Blocks of several chunks: 81 threads per block add the partial sums in chunk
+// order and write the block (and b_r for a diagonal block).
+__global__ __launch_bounds__(128) void k_schur_reduce(SchurChunks ch, const int64_t *__restrict__ n_blocks_p,
+                                                      const int2 *__restrict__ blk_key,
+                                                      const int32_t *__restrict__ cam_cluster, int32_t l,
+                                                      const int32_t *__restrict__ cam_local,
+                                                      const int32_t *__restrict__ cl_Np,
+                                                      const int64_t *__restrict__ S_off,
+                                                      const double *__restrict__ lam2, double *__restrict__ S,
+                                                      double *__restrict__ b) {
+    const int64_t nb = n_blocks_p[0];
+    const int t = threadIdx.x;
+    const double lam = lam2[0];
+    for (int64_t bk = blockIdx.x; bk < nb; bk += gridDim.x) {
+        const int64_t c0 = ch.blk_chunk_off[bk];
+        const int64_t nch = ch.blk_chunk_off[bk + 1] - c0;
+        if (nch < 2) continue;
+        const int2 key = blk_key[bk];
+        const int32_t r = key.x, c = key.y;
+        const int32_t kr = cam_cluster[r];
+        if (kr < 0 || kr >= l || cam_cluster[c] != kr) continue;
+        const int64_t Np = cl_Np[kr];
+        if (Np == 0) continue;
+        const bool diag = r == c;
+        if (t >= 90 || (!diag && t >= 81)) continue;
+        const double *q = ch.part + c0 * kSchurPart;
+        if (t < 81) {
+            const int e = t / 9, k = t - 9 * (t / 9);
+            double v = 0.0, dv = 0.0;
+            for (int64_t j = 0; j < nch; ++j) v += q[j * kSchurPart + t];
+            if (diag && e == k) {
+                for (int64_t j = 0; j < nch; ++j) dv += q[j * kSchurPart + 81 + e];
+                v += lam * dv;
+            }
+            double *A = S + S_off[kr];
+            A[9 * cam_local[r] + e + (9 * (int64_t)cam_local[c] + k) * Np] = diag ? v : -v;
+        } else {
+            const int e = t - 81;
+            double v = 0.0;
+            for (int64_t j = 0; j < nch; ++j) v += q[j * kSchurPart + 90 + e];
+            b[9 * (int64_t)r + e] = -v;
         }
     }
 }
@@ -740,21 +857,22 @@ hipError_t launch_set_damping(double *slot, double lambda, double lambda_corr, h
 template <typename T>
 hipError_t launch_points(const stba_problem &p, const int64_t *pt_off, const int32_t *cam_cluster, int32_t l,
                          const T *f, const T *Jc, const T *Jp, const double *lam2, uint64_t seed, uint64_t t,
-                         uint64_t thr, int32_t *seg_head, T *obsd, double *Vinv, double *wph, int32_t *status,
-                         hipStream_t st) {
+                         uint64_t thr, int32_t *seg_head, double *seg_rec, T *obsd, double *Vinv, double *wph,
+                         int32_t *status, hipStream_t st) {
     (void)l;
-    k_points<T><<<grid_for(p.n), 256, 0, st>>>(p.n, pt_off, p.obs_cam, cam_cluster, f, Jc, Jp, lam2, seed, t, thr,
-                                               seg_head, obsd, Vinv, wph, status);
+    k_points<T><<<grid_for(p.n, 64), 64, 0, st>>>(p.n, pt_off, p.obs_cam, cam_cluster, f, Jp, lam2, seed, t, thr,
+                                                  seg_head, seg_rec, Vinv, wph, status);
+    k_obs_rec<T><<<grid_for(p.q), 256, 0, st>>>(p.q, seg_head, seg_rec, f, Jc, Jp, obsd);
     return hipGetLastError();
 }
 template hipError_t launch_points<double>(const stba_problem &, const int64_t *, const int32_t *, int32_t,
                                           const double *, const double *, const double *, const double *, uint64_t,
-                                          uint64_t, uint64_t, int32_t *, double *, double *, double *, int32_t *,
-                                          hipStream_t);
+                                          uint64_t, uint64_t, int32_t *, double *, double *, double *, double *,
+                                          int32_t *, hipStream_t);
 template hipError_t launch_points<float>(const stba_problem &, const int64_t *, const int32_t *, int32_t,
                                          const float *, const float *, const float *, const double *, uint64_t,
-                                         uint64_t, uint64_t, int32_t *, float *, double *, double *, int32_t *,
-                                         hipStream_t);
+                                         uint64_t, uint64_t, int32_t *, double *, float *, double *, double *,
+                                         int32_t *, hipStream_t);
 
 hipError_t launch_fill_S(double *S, double *b, int32_t m, const int64_t *S_off, int32_t l, int64_t S_cap,
                          const int32_t *cl_n, const int32_t *cl_Np, hipStream_t st) {
@@ -767,26 +885,31 @@ hipError_t launch_fill_S(double *S, double *b, int32_t m, const int64_t *S_off, 
 }
 
 template <typename T>
-hipError_t launch_schur(const int64_t *n_blocks, int64_t n_blocks_cap, const int2 *blk_key,
+hipError_t launch_schur(const int64_t *n_blocks, int64_t n_blocks_cap, const SchurChunks &ch, const int2 *blk_key,
                         const int64_t *blk_start, const uint64_t *pairs, const int32_t *cam_cluster, int32_t l,
                         const int32_t *cam_local, const int32_t *cl_Np, const int64_t *S_off,
                         const int32_t *seg_head, const T *Jc, const T *obsd, const double *lam2, double *S,
                         double *b, hipStream_t st) {
-    int64_t wgs = (n_blocks_cap + 3) / 4;
+    int64_t wgs = (ch.chunk_cap + 3) / 4;
     if (wgs > 16384) wgs = 16384;
     if (wgs < 1) wgs = 1;
-    k_schur<T><<<(unsigned)wgs, 256, 0, st>>>(n_blocks, blk_key, blk_start, pairs, cam_cluster, l, cam_local, cl_Np,
+    k_schur<T><<<(unsigned)wgs, 256, 0, st>>>(ch, blk_key, blk_start, pairs, cam_cluster, l, cam_local, cl_Np,
                                               S_off, seg_head, Jc, obsd, lam2, S, b);
+    int64_t rb = n_blocks_cap;
+    if (rb > 8192) rb = 8192;
+    if (rb < 1) rb = 1;
+    k_schur_reduce<<<(unsigned)rb, 128, 0, st>>>(ch, n_blocks, blk_key, cam_cluster, l, cam_local, cl_Np, S_off, lam2,
+                                                 S, b);
     return hipGetLastError();
 }
-template hipError_t launch_schur<double>(const int64_t *, int64_t, const int2 *, const int64_t *, const uint64_t *,
-                                         const int32_t *, int32_t, const int32_t *, const int32_t *,
-                                         const int64_t *, const int32_t *, const double *, const double *,
-                                         const double *, double *, double *, hipStream_t);
-template hipError_t launch_schur<float>(const int64_t *, int64_t, const int2 *, const int64_t *, const uint64_t *,
-                                        const int32_t *, int32_t, const int32_t *, const int32_t *, const int64_t *,
-                                        const int32_t *, const float *, const float *, const double *, double *,
-                                        double *, hipStream_t);
+template hipError_t launch_schur<double>(const int64_t *, int64_t, const SchurChunks &, const int2 *, const int64_t *,
+                                         const uint64_t *, const int32_t *, int32_t, const int32_t *,
+                                         const int32_t *, const int64_t *, const int32_t *, const double *,
+                                         const double *, const double *, double *, double *, hipStream_t);
+template hipError_t launch_schur<float>(const int64_t *, int64_t, const SchurChunks &, const int2 *, const int64_t *,
+                                        const uint64_t *, const int32_t *, int32_t, const int32_t *, const int32_t *,
+                                        const int64_t *, const int32_t *, const float *, const float *,
+                                        const double *, double *, double *, hipStream_t);
 
 template <typename T>
 hipError_t launch_backsub(const stba_problem &p, const int64_t *pt_off, const T *Jc, const T *Jp,

@@ -20,6 +20,11 @@ struct PrepBufs {
     int64_t *blk_start;   // [n_pairs + 1] first pair of each block
     int64_t *n_blocks;    // [1]
     int64_t *diag_blk;    // [m] block index of camera pair (i, i)
+    int64_t blk_cap;         // bound on the number of blocks: min(n_pairs, m (m + 1) / 2)
+    int64_t *blk_chunk_off;  // [blk_cap + 1] first chunk of each block (chunks of kSchurChunk pairs)
+    int32_t *chunk_blk;      // [chunk_cap] block of each chunk
+    int64_t chunk_cap;       // blk_cap + n_pairs / kSchurChunk + 1
+    int64_t *n_chunks;       // [1]
     void *tmp;            // rocPRIM temporary storage
     size_t tmp_bytes;
 };
@@ -46,14 +51,21 @@ hipError_t launch_set_damping(double *slot, double lambda, double lambda_corr, h
 template <typename T>
 hipError_t launch_points(const stba_problem &p, const int64_t *pt_off, const int32_t *cam_cluster, int32_t l,
                          const T *f, const T *Jc, const T *Jp, const double *lam2, uint64_t seed, uint64_t t,
-                         uint64_t thr, int32_t *seg_head, T *obsd, double *Vinv, double *wph, int32_t *status,
-                         hipStream_t st);
+                         uint64_t thr, int32_t *seg_head, double *seg_rec, T *obsd, double *Vinv, double *wph,
+                         int32_t *status, hipStream_t st);
 
 hipError_t launch_fill_S(double *S, double *b, int32_t m, const int64_t *S_off, int32_t l, int64_t S_cap,
                          const int32_t *cl_n, const int32_t *cl_Np, hipStream_t st);
 
+struct SchurChunks {
+    const int64_t *n_chunks;
+    const int64_t *blk_chunk_off;
+    const int32_t *chunk_blk;
+    int64_t chunk_cap;
+    double *part;          // partial sums, kSchurPart doubles per chunk
+};
 template <typename T>
-hipError_t launch_schur(const int64_t *n_blocks, int64_t n_blocks_cap, const int2 *blk_key,
+hipError_t launch_schur(const int64_t *n_blocks, int64_t n_blocks_cap, const SchurChunks &ch, const int2 *blk_key,
                         const int64_t *blk_start, const uint64_t *pairs, const int32_t *cam_cluster, int32_t l,
                         const int32_t *cam_local, const int32_t *cl_Np, const int64_t *S_off,
                         const int32_t *seg_head, const T *Jc, const T *obsd, const double *lam2, double *S,

@@ -107,6 +107,33 @@ __global__ __launch_bounds__(256) void k_scatter_heads(int64_t np, int32_t m, co
     }
 }
 
+// chunks of each block for the Schur assembly (zero past the last block)
+__global__ __launch_bounds__(256) void k_block_chunks(int64_t cap, const int64_t *n_blocks, const int64_t *blk_start,
+                                                      int64_t *nch) {
+    const int64_t nb = n_blocks[0];
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b <= cap; b += (int64_t)gridDim.x * blockDim.x) {
+        int64_t c = 0;
+        if (b < nb) {
+            const int64_t len = blk_start[b + 1] - blk_start[b];
+            c = (len + kSchurChunk - 1) / kSchurChunk;
+        }
+        nch[b] = c;
+    }
+}
+
+// block index of every chunk
+__global__ __launch_bounds__(256) void k_chunk_blk(const int64_t *n_blocks, const int64_t *blk_chunk_off,
+                                                   int32_t *chunk_blk) {
+    const int64_t nb = n_blocks[0];
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x) {
+        for (int64_t c = blk_chunk_off[b]; c < blk_chunk_off[b + 1]; ++c) chunk_blk[c] = (int32_t)b;
+    }
+}
+
+__global__ void k_total_chunks(const int64_t *n_blocks, const int64_t *blk_chunk_off, int64_t *n_chunks) {
+    n_chunks[0] = blk_chunk_off[n_blocks[0]];
+}
+
 __global__ void k_fill_i64(int64_t *a, int64_t len, int64_t v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < len) a[i] = v;
@@ -137,7 +164,7 @@ size_t prepare_tmp_bytes(int64_t n_pairs, int32_t m, hipStream_t st) {
                               (uint64_t *)nullptr, (size_t)n_pairs, 0u, key_bits(m), st);
     // the scans run over n points and n_pairs pairs; n <= n_pairs
     (void)rocprim::exclusive_scan((void *)nullptr, b, (int64_t *)nullptr, (int64_t *)nullptr, (int64_t)0,
-                            (size_t)n_pairs, rocprim::plus<int64_t>(), st);
+                            (size_t)n_pairs + 1, rocprim::plus<int64_t>(), st);
     return a > b ? a : b;
 }
 
@@ -162,6 +189,15 @@ hipError_t launch_prepare(const stba_problem &p, int64_t np, const PrepBufs &b, 
     k_fill_i64<<<grid_for(p.m), 256, 0, st>>>(b.diag_blk, p.m, -1);
     k_scatter_heads<<<grid_for(np), 256, 0, st>>>(np, p.m, b.keys_out, b.scratch_a, b.blk_of, b.blk_key,
                                                   b.blk_start, b.n_blocks, b.diag_blk);
+    // Schur work items: chunk counts into the (now free) sort buffer, exclusive scan, chunk -> block
+    int64_t *nch = reinterpret_cast<int64_t *>(b.keys_in);
+    k_block_chunks<<<grid_for(b.blk_cap + 1), 256, 0, st>>>(b.blk_cap, b.n_blocks, b.blk_start, nch);
+    tb = b.tmp_bytes;
+    e = rocprim::exclusive_scan(b.tmp, tb, nch, b.blk_chunk_off, (int64_t)0, (size_t)b.blk_cap + 1,
+                                rocprim::plus<int64_t>(), st);
+    if (e != hipSuccess) return e;
+    k_chunk_blk<<<grid_for(b.blk_cap), 256, 0, st>>>(b.n_blocks, b.blk_chunk_off, b.chunk_blk);
+    k_total_chunks<<<1, 1, 0, st>>>(b.n_blocks, b.blk_chunk_off, b.n_chunks);
     return hipGetLastError();
 }
 

@@ -12,11 +12,12 @@ struct Layout {
     size_t status, lam2;
     // static plan (stba_prepare)
     size_t pt_off, pair_off, scratch_a, keys_in, keys_out, vals_in, pairs, blk_of, blk_key, blk_start, n_blocks,
-        diag_blk, tmp;
+        diag_blk, blk_chunk_off, chunk_blk, n_chunks, part, tmp;
+    int64_t blk_cap, chunk_cap;
     size_t tmp_bytes;
     // per iteration
     size_t cl_n, cl_Np, cl_start, cl_cams, cam_local, cl_status, S_off;
-    size_t f, Jc, Jp, seg_head, obsd, Vinv, wph, S, b, dcam, dpt, partials;
+    size_t f, Jc, Jp, seg_head, seg_rec, obsd, Vinv, wph, S, b, dcam, dpt, partials;
     int64_t S_cap, n_partials;
     int32_t max_Np;
     size_t total;
@@ -72,15 +73,24 @@ bool make_layout(const stba_problem *p, const stba_dims *d, int precision, Layou
     L.pt_off = take(8 * (n + 1));
     L.pair_off = take(8 * (n + 1));
     L.scratch_a = take(8 * np);
-    L.keys_in = take(8 * np);
+    L.keys_in = take(8 * (np + 1));
     L.keys_out = take(8 * np);
-    L.vals_in = take(8 * np);
+    L.vals_in = take(8 * (np + 1));
     L.pairs = take(8 * np);
     L.blk_of = take(8 * np);
     L.blk_key = take(8 * np);
     L.blk_start = take(8 * (np + 1));
     L.n_blocks = take(8);
     L.diag_blk = take(8 * m);
+    // blocks are camera pairs (r, c), r >= c, with at least one pair each
+    L.blk_cap = (int64_t)np;
+    if ((int64_t)m * ((int64_t)m + 1) / 2 < L.blk_cap) L.blk_cap = (int64_t)m * ((int64_t)m + 1) / 2;
+    // a block of len pairs has ceil(len / chunk) <= 1 + len / chunk chunks
+    L.chunk_cap = L.blk_cap + (int64_t)np / kSchurChunk + 1;
+    L.blk_chunk_off = take(8 * (size_t)(L.blk_cap + 1));
+    L.chunk_blk = take(4 * (size_t)L.chunk_cap);
+    L.n_chunks = take(8);
+    L.part = take(8 * (size_t)kSchurPart * (size_t)L.chunk_cap);
     L.tmp_bytes = prepare_tmp_bytes(d->n_pairs, p->m, 0);
     L.tmp = take(L.tmp_bytes);
     L.cl_n = take(4 * m);
@@ -94,6 +104,7 @@ bool make_layout(const stba_problem *p, const stba_dims *d, int precision, Layou
     L.Jc = take(es * 18 * q);
     L.Jp = take(es * 6 * q);
     L.seg_head = take(4 * q);
+    L.seg_rec = take(8 * (size_t)kSegRec * q);
     L.obsd = take(es * kObsRec * q);
     L.Vinv = take(8 * 6 * n);
     L.wph = take(8 * 3 * n);
@@ -142,6 +153,16 @@ int front(const stba_problem *p, const stba_dims *d, int precision, void *ws, si
     return check_ws(L, ws, ws_bytes);
 }
 
+SchurChunks chunks_of(const Layout &L, void *ws) {
+    SchurChunks c;
+    c.n_chunks = at<int64_t>(ws, L.n_chunks);
+    c.blk_chunk_off = at<int64_t>(ws, L.blk_chunk_off);
+    c.chunk_blk = at<int32_t>(ws, L.chunk_blk);
+    c.chunk_cap = L.chunk_cap;
+    c.part = at<double>(ws, L.part);
+    return c;
+}
+
 template <typename T>
 int build_rcs_impl(const stba_problem *p, const stba_dims *d, const stba_sample *s, const double *lam2,
                    const T *f, const T *Jc, const T *Jp, const Layout &L, void *ws, hipStream_t st) {
@@ -150,11 +171,11 @@ int build_rcs_impl(const stba_problem *p, const stba_dims *d, const stba_sample 
                              at<int32_t>(ws, L.cl_Np), at<int32_t>(ws, L.cl_start), at<int32_t>(ws, L.cl_cams),
                              at<int32_t>(ws, L.cam_local), at<int64_t>(ws, L.S_off), status, st));
     STBA_HIP(launch_points<T>(*p, at<int64_t>(ws, L.pt_off), s->cam_cluster, s->l, f, Jc, Jp, lam2, s->seed, s->iter,
-                              keep_threshold(s->alpha), at<int32_t>(ws, L.seg_head), at<T>(ws, L.obsd),
+                              keep_threshold(s->alpha), at<int32_t>(ws, L.seg_head), at<double>(ws, L.seg_rec), at<T>(ws, L.obsd),
                               at<double>(ws, L.Vinv), at<double>(ws, L.wph), status, st));
     STBA_HIP(launch_fill_S(at<double>(ws, L.S), at<double>(ws, L.b), p->m, at<int64_t>(ws, L.S_off), s->l, L.S_cap,
                            at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np), st));
-    STBA_HIP(launch_schur<T>(at<int64_t>(ws, L.n_blocks), d->n_pairs, at<int2>(ws, L.blk_key),
+    STBA_HIP(launch_schur<T>(at<int64_t>(ws, L.n_blocks), L.blk_cap, chunks_of(L, ws), at<int2>(ws, L.blk_key),
                              at<int64_t>(ws, L.blk_start), at<uint64_t>(ws, L.pairs), s->cam_cluster, s->l,
                              at<int32_t>(ws, L.cam_local), at<int32_t>(ws, L.cl_Np), at<int64_t>(ws, L.S_off),
                              at<int32_t>(ws, L.seg_head), Jc, at<T>(ws, L.obsd), lam2, at<double>(ws, L.S),
@@ -194,13 +215,13 @@ int lm_step_impl(const stba_problem *p, const stba_dims *d, const stba_sample *s
     STBA_HIP(launch_init_cost(at<double>(ws, L.partials), L.n_partials, stt, st));
     STBA_TRY(mark(2));
     STBA_HIP(launch_points<T>(*p, at<int64_t>(ws, L.pt_off), s->cam_cluster, s->l, f, Jc, Jp, lam2, s->seed, s->iter,
-                              keep_threshold(s->alpha), at<int32_t>(ws, L.seg_head), at<T>(ws, L.obsd),
+                              keep_threshold(s->alpha), at<int32_t>(ws, L.seg_head), at<double>(ws, L.seg_rec), at<T>(ws, L.obsd),
                               at<double>(ws, L.Vinv), at<double>(ws, L.wph), status, st));
     STBA_TRY(mark(3));
     STBA_HIP(launch_fill_S(at<double>(ws, L.S), at<double>(ws, L.b), p->m, at<int64_t>(ws, L.S_off), s->l, L.S_cap,
                            at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np), st));
     STBA_TRY(mark(4));
-    STBA_HIP(launch_schur<T>(at<int64_t>(ws, L.n_blocks), d->n_pairs, at<int2>(ws, L.blk_key),
+    STBA_HIP(launch_schur<T>(at<int64_t>(ws, L.n_blocks), L.blk_cap, chunks_of(L, ws), at<int2>(ws, L.blk_key),
                              at<int64_t>(ws, L.blk_start), at<uint64_t>(ws, L.pairs), s->cam_cluster, s->l,
                              at<int32_t>(ws, L.cam_local), at<int32_t>(ws, L.cl_Np), at<int64_t>(ws, L.S_off),
                              at<int32_t>(ws, L.seg_head), Jc, at<T>(ws, L.obsd), lam2, at<double>(ws, L.S),
@@ -278,6 +299,11 @@ int stba_prepare(const stba_problem *p, const stba_dims *dims, int precision, vo
     b.blk_start = at<int64_t>(ws, L.blk_start);
     b.n_blocks = at<int64_t>(ws, L.n_blocks);
     b.diag_blk = at<int64_t>(ws, L.diag_blk);
+    b.blk_chunk_off = at<int64_t>(ws, L.blk_chunk_off);
+    b.blk_cap = L.blk_cap;
+    b.chunk_blk = at<int32_t>(ws, L.chunk_blk);
+    b.chunk_cap = L.chunk_cap;
+    b.n_chunks = at<int64_t>(ws, L.n_chunks);
     b.tmp = at<void>(ws, L.tmp);
     b.tmp_bytes = L.tmp_bytes;
     STBA_HIP(launch_reset_status(at<int32_t>(ws, L.status), stream));
