@@ -30,68 +30,100 @@ __device__ inline double readlane_d(double v, int l) {
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-// Diagonal tile (rows/cols off..off+31), one wavefront, registers only.  Lane r
-// owns row r (lanes 32..63 mirror rows 0..31).  L = chol(A_pp) right-looking with
-// the pivot column broadcast by v_readlane; entries above the diagonal hold
-// don't-care values, so the updates carry no predicate.  Then W = L^-1, lane c
-// computing column c by forward substitution with L[rr][k] read from lane rr.
-// Writes L to the lower triangle of A, W^T to its strict upper triangle, W to
-// LDS, and replaces x_p by y_p = W x_p.  Returns true if a pivot failed.
-__device__ __attribute__((noinline)) bool diag_factor_invert(double *A, int64_t Np, int64_t off, int lane, double (*Wi)[kNB + 1],
-                                          double *x) {
+// Diagonal tile (rows/cols off..off+31), one wavefront.  Lane r owns row r of
+// the tile in registers (lanes 32..63 mirror rows 0..31).
+//   Factor, right-looking: at step k the pivot comes from lane k (v_readlane),
+//   every lane scales its entry of column k and writes it to LDS, and all lanes
+//   read the column back (LDS operations of one wavefront complete in order) to
+//   update their row.  Entries above the diagonal are carried as don't-care
+//   values so that no update is predicated.
+//   Invert, W = L^-1: lane c forward-substitutes column c, reading the rows of L
+//   from LDS (the same address in every lane).
+// kTile = false: the tile is read from A; L (with its diagonal) goes to the
+//   lower triangle of A, W^T to the strict upper triangle, and x_p (LDS) is
+//   replaced by y_p = W x_p.
+// kTile = true: the tile is read from Ls (row-major); the lower triangle of A
+//   receives L without its diagonal, the upper triangle with the diagonal
+//   receives W^T (so the diagonal holds 1 / L_rr), all with device-scope stores.
+// Both leave W row-major in Wi.  Returns true if a pivot was not positive.
+template <bool kTile>
+__device__ __forceinline__ bool diag_factor_invert(double *A, int64_t Np, int64_t off, int lane,
+                                                             double (*Ls)[kNB + 1], double (*Wi)[kNB + 1],
+                                                             double *col, double *x) {
     const int r = lane & (kNB - 1);
     double a[kNB];
 #pragma unroll
-    for (int j = 0; j < kNB; ++j) a[j] = A[(off + r) + (off + j) * Np];
+    for (int j = 0; j < kNB; ++j) a[j] = kTile ? Ls[r][j] : A[(off + r) + (off + j) * Np];
     bool bad = false;
-    int rq = r;
+    // scheduling barriers keep each step's instructions together, so that the
+    // unrolled steps are not interleaved into more live registers than exist
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int k = 0; k < kNB; ++k) {
-        // make the lane index opaque per step so the lane-mask compares of all 32
-        // steps are not hoisted into SGPRs at once
-        asm volatile("" : "+v"(rq));
         double d = readlane_d(a[k], k);
         if (!(d > 0.0) || !isfinite(d)) {
             bad = true;
             d = 1.0;
         }
-        const double s = sqrt(d);
-        const double is = 1.0 / s;
-        a[k] = (rq == k) ? s : ((rq > k) ? a[k] * is : 0.0);
-        // readlane results live in SGPRs: consume them in chunks of 8 so that at
-        // most 16 SGPRs are live at a time (scheduling barriers stop hoisting)
+        const double sd = sqrt(d);
+        const double is = 1.0 / sd;
+        a[k] = (r == k) ? sd : ((r > k) ? a[k] * is : 0.0);
+        if (lane == 0) col[kNB + k] = is;
+        if (k + 1 < kNB) {
+            col[r] = a[k];
 #pragma unroll
-        for (int j = k + 1; j < kNB; ++j) {
-            a[j] = fma(-a[k], readlane_d(a[k], j), a[j]);
-            if (((j - k) & 7) == 0) __builtin_amdgcn_sched_barrier(0);
+            for (int j = k + 1; j < kNB; ++j) a[j] = fma(-a[k], col[j], a[j]);
+            // pin the updated row here: otherwise the updates are sunk to the
+            // next use of each entry and every column read stays live
+#pragma unroll
+            for (int j = k + 1; j < kNB; ++j) asm volatile("" : "+v"(a[j]));
         }
         __builtin_amdgcn_sched_barrier(0);
     }
+    // L row r to LDS (zero above the diagonal) and to A
+    if (lane < kNB) {
+#pragma unroll
+        for (int j = 0; j < kNB; ++j) {
+            const double v = j <= r ? a[j] : 0.0;
+            Ls[r][j] = v;
+            if (kTile) {
+                if (j < r)
+                    __hip_atomic_store(A + (off + r) + (off + j) * Np, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                if (j <= r) A[(off + r) + (off + j) * Np] = v;
+            }
+        }
+    }
+    __syncwarp();
     const int c = r;
     double w[kNB];
-    int cq = c;
 #pragma unroll
     for (int rr = 0; rr < kNB; ++rr) {
-        asm volatile("" : "+v"(cq));
-        double s0 = (cq == rr) ? 1.0 : 0.0, s1 = 0.0;
+        double s0 = (c == rr) ? 1.0 : 0.0, s1 = 0.0;
 #pragma unroll
         for (int k = 0; k < rr; ++k) {
-            if (k & 1) s1 = fma(-readlane_d(a[k], rr), w[k], s1);
-            else s0 = fma(-readlane_d(a[k], rr), w[k], s0);
-            if ((k & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+            if (k & 1) s1 = fma(-Ls[rr][k], w[k], s1);
+            else s0 = fma(-Ls[rr][k], w[k], s0);
         }
-        w[rr] = (s0 + s1) / readlane_d(a[rr], rr);
+        w[rr] = (s0 + s1) * col[kNB + rr];
+        asm volatile("" : "+v"(w[rr]));
         __builtin_amdgcn_sched_barrier(0);
     }
     if (lane < kNB) {
 #pragma unroll
         for (int j = 0; j < kNB; ++j) {
-            if (j <= r) A[(off + r) + (off + j) * Np] = a[j];   // L (lower, with diagonal)
-            else A[(off + r) + (off + j) * Np] = w[j];           // W^T: W[j][r] at (row r, column j)
             Wi[j][c] = w[j];
+            if (kTile) {
+                if (j >= r)
+                    __hip_atomic_store(A + (off + r) + (off + j) * Np, w[j], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);   // W^T: W[j][r] at (row r, column j)
+            } else {
+                if (j > r) A[(off + r) + (off + j) * Np] = w[j];
+            }
         }
     }
     __syncwarp();
+    if (kTile) return bad;
     double y = 0.0;
 #pragma unroll 8
     for (int j = 0; j < kNB; ++j) y = fma(Wi[c][j], x[off + j], y);
@@ -188,7 +220,9 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(int32_t l, const int32_t 
                                                        int32_t *__restrict__ cl_status, int32_t max_Np) {
     extern __shared__ double smem[];
     double(*Wi)[kNB + 1] = reinterpret_cast<double(*)[kNB + 1]>(smem);
-    double *x = smem + kNB * (kNB + 1);
+    double(*Ls)[kNB + 1] = reinterpret_cast<double(*)[kNB + 1]>(smem + kNB * (kNB + 1));
+    double *col = smem + 2 * kNB * (kNB + 1);   // 2 kNB
+    double *x = col + 2 * kNB;
     double *red = x + max_Np;             // kCholThreads
     double *zb = red + kCholThreads;      // kNB
     __shared__ int bad;
@@ -212,7 +246,7 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(int32_t l, const int32_t 
     // updated first; then wave 0 factors diagonal tile p + 1 while the other
     // waves finish the trailing update of step p.
     if (wave == 0) {
-        const bool fb = diag_factor_invert(A, Np, 0, lane, Wi, x);
+        const bool fb = diag_factor_invert<false>(A, Np, 0, lane, Ls, Wi, col, x);
         if (fb && lane == 0) bad = 1;
     }
     __syncthreads();
@@ -226,7 +260,7 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(int32_t l, const int32_t 
             tile_update(A, Np, (int64_t)i * kNB, (int64_t)q * kNB, off, lane);
         __syncthreads();
         if (wave == 0) {
-            const bool fb = diag_factor_invert(A, Np, (int64_t)q * kNB, lane, Wi, x);
+            const bool fb = diag_factor_invert<false>(A, Np, (int64_t)q * kNB, lane, Ls, Wi, col, x);
             if (fb && lane == 0) bad = 1;
         } else {
             // remaining trailing tiles (i, j), q < j <= i
@@ -277,12 +311,284 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(int32_t l, const int32_t 
     if (tid == 0) cl_status[k] = bad ? STBA_ENOTPD : STBA_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Tile-parallel variant for maps with few clusters: one wavefront per lower
+// 32 x 32 tile (i, j) of every S_k, so a cluster is spread over up to
+// T (T + 1) / 2 compute units instead of one.  The owner of tile (i, j) keeps it
+// in MFMA registers, applies A_ij -= L_ip L_jp^T for p < j as soon as tiles
+// (i, p) and (j, p) are final, then either factors and inverts it (i == j) or
+// solves the panel X = A_ij W_jj^T.  A final tile is written with device-scope
+// stores, and a per-tile flag is raised after the stores have completed; a
+// reader polls the flag and reads the tile with device-scope loads.  This needs
+// no cache write-back or invalidation, since a tile is read by other waves only
+// after it is final.  Every dependency of a task points to an earlier (step,
+// kind, row) key, so with all waves resident the dataflow cannot deadlock; every
+// wait is still bounded, and a time-out raises a grid-wide abort word that ends
+// all other waits (the cluster then reports STBA_EHIP).
+// The diagonal owners then run the two triangular solves as chains:
+//   y_i = W_ii (b_i - sum_{j < i} L_ij y_j),  x_i = W_ii^T (y_i - sum_{k > i} L_ki^T x_k),
+// each sum taken in a fixed order.
+// ---------------------------------------------------------------------------
+constexpr int kWaitPolls = 1 << 20;
+
+__device__ inline double ld_dev(const double *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_dev(double *p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Lane 0 polls *f until it is non-zero or the abort word is set; every lane gets
+// the flag value (0: aborted or timed out).
+__device__ inline int wait_flag(const int32_t *f, int32_t *abort_w) {
+    int v = 0;
+    if ((threadIdx.x & 63) == 0) {
+        for (int it = 0; it < kWaitPolls; ++it) {
+            v = __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (v != 0) break;
+            if (__hip_atomic_load(abort_w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+            __builtin_amdgcn_s_sleep(1);
+        }
+        if (v == 0) __hip_atomic_store(abort_w, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    v = __shfl(v, 0, 64);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    return v;
+}
+
+// Raise *f = v after all earlier stores of the wavefront have completed.
+__device__ inline void raise_flag(int32_t *f, int v) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);
+    if ((threadIdx.x & 63) == 0) __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline int tile_ix(int i, int j) { return i * (i + 1) / 2 + j; }
+
+// Broadcast the 32 values v (lane r holds entry r) through LDS.
+__device__ inline void share32(double *zs, double v, int lane) {
+    __syncwarp();
+    if (lane < kNB) zs[lane] = v;
+    __syncwarp();
+}
+
+// Flags per cluster: [tile (i, j) at i (i + 1) / 2 + j][y_i at tpc + i][x_i at tpc + tmax + i];
+// tile flags are 1 (final) or 2 (final, pivot failed).  The word after the last
+// cluster is the abort word.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_chol_tiles(int32_t tpc, int32_t tmax, int32_t fpc,
+                                                   const int32_t *__restrict__ cl_n,
+                                                   const int32_t *__restrict__ cl_Np,
+                                                   const int64_t *__restrict__ S_off,
+                                                   const int32_t *__restrict__ cl_start,
+                                                   const int32_t *__restrict__ cl_cams, double *__restrict__ S,
+                                                   const double *__restrict__ b, double *__restrict__ dcam,
+                                                   int32_t *__restrict__ cl_status, int32_t *flags, int32_t l,
+                                                   double *yx) {
+    __shared__ double Wi[kNB][kNB + 1];
+    __shared__ double Ls[kNB][kNB + 1];
+    __shared__ __align__(16) double zs[2 * kNB];
+    const int lane = threadIdx.x;
+    const int k = (int)(blockIdx.x / (unsigned)tpc);
+    const int t = (int)(blockIdx.x - (unsigned)k * (unsigned)tpc);
+    int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((i + 1) * (i + 2) / 2 <= t) ++i;
+    while (i * (i + 1) / 2 > t) --i;
+    const int j = t - i * (i + 1) / 2;
+    const int64_t Np = cl_Np[k];
+    const int T = (int)(Np / kNB);
+    if (T == 0) {
+        if (t == 0 && lane == 0) cl_status[k] = STBA_OK;
+        return;
+    }
+    if (i >= T) return;
+    int32_t *fl = flags + (int64_t)k * fpc;
+    int32_t *abort_w = flags + (int64_t)l * fpc;
+    double *A = S + S_off[k];
+    const int64_t ri = (int64_t)i * kNB, cj = (int64_t)j * kNB;
+    const int lr = lane & 15, lk = lane >> 4;
+    bool ok = true;
+    // the tile in the MFMA result layout: acc[R][C][v] = A(ri + 16 R + lr, cj + 16 C + 4 v + lk)
+    d4 acc[2][2];
+#pragma unroll
+    for (int R = 0; R < 2; ++R)
+#pragma unroll
+        for (int C = 0; C < 2; ++C)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[R][C][v] = A[(ri + 16 * R + lr) + (cj + 16 * C + 4 * v + lk) * Np];
+    for (int p = 0; p < j; ++p) {
+        ok &= wait_flag(fl + tile_ix(i, p), abort_w) != 0;
+        if (i != j) ok &= wait_flag(fl + tile_ix(j, p), abort_w) != 0;
+        const int64_t off = (int64_t)p * kNB;
+        double bi[2][8], aj[2][8];
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk) {
+            const int64_t col = (off + 4 * kk + lk) * Np;
+            bi[0][kk] = ld_dev(A + ri + lr + col);
+            bi[1][kk] = ld_dev(A + ri + 16 + lr + col);
+            if (i != j) {
+                aj[0][kk] = -ld_dev(A + cj + lr + col);
+                aj[1][kk] = -ld_dev(A + cj + 16 + lr + col);
+            } else {
+                aj[0][kk] = -bi[0][kk];
+                aj[1][kk] = -bi[1][kk];
+            }
+        }
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk) {
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(aj[0][kk], bi[0][kk], acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(aj[1][kk], bi[0][kk], acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(aj[0][kk], bi[1][kk], acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(aj[1][kk], bi[1][kk], acc[1][1], 0, 0, 0);
+        }
+    }
+    if (i != j) {
+        // panel: X = A_ij W_jj^T with W[c][q] = (q <= c) ? diag tile (row q, column c) : 0
+        ok &= wait_flag(fl + tile_ix(j, j), abort_w) != 0;
+        const double *D = A + cj + cj * Np;
+        d4 x[2][2];
+#pragma unroll
+        for (int R = 0; R < 2; ++R)
+#pragma unroll
+            for (int C = 0; C < 2; ++C) x[R][C] = (d4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk) {
+            const int q = 4 * kk + lk;
+            const double w0 = ld_dev(D + q + (int64_t)lr * Np);
+            const double w1 = ld_dev(D + q + (int64_t)(16 + lr) * Np);
+            const double a0 = q <= lr ? w0 : 0.0;
+            const double a1 = q <= 16 + lr ? w1 : 0.0;
+            // operand B: A_ij(16 R + lr, q) = acc[R][kk / 4][kk % 4]
+            x[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, acc[0][kk >> 2][kk & 3], x[0][0], 0, 0, 0);
+            x[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, acc[0][kk >> 2][kk & 3], x[0][1], 0, 0, 0);
+            x[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, acc[1][kk >> 2][kk & 3], x[1][0], 0, 0, 0);
+            x[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, acc[1][kk >> 2][kk & 3], x[1][1], 0, 0, 0);
+        }
+#pragma unroll
+        for (int R = 0; R < 2; ++R)
+#pragma unroll
+            for (int C = 0; C < 2; ++C)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) st_dev(A + (ri + 16 * R + lr) + (cj + 16 * C + 4 * v + lk) * Np, x[R][C][v]);
+        raise_flag(fl + tile_ix(i, j), 1);
+        if (!ok && lane == 0) cl_status[k] = STBA_EHIP;
+        return;
+    }
+    // diagonal tile: factor and invert in registers (handed over through LDS, so
+    // the tile in S is only ever written at device scope)
+#pragma unroll
+    for (int R = 0; R < 2; ++R)
+#pragma unroll
+        for (int C = 0; C < 2; ++C)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Ls[16 * R + lr][16 * C + 4 * v + lk] = acc[R][C][v];
+    __syncwarp();
+    const bool bad = diag_factor_invert<true>(A, Np, ri, lane, Ls, Wi, zs, nullptr);
+    raise_flag(fl + tile_ix(i, i), bad ? 2 : 1);
+    // forward: y_i = W_ii (b_i - sum_j L_ij y_j); lane r (and r + 32) holds entry r
+    const int r = lane & (kNB - 1);
+    const int N = 9 * cl_n[k];
+    const int c0 = cl_start[k];
+    double *yv = yx + (int64_t)k * 2 * tmax * kNB;   // y_0 .. y_{T-1}, then x_0 .. x_{T-1}
+    double *xv = yv + (int64_t)tmax * kNB;
+    const int64_t row = ri + r;
+    double z = row < N ? b[9 * (int64_t)cl_cams[c0 + row / 9] + row % 9] : 0.0;
+    for (int jj = 0; jj < i; ++jj) {
+        ok &= wait_flag(fl + tpc + jj, abort_w) != 0;
+        const double *L = A + ri + r + (int64_t)jj * kNB * Np;
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int c = 0; c < kNB; c += 2) {
+            s0 = fma(ld_dev(L + (int64_t)c * Np), ld_dev(yv + jj * kNB + c), s0);
+            s1 = fma(ld_dev(L + (int64_t)(c + 1) * Np), ld_dev(yv + jj * kNB + c + 1), s1);
+        }
+        z -= s0 + s1;
+    }
+    share32(zs, z, lane);
+    double y = 0.0;
+#pragma unroll 8
+    for (int c = 0; c < kNB; ++c) y = fma(Wi[r][c], zs[c], y);
+    if (lane < kNB) st_dev(yv + ri + r, y);
+    raise_flag(fl + tpc + i, 1);
+    // backward: x_i = W_ii^T (y_i - sum_{kk > i} L_{kk,i}^T x_kk), kk descending
+    z = y;
+    for (int kk = T - 1; kk > i; --kk) {
+        ok &= wait_flag(fl + tpc + tmax + kk, abort_w) != 0;
+        const double *L = A + (int64_t)kk * kNB + (ri + r) * Np;   // column r of tile (kk, i)
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int c = 0; c < kNB; c += 2) {
+            s0 = fma(ld_dev(L + c), ld_dev(xv + kk * kNB + c), s0);
+            s1 = fma(ld_dev(L + c + 1), ld_dev(xv + kk * kNB + c + 1), s1);
+        }
+        z -= s0 + s1;
+    }
+    share32(zs, z, lane);
+    double xr = 0.0;
+#pragma unroll 8
+    for (int c = 0; c < kNB; ++c) xr = fma(Wi[c][r], zs[c], xr);
+    if (lane < kNB) {
+        st_dev(xv + ri + r, xr);
+        if (row < N) dcam[9 * (int64_t)cl_cams[c0 + row / 9] + row % 9] = xr;
+    }
+    raise_flag(fl + tpc + tmax + i, 1);
+    if (i == 0 && lane == 0) {
+        // x_0 depends on every tile of the cluster: all pivots are known here
+        bool anybad = false;
+        for (int p = 0; p < T; ++p)
+            anybad |= __hip_atomic_load(fl + tile_ix(p, p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 2;
+        const bool aborted = __hip_atomic_load(abort_w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+        cl_status[k] = (!ok || aborted) ? STBA_EHIP : (anybad ? STBA_ENOTPD : STBA_OK);
+    } else if (!ok && lane == 0) {
+        cl_status[k] = STBA_EHIP;
+    }
+}
+
+__global__ void k_zero_flags(int32_t *flags, int64_t count) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        flags[i] = 0;
+}
+
 }  // namespace
+
+// Wavefronts of k_chol_tiles that the device holds at once (its dataflow waits
+// need every wavefront of the grid resident); 0 if the query fails.
+int64_t chol_tile_resident() {
+    static const int64_t cap = [] {
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return (int64_t)0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return (int64_t)0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(k_chol_tiles), 64,
+                                                         0) != hipSuccess)
+            return (int64_t)0;
+        return (int64_t)cus * per_cu;
+    }();
+    return cap;
+}
+
+int chol_tile_layout(int32_t l, int32_t max_Np, int32_t *tpc, int32_t *tmax, int32_t *fpc) {
+    const int32_t tm = max_Np / kNB;
+    const int64_t per = (int64_t)tm * (tm + 1) / 2;
+    if (tm < 1 || (int64_t)l * per > kCholTileWaves) return 0;
+    // keep a quarter of the resident capacity in reserve
+    if (4 * (int64_t)l * per > 3 * chol_tile_resident()) return 0;
+    *tmax = tm;
+    *tpc = (int32_t)per;
+    *fpc = (int32_t)(per + 2 * tm);
+    return 1;
+}
 
 hipError_t launch_chol(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, const int64_t *S_off,
                        const int32_t *cl_start, const int32_t *cl_cams, double *S, const double *b, double *dcam,
-                       int32_t *cl_status, int32_t max_Np, hipStream_t st) {
-    const size_t shmem = sizeof(double) * ((size_t)kNB * (kNB + 1) + (size_t)max_Np + kCholThreads + kNB);
+                       int32_t *cl_status, int32_t max_Np, int32_t *flags, double *yx, hipStream_t st) {
+    int32_t tpc = 0, tmax = 0, fpc = 0;
+    if (flags && yx && chol_tile_layout(l, max_Np, &tpc, &tmax, &fpc)) {
+        const int64_t nflags = (int64_t)l * fpc + 1;
+        k_zero_flags<<<(unsigned)((nflags + 255) / 256), 256, 0, st>>>(flags, nflags);
+        k_chol_tiles<<<(unsigned)((int64_t)l * tpc), 64, 0, st>>>(tpc, tmax, fpc, cl_n, cl_Np, S_off, cl_start, cl_cams,
+                                                                 S, b, dcam, cl_status, flags, l, yx);
+        return hipGetLastError();
+    }
+    const size_t shmem = sizeof(double) * (2 * (size_t)kNB * (kNB + 1) + 2 * kNB + (size_t)max_Np + kCholThreads + kNB);
     k_chol<<<(unsigned)l, kCholThreads, shmem, st>>>(l, cl_n, cl_Np, S_off, cl_start, cl_cams, S, b, dcam, cl_status,
                                                      max_Np);
     return hipGetLastError();

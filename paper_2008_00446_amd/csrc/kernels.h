@@ -71,9 +71,17 @@ hipError_t launch_schur(const int64_t *n_blocks, int64_t n_blocks_cap, const Sch
                         const int32_t *seg_head, const T *Jc, const T *obsd, const double *lam2, double *S,
                         double *b, hipStream_t st);
 
+// Cluster solves.  With l * T (T + 1) / 2 <= kCholTileWaves (T = max_Np / 32)
+// and flags / yx given, one wavefront per tile (tile-parallel dataflow);
+// otherwise one workgroup per cluster.  flags: chol_flag_words(kCholTileWaves)
+// int32; yx: 2 * l * max_Np doubles.
+constexpr int kCholTileWaves = 1536;
+inline int64_t chol_flag_words() { return 3 * (int64_t)kCholTileWaves + 1; }
+int chol_tile_layout(int32_t l, int32_t max_Np, int32_t *tpc, int32_t *tmax, int32_t *fpc);
 hipError_t launch_chol(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, const int64_t *S_off,
                        const int32_t *cl_start, const int32_t *cl_cams, double *S, const double *b,
-                       double *dcam, int32_t *cl_status, int32_t max_Np, hipStream_t st);
+                       double *dcam, int32_t *cl_status, int32_t max_Np, int32_t *flags, double *yx,
+                       hipStream_t st);
 
 template <typename T>
 hipError_t launch_backsub(const stba_problem &p, const int64_t *pt_off, const T *Jc, const T *Jp,

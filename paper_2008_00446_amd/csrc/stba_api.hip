@@ -17,7 +17,7 @@ struct Layout {
     size_t tmp_bytes;
     // per iteration
     size_t cl_n, cl_Np, cl_start, cl_cams, cam_local, cl_status, S_off;
-    size_t f, Jc, Jp, seg_head, seg_rec, obsd, Vinv, wph, S, b, dcam, dpt, partials;
+    size_t f, Jc, Jp, seg_head, seg_rec, obsd, Vinv, wph, S, b, dcam, dpt, partials, chol_flags, chol_yx;
     int64_t S_cap, n_partials;
     int32_t max_Np;
     size_t total;
@@ -104,6 +104,8 @@ bool make_layout(const stba_problem *p, const stba_dims *d, int precision, Layou
     L.Jc = take(es * 18 * q);
     L.Jp = take(es * 6 * q);
     L.seg_head = take(4 * q);
+    L.chol_flags = take(4 * (size_t)chol_flag_words());
+    L.chol_yx = take(8 * 2 * (size_t)kCholTileWaves * kNB);
     L.seg_rec = take(8 * (size_t)kSegRec * q);
     L.obsd = take(es * kObsRec * q);
     L.Vinv = take(8 * 6 * n);
@@ -189,7 +191,8 @@ int solve_impl(const stba_problem *p, const stba_dims *d, int32_t l, const T *Jc
     (void)d;
     STBA_HIP(launch_chol(l, at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np), at<int64_t>(ws, L.S_off),
                          at<int32_t>(ws, L.cl_start), at<int32_t>(ws, L.cl_cams), at<double>(ws, L.S),
-                         at<double>(ws, L.b), dcam, cl_status, L.max_Np, st));
+                         at<double>(ws, L.b), dcam, cl_status, L.max_Np, at<int32_t>(ws, L.chol_flags),
+                         at<double>(ws, L.chol_yx), st));
     STBA_HIP(launch_backsub<T>(*p, at<int64_t>(ws, L.pt_off), Jc, Jp, at<double>(ws, L.Vinv), at<double>(ws, L.wph),
                                dcam, dpt, st));
     return STBA_OK;
@@ -230,7 +233,8 @@ int lm_step_impl(const stba_problem *p, const stba_dims *d, const stba_sample *s
     double *dcam = at<double>(ws, L.dcam), *dpt = at<double>(ws, L.dpt);
     STBA_HIP(launch_chol(s->l, at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np), at<int64_t>(ws, L.S_off),
                          at<int32_t>(ws, L.cl_start), at<int32_t>(ws, L.cl_cams), at<double>(ws, L.S),
-                         at<double>(ws, L.b), dcam, at<int32_t>(ws, L.cl_status), L.max_Np, st));
+                         at<double>(ws, L.b), dcam, at<int32_t>(ws, L.cl_status), L.max_Np,
+                         at<int32_t>(ws, L.chol_flags), at<double>(ws, L.chol_yx), st));
     STBA_TRY(mark(6));
     STBA_HIP(launch_backsub<T>(*p, at<int64_t>(ws, L.pt_off), Jc, Jp, at<double>(ws, L.Vinv), at<double>(ws, L.wph),
                                dcam, dpt, st));
