@@ -30,30 +30,44 @@ __device__ inline double readlane_d(double v, int l) {
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-// Diagonal tile (rows/cols off..off+31), one wavefront.  Lane r owns row r of
-// the tile in registers (lanes 32..63 mirror rows 0..31).
-//   Factor, right-looking: at step k the pivot comes from lane k (v_readlane),
-//   every lane scales its entry of column k and writes it to LDS, and all lanes
-//   read the column back (LDS operations of one wavefront complete in order) to
-//   update their row.  Entries above the diagonal are carried as don't-care
-//   values so that no update is predicated.
-//   Invert, W = L^-1: lane c forward-substitutes column c, reading the rows of L
-//   from LDS (the same address in every lane).
+// 1 / sqrt(d): the hardware estimate and two Newton steps y += y (1/2 - d y^2 / 2),
+// each of which squares the relative error; a shorter dependent chain than a
+// correctly rounded square root followed by a division.
+__device__ inline double rsqrt_refined(double d) {
+    const double h = 0.5 * d;
+    double y = __builtin_amdgcn_rsq(d);
+    y = fma(y, fma(-h * y, y, 0.5), y);
+    y = fma(y, fma(-h * y, y, 0.5), y);
+    return y;
+}
+
+// Diagonal tile (rows/cols off..off+31), one wavefront, right-looking.  Lane r
+// holds row r of the tile in registers (lanes 32..63 mirror rows 0..31).  At
+// step k the pivot comes from lane k (v_readlane); every lane scales its entry
+// of column k and writes it to LDS, and all lanes read the column back (LDS
+// operations of one wavefront complete in order) to update their row.  Entries
+// above the diagonal are carried as don't-care values, so no update is
+// predicated.  The inverse W = L^-1 is built in the same sweep from the same
+// broadcast column: lane c holds column c of W, and at step k
+//   W[k][c] /= L_kk,   W[r][c] -= L_rk W[k][c]  (r > k).
 // kTile = false: the tile is read from A; L (with its diagonal) goes to the
 //   lower triangle of A, W^T to the strict upper triangle, and x_p (LDS) is
 //   replaced by y_p = W x_p.
-// kTile = true: the tile is read from Ls (row-major); the lower triangle of A
-//   receives L without its diagonal, the upper triangle with the diagonal
-//   receives W^T (so the diagonal holds 1 / L_rr), all with device-scope stores.
+// kTile = true: the tile is read from Ls (row-major); the upper triangle of A
+//   with the diagonal receives W^T (so the diagonal holds 1 / L_rr), at device
+//   scope; the lower triangle is left as it was (no reader needs it).
 // Both leave W row-major in Wi.  Returns true if a pivot was not positive.
 template <bool kTile>
 __device__ __forceinline__ bool diag_factor_invert(double *A, int64_t Np, int64_t off, int lane,
-                                                             double (*Ls)[kNB + 1], double (*Wi)[kNB + 1],
-                                                             double *col, double *x) {
+                                                   double (*Ls)[kNB + 1], double (*Wi)[kNB + 1], double *col,
+                                                   double *x) {
     const int r = lane & (kNB - 1);
-    double a[kNB];
+    double a[kNB], w[kNB];
 #pragma unroll
-    for (int j = 0; j < kNB; ++j) a[j] = kTile ? Ls[r][j] : A[(off + r) + (off + j) * Np];
+    for (int j = 0; j < kNB; ++j) {
+        a[j] = kTile ? Ls[r][j] : A[(off + r) + (off + j) * Np];
+        w[j] = (j == r) ? 1.0 : 0.0;
+    }
     bool bad = false;
     // scheduling barriers keep each step's instructions together, so that the
     // unrolled steps are not interleaved into more live registers than exist
@@ -65,50 +79,26 @@ __device__ __forceinline__ bool diag_factor_invert(double *A, int64_t Np, int64_
             bad = true;
             d = 1.0;
         }
-        const double sd = sqrt(d);
-        const double is = 1.0 / sd;
+        const double is = rsqrt_refined(d);
+        const double sd = d * is;
         a[k] = (r == k) ? sd : ((r > k) ? a[k] * is : 0.0);
-        if (lane == 0) col[kNB + k] = is;
+        w[k] *= is;
         if (k + 1 < kNB) {
             col[r] = a[k];
 #pragma unroll
-            for (int j = k + 1; j < kNB; ++j) a[j] = fma(-a[k], col[j], a[j]);
-            // pin the updated row here: otherwise the updates are sunk to the
+            for (int j = k + 1; j < kNB; ++j) {
+                const double lj = col[j];
+                a[j] = fma(-a[k], lj, a[j]);
+                w[j] = fma(-lj, w[k], w[j]);
+            }
+            // pin the updated rows here: otherwise the updates are sunk to the
             // next use of each entry and every column read stays live
 #pragma unroll
-            for (int j = k + 1; j < kNB; ++j) asm volatile("" : "+v"(a[j]));
+            for (int j = k + 1; j < kNB; ++j) asm volatile("" : "+v"(a[j]), "+v"(w[j]));
         }
         __builtin_amdgcn_sched_barrier(0);
     }
-    // L row r to LDS (zero above the diagonal) and to A
-    if (lane < kNB) {
-#pragma unroll
-        for (int j = 0; j < kNB; ++j) {
-            const double v = j <= r ? a[j] : 0.0;
-            Ls[r][j] = v;
-            if (kTile) {
-                if (j < r)
-                    __hip_atomic_store(A + (off + r) + (off + j) * Np, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            } else {
-                if (j <= r) A[(off + r) + (off + j) * Np] = v;
-            }
-        }
-    }
-    __syncwarp();
     const int c = r;
-    double w[kNB];
-#pragma unroll
-    for (int rr = 0; rr < kNB; ++rr) {
-        double s0 = (c == rr) ? 1.0 : 0.0, s1 = 0.0;
-#pragma unroll
-        for (int k = 0; k < rr; ++k) {
-            if (k & 1) s1 = fma(-Ls[rr][k], w[k], s1);
-            else s0 = fma(-Ls[rr][k], w[k], s0);
-        }
-        w[rr] = (s0 + s1) * col[kNB + rr];
-        asm volatile("" : "+v"(w[rr]));
-        __builtin_amdgcn_sched_barrier(0);
-    }
     if (lane < kNB) {
 #pragma unroll
         for (int j = 0; j < kNB; ++j) {
@@ -118,7 +108,7 @@ __device__ __forceinline__ bool diag_factor_invert(double *A, int64_t Np, int64_
                     __hip_atomic_store(A + (off + r) + (off + j) * Np, w[j], __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);   // W^T: W[j][r] at (row r, column j)
             } else {
-                if (j > r) A[(off + r) + (off + j) * Np] = w[j];
+                A[(off + r) + (off + j) * Np] = j <= r ? a[j] : w[j];
             }
         }
     }
@@ -312,22 +302,26 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(int32_t l, const int32_t 
 }
 
 // ---------------------------------------------------------------------------
-// Tile-parallel variant for maps with few clusters: one wavefront per lower
-// 32 x 32 tile (i, j) of every S_k, so a cluster is spread over up to
-// T (T + 1) / 2 compute units instead of one.  The owner of tile (i, j) keeps it
-// in MFMA registers, applies A_ij -= L_ip L_jp^T for p < j as soon as tiles
-// (i, p) and (j, p) are final, then either factors and inverts it (i == j) or
-// solves the panel X = A_ij W_jj^T.  A final tile is written with device-scope
-// stores, and a per-tile flag is raised after the stores have completed; a
-// reader polls the flag and reads the tile with device-scope loads.  This needs
-// no cache write-back or invalidation, since a tile is read by other waves only
-// after it is final.  Every dependency of a task points to an earlier (step,
-// kind, row) key, so with all waves resident the dataflow cannot deadlock; every
-// wait is still bounded, and a time-out raises a grid-wide abort word that ends
-// all other waits (the cluster then reports STBA_EHIP).
-// The diagonal owners then run the two triangular solves as chains:
+// Tile-parallel variant for maps with few clusters: the lower 32 x 32 tiles of
+// every S_k are spread over wavefronts, so a cluster runs on up to ~T^2 / 2
+// compute units instead of one.  Wavefront i of a cluster (the row worker)
+// owns the diagonal tile (i, i) and the tile (i, i-1) next to it; every other
+// tile (i, j), j <= i - 2, has a wavefront of its own.  An owner keeps its
+// tiles in MFMA registers and applies A_ij -= L_ip L_jp^T for p < j as soon as
+// tiles (i, p) and (j, p) are final, then solves the panel X = A_ij W_jj^T.  The
+// row worker solves (i, i-1), applies it to (i, i) straight from registers and
+// factors and inverts (i, i), so one hand-over separates consecutive diagonal
+// factorisations.  A final tile is written with device-scope stores and a flag
+// is raised after the stores have completed; readers poll the flag and read the
+// tile with device-scope loads.  No cache write-back or invalidation is needed,
+// since no wavefront reads a tile before it is final.  Every dependency of a
+// task points to an earlier (step, kind, row) key, so with all wavefronts
+// resident the dataflow cannot deadlock; every wait is still bounded, and a
+// time-out raises a grid-wide abort word that ends all other waits (the
+// cluster then reports STBA_EHIP).
+// The row workers then run the two triangular solves as chains:
 //   y_i = W_ii (b_i - sum_{j < i} L_ij y_j),  x_i = W_ii^T (y_i - sum_{k > i} L_ki^T x_k),
-// each sum taken in a fixed order.
+// each sum in a fixed order.
 // ---------------------------------------------------------------------------
 constexpr int kWaitPolls = 1 << 20;
 
@@ -365,6 +359,70 @@ __device__ inline void raise_flag(int32_t *f, int v) {
 
 __device__ inline int tile_ix(int i, int j) { return i * (i + 1) / 2 + j; }
 
+// Rows row0..row0+31 of the final panel p (columns off..off+31) as MFMA operands:
+// v[R][kk] = L(row0 + 16 R + lr, off + 4 kk + lk).
+__device__ inline void load_panel(const double *A, int64_t Np, int64_t row0, int64_t off, int lr, int lk,
+                                  double (&v)[2][8]) {
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+        const int64_t col = (off + 4 * kk + lk) * Np;
+        v[0][kk] = ld_dev(A + row0 + lr + col);
+        v[1][kk] = ld_dev(A + row0 + 16 + lr + col);
+    }
+}
+
+// acc -= Li Lj^T, acc[R][C][v] = tile(16 R + lr, 16 C + 4 v + lk), Li and Lj as from load_panel.
+__device__ inline void mfma_downdate(d4 (&acc)[2][2], const double (&li)[2][8], const double (&lj)[2][8]) {
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(-lj[0][kk], li[0][kk], acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-lj[1][kk], li[0][kk], acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(-lj[0][kk], li[1][kk], acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-lj[1][kk], li[1][kk], acc[1][1], 0, 0, 0);
+    }
+}
+
+// Panel solve X = T W^T for the tile T in acc, W = L_jj^-1 read from the final
+// diagonal tile D (W[c][q] = D(q, c) for q <= c, else 0).
+__device__ inline void panel_solve(const d4 (&acc)[2][2], const double *D, int64_t Np, int lr, int lk, d4 (&x)[2][2]) {
+#pragma unroll
+    for (int R = 0; R < 2; ++R)
+#pragma unroll
+        for (int C = 0; C < 2; ++C) x[R][C] = (d4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+        const int q = 4 * kk + lk;
+        const double w0 = ld_dev(D + q + (int64_t)lr * Np);
+        const double w1 = ld_dev(D + q + (int64_t)(16 + lr) * Np);
+        const double a0 = q <= lr ? w0 : 0.0;
+        const double a1 = q <= 16 + lr ? w1 : 0.0;
+        // operand B: T(16 R + lr, q) = acc[R][kk / 4][kk % 4]
+        x[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, acc[0][kk >> 2][kk & 3], x[0][0], 0, 0, 0);
+        x[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, acc[0][kk >> 2][kk & 3], x[0][1], 0, 0, 0);
+        x[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, acc[1][kk >> 2][kk & 3], x[1][0], 0, 0, 0);
+        x[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, acc[1][kk >> 2][kk & 3], x[1][1], 0, 0, 0);
+    }
+}
+
+__device__ inline void load_tile(const double *A, int64_t Np, int64_t ri, int64_t cj, int lr, int lk, d4 (&acc)[2][2]) {
+#pragma unroll
+    for (int R = 0; R < 2; ++R)
+#pragma unroll
+        for (int C = 0; C < 2; ++C)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[R][C][v] = A[(ri + 16 * R + lr) + (cj + 16 * C + 4 * v + lk) * Np];
+}
+
+__device__ inline void store_tile_dev(double *A, int64_t Np, int64_t ri, int64_t cj, int lr, int lk,
+                                      const d4 (&x)[2][2]) {
+#pragma unroll
+    for (int R = 0; R < 2; ++R)
+#pragma unroll
+        for (int C = 0; C < 2; ++C)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) st_dev(A + (ri + 16 * R + lr) + (cj + 16 * C + 4 * v + lk) * Np, x[R][C][v]);
+}
+
 // Broadcast the 32 values v (lane r holds entry r) through LDS.
 __device__ inline void share32(double *zs, double v, int lane) {
     __syncwarp();
@@ -372,106 +430,89 @@ __device__ inline void share32(double *zs, double v, int lane) {
     __syncwarp();
 }
 
-// Flags per cluster: [tile (i, j) at i (i + 1) / 2 + j][y_i at tpc + i][x_i at tpc + tmax + i];
-// tile flags are 1 (final) or 2 (final, pivot failed).  The word after the last
-// cluster is the abort word.
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_chol_tiles(int32_t tpc, int32_t tmax, int32_t fpc,
-                                                   const int32_t *__restrict__ cl_n,
-                                                   const int32_t *__restrict__ cl_Np,
-                                                   const int64_t *__restrict__ S_off,
-                                                   const int32_t *__restrict__ cl_start,
-                                                   const int32_t *__restrict__ cl_cams, double *__restrict__ S,
-                                                   const double *__restrict__ b, double *__restrict__ dcam,
-                                                   int32_t *__restrict__ cl_status, int32_t *flags, int32_t l,
-                                                   double *yx) {
+// Flags per cluster: [tile (i, j) at i (i + 1) / 2 + j][y_i at tt + i][x_i at tt + tmax + i],
+// tt = tmax (tmax + 1) / 2; tile flags are 1 (final) or 2 (final, pivot failed).
+// The word after the last cluster is the abort word.  Wavefronts per cluster:
+// tmax row workers, then one per tile (i, j), j <= i - 2.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_chol_tiles(
+    int32_t wpc, int32_t tmax, int32_t fpc, const int32_t *__restrict__ cl_n, const int32_t *__restrict__ cl_Np,
+    const int64_t *__restrict__ S_off, const int32_t *__restrict__ cl_start, const int32_t *__restrict__ cl_cams,
+    double *__restrict__ S, const double *__restrict__ b, double *__restrict__ dcam, int32_t *__restrict__ cl_status,
+    int32_t *flags, int32_t l, double *yx) {
     __shared__ double Wi[kNB][kNB + 1];
     __shared__ double Ls[kNB][kNB + 1];
     __shared__ __align__(16) double zs[2 * kNB];
     const int lane = threadIdx.x;
-    const int k = (int)(blockIdx.x / (unsigned)tpc);
-    const int t = (int)(blockIdx.x - (unsigned)k * (unsigned)tpc);
-    int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-    while ((i + 1) * (i + 2) / 2 <= t) ++i;
-    while (i * (i + 1) / 2 > t) --i;
-    const int j = t - i * (i + 1) / 2;
+    const int k = (int)(blockIdx.x / (unsigned)wpc);
+    const int w = (int)(blockIdx.x - (unsigned)k * (unsigned)wpc);
     const int64_t Np = cl_Np[k];
     const int T = (int)(Np / kNB);
     if (T == 0) {
-        if (t == 0 && lane == 0) cl_status[k] = STBA_OK;
+        if (w == 0 && lane == 0) cl_status[k] = STBA_OK;
         return;
     }
-    if (i >= T) return;
+    const int tt = tmax * (tmax + 1) / 2;
     int32_t *fl = flags + (int64_t)k * fpc;
     int32_t *abort_w = flags + (int64_t)l * fpc;
     double *A = S + S_off[k];
-    const int64_t ri = (int64_t)i * kNB, cj = (int64_t)j * kNB;
     const int lr = lane & 15, lk = lane >> 4;
     bool ok = true;
-    // the tile in the MFMA result layout: acc[R][C][v] = A(ri + 16 R + lr, cj + 16 C + 4 v + lk)
-    d4 acc[2][2];
-#pragma unroll
-    for (int R = 0; R < 2; ++R)
-#pragma unroll
-        for (int C = 0; C < 2; ++C)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc[R][C][v] = A[(ri + 16 * R + lr) + (cj + 16 * C + 4 * v + lk) * Np];
-    for (int p = 0; p < j; ++p) {
-        ok &= wait_flag(fl + tile_ix(i, p), abort_w) != 0;
-        if (i != j) ok &= wait_flag(fl + tile_ix(j, p), abort_w) != 0;
-        const int64_t off = (int64_t)p * kNB;
-        double bi[2][8], aj[2][8];
-#pragma unroll
-        for (int kk = 0; kk < 8; ++kk) {
-            const int64_t col = (off + 4 * kk + lk) * Np;
-            bi[0][kk] = ld_dev(A + ri + lr + col);
-            bi[1][kk] = ld_dev(A + ri + 16 + lr + col);
-            if (i != j) {
-                aj[0][kk] = -ld_dev(A + cj + lr + col);
-                aj[1][kk] = -ld_dev(A + cj + 16 + lr + col);
-            } else {
-                aj[0][kk] = -bi[0][kk];
-                aj[1][kk] = -bi[1][kk];
-            }
+    if (w >= tmax) {
+        // tile (i, j), j <= i - 2
+        const int g = w - tmax;
+        int i2 = (int)((sqrt(8.0 * g + 1.0) - 1.0) * 0.5);
+        while ((i2 + 1) * (i2 + 2) / 2 <= g) ++i2;
+        while (i2 * (i2 + 1) / 2 > g) --i2;
+        const int j = g - i2 * (i2 + 1) / 2;
+        const int i = i2 + 2;
+        if (i >= T) return;
+        const int64_t ri = (int64_t)i * kNB, cj = (int64_t)j * kNB;
+        d4 acc[2][2];
+        load_tile(A, Np, ri, cj, lr, lk, acc);
+        for (int p = 0; p < j; ++p) {
+            ok &= wait_flag(fl + tile_ix(i, p), abort_w) != 0;
+            ok &= wait_flag(fl + tile_ix(j, p), abort_w) != 0;
+            double li[2][8], lj[2][8];
+            load_panel(A, Np, ri, (int64_t)p * kNB, lr, lk, li);
+            load_panel(A, Np, cj, (int64_t)p * kNB, lr, lk, lj);
+            mfma_downdate(acc, li, lj);
         }
-#pragma unroll
-        for (int kk = 0; kk < 8; ++kk) {
-            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(aj[0][kk], bi[0][kk], acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(aj[1][kk], bi[0][kk], acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(aj[0][kk], bi[1][kk], acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(aj[1][kk], bi[1][kk], acc[1][1], 0, 0, 0);
-        }
-    }
-    if (i != j) {
-        // panel: X = A_ij W_jj^T with W[c][q] = (q <= c) ? diag tile (row q, column c) : 0
         ok &= wait_flag(fl + tile_ix(j, j), abort_w) != 0;
-        const double *D = A + cj + cj * Np;
         d4 x[2][2];
-#pragma unroll
-        for (int R = 0; R < 2; ++R)
-#pragma unroll
-            for (int C = 0; C < 2; ++C) x[R][C] = (d4){0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int kk = 0; kk < 8; ++kk) {
-            const int q = 4 * kk + lk;
-            const double w0 = ld_dev(D + q + (int64_t)lr * Np);
-            const double w1 = ld_dev(D + q + (int64_t)(16 + lr) * Np);
-            const double a0 = q <= lr ? w0 : 0.0;
-            const double a1 = q <= 16 + lr ? w1 : 0.0;
-            // operand B: A_ij(16 R + lr, q) = acc[R][kk / 4][kk % 4]
-            x[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, acc[0][kk >> 2][kk & 3], x[0][0], 0, 0, 0);
-            x[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, acc[0][kk >> 2][kk & 3], x[0][1], 0, 0, 0);
-            x[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, acc[1][kk >> 2][kk & 3], x[1][0], 0, 0, 0);
-            x[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, acc[1][kk >> 2][kk & 3], x[1][1], 0, 0, 0);
-        }
-#pragma unroll
-        for (int R = 0; R < 2; ++R)
-#pragma unroll
-            for (int C = 0; C < 2; ++C)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) st_dev(A + (ri + 16 * R + lr) + (cj + 16 * C + 4 * v + lk) * Np, x[R][C][v]);
+        panel_solve(acc, A + cj + cj * Np, Np, lr, lk, x);
+        store_tile_dev(A, Np, ri, cj, lr, lk, x);
         raise_flag(fl + tile_ix(i, j), 1);
         if (!ok && lane == 0) cl_status[k] = STBA_EHIP;
         return;
+    }
+    // row worker i: tiles (i, i) and (i, i-1)
+    const int i = w;
+    if (i >= T) return;
+    const int64_t ri = (int64_t)i * kNB;
+    d4 accD[2][2], accP[2][2];
+    load_tile(A, Np, ri, ri, lr, lk, accD);
+    if (i >= 1) load_tile(A, Np, ri, ri - kNB, lr, lk, accP);
+    for (int p = 0; p + 1 < i; ++p) {
+        ok &= wait_flag(fl + tile_ix(i, p), abort_w) != 0;
+        ok &= wait_flag(fl + tile_ix(i - 1, p), abort_w) != 0;
+        double li[2][8], lj[2][8];
+        load_panel(A, Np, ri, (int64_t)p * kNB, lr, lk, li);
+        load_panel(A, Np, ri - kNB, (int64_t)p * kNB, lr, lk, lj);
+        mfma_downdate(accP, li, lj);
+        mfma_downdate(accD, li, li);
+    }
+    if (i >= 1) {
+        ok &= wait_flag(fl + tile_ix(i - 1, i - 1), abort_w) != 0;
+        d4 x[2][2];
+        panel_solve(accP, A + (ri - kNB) + (ri - kNB) * Np, Np, lr, lk, x);
+        store_tile_dev(A, Np, ri, ri - kNB, lr, lk, x);
+        raise_flag(fl + tile_ix(i, i - 1), 1);
+        double li[2][8];
+#pragma unroll
+        for (int R = 0; R < 2; ++R)
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) li[R][kk] = x[R][kk >> 2][kk & 3];
+        mfma_downdate(accD, li, li);
     }
     // diagonal tile: factor and invert in registers (handed over through LDS, so
     // the tile in S is only ever written at device scope)
@@ -480,7 +521,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void
 #pragma unroll
         for (int C = 0; C < 2; ++C)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) Ls[16 * R + lr][16 * C + 4 * v + lk] = acc[R][C][v];
+            for (int v = 0; v < 4; ++v) Ls[16 * R + lr][16 * C + 4 * v + lk] = accD[R][C][v];
     __syncwarp();
     const bool bad = diag_factor_invert<true>(A, Np, ri, lane, Ls, Wi, zs, nullptr);
     raise_flag(fl + tile_ix(i, i), bad ? 2 : 1);
@@ -493,7 +534,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void
     const int64_t row = ri + r;
     double z = row < N ? b[9 * (int64_t)cl_cams[c0 + row / 9] + row % 9] : 0.0;
     for (int jj = 0; jj < i; ++jj) {
-        ok &= wait_flag(fl + tpc + jj, abort_w) != 0;
+        ok &= wait_flag(fl + tt + jj, abort_w) != 0;
         const double *L = A + ri + r + (int64_t)jj * kNB * Np;
         double s0 = 0.0, s1 = 0.0;
 #pragma unroll
@@ -508,11 +549,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void
 #pragma unroll 8
     for (int c = 0; c < kNB; ++c) y = fma(Wi[r][c], zs[c], y);
     if (lane < kNB) st_dev(yv + ri + r, y);
-    raise_flag(fl + tpc + i, 1);
+    raise_flag(fl + tt + i, 1);
     // backward: x_i = W_ii^T (y_i - sum_{kk > i} L_{kk,i}^T x_kk), kk descending
     z = y;
     for (int kk = T - 1; kk > i; --kk) {
-        ok &= wait_flag(fl + tpc + tmax + kk, abort_w) != 0;
+        ok &= wait_flag(fl + tt + tmax + kk, abort_w) != 0;
         const double *L = A + (int64_t)kk * kNB + (ri + r) * Np;   // column r of tile (kk, i)
         double s0 = 0.0, s1 = 0.0;
 #pragma unroll
@@ -530,7 +571,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void
         st_dev(xv + ri + r, xr);
         if (row < N) dcam[9 * (int64_t)cl_cams[c0 + row / 9] + row % 9] = xr;
     }
-    raise_flag(fl + tpc + tmax + i, 1);
+    raise_flag(fl + tt + tmax + i, 1);
     if (i == 0 && lane == 0) {
         // x_0 depends on every tile of the cluster: all pivots are known here
         bool anybad = false;
@@ -565,26 +606,29 @@ int64_t chol_tile_resident() {
     return cap;
 }
 
-int chol_tile_layout(int32_t l, int32_t max_Np, int32_t *tpc, int32_t *tmax, int32_t *fpc) {
+int chol_tile_layout(int32_t l, int32_t max_Np, int32_t *wpc, int32_t *tmax, int32_t *fpc) {
     const int32_t tm = max_Np / kNB;
-    const int64_t per = (int64_t)tm * (tm + 1) / 2;
-    if (tm < 1 || (int64_t)l * per > kCholTileWaves) return 0;
+    if (tm < 1) return 0;
+    const int64_t waves = (int64_t)tm + (int64_t)(tm - 1) * (tm - 2) / 2;
+    if ((int64_t)l * waves > kCholTileWaves) return 0;
     // keep a quarter of the resident capacity in reserve
-    if (4 * (int64_t)l * per > 3 * chol_tile_resident()) return 0;
+    if (4 * (int64_t)l * waves > 3 * chol_tile_resident()) return 0;
+    const int64_t words = (int64_t)tm * (tm + 1) / 2 + 2 * tm;
+    if ((int64_t)l * words + 1 > chol_flag_words() || 2 * (int64_t)l * tm * kNB > chol_yx_doubles()) return 0;
     *tmax = tm;
-    *tpc = (int32_t)per;
-    *fpc = (int32_t)(per + 2 * tm);
+    *wpc = (int32_t)waves;
+    *fpc = (int32_t)words;
     return 1;
 }
 
 hipError_t launch_chol(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, const int64_t *S_off,
                        const int32_t *cl_start, const int32_t *cl_cams, double *S, const double *b, double *dcam,
                        int32_t *cl_status, int32_t max_Np, int32_t *flags, double *yx, hipStream_t st) {
-    int32_t tpc = 0, tmax = 0, fpc = 0;
-    if (flags && yx && chol_tile_layout(l, max_Np, &tpc, &tmax, &fpc)) {
+    int32_t wpc = 0, tmax = 0, fpc = 0;
+    if (flags && yx && chol_tile_layout(l, max_Np, &wpc, &tmax, &fpc)) {
         const int64_t nflags = (int64_t)l * fpc + 1;
         k_zero_flags<<<(unsigned)((nflags + 255) / 256), 256, 0, st>>>(flags, nflags);
-        k_chol_tiles<<<(unsigned)((int64_t)l * tpc), 64, 0, st>>>(tpc, tmax, fpc, cl_n, cl_Np, S_off, cl_start, cl_cams,
+        k_chol_tiles<<<(unsigned)((int64_t)l * wpc), 64, 0, st>>>(wpc, tmax, fpc, cl_n, cl_Np, S_off, cl_start, cl_cams,
                                                                  S, b, dcam, cl_status, flags, l, yx);
         return hipGetLastError();
     }

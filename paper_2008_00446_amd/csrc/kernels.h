@@ -71,13 +71,16 @@ hipError_t launch_schur(const int64_t *n_blocks, int64_t n_blocks_cap, const Sch
                         const int32_t *seg_head, const T *Jc, const T *obsd, const double *lam2, double *S,
                         double *b, hipStream_t st);
 
-// Cluster solves.  With l * T (T + 1) / 2 <= kCholTileWaves (T = max_Np / 32)
-// and flags / yx given, one wavefront per tile (tile-parallel dataflow);
-// otherwise one workgroup per cluster.  flags: chol_flag_words(kCholTileWaves)
-// int32; yx: 2 * l * max_Np doubles.
+// Cluster solves.  With few clusters (l wavefront sets of T + (T-1)(T-2)/2,
+// T = max_Np / 32, within kCholTileWaves and resident at once) and flags / yx
+// given: one wavefront per tile (tile-parallel dataflow); otherwise one
+// workgroup per cluster.  flags: chol_flag_words() int32; yx: chol_yx_doubles().
 constexpr int kCholTileWaves = 1536;
-inline int64_t chol_flag_words() { return 3 * (int64_t)kCholTileWaves + 1; }
-int chol_tile_layout(int32_t l, int32_t max_Np, int32_t *tpc, int32_t *tmax, int32_t *fpc);
+// per cluster T (T + 1) / 2 + 2 T flag words <= 3.5 x its wavefronts, plus the abort word
+inline int64_t chol_flag_words() { return 4 * (int64_t)kCholTileWaves + 1; }
+// per cluster 2 T 32 doubles, T <= its wavefronts
+inline int64_t chol_yx_doubles() { return 2 * (int64_t)kCholTileWaves * kNB; }
+int chol_tile_layout(int32_t l, int32_t max_Np, int32_t *wpc, int32_t *tmax, int32_t *fpc);
 hipError_t launch_chol(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, const int64_t *S_off,
                        const int32_t *cl_start, const int32_t *cl_cams, double *S, const double *b,
                        double *dcam, int32_t *cl_status, int32_t max_Np, int32_t *flags, double *yx,

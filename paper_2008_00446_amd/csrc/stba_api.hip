@@ -105,7 +105,7 @@ bool make_layout(const stba_problem *p, const stba_dims *d, int precision, Layou
     L.Jp = take(es * 6 * q);
     L.seg_head = take(4 * q);
     L.chol_flags = take(4 * (size_t)chol_flag_words());
-    L.chol_yx = take(8 * 2 * (size_t)kCholTileWaves * kNB);
+    L.chol_yx = take(8 * (size_t)chol_yx_doubles());
     L.seg_rec = take(8 * (size_t)kSegRec * q);
     L.obsd = take(es * kObsRec * q);
     L.Vinv = take(8 * 6 * n);
