@@ -50,12 +50,12 @@ __device__ inline double rsqrt_refined(double d) {
 // predicated.  The inverse W = L^-1 is built in the same sweep from the same
 // broadcast column: lane c holds column c of W, and at step k
 //   W[k][c] /= L_kk,   W[r][c] -= L_rk W[k][c]  (r > k).
-// kTile = false: the tile is read from A; L (with its diagonal) goes to the
-//   lower triangle of A, W^T to the strict upper triangle, and x_p (LDS) is
-//   replaced by y_p = W x_p.
-// kTile = true: the tile is read from Ls (row-major); the upper triangle of A
-//   with the diagonal receives W^T (so the diagonal holds 1 / L_rr), at device
-//   scope; the lower triangle is left as it was (no reader needs it).
+// Both store W^T in the upper triangle of the tile with its diagonal (so the
+// diagonal holds 1 / L_rr).
+// kTile = false: the tile is read from A; L goes to the strict lower triangle
+//   and x_p (LDS) is replaced by y_p = W x_p.
+// kTile = true: the tile is read from Ls (row-major); the stores are at device
+//   scope and the lower triangle is left as it was (no reader needs it).
 // Both leave W row-major in Wi.  Returns true if a pivot was not positive.
 template <bool kTile>
 __device__ __forceinline__ bool diag_factor_invert(double *A, int64_t Np, int64_t off, int lane,
@@ -108,7 +108,7 @@ __device__ __forceinline__ bool diag_factor_invert(double *A, int64_t Np, int64_
                     __hip_atomic_store(A + (off + r) + (off + j) * Np, w[j], __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);   // W^T: W[j][r] at (row r, column j)
             } else {
-                A[(off + r) + (off + j) * Np] = j <= r ? a[j] : w[j];
+                A[(off + r) + (off + j) * Np] = j < r ? a[j] : w[j];
             }
         }
     }
@@ -201,6 +201,67 @@ __device__ inline void tile_update(double *A, int64_t Np, int64_t ri, int64_t cj
             for (int v = 0; v < 4; ++v) A[(ri + 16 * R + lr) + (cj + 16 * C + 4 * v + lk) * Np] = acc[R][C][v];
 }
 
+// Block triangular solves with a factored S_k (L in the lower tiles, W_pp^T in
+// the upper triangle of each diagonal tile, diagonal included), in place on x
+// (LDS), by all kCholThreads threads; sums in a fixed order.
+//   forward:  x_p = W_pp (x_p - sum_{j < p} L_pj x_j)
+//   backward: x_p = W_pp^T (x_p - sum_{i > p} L_ip^T x_i)
+__device__ void block_forward(const double *A, int64_t Np, int nt, double *x, double *red, double *zb, int tid) {
+    constexpr int G = kCholThreads / kNB;
+    for (int p = 0; p < nt; ++p) {
+        const int64_t off = (int64_t)p * kNB;
+        {
+            const int c = tid / G, g = tid % G;
+            double s = 0.0;
+            for (int64_t j = g; j < off; j += G) s = fma(A[(off + c) + j * Np], x[j], s);
+            red[c * G + g] = s;
+        }
+        __syncthreads();
+        if (tid < kNB) {
+            double s = x[off + tid];
+#pragma unroll
+            for (int g = 0; g < G; ++g) s -= red[tid * G + g];
+            zb[tid] = s;
+        }
+        __syncthreads();
+        if (tid < kNB) {
+            const int r = tid;
+            double s = 0.0;
+            for (int q = 0; q <= r; ++q) s = fma(A[(off + q) + (off + r) * Np], zb[q], s);   // W[r][q]
+            x[off + r] = s;
+        }
+        __syncthreads();
+    }
+}
+
+__device__ void block_backward(const double *A, int64_t Np, int nt, double *x, double *red, double *zb, int tid) {
+    constexpr int G = kCholThreads / kNB;
+    for (int p = nt - 1; p >= 0; --p) {
+        const int64_t off = (int64_t)p * kNB;
+        {
+            const int c = tid / G, g = tid % G;
+            double s = 0.0;
+            for (int64_t row = off + kNB + g; row < Np; row += G) s = fma(A[row + (off + c) * Np], x[row], s);
+            red[c * G + g] = s;
+        }
+        __syncthreads();
+        if (tid < kNB) {
+            double s = x[off + tid];
+#pragma unroll
+            for (int g = 0; g < G; ++g) s -= red[tid * G + g];
+            zb[tid] = s;
+        }
+        __syncthreads();
+        if (tid < kNB) {
+            const int r = tid;
+            double s = 0.0;
+            for (int c = r; c < kNB; ++c) s = fma(A[(off + r) + (off + c) * Np], zb[c], s);   // W[c][r]
+            x[off + r] = s;
+        }
+        __syncthreads();
+    }
+}
+
 __global__ __launch_bounds__(kCholThreads) void k_chol(int32_t l, const int32_t *__restrict__ cl_n,
                                                        const int32_t *__restrict__ cl_Np,
                                                        const int64_t *__restrict__ S_off,
@@ -270,33 +331,8 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(int32_t l, const int32_t 
             tile_trsm(A, Np, (int64_t)i * kNB, offq, lane, Wi, x + offq, x);
         __syncthreads();
     }
-    // backward solve L^T x = y: x_p = W_p^T (y_p - sum_{i > p} L_ip^T x_i)
-    for (int p = nt - 1; p >= 0; --p) {
-        const int64_t off = (int64_t)p * kNB;
-        {
-            constexpr int G = kCholThreads / kNB;
-            const int c = tid / G, g = tid % G;
-            double s = 0.0;
-            for (int64_t row = off + kNB + g; row < Np; row += G) s = fma(A[row + (off + c) * Np], x[row], s);
-            red[c * G + g] = s;
-        }
-        __syncthreads();
-        if (tid < kNB) {
-            constexpr int G = kCholThreads / kNB;
-            double s = x[off + tid];
-#pragma unroll
-            for (int g = 0; g < G; ++g) s -= red[tid * G + g];
-            zb[tid] = s;
-        }
-        __syncthreads();
-        if (tid < kNB) {
-            const int r = tid;
-            double s = zb[r] / A[(off + r) + (off + r) * Np];
-            for (int c = r + 1; c < kNB; ++c) s = fma(A[(off + r) + (off + c) * Np], zb[c], s);   // W[c][r]
-            x[off + r] = s;
-        }
-        __syncthreads();
-    }
+    // backward solve L^T x = y
+    block_backward(A, Np, nt, x, red, zb, tid);
     for (int i = tid; i < N; i += kCholThreads) dcam[9 * (int64_t)cl_cams[c0 + i / 9] + i % 9] = x[i];
     if (tid == 0) cl_status[k] = bad ? STBA_ENOTPD : STBA_OK;
 }
@@ -584,6 +620,65 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void
     }
 }
 
+// One step of iterative refinement in FP64 (MIXED precision): with S0 the
+// assembled S_k kept from before the factorisation,
+//   r = b - S0 x,  x += S^-1 r  (the factors of S_k),
+// one workgroup per cluster; S0 is symmetric with its lower triangle stored.
+__global__ __launch_bounds__(kCholThreads) void k_refine(const int32_t *__restrict__ cl_n,
+                                                         const int32_t *__restrict__ cl_Np,
+                                                         const int64_t *__restrict__ S_off,
+                                                         const int32_t *__restrict__ cl_start,
+                                                         const int32_t *__restrict__ cl_cams,
+                                                         const double *__restrict__ S, const double *__restrict__ S0,
+                                                         const double *__restrict__ b, double *__restrict__ dcam,
+                                                         int32_t max_Np) {
+    extern __shared__ double smem[];
+    double *x = smem;
+    double *rr = x + max_Np;
+    double *red = rr + max_Np;       // kCholThreads
+    double *zb = red + kCholThreads; // kNB
+    const int k = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int nk = cl_n[k];
+    if (nk == 0) return;
+    const int64_t Np = cl_Np[k];
+    const int N = 9 * nk;
+    const int nt = (int)(Np / kNB);
+    const double *A = S + S_off[k];
+    const double *A0 = S0 + S_off[k];
+    const int c0 = cl_start[k];
+    for (int i = tid; i < Np; i += kCholThreads) x[i] = (i < N) ? dcam[9 * (int64_t)cl_cams[c0 + i / 9] + i % 9] : 0.0;
+    __syncthreads();
+    constexpr int G = kCholThreads / kNB;
+    for (int64_t rb = 0; rb < Np; rb += kNB) {
+        const int c = tid / G, g = tid % G;
+        const int64_t i = rb + c;
+        double s = 0.0;
+        for (int64_t j = g; j < Np; j += G) s = fma(j <= i ? A0[i + j * Np] : A0[j + i * Np], x[j], s);
+        red[c * G + g] = s;
+        __syncthreads();
+        if (tid < kNB) {
+            const int64_t row = rb + tid;
+            double v = row < N ? b[9 * (int64_t)cl_cams[c0 + row / 9] + row % 9] : 0.0;
+#pragma unroll
+            for (int gg = 0; gg < G; ++gg) v -= red[tid * G + gg];
+            rr[row] = v;
+        }
+        __syncthreads();
+    }
+    block_forward(A, Np, nt, rr, red, zb, tid);
+    block_backward(A, Np, nt, rr, red, zb, tid);
+    for (int i = tid; i < N; i += kCholThreads) dcam[9 * (int64_t)cl_cams[c0 + i / 9] + i % 9] = x[i] + rr[i];
+}
+
+// S0 = S over the used part (S_off[l] entries)
+__global__ void k_copy_S(const double *__restrict__ S, double *__restrict__ S0, const int64_t *__restrict__ S_off,
+                         int32_t l) {
+    const int64_t n = S_off[l];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        S0[i] = S[i];
+}
+
 __global__ void k_zero_flags(int32_t *flags, int64_t count) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
         flags[i] = 0;
@@ -635,6 +730,23 @@ hipError_t launch_chol(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, con
     const size_t shmem = sizeof(double) * (2 * (size_t)kNB * (kNB + 1) + 2 * kNB + (size_t)max_Np + kCholThreads + kNB);
     k_chol<<<(unsigned)l, kCholThreads, shmem, st>>>(l, cl_n, cl_Np, S_off, cl_start, cl_cams, S, b, dcam, cl_status,
                                                      max_Np);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_S(const double *S, double *S0, const int64_t *S_off, int32_t l, int64_t S_cap,
+                        hipStream_t st) {
+    int64_t blocks = (S_cap + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    k_copy_S<<<(unsigned)blocks, 256, 0, st>>>(S, S0, S_off, l);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, const int64_t *S_off,
+                         const int32_t *cl_start, const int32_t *cl_cams, const double *S, const double *S0,
+                         const double *b, double *dcam, int32_t max_Np, hipStream_t st) {
+    const size_t shmem = sizeof(double) * (2 * (size_t)max_Np + kCholThreads + kNB);
+    k_refine<<<(unsigned)l, kCholThreads, shmem, st>>>(cl_n, cl_Np, S_off, cl_start, cl_cams, S, S0, b, dcam, max_Np);
     return hipGetLastError();
 }
 

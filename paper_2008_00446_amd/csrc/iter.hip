@@ -14,7 +14,7 @@ inline unsigned grid_for(int64_t count, int bs = 256) { return (unsigned)((count
 // ---------------------------------------------------------------------------
 // cluster layout: cameras grouped by cluster (ascending id inside a cluster),
 // per-cluster sizes, padded orders and offsets of S_k (Eq. 13).
-// One 1024-thread workgroup; bitonic sort of (cluster, camera) keys in LDS.
+// One workgroup of up to 1024 threads; bitonic sort of (cluster, camera) keys in LDS.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_clusters(const int32_t *cam_cluster, int32_t m, int32_t l,
                                                    int32_t gamma_max, int32_t *cl_n, int32_t *cl_Np,
@@ -24,11 +24,12 @@ __global__ __launch_bounds__(1024) void k_clusters(const int32_t *cam_cluster, i
     __shared__ int64_t part[1024];
     __shared__ int bad;
     const int tid = threadIdx.x;
+    const int nt = blockDim.x;
     int P = 1;
     while (P < m) P <<= 1;
     if (tid == 0) bad = 0;
     __syncthreads();
-    for (int i = tid; i < P; i += 1024) {
+    for (int i = tid; i < P; i += nt) {
         uint32_t key = 0xFFFFFFFFu;
         if (i < m) {
             int k = cam_cluster[i];
@@ -43,7 +44,7 @@ __global__ __launch_bounds__(1024) void k_clusters(const int32_t *cam_cluster, i
     __syncthreads();
     for (int size = 2; size <= P; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int i = tid; i < (P >> 1); i += 1024) {
+            for (int i = tid; i < (P >> 1); i += nt) {
                 const int lo = 2 * stride * (i / stride) + (i % stride);
                 const int hi = lo + stride;
                 const bool up = (lo & size) == 0;
@@ -56,7 +57,7 @@ __global__ __launch_bounds__(1024) void k_clusters(const int32_t *cam_cluster, i
             __syncthreads();
         }
     }
-    for (int k = tid; k <= l; k += 1024) {
+    for (int k = tid; k <= l; k += nt) {
         int lo = 0, hi = m;
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
@@ -64,13 +65,13 @@ __global__ __launch_bounds__(1024) void k_clusters(const int32_t *cam_cluster, i
         }
         cl_start[k] = lo;
     }
-    for (int p = tid; p < m; p += 1024) cl_cams[p] = (int32_t)(keys[p] & 0x7FFFu);
+    for (int p = tid; p < m; p += nt) cl_cams[p] = (int32_t)(keys[p] & 0x7FFFu);
     __syncthreads();
-    for (int p = tid; p < m; p += 1024) {
+    for (int p = tid; p < m; p += nt) {
         const int32_t cam = (int32_t)(keys[p] & 0x7FFFu);
         cam_local[cam] = p - cl_start[keys[p] >> 15];
     }
-    for (int k = tid; k < l; k += 1024) {
+    for (int k = tid; k < l; k += nt) {
         const int nk = cl_start[k + 1] - cl_start[k];
         if (nk > gamma_max) bad = 2;
         cl_n[k] = nk;
@@ -79,7 +80,7 @@ __global__ __launch_bounds__(1024) void k_clusters(const int32_t *cam_cluster, i
     __syncthreads();
     if (bad) {
         // nothing is assembled or solved for an invalid map; the step is rejected
-        for (int k = tid; k < l; k += 1024) {
+        for (int k = tid; k < l; k += nt) {
             cl_n[k] = 0;
             cl_Np[k] = 0;
         }
@@ -87,7 +88,7 @@ __global__ __launch_bounds__(1024) void k_clusters(const int32_t *cam_cluster, i
     }
     __syncthreads();
     // exclusive scan of Np^2 over clusters
-    const int chunk = (l + 1023) / 1024;
+    const int chunk = (l + nt - 1) / nt;
     const int k0 = tid * chunk, k1 = min(l, k0 + chunk);
     int64_t s = 0;
     for (int k = k0; k < k1; ++k) s += (int64_t)cl_Np[k] * cl_Np[k];
@@ -95,7 +96,7 @@ __global__ __launch_bounds__(1024) void k_clusters(const int32_t *cam_cluster, i
     __syncthreads();
     if (tid == 0) {
         int64_t run = 0;
-        for (int t = 0; t < 1024; ++t) {
+        for (int t = 0; t < nt; ++t) {
             const int64_t v = part[t];
             part[t] = run;
             run += v;
@@ -820,8 +821,15 @@ hipError_t launch_lm_init(stba_lm_state *s, double lambda0, double lambda_corr, 
 hipError_t launch_clusters(const int32_t *cam_cluster, int32_t m, int32_t l, int32_t gamma_max, int32_t *cl_n,
                            int32_t *cl_Np, int32_t *cl_start, int32_t *cl_cams, int32_t *cam_local,
                            int64_t *S_off, int32_t *status, hipStream_t st) {
-    k_clusters<<<1, 1024, 0, st>>>(cam_cluster, m, l, gamma_max, cl_n, cl_Np, cl_start, cl_cams, cam_local, S_off,
-                                   status);
+    // one thread per compare-exchange of the bitonic sort, so a small map uses a
+    // small block (cheaper barriers)
+    int P = 1;
+    while (P < m) P <<= 1;
+    int threads = P / 2;
+    if (threads < 64) threads = 64;
+    if (threads > 1024) threads = 1024;
+    k_clusters<<<1, threads, 0, st>>>(cam_cluster, m, l, gamma_max, cl_n, cl_Np, cl_start, cl_cams, cam_local, S_off,
+                                      status);
     return hipGetLastError();
 }
 

@@ -86,6 +86,14 @@ hipError_t launch_chol(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, con
                        double *dcam, int32_t *cl_status, int32_t max_Np, int32_t *flags, double *yx,
                        hipStream_t st);
 
+// MIXED precision: S0 = S before the factorisation, then one FP64 refinement
+// step of dcam against S0 with the factors.
+hipError_t launch_copy_S(const double *S, double *S0, const int64_t *S_off, int32_t l, int64_t S_cap,
+                         hipStream_t st);
+hipError_t launch_refine(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, const int64_t *S_off,
+                         const int32_t *cl_start, const int32_t *cl_cams, const double *S, const double *S0,
+                         const double *b, double *dcam, int32_t max_Np, hipStream_t st);
+
 template <typename T>
 hipError_t launch_backsub(const stba_problem &p, const int64_t *pt_off, const T *Jc, const T *Jp,
                           const double *Vinv, const double *wph, const double *dcam, double *dpt, hipStream_t st);

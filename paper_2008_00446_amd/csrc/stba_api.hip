@@ -17,7 +17,7 @@ struct Layout {
     size_t tmp_bytes;
     // per iteration
     size_t cl_n, cl_Np, cl_start, cl_cams, cam_local, cl_status, S_off;
-    size_t f, Jc, Jp, seg_head, seg_rec, obsd, Vinv, wph, S, b, dcam, dpt, partials, chol_flags, chol_yx;
+    size_t f, Jc, Jp, seg_head, seg_rec, obsd, Vinv, wph, S, S0, b, dcam, dpt, partials, chol_flags, chol_yx;
     int64_t S_cap, n_partials;
     int32_t max_Np;
     size_t total;
@@ -112,6 +112,8 @@ bool make_layout(const stba_problem *p, const stba_dims *d, int precision, Layou
     L.wph = take(8 * 3 * n);
     L.S_cap = s_capacity(p->m, d->gamma_max);
     L.S = take(8 * (size_t)L.S_cap);
+    // MIXED keeps the assembled S for the refinement step
+    L.S0 = precision == STBA_MIXED ? take(8 * (size_t)L.S_cap) : 0;
     L.b = take(8 * 9 * m);
     L.dcam = take(8 * 9 * m);
     L.dpt = take(8 * 3 * n);
@@ -185,14 +187,29 @@ int build_rcs_impl(const stba_problem *p, const stba_dims *d, const stba_sample 
     return STBA_OK;
 }
 
+// The cluster solves of Eq. 13; in MIXED precision with one FP64 refinement
+// step against the assembled S.
 template <typename T>
-int solve_impl(const stba_problem *p, const stba_dims *d, int32_t l, const T *Jc, const T *Jp, double *dcam,
-               double *dpt, int32_t *cl_status, const Layout &L, void *ws, hipStream_t st) {
-    (void)d;
+int cluster_solve(int32_t l, double *dcam, int32_t *cl_status, const Layout &L, void *ws, hipStream_t st) {
+    const bool mixed = sizeof(T) == sizeof(float);
+    if (mixed)
+        STBA_HIP(launch_copy_S(at<double>(ws, L.S), at<double>(ws, L.S0), at<int64_t>(ws, L.S_off), l, L.S_cap, st));
     STBA_HIP(launch_chol(l, at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np), at<int64_t>(ws, L.S_off),
                          at<int32_t>(ws, L.cl_start), at<int32_t>(ws, L.cl_cams), at<double>(ws, L.S),
                          at<double>(ws, L.b), dcam, cl_status, L.max_Np, at<int32_t>(ws, L.chol_flags),
                          at<double>(ws, L.chol_yx), st));
+    if (mixed)
+        STBA_HIP(launch_refine(l, at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np), at<int64_t>(ws, L.S_off),
+                               at<int32_t>(ws, L.cl_start), at<int32_t>(ws, L.cl_cams), at<double>(ws, L.S),
+                               at<double>(ws, L.S0), at<double>(ws, L.b), dcam, L.max_Np, st));
+    return STBA_OK;
+}
+
+template <typename T>
+int solve_impl(const stba_problem *p, const stba_dims *d, int32_t l, const T *Jc, const T *Jp, double *dcam,
+               double *dpt, int32_t *cl_status, const Layout &L, void *ws, hipStream_t st) {
+    (void)d;
+    STBA_TRY(cluster_solve<T>(l, dcam, cl_status, L, ws, st));
     STBA_HIP(launch_backsub<T>(*p, at<int64_t>(ws, L.pt_off), Jc, Jp, at<double>(ws, L.Vinv), at<double>(ws, L.wph),
                                dcam, dpt, st));
     return STBA_OK;
@@ -231,10 +248,7 @@ int lm_step_impl(const stba_problem *p, const stba_dims *d, const stba_sample *s
                              at<double>(ws, L.b), st));
     STBA_TRY(mark(5));
     double *dcam = at<double>(ws, L.dcam), *dpt = at<double>(ws, L.dpt);
-    STBA_HIP(launch_chol(s->l, at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np), at<int64_t>(ws, L.S_off),
-                         at<int32_t>(ws, L.cl_start), at<int32_t>(ws, L.cl_cams), at<double>(ws, L.S),
-                         at<double>(ws, L.b), dcam, at<int32_t>(ws, L.cl_status), L.max_Np,
-                         at<int32_t>(ws, L.chol_flags), at<double>(ws, L.chol_yx), st));
+    STBA_TRY(cluster_solve<T>(s->l, dcam, at<int32_t>(ws, L.cl_status), L, ws, st));
     STBA_TRY(mark(6));
     STBA_HIP(launch_backsub<T>(*p, at<int64_t>(ws, L.pt_off), Jc, Jp, at<double>(ws, L.Vinv), at<double>(ws, L.wph),
                                dcam, dpt, st));

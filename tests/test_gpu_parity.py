@@ -207,3 +207,88 @@ def test_residual_vjp_matches_oracle_gradient(precision, tol):
     assert rel(cam.grad.cpu().numpy(), gc) < tol
     assert rel(pt.grad.cpu().numpy(), gp) < tol
     assert rel(uv.grad.cpu().numpy(), gu) < tol
+
+
+@pytest.mark.parametrize("gamma", [3, 7, 11])
+def test_tile_parallel_cholesky_small_tile_counts(gamma):
+    """Cluster caps giving 1, 2 and 4 diagonal tiles per cluster (tile-parallel solve)."""
+    s = _small()
+    lab = _sgc(s, gamma, 1)
+    g = GpuProblem(s, gamma_max=gamma)
+    f, Jc, Jp, _ = g.residual_jacobian()
+    rcs = g.build(f, Jc, Jp, lab, 1e-3, 0.8, 2, 1)
+    dcam, dpt, cs = g.solve(rcs, Jc, Jp)
+    ref = O.stba_step(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv, lab, 1e-3, 0.8, 2, 1)
+    assert np.all(cs == 0)
+    assert rel(dcam, ref.dcam) < 1e-9
+    assert rel(dpt, ref.dpt) < 1e-9
+
+
+@pytest.mark.parametrize("precision,tol", [(S.STBA_FP64, 1e-9), (S.STBA_MIXED, 1e-4)])
+def test_many_clusters_use_workgroup_cholesky(precision, tol):
+    """40 singleton clusters with a cap of 40 cameras: too many tile wavefronts,
+    so every cluster is solved by one workgroup."""
+    s = _small()
+    lab = np.arange(s.m, dtype=np.int32)
+    g = GpuProblem(s, gamma_max=s.m, precision=precision)
+    f, Jc, Jp, _ = g.residual_jacobian()
+    rcs = g.build(f, Jc, Jp, lab, 1e-2)
+    dcam, dpt, cs = g.solve(rcs, Jc, Jp)
+    ref = O.stba_step(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv, lab, 1e-2)
+    assert np.all(cs == 0)
+    print(f"precision {precision}: dcam rel {rel(dcam, ref.dcam):.2e} dpt rel {rel(dpt, ref.dpt):.2e}")
+    assert rel(dcam, ref.dcam) < tol
+    assert rel(dpt, ref.dpt) < tol
+
+
+@pytest.mark.parametrize("lam", [1e-3, 1e-1])
+def test_mixed_precision_steps_match_oracle(lam):
+    """FP32 Jacobian and Schur assembly, FP64 Cholesky plus one refinement step:
+    steps and the candidate cost within 1e-4 relative of the FP64 oracle."""
+    s = _small()
+    seed, t = 5, 2
+    lab = _sgc(s, 12, t)
+    g = GpuProblem(s, gamma_max=12, precision=S.STBA_MIXED)
+    f, Jc, Jp, _ = g.residual_jacobian()
+    rcs = g.build(f, Jc, Jp, lab, lam, 1.0, seed, t)
+    dcam, dpt, cs = g.solve(rcs, Jc, Jp)
+    ref = O.stba_step(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv, lab, lam, 1.0, seed, t)
+    assert np.all(cs == 0)
+    ec, ep = rel(dcam, ref.dcam), rel(dpt, ref.dpt)
+    F_gpu = O.cost(O.residuals(s.cam0 + dcam, s.pt0 + dpt, s.obs_cam, s.obs_pt, s.obs_uv))
+    F_ref = O.cost(O.residuals(s.cam0 + ref.dcam, s.pt0 + ref.dpt, s.obs_cam, s.obs_pt, s.obs_uv))
+    print(f"lambda {lam}: dcam rel {ec:.2e} dpt rel {ep:.2e} F rel {abs(F_gpu - F_ref) / F_ref:.2e}")
+    assert ec < 1e-4 and ep < 1e-4
+    assert abs(F_gpu - F_ref) <= 1e-4 * F_ref
+
+
+def test_mixed_lm_iteration_matches_oracle():
+    s = synth.tiny_circle()
+    lab = synth.halves_map(16)
+    sol = S.StbaSolver(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv, gamma_max=8, lambda0=1e-3,
+                       precision=S.STBA_MIXED)
+    sol.step(sol.sample(lab, alpha=1.0, seed=0, it=0))
+    st = sol.read_state()
+    ref = O.lm_iteration(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv, lab, 1e-3, 1.0, 0, 0)
+    print(f"mixed F_new {st['F_new']:.9e} oracle {ref.F_new:.9e}")
+    assert st["status"] == 0
+    assert bool(st["accepted"]) == ref.accepted
+    assert abs(st["F_new"] - ref.F_new) <= 1e-4 * ref.F_new
+    assert rel(sol.cam.cpu().numpy() - s.cam0, ref.cam - s.cam0) < 1e-4
+
+
+def test_full_size_ring_iteration_matches_oracle():
+    """One LM iteration on the 200-camera ring (50k points, 400k observations)
+    with a Gamma = 50 graph-clustering map, against the FP64 oracle."""
+    s = synth.ring(m=200, n=50000, views=8, seed=0)
+    lab = _sgc(s, 50, 0)
+    sol = S.StbaSolver(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv, gamma_max=50, lambda0=1e-4)
+    sol.step(sol.sample(lab, alpha=1.0, seed=0, it=0))
+    st = sol.read_state()
+    ref = O.lm_iteration(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv, lab, 1e-4, 1.0, 0, 0)
+    print(f"ring: accepted {st['accepted']} F_new {st['F_new']:.12e} oracle {ref.F_new:.12e}")
+    assert st["status"] == 0
+    assert bool(st["accepted"]) == ref.accepted
+    assert abs(st["F_new"] - ref.F_new) <= 1e-9 * ref.F_new
+    assert rel(sol.cam.cpu().numpy() - s.cam0, ref.cam - s.cam0) < 1e-9
+    assert rel(sol.pt.cpu().numpy() - s.pt0, ref.pt - s.pt0) < 1e-9
