@@ -9,10 +9,19 @@ segments and correction, Schur assembly, cluster Cholesky, point update,
 candidate cost, accept).  Inputs are resident in HBM before the timed region;
 the cluster maps of all timed iterations are drawn and uploaded beforehand.
 
-Prints ONE JSON line.  `value` is LM iterations per second; `obs_per_s` is
-q x iterations/s.  `roofline` describes the kernel with the largest time per
-iteration, timed with HIP events on the library's stream; `cpu_baseline` times
-the FP64 oracle on the host for the first iterations of the same run.
+Prints ONE JSON line.  `value` is LM iterations per second of the timed FP64
+run (no events inside it); `obs_per_s` is q x iterations/s.  The per-phase
+split comes from a second, identical pass with HIP events between the phases on
+the library's stream.  `roofline` describes the phase with the largest time per
+iteration.  `mixed_vs_fp64` runs the same iterations in MIXED precision (FP32
+Jacobian and Schur assembly, FP64 Cholesky with one refinement step and FP64
+cost) from the same start and maps, and times it until its cost reaches the
+FP64 cost after K iterations (equal cost reduction).  `cpu_baseline` times the
+FP64 oracle on the host for the first iterations of the same run.
+
+--pmc-summary turns rocprofv3 counter CSVs (FETCH_SIZE and WRITE_SIZE runs of
+this benchmark and of --copy-calibration) into profiles/pmc_<phase>_<workload>.txt,
+the HBM traffic that `roofline.traffic` reports while the sources are unchanged.
 """
 from __future__ import annotations
 
@@ -54,6 +63,17 @@ def parse_args():
     ap.add_argument("--cpu-iters", type=int, default=2, help="oracle iterations timed for cpu_baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (to scale HBM counters)")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
+    ap.add_argument("--pmc-summary", action="store_true",
+                    help="write a profiles/pmc_*.txt summary from counter CSVs (no GPU work)")
+    ap.add_argument("--phase", default="cluster_cholesky")
+    ap.add_argument("--kernels", default="k_chol_tiles,k_zero_flags",
+                    help="comma-separated kernel name fragments belonging to --phase")
+    ap.add_argument("--fetch-csv")
+    ap.add_argument("--write-csv")
+    ap.add_argument("--calib-fetch-csv")
+    ap.add_argument("--calib-write-csv")
+    ap.add_argument("--command", default="", help="the commands that produced the CSVs (recorded)")
     return ap.parse_args()
 
 
@@ -65,6 +85,47 @@ def copy_calibration():
         y.copy_(x)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_read": x.numel() * 8, "copy_bytes_written": y.numel() * 8, "launches": 3}))
+
+
+def _counter_rows(path, counter):
+    import csv
+    return [(r["Kernel_Name"], float(r["Counter_Value"])) for r in csv.DictReader(open(path))
+            if r["Counter_Name"] == counter]
+
+
+def pmc_summary(args, workload):
+    """Average FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the phase's kernels,
+    scaled by what the same counters read for a copy of known size."""
+    frags = [k for k in args.kernels.split(",") if k]
+
+    def per_step(path, counter):
+        rows = [(n, v) for n, v in _counter_rows(path, counter) if any(f in n for f in frags)]
+        main = [v for n, v in rows if frags[0] in n]
+        # dispatches of the first kernel = phase launches; all kernels of the phase summed per launch
+        return sum(v for _, v in rows) / max(1, len(main)), len(main)
+
+    def calib(path, counter):
+        rows = [v for n, v in _counter_rows(path, counter) if "copyBuffer" in n or "copy" in n.lower()]
+        return max(rows)
+
+    fetch_kib, n_f = per_step(args.fetch_csv, "FETCH_SIZE")
+    write_kib, n_w = per_step(args.write_csv, "WRITE_SIZE")
+    copy_bytes = float(1 << 30)
+    cf = copy_bytes / (calib(args.calib_fetch_csv, "FETCH_SIZE"))   # bytes per counted KiB (fetch)
+    cw = copy_bytes / (calib(args.calib_write_csv, "WRITE_SIZE"))
+    traffic = fetch_kib * cf + write_kib * cw
+    path = os.path.join(ROOT, "profiles", f"pmc_{args.phase}_{workload}.txt")
+    with open(path, "w") as fh:
+        fh.write(f"# HBM traffic of phase {args.phase} (kernels {args.kernels}) on {workload}\n")
+        fh.write(f"# rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE, over bench.py; the same counters over\n")
+        fh.write(f"# bench.py --copy-calibration (1 GiB read + 1 GiB written per copy) give the scale.\n")
+        fh.write(f"# commands: {args.command}\n")
+        fh.write(f"source_hash = {source_hash()}\n")
+        fh.write(f"dispatches_fetch = {n_f}\ndispatches_write = {n_w}\n")
+        fh.write(f"fetch_kib_per_launch = {fetch_kib:.1f}\nwrite_kib_per_launch = {write_kib:.1f}\n")
+        fh.write(f"copy_bytes_per_fetch_kib = {cf:.2f}\ncopy_bytes_per_write_kib = {cw:.2f}\n")
+        fh.write(f"traffic_bytes_per_launch = {traffic:.0f}\n")
+    print(open(path).read())
 
 
 def algorithmic_model(scene, maps, es):
@@ -152,6 +213,30 @@ def cpu_baseline(scene, maps, lam0, iters):
             "F_after": F}
 
 
+def run_iterations(sol, samples, cam0, pt0, lam0, steps, events=None, snapshots=None):
+    """LM iterations 0..steps-1 from x0 (asynchronous).  events: per-iteration
+    phase events; snapshots: a device tensor receiving the cost after each
+    iteration."""
+    import paper_2008_00446_amd as S
+    sol.cam.copy_(cam0)
+    sol.pt.copy_(pt0)
+    S.stba_lm_init(sol.state, lam0, 0.1)
+    F_dev = sol.state[16:24].view(sol.cam.dtype)     # stba_lm_state.F
+    for t in range(steps):
+        sol.step(samples[t], events=None if events is None else events[t])
+        if snapshots is not None:
+            snapshots[t:t + 1].copy_(F_dev)
+
+
+def timed(fn):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
 def main():
     args = parse_args()
     if args.gpus != 1:
@@ -160,6 +245,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.pmc_summary:
+        pmc_summary(args, "ring_m200_n50000_q400000")
         return
     import torch
     import paper_2008_00446_amd as S
@@ -170,7 +258,8 @@ def main():
     scene = synth.ring(m=200, n=50_000, views=8, seed=0)
     workload = f"ring_m{scene.m}_n{scene.n}_q{scene.q}"
     e, w = synth.camera_graph(scene.obs_cam, scene.obs_pt, scene.m)
-    total = max(args.steps, args.warmup, args.cpu_iters)
+    mixed_max = 3 * args.steps
+    total = max(args.steps, args.warmup, args.cpu_iters, mixed_max)
     maps = [synth.sgc_map(e, w, scene.m, args.gamma, 10.0, 0, t) for t in range(total)]
     lam0 = 1e-4
     sol = S.StbaSolver(scene.cam0, scene.pt0, scene.obs_cam, scene.obs_pt, scene.obs_uv,
@@ -178,22 +267,15 @@ def main():
     samples = [sol.sample(maps[t], alpha=1.0, seed=0, it=t) for t in range(total)]
     cam0 = sol.cam.clone()
     pt0 = sol.pt.clone()
-    # warm-up iterations, then restart from x0 so the timed steps are iterations 0..K-1
-    for t in range(args.warmup):
-        sol.step(samples[t])
-    torch.cuda.synchronize()
-    sol.cam.copy_(cam0)
-    sol.pt.copy_(pt0)
-    S.stba_lm_init(sol.state, lam0, 0.1)
+    run_iterations(sol, samples, cam0, pt0, lam0, args.warmup)
+    # timed: K iterations, nothing else on the stream
+    elapsed = timed(lambda: run_iterations(sol, samples, cam0, pt0, lam0, args.steps))
+    st = sol.read_state()
+    # per-phase split: the same iterations again with events between the phases
     P = S.STBA_NUM_PHASES
     evs = [S.hip_events(P + 1) for _ in range(args.steps)]
+    run_iterations(sol, samples, cam0, pt0, lam0, args.steps, events=evs)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for t in range(args.steps):
-        sol.step(samples[t], events=evs[t])
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    st = sol.read_state()
     phase_ms = np.zeros(P)
     for ev in evs:
         for k in range(P):
@@ -236,15 +318,50 @@ def main():
         "obs_per_s": scene.q * args.steps / elapsed,
         "roofline": roofline,
         "phases": per_phase,
-        "lm": {"F_final": st["F"], "accepted": st["n_accept"], "jacobian_evals": st["n_jac"],
-               "rcs_builds": st["n_rcs"], "lambda_final": st["lambda_"], "status": st["status"]},
+        "lm": {"F_final": st["F"],
+               "accepted": st["n_accept"], "jacobian_evals": st["n_jac"], "rcs_builds": st["n_rcs"],
+               "lambda_final": st["lambda_"], "status": st["status"]},
         "model": stats, "source_hash": source_hash(),
     }
+    if not args.no_mixed and precision == S.STBA_FP64:
+        out["mixed_vs_fp64"] = mixed_leg(S, scene, samples_maps=maps, args=args, lam0=lam0, F_target=st["F"],
+                                         fp64_seconds=elapsed, cam0=cam0, pt0=pt0)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, maps, lam0, args.cpu_iters)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out))
+
+
+def mixed_leg(S, scene, samples_maps, args, lam0, F_target, fp64_seconds, cam0, pt0):
+    """Equal cost reduction: MIXED iterations from the same x0 and maps until the
+    cost is at most the FP64 cost after K iterations."""
+    import torch
+    solm = S.StbaSolver(scene.cam0, scene.pt0, scene.obs_cam, scene.obs_pt, scene.obs_uv,
+                        gamma_max=args.gamma, precision=S.STBA_MIXED, lambda0=lam0)
+    kmax = 3 * args.steps
+    samples = [solm.sample(samples_maps[t], alpha=1.0, seed=0, it=t) for t in range(kmax)]
+    run_iterations(solm, samples, cam0, pt0, lam0, args.warmup)
+    Fs = torch.empty(kmax, dtype=torch.float64, device="cuda")
+    run_iterations(solm, samples, cam0, pt0, lam0, kmax, snapshots=Fs)
+    Fh = Fs.cpu().numpy()
+    hit = np.nonzero(Fh <= F_target)[0]
+    res = {"F_target_fp64": F_target, "fp64_iterations": args.steps, "fp64_seconds": fp64_seconds,
+           "mixed_F_after_fp64_iterations": float(Fh[args.steps - 1])}
+    k_mixed = args.steps
+    t_same = timed(lambda: run_iterations(solm, samples, cam0, pt0, lam0, k_mixed))
+    res["mixed_iter_per_s"] = k_mixed / t_same
+    res["mixed_obs_per_s"] = scene.q * k_mixed / t_same
+    if hit.size:
+        n_to = int(hit[0]) + 1
+        t_to = timed(lambda: run_iterations(solm, samples, cam0, pt0, lam0, n_to))
+        res.update({"mixed_iterations_to_target": n_to, "mixed_seconds_to_target": t_to,
+                    "speedup_at_equal_cost_reduction": fp64_seconds / t_to})
+    else:
+        res.update({"mixed_iterations_to_target": None, "mixed_seconds_to_target": None,
+                    "speedup_at_equal_cost_reduction": None,
+                    "note": f"target not reached within {kmax} iterations"})
+    return res
 
 
 if __name__ == "__main__":
