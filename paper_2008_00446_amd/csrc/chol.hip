@@ -122,6 +122,76 @@ __device__ __forceinline__ bool diag_factor_invert(double *A, int64_t Np, int64_
     return bad;
 }
 
+// Diagonal tile of the tile-parallel factorisation, one wavefront: the tile
+// comes in Ls (row-major).  Lanes 0..31 carry row r of the tile and become row
+// r of L; lanes 32..63 carry column r of the identity and become column r of
+// W = L^-1.  Both updates of a right-looking step have the form
+// v_j -= v_k l_jk (row: l_rk l_jk; column of W: W[k][c] l_jk), so one
+// instruction serves both halves.  At step k the pivot comes from lane k
+// (v_readlane), the scaled column l_.k goes through LDS, and row k of W is final
+// and is written at once: W^T to the upper triangle of the tile in A (device
+// scope, diagonal included, so it holds 1 / L_kk) and W row-major to Wl.
+// Returns true if a pivot was not positive.
+__device__ __forceinline__ bool band_factor_invert(double *A, int64_t Np, int64_t off, int lane,
+                                                   double (*Ls)[kNB + 1], double (*Wl)[kNB + 1],
+                                                   double *col) {
+    const int r = lane & (kNB - 1);
+    const bool wl = lane >= kNB;
+    double v[kNB];
+#pragma unroll
+    for (int j = 0; j < kNB; ++j) v[j] = wl ? (j == r ? 1.0 : 0.0) : Ls[r][j];
+    bool bad = false;
+    int rq = r;
+    // the pivot of the next step only needs lane k+1's own entries
+    // (a_k+1,k+1 - l_k+1,k^2), so its reciprocal square root is computed while
+    // the broadcast of column k through LDS is in flight
+    double d = readlane_d(v[0], 0);
+    if (!(d > 0.0) || !isfinite(d)) {
+        bad = true;
+        d = 1.0;
+    }
+    double is = rsqrt_refined(d);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < kNB; ++k) {
+        // an opaque copy of the lane index per step: the lane compares are not
+        // hoisted into masks for all 32 steps at once
+        asm volatile("" : "+v"(rq));
+        // one scaling for every lane: rows r > k get l_rk, lane k gets d / sqrt(d)
+        // = L_kk, W lanes get W[k][c]; rows above k keep don't-care values that
+        // only touch entries above the diagonal
+        v[k] *= is;
+        if (k + 1 < kNB) {
+            if (!wl) col[rq] = v[k];
+            double lc[kNB];
+#pragma unroll
+            for (int j = k + 1; j < kNB; ++j) lc[j] = col[j];
+            __builtin_amdgcn_sched_barrier(0);
+            const double t = fma(-v[k], v[k], v[k + 1]);
+            double dn = readlane_d(t, k + 1);
+            if (!(dn > 0.0) || !isfinite(dn)) {
+                bad = true;
+                dn = 1.0;
+            }
+            is = rsqrt_refined(dn);
+            asm volatile("" : "+v"(is));   // computed here, not sunk to its use
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int j = k + 1; j < kNB; ++j) v[j] = fma(-v[k], lc[j], v[j]);
+#pragma unroll
+            for (int j = k + 1; j < kNB; ++j) asm volatile("" : "+v"(v[j]));
+        }
+        if (wl) {   // W[k][r] is final
+            Wl[k][rq] = v[k];
+            if (rq <= k)
+                __hip_atomic_store(A + (off + rq) + (off + k) * Np, v[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncwarp();
+    return bad;
+}
+
 // MFMA f64 16x16x4 register layout on gfx950 (checked on the device): operand
 // A[i][k] (16 x 4) in lane i + 16 k, operand B[k][j] (4 x 16) in lane j + 16 k,
 // result D[i][j] in lane j + 16 (i % 4), element i / 4.  With the first operand
@@ -201,39 +271,10 @@ __device__ inline void tile_update(double *A, int64_t Np, int64_t ri, int64_t cj
             for (int v = 0; v < 4; ++v) A[(ri + 16 * R + lr) + (cj + 16 * C + 4 * v + lk) * Np] = acc[R][C][v];
 }
 
-// Block triangular solves with a factored S_k (L in the lower tiles, W_pp^T in
-// the upper triangle of each diagonal tile, diagonal included), in place on x
-// (LDS), by all kCholThreads threads; sums in a fixed order.
-//   forward:  x_p = W_pp (x_p - sum_{j < p} L_pj x_j)
-//   backward: x_p = W_pp^T (x_p - sum_{i > p} L_ip^T x_i)
-__device__ void block_forward(const double *A, int64_t Np, int nt, double *x, double *red, double *zb, int tid) {
-    constexpr int G = kCholThreads / kNB;
-    for (int p = 0; p < nt; ++p) {
-        const int64_t off = (int64_t)p * kNB;
-        {
-            const int c = tid / G, g = tid % G;
-            double s = 0.0;
-            for (int64_t j = g; j < off; j += G) s = fma(A[(off + c) + j * Np], x[j], s);
-            red[c * G + g] = s;
-        }
-        __syncthreads();
-        if (tid < kNB) {
-            double s = x[off + tid];
-#pragma unroll
-            for (int g = 0; g < G; ++g) s -= red[tid * G + g];
-            zb[tid] = s;
-        }
-        __syncthreads();
-        if (tid < kNB) {
-            const int r = tid;
-            double s = 0.0;
-            for (int q = 0; q <= r; ++q) s = fma(A[(off + q) + (off + r) * Np], zb[q], s);   // W[r][q]
-            x[off + r] = s;
-        }
-        __syncthreads();
-    }
-}
-
+// Backward block solve with a factored S_k (L in the lower tiles, W_pp^T in the
+// upper triangle of each diagonal tile, diagonal included), in place on x
+// (LDS), by all kCholThreads threads; sums in a fixed order:
+//   x_p = W_pp^T (x_p - sum_{i > p} L_ip^T x_i)
 __device__ void block_backward(const double *A, int64_t Np, int nt, double *x, double *red, double *zb, int tid) {
     constexpr int G = kCholThreads / kNB;
     for (int p = nt - 1; p >= 0; --p) {
@@ -340,24 +381,24 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(int32_t l, const int32_t 
 // ---------------------------------------------------------------------------
 // Tile-parallel variant for maps with few clusters: the lower 32 x 32 tiles of
 // every S_k are spread over wavefronts, so a cluster runs on up to ~T^2 / 2
-// compute units instead of one.  Wavefront i of a cluster (the row worker)
-// owns the diagonal tile (i, i) and the tile (i, i-1) next to it; every other
-// tile (i, j), j <= i - 2, has a wavefront of its own.  An owner keeps its
-// tiles in MFMA registers and applies A_ij -= L_ip L_jp^T for p < j as soon as
-// tiles (i, p) and (j, p) are final, then solves the panel X = A_ij W_jj^T.  The
-// row worker solves (i, i-1), applies it to (i, i) straight from registers and
-// factors and inverts (i, i), so one hand-over separates consecutive diagonal
-// factorisations.  A final tile is written with device-scope stores and a flag
-// is raised after the stores have completed; readers poll the flag and read the
-// tile with device-scope loads.  No cache write-back or invalidation is needed,
-// since no wavefront reads a tile before it is final.  Every dependency of a
-// task points to an earlier (step, kind, row) key, so with all wavefronts
-// resident the dataflow cannot deadlock; every wait is still bounded, and a
-// time-out raises a grid-wide abort word that ends all other waits (the
-// cluster then reports STBA_EHIP).
-// The row workers then run the two triangular solves as chains:
-//   y_i = W_ii (b_i - sum_{j < i} L_ij y_j),  x_i = W_ii^T (y_i - sum_{k > i} L_ki^T x_k),
-// each sum in a fixed order.
+// compute units instead of one.  One band wavefront per cluster runs the whole
+// diagonal chain (panel (i, i-1), its update of (i, i), factor and inverse of
+// (i, i)) with W kept in its LDS, so no hand-over between wavefronts lies on the
+// critical path; row workers apply the other updates of tiles (i, i) and
+// (i, i-1) ahead of time, and every other tile (i, j), j <= i - 2, has its own
+// wavefront that keeps the tile in MFMA registers, applies A_ij -= L_ip L_jp^T
+// for p < j as soon as tiles (i, p) and (j, p) are final, then solves the panel
+// X = A_ij W_jj^T.  A tile handed to another wavefront (final, or partial for
+// the band worker) is written with device-scope stores and a flag is raised
+// after the stores have completed; readers poll the flag and read with
+// device-scope loads.  No cache write-back or invalidation is needed, since a
+// wavefront reads another's tile only after its flag.  Every dependency points
+// to an earlier diagonal step, so with all wavefronts resident the dataflow
+// cannot deadlock; every wait is still bounded, and a time-out raises a
+// grid-wide abort word that ends all other waits (the cluster then reports
+// STBA_EHIP).  The row workers also run the forward substitution
+// y_i = W_ii (b_i - sum_{j < i} L_ij y_j) as a chain; the backward solve is a
+// separate kernel (k_trisolve).
 // ---------------------------------------------------------------------------
 constexpr int kWaitPolls = 1 << 20;
 
@@ -466,10 +507,49 @@ __device__ inline void share32(double *zs, double v, int lane) {
     __syncwarp();
 }
 
-// Flags per cluster: [tile (i, j) at i (i + 1) / 2 + j][y_i at tt + i][x_i at tt + tmax + i],
-// tt = tmax (tmax + 1) / 2; tile flags are 1 (final) or 2 (final, pivot failed).
-// The word after the last cluster is the abort word.  Wavefronts per cluster:
-// tmax row workers, then one per tile (i, j), j <= i - 2.
+// Panel solve X = T W^T with W = L_jj^-1 row-major in LDS (zero above the diagonal).
+__device__ inline void panel_solve_lds(const d4 (&acc)[2][2], const double (*Wl)[kNB + 1], int lr, int lk,
+                                       d4 (&x)[2][2]) {
+#pragma unroll
+    for (int R = 0; R < 2; ++R)
+#pragma unroll
+        for (int C = 0; C < 2; ++C) x[R][C] = (d4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+        const double a0 = Wl[lr][4 * kk + lk], a1 = Wl[16 + lr][4 * kk + lk];
+        x[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, acc[0][kk >> 2][kk & 3], x[0][0], 0, 0, 0);
+        x[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, acc[0][kk >> 2][kk & 3], x[0][1], 0, 0, 0);
+        x[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, acc[1][kk >> 2][kk & 3], x[1][0], 0, 0, 0);
+        x[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, acc[1][kk >> 2][kk & 3], x[1][1], 0, 0, 0);
+    }
+}
+
+__device__ inline void load_tile_dev(const double *A, int64_t Np, int64_t ri, int64_t cj, int lr, int lk,
+                                     d4 (&acc)[2][2]) {
+#pragma unroll
+    for (int R = 0; R < 2; ++R)
+#pragma unroll
+        for (int C = 0; C < 2; ++C)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                acc[R][C][v] = ld_dev(A + (ri + 16 * R + lr) + (cj + 16 * C + 4 * v + lk) * Np);
+}
+
+// Wavefront roles per cluster (wave w of the cluster's wpc wavefronts):
+//   w = 0, the band worker: the whole diagonal chain.  Step i takes the partial
+//     tiles P_i,i-1 and P_ii (all updates but the last applied), solves the panel
+//     L_i,i-1 = P_i,i-1 W_i-1^T with W_i-1 still in its LDS, applies
+//     P_ii -= L_i,i-1 L_i,i-1^T from registers, and factors and inverts the
+//     diagonal tile; no hand-over between wavefronts lies on this chain.
+//   w = 1 + i, row worker i: applies A_ii -= L_ip L_ip^T and
+//     A_i,i-1 -= L_ip L_i-1,p^T for p <= i - 2 as the panels become final,
+//     publishes the partial tiles, then runs the forward chain
+//     y_i = W_ii (b_i - sum_{j < i} L_ij y_j).
+//   w > tmax, one wavefront per tile (i, j), j <= i - 2.
+// Flags per cluster: [tile (i, j) final at i (i + 1) / 2 + j][y_i at tt + i]
+// [partial tiles of row i at tt + tmax + i], tt = tmax (tmax + 1) / 2; diagonal
+// tile flags are 1 (final) or 2 (final, pivot failed).  The word after the last
+// cluster is the abort word.
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_chol_tiles(
     int32_t wpc, int32_t tmax, int32_t fpc, const int32_t *__restrict__ cl_n, const int32_t *__restrict__ cl_Np,
     const int64_t *__restrict__ S_off, const int32_t *__restrict__ cl_start, const int32_t *__restrict__ cl_cams,
@@ -489,13 +569,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void
     }
     const int tt = tmax * (tmax + 1) / 2;
     int32_t *fl = flags + (int64_t)k * fpc;
+    int32_t *fl_y = fl + tt;
+    int32_t *fl_part = fl + tt + tmax;
     int32_t *abort_w = flags + (int64_t)l * fpc;
     double *A = S + S_off[k];
     const int lr = lane & 15, lk = lane >> 4;
     bool ok = true;
-    if (w >= tmax) {
+    if (w > tmax) {
         // tile (i, j), j <= i - 2
-        const int g = w - tmax;
+        const int g = w - 1 - tmax;
         int i2 = (int)((sqrt(8.0 * g + 1.0) - 1.0) * 0.5);
         while ((i2 + 1) * (i2 + 2) / 2 <= g) ++i2;
         while (i2 * (i2 + 1) / 2 > g) --i2;
@@ -521,56 +603,71 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void
         if (!ok && lane == 0) cl_status[k] = STBA_EHIP;
         return;
     }
-    // row worker i: tiles (i, i) and (i, i-1)
-    const int i = w;
+    if (w == 0) {
+        // band worker
+        for (int i = 0; i < T; ++i) {
+            ok &= wait_flag(fl_part + i, abort_w) != 0;
+            const int64_t ri = (int64_t)i * kNB;
+            d4 accD[2][2];
+            load_tile_dev(A, Np, ri, ri, lr, lk, accD);
+            if (i >= 1) {
+                d4 accP[2][2], x[2][2];
+                load_tile_dev(A, Np, ri, ri - kNB, lr, lk, accP);
+                panel_solve_lds(accP, Wi, lr, lk, x);
+                store_tile_dev(A, Np, ri, ri - kNB, lr, lk, x);
+                double li[2][8];
+#pragma unroll
+                for (int R = 0; R < 2; ++R)
+#pragma unroll
+                    for (int kk = 0; kk < 8; ++kk) li[R][kk] = x[R][kk >> 2][kk & 3];
+                mfma_downdate(accD, li, li);
+            }
+            __syncwarp();   // the previous step's W has been read
+#pragma unroll
+            for (int R = 0; R < 2; ++R)
+#pragma unroll
+                for (int C = 0; C < 2; ++C)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) Ls[16 * R + lr][16 * C + 4 * v + lk] = accD[R][C][v];
+            // the panel stores were issued before the update: their flag now waits less
+            if (i >= 1) raise_flag(fl + tile_ix(i, i - 1), 1);
+            __syncwarp();
+            const bool bad = band_factor_invert(A, Np, ri, lane, Ls, Wi, zs);
+            raise_flag(fl + tile_ix(i, i), bad ? 2 : 1);
+        }
+        if (!ok && lane == 0) cl_status[k] = STBA_EHIP;
+        return;
+    }
+    // row worker i
+    const int i = w - 1;
     if (i >= T) return;
     const int64_t ri = (int64_t)i * kNB;
-    d4 accD[2][2], accP[2][2];
-    load_tile(A, Np, ri, ri, lr, lk, accD);
-    if (i >= 1) load_tile(A, Np, ri, ri - kNB, lr, lk, accP);
-    for (int p = 0; p + 1 < i; ++p) {
-        ok &= wait_flag(fl + tile_ix(i, p), abort_w) != 0;
-        ok &= wait_flag(fl + tile_ix(i - 1, p), abort_w) != 0;
-        double li[2][8], lj[2][8];
-        load_panel(A, Np, ri, (int64_t)p * kNB, lr, lk, li);
-        load_panel(A, Np, ri - kNB, (int64_t)p * kNB, lr, lk, lj);
-        mfma_downdate(accP, li, lj);
-        mfma_downdate(accD, li, li);
+    {
+        d4 accD[2][2], accP[2][2];
+        load_tile(A, Np, ri, ri, lr, lk, accD);
+        if (i >= 1) load_tile(A, Np, ri, ri - kNB, lr, lk, accP);
+        for (int p = 0; p + 1 < i; ++p) {
+            ok &= wait_flag(fl + tile_ix(i, p), abort_w) != 0;
+            ok &= wait_flag(fl + tile_ix(i - 1, p), abort_w) != 0;
+            double li[2][8], lj[2][8];
+            load_panel(A, Np, ri, (int64_t)p * kNB, lr, lk, li);
+            load_panel(A, Np, ri - kNB, (int64_t)p * kNB, lr, lk, lj);
+            mfma_downdate(accP, li, lj);
+            mfma_downdate(accD, li, li);
+        }
+        store_tile_dev(A, Np, ri, ri, lr, lk, accD);
+        if (i >= 1) store_tile_dev(A, Np, ri, ri - kNB, lr, lk, accP);
+        raise_flag(fl_part + i, 1);
     }
-    if (i >= 1) {
-        ok &= wait_flag(fl + tile_ix(i - 1, i - 1), abort_w) != 0;
-        d4 x[2][2];
-        panel_solve(accP, A + (ri - kNB) + (ri - kNB) * Np, Np, lr, lk, x);
-        store_tile_dev(A, Np, ri, ri - kNB, lr, lk, x);
-        raise_flag(fl + tile_ix(i, i - 1), 1);
-        double li[2][8];
-#pragma unroll
-        for (int R = 0; R < 2; ++R)
-#pragma unroll
-            for (int kk = 0; kk < 8; ++kk) li[R][kk] = x[R][kk >> 2][kk & 3];
-        mfma_downdate(accD, li, li);
-    }
-    // diagonal tile: factor and invert in registers (handed over through LDS, so
-    // the tile in S is only ever written at device scope)
-#pragma unroll
-    for (int R = 0; R < 2; ++R)
-#pragma unroll
-        for (int C = 0; C < 2; ++C)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) Ls[16 * R + lr][16 * C + 4 * v + lk] = accD[R][C][v];
-    __syncwarp();
-    const bool bad = diag_factor_invert<true>(A, Np, ri, lane, Ls, Wi, zs, nullptr);
-    raise_flag(fl + tile_ix(i, i), bad ? 2 : 1);
     // forward: y_i = W_ii (b_i - sum_j L_ij y_j); lane r (and r + 32) holds entry r
     const int r = lane & (kNB - 1);
     const int N = 9 * cl_n[k];
     const int c0 = cl_start[k];
-    double *yv = yx + (int64_t)k * 2 * tmax * kNB;   // y_0 .. y_{T-1}, then x_0 .. x_{T-1}
-    double *xv = yv + (int64_t)tmax * kNB;
+    double *yv = yx + (int64_t)k * tmax * kNB;   // y_0 .. y_{T-1}
     const int64_t row = ri + r;
     double z = row < N ? b[9 * (int64_t)cl_cams[c0 + row / 9] + row % 9] : 0.0;
     for (int jj = 0; jj < i; ++jj) {
-        ok &= wait_flag(fl + tt + jj, abort_w) != 0;
+        ok &= wait_flag(fl_y + jj, abort_w) != 0;
         const double *L = A + ri + r + (int64_t)jj * kNB * Np;
         double s0 = 0.0, s1 = 0.0;
 #pragma unroll
@@ -581,35 +678,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void
         z -= s0 + s1;
     }
     share32(zs, z, lane);
-    double y = 0.0;
-#pragma unroll 8
-    for (int c = 0; c < kNB; ++c) y = fma(Wi[r][c], zs[c], y);
-    if (lane < kNB) st_dev(yv + ri + r, y);
-    raise_flag(fl + tt + i, 1);
-    // backward: x_i = W_ii^T (y_i - sum_{kk > i} L_{kk,i}^T x_kk), kk descending
-    z = y;
-    for (int kk = T - 1; kk > i; --kk) {
-        ok &= wait_flag(fl + tt + tmax + kk, abort_w) != 0;
-        const double *L = A + (int64_t)kk * kNB + (ri + r) * Np;   // column r of tile (kk, i)
-        double s0 = 0.0, s1 = 0.0;
+    ok &= wait_flag(fl + tile_ix(i, i), abort_w) != 0;
+    // W[r][q] = W^T[q][r], the upper triangle of the final diagonal tile
+    const double *D = A + ri + (ri + r) * Np;
+    double y0 = 0.0, y1 = 0.0;
 #pragma unroll
-        for (int c = 0; c < kNB; c += 2) {
-            s0 = fma(ld_dev(L + c), ld_dev(xv + kk * kNB + c), s0);
-            s1 = fma(ld_dev(L + c + 1), ld_dev(xv + kk * kNB + c + 1), s1);
-        }
-        z -= s0 + s1;
+    for (int q = 0; q < kNB; q += 2) {
+        const double w0 = ld_dev(D + q), w1 = ld_dev(D + q + 1);
+        y0 = fma(q <= r ? w0 : 0.0, zs[q], y0);
+        y1 = fma(q + 1 <= r ? w1 : 0.0, zs[q + 1], y1);
     }
-    share32(zs, z, lane);
-    double xr = 0.0;
-#pragma unroll 8
-    for (int c = 0; c < kNB; ++c) xr = fma(Wi[c][r], zs[c], xr);
-    if (lane < kNB) {
-        st_dev(xv + ri + r, xr);
-        if (row < N) dcam[9 * (int64_t)cl_cams[c0 + row / 9] + row % 9] = xr;
-    }
-    raise_flag(fl + tt + tmax + i, 1);
-    if (i == 0 && lane == 0) {
-        // x_0 depends on every tile of the cluster: all pivots are known here
+    if (lane < kNB) st_dev(yv + ri + r, y0 + y1);
+    raise_flag(fl_y + i, 1);
+    // y_{T-1} depends on every tile of the cluster: all pivots are known here
+    if (i == T - 1 && lane == 0) {
         bool anybad = false;
         for (int p = 0; p < T; ++p)
             anybad |= __hip_atomic_load(fl + tile_ix(p, p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 2;
@@ -620,55 +702,203 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void
     }
 }
 
-// One step of iterative refinement in FP64 (MIXED precision): with S0 the
-// assembled S_k kept from before the factorisation,
-//   r = b - S0 x,  x += S^-1 r  (the factors of S_k),
-// one workgroup per cluster; S0 is symmetric with its lower triangle stored.
-__global__ __launch_bounds__(kCholThreads) void k_refine(const int32_t *__restrict__ cl_n,
+// ---------------------------------------------------------------------------
+// Triangular solves with the factors of S_k (L in the lower tiles, W_pp^T in
+// the upper triangle of diagonal tile p, diagonal included), one workgroup per
+// cluster, right-looking: once block p of the solution is known, the right-hand
+// sides of all remaining blocks are updated at once, and every thread loads the
+// factor entries of its next step while the current step runs, so a step is two
+// barriers and two short dot products instead of a memory round trip.
+//   forward:  y_p = W_pp z_p,   z_i -= L_ip y_p   (i > p)
+//   backward: x_p = W_pp^T z_p, z_j -= L_pj^T x_p (j < p)
+// Threads 0..kTsUpd-1 update right-hand sides (output o keeps the same block
+// row across steps); the last wavefront applies the diagonal blocks.
+// Modes: kTsFromY: dcam = backward(y), y = the forward solution of the tile
+//   factorisation; kTsRefine (MIXED): dcam += backward(forward(r)) with r the
+//   residual b - S0 x from k_resid (one FP64 refinement step).
+// ---------------------------------------------------------------------------
+constexpr int kTsThreads = 512;
+constexpr int kTsUpd = kTsThreads - 64;
+constexpr int kTsFromY = 1, kTsRefine = 2;
+
+// Workgroup barrier for data exchanged through LDS only: waits for this
+// wavefront's LDS operations, not for its global loads, so that loads issued for
+// a later step stay in flight across the barrier (__syncthreads would wait for
+// them).  The empty asm statements keep the compiler from moving memory
+// accesses across it.
+__device__ inline void lds_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0); vmcnt and expcnt untouched
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// One sweep over the tiles; v (LDS) holds the right-hand side and receives the
+// solution; ys (LDS, 32) carries the block just solved.
+template <bool kFwd>
+__device__ __attribute__((noinline)) void ts_sweep(const double *A, int64_t Np, int T, double *v, double *ys, int tid) {
+    const int r = tid & (kNB - 1);
+    const bool diag_wave = tid >= kTsUpd;
+    const int o = tid;   // update output (first one; more only for T > kTsUpd / 32 + 1)
+    double cur[kNB];
+    // prefetch for the first step
+    auto addr_upd = [&](int p, int oo) -> const double * {
+        if (kFwd) {   // z_i, i = T-1 - oo/32, row r: L(off_i + r, off_p + c) at + c * Np
+            const int i = T - 1 - oo / kNB;
+            return A + (int64_t)i * kNB + (oo & (kNB - 1)) + (int64_t)p * kNB * Np;
+        } else {      // z_j, j = oo/32, column c: L(off_p + rr, off_j + c) at + rr
+            const int j = oo / kNB;
+            return A + (int64_t)p * kNB + ((int64_t)j * kNB + (oo & (kNB - 1))) * Np;
+        }
+    };
+    auto addr_diag = [&](int p) -> const double * {
+        const int64_t off = (int64_t)p * kNB;
+        // forward: W[r][q] = D(q, r) at + q; backward: W^T[r][c] = D(r, c) at + c * Np
+        return kFwd ? A + off + (off + r) * Np : A + (off + r) + off * Np;
+    };
+    const int p0 = kFwd ? 0 : T - 1;
+    if (diag_wave) {
+        const double *d = addr_diag(p0);
+#pragma unroll
+        for (int c = 0; c < kNB; ++c) cur[c] = kFwd ? d[c] : d[(int64_t)c * Np];
+    } else {
+        const int nact = kFwd ? (T - 1 - p0) * kNB : p0 * kNB;
+        if (o < nact) {
+            const double *u = addr_upd(p0, o);
+#pragma unroll
+            for (int c = 0; c < kNB; ++c) cur[c] = kFwd ? u[(int64_t)c * Np] : u[c];
+        }
+    }
+    for (int step = 0; step < T; ++step) {
+        const int p = kFwd ? step : T - 1 - step;
+        const int pn = kFwd ? p + 1 : p - 1;   // next step's block
+        const int64_t off = (int64_t)p * kNB;
+        double nxt[kNB];
+        if (diag_wave) {
+            if (step + 1 < T) {
+                const double *d = addr_diag(pn);
+#pragma unroll
+                for (int c = 0; c < kNB; ++c) nxt[c] = kFwd ? d[c] : d[(int64_t)c * Np];
+            }
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int c = 0; c < kNB; c += 2) {
+                const bool in0 = kFwd ? c <= r : c >= r, in1 = kFwd ? c + 1 <= r : c + 1 >= r;
+                s0 = fma(in0 ? cur[c] : 0.0, v[off + c], s0);
+                s1 = fma(in1 ? cur[c + 1] : 0.0, v[off + c + 1], s1);
+            }
+            if (tid < kTsUpd + kNB) ys[r] = s0 + s1;
+        } else {
+            const int nn = kFwd ? (T - 1 - pn) * kNB : pn * kNB;   // outputs of the next step
+            if (step + 1 < T && o < nn) {
+                const double *u = addr_upd(pn, o);
+#pragma unroll
+                for (int c = 0; c < kNB; ++c) nxt[c] = kFwd ? u[(int64_t)c * Np] : u[c];
+            }
+        }
+        lds_barrier();
+        if (diag_wave) {
+            if (tid < kTsUpd + kNB) v[off + r] = ys[r];
+        } else {
+            const int nact = kFwd ? (T - 1 - p) * kNB : p * kNB;
+            if (o < nact) {
+                double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+                for (int c = 0; c < kNB; c += 2) {
+                    s0 = fma(cur[c], ys[c], s0);
+                    s1 = fma(cur[c + 1], ys[c + 1], s1);
+                }
+                const int blk = kFwd ? T - 1 - o / kNB : o / kNB;
+                v[(int64_t)blk * kNB + (o & (kNB - 1))] -= s0 + s1;
+            }
+            for (int oo = o + kTsUpd; oo < nact; oo += kTsUpd) {   // clusters with many tiles
+                const double *u = addr_upd(p, oo);
+                double s = 0.0;
+                for (int c = 0; c < kNB; ++c) s = fma(kFwd ? u[(int64_t)c * Np] : u[c], ys[c], s);
+                const int blk = kFwd ? T - 1 - oo / kNB : oo / kNB;
+                v[(int64_t)blk * kNB + (oo & (kNB - 1))] -= s;
+            }
+        }
+        lds_barrier();
+        if (step + 1 < T) {
+#pragma unroll
+            for (int c = 0; c < kNB; ++c) cur[c] = nxt[c];
+        }
+    }
+}
+
+__global__ __launch_bounds__(kTsThreads) void k_trisolve(int mode, const int32_t *__restrict__ cl_n,
                                                          const int32_t *__restrict__ cl_Np,
                                                          const int64_t *__restrict__ S_off,
                                                          const int32_t *__restrict__ cl_start,
                                                          const int32_t *__restrict__ cl_cams,
-                                                         const double *__restrict__ S, const double *__restrict__ S0,
-                                                         const double *__restrict__ b, double *__restrict__ dcam,
-                                                         int32_t max_Np) {
+                                                         const double *__restrict__ S,
+                                                         const double *__restrict__ rhs, int32_t rstride,
+                                                         double *__restrict__ dcam, int32_t max_Np) {
     extern __shared__ double smem[];
-    double *x = smem;
-    double *rr = x + max_Np;
-    double *red = rr + max_Np;       // kCholThreads
-    double *zb = red + kCholThreads; // kNB
+    double *v = smem;               // max_Np
+    double *ys = v + max_Np;        // kNB
     const int k = blockIdx.x;
     const int tid = threadIdx.x;
     const int nk = cl_n[k];
     if (nk == 0) return;
     const int64_t Np = cl_Np[k];
     const int N = 9 * nk;
-    const int nt = (int)(Np / kNB);
+    const int T = (int)(Np / kNB);
     const double *A = S + S_off[k];
-    const double *A0 = S0 + S_off[k];
     const int c0 = cl_start[k];
-    for (int i = tid; i < Np; i += kCholThreads) x[i] = (i < N) ? dcam[9 * (int64_t)cl_cams[c0 + i / 9] + i % 9] : 0.0;
+    for (int i = tid; i < Np; i += kTsThreads) v[i] = rhs[(int64_t)k * rstride + i];
     __syncthreads();
-    constexpr int G = kCholThreads / kNB;
-    for (int64_t rb = 0; rb < Np; rb += kNB) {
-        const int c = tid / G, g = tid % G;
-        const int64_t i = rb + c;
-        double s = 0.0;
-        for (int64_t j = g; j < Np; j += G) s = fma(j <= i ? A0[i + j * Np] : A0[j + i * Np], x[j], s);
-        red[c * G + g] = s;
-        __syncthreads();
-        if (tid < kNB) {
-            const int64_t row = rb + tid;
-            double v = row < N ? b[9 * (int64_t)cl_cams[c0 + row / 9] + row % 9] : 0.0;
-#pragma unroll
-            for (int gg = 0; gg < G; ++gg) v -= red[tid * G + gg];
-            rr[row] = v;
-        }
-        __syncthreads();
+    if (mode == kTsRefine) ts_sweep<true>(A, Np, T, v, ys, tid);
+    ts_sweep<false>(A, Np, T, v, ys, tid);
+    __syncthreads();
+    for (int i = tid; i < N; i += kTsThreads) {
+        double *d = dcam + 9 * (int64_t)cl_cams[c0 + i / 9] + i % 9;
+        *d = mode == kTsRefine ? *d + v[i] : v[i];
     }
-    block_forward(A, Np, nt, rr, red, zb, tid);
-    block_backward(A, Np, nt, rr, red, zb, tid);
-    for (int i = tid; i < N; i += kCholThreads) dcam[9 * (int64_t)cl_cams[c0 + i / 9] + i % 9] = x[i] + rr[i];
+}
+
+// MIXED refinement residual r = b - S0 x for 32 rows of one cluster per
+// workgroup (x = the current dcam); S0 is symmetric with its lower triangle
+// stored.  8 threads per row, partial sums added in a fixed order.
+__global__ __launch_bounds__(256) void k_resid(int32_t nrb, const int32_t *__restrict__ cl_n,
+                                               const int32_t *__restrict__ cl_Np,
+                                               const int64_t *__restrict__ S_off,
+                                               const int32_t *__restrict__ cl_start,
+                                               const int32_t *__restrict__ cl_cams,
+                                               const double *__restrict__ S0, const double *__restrict__ b,
+                                               const double *__restrict__ dcam, double *__restrict__ r,
+                                               int32_t rstride) {
+    extern __shared__ double smem[];
+    double *x = smem;                // Np
+    __shared__ double red[8][kNB];
+    const int k = (int)(blockIdx.x / (unsigned)nrb);
+    const int rb = (int)(blockIdx.x - (unsigned)k * (unsigned)nrb);
+    const int nk = cl_n[k];
+    const int64_t Np = cl_Np[k];
+    if (nk == 0 || (int64_t)rb * kNB >= Np) return;
+    const int N = 9 * nk;
+    const int c0 = cl_start[k];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < Np; i += 256) x[i] = (i < N) ? dcam[9 * (int64_t)cl_cams[c0 + i / 9] + i % 9] : 0.0;
+    __syncthreads();
+    const double *A0 = S0 + S_off[k];
+    const int rr = tid & (kNB - 1), g = tid >> 5;
+    const int64_t i = (int64_t)rb * kNB + rr;
+    double s0 = 0.0, s1 = 0.0;
+    int64_t j = g;
+    for (; j <= i; j += 8) s0 = fma(A0[i + j * Np], x[j], s0);        // lower part of row i
+    for (; j < Np; j += 8) s1 = fma(A0[j + i * Np], x[j], s1);        // the rest by symmetry
+    red[g][rr] = s0 + s1;
+    __syncthreads();
+    if (tid < kNB) {
+        double s = 0.0;
+#pragma unroll
+        for (int gg = 0; gg < 8; ++gg) s += red[gg][tid];
+        const int64_t row = (int64_t)rb * kNB + tid;
+        const double bi = row < N ? b[9 * (int64_t)cl_cams[c0 + row / 9] + row % 9] : 0.0;
+        r[(int64_t)k * rstride + row] = bi - s;
+    }
 }
 
 // S0 = S over the used part (S_off[l] entries)
@@ -704,12 +934,12 @@ int64_t chol_tile_resident() {
 int chol_tile_layout(int32_t l, int32_t max_Np, int32_t *wpc, int32_t *tmax, int32_t *fpc) {
     const int32_t tm = max_Np / kNB;
     if (tm < 1) return 0;
-    const int64_t waves = (int64_t)tm + (int64_t)(tm - 1) * (tm - 2) / 2;
+    const int64_t waves = 1 + (int64_t)tm + (int64_t)(tm - 1) * (tm - 2) / 2;   // band, rows, tiles
     if ((int64_t)l * waves > kCholTileWaves) return 0;
     // keep a quarter of the resident capacity in reserve
     if (4 * (int64_t)l * waves > 3 * chol_tile_resident()) return 0;
     const int64_t words = (int64_t)tm * (tm + 1) / 2 + 2 * tm;
-    if ((int64_t)l * words + 1 > chol_flag_words() || 2 * (int64_t)l * tm * kNB > chol_yx_doubles()) return 0;
+    if ((int64_t)l * words + 1 > chol_flag_words() || (int64_t)l * tm * kNB > chol_yx_doubles()) return 0;
     *tmax = tm;
     *wpc = (int32_t)waves;
     *fpc = (int32_t)words;
@@ -718,18 +948,33 @@ int chol_tile_layout(int32_t l, int32_t max_Np, int32_t *wpc, int32_t *tmax, int
 
 hipError_t launch_chol(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, const int64_t *S_off,
                        const int32_t *cl_start, const int32_t *cl_cams, double *S, const double *b, double *dcam,
-                       int32_t *cl_status, int32_t max_Np, int32_t *flags, double *yx, hipStream_t st) {
+                       int32_t *cl_status, int32_t max_Np, int32_t *flags, double *yx, const double *S0,
+                       double *rbuf, hipStream_t st) {
     int32_t wpc = 0, tmax = 0, fpc = 0;
     if (flags && yx && chol_tile_layout(l, max_Np, &wpc, &tmax, &fpc)) {
         const int64_t nflags = (int64_t)l * fpc + 1;
         k_zero_flags<<<(unsigned)((nflags + 255) / 256), 256, 0, st>>>(flags, nflags);
         k_chol_tiles<<<(unsigned)((int64_t)l * wpc), 64, 0, st>>>(wpc, tmax, fpc, cl_n, cl_Np, S_off, cl_start, cl_cams,
                                                                  S, b, dcam, cl_status, flags, l, yx);
+        // backward solve by one workgroup per cluster
+        const size_t shmem = sizeof(double) * ((size_t)max_Np + kNB);
+        k_trisolve<<<(unsigned)l, kTsThreads, shmem, st>>>(kTsFromY, cl_n, cl_Np, S_off, cl_start, cl_cams, S, yx,
+                                                           tmax * kNB, dcam, max_Np);
+        if (S0) {
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            return launch_refine(l, cl_n, cl_Np, S_off, cl_start, cl_cams, S, S0, b, dcam, rbuf, max_Np, st);
+        }
         return hipGetLastError();
     }
     const size_t shmem = sizeof(double) * (2 * (size_t)kNB * (kNB + 1) + 2 * kNB + (size_t)max_Np + kCholThreads + kNB);
     k_chol<<<(unsigned)l, kCholThreads, shmem, st>>>(l, cl_n, cl_Np, S_off, cl_start, cl_cams, S, b, dcam, cl_status,
                                                      max_Np);
+    if (S0) {
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        return launch_refine(l, cl_n, cl_Np, S_off, cl_start, cl_cams, S, S0, b, dcam, rbuf, max_Np, st);
+    }
     return hipGetLastError();
 }
 
@@ -744,9 +989,13 @@ hipError_t launch_copy_S(const double *S, double *S0, const int64_t *S_off, int3
 
 hipError_t launch_refine(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, const int64_t *S_off,
                          const int32_t *cl_start, const int32_t *cl_cams, const double *S, const double *S0,
-                         const double *b, double *dcam, int32_t max_Np, hipStream_t st) {
-    const size_t shmem = sizeof(double) * (2 * (size_t)max_Np + kCholThreads + kNB);
-    k_refine<<<(unsigned)l, kCholThreads, shmem, st>>>(cl_n, cl_Np, S_off, cl_start, cl_cams, S, S0, b, dcam, max_Np);
+                         const double *b, double *dcam, double *rbuf, int32_t max_Np, hipStream_t st) {
+    const int32_t nrb = max_Np / kNB;
+    k_resid<<<(unsigned)((int64_t)l * nrb), 256, sizeof(double) * (size_t)max_Np, st>>>(
+        nrb, cl_n, cl_Np, S_off, cl_start, cl_cams, S0, b, dcam, rbuf, max_Np);
+    const size_t shmem = sizeof(double) * ((size_t)max_Np + kNB);
+    k_trisolve<<<(unsigned)l, kTsThreads, shmem, st>>>(kTsRefine, cl_n, cl_Np, S_off, cl_start, cl_cams, S, rbuf,
+                                                       max_Np, dcam, max_Np);
     return hipGetLastError();
 }
 

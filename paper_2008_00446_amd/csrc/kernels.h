@@ -78,13 +78,15 @@ hipError_t launch_schur(const int64_t *n_blocks, int64_t n_blocks_cap, const Sch
 constexpr int kCholTileWaves = 1536;
 // per cluster T (T + 1) / 2 + 2 T flag words <= 3.5 x its wavefronts, plus the abort word
 inline int64_t chol_flag_words() { return 4 * (int64_t)kCholTileWaves + 1; }
-// per cluster 2 T 32 doubles, T <= its wavefronts
-inline int64_t chol_yx_doubles() { return 2 * (int64_t)kCholTileWaves * kNB; }
+// per cluster T 32 doubles (the forward solution y), T <= its wavefronts
+inline int64_t chol_yx_doubles() { return (int64_t)kCholTileWaves * kNB; }
 int chol_tile_layout(int32_t l, int32_t max_Np, int32_t *wpc, int32_t *tmax, int32_t *fpc);
+// S0 (nullable): the assembled S kept for one FP64 refinement step (MIXED),
+// with rbuf (l * max_Np doubles) for its residual.
 hipError_t launch_chol(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, const int64_t *S_off,
                        const int32_t *cl_start, const int32_t *cl_cams, double *S, const double *b,
                        double *dcam, int32_t *cl_status, int32_t max_Np, int32_t *flags, double *yx,
-                       hipStream_t st);
+                       const double *S0, double *rbuf, hipStream_t st);
 
 // MIXED precision: S0 = S before the factorisation, then one FP64 refinement
 // step of dcam against S0 with the factors.
@@ -92,7 +94,7 @@ hipError_t launch_copy_S(const double *S, double *S0, const int64_t *S_off, int3
                          hipStream_t st);
 hipError_t launch_refine(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, const int64_t *S_off,
                          const int32_t *cl_start, const int32_t *cl_cams, const double *S, const double *S0,
-                         const double *b, double *dcam, int32_t max_Np, hipStream_t st);
+                         const double *b, double *dcam, double *rbuf, int32_t max_Np, hipStream_t st);
 
 template <typename T>
 hipError_t launch_backsub(const stba_problem &p, const int64_t *pt_off, const T *Jc, const T *Jp,

@@ -17,7 +17,7 @@ struct Layout {
     size_t tmp_bytes;
     // per iteration
     size_t cl_n, cl_Np, cl_start, cl_cams, cam_local, cl_status, S_off;
-    size_t f, Jc, Jp, seg_head, seg_rec, obsd, Vinv, wph, S, S0, b, dcam, dpt, partials, chol_flags, chol_yx;
+    size_t f, Jc, Jp, seg_head, seg_rec, obsd, Vinv, wph, S, S0, rres, b, dcam, dpt, partials, chol_flags, chol_yx;
     int64_t S_cap, n_partials;
     int32_t max_Np;
     size_t total;
@@ -110,16 +110,17 @@ bool make_layout(const stba_problem *p, const stba_dims *d, int precision, Layou
     L.obsd = take(es * kObsRec * q);
     L.Vinv = take(8 * 6 * n);
     L.wph = take(8 * 3 * n);
+    L.max_Np = (int32_t)round_up(9 * (int64_t)d->gamma_max, kNB);
     L.S_cap = s_capacity(p->m, d->gamma_max);
     L.S = take(8 * (size_t)L.S_cap);
     // MIXED keeps the assembled S for the refinement step
     L.S0 = precision == STBA_MIXED ? take(8 * (size_t)L.S_cap) : 0;
+    L.rres = precision == STBA_MIXED ? take(8 * m * (size_t)L.max_Np) : 0;
     L.b = take(8 * 9 * m);
     L.dcam = take(8 * 9 * m);
     L.dpt = take(8 * 3 * n);
     L.n_partials = rj_blocks(p->q);
     L.partials = take(8 * (size_t)L.n_partials);
-    L.max_Np = (int32_t)round_up(9 * (int64_t)d->gamma_max, kNB);
     L.total = off;
     return true;
 }
@@ -197,11 +198,8 @@ int cluster_solve(int32_t l, double *dcam, int32_t *cl_status, const Layout &L, 
     STBA_HIP(launch_chol(l, at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np), at<int64_t>(ws, L.S_off),
                          at<int32_t>(ws, L.cl_start), at<int32_t>(ws, L.cl_cams), at<double>(ws, L.S),
                          at<double>(ws, L.b), dcam, cl_status, L.max_Np, at<int32_t>(ws, L.chol_flags),
-                         at<double>(ws, L.chol_yx), st));
-    if (mixed)
-        STBA_HIP(launch_refine(l, at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np), at<int64_t>(ws, L.S_off),
-                               at<int32_t>(ws, L.cl_start), at<int32_t>(ws, L.cl_cams), at<double>(ws, L.S),
-                               at<double>(ws, L.S0), at<double>(ws, L.b), dcam, L.max_Np, st));
+                         at<double>(ws, L.chol_yx), mixed ? at<double>(ws, L.S0) : nullptr,
+                         mixed ? at<double>(ws, L.rres) : nullptr, st));
     return STBA_OK;
 }
 
