@@ -173,13 +173,15 @@ __device__ __forceinline__ bool band_factor_invert(double *A, int64_t Np, int64_
                 bad = true;
                 dn = 1.0;
             }
-            is = rsqrt_refined(dn);
-            asm volatile("" : "+v"(is));   // computed here, not sunk to its use
-            __builtin_amdgcn_sched_barrier(0);
+            const double is_next = rsqrt_refined(dn);
 #pragma unroll
             for (int j = k + 1; j < kNB; ++j) v[j] = fma(-v[k], lc[j], v[j]);
 #pragma unroll
             for (int j = k + 1; j < kNB; ++j) asm volatile("" : "+v"(v[j]));
+            // computed within this step (its chain interleaved with the updates),
+            // not sunk to its use in the next one
+            is = is_next;
+            asm volatile("" : "+v"(is));
         }
         if (wl) {   // W[k][r] is final
             Wl[k][rq] = v[k];

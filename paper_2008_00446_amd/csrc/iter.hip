@@ -417,6 +417,162 @@ __global__ __launch_bounds__(256) void k_obs_rec(int64_t q, const int32_t *__res
     rec[31] = (T)((double)f[2 * a + 1] + jp[3] * u[0] + jp[4] * u[1] + jp[5] * u[2]);
 }
 
+// ---------------------------------------------------------------------------
+// The same work as k_points + k_obs_rec with one lane per observation: wavefront
+// g takes the points whose first observation lies in [G g, G (g + 1)), which
+// spans at most G - 1 + max_track <= 64 observations.  Each lane finds its chain
+// predecessor (the nearest earlier observation of its point in the same
+// cluster) by shuffles, draws its link, and the segment heads follow by pointer
+// jumping.  The point's and the segment's blocks are summed from LDS in
+// observation order (the order k_points uses), every lane factors its
+// segment's V*_s (3x3, in registers) and writes its own record.
+// ---------------------------------------------------------------------------
+constexpr int kPtWaves = 4;
+
+template <typename T>
+__global__ __launch_bounds__(64 * kPtWaves) void k_points_obs(
+    int64_t ngroups, const int32_t *__restrict__ grp_first, const int64_t *__restrict__ pt_off,
+    const int32_t *__restrict__ obs_pt, const int32_t *__restrict__ obs_cam, const int32_t *__restrict__ cam_cluster,
+    const T *__restrict__ f, const T *__restrict__ Jc, const T *__restrict__ Jp, const double *__restrict__ lam2,
+    uint64_t seed, uint64_t t, uint64_t thr, int32_t *__restrict__ seg_head, T *__restrict__ obsd,
+    double *__restrict__ Vinv, double *__restrict__ wph, int32_t *status) {
+    __shared__ double sV[kPtWaves][9][64];   // J_p^T J_p (6) and -J_p^T f (3) of each lane
+    __shared__ int32_t sHead[kPtWaves][64];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int64_t g = (int64_t)blockIdx.x * kPtWaves + wv;
+    if (g >= ngroups) return;
+    // every window of G observations inside [0, q) holds a point start (G > max_track);
+    // only the last window can be empty, and then the group before it runs to n
+    const int32_t pa = grp_first[g];
+    int32_t pb = grp_first[g + 1];
+    if (pb < 0) pb = grp_first[ngroups];
+    if (pa < 0 || pb < pa) return;
+    const int64_t o0 = pt_off[pa], o1 = pt_off[pb];
+    if (o1 - o0 > 64) {   // the plan does not fit this data (inconsistent max_track)
+        if (lane == 0) set_status(status + kStSticky, STBA_EDATA);
+        return;
+    }
+    const int cnt = (int)(o1 - o0);
+    const bool act = lane < cnt;
+    const int64_t a = o0 + (act ? lane : 0);
+    const double lam = lam2[0];
+    const bool corr = lam >= lam2[1];
+    const int32_t j = obs_pt[a];
+    const int32_t cam = obs_cam[a];
+    const int32_t cl = act ? cam_cluster[cam] : -1;
+    const int first = act ? (int)(pt_off[j] - o0) : lane;   // first lane of my point
+    const int last = act ? (int)(pt_off[j + 1] - o0) : lane + 1;
+    double jp[6];
+    load_jp(Jp, a, jp);
+    const double f0 = (double)f[2 * a], f1 = (double)f[2 * a + 1];
+    double c[9];
+    c[0] = jp[0] * jp[0] + jp[3] * jp[3];
+    c[1] = jp[0] * jp[1] + jp[3] * jp[4];
+    c[2] = jp[0] * jp[2] + jp[3] * jp[5];
+    c[3] = jp[1] * jp[1] + jp[4] * jp[4];
+    c[4] = jp[1] * jp[2] + jp[4] * jp[5];
+    c[5] = jp[2] * jp[2] + jp[5] * jp[5];
+    c[6] = -(jp[0] * f0 + jp[3] * f1);
+    c[7] = -(jp[1] * f0 + jp[4] * f1);
+    c[8] = -(jp[2] * f0 + jp[5] * f1);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) sV[wv][k][lane] = act ? c[k] : 0.0;
+    // chain predecessor: nearest earlier lane of the same point in the same cluster
+    int pred = -1;
+    for (int d = 1; d < 64; ++d) {
+        const int src = lane - d;
+        const int32_t cl_o = __shfl(cl, src < 0 ? 0 : src, 64);
+        if (pred < 0 && src >= first && cl_o == cl) pred = src;
+    }
+    int head = lane;
+    if (act && pred >= 0 && keep_link(seed, t, (uint64_t)j, (uint64_t)cam, thr)) head = pred;
+    // pointer jumping: chains are at most 64 long
+#pragma unroll
+    for (int it = 0; it < 6; ++it) head = __shfl(head, head, 64);
+    sHead[wv][lane] = head;
+    __syncwarp();
+    // point sums (V_j, w_j) and segment sums (V_s, w'_s) in observation order
+    double V[6] = {0, 0, 0, 0, 0, 0}, w[3] = {0, 0, 0}, Vs[6] = {0, 0, 0, 0, 0, 0}, ws[3] = {0, 0, 0};
+    for (int b = first; b < last; ++b) {
+        const bool mine = sHead[wv][b] == head;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const double x = sV[wv][k][b];
+            V[k] += x;
+            if (mine) Vs[k] += x;
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double x = sV[wv][6 + k][b];
+            w[k] += x;
+            if (mine) ws[k] += x;
+        }
+    }
+    if (!act) return;
+    bool ok = true;
+    if (lane == first) {
+        double Vd[6] = {V[0] * (1.0 + lam), V[1], V[2], V[3] * (1.0 + lam), V[4], V[5] * (1.0 + lam)};
+        const Chol3 cj = chol3(Vd);
+        ok &= cj.ok;
+        double Vi[6];
+        chol3_inverse(cj, Vi);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) Vinv[6 * (int64_t)j + k] = Vi[k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) wph[3 * (int64_t)j + k] = w[k];
+    }
+    if (corr) {
+        // g'_s = h_s (sum_s g_s) / (sum_s h_s), h_s = (1 + lambda) diag(V_s);
+        // sum_s g_s = w_j and sum_s diag(V_s) = diag(V_j)
+        ws[0] = Vs[0] * w[0] / V[0];
+        ws[1] = Vs[3] * w[1] / V[3];
+        ws[2] = Vs[5] * w[2] / V[5];
+    }
+    const double Vd[6] = {Vs[0] * (1.0 + lam), Vs[1], Vs[2], Vs[3] * (1.0 + lam), Vs[4], Vs[5] * (1.0 + lam)};
+    const Chol3 cs = chol3(Vd);
+    ok &= cs.ok;
+    double Vi[6], u[3];
+    chol3_inverse(cs, Vi);
+    sym3_mul(Vi, ws, u);   // V*_s^-1 w'_s
+    seg_head[a] = (int32_t)(o0 + head);
+    double jc[18];
+#pragma unroll
+    for (int k = 0; k < 18; ++k) jc[k] = (double)Jc[18 * a + k];
+    T *rec = obsd + (int64_t)kObsRec * a;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        const double W0 = jc[e] * jp[0] + jc[9 + e] * jp[3];
+        const double W1 = jc[e] * jp[1] + jc[9 + e] * jp[4];
+        const double W2 = jc[e] * jp[2] + jc[9 + e] * jp[5];
+        rec[3 * e + 0] = (T)(W0 * cs.I00);
+        rec[3 * e + 1] = (T)(W0 * cs.I01 + W1 * cs.I11);
+        rec[3 * e + 2] = (T)(W0 * cs.I02 + W1 * cs.I12 + W2 * cs.I22);
+    }
+    double G0[3], G1[3];
+    const double r0v[3] = {jp[0], jp[1], jp[2]}, r1v[3] = {jp[3], jp[4], jp[5]};
+    sym3_mul(Vi, r0v, G0);
+    sym3_mul(Vi, r1v, G1);
+    rec[27] = (T)(1.0 - (G0[0] * jp[0] + G0[1] * jp[1] + G0[2] * jp[2]));
+    rec[28] = (T)(-(G0[0] * jp[3] + G0[1] * jp[4] + G0[2] * jp[5]));
+    rec[29] = (T)(1.0 - (G1[0] * jp[3] + G1[1] * jp[4] + G1[2] * jp[5]));
+    rec[30] = (T)(f0 + jp[0] * u[0] + jp[1] * u[1] + jp[2] * u[2]);
+    rec[31] = (T)(f1 + jp[3] * u[0] + jp[4] * u[1] + jp[5] * u[2]);
+    if (!ok) set_status(status + kStPointBad, STBA_ENOTPD);
+}
+
+// first point of every group of k_points_obs: group g holds the points whose
+// first observation lies in [G g, G (g + 1))
+__global__ void k_point_groups(int32_t n, const int64_t *__restrict__ pt_off, int32_t G, int64_t ngroups,
+                               int32_t *__restrict__ grp_first) {
+    const int64_t jj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (jj < n) {
+        const int64_t gg = pt_off[jj] / G;
+        if (jj == 0 || pt_off[jj - 1] / G != gg) grp_first[gg] = (int32_t)jj;
+    }
+    if (jj == 0) grp_first[ngroups] = n;
+}
+
 // zero S (all clusters) and b; identity on the padded tail of each S_k
 __global__ __launch_bounds__(256) void k_zero_S(double *S, double *b, int32_t m, const int64_t *S_off, int32_t l,
                                                 int64_t S_cap) {
@@ -866,8 +1022,15 @@ template <typename T>
 hipError_t launch_points(const stba_problem &p, const int64_t *pt_off, const int32_t *cam_cluster, int32_t l,
                          const T *f, const T *Jc, const T *Jp, const double *lam2, uint64_t seed, uint64_t t,
                          uint64_t thr, int32_t *seg_head, double *seg_rec, T *obsd, double *Vinv, double *wph,
-                         int32_t *status, hipStream_t st) {
+                         int32_t *status, int32_t group_size, const int32_t *grp_first, hipStream_t st) {
     (void)l;
+    if (group_size > 0) {
+        const int64_t ng = (p.q + group_size - 1) / group_size;
+        k_points_obs<T><<<(unsigned)((ng + kPtWaves - 1) / kPtWaves), 64 * kPtWaves, 0, st>>>(
+            ng, grp_first, pt_off, p.obs_pt, p.obs_cam, cam_cluster, f, Jc, Jp, lam2, seed, t, thr, seg_head, obsd,
+            Vinv, wph, status);
+        return hipGetLastError();
+    }
     k_points<T><<<grid_for(p.n, 64), 64, 0, st>>>(p.n, pt_off, p.obs_cam, cam_cluster, f, Jp, lam2, seed, t, thr,
                                                   seg_head, seg_rec, Vinv, wph, status);
     k_obs_rec<T><<<grid_for(p.q), 256, 0, st>>>(p.q, seg_head, seg_rec, f, Jc, Jp, obsd);
@@ -876,11 +1039,23 @@ hipError_t launch_points(const stba_problem &p, const int64_t *pt_off, const int
 template hipError_t launch_points<double>(const stba_problem &, const int64_t *, const int32_t *, int32_t,
                                           const double *, const double *, const double *, const double *, uint64_t,
                                           uint64_t, uint64_t, int32_t *, double *, double *, double *, double *,
-                                          int32_t *, hipStream_t);
+                                          int32_t *, int32_t, const int32_t *, hipStream_t);
 template hipError_t launch_points<float>(const stba_problem &, const int64_t *, const int32_t *, int32_t,
                                          const float *, const float *, const float *, const double *, uint64_t,
                                          uint64_t, uint64_t, int32_t *, double *, float *, double *, double *,
-                                         int32_t *, hipStream_t);
+                                         int32_t *, int32_t, const int32_t *, hipStream_t);
+
+__global__ void k_fill_i32(int32_t *a, int64_t len, int32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = v;
+}
+
+hipError_t launch_point_groups(int32_t n, const int64_t *pt_off, int32_t group_size, int64_t ngroups,
+                               int32_t *grp_first, hipStream_t st) {
+    k_fill_i32<<<grid_for(ngroups + 1), 256, 0, st>>>(grp_first, ngroups + 1, -1);
+    k_point_groups<<<grid_for(n), 256, 0, st>>>(n, pt_off, group_size, ngroups, grp_first);
+    return hipGetLastError();
+}
 
 hipError_t launch_fill_S(double *S, double *b, int32_t m, const int64_t *S_off, int32_t l, int64_t S_cap,
                          const int32_t *cl_n, const int32_t *cl_Np, hipStream_t st) {

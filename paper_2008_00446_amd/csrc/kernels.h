@@ -48,11 +48,19 @@ hipError_t launch_sum_partials(const double *partials, int64_t count, double *ou
 hipError_t launch_init_cost(const double *partials, int64_t count, stba_lm_state *s, hipStream_t st);
 hipError_t launch_set_damping(double *slot, double lambda, double lambda_corr, hipStream_t st);
 
+// Segments, point blocks and per-observation records.  group_size > 0: one
+// lane per observation (groups from launch_point_groups, max_track <= 32);
+// otherwise one thread per point and one per observation (seg_rec staging).
 template <typename T>
 hipError_t launch_points(const stba_problem &p, const int64_t *pt_off, const int32_t *cam_cluster, int32_t l,
                          const T *f, const T *Jc, const T *Jp, const double *lam2, uint64_t seed, uint64_t t,
                          uint64_t thr, int32_t *seg_head, double *seg_rec, T *obsd, double *Vinv, double *wph,
-                         int32_t *status, hipStream_t st);
+                         int32_t *status, int32_t group_size, const int32_t *grp_first, hipStream_t st);
+// group g of the one-lane-per-observation path starts at grp_first[g]
+// (ngroups + 1 entries); group_size = 65 - max_track
+hipError_t launch_point_groups(int32_t n, const int64_t *pt_off, int32_t group_size, int64_t ngroups,
+                               int32_t *grp_first, hipStream_t st);
+inline int32_t point_group_size(int32_t max_track) { return max_track <= 32 ? 65 - max_track : 0; }
 
 hipError_t launch_fill_S(double *S, double *b, int32_t m, const int64_t *S_off, int32_t l, int64_t S_cap,
                          const int32_t *cl_n, const int32_t *cl_Np, hipStream_t st);

@@ -17,8 +17,9 @@ struct Layout {
     size_t tmp_bytes;
     // per iteration
     size_t cl_n, cl_Np, cl_start, cl_cams, cam_local, cl_status, S_off;
-    size_t f, Jc, Jp, seg_head, seg_rec, obsd, Vinv, wph, S, S0, rres, b, dcam, dpt, partials, chol_flags, chol_yx;
+    size_t f, Jc, Jp, seg_head, seg_rec, grp_first, obsd, Vinv, wph, S, S0, rres, b, dcam, dpt, partials, chol_flags, chol_yx;
     int64_t S_cap, n_partials;
+    int32_t group_size;
     int32_t max_Np;
     size_t total;
 };
@@ -35,6 +36,7 @@ int check_problem(const stba_problem *p) {
 int check_dims(const stba_problem *p, const stba_dims *d) {
     if (!d || d->n_pairs < p->n || d->n_pairs < p->q || d->gamma_max < 1 || d->gamma_max > p->m)
         return STBA_EINVAL;
+    if (d->max_track < 1 || d->max_track > p->q) return STBA_EINVAL;
     return STBA_OK;
 }
 
@@ -106,7 +108,10 @@ bool make_layout(const stba_problem *p, const stba_dims *d, int precision, Layou
     L.seg_head = take(4 * q);
     L.chol_flags = take(4 * (size_t)chol_flag_words());
     L.chol_yx = take(8 * (size_t)chol_yx_doubles());
-    L.seg_rec = take(8 * (size_t)kSegRec * q);
+    L.grp_first = take(4 * (q + 2));
+    L.group_size = point_group_size(d->max_track);
+    // the staged segment records are used only when the one-lane-per-observation path is off
+    L.seg_rec = take(L.group_size > 0 ? 8 : 8 * (size_t)kSegRec * q);
     L.obsd = take(es * kObsRec * q);
     L.Vinv = take(8 * 6 * n);
     L.wph = take(8 * 3 * n);
@@ -177,7 +182,8 @@ int build_rcs_impl(const stba_problem *p, const stba_dims *d, const stba_sample 
                              at<int32_t>(ws, L.cam_local), at<int64_t>(ws, L.S_off), status, st));
     STBA_HIP(launch_points<T>(*p, at<int64_t>(ws, L.pt_off), s->cam_cluster, s->l, f, Jc, Jp, lam2, s->seed, s->iter,
                               keep_threshold(s->alpha), at<int32_t>(ws, L.seg_head), at<double>(ws, L.seg_rec), at<T>(ws, L.obsd),
-                              at<double>(ws, L.Vinv), at<double>(ws, L.wph), status, st));
+                              at<double>(ws, L.Vinv), at<double>(ws, L.wph), status, L.group_size,
+                              at<int32_t>(ws, L.grp_first), st));
     STBA_HIP(launch_fill_S(at<double>(ws, L.S), at<double>(ws, L.b), p->m, at<int64_t>(ws, L.S_off), s->l, L.S_cap,
                            at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np), st));
     STBA_HIP(launch_schur<T>(at<int64_t>(ws, L.n_blocks), L.blk_cap, chunks_of(L, ws), at<int2>(ws, L.blk_key),
@@ -234,7 +240,8 @@ int lm_step_impl(const stba_problem *p, const stba_dims *d, const stba_sample *s
     STBA_TRY(mark(2));
     STBA_HIP(launch_points<T>(*p, at<int64_t>(ws, L.pt_off), s->cam_cluster, s->l, f, Jc, Jp, lam2, s->seed, s->iter,
                               keep_threshold(s->alpha), at<int32_t>(ws, L.seg_head), at<double>(ws, L.seg_rec), at<T>(ws, L.obsd),
-                              at<double>(ws, L.Vinv), at<double>(ws, L.wph), status, st));
+                              at<double>(ws, L.Vinv), at<double>(ws, L.wph), status, L.group_size,
+                              at<int32_t>(ws, L.grp_first), st));
     STBA_TRY(mark(3));
     STBA_HIP(launch_fill_S(at<double>(ws, L.S), at<double>(ws, L.b), p->m, at<int64_t>(ws, L.S_off), s->l, L.S_cap,
                            at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np), st));
@@ -324,6 +331,9 @@ int stba_prepare(const stba_problem *p, const stba_dims *dims, int precision, vo
     b.tmp_bytes = L.tmp_bytes;
     STBA_HIP(launch_reset_status(at<int32_t>(ws, L.status), stream));
     STBA_HIP(launch_prepare(*p, dims->n_pairs, b, at<int32_t>(ws, L.status), stream));
+    if (L.group_size > 0)
+        STBA_HIP(launch_point_groups(p->n, b.pt_off, L.group_size, (p->q + L.group_size - 1) / L.group_size,
+                                     at<int32_t>(ws, L.grp_first), stream));
     return STBA_OK;
 }
 

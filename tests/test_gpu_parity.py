@@ -292,3 +292,19 @@ def test_full_size_ring_iteration_matches_oracle():
     assert abs(st["F_new"] - ref.F_new) <= 1e-9 * ref.F_new
     assert rel(sol.cam.cpu().numpy() - s.cam0, ref.cam - s.cam0) < 1e-9
     assert rel(sol.pt.cpu().numpy() - s.pt0, ref.pt - s.pt0) < 1e-9
+
+
+def test_long_tracks_use_thread_per_point_path():
+    """Points seen by 40 cameras: the one-lane-per-observation kernel does not
+    apply (tracks above 32), the thread-per-point path runs instead."""
+    s = synth.small_ring(m=50, n=400, views=40, seed=3)
+    lab = _sgc(s, 20, 0)
+    g = GpuProblem(s, gamma_max=20)
+    assert g.dims.max_track > 32
+    f, Jc, Jp, _ = g.residual_jacobian()
+    rcs = g.build(f, Jc, Jp, lab, 0.2, 0.7, 4, 0)
+    dcam, dpt, cs = g.solve(rcs, Jc, Jp)
+    ref = O.stba_step(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv, lab, 0.2, 0.7, 4, 0)
+    assert np.all(cs == 0)
+    assert rel(dcam, ref.dcam) < 1e-9
+    assert rel(dpt, ref.dpt) < 1e-9
