@@ -15,6 +15,7 @@ inline unsigned grid_for(int64_t count, int bs = 256) { return (unsigned)((count
 // cluster layout: cameras grouped by cluster (ascending id inside a cluster),
 // per-cluster sizes, padded orders and offsets of S_k (Eq. 13).
 // One workgroup of up to 1024 threads; bitonic sort of (cluster, camera) keys in LDS.
+// As the first kernel of an iteration it also clears the status words.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_clusters(const int32_t *cam_cluster, int32_t m, int32_t l,
                                                    int32_t gamma_max, int32_t *cl_n, int32_t *cl_Np,
@@ -27,6 +28,7 @@ __global__ __launch_bounds__(1024) void k_clusters(const int32_t *cam_cluster, i
     const int nt = blockDim.x;
     int P = 1;
     while (P < m) P <<= 1;
+    if (tid < kStCount) status[tid] = 0;
     if (tid == 0) bad = 0;
     __syncthreads();
     for (int i = tid; i < P; i += nt) {
@@ -186,18 +188,6 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double *partials, in
     for (int64_t i = threadIdx.x; i < count; i += 256) s += partials[i];
     s = block_sum_256(s, sh);
     if (threadIdx.x == 0) out[0] = s;
-}
-
-__global__ __launch_bounds__(256) void k_init_cost(const double *partials, int64_t count, stba_lm_state *st) {
-    __shared__ double sh[256];
-    if (!(st->need_jac && !st->have_F)) return;
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < count; i += 256) s += partials[i];
-    s = block_sum_256(s, sh);
-    if (threadIdx.x == 0) {
-        st->F = s;
-        st->have_F = 1;
-    }
 }
 
 __global__ void k_set_damping(double *slot, double lambda, double lambda_corr) {
@@ -573,22 +563,26 @@ __global__ void k_point_groups(int32_t n, const int64_t *__restrict__ pt_off, in
     if (jj == 0) grp_first[ngroups] = n;
 }
 
-// zero S (all clusters) and b; identity on the padded tail of each S_k
+// zero S (all clusters) and b.  With st given, block 0 also sets F(x) from the
+// residual kernel's per-block partials on the first iteration of a linearisation
+// (the LM state keeps it otherwise).
 __global__ __launch_bounds__(256) void k_zero_S(double *S, double *b, int32_t m, const int64_t *S_off, int32_t l,
-                                                int64_t S_cap) {
+                                                int64_t S_cap, stba_lm_state *st, const double *partials,
+                                                int64_t count) {
+    __shared__ double sh[256];
     int64_t total = S_off[l];
     if (total > S_cap) total = S_cap;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) S[i] = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 9 * (int64_t)m; i += stride) b[i] = 0.0;
-}
-
-__global__ __launch_bounds__(64) void k_pad_S(double *S, const int64_t *S_off, const int32_t *cl_n,
-                                              const int32_t *cl_Np) {
-    const int k = blockIdx.x;
-    const int64_t Np = cl_Np[k];
-    double *A = S + S_off[k];
-    for (int64_t i = 9 * (int64_t)cl_n[k] + threadIdx.x; i < Np; i += 64) A[i + i * Np] = 1.0;
+    if (st == nullptr || blockIdx.x != 0 || !(st->need_jac && !st->have_F)) return;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < count; i += 256) s += partials[i];
+    s = block_sum_256(s, sh);
+    if (threadIdx.x == 0) {
+        st->F = s;
+        st->have_F = 1;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -745,11 +739,13 @@ __global__ __launch_bounds__(256) void k_schur(SchurChunks ch, const int2 *__res
 }
 
 // Blocks of several chunks: 81 threads per block add the partial sums in chunk
-// order and write the block (and b_r for a diagonal block).
+// order and write the block (and b_r for a diagonal block).  The same grid puts
+// ones on the diagonal of the padded tail of every S_k (rows 9 n_k .. Np - 1).
 __global__ __launch_bounds__(128) void k_schur_reduce(SchurChunks ch, const int64_t *__restrict__ n_blocks_p,
                                                       const int2 *__restrict__ blk_key,
                                                       const int32_t *__restrict__ cam_cluster, int32_t l,
                                                       const int32_t *__restrict__ cam_local,
+                                                      const int32_t *__restrict__ cl_n,
                                                       const int32_t *__restrict__ cl_Np,
                                                       const int64_t *__restrict__ S_off,
                                                       const double *__restrict__ lam2, double *__restrict__ S,
@@ -757,6 +753,11 @@ __global__ __launch_bounds__(128) void k_schur_reduce(SchurChunks ch, const int6
     const int64_t nb = n_blocks_p[0];
     const int t = threadIdx.x;
     const double lam = lam2[0];
+    for (int32_t k = blockIdx.x; k < l; k += gridDim.x) {
+        const int64_t Np = cl_Np[k];
+        double *A = S + S_off[k];
+        for (int64_t i = 9 * (int64_t)cl_n[k] + t; i < Np; i += blockDim.x) A[i + i * Np] = 1.0;
+    }
     for (int64_t bk = blockIdx.x; bk < nb; bk += gridDim.x) {
         const int64_t c0 = ch.blk_chunk_off[bk];
         const int64_t nch = ch.blk_chunk_off[bk + 1] - c0;
@@ -829,9 +830,12 @@ __global__ __launch_bounds__(256) void k_cost_at(int64_t q, const double *__rest
                                                  const double *__restrict__ pt, const int32_t *__restrict__ oc,
                                                  const int32_t *__restrict__ op, const double *__restrict__ uv,
                                                  const double *__restrict__ dcam, const double *__restrict__ dpt,
-                                                 double *__restrict__ partials) {
+                                                 double *__restrict__ partials, const stba_lm_state *st,
+                                                 double *__restrict__ F_ref) {
     __shared__ double sh[256];
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // F(x) as it stands before the decision, for every block of k_accept_update
+    if (F_ref != nullptr && o == 0) F_ref[0] = st->F;
     double sq = 0.0;
     if (o < q) {
         const int64_t i = oc[o], j = op[o];
@@ -850,9 +854,14 @@ __global__ __launch_bounds__(256) void k_cost_at(int64_t q, const double *__rest
 }
 
 // a7: accept iff F(x + dx) < F(x), the step is finite and every S_k factorised
-// (Alg. 1); lambda /= 3 on accept, *= 3 otherwise.
-__global__ __launch_bounds__(256) void k_accept(const double *partials, int64_t count, const int32_t *cl_status,
-                                                int32_t l, const int32_t *status, stba_lm_state *st) {
+// (Alg. 1); lambda /= 3 on accept, *= 3 otherwise; x += dx on accept.  Every
+// block sums the candidate partials in the same fixed order and compares with
+// F_ref (F(x) copied by k_cost_at), so all blocks take the same decision while
+// block 0 rewrites the LM state.
+__global__ __launch_bounds__(256) void k_accept_update(const double *partials, int64_t count, const double *F_ref,
+                                                       const int32_t *cl_status, int32_t l, const int32_t *status,
+                                                       stba_lm_state *st, int32_t m, int32_t n, double *cam,
+                                                       double *pt, const double *dcam, const double *dpt) {
     __shared__ double sh[256];
     __shared__ int bad_pd;
     if (threadIdx.x == 0) bad_pd = 0;
@@ -861,13 +870,14 @@ __global__ __launch_bounds__(256) void k_accept(const double *partials, int64_t 
     for (int64_t i = threadIdx.x; i < count; i += 256) s += partials[i];
     for (int k = threadIdx.x; k < l; k += 256)
         if (cl_status[k] != STBA_OK) bad_pd = 1;
-    s = block_sum_256(s, sh);
-    if (threadIdx.x == 0) {
-        const double Fn = s;
-        const bool pd = !bad_pd && status[kStPointBad] == 0;
-        const bool fin = isfinite(Fn);
-        const bool valid = pd && fin && status[kStSticky] == 0;
-        const bool acc = valid && (Fn < st->F);
+    s = block_sum_256(s, sh);   // its barriers also publish bad_pd
+    const double Fn = s;
+    const int32_t sticky = status[kStSticky];
+    const bool pd = !bad_pd && status[kStPointBad] == 0;
+    const bool fin = isfinite(Fn);
+    const bool valid = pd && fin && sticky == 0;
+    const bool acc = valid && (Fn < F_ref[0]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->F_new = Fn;
         st->accepted = acc ? 1 : 0;
         st->lambda = acc ? st->lambda / 3.0 : st->lambda * 3.0;
@@ -876,17 +886,16 @@ __global__ __launch_bounds__(256) void k_accept(const double *partials, int64_t 
         st->n_rcs += 1;
         st->n_accept += acc ? 1 : 0;
         st->n_jac += status[kStJacRan] ? 1 : 0;
-        st->last_status = !pd ? STBA_ENOTPD : (!fin ? STBA_ENONFINITE : status[kStSticky]);
-        if (st->status == 0 && status[kStSticky] != 0) st->status = status[kStSticky];
+        st->last_status = !pd ? STBA_ENOTPD : (!fin ? STBA_ENONFINITE : sticky);
+        if (st->status == 0 && sticky != 0) st->status = sticky;
     }
-}
-
-__global__ __launch_bounds__(256) void k_update(int32_t m, int32_t n, const stba_lm_state *st, double *cam,
-                                                double *pt, const double *dcam, const double *dpt) {
-    if (!st->accepted) return;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < 9 * (int64_t)m) cam[i] += dcam[i];
-    else if (i < 9 * (int64_t)m + 3 * (int64_t)n) pt[i - 9 * (int64_t)m] += dpt[i - 9 * (int64_t)m];
+    if (!acc) return;
+    const int64_t nc = 9 * (int64_t)m, total = nc + 3 * (int64_t)n;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        if (i < nc) cam[i] += dcam[i];
+        else pt[i - nc] += dpt[i - nc];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1008,11 +1017,6 @@ hipError_t launch_sum_partials(const double *partials, int64_t count, double *ou
     return hipGetLastError();
 }
 
-hipError_t launch_init_cost(const double *partials, int64_t count, stba_lm_state *s, hipStream_t st) {
-    k_init_cost<<<1, 256, 0, st>>>(partials, count, s);
-    return hipGetLastError();
-}
-
 hipError_t launch_set_damping(double *slot, double lambda, double lambda_corr, hipStream_t st) {
     k_set_damping<<<1, 1, 0, st>>>(slot, lambda, lambda_corr);
     return hipGetLastError();
@@ -1058,19 +1062,18 @@ hipError_t launch_point_groups(int32_t n, const int64_t *pt_off, int32_t group_s
 }
 
 hipError_t launch_fill_S(double *S, double *b, int32_t m, const int64_t *S_off, int32_t l, int64_t S_cap,
-                         const int32_t *cl_n, const int32_t *cl_Np, hipStream_t st) {
+                         stba_lm_state *s, const double *partials, int64_t count, hipStream_t st) {
     int64_t blocks = (S_cap + 1023) / 1024;
     if (blocks > 8192) blocks = 8192;
     if (blocks < 1) blocks = 1;
-    k_zero_S<<<(unsigned)blocks, 256, 0, st>>>(S, b, m, S_off, l, S_cap);
-    k_pad_S<<<(unsigned)l, 64, 0, st>>>(S, S_off, cl_n, cl_Np);
+    k_zero_S<<<(unsigned)blocks, 256, 0, st>>>(S, b, m, S_off, l, S_cap, s, partials, count);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_schur(const int64_t *n_blocks, int64_t n_blocks_cap, const SchurChunks &ch, const int2 *blk_key,
                         const int64_t *blk_start, const uint64_t *pairs, const int32_t *cam_cluster, int32_t l,
-                        const int32_t *cam_local, const int32_t *cl_Np, const int64_t *S_off,
+                        const int32_t *cam_local, const int32_t *cl_n, const int32_t *cl_Np, const int64_t *S_off,
                         const int32_t *seg_head, const T *Jc, const T *obsd, const double *lam2, double *S,
                         double *b, hipStream_t st) {
     int64_t wgs = (ch.chunk_cap + 3) / 4;
@@ -1081,17 +1084,17 @@ hipError_t launch_schur(const int64_t *n_blocks, int64_t n_blocks_cap, const Sch
     int64_t rb = n_blocks_cap;
     if (rb > 8192) rb = 8192;
     if (rb < 1) rb = 1;
-    k_schur_reduce<<<(unsigned)rb, 128, 0, st>>>(ch, n_blocks, blk_key, cam_cluster, l, cam_local, cl_Np, S_off, lam2,
-                                                 S, b);
+    k_schur_reduce<<<(unsigned)rb, 128, 0, st>>>(ch, n_blocks, blk_key, cam_cluster, l, cam_local, cl_n, cl_Np, S_off,
+                                                 lam2, S, b);
     return hipGetLastError();
 }
 template hipError_t launch_schur<double>(const int64_t *, int64_t, const SchurChunks &, const int2 *, const int64_t *,
-                                         const uint64_t *, const int32_t *, int32_t, const int32_t *,
+                                         const uint64_t *, const int32_t *, int32_t, const int32_t *, const int32_t *,
                                          const int32_t *, const int64_t *, const int32_t *, const double *,
                                          const double *, const double *, double *, double *, hipStream_t);
 template hipError_t launch_schur<float>(const int64_t *, int64_t, const SchurChunks &, const int2 *, const int64_t *,
                                         const uint64_t *, const int32_t *, int32_t, const int32_t *, const int32_t *,
-                                        const int64_t *, const int32_t *, const float *, const float *,
+                                        const int32_t *, const int64_t *, const int32_t *, const float *, const float *,
                                         const double *, double *, double *, hipStream_t);
 
 template <typename T>
@@ -1106,20 +1109,21 @@ template hipError_t launch_backsub<float>(const stba_problem &, const int64_t *,
                                           const double *, const double *, const double *, double *, hipStream_t);
 
 hipError_t launch_cost_at(const stba_problem &p, const double *dcam, const double *dpt, double *partials,
-                          hipStream_t st) {
-    k_cost_at<<<grid_for(p.q), 256, 0, st>>>(p.q, p.cam, p.pt, p.obs_cam, p.obs_pt, p.obs_uv, dcam, dpt, partials);
+                          const stba_lm_state *s, double *F_ref, hipStream_t st) {
+    k_cost_at<<<grid_for(p.q), 256, 0, st>>>(p.q, p.cam, p.pt, p.obs_cam, p.obs_pt, p.obs_uv, dcam, dpt, partials, s,
+                                             F_ref);
     return hipGetLastError();
 }
 
-hipError_t launch_accept(const double *partials, int64_t count, const int32_t *cl_status, int32_t l,
-                         const int32_t *status, stba_lm_state *s, hipStream_t st) {
-    k_accept<<<1, 256, 0, st>>>(partials, count, cl_status, l, status, s);
-    return hipGetLastError();
-}
-
-hipError_t launch_update(const stba_problem &p, const stba_lm_state *s, const double *dcam, const double *dpt,
-                         hipStream_t st) {
-    k_update<<<grid_for(9 * (int64_t)p.m + 3 * (int64_t)p.n), 256, 0, st>>>(p.m, p.n, s, p.cam, p.pt, dcam, dpt);
+hipError_t launch_accept_update(const stba_problem &p, const double *partials, int64_t count, const double *F_ref,
+                                const int32_t *cl_status, int32_t l, const int32_t *status, stba_lm_state *s,
+                                const double *dcam, const double *dpt, hipStream_t st) {
+    // few blocks: each one re-sums the candidate partials before its share of x += dx
+    unsigned blocks = grid_for(9 * (int64_t)p.m + 3 * (int64_t)p.n);
+    if (blocks > 128) blocks = 128;
+    if (blocks < 1) blocks = 1;
+    k_accept_update<<<blocks, 256, 0, st>>>(partials, count, F_ref, cl_status, l, status, s, p.m, p.n, p.cam, p.pt,
+                                            dcam, dpt);
     return hipGetLastError();
 }
 

@@ -35,6 +35,7 @@ hipError_t launch_prepare(const stba_problem &p, int64_t n_pairs, const PrepBufs
 // --- per iteration ----------------------------------------------------------
 hipError_t launch_reset_status(int32_t *status, hipStream_t st);
 hipError_t launch_lm_init(stba_lm_state *s, double lambda0, double lambda_corr, hipStream_t st);
+// also clears the status words
 hipError_t launch_clusters(const int32_t *cam_cluster, int32_t m, int32_t l, int32_t gamma_max,
                            int32_t *cl_n, int32_t *cl_Np, int32_t *cl_start, int32_t *cl_cams,
                            int32_t *cam_local, int64_t *S_off, int32_t *status, hipStream_t st);
@@ -45,7 +46,6 @@ hipError_t launch_rj(const stba_problem &p, T *f, T *Jc, T *Jp, double *partials
 int64_t rj_blocks(int64_t q);
 
 hipError_t launch_sum_partials(const double *partials, int64_t count, double *out, hipStream_t st);
-hipError_t launch_init_cost(const double *partials, int64_t count, stba_lm_state *s, hipStream_t st);
 hipError_t launch_set_damping(double *slot, double lambda, double lambda_corr, hipStream_t st);
 
 // Segments, point blocks and per-observation records.  group_size > 0: one
@@ -62,8 +62,9 @@ hipError_t launch_point_groups(int32_t n, const int64_t *pt_off, int32_t group_s
                                int32_t *grp_first, hipStream_t st);
 inline int32_t point_group_size(int32_t max_track) { return max_track <= 32 ? 65 - max_track : 0; }
 
+// zero S and b; s (nullable): set F(x) from the residual partials if the state asks for it
 hipError_t launch_fill_S(double *S, double *b, int32_t m, const int64_t *S_off, int32_t l, int64_t S_cap,
-                         const int32_t *cl_n, const int32_t *cl_Np, hipStream_t st);
+                         stba_lm_state *s, const double *partials, int64_t count, hipStream_t st);
 
 struct SchurChunks {
     const int64_t *n_chunks;
@@ -75,7 +76,7 @@ struct SchurChunks {
 template <typename T>
 hipError_t launch_schur(const int64_t *n_blocks, int64_t n_blocks_cap, const SchurChunks &ch, const int2 *blk_key,
                         const int64_t *blk_start, const uint64_t *pairs, const int32_t *cam_cluster, int32_t l,
-                        const int32_t *cam_local, const int32_t *cl_Np, const int64_t *S_off,
+                        const int32_t *cam_local, const int32_t *cl_n, const int32_t *cl_Np, const int64_t *S_off,
                         const int32_t *seg_head, const T *Jc, const T *obsd, const double *lam2, double *S,
                         double *b, hipStream_t st);
 
@@ -108,14 +109,13 @@ template <typename T>
 hipError_t launch_backsub(const stba_problem &p, const int64_t *pt_off, const T *Jc, const T *Jp,
                           const double *Vinv, const double *wph, const double *dcam, double *dpt, hipStream_t st);
 
+// F_ref (nullable): receives s->F for launch_accept_update
 hipError_t launch_cost_at(const stba_problem &p, const double *dcam, const double *dpt, double *partials,
-                          hipStream_t st);
+                          const stba_lm_state *s, double *F_ref, hipStream_t st);
 
-hipError_t launch_accept(const double *partials, int64_t count, const int32_t *cl_status, int32_t l,
-                         const int32_t *status, stba_lm_state *s, hipStream_t st);
-
-hipError_t launch_update(const stba_problem &p, const stba_lm_state *s, const double *dcam, const double *dpt,
-                         hipStream_t st);
+hipError_t launch_accept_update(const stba_problem &p, const double *partials, int64_t count, const double *F_ref,
+                                const int32_t *cl_status, int32_t l, const int32_t *status, stba_lm_state *s,
+                                const double *dcam, const double *dpt, hipStream_t st);
 
 template <typename T>
 hipError_t launch_vjp(const stba_problem &p, const int64_t *pt_off, const int64_t *diag_blk,

@@ -125,7 +125,7 @@ bool make_layout(const stba_problem *p, const stba_dims *d, int precision, Layou
     L.dcam = take(8 * 9 * m);
     L.dpt = take(8 * 3 * n);
     L.n_partials = rj_blocks(p->q);
-    L.partials = take(8 * (size_t)L.n_partials);
+    L.partials = take(8 * (size_t)L.n_partials + 8);   // + F(x) before the accept decision
     L.total = off;
     return true;
 }
@@ -185,10 +185,11 @@ int build_rcs_impl(const stba_problem *p, const stba_dims *d, const stba_sample 
                               at<double>(ws, L.Vinv), at<double>(ws, L.wph), status, L.group_size,
                               at<int32_t>(ws, L.grp_first), st));
     STBA_HIP(launch_fill_S(at<double>(ws, L.S), at<double>(ws, L.b), p->m, at<int64_t>(ws, L.S_off), s->l, L.S_cap,
-                           at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np), st));
+                           nullptr, nullptr, 0, st));
     STBA_HIP(launch_schur<T>(at<int64_t>(ws, L.n_blocks), L.blk_cap, chunks_of(L, ws), at<int2>(ws, L.blk_key),
                              at<int64_t>(ws, L.blk_start), at<uint64_t>(ws, L.pairs), s->cam_cluster, s->l,
-                             at<int32_t>(ws, L.cam_local), at<int32_t>(ws, L.cl_Np), at<int64_t>(ws, L.S_off),
+                             at<int32_t>(ws, L.cam_local), at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np),
+                             at<int64_t>(ws, L.S_off),
                              at<int32_t>(ws, L.seg_head), Jc, at<T>(ws, L.obsd), lam2, at<double>(ws, L.S),
                              at<double>(ws, L.b), st));
     return STBA_OK;
@@ -230,25 +231,25 @@ int lm_step_impl(const stba_problem *p, const stba_dims *d, const stba_sample *s
         return STBA_OK;
     };
     STBA_TRY(mark(0));
-    STBA_HIP(launch_reset_status(status, st));
     STBA_HIP(launch_clusters(s->cam_cluster, p->m, s->l, d->gamma_max, at<int32_t>(ws, L.cl_n),
                              at<int32_t>(ws, L.cl_Np), at<int32_t>(ws, L.cl_start), at<int32_t>(ws, L.cl_cams),
                              at<int32_t>(ws, L.cam_local), at<int64_t>(ws, L.S_off), status, st));
     STBA_TRY(mark(1));
     STBA_HIP(launch_rj<T>(*p, f, Jc, Jp, at<double>(ws, L.partials), &stt->need_jac, status + kStJacRan, st));
-    STBA_HIP(launch_init_cost(at<double>(ws, L.partials), L.n_partials, stt, st));
     STBA_TRY(mark(2));
     STBA_HIP(launch_points<T>(*p, at<int64_t>(ws, L.pt_off), s->cam_cluster, s->l, f, Jc, Jp, lam2, s->seed, s->iter,
                               keep_threshold(s->alpha), at<int32_t>(ws, L.seg_head), at<double>(ws, L.seg_rec), at<T>(ws, L.obsd),
                               at<double>(ws, L.Vinv), at<double>(ws, L.wph), status, L.group_size,
                               at<int32_t>(ws, L.grp_first), st));
     STBA_TRY(mark(3));
+    // also F(x) from the residual kernel's partials when the state has none yet
     STBA_HIP(launch_fill_S(at<double>(ws, L.S), at<double>(ws, L.b), p->m, at<int64_t>(ws, L.S_off), s->l, L.S_cap,
-                           at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np), st));
+                           stt, at<double>(ws, L.partials), L.n_partials, st));
     STBA_TRY(mark(4));
     STBA_HIP(launch_schur<T>(at<int64_t>(ws, L.n_blocks), L.blk_cap, chunks_of(L, ws), at<int2>(ws, L.blk_key),
                              at<int64_t>(ws, L.blk_start), at<uint64_t>(ws, L.pairs), s->cam_cluster, s->l,
-                             at<int32_t>(ws, L.cam_local), at<int32_t>(ws, L.cl_Np), at<int64_t>(ws, L.S_off),
+                             at<int32_t>(ws, L.cam_local), at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np),
+                             at<int64_t>(ws, L.S_off),
                              at<int32_t>(ws, L.seg_head), Jc, at<T>(ws, L.obsd), lam2, at<double>(ws, L.S),
                              at<double>(ws, L.b), st));
     STBA_TRY(mark(5));
@@ -258,11 +259,11 @@ int lm_step_impl(const stba_problem *p, const stba_dims *d, const stba_sample *s
     STBA_HIP(launch_backsub<T>(*p, at<int64_t>(ws, L.pt_off), Jc, Jp, at<double>(ws, L.Vinv), at<double>(ws, L.wph),
                                dcam, dpt, st));
     STBA_TRY(mark(7));
-    STBA_HIP(launch_cost_at(*p, dcam, dpt, at<double>(ws, L.partials), st));
+    double *F_ref = at<double>(ws, L.partials) + L.n_partials;
+    STBA_HIP(launch_cost_at(*p, dcam, dpt, at<double>(ws, L.partials), stt, F_ref, st));
     STBA_TRY(mark(8));
-    STBA_HIP(launch_accept(at<double>(ws, L.partials), L.n_partials, at<int32_t>(ws, L.cl_status), s->l, status, stt,
-                           st));
-    STBA_HIP(launch_update(*p, stt, dcam, dpt, st));
+    STBA_HIP(launch_accept_update(*p, at<double>(ws, L.partials), L.n_partials, F_ref, at<int32_t>(ws, L.cl_status),
+                                  s->l, status, stt, dcam, dpt, st));
     STBA_TRY(mark(9));
     return STBA_OK;
 }
@@ -360,7 +361,6 @@ int stba_build_cluster_rcs(const stba_problem *p, const stba_dims *dims, const s
     if (!d || !(d->lambda > 0.0) || !(d->lambda_corr >= 0.0) || !f || !Jc || !Jp || !out) return STBA_EINVAL;
     double *lam2 = at<double>(ws, L.lam2);
     STBA_HIP(launch_set_damping(lam2, d->lambda, d->lambda_corr, stream));
-    STBA_HIP(launch_reset_status(at<int32_t>(ws, L.status), stream));
     if (precision == STBA_FP64)
         STBA_TRY(build_rcs_impl<double>(p, dims, s, lam2, (const double *)f, (const double *)Jc, (const double *)Jp, L,
                                         ws, stream));
