@@ -605,6 +605,9 @@ __device__ inline void schur_butterfly(T (&acc)[5][9], T (&du)[5], T (&rb)[5], b
     for (int d = 2; d < 64; d <<= 1) {
 #pragma unroll
         for (int i = 0; i < 5; ++i) {
+            // one row in flight at a time: the exchanged copies would otherwise
+            // double the accumulator registers
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int k = 0; k < 9; ++k) acc[i][k] += __shfl_xor(acc[i][k], d, 64);
         }
@@ -618,8 +621,41 @@ __device__ inline void schur_butterfly(T (&acc)[5][9], T (&du)[5], T (&rb)[5], b
     }
 }
 
+// Staging of one wavefront's work in LDS.  A batch is 32 pairs: 64 records
+// (off-diagonal) or 32 sets of J_c and record elements 26..31 (diagonal), moved
+// from memory straight into LDS by load-to-LDS instructions (no registers hold
+// them in flight), whole cache lines per instruction.
+template <typename T> struct SchurShape {
+    static constexpr int kPart = 16 / (int)sizeof(T);      // elements per 16-byte part
+    static constexpr int kLanesRec = kObsRec / kPart;        // lanes per record (16 | 8)
+    static constexpr int kRecStep = 64 / kLanesRec;          // records per load instruction
+    static constexpr int kLoads = 64 / kRecStep;             // loads per lane for 64 records
+    static constexpr int kStage = 256;                       // pairs compacted at a time
+    // Off-diagonal batches go from memory to LDS without passing through
+    // registers.  Load instruction i fills its own block of 64 x 16 bytes (lane j
+    // writes bytes [16 j, 16 j + 16)) with part j / kRecStep of record kRecStep i
+    // + j % kRecStep; blocks are kBlk bytes apart.  So record R starts at
+    // row_at(R), its parts kRecStep * 16 bytes apart, and the slack of kBlk over
+    // 1 KB puts the 32 records that the slots read together on 16 bank groups.
+    static constexpr int kBlk = 1024 + (sizeof(T) == 8 ? 64 : 128);
+    static constexpr int kDmaBytes = kLoads * kBlk;
+    __device__ static int row_at(int R) { return (R / kRecStep) * kBlk + (R % kRecStep) * 16; }
+    __device__ static constexpr int elem_at(int k) { return (k / kPart) * kRecStep * 16 + (k % kPart) * (int)sizeof(T); }
+    // Diagonal batches: 24 elements per pair in units of kDU bytes, kDStep pairs
+    // per load instruction, blocks kDBlk bytes apart (32 pairs on 16 or 32 bank groups).
+    static constexpr int kDU = sizeof(T) == 8 ? 16 : 4;
+    static constexpr int kDUE = kDU / (int)sizeof(T);        // elements per unit
+    static constexpr int kDUnits = 24 / kDUE;                // units per pair (12 | 24)
+    static constexpr int kDStep = kDUnits > 16 ? 2 : 4;      // pairs per load instruction
+    static constexpr int kDLoads = 32 / kDStep;              // load instructions per batch
+    static constexpr int kDBlk = 64 * kDU + (sizeof(T) == 8 ? 64 : 8);
+    static constexpr int kDBytes = kDLoads * kDBlk;
+    __device__ static int drow_at(int q) { return (q / kDStep) * kDBlk + (q % kDStep) * kDU; }
+    __device__ static constexpr int delem_at(int k) { return (k / kDUE) * kDStep * kDU + (k % kDUE) * (int)sizeof(T); }
+};
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_schur(SchurChunks ch, const int2 *__restrict__ blk_key,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_schur(SchurChunks ch, const int2 *__restrict__ blk_key,
                                                const int64_t *__restrict__ blk_start,
                                                const uint64_t *__restrict__ pairs,
                                                const int32_t *__restrict__ cam_cluster, int32_t l,
@@ -628,10 +664,13 @@ __global__ __launch_bounds__(256) void k_schur(SchurChunks ch, const int2 *__res
                                                const int32_t *__restrict__ seg_head, const T *__restrict__ Jc,
                                                const T *__restrict__ obsd, const double *__restrict__ lam2,
                                                double *__restrict__ S, double *__restrict__ b) {
-    const int lane = threadIdx.x & 63;
+    using Sh = SchurShape<T>;
+    constexpr int kBuf = Sh::kDmaBytes > Sh::kDBytes ? Sh::kDmaBytes : Sh::kDBytes;
+    __shared__ int2 s_pairs[4][Sh::kStage];
+    __shared__ __align__(16) char s_rec[4][kBuf];
     const int wv = threadIdx.x >> 6;
-    const int slot = lane >> 1;
-    const int e0 = 5 * (lane & 1);   // rows e0..e0+4; row 9 of the upper half is computed and dropped
+    int2 *sp = s_pairs[wv];
+    char *sb = s_rec[wv];
     const int64_t nc = ch.n_chunks[0];
     const double lam = lam2[0];
     const int64_t wstride = (int64_t)gridDim.x * 4;
@@ -646,7 +685,18 @@ __global__ __launch_bounds__(256) void k_schur(SchurChunks ch, const int2 *__res
         const int64_t c0 = ch.blk_chunk_off[bk];
         const int64_t nch = ch.blk_chunk_off[bk + 1] - c0;
         const int64_t s0 = blk_start[bk] + (item - c0) * kSchurChunk;
-        const int64_t s1 = min(s0 + (int64_t)kSchurChunk, blk_start[bk + 1]);
+        const int32_t len = (int32_t)min((int64_t)kSchurChunk, blk_start[bk + 1] - s0);   // >= 1
+        const bool diag = r == c;
+        // an opaque copy of the lane index per item: the lane-dependent addresses of
+        // the two paths below are derived inside them instead of being hoisted out
+        // of the item loop, where both sets would hold registers at once
+        int lane = threadIdx.x & 63;
+        asm volatile("" : "+v"(lane));
+        const int slot = lane >> 1;
+        // rows e0..e0 + 4: 0..4 and 4..8 (row 4 of the upper half is dropped), so
+        // both halves start on a whole 16-byte part of a record
+        const int e0 = 4 * (lane & 1);
+        const int i0 = lane & 1;   // first row a half writes
         T acc[5][9], du[5], rb[5];
 #pragma unroll
         for (int i = 0; i < 5; ++i) {
@@ -654,46 +704,138 @@ __global__ __launch_bounds__(256) void k_schur(SchurChunks ch, const int2 *__res
 #pragma unroll
             for (int k = 0; k < 9; ++k) acc[i][k] = (T)0;
         }
-        const bool diag = r == c;
-        if (diag) {
-            // pairs of a diagonal block are (a, a): J_c^T M J_c, diag(J_c^T J_c), J_c^T r
-            for (int64_t p = s0 + slot; p < s1; p += 32) {
-                const int64_t a = (int64_t)(pairs[p] >> 32);
-                const T *jc = Jc + 18 * a;
-                const T *od = obsd + (int64_t)kObsRec * a;
-                T t0[9], t1[9];
-                const T m00 = od[27], m01 = od[28], m11 = od[29], r0 = od[30], r1 = od[31];
+        for (int h0 = 0; h0 < len; h0 += Sh::kStage) {
+            // the pairs of one segment among the next kStage, in pair order,
+            // compacted into LDS (the others fill the tail in reverse); all pair
+            // entries, then all segment heads, are requested before any is used
+            const int hl = min(Sh::kStage, len - h0);
+            constexpr int kRounds = Sh::kStage / 64;
+            uint64_t pr[kRounds];
 #pragma unroll
-                for (int k = 0; k < 9; ++k) {
-                    const T j0 = jc[k], j1 = jc[9 + k];
-                    t0[k] = m00 * j0 + m01 * j1;
-                    t1[k] = m01 * j0 + m11 * j1;
-                }
+            for (int i = 0; i < kRounds; ++i) pr[i] = pairs[s0 + h0 + min(i * 64 + lane, hl - 1)];
+            int32_t hu[kRounds], hw[kRounds];
 #pragma unroll
-                for (int i = 0; i < 5; ++i) {
-                    const int e = min(e0 + i, 8);
-                    const T je0 = jc[e], je1 = jc[9 + e];
+            for (int i = 0; i < kRounds; ++i) hu[i] = hw[i] = 0;
+            if (!diag) {
 #pragma unroll
-                    for (int k = 0; k < 9; ++k) acc[i][k] += je0 * t0[k] + je1 * t1[k];
-                    du[i] += je0 * je0 + je1 * je1;
-                    rb[i] += je0 * r0 + je1 * r1;
+                for (int i = 0; i < kRounds; ++i) {
+                    hu[i] = seg_head[(int64_t)(pr[i] >> 32)];
+                    hw[i] = seg_head[(int64_t)(pr[i] & 0xFFFFFFFFull)];
                 }
             }
-        } else {
-            for (int64_t p = s0 + slot; p < s1; p += 32) {
-                const uint64_t pr = pairs[p];
-                const int64_t u = (int64_t)(pr >> 32), w = (int64_t)(pr & 0xFFFFFFFFull);
-                if (seg_head[u] != seg_head[w]) continue;
-                const T *yw = obsd + (int64_t)kObsRec * w;
-                const T *yu = obsd + (int64_t)kObsRec * u + 3 * e0;   // rows e0.. (row 9: still inside the record)
-                T y[27];
+            __builtin_amdgcn_wave_barrier();   // earlier reads of sp are done
+            int32_t npv = 0, nskip = 0;
 #pragma unroll
-                for (int k = 0; k < 27; ++k) y[k] = yw[k];
+            for (int i = 0; i < kRounds; ++i) {
+                const bool ok = i * 64 + lane < hl && hu[i] == hw[i];
+                const uint64_t mask = __ballot(ok);
+                const uint64_t mk = ok ? mask : ~mask;
+                const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
+                const int pos = ok ? npv + rank : Sh::kStage - 1 - (nskip + rank);
+                sp[pos] = make_int2((int32_t)(pr[i] >> 32), (int32_t)(pr[i] & 0xFFFFFFFFull));
+                npv += __popcll(mask);
+                nskip += 64 - __popcll(mask);
+            }
+            __builtin_amdgcn_wave_barrier();
+            const int nbat = (npv + 31) >> 5;
+            int pl = lane;   // again opaque: nothing of a path is hoisted out of the stage loop
+            asm volatile("" : "+v"(pl));
+            if (diag) {
+                // pairs (a, a): J_c^T M J_c, diag(J_c^T J_c), J_c^T r from J_c (18
+                // elements) and record elements 26..31, straight from memory to LDS
+                // in units of kDU bytes (J_c rows of FP32 are only 8-byte aligned).
+                // Unit p of pair kDStep i + dq comes from lane kDStep p + dq of load
+                // instruction i; units past kDUnits repeat the last one into the pad.
+                const int dq = pl % Sh::kDStep, dp = min(pl / Sh::kDStep, Sh::kDUnits - 1);
+                const int el = dp * Sh::kDUE;
+                const bool from_jc = el < 18;
+                const T *src_base = (from_jc ? Jc : obsd) + (from_jc ? el : 8 + el);
+                const int64_t src_stride = from_jc ? 18 : kObsRec;
+                auto fetch = [&](int bt) {
 #pragma unroll
-                for (int i = 0; i < 5; ++i) {
-                    const T a0 = yu[3 * i], a1 = yu[3 * i + 1], a2 = yu[3 * i + 2];
+                    for (int i = 0; i < Sh::kDLoads; ++i) {
+                        const int64_t a = sp[min(bt * 32 + i * Sh::kDStep + dq, npv - 1)].x;
+                        const void *g = (const void *)(src_base + a * src_stride);
+                        auto *l = (void __attribute__((address_space(3))) *)(sb + i * Sh::kDBlk);
+                        // the unit size has to be a literal for the builtin
+                        if constexpr (Sh::kDU == 16) __builtin_amdgcn_global_load_lds(g, l, 16, 0, 0);
+                        else __builtin_amdgcn_global_load_lds(g, l, 4, 0, 0);
+                    }
+                };
+                const char *dd = sb + Sh::drow_at(pl >> 1);
+                const char *de = dd + Sh::delem_at(e0);   // row e0 (e0 is a whole number of units)
+                auto d = [&](int k) -> T { return *reinterpret_cast<const T *>(dd + Sh::delem_at(k)); };
+                auto dr = [&](int k) -> T { return *reinterpret_cast<const T *>(de + Sh::delem_at(k)); };
+                for (int bt = 0; bt < nbat; ++bt) {
+                    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): the previous batch has been read
+                    asm volatile("" ::: "memory");
+                    fetch(bt);
+                    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the batch is in LDS
+                    asm volatile("" ::"v"(sb) : "memory");
+                    if (bt * 32 + slot < npv) {
+                        // J_c (0..17), record 26..31 (18..23)
+                        const T m00 = d(19), m01 = d(20), m11 = d(21), r0 = d(22), r1 = d(23);
+                        // rows e of J_c^T M, then one column of J_c at a time
+                        T p0[5], p1[5];
 #pragma unroll
-                    for (int k = 0; k < 9; ++k) acc[i][k] += a0 * y[3 * k] + a1 * y[3 * k + 1] + a2 * y[3 * k + 2];
+                        for (int i = 0; i < 5; ++i) {
+                            const T je0 = dr(i), je1 = dr(9 + i);
+                            p0[i] = fma(je1, m01, je0 * m00);
+                            p1[i] = fma(je1, m11, je0 * m01);
+                            du[i] = fma(je1, je1, fma(je0, je0, du[i]));
+                            rb[i] = fma(je1, r1, fma(je0, r0, rb[i]));
+                        }
+#pragma unroll
+                        for (int k = 0; k < 9; ++k) {
+                            const T j0 = d(k), j1 = d(9 + k);
+#pragma unroll
+                            for (int i = 0; i < 5; ++i) acc[i][k] = fma(p1[i], j1, fma(p0[i], j0, acc[i][k]));
+                        }
+                    }
+                }
+            } else {
+                // off-diagonal pairs (u, w): S_rc -= Y_u Y_w^T.  Records 0..31 of a
+                // batch are the Y_u, 32..63 the Y_w.
+                const int yr = pl % Sh::kRecStep, yp = pl / Sh::kRecStep;
+                const T *src0 = obsd + yp * Sh::kPart;
+                auto fetch = [&](int bt) {
+#pragma unroll
+                    for (int i = 0; i < Sh::kLoads; ++i) {
+                        const int R = i * Sh::kRecStep + yr;
+                        const int2 uw = sp[min(bt * 32 + (R & 31), npv - 1)];
+                        const int64_t o = R < 32 ? uw.x : uw.y;
+                        __builtin_amdgcn_global_load_lds((const void *)(src0 + (int64_t)kObsRec * o),
+                                                         (void __attribute__((address_space(3))) *)(sb + i * Sh::kBlk),
+                                                         16, 0, 0);
+                    }
+                };
+                const char *ru = sb + Sh::row_at(pl >> 1) + Sh::elem_at(3 * e0);   // Y_u from row e0
+                const char *rw = sb + Sh::row_at(32 + (pl >> 1));
+                for (int bt = 0; bt < nbat; ++bt) {
+                    // the previous batch has been read before the next one lands
+                    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0)
+                    asm volatile("" ::: "memory");
+                    fetch(bt);
+                    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the batch is in LDS
+                    asm volatile("" ::"v"(sb) : "memory");
+                    if (bt * 32 + slot < npv) {
+                        T a[5][3];
+#pragma unroll
+                        for (int i = 0; i < 5; ++i)
+#pragma unroll
+                            for (int t = 0; t < 3; ++t)
+                                a[i][t] = *reinterpret_cast<const T *>(ru + Sh::elem_at(3 * i + t));
+#pragma unroll
+                        for (int k = 0; k < 9; ++k) {
+                            const T y0 = *reinterpret_cast<const T *>(rw + Sh::elem_at(3 * k));
+                            const T y1 = *reinterpret_cast<const T *>(rw + Sh::elem_at(3 * k + 1));
+                            const T y2 = *reinterpret_cast<const T *>(rw + Sh::elem_at(3 * k + 2));
+#pragma unroll
+                            for (int i = 0; i < 5; ++i)
+                                acc[i][k] = fma(a[i][2], y2, fma(a[i][1], y1, fma(a[i][0], y0, acc[i][k])));
+                        }
+                    }
                 }
             }
         }
@@ -708,13 +850,12 @@ __global__ __launch_bounds__(256) void k_schur(SchurChunks ch, const int2 *__res
                 if (slot == k) col[i] = acc[i][k];
         }
         if (slot >= 9) continue;
-        const int nrow = e0 == 0 ? 5 : 4;
         if (nch == 1) {
             double *A = S + S_off[kr];
             const int64_t lr = cam_local[r];
             const int64_t lc = cam_local[c];
             double *colp = A + 9 * lr + (9 * lc + slot) * Np;
-            for (int i = 0; i < nrow; ++i) {
+            for (int i = i0; i < 5; ++i) {
                 const int e = e0 + i;
                 double v = (double)col[i];
                 if (diag) {
@@ -725,12 +866,12 @@ __global__ __launch_bounds__(256) void k_schur(SchurChunks ch, const int2 *__res
                 colp[e] = v;
             }
             if (diag && slot == 0)
-                for (int i = 0; i < nrow; ++i) b[9 * (int64_t)r + e0 + i] = -(double)rb[i];
+                for (int i = i0; i < 5; ++i) b[9 * (int64_t)r + e0 + i] = -(double)rb[i];
         } else {
             double *mine = ch.part + item * kSchurPart;
-            for (int i = 0; i < nrow; ++i) mine[9 * (e0 + i) + slot] = (double)col[i];
+            for (int i = i0; i < 5; ++i) mine[9 * (e0 + i) + slot] = (double)col[i];
             if (diag && slot == 0)
-                for (int i = 0; i < nrow; ++i) {
+                for (int i = i0; i < 5; ++i) {
                     mine[81 + e0 + i] = (double)du[i];
                     mine[90 + e0 + i] = (double)rb[i];
                 }
