@@ -836,12 +836,19 @@ __global__ __launch_bounds__(kTsThreads) void k_trisolve(int mode, const int32_t
                                                          const int32_t *__restrict__ cl_cams,
                                                          const double *__restrict__ S,
                                                          const double *__restrict__ rhs, int32_t rstride,
-                                                         double *__restrict__ dcam, int32_t max_Np) {
+                                                         double *__restrict__ dcam, int32_t max_Np,
+                                                         int32_t *__restrict__ flags, int32_t fpc) {
     extern __shared__ double smem[];
     double *v = smem;               // max_Np
     double *ys = v + max_Np;        // kNB
     const int k = blockIdx.x;
     const int tid = threadIdx.x;
+    if (flags != nullptr) {
+        // after the tile-parallel factorisation: clear its flag words (cluster k's
+        // and the abort word) so that they are zero when the next one starts
+        for (int i = tid; i < fpc; i += kTsThreads) flags[(int64_t)k * fpc + i] = 0;
+        if (k == 0 && tid == 0) flags[(int64_t)gridDim.x * fpc] = 0;
+    }
     const int nk = cl_n[k];
     if (nk == 0) return;
     const int64_t Np = cl_Np[k];
@@ -954,14 +961,14 @@ hipError_t launch_chol(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, con
                        double *rbuf, hipStream_t st) {
     int32_t wpc = 0, tmax = 0, fpc = 0;
     if (flags && yx && chol_tile_layout(l, max_Np, &wpc, &tmax, &fpc)) {
-        const int64_t nflags = (int64_t)l * fpc + 1;
-        k_zero_flags<<<(unsigned)((nflags + 255) / 256), 256, 0, st>>>(flags, nflags);
+        // the flag words are zero here: cleared when the workspace was prepared and
+        // after every factorisation by the solve that follows it
         k_chol_tiles<<<(unsigned)((int64_t)l * wpc), 64, 0, st>>>(wpc, tmax, fpc, cl_n, cl_Np, S_off, cl_start, cl_cams,
                                                                  S, b, dcam, cl_status, flags, l, yx);
         // backward solve by one workgroup per cluster
         const size_t shmem = sizeof(double) * ((size_t)max_Np + kNB);
         k_trisolve<<<(unsigned)l, kTsThreads, shmem, st>>>(kTsFromY, cl_n, cl_Np, S_off, cl_start, cl_cams, S, yx,
-                                                           tmax * kNB, dcam, max_Np);
+                                                           tmax * kNB, dcam, max_Np, flags, fpc);
         if (S0) {
             const hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
@@ -989,6 +996,12 @@ hipError_t launch_copy_S(const double *S, double *S0, const int64_t *S_off, int3
     return hipGetLastError();
 }
 
+hipError_t launch_clear_chol_flags(int32_t *flags, hipStream_t st) {
+    const int64_t n = chol_flag_words();
+    k_zero_flags<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(flags, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_refine(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, const int64_t *S_off,
                          const int32_t *cl_start, const int32_t *cl_cams, const double *S, const double *S0,
                          const double *b, double *dcam, double *rbuf, int32_t max_Np, hipStream_t st) {
@@ -997,7 +1010,7 @@ hipError_t launch_refine(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, c
         nrb, cl_n, cl_Np, S_off, cl_start, cl_cams, S0, b, dcam, rbuf, max_Np);
     const size_t shmem = sizeof(double) * ((size_t)max_Np + kNB);
     k_trisolve<<<(unsigned)l, kTsThreads, shmem, st>>>(kTsRefine, cl_n, cl_Np, S_off, cl_start, cl_cams, S, rbuf,
-                                                       max_Np, dcam, max_Np);
+                                                       max_Np, dcam, max_Np, nullptr, 0);
     return hipGetLastError();
 }
 

@@ -113,6 +113,98 @@ __global__ __launch_bounds__(1024) void k_clusters(const int32_t *cam_cluster, i
     if (k0 < l && k1 == l) S_off[l] = s;
 }
 
+// Exclusive scan over the block (at most 1024 threads, whole wavefronts): wave
+// scans by shuffles, then a scan of the wave totals.  *total gets the sum.
+template <typename V>
+__device__ inline V block_exclusive_scan(V v, V *wsum, V *total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    V inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const V n = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += n;
+    }
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    if (w == 0) {
+        V x = lane < nw ? wsum[lane] : (V)0;
+#pragma unroll
+        for (int d = 1; d < 16; d <<= 1) {
+            const V n = __shfl_up(x, d, 64);
+            if (lane >= d) x += n;
+        }
+        if (lane < nw) wsum[lane] = x;
+    }
+    __syncthreads();
+    const V base = w > 0 ? wsum[w - 1] : (V)0;
+    *total = wsum[nw - 1];
+    __syncthreads();   // wsum may be reused by the next scan
+    return base + inc - v;
+}
+
+// The same layout for m <= 1024 cameras without sorting: one thread per camera
+// and per cluster (l <= m), per-cluster counts in LDS, the position of a camera
+// in its cluster = the number of lower-numbered cameras of that cluster.
+__global__ __launch_bounds__(1024) void k_clusters_small(const int32_t *cam_cluster, int32_t m, int32_t l,
+                                                         int32_t gamma_max, int32_t *cl_n, int32_t *cl_Np,
+                                                         int32_t *cl_start, int32_t *cl_cams, int32_t *cam_local,
+                                                         int64_t *S_off, int32_t *status) {
+    __shared__ __align__(16) int32_t cl[1024];
+    __shared__ int32_t cnt[1024];
+    __shared__ int32_t ws32[16];
+    __shared__ int64_t ws64[16];
+    __shared__ int bad;
+    const int t = threadIdx.x;
+    if (t < kStCount) status[t] = 0;
+    if (t == 0) bad = 0;
+    int32_t k = -1;
+    if (t < m) {
+        k = cam_cluster[t];
+        if (k < 0 || k >= l) {
+            bad = 1;
+            k = -1;
+        }
+    }
+    cl[t] = k;
+    cnt[t] = 0;
+    __syncthreads();
+    if (k >= 0) atomicAdd(&cnt[k], 1);
+    // four ids per LDS read, several reads in flight (entries past m hold -1)
+    int32_t rank = 0;
+    const int4 *cl4 = reinterpret_cast<const int4 *>(cl);
+#pragma unroll 8
+    for (int j4 = 0; j4 < (m + 3) / 4; ++j4) {
+        const int4 v = cl4[j4];
+        const int j = 4 * j4;
+        rank += (j < t && v.x == k) + (j + 1 < t && v.y == k) + (j + 2 < t && v.z == k) + (j + 3 < t && v.w == k);
+    }
+    __syncthreads();
+    const int32_t nk = t < l ? cnt[t] : 0;
+    if (nk > gamma_max) bad = 2;
+    int32_t tot32;
+    const int32_t start = block_exclusive_scan<int32_t>(nk, ws32, &tot32);   // barriers publish bad
+    const bool ok = bad == 0;
+    const int32_t n_out = ok ? nk : 0;
+    const int32_t np_out = ok ? (int32_t)round_up(9 * (int64_t)nk, kNB) : 0;
+    if (t < l) {
+        cl_n[t] = n_out;
+        cl_Np[t] = np_out;
+        cl_start[t] = start;
+        cnt[t] = start;   // now the first slot of cluster t
+    }
+    if (t == 0) cl_start[l] = tot32;
+    if (!ok && t == 0) set_status(status + kStSticky, STBA_EINVAL);
+    __syncthreads();
+    if (k >= 0) {
+        cl_cams[cnt[k] + rank] = t;
+        cam_local[t] = rank;
+    }
+    int64_t tot64;
+    const int64_t off = block_exclusive_scan<int64_t>(t < l ? (int64_t)np_out * np_out : 0, ws64, &tot64);
+    if (t < l) S_off[t] = off;
+    if (t == 0) S_off[l] = tot64;
+}
+
 __global__ void k_reset_status(int32_t *status) {
     if (threadIdx.x < kStCount) status[threadIdx.x] = 0;
 }
@@ -141,8 +233,17 @@ __global__ __launch_bounds__(256) void k_rj(int64_t q, const double *__restrict_
                                             const int32_t *__restrict__ oc, const int32_t *__restrict__ op,
                                             const double *__restrict__ uv, T *__restrict__ f, T *__restrict__ Jc,
                                             T *__restrict__ Jp, double *__restrict__ partials,
-                                            const int32_t *need_jac, int32_t *jac_ran) {
+                                            const int32_t *need_jac, int32_t *jac_ran, ZeroS z) {
     __shared__ double sh[256];
+    if (z.S != nullptr) {
+        // S and b of this iteration start from zero (the grid runs even when the
+        // Jacobian is kept)
+        int64_t total = z.S_off[z.l];
+        if (total > z.S_cap) total = z.S_cap;
+        const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) z.S[i] = 0.0;
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < z.nb; i += stride) z.b[i] = 0.0;
+    }
     if (need_jac != nullptr && need_jac[0] == 0) return;
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double sq = 0.0;
@@ -563,26 +664,14 @@ __global__ void k_point_groups(int32_t n, const int64_t *__restrict__ pt_off, in
     if (jj == 0) grp_first[ngroups] = n;
 }
 
-// zero S (all clusters) and b.  With st given, block 0 also sets F(x) from the
-// residual kernel's per-block partials on the first iteration of a linearisation
-// (the LM state keeps it otherwise).
+// zero S (all clusters) and b
 __global__ __launch_bounds__(256) void k_zero_S(double *S, double *b, int32_t m, const int64_t *S_off, int32_t l,
-                                                int64_t S_cap, stba_lm_state *st, const double *partials,
-                                                int64_t count) {
-    __shared__ double sh[256];
+                                                int64_t S_cap) {
     int64_t total = S_off[l];
     if (total > S_cap) total = S_cap;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) S[i] = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 9 * (int64_t)m; i += stride) b[i] = 0.0;
-    if (st == nullptr || blockIdx.x != 0 || !(st->need_jac && !st->have_F)) return;
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < count; i += 256) s += partials[i];
-    s = block_sum_256(s, sh);
-    if (threadIdx.x == 0) {
-        st->F = s;
-        st->have_F = 1;
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -975,8 +1064,12 @@ __global__ __launch_bounds__(256) void k_cost_at(int64_t q, const double *__rest
                                                  double *__restrict__ F_ref) {
     __shared__ double sh[256];
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    // F(x) as it stands before the decision, for every block of k_accept_update
-    if (F_ref != nullptr && o == 0) F_ref[0] = st->F;
+    // F(x) as it stands before the decision (and whether it is known yet), for
+    // every block of k_accept_update
+    if (F_ref != nullptr && o == 0) {
+        F_ref[0] = st->F;
+        F_ref[1] = st->have_F ? 1.0 : 0.0;
+    }
     double sq = 0.0;
     if (o < q) {
         const int64_t i = oc[o], j = op[o];
@@ -996,10 +1089,12 @@ __global__ __launch_bounds__(256) void k_cost_at(int64_t q, const double *__rest
 
 // a7: accept iff F(x + dx) < F(x), the step is finite and every S_k factorised
 // (Alg. 1); lambda /= 3 on accept, *= 3 otherwise; x += dx on accept.  Every
-// block sums the candidate partials in the same fixed order and compares with
-// F_ref (F(x) copied by k_cost_at), so all blocks take the same decision while
-// block 0 rewrites the LM state.
-__global__ __launch_bounds__(256) void k_accept_update(const double *partials, int64_t count, const double *F_ref,
+// block sums the per-block partials in the same fixed order and compares with
+// F(x): F_ref[0] (copied by k_cost_at) once the state holds it (F_ref[1] != 0),
+// else the sum of the residual kernel's partials.  So all blocks take the same
+// decision while block 0 rewrites the LM state.
+__global__ __launch_bounds__(256) void k_accept_update(const double *rj_partials, const double *partials,
+                                                       int64_t count, const double *F_ref,
                                                        const int32_t *cl_status, int32_t l, const int32_t *status,
                                                        stba_lm_state *st, int32_t m, int32_t n, double *cam,
                                                        double *pt, const double *dcam, const double *dpt) {
@@ -1013,12 +1108,21 @@ __global__ __launch_bounds__(256) void k_accept_update(const double *partials, i
         if (cl_status[k] != STBA_OK) bad_pd = 1;
     s = block_sum_256(s, sh);   // its barriers also publish bad_pd
     const double Fn = s;
+    const bool have_F = F_ref[1] != 0.0;
+    double F0 = F_ref[0];
+    if (!have_F) {
+        double s0 = 0.0;
+        for (int64_t i = threadIdx.x; i < count; i += 256) s0 += rj_partials[i];
+        F0 = block_sum_256(s0, sh);
+    }
     const int32_t sticky = status[kStSticky];
     const bool pd = !bad_pd && status[kStPointBad] == 0;
     const bool fin = isfinite(Fn);
     const bool valid = pd && fin && sticky == 0;
-    const bool acc = valid && (Fn < F_ref[0]);
+    const bool acc = valid && (Fn < F0);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->F = F0;
+        st->have_F = 1;
         st->F_new = Fn;
         st->accepted = acc ? 1 : 0;
         st->lambda = acc ? st->lambda / 3.0 : st->lambda * 3.0;
@@ -1127,6 +1231,11 @@ hipError_t launch_lm_init(stba_lm_state *s, double lambda0, double lambda_corr, 
 hipError_t launch_clusters(const int32_t *cam_cluster, int32_t m, int32_t l, int32_t gamma_max, int32_t *cl_n,
                            int32_t *cl_Np, int32_t *cl_start, int32_t *cl_cams, int32_t *cam_local,
                            int64_t *S_off, int32_t *status, hipStream_t st) {
+    if (m <= 1024) {
+        k_clusters_small<<<1, (unsigned)round_up(m, 64), 0, st>>>(cam_cluster, m, l, gamma_max, cl_n, cl_Np, cl_start,
+                                                                  cl_cams, cam_local, S_off, status);
+        return hipGetLastError();
+    }
     // one thread per compare-exchange of the bitonic sort, so a small map uses a
     // small block (cheaper barriers)
     int P = 1;
@@ -1143,15 +1252,15 @@ int64_t rj_blocks(int64_t q) { return (q + 255) / 256; }
 
 template <typename T>
 hipError_t launch_rj(const stba_problem &p, T *f, T *Jc, T *Jp, double *partials, const int32_t *need_jac,
-                     int32_t *jac_ran, hipStream_t st) {
+                     int32_t *jac_ran, const ZeroS &z, hipStream_t st) {
     k_rj<T><<<grid_for(p.q), 256, 0, st>>>(p.q, p.cam, p.pt, p.obs_cam, p.obs_pt, p.obs_uv, f, Jc, Jp, partials,
-                                           need_jac, jac_ran);
+                                           need_jac, jac_ran, z);
     return hipGetLastError();
 }
 template hipError_t launch_rj<double>(const stba_problem &, double *, double *, double *, double *,
-                                      const int32_t *, int32_t *, hipStream_t);
+                                      const int32_t *, int32_t *, const ZeroS &, hipStream_t);
 template hipError_t launch_rj<float>(const stba_problem &, float *, float *, float *, double *, const int32_t *,
-                                     int32_t *, hipStream_t);
+                                     int32_t *, const ZeroS &, hipStream_t);
 
 hipError_t launch_sum_partials(const double *partials, int64_t count, double *out, hipStream_t st) {
     k_sum_partials<<<1, 256, 0, st>>>(partials, count, out);
@@ -1203,11 +1312,11 @@ hipError_t launch_point_groups(int32_t n, const int64_t *pt_off, int32_t group_s
 }
 
 hipError_t launch_fill_S(double *S, double *b, int32_t m, const int64_t *S_off, int32_t l, int64_t S_cap,
-                         stba_lm_state *s, const double *partials, int64_t count, hipStream_t st) {
+                         hipStream_t st) {
     int64_t blocks = (S_cap + 1023) / 1024;
     if (blocks > 8192) blocks = 8192;
     if (blocks < 1) blocks = 1;
-    k_zero_S<<<(unsigned)blocks, 256, 0, st>>>(S, b, m, S_off, l, S_cap, s, partials, count);
+    k_zero_S<<<(unsigned)blocks, 256, 0, st>>>(S, b, m, S_off, l, S_cap);
     return hipGetLastError();
 }
 
@@ -1256,15 +1365,16 @@ hipError_t launch_cost_at(const stba_problem &p, const double *dcam, const doubl
     return hipGetLastError();
 }
 
-hipError_t launch_accept_update(const stba_problem &p, const double *partials, int64_t count, const double *F_ref,
-                                const int32_t *cl_status, int32_t l, const int32_t *status, stba_lm_state *s,
-                                const double *dcam, const double *dpt, hipStream_t st) {
+hipError_t launch_accept_update(const stba_problem &p, const double *rj_partials, const double *partials,
+                                int64_t count, const double *F_ref, const int32_t *cl_status, int32_t l,
+                                const int32_t *status, stba_lm_state *s, const double *dcam, const double *dpt,
+                                hipStream_t st) {
     // few blocks: each one re-sums the candidate partials before its share of x += dx
     unsigned blocks = grid_for(9 * (int64_t)p.m + 3 * (int64_t)p.n);
     if (blocks > 128) blocks = 128;
     if (blocks < 1) blocks = 1;
-    k_accept_update<<<blocks, 256, 0, st>>>(partials, count, F_ref, cl_status, l, status, s, p.m, p.n, p.cam, p.pt,
-                                            dcam, dpt);
+    k_accept_update<<<blocks, 256, 0, st>>>(rj_partials, partials, count, F_ref, cl_status, l, status, s, p.m, p.n,
+                                            p.cam, p.pt, dcam, dpt);
     return hipGetLastError();
 }
 

@@ -40,9 +40,18 @@ hipError_t launch_clusters(const int32_t *cam_cluster, int32_t m, int32_t l, int
                            int32_t *cl_n, int32_t *cl_Np, int32_t *cl_start, int32_t *cl_cams,
                            int32_t *cam_local, int64_t *S_off, int32_t *status, hipStream_t st);
 
+// S (nullable): also zero S (the first min(S_off[l], S_cap) doubles) and b (nb doubles)
+struct ZeroS {
+    double *S = nullptr;
+    const int64_t *S_off = nullptr;
+    int32_t l = 0;
+    int64_t S_cap = 0;
+    double *b = nullptr;
+    int64_t nb = 0;
+};
 template <typename T>
 hipError_t launch_rj(const stba_problem &p, T *f, T *Jc, T *Jp, double *partials, const int32_t *need_jac,
-                     int32_t *jac_ran, hipStream_t st);
+                     int32_t *jac_ran, const ZeroS &z, hipStream_t st);
 int64_t rj_blocks(int64_t q);
 
 hipError_t launch_sum_partials(const double *partials, int64_t count, double *out, hipStream_t st);
@@ -62,9 +71,9 @@ hipError_t launch_point_groups(int32_t n, const int64_t *pt_off, int32_t group_s
                                int32_t *grp_first, hipStream_t st);
 inline int32_t point_group_size(int32_t max_track) { return max_track <= 32 ? 65 - max_track : 0; }
 
-// zero S and b; s (nullable): set F(x) from the residual partials if the state asks for it
+// zero S and b
 hipError_t launch_fill_S(double *S, double *b, int32_t m, const int64_t *S_off, int32_t l, int64_t S_cap,
-                         stba_lm_state *s, const double *partials, int64_t count, hipStream_t st);
+                         hipStream_t st);
 
 struct SchurChunks {
     const int64_t *n_chunks;
@@ -90,6 +99,9 @@ inline int64_t chol_flag_words() { return 4 * (int64_t)kCholTileWaves + 1; }
 // per cluster T 32 doubles (the forward solution y), T <= its wavefronts
 inline int64_t chol_yx_doubles() { return (int64_t)kCholTileWaves * kNB; }
 int chol_tile_layout(int32_t l, int32_t max_Np, int32_t *wpc, int32_t *tmax, int32_t *fpc);
+// the flag words have to be zero before the first factorisation; every
+// tile-parallel factorisation leaves them zero again
+hipError_t launch_clear_chol_flags(int32_t *flags, hipStream_t st);
 // S0 (nullable): the assembled S kept for one FP64 refinement step (MIXED),
 // with rbuf (l * max_Np doubles) for its residual.
 hipError_t launch_chol(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, const int64_t *S_off,
@@ -109,13 +121,15 @@ template <typename T>
 hipError_t launch_backsub(const stba_problem &p, const int64_t *pt_off, const T *Jc, const T *Jp,
                           const double *Vinv, const double *wph, const double *dcam, double *dpt, hipStream_t st);
 
-// F_ref (nullable): receives s->F for launch_accept_update
+// F_ref (nullable, 2 doubles): receives s->F and s->have_F for launch_accept_update
 hipError_t launch_cost_at(const stba_problem &p, const double *dcam, const double *dpt, double *partials,
                           const stba_lm_state *s, double *F_ref, hipStream_t st);
 
-hipError_t launch_accept_update(const stba_problem &p, const double *partials, int64_t count, const double *F_ref,
-                                const int32_t *cl_status, int32_t l, const int32_t *status, stba_lm_state *s,
-                                const double *dcam, const double *dpt, hipStream_t st);
+// rj_partials: the residual kernel's partials (F(x) while the state has none)
+hipError_t launch_accept_update(const stba_problem &p, const double *rj_partials, const double *partials,
+                                int64_t count, const double *F_ref, const int32_t *cl_status, int32_t l,
+                                const int32_t *status, stba_lm_state *s, const double *dcam, const double *dpt,
+                                hipStream_t st);
 
 template <typename T>
 hipError_t launch_vjp(const stba_problem &p, const int64_t *pt_off, const int64_t *diag_blk,

@@ -125,7 +125,8 @@ bool make_layout(const stba_problem *p, const stba_dims *d, int precision, Layou
     L.dcam = take(8 * 9 * m);
     L.dpt = take(8 * 3 * n);
     L.n_partials = rj_blocks(p->q);
-    L.partials = take(8 * (size_t)L.n_partials + 8);   // + F(x) before the accept decision
+    // residual partials, candidate-cost partials, F(x) and have_F before the accept decision
+    L.partials = take(8 * (2 * (size_t)L.n_partials + 2));
     L.total = off;
     return true;
 }
@@ -185,7 +186,7 @@ int build_rcs_impl(const stba_problem *p, const stba_dims *d, const stba_sample 
                               at<double>(ws, L.Vinv), at<double>(ws, L.wph), status, L.group_size,
                               at<int32_t>(ws, L.grp_first), st));
     STBA_HIP(launch_fill_S(at<double>(ws, L.S), at<double>(ws, L.b), p->m, at<int64_t>(ws, L.S_off), s->l, L.S_cap,
-                           nullptr, nullptr, 0, st));
+                           st));
     STBA_HIP(launch_schur<T>(at<int64_t>(ws, L.n_blocks), L.blk_cap, chunks_of(L, ws), at<int2>(ws, L.blk_key),
                              at<int64_t>(ws, L.blk_start), at<uint64_t>(ws, L.pairs), s->cam_cluster, s->l,
                              at<int32_t>(ws, L.cam_local), at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np),
@@ -235,17 +236,21 @@ int lm_step_impl(const stba_problem *p, const stba_dims *d, const stba_sample *s
                              at<int32_t>(ws, L.cl_Np), at<int32_t>(ws, L.cl_start), at<int32_t>(ws, L.cl_cams),
                              at<int32_t>(ws, L.cam_local), at<int64_t>(ws, L.S_off), status, st));
     STBA_TRY(mark(1));
-    STBA_HIP(launch_rj<T>(*p, f, Jc, Jp, at<double>(ws, L.partials), &stt->need_jac, status + kStJacRan, st));
+    ZeroS z;   // S and b are zeroed by the residual kernel's grid
+    z.S = at<double>(ws, L.S);
+    z.S_off = at<int64_t>(ws, L.S_off);
+    z.l = s->l;
+    z.S_cap = L.S_cap;
+    z.b = at<double>(ws, L.b);
+    z.nb = 9 * (int64_t)p->m;
+    STBA_HIP(launch_rj<T>(*p, f, Jc, Jp, at<double>(ws, L.partials), &stt->need_jac, status + kStJacRan, z, st));
     STBA_TRY(mark(2));
     STBA_HIP(launch_points<T>(*p, at<int64_t>(ws, L.pt_off), s->cam_cluster, s->l, f, Jc, Jp, lam2, s->seed, s->iter,
                               keep_threshold(s->alpha), at<int32_t>(ws, L.seg_head), at<double>(ws, L.seg_rec), at<T>(ws, L.obsd),
                               at<double>(ws, L.Vinv), at<double>(ws, L.wph), status, L.group_size,
                               at<int32_t>(ws, L.grp_first), st));
     STBA_TRY(mark(3));
-    // also F(x) from the residual kernel's partials when the state has none yet
-    STBA_HIP(launch_fill_S(at<double>(ws, L.S), at<double>(ws, L.b), p->m, at<int64_t>(ws, L.S_off), s->l, L.S_cap,
-                           stt, at<double>(ws, L.partials), L.n_partials, st));
-    STBA_TRY(mark(4));
+    STBA_TRY(mark(4));   // S was zeroed with the residuals: nothing between the marks
     STBA_HIP(launch_schur<T>(at<int64_t>(ws, L.n_blocks), L.blk_cap, chunks_of(L, ws), at<int2>(ws, L.blk_key),
                              at<int64_t>(ws, L.blk_start), at<uint64_t>(ws, L.pairs), s->cam_cluster, s->l,
                              at<int32_t>(ws, L.cam_local), at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np),
@@ -259,11 +264,12 @@ int lm_step_impl(const stba_problem *p, const stba_dims *d, const stba_sample *s
     STBA_HIP(launch_backsub<T>(*p, at<int64_t>(ws, L.pt_off), Jc, Jp, at<double>(ws, L.Vinv), at<double>(ws, L.wph),
                                dcam, dpt, st));
     STBA_TRY(mark(7));
-    double *F_ref = at<double>(ws, L.partials) + L.n_partials;
-    STBA_HIP(launch_cost_at(*p, dcam, dpt, at<double>(ws, L.partials), stt, F_ref, st));
+    double *rj_part = at<double>(ws, L.partials), *cost_part = rj_part + L.n_partials;
+    double *F_ref = cost_part + L.n_partials;
+    STBA_HIP(launch_cost_at(*p, dcam, dpt, cost_part, stt, F_ref, st));
     STBA_TRY(mark(8));
-    STBA_HIP(launch_accept_update(*p, at<double>(ws, L.partials), L.n_partials, F_ref, at<int32_t>(ws, L.cl_status),
-                                  s->l, status, stt, dcam, dpt, st));
+    STBA_HIP(launch_accept_update(*p, rj_part, cost_part, L.n_partials, F_ref, at<int32_t>(ws, L.cl_status), s->l,
+                                  status, stt, dcam, dpt, st));
     STBA_TRY(mark(9));
     return STBA_OK;
 }
@@ -332,6 +338,7 @@ int stba_prepare(const stba_problem *p, const stba_dims *dims, int precision, vo
     b.tmp_bytes = L.tmp_bytes;
     STBA_HIP(launch_reset_status(at<int32_t>(ws, L.status), stream));
     STBA_HIP(launch_prepare(*p, dims->n_pairs, b, at<int32_t>(ws, L.status), stream));
+    STBA_HIP(launch_clear_chol_flags(at<int32_t>(ws, L.chol_flags), stream));
     if (L.group_size > 0)
         STBA_HIP(launch_point_groups(p->n, b.pt_off, L.group_size, (p->q + L.group_size - 1) / L.group_size,
                                      at<int32_t>(ws, L.grp_first), stream));
@@ -345,9 +352,11 @@ int stba_residual_jacobian(const stba_problem *p, const stba_dims *dims, int pre
     if (!f || ((Jc == nullptr) != (Jp == nullptr))) return STBA_EINVAL;
     double *partials = cost ? at<double>(ws, L.partials) : nullptr;
     if (precision == STBA_FP64)
-        STBA_HIP(launch_rj<double>(*p, (double *)f, (double *)Jc, (double *)Jp, partials, nullptr, nullptr, stream));
+        STBA_HIP(launch_rj<double>(*p, (double *)f, (double *)Jc, (double *)Jp, partials, nullptr, nullptr, ZeroS(),
+                                   stream));
     else
-        STBA_HIP(launch_rj<float>(*p, (float *)f, (float *)Jc, (float *)Jp, partials, nullptr, nullptr, stream));
+        STBA_HIP(launch_rj<float>(*p, (float *)f, (float *)Jc, (float *)Jp, partials, nullptr, nullptr, ZeroS(),
+                                  stream));
     if (cost) STBA_HIP(launch_sum_partials(partials, L.n_partials, cost, stream));
     return STBA_OK;
 }

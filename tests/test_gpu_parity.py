@@ -11,7 +11,7 @@ import torch
 import oracle as O
 import paper_2008_00446_amd as S
 import synth
-from gpu_helpers import GpuProblem, dev, rel, rel_max
+from gpu_helpers import GpuProblem, dev, rel, rel_max, ws_view
 
 pytestmark = pytest.mark.gpu
 
@@ -137,6 +137,38 @@ def test_extreme_clusterings(mode):
     assert np.all(cs == 0)
     assert rel(dcam, ref_c) < 1e-9
     assert rel(dpt, ref_p) < 1e-9
+
+
+@pytest.mark.parametrize("m,l", [(200, 23), (1100, 150)])
+def test_cluster_layout_bit_exact(m, l):
+    """Cameras grouped by cluster (ascending ids), sizes, padded orders and S_k
+    offsets; 200 cameras take the counting layout, 1100 the sorting one.  Some
+    cluster ids are left unused (empty clusters)."""
+    s = synth.small_ring(m=m, n=2500, views=4, seed=11)
+    rng = np.random.default_rng(4)
+    lab = rng.integers(0, l - 3, size=m).astype(np.int32)   # ids l-3 .. l-1 stay empty
+    assert np.bincount(lab).max() <= 40
+    g = GpuProblem(s, gamma_max=40)
+    f, Jc, Jp, _ = g.residual_jacobian()
+    lab_d = dev(lab, torch.int32)
+    rcs = S.stba_build_cluster_rcs(g.prob, g.dims, S.make_sample(lab_d, l), S.StbaDamping(1e-3, 0.1),
+                                   S.STBA_FP64, f, Jc, Jp, g.ws)
+    torch.cuda.synchronize()
+    got = {k: ws_view(g.ws, getattr(rcs, k), dt, cnt).cpu().numpy() for k, dt, cnt in [
+        ("cl_n", torch.int32, l), ("cl_Np", torch.int32, l), ("cl_start", torch.int32, l + 1),
+        ("cl_cams", torch.int32, m), ("cam_local", torch.int32, m), ("S_off", torch.int64, l + 1)]}
+    n_k = np.bincount(lab, minlength=l)
+    Np = (9 * n_k + 31) // 32 * 32
+    order = np.argsort(lab, kind="stable")
+    local = np.empty(m, dtype=np.int64)
+    start = np.concatenate([[0], np.cumsum(n_k)])
+    local[order] = np.arange(m) - start[lab[order]]
+    assert np.array_equal(got["cl_n"], n_k)
+    assert np.array_equal(got["cl_Np"], Np)
+    assert np.array_equal(got["cl_start"], start)
+    assert np.array_equal(got["cl_cams"], order)
+    assert np.array_equal(got["cam_local"], local)
+    assert np.array_equal(got["S_off"], np.concatenate([[0], np.cumsum(Np.astype(np.int64) ** 2)]))
 
 
 def test_invalid_maps_are_rejected_on_device():
