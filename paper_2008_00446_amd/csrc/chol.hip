@@ -738,7 +738,7 @@ __device__ inline void lds_barrier() {
 // One sweep over the tiles; v (LDS) holds the right-hand side and receives the
 // solution; ys (LDS, 32) carries the block just solved.
 template <bool kFwd>
-__device__ __attribute__((noinline)) void ts_sweep(const double *A, int64_t Np, int T, double *v, double *ys, int tid) {
+__device__ __attribute__((always_inline)) inline void ts_sweep(const double *A, int64_t Np, int T, double *v, double *ys, int tid) {
     const int r = tid & (kNB - 1);
     const bool diag_wave = tid >= kTsUpd;
     const int o = tid;   // update output (first one; more only for T > kTsUpd / 32 + 1)
