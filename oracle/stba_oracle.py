@@ -235,13 +235,18 @@ def link_draws(seed, t, point, camera):
 # ---------------------------------------------------------------------------
 
 
-def segments(obs_cam, obs_pt, cam_cluster, alpha, seed, t):
+def segments(obs_cam, obs_pt, cam_cluster, alpha, seed, t, ids=None):
     """Point splitting then point binding (Sec. 4.1-4.2).
 
     Each observation starts as its own virtual point; the constraints of a
     physical point join consecutive observations (in (cluster, camera) order) of
     the same cluster; a sampled constraint (theta = 1) binds them.  Cross-cluster
     constraints are never bound, which makes S' cluster-diagonal (Sec. 4.2).
+
+    ids: optional (point number, camera number) per observation that key the
+    draw, for a problem cut out of a larger one with its cameras and points
+    renumbered in increasing order (the draw belongs to the physical point and
+    camera, not to their position in the cut-out arrays).
 
     Returns (seg [q] segment id per observation, n_seg, seg_point [n_seg],
     kept_links [k,2] (earlier obs, later obs), all_links [r,2] intra-point
@@ -254,7 +259,10 @@ def segments(obs_cam, obs_pt, cam_cluster, alpha, seed, t):
     p_o, c_o, k_o = obs_pt[order], obs_cam[order], clus[order]
     same_pt = np.r_[False, p_o[1:] == p_o[:-1]]
     same_cl = same_pt & np.r_[False, k_o[1:] == k_o[:-1]]
-    u = link_draws(seed, t, p_o, c_o)
+    if ids is None:
+        u = link_draws(seed, t, p_o, c_o)
+    else:
+        u = link_draws(seed, t, np.asarray(ids[0], dtype=np.int64)[order], np.asarray(ids[1], dtype=np.int64)[order])
     kept = same_cl & (u < np.uint64(keep_threshold(alpha)))
     seg_sorted = np.cumsum(~kept) - 1
     seg = np.empty(q, dtype=np.int64)
@@ -390,15 +398,15 @@ class StbaStep:
 
 
 def stba_step(cam, pt, obs_cam, obs_pt, obs_uv, cam_cluster, lam, alpha=1.0, seed=0, t=0,
-              lam_corr=0.1, Jc=None, Jp=None, f=None):
+              lam_corr=0.1, Jc=None, Jp=None, f=None, ids=None):
     """One STBA step for a given clustering (Alg. 1, one pass of the while loop
-    up to the point update)."""
+    up to the point update).  ids: see `segments`."""
     m, n = cam.shape[0], pt.shape[0]
     if f is None:
         f = residuals(cam, pt, obs_cam, obs_pt, obs_uv)
     if Jc is None or Jp is None:
         Jc, Jp = jacobian(cam, pt, obs_cam, obs_pt)
-    seg, n_seg, seg_point, _, _, _ = segments(obs_cam, obs_pt, cam_cluster, alpha, seed, t)
+    seg, n_seg, seg_point, _, _, _ = segments(obs_cam, obs_pt, cam_cluster, alpha, seed, t, ids)
     fv = np.asarray(f, dtype=np.float64).reshape(-1)
     Jc_m = jc_matrix(Jc, obs_cam, m)
     Jp_virt = jp_matrix(Jp, seg, n_seg)

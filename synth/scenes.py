@@ -93,8 +93,13 @@ def _pixels(P: np.ndarray, f: np.ndarray, k1: np.ndarray, k2: np.ndarray) -> np.
 
 
 def _assemble(name, R, C, intr, X, vis_cam, vis_pt, rng, noise_px, rot_pert=0.01,
-              t_pert=0.05, pt_pert=0.05, meta=None) -> Scene:
-    """Sort the visibility list, synthesise pixels, perturb the start values."""
+              t_pert=0.05, pt_pert=0.05, meta=None, keep_centres=False) -> Scene:
+    """Sort the visibility list, synthesise pixels, perturb the start values.
+
+    keep_centres: after the rotation-vector offset, t is recomputed so that each
+    camera keeps its centre (then the translation noise is added).  Without it a
+    0.01 rad offset turns a camera about the world origin, which on a scene
+    kilometres across moves it by tens of metres."""
     m = R.shape[0]
     n = X.shape[0]
     order = np.lexsort((vis_cam, vis_pt))
@@ -114,6 +119,8 @@ def _assemble(name, R, C, intr, X, vis_cam, vis_pt, rng, noise_px, rot_pert=0.01
     d /= np.linalg.norm(d, axis=1, keepdims=True)
     cam0 = cam_gt.copy()
     cam0[:, 0:3] += rot_pert * d
+    if keep_centres:
+        cam0[:, 3:6] = -np.einsum("kab,kb->ka", Rotation.from_rotvec(cam0[:, 0:3]).as_matrix(), C)
     cam0[:, 3:6] += rng.normal(0.0, t_pert, size=(m, 3))
     pt0 = X + rng.normal(0.0, pt_pert, size=(n, 3))
     return Scene(cam_gt=cam_gt, pt_gt=X.copy(), cam0=cam0, pt0=pt0, obs_cam=obs_cam,
@@ -307,7 +314,7 @@ def slam(seed: int = 0, m: int = 5000, n: int = 1_000_000, p_geom: float = 0.25,
     offs = np.arange(vis_pt.shape[0]) - np.repeat(np.cumsum(L) - L, L)
     vis_cam = first[vis_pt] + offs
     return _assemble("slam", R, C, intr, X, vis_cam, vis_pt, rng, 0.7,
-                     meta=dict(track_mean=float(L.mean())))
+                     meta=dict(track_mean=float(L.mean())), keep_centres=True)
 
 
 def _unit(v):

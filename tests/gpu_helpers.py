@@ -77,6 +77,18 @@ class GpuProblem:
         seg = ws_view(self.ws, rcs.seg_head, torch.int32, self.q).cpu().numpy()
         return blocks, b, seg, cl_n
 
+    def read_cluster(self, rcs, k):
+        """Cluster k's S_k (symmetric, from its lower part) and the b of all cameras."""
+        torch.cuda.synchronize()
+        l = rcs.l
+        S_off = ws_view(self.ws, rcs.S_off, torch.int64, l + 1).cpu().numpy()
+        Np = int(ws_view(self.ws, rcs.cl_Np, torch.int32, l).cpu().numpy()[k])
+        N = 9 * int(ws_view(self.ws, rcs.cl_n, torch.int32, l).cpu().numpy()[k])
+        base = ws_view(self.ws, rcs.S, torch.float64, int(S_off[l]))
+        A = base[int(S_off[k]):int(S_off[k]) + Np * Np].cpu().numpy().reshape(Np, Np).T[:N, :N]
+        b = ws_view(self.ws, rcs.b, torch.float64, 9 * self.prob.m).cpu().numpy().reshape(-1, 9)
+        return np.tril(A) + np.tril(A, -1).T, b
+
     def solve(self, rcs, Jc, Jp):
         m, n = self.prob.m, self.prob.n
         dcam = torch.empty((m, 9), dtype=torch.float64, device="cuda")

@@ -10,12 +10,16 @@
 * S' is cluster-diagonal and symmetric; with one camera per cluster each 9x9 block
   has its closed form; the point step satisfies Eq. 6 for the computed dc.
 * LM: accepted steps lower F, rejected steps leave x unchanged, lambda /3 and x3.
+* below the correction threshold, one cluster cut out of the problem (cameras and
+  points renumbered, draws keyed by the original numbers) gives the same S_k,
+  b_k, camera step and interior point steps as the whole problem.
 """
 import numpy as np
 import pytest
 
 import oracle as O
 import synth
+from cluster_cut import cut_args, cut_cluster
 
 
 def _tiny(seed=3, m=5, n=12, views=3):
@@ -182,3 +186,28 @@ def test_lm_rejects_non_finite_step_and_keeps_x():
                        F=F)
     assert not r.accepted and r.F == F and np.isclose(r.lam, 3e-3)
     assert np.array_equal(r.cam, cam, equal_nan=True) and np.array_equal(r.pt, s.pt0)
+
+
+@pytest.mark.parametrize("alpha,lam", [(1.0, 1e-4), (0.6, 1e-3), (0.3, 0.05)])
+def test_cluster_cut_reproduces_the_whole_problem(alpha, lam):
+    s = synth.small_ring(m=24, n=600, views=6, seed=8)
+    e, w = synth.camera_graph(s.obs_cam, s.obs_pt, s.m)
+    lab = synth.sgc_map(e, w, s.m, 8, 10.0, 1, 2)
+    assert lab.max() >= 2
+    full = O.stba_step(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv, lab, lam, alpha, 5, 2)
+    assert not full.corrected
+    differs = False
+    for k in range(int(lab.max()) + 1):
+        cut = cut_cluster(s.obs_cam, s.obs_pt, lab, k)
+        args, ids = cut_args(s, cut)
+        sub = O.stba_step(*args, lam, alpha, 5, 2, ids=ids)
+        assert _rel(sub.S_blocks[0], full.S_blocks[k]) < 1e-13
+        assert _rel(sub.b_blocks[0], full.b_blocks[k]) < 1e-12
+        assert _rel(sub.dcam, full.dcam[cut.cams]) < 1e-10
+        if cut.interior.size:
+            assert _rel(sub.dpt[cut.interior], full.dpt[cut.pts[cut.interior]]) < 1e-10
+        # the draw belongs to the original numbers: renumbered draws split differently
+        plain = O.segments(args[2], args[3], args[5], alpha, 5, 2)[0]
+        keyed = O.segments(args[2], args[3], args[5], alpha, 5, 2, ids)[0]
+        differs |= not np.array_equal(O.canonical_segments(plain), O.canonical_segments(keyed))
+    assert differs == (alpha < 1.0)
