@@ -171,7 +171,8 @@ int stba_build_cluster_rcs(const stba_problem *p, const stba_dims *dims, const s
                            stba_rcs *out, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* Solve every S_k dc_k = b_k by dense FP64 Cholesky (Eq. 13; plus one FP64
- * refinement step in STBA_MIXED), then the point step
+ * refinement step in STBA_MIXED, against the copy of S_k that the last
+ * stba_build_cluster_rcs wrote beside it in the workspace), then the point step
  * dp_j = C_j^-1 (w_j - sum_o W_o^T dc) with the physical blocks (Eq. 15).
  * Jc, Jp: the Jacobian passed to stba_build_cluster_rcs.  dcam [m][9], dpt [n][3]
  * (device, FP64).  cluster_status (device int32 [l], nullable): STBA_OK or

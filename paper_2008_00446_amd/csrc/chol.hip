@@ -400,7 +400,7 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(int32_t l, const int32_t 
 // grid-wide abort word that ends all other waits (the cluster then reports
 // STBA_EHIP).  The row workers also run the forward substitution
 // y_i = W_ii (b_i - sum_{j < i} L_ij y_j) as a chain; the backward solve is a
-// separate kernel (k_trisolve).
+// separate kernel (k_sweep).
 // ---------------------------------------------------------------------------
 constexpr int kWaitPolls = 1 << 20;
 
@@ -705,148 +705,154 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void
 }
 
 // ---------------------------------------------------------------------------
-// Triangular solves with the factors of S_k (L in the lower tiles, W_pp^T in
-// the upper triangle of diagonal tile p, diagonal included), one workgroup per
-// cluster, right-looking: once block p of the solution is known, the right-hand
-// sides of all remaining blocks are updated at once, and every thread loads the
-// factor entries of its next step while the current step runs, so a step is two
-// barriers and two short dot products instead of a memory round trip.
+// Triangular sweeps with the factors of S_k (L in the lower tiles, W_pp^T in
+// the upper triangle of diagonal tile p, diagonal included), one 1024-thread
+// workgroup per cluster, right-looking: once block p of the solution is known,
+// the right-hand sides of all remaining blocks are updated at once.
 //   forward:  y_p = W_pp z_p,   z_i -= L_ip y_p   (i > p)
 //   backward: x_p = W_pp^T z_p, z_j -= L_pj^T x_p (j < p)
-// Threads 0..kTsUpd-1 update right-hand sides (output o keeps the same block
-// row across steps); the last wavefront applies the diagonal blocks.
-// Modes: kTsFromY: dcam = backward(y), y = the forward solution of the tile
-//   factorisation; kTsRefine (MIXED): dcam += backward(forward(r)) with r the
+// One workgroup alone pulls at most about 80 GB/s, so the sweep is bound by
+// streaming the factor (T (T + 1) / 2 tiles of 8 KB) through the CU.  The tiles
+// flow through a ring of kRing LDS slots in the order the sweep uses them
+// (step s: the diagonal tile, then the panel of step s), moved by load-to-LDS
+// instructions: wavefront w owns slot w, keeps one tile in flight and loads the
+// tile kRing further on as soon as the previous one has been used, so about
+// 128 KB stay in flight.  The tiles are used in segments of at most kSeg
+// tiles of one step: wait for the segment's tiles, the diagonal block (first
+// segment of a step), then the segment's panel updates, each output a dot
+// product of 32 shared by four lanes.
+// Column col of a tile occupies 256 bytes of its slot, its 16-byte part q (rows
+// 2q, 2q + 1) at position (q + col) mod 16: the 32 lanes that read one row of 32
+// columns, or 32 rows of one column, meet at most two to a bank.
+// Modes: kSwFromY: dcam = backward(y), y = the forward solution of the tile
+//   factorisation; kSwRefine (MIXED): dcam += backward(forward(r)) with r the
 //   residual b - S0 x from k_resid (one FP64 refinement step).
 // ---------------------------------------------------------------------------
-constexpr int kTsThreads = 512;
-constexpr int kTsUpd = kTsThreads - 64;
-constexpr int kTsFromY = 1, kTsRefine = 2;
+constexpr int kSwThreads = 1024;
+constexpr int kRing = kSwThreads / 64;             // one slot per wavefront
+constexpr int kSeg = 8;
+constexpr int kTileBytes = kNB * kNB * 8;
+constexpr int kSwFromY = 1, kSwRefine = 2;
+constexpr size_t kSwStaticLds = (size_t)kRing * kTileBytes + kNB * 8;
 
-// Workgroup barrier for data exchanged through LDS only: waits for this
-// wavefront's LDS operations, not for its global loads, so that loads issued for
-// a later step stay in flight across the barrier (__syncthreads would wait for
-// them).  The empty asm statements keep the compiler from moving memory
-// accesses across it.
-__device__ inline void lds_barrier() {
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0); vmcnt and expcnt untouched
-    __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");
+// element (row, col) of a tile in its ring slot
+__device__ inline int sw_at(int row, int col) { return col * 256 + ((((row >> 1) + col) & 15) << 4) + ((row & 1) << 3); }
+
+// tile t of the sweep sequence (T diagonal tiles; forward steps first in
+// refinement mode): block row a, block column b, step, index k in the step
+__device__ inline void sw_tile(int t, int T, bool refine, int *a, int *b, bool *fwd) {
+    const int n = T * (T + 1) / 2;
+    *fwd = refine && t < n;
+    if (refine && t >= n) t -= n;
+    int s = 0, off = 0;
+    while (off + (T - s) <= t) {
+        off += T - s;
+        ++s;
+    }
+    const int k = t - off;
+    if (*fwd) {            // step s: W_ss, then L_{s+k, s}
+        *a = k == 0 ? s : s + k;
+        *b = s;
+    } else {               // step s (block p = T-1-s): W_pp, then L_{p, k-1}
+        const int p = T - 1 - s;
+        *a = p;
+        *b = k == 0 ? p : k - 1;
+    }
 }
 
-// One sweep over the tiles; v (LDS) holds the right-hand side and receives the
-// solution; ys (LDS, 32) carries the block just solved.
+// wavefront-uniform: issue the eight 1 KB load-to-LDS instructions of tile t
+__device__ inline void sw_issue(const double *A, int64_t Np, int T, bool refine, int t, char *slot, int lane) {
+    int a, b;
+    bool fwd;
+    sw_tile(t, T, refine, &a, &b, &fwd);
+    const int sl = lane & 15;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int col = 4 * i + (lane >> 4);
+        const int q = (sl - col) & 15;   // part stored at position sl of column col
+        const double *src = A + (int64_t)a * kNB + 2 * q + ((int64_t)b * kNB + col) * Np;
+        __builtin_amdgcn_global_load_lds((const void *)src,
+                                         (void __attribute__((address_space(3))) *)(slot + i * 1024), 16, 0, 0);
+    }
+}
+
+// The diagonal block of a step: 32 outputs, one lane each (all 32 terms, four
+// partial sums), into xb.
 template <bool kFwd>
-__device__ __attribute__((always_inline)) inline void ts_sweep(const double *A, int64_t Np, int T, double *v, double *ys, int tid) {
-    const int r = tid & (kNB - 1);
-    const bool diag_wave = tid >= kTsUpd;
-    const int o = tid;   // update output (first one; more only for T > kTsUpd / 32 + 1)
-    double cur[kNB];
-    // prefetch for the first step
-    auto addr_upd = [&](int p, int oo) -> const double * {
-        if (kFwd) {   // z_i, i = T-1 - oo/32, row r: L(off_i + r, off_p + c) at + c * Np
-            const int i = T - 1 - oo / kNB;
-            return A + (int64_t)i * kNB + (oo & (kNB - 1)) + (int64_t)p * kNB * Np;
-        } else {      // z_j, j = oo/32, column c: L(off_p + rr, off_j + c) at + rr
-            const int j = oo / kNB;
-            return A + (int64_t)p * kNB + ((int64_t)j * kNB + (oo & (kNB - 1))) * Np;
-        }
-    };
-    auto addr_diag = [&](int p) -> const double * {
-        const int64_t off = (int64_t)p * kNB;
-        // forward: W[r][q] = D(q, r) at + q; backward: W^T[r][c] = D(r, c) at + c * Np
-        return kFwd ? A + off + (off + r) * Np : A + (off + r) + off * Np;
-    };
-    const int p0 = kFwd ? 0 : T - 1;
-    if (diag_wave) {
-        const double *d = addr_diag(p0);
+__device__ __forceinline__ void sw_diag(const char *d, const double *z, double *xb, int p, int tid) {
+    if (tid >= kNB) return;
+    int r = tid;
+    asm volatile("" : "+v"(r));   // opaque: the 32 addresses below are not hoisted out of the step loop
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int c = 0; c < kNB; ++c) cur[c] = kFwd ? d[c] : d[(int64_t)c * Np];
-    } else {
-        const int nact = kFwd ? (T - 1 - p0) * kNB : p0 * kNB;
-        if (o < nact) {
-            const double *u = addr_upd(p0, o);
+    for (int h = 0; h < 2; ++h) {   // two halves of 16 terms: the registers of a 1024-thread block are few
+        double dv[16], zv[16];
 #pragma unroll
-            for (int c = 0; c < kNB; ++c) cur[c] = kFwd ? u[(int64_t)c * Np] : u[c];
+        for (int m = 0; m < 16; ++m) {   // forward: W[r][c] = D(c, r); backward: W[c][r] = D(r, c)
+            const int c = 16 * h + m;
+            dv[m] = *reinterpret_cast<const double *>(d + (kFwd ? sw_at(c, r) : sw_at(r, c)));
+            zv[m] = z[p * kNB + c];
         }
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const int c = 16 * h + m;
+            const bool in = kFwd ? c <= r : c >= r;   // y_r = sum_{c <= r} W[r][c] z_c; x_r = sum_{c >= r} W[c][r] z_c
+            acc[m & 3] = fma(in ? dv[m] : 0.0, zv[m], acc[m & 3]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
     }
-    for (int step = 0; step < T; ++step) {
-        const int p = kFwd ? step : T - 1 - step;
-        const int pn = kFwd ? p + 1 : p - 1;   // next step's block
-        const int64_t off = (int64_t)p * kNB;
-        double nxt[kNB];
-        if (diag_wave) {
-            if (step + 1 < T) {
-                const double *d = addr_diag(pn);
-#pragma unroll
-                for (int c = 0; c < kNB; ++c) nxt[c] = kFwd ? d[c] : d[(int64_t)c * Np];
-            }
-            double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-            for (int c = 0; c < kNB; c += 2) {
-                const bool in0 = kFwd ? c <= r : c >= r, in1 = kFwd ? c + 1 <= r : c + 1 >= r;
-                s0 = fma(in0 ? cur[c] : 0.0, v[off + c], s0);
-                s1 = fma(in1 ? cur[c + 1] : 0.0, v[off + c + 1], s1);
-            }
-            if (tid < kTsUpd + kNB) ys[r] = s0 + s1;
-        } else {
-            const int nn = kFwd ? (T - 1 - pn) * kNB : pn * kNB;   // outputs of the next step
-            if (step + 1 < T && o < nn) {
-                const double *u = addr_upd(pn, o);
-#pragma unroll
-                for (int c = 0; c < kNB; ++c) nxt[c] = kFwd ? u[(int64_t)c * Np] : u[c];
-            }
-        }
-        lds_barrier();
-        if (diag_wave) {
-            if (tid < kTsUpd + kNB) v[off + r] = ys[r];
-        } else {
-            const int nact = kFwd ? (T - 1 - p) * kNB : p * kNB;
-            if (o < nact) {
-                double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-                for (int c = 0; c < kNB; c += 2) {
-                    s0 = fma(cur[c], ys[c], s0);
-                    s1 = fma(cur[c + 1], ys[c + 1], s1);
-                }
-                const int blk = kFwd ? T - 1 - o / kNB : o / kNB;
-                v[(int64_t)blk * kNB + (o & (kNB - 1))] -= s0 + s1;
-            }
-            for (int oo = o + kTsUpd; oo < nact; oo += kTsUpd) {   // clusters with many tiles
-                const double *u = addr_upd(p, oo);
-                double s = 0.0;
-                for (int c = 0; c < kNB; ++c) s = fma(kFwd ? u[(int64_t)c * Np] : u[c], ys[c], s);
-                const int blk = kFwd ? T - 1 - oo / kNB : oo / kNB;
-                v[(int64_t)blk * kNB + (oo & (kNB - 1))] -= s;
-            }
-        }
-        lds_barrier();
-        if (step + 1 < T) {
-#pragma unroll
-            for (int c = 0; c < kNB; ++c) cur[c] = nxt[c];
-        }
-    }
+    xb[r] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
-__global__ __launch_bounds__(kTsThreads) void k_trisolve(int mode, const int32_t *__restrict__ cl_n,
-                                                         const int32_t *__restrict__ cl_Np,
-                                                         const int64_t *__restrict__ S_off,
-                                                         const int32_t *__restrict__ cl_start,
-                                                         const int32_t *__restrict__ cl_cams,
-                                                         const double *__restrict__ S,
-                                                         const double *__restrict__ rhs, int32_t rstride,
-                                                         double *__restrict__ dcam, int32_t max_Np,
-                                                         int32_t *__restrict__ flags, int32_t fpc) {
-    extern __shared__ double smem[];
-    double *v = smem;               // max_Np
-    double *ys = v + max_Np;        // kNB
+// The panel tiles [kb, k1) of the step whose diagonal block is p (tile index k
+// >= 1 in the step): 8 tiles x 32 outputs x 4 lanes (8 of the 32 terms each).
+template <bool kFwd>
+__device__ __forceinline__ void sw_panel(const char *ring, double *z, const double *xb, int p, int kb, int k1, int t0,
+                                         int tid) {
+    int lt = tid;
+    asm volatile("" : "+v"(lt));   // opaque, as in sw_diag
+    const int g = lt >> 7, e = (lt >> 2) & 31, qq = lt & 3;
+    const int kk = kb + g;
+    double acc = 0.0;
+    const bool act = kk < k1;
+    if (act) {
+        const char *d = ring + (((t0 + kk) % kRing) * kTileBytes);
+        double lv[8], xv[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const int c = 8 * qq + m;
+            // forward, tile L_{p+kk, p}: z_{p+kk}[e] -= sum_c L(e, c) y_p[c];
+            // backward, tile L_{p, kk-1}: z_{kk-1}[e] -= sum_c L(c, e) x_p[c]
+            lv[m] = *reinterpret_cast<const double *>(d + (kFwd ? sw_at(e, c) : sw_at(c, e)));
+            xv[m] = xb[c];
+        }
+#pragma unroll
+        for (int m = 0; m < 8; ++m) acc = fma(lv[m], xv[m], acc);
+    }
+    acc += __shfl_xor(acc, 1, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    if (act && qq == 0) z[(kFwd ? p + kk : kk - 1) * kNB + e] -= acc;
+}
+
+__global__ __launch_bounds__(kSwThreads) void k_sweep(int mode, const int32_t *__restrict__ cl_n,
+                                                      const int32_t *__restrict__ cl_Np,
+                                                      const int64_t *__restrict__ S_off,
+                                                      const int32_t *__restrict__ cl_start,
+                                                      const int32_t *__restrict__ cl_cams,
+                                                      const double *__restrict__ S,
+                                                      const double *__restrict__ rhs, int32_t rstride,
+                                                      double *__restrict__ dcam, int32_t *__restrict__ flags,
+                                                      int32_t fpc) {
+    __shared__ __align__(16) char ring[kRing * kTileBytes];
+    __shared__ double xb[kNB];
+    extern __shared__ double z[];   // Np
     const int k = blockIdx.x;
     const int tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
     if (flags != nullptr) {
         // after the tile-parallel factorisation: clear its flag words (cluster k's
         // and the abort word) so that they are zero when the next one starts
-        for (int i = tid; i < fpc; i += kTsThreads) flags[(int64_t)k * fpc + i] = 0;
+        for (int i = tid; i < fpc; i += kSwThreads) flags[(int64_t)k * fpc + i] = 0;
         if (k == 0 && tid == 0) flags[(int64_t)gridDim.x * fpc] = 0;
     }
     const int nk = cl_n[k];
@@ -856,20 +862,62 @@ __global__ __launch_bounds__(kTsThreads) void k_trisolve(int mode, const int32_t
     const int T = (int)(Np / kNB);
     const double *A = S + S_off[k];
     const int c0 = cl_start[k];
-    for (int i = tid; i < Np; i += kTsThreads) v[i] = rhs[(int64_t)k * rstride + i];
+    const bool refine = mode == kSwRefine;
+    const int n1 = T * (T + 1) / 2;
+    const int ntiles = refine ? 2 * n1 : n1;
+    char *slot = ring + w * kTileBytes;
+    int mine = w;   // the tile this wavefront has in flight (or has landed)
+    if (mine < ntiles) sw_issue(A, Np, T, refine, mine, slot, lane);
+    for (int i = tid; i < Np; i += kSwThreads) z[i] = rhs[(int64_t)k * rstride + i];
+    // segments: (sweep, step s, tiles [k0, k1) of the step).  One barrier between
+    // segments: it publishes the previous segment's results and its end of use of
+    // the ring slots, and (after the owners' waits) the landing of this one's tiles.
+    int t0 = 0, pa = 0, pb = 0;   // the previous segment's tiles [pa, pb)
+    for (int sweep = 0; sweep < (refine ? 2 : 1); ++sweep) {
+        const bool fwd = refine && sweep == 0;
+        for (int s = 0; s < T; ++s) {
+            const int cnt = T - s;
+            const int p = fwd ? s : T - 1 - s;   // the diagonal block of the step
+            for (int k0 = 0; k0 < cnt; k0 += kSeg) {
+                const int k1 = min(cnt, k0 + kSeg);
+                const int ta = t0 + k0, tb = t0 + k1;
+                if (mine >= ta && mine < tb) __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): my tile landed
+                __syncthreads();
+                asm volatile("" ::"v"(ring) : "memory");
+                if (mine >= pa && mine < pb) {   // my previous tile is used: load the one kRing further
+                    mine += kRing;
+                    if (mine < ntiles) sw_issue(A, Np, T, refine, mine, slot, lane);
+                }
+                if (k0 == 0) {
+                    const char *dg = ring + ((t0 % kRing) * kTileBytes);
+                    if (fwd) sw_diag<true>(dg, z, xb, p, tid);
+                    else sw_diag<false>(dg, z, xb, p, tid);
+                    __syncthreads();
+                    if (tid >= kSwThreads - kNB) z[p * kNB + tid - (kSwThreads - kNB)] = xb[tid - (kSwThreads - kNB)];
+                }
+                const int kb = k0 == 0 ? 1 : k0;
+                if (fwd) sw_panel<true>(ring, z, xb, p, kb, k1, t0, tid);
+                else sw_panel<false>(ring, z, xb, p, kb, k1, t0, tid);
+                pa = ta;
+                pb = tb;
+            }
+            t0 += cnt;
+        }
+    }
     __syncthreads();
-    if (mode == kTsRefine) ts_sweep<true>(A, Np, T, v, ys, tid);
-    ts_sweep<false>(A, Np, T, v, ys, tid);
-    __syncthreads();
-    for (int i = tid; i < N; i += kTsThreads) {
+    for (int i = tid; i < N; i += kSwThreads) {
         double *d = dcam + 9 * (int64_t)cl_cams[c0 + i / 9] + i % 9;
-        *d = mode == kTsRefine ? *d + v[i] : v[i];
+        *d = refine ? *d + z[i] : z[i];
     }
 }
 
+
 // MIXED refinement residual r = b - S0 x for 32 rows of one cluster per
 // workgroup (x = the current dcam); S0 is symmetric with its lower triangle
-// stored.  8 threads per row, partial sums added in a fixed order.
+// stored.  Row i takes sum_{j <= i} S0(i, j) x_j along row i (32 rows of one
+// column at a time: consecutive addresses) plus sum_{j > i} S0(j, i) x_j down
+// column i (one wavefront per 8 columns, lanes down the column); every sum in
+// a fixed order.
 __global__ __launch_bounds__(256) void k_resid(int32_t nrb, const int32_t *__restrict__ cl_n,
                                                const int32_t *__restrict__ cl_Np,
                                                const int64_t *__restrict__ S_off,
@@ -894,14 +942,23 @@ __global__ __launch_bounds__(256) void k_resid(int32_t nrb, const int32_t *__res
     const double *A0 = S0 + S_off[k];
     const int rr = tid & (kNB - 1), g = tid >> 5;
     const int64_t i = (int64_t)rb * kNB + rr;
-    double s0 = 0.0, s1 = 0.0;
-    int64_t j = g;
-    for (; j <= i; j += 8) s0 = fma(A0[i + j * Np], x[j], s0);        // lower part of row i
-    for (; j < Np; j += 8) s1 = fma(A0[j + i * Np], x[j], s1);        // the rest by symmetry
-    red[g][rr] = s0 + s1;
+    double s0 = 0.0;
+    for (int64_t j = g; j <= i; j += 8) s0 = fma(A0[i + j * Np], x[j], s0);   // row i, columns j <= i
+    red[g][rr] = s0;
+    // column part: wavefront v takes columns rb*32 + 8v .. + 7
+    __shared__ double colp[kNB];
+    const int v = tid >> 6, lane = tid & 63;
+    for (int cc = 0; cc < 8; ++cc) {
+        const int64_t ic = (int64_t)rb * kNB + 8 * v + cc;
+        double s1 = 0.0;
+        for (int64_t j = ic + 1 + lane; j < Np; j += 64) s1 = fma(A0[j + ic * Np], x[j], s1);
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) s1 += __shfl_xor(s1, d, 64);
+        if (lane == 0) colp[8 * v + cc] = s1;
+    }
     __syncthreads();
     if (tid < kNB) {
-        double s = 0.0;
+        double s = colp[tid];
 #pragma unroll
         for (int gg = 0; gg < 8; ++gg) s += red[gg][tid];
         const int64_t row = (int64_t)rb * kNB + tid;
@@ -911,13 +968,6 @@ __global__ __launch_bounds__(256) void k_resid(int32_t nrb, const int32_t *__res
 }
 
 // S0 = S over the used part (S_off[l] entries)
-__global__ void k_copy_S(const double *__restrict__ S, double *__restrict__ S0, const int64_t *__restrict__ S_off,
-                         int32_t l) {
-    const int64_t n = S_off[l];
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        S0[i] = S[i];
-}
-
 __global__ void k_zero_flags(int32_t *flags, int64_t count) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
         flags[i] = 0;
@@ -966,9 +1016,9 @@ hipError_t launch_chol(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, con
         k_chol_tiles<<<(unsigned)((int64_t)l * wpc), 64, 0, st>>>(wpc, tmax, fpc, cl_n, cl_Np, S_off, cl_start, cl_cams,
                                                                  S, b, dcam, cl_status, flags, l, yx);
         // backward solve by one workgroup per cluster
-        const size_t shmem = sizeof(double) * ((size_t)max_Np + kNB);
-        k_trisolve<<<(unsigned)l, kTsThreads, shmem, st>>>(kTsFromY, cl_n, cl_Np, S_off, cl_start, cl_cams, S, yx,
-                                                           tmax * kNB, dcam, max_Np, flags, fpc);
+        if (kSwStaticLds + sizeof(double) * (size_t)max_Np > 160 * 1024) return hipErrorInvalidConfiguration;
+        k_sweep<<<(unsigned)l, kSwThreads, sizeof(double) * (size_t)max_Np, st>>>(
+            kSwFromY, cl_n, cl_Np, S_off, cl_start, cl_cams, S, yx, tmax * kNB, dcam, flags, fpc);
         if (S0) {
             const hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
@@ -987,15 +1037,6 @@ hipError_t launch_chol(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, con
     return hipGetLastError();
 }
 
-hipError_t launch_copy_S(const double *S, double *S0, const int64_t *S_off, int32_t l, int64_t S_cap,
-                        hipStream_t st) {
-    int64_t blocks = (S_cap + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
-    if (blocks < 1) blocks = 1;
-    k_copy_S<<<(unsigned)blocks, 256, 0, st>>>(S, S0, S_off, l);
-    return hipGetLastError();
-}
-
 hipError_t launch_clear_chol_flags(int32_t *flags, hipStream_t st) {
     const int64_t n = chol_flag_words();
     k_zero_flags<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(flags, n);
@@ -1008,9 +1049,9 @@ hipError_t launch_refine(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, c
     const int32_t nrb = max_Np / kNB;
     k_resid<<<(unsigned)((int64_t)l * nrb), 256, sizeof(double) * (size_t)max_Np, st>>>(
         nrb, cl_n, cl_Np, S_off, cl_start, cl_cams, S0, b, dcam, rbuf, max_Np);
-    const size_t shmem = sizeof(double) * ((size_t)max_Np + kNB);
-    k_trisolve<<<(unsigned)l, kTsThreads, shmem, st>>>(kTsRefine, cl_n, cl_Np, S_off, cl_start, cl_cams, S, rbuf,
-                                                       max_Np, dcam, max_Np, nullptr, 0);
+    if (kSwStaticLds + sizeof(double) * (size_t)max_Np > 160 * 1024) return hipErrorInvalidConfiguration;
+    k_sweep<<<(unsigned)l, kSwThreads, sizeof(double) * (size_t)max_Np, st>>>(
+        kSwRefine, cl_n, cl_Np, S_off, cl_start, cl_cams, S, rbuf, max_Np, dcam, nullptr, 0);
     return hipGetLastError();
 }
 

@@ -241,7 +241,10 @@ __global__ __launch_bounds__(256) void k_rj(int64_t q, const double *__restrict_
         int64_t total = z.S_off[z.l];
         if (total > z.S_cap) total = z.S_cap;
         const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) z.S[i] = 0.0;
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+            z.S[i] = 0.0;
+            if (z.S0 != nullptr) z.S0[i] = 0.0;
+        }
         for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < z.nb; i += stride) z.b[i] = 0.0;
     }
     if (need_jac != nullptr && need_jac[0] == 0) return;
@@ -664,13 +667,16 @@ __global__ void k_point_groups(int32_t n, const int64_t *__restrict__ pt_off, in
     if (jj == 0) grp_first[ngroups] = n;
 }
 
-// zero S (all clusters) and b
-__global__ __launch_bounds__(256) void k_zero_S(double *S, double *b, int32_t m, const int64_t *S_off, int32_t l,
-                                                int64_t S_cap) {
+// zero S (all clusters), S0 (if given) and b
+__global__ __launch_bounds__(256) void k_zero_S(double *S, double *S0, double *b, int32_t m, const int64_t *S_off,
+                                                int32_t l, int64_t S_cap) {
     int64_t total = S_off[l];
     if (total > S_cap) total = S_cap;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) S[i] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        S[i] = 0.0;
+        if (S0 != nullptr) S0[i] = 0.0;
+    }
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 9 * (int64_t)m; i += stride) b[i] = 0.0;
 }
 
@@ -940,10 +946,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         }
         if (slot >= 9) continue;
         if (nch == 1) {
-            double *A = S + S_off[kr];
-            const int64_t lr = cam_local[r];
-            const int64_t lc = cam_local[c];
-            double *colp = A + 9 * lr + (9 * lc + slot) * Np;
+            const int64_t at0 = S_off[kr] + 9 * (int64_t)cam_local[r] + (9 * (int64_t)cam_local[c] + slot) * Np;
+            double *colp = S + at0;
+            double *colp0 = ch.S0 != nullptr ? ch.S0 + at0 : nullptr;   // MIXED: the copy kept for refinement
             for (int i = i0; i < 5; ++i) {
                 const int e = e0 + i;
                 double v = (double)col[i];
@@ -953,6 +958,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                     v = -v;
                 }
                 colp[e] = v;
+                if (colp0 != nullptr) colp0[e] = v;
             }
             if (diag && slot == 0)
                 for (int i = i0; i < 5; ++i) b[9 * (int64_t)r + e0 + i] = -(double)rb[i];
@@ -986,7 +992,11 @@ __global__ __launch_bounds__(128) void k_schur_reduce(SchurChunks ch, const int6
     for (int32_t k = blockIdx.x; k < l; k += gridDim.x) {
         const int64_t Np = cl_Np[k];
         double *A = S + S_off[k];
-        for (int64_t i = 9 * (int64_t)cl_n[k] + t; i < Np; i += blockDim.x) A[i + i * Np] = 1.0;
+        double *A0 = ch.S0 != nullptr ? ch.S0 + S_off[k] : nullptr;
+        for (int64_t i = 9 * (int64_t)cl_n[k] + t; i < Np; i += blockDim.x) {
+            A[i + i * Np] = 1.0;
+            if (A0 != nullptr) A0[i + i * Np] = 1.0;
+        }
     }
     for (int64_t bk = blockIdx.x; bk < nb; bk += gridDim.x) {
         const int64_t c0 = ch.blk_chunk_off[bk];
@@ -1009,8 +1019,9 @@ __global__ __launch_bounds__(128) void k_schur_reduce(SchurChunks ch, const int6
                 for (int64_t j = 0; j < nch; ++j) dv += q[j * kSchurPart + 81 + e];
                 v += lam * dv;
             }
-            double *A = S + S_off[kr];
-            A[9 * cam_local[r] + e + (9 * (int64_t)cam_local[c] + k) * Np] = diag ? v : -v;
+            const int64_t at0 = S_off[kr] + 9 * cam_local[r] + e + (9 * (int64_t)cam_local[c] + k) * Np;
+            S[at0] = diag ? v : -v;
+            if (ch.S0 != nullptr) ch.S0[at0] = diag ? v : -v;
         } else {
             const int e = t - 81;
             double v = 0.0;
@@ -1311,12 +1322,12 @@ hipError_t launch_point_groups(int32_t n, const int64_t *pt_off, int32_t group_s
     return hipGetLastError();
 }
 
-hipError_t launch_fill_S(double *S, double *b, int32_t m, const int64_t *S_off, int32_t l, int64_t S_cap,
+hipError_t launch_fill_S(double *S, double *S0, double *b, int32_t m, const int64_t *S_off, int32_t l, int64_t S_cap,
                          hipStream_t st) {
     int64_t blocks = (S_cap + 1023) / 1024;
     if (blocks > 8192) blocks = 8192;
     if (blocks < 1) blocks = 1;
-    k_zero_S<<<(unsigned)blocks, 256, 0, st>>>(S, b, m, S_off, l, S_cap);
+    k_zero_S<<<(unsigned)blocks, 256, 0, st>>>(S, S0, b, m, S_off, l, S_cap);
     return hipGetLastError();
 }
 

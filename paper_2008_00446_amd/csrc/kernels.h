@@ -40,9 +40,11 @@ hipError_t launch_clusters(const int32_t *cam_cluster, int32_t m, int32_t l, int
                            int32_t *cl_n, int32_t *cl_Np, int32_t *cl_start, int32_t *cl_cams,
                            int32_t *cam_local, int64_t *S_off, int32_t *status, hipStream_t st);
 
-// S (nullable): also zero S (the first min(S_off[l], S_cap) doubles) and b (nb doubles)
+// S (nullable): also zero S (the first min(S_off[l], S_cap) doubles), S0 (if
+// given, the same extent) and b (nb doubles)
 struct ZeroS {
     double *S = nullptr;
+    double *S0 = nullptr;
     const int64_t *S_off = nullptr;
     int32_t l = 0;
     int64_t S_cap = 0;
@@ -71,8 +73,8 @@ hipError_t launch_point_groups(int32_t n, const int64_t *pt_off, int32_t group_s
                                int32_t *grp_first, hipStream_t st);
 inline int32_t point_group_size(int32_t max_track) { return max_track <= 32 ? 65 - max_track : 0; }
 
-// zero S and b
-hipError_t launch_fill_S(double *S, double *b, int32_t m, const int64_t *S_off, int32_t l, int64_t S_cap,
+// zero S, S0 (nullable) and b
+hipError_t launch_fill_S(double *S, double *S0, double *b, int32_t m, const int64_t *S_off, int32_t l, int64_t S_cap,
                          hipStream_t st);
 
 struct SchurChunks {
@@ -81,6 +83,7 @@ struct SchurChunks {
     const int32_t *chunk_blk;
     int64_t chunk_cap;
     double *part;          // partial sums, kSchurPart doubles per chunk
+    double *S0 = nullptr;  // MIXED: every entry written to S is written here too (kept for refinement)
 };
 template <typename T>
 hipError_t launch_schur(const int64_t *n_blocks, int64_t n_blocks_cap, const SchurChunks &ch, const int2 *blk_key,
@@ -109,10 +112,8 @@ hipError_t launch_chol(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, con
                        double *dcam, int32_t *cl_status, int32_t max_Np, int32_t *flags, double *yx,
                        const double *S0, double *rbuf, hipStream_t st);
 
-// MIXED precision: S0 = S before the factorisation, then one FP64 refinement
-// step of dcam against S0 with the factors.
-hipError_t launch_copy_S(const double *S, double *S0, const int64_t *S_off, int32_t l, int64_t S_cap,
-                         hipStream_t st);
+// MIXED precision: one FP64 refinement step of dcam against S0 (the assembled
+// S, written alongside it by the assembly) with the factors.
 hipError_t launch_refine(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, const int64_t *S_off,
                          const int32_t *cl_start, const int32_t *cl_cams, const double *S, const double *S0,
                          const double *b, double *dcam, double *rbuf, int32_t max_Np, hipStream_t st);

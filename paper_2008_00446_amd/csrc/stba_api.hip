@@ -18,6 +18,7 @@ struct Layout {
     // per iteration
     size_t cl_n, cl_Np, cl_start, cl_cams, cam_local, cl_status, S_off;
     size_t f, Jc, Jp, seg_head, seg_rec, grp_first, obsd, Vinv, wph, S, S0, rres, b, dcam, dpt, partials, chol_flags, chol_yx;
+    bool mixed = false;   // S0 and rres exist
     int64_t S_cap, n_partials;
     int32_t group_size;
     int32_t max_Np;
@@ -119,7 +120,8 @@ bool make_layout(const stba_problem *p, const stba_dims *d, int precision, Layou
     L.S_cap = s_capacity(p->m, d->gamma_max);
     L.S = take(8 * (size_t)L.S_cap);
     // MIXED keeps the assembled S for the refinement step
-    L.S0 = precision == STBA_MIXED ? take(8 * (size_t)L.S_cap) : 0;
+    L.mixed = precision == STBA_MIXED;
+    L.S0 = L.mixed ? take(8 * (size_t)L.S_cap) : 0;
     L.rres = precision == STBA_MIXED ? take(8 * m * (size_t)L.max_Np) : 0;
     L.b = take(8 * 9 * m);
     L.dcam = take(8 * 9 * m);
@@ -171,6 +173,7 @@ SchurChunks chunks_of(const Layout &L, void *ws) {
     c.chunk_blk = at<int32_t>(ws, L.chunk_blk);
     c.chunk_cap = L.chunk_cap;
     c.part = at<double>(ws, L.part);
+    c.S0 = L.mixed ? at<double>(ws, L.S0) : nullptr;
     return c;
 }
 
@@ -185,8 +188,8 @@ int build_rcs_impl(const stba_problem *p, const stba_dims *d, const stba_sample 
                               keep_threshold(s->alpha), at<int32_t>(ws, L.seg_head), at<double>(ws, L.seg_rec), at<T>(ws, L.obsd),
                               at<double>(ws, L.Vinv), at<double>(ws, L.wph), status, L.group_size,
                               at<int32_t>(ws, L.grp_first), st));
-    STBA_HIP(launch_fill_S(at<double>(ws, L.S), at<double>(ws, L.b), p->m, at<int64_t>(ws, L.S_off), s->l, L.S_cap,
-                           st));
+    STBA_HIP(launch_fill_S(at<double>(ws, L.S), L.mixed ? at<double>(ws, L.S0) : nullptr, at<double>(ws, L.b), p->m,
+                           at<int64_t>(ws, L.S_off), s->l, L.S_cap, st));
     STBA_HIP(launch_schur<T>(at<int64_t>(ws, L.n_blocks), L.blk_cap, chunks_of(L, ws), at<int2>(ws, L.blk_key),
                              at<int64_t>(ws, L.blk_start), at<uint64_t>(ws, L.pairs), s->cam_cluster, s->l,
                              at<int32_t>(ws, L.cam_local), at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np),
@@ -200,9 +203,8 @@ int build_rcs_impl(const stba_problem *p, const stba_dims *d, const stba_sample 
 // step against the assembled S.
 template <typename T>
 int cluster_solve(int32_t l, double *dcam, int32_t *cl_status, const Layout &L, void *ws, hipStream_t st) {
+    // MIXED: S0, the copy of S kept for the refinement step, was written by the assembly
     const bool mixed = sizeof(T) == sizeof(float);
-    if (mixed)
-        STBA_HIP(launch_copy_S(at<double>(ws, L.S), at<double>(ws, L.S0), at<int64_t>(ws, L.S_off), l, L.S_cap, st));
     STBA_HIP(launch_chol(l, at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np), at<int64_t>(ws, L.S_off),
                          at<int32_t>(ws, L.cl_start), at<int32_t>(ws, L.cl_cams), at<double>(ws, L.S),
                          at<double>(ws, L.b), dcam, cl_status, L.max_Np, at<int32_t>(ws, L.chol_flags),
@@ -238,6 +240,7 @@ int lm_step_impl(const stba_problem *p, const stba_dims *d, const stba_sample *s
     STBA_TRY(mark(1));
     ZeroS z;   // S and b are zeroed by the residual kernel's grid
     z.S = at<double>(ws, L.S);
+    z.S0 = L.mixed ? at<double>(ws, L.S0) : nullptr;
     z.S_off = at<int64_t>(ws, L.S_off);
     z.l = s->l;
     z.S_cap = L.S_cap;
