@@ -67,7 +67,7 @@ def parse_args():
     ap.add_argument("--pmc-summary", action="store_true",
                     help="write a profiles/pmc_*.txt summary from counter CSVs (no GPU work)")
     ap.add_argument("--phase", default="cluster_cholesky")
-    ap.add_argument("--kernels", default="k_chol_tiles,k_trisolve",
+    ap.add_argument("--kernels", default="k_chol_tiles,k_sweep",
                     help="comma-separated kernel name fragments belonging to --phase")
     ap.add_argument("--fetch-csv")
     ap.add_argument("--write-csv")

@@ -30,6 +30,16 @@ __device__ inline double readlane_d(double v, int l) {
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+// 1 / sqrt(d) from v_rsq_f64 (about 24 correct bits) and one Newton step: relative error near
+// 2^-47, below the rounding that a column of 32 or more products already
+// carries; used on the diagonal chain of the tile factorisation, where every
+// dependent operation costs about 32 cycles.
+__device__ inline double rsqrt_once(double d) {
+    const double h = 0.5 * d;
+    const double y = __builtin_amdgcn_rsq(d);
+    return fma(y, fma(-h * y, y, 0.5), y);
+}
+
 // 1 / sqrt(d): the hardware estimate and two Newton steps y += y (1/2 - d y^2 / 2),
 // each of which squares the relative error; a shorter dependent chain than a
 // correctly rounded square root followed by a division.
@@ -150,7 +160,7 @@ __device__ __forceinline__ bool band_factor_invert(double *A, int64_t Np, int64_
         bad = true;
         d = 1.0;
     }
-    double is = rsqrt_refined(d);
+    double is = rsqrt_once(d);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int k = 0; k < kNB; ++k) {
@@ -173,7 +183,7 @@ __device__ __forceinline__ bool band_factor_invert(double *A, int64_t Np, int64_
                 bad = true;
                 dn = 1.0;
             }
-            const double is_next = rsqrt_refined(dn);
+            const double is_next = rsqrt_once(dn);
 #pragma unroll
             for (int j = k + 1; j < kNB; ++j) v[j] = fma(-v[k], lc[j], v[j]);
 #pragma unroll

@@ -318,7 +318,9 @@ def test_full_size_ring_iteration_matches_oracle():
     sol.step(sol.sample(lab, alpha=1.0, seed=0, it=0))
     st = sol.read_state()
     ref = O.lm_iteration(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv, lab, 1e-4, 1.0, 0, 0)
-    print(f"ring: accepted {st['accepted']} F_new {st['F_new']:.12e} oracle {ref.F_new:.12e}")
+    print(f"ring: accepted {st['accepted']} F_new {st['F_new']:.12e} oracle {ref.F_new:.12e} "
+          f"dcam {rel(sol.cam.cpu().numpy() - s.cam0, ref.cam - s.cam0):.2e} "
+          f"dpt {rel(sol.pt.cpu().numpy() - s.pt0, ref.pt - s.pt0):.2e}")
     assert st["status"] == 0
     assert bool(st["accepted"]) == ref.accepted
     assert abs(st["F_new"] - ref.F_new) <= 1e-9 * ref.F_new
