@@ -408,9 +408,18 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(int32_t l, const int32_t 
 // to an earlier diagonal step, so with all wavefronts resident the dataflow
 // cannot deadlock; every wait is still bounded, and a time-out raises a
 // grid-wide abort word that ends all other waits (the cluster then reports
-// STBA_EHIP).  The row workers also run the forward substitution
-// y_i = W_ii (b_i - sum_{j < i} L_ij y_j) as a chain; the backward solve is a
-// separate kernel (k_sweep).
+// STBA_EHIP).  The row workers then run the substitutions as chains over the
+// blocks, each block vector handed on as soon as it is known:
+//   forward   y_i = W_ii (b_i - sum_{j < i} L_ij y_j),
+//   backward  x_i = W_ii^T (y_i - sum_{j > i} L_ji^T x_j),
+// and with S0 (MIXED) one FP64 refinement step against the assembled matrix:
+//   r_i = b_i - sum_j S0_ij x_j (summed while the x_j arrive),
+//   forward d from r, backward e from d, and dcam = x + e.
+// A block vector goes to the other row workers through memory: its entries
+// start as kEmpty and a reader polls the 32 entries themselves, so a hand-over
+// costs one store and the reader's next poll.  The last wavefront of a cluster
+// to finish writes the cluster's status and returns its flag words and vector
+// entries to their initial state for the next factorisation.
 // ---------------------------------------------------------------------------
 constexpr int kWaitPolls = 1 << 20;
 
@@ -437,6 +446,30 @@ __device__ inline int wait_flag(const int32_t *f, int32_t *abort_w) {
     v = __shfl(v, 0, 64);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     return v;
+}
+
+// The entries of the block vectors that row workers hand to each other start
+// as this signalling NaN.  Arithmetic never yields it (a NaN result is quiet),
+// so an entry that differs from it has been published.
+constexpr long long kEmpty = 0x7FF4535442410000ll;
+
+// Every lane: entry (lane mod 32) of the 32-vector v once all 32 entries have
+// been published by another wavefront.  Bounded like wait_flag; on time-out or
+// abort it returns 0 and clears ok.
+__device__ inline double wait_vec(const double *v, int32_t *abort_w, bool &ok) {
+    const int lane = threadIdx.x & 63;
+    const double *p = v + (lane & (kNB - 1));
+    for (int it = 0; it < kWaitPolls; ++it) {
+        const double x = ld_dev(p);
+        if (__ballot(__double_as_longlong(x) != kEmpty) == ~0ull) return x;
+        int a = 0;
+        if (lane == 0) a = __hip_atomic_load(abort_w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (__shfl(a, 0, 64) != 0) break;
+        __builtin_amdgcn_s_sleep(1);
+    }
+    if (lane == 0) __hip_atomic_store(abort_w, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    ok = false;
+    return 0.0;
 }
 
 // Raise *f = v after all earlier stores of the wavefront have completed.
@@ -547,6 +580,132 @@ __device__ inline void load_tile_dev(const double *A, int64_t Np, int64_t ri, in
                 acc[R][C][v] = ld_dev(A + (ri + 16 * R + lr) + (cj + 16 * C + 4 * v + lk) * Np);
 }
 
+// Row-worker chains.  Lane (r, h) = (lane mod 32, lane / 32) holds entry r of
+// a block vector and columns hc = 16 h .. 16 h + 15 of a tile, so a 32 x 32
+// block product is two 16-term partial sums per entry, added across the halves.
+
+// t[m] = A(r0, c0 + m): along a row (the lanes of a half read 32 consecutive
+// rows of one column at a time).  kDev: device-scope loads (tiles written by
+// other wavefronts of this kernel).
+template <bool kDev>
+__device__ inline void ld_row16(const double *A, int64_t Np, int64_t r0, int64_t c0, double (&t)[16]) {
+#pragma unroll
+    for (int m = 0; m < 16; ++m) t[m] = kDev ? ld_dev(A + r0 + (c0 + m) * Np) : A[r0 + (c0 + m) * Np];
+}
+
+// t[m] = A(r0 + m, c0): 16 consecutive entries down a column
+template <bool kDev>
+__device__ inline void ld_col16(const double *A, int64_t Np, int64_t r0, int64_t c0, double (&t)[16]) {
+#pragma unroll
+    for (int m = 0; m < 16; ++m) t[m] = kDev ? ld_dev(A + r0 + m + c0 * Np) : A[r0 + m + c0 * Np];
+}
+
+// sum_m t[m] z[m] in a fixed order (four partial sums)
+__device__ inline double dot16(const double (&t)[16], const double *z) {
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int m = 0; m < 16; ++m) a[m & 3] = fma(t[m], z[m], a[m & 3]);
+    return (a[0] + a[1]) + (a[2] + a[3]);
+}
+
+// the two halves' partial sums of entry r (the same value in lanes r and r + 32)
+__device__ inline double halves(double s) { return s + __shfl_xor(s, 32, 64); }
+
+// W_ii = L_ii^-1 from the final diagonal tile D (W^T in its upper triangle,
+// diagonal included), zero outside the triangle, for the forward product
+// y_r = sum_{q <= r} W[r][q] z_q, W[r][q] = D(q, r), or the backward one
+// x_r = sum_{q >= r} W[q][r] z_q, W[q][r] = D(r, q).
+template <bool kFwd>
+__device__ inline void ld_w16(const double *A, int64_t Np, int64_t ri, int r, int hc, double (&w)[16]) {
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        const int q = hc + m;
+        const double v = kFwd ? ld_dev(A + ri + q + (ri + r) * Np) : ld_dev(A + ri + r + (ri + q) * Np);
+        w[m] = (kFwd ? q <= r : q >= r) ? v : 0.0;
+    }
+}
+
+__device__ inline void publish(double *v, double x, int lane) {
+    if (lane < kNB) st_dev(v + lane, x);
+}
+
+// Forward chain, block i: v_i = W_ii (rhs - sum_{j < i} L_ij v_j), published
+// to v (blocks of 32).  Every tile of block row i is final; w from ld_w16<true>.
+// The tile of the next step is loaded while the current v_j is awaited.
+__device__ __forceinline__ double fwd_chain(const double *A, int64_t Np, int i, int r, int hc, double rhs,
+                                            const double (&w)[16], double *v, double *zs, int lane,
+                                            int32_t *abort_w, bool &ok) {
+    const int64_t ri = (int64_t)i * kNB;
+    double s = 0.0;
+    double t[16], tn[16];
+    ld_row16<true>(A, Np, ri + r, hc, t);
+    for (int j = 0; j < i; ++j) {
+        // at j + 1 == i: columns of the diagonal tile (in bounds, not used)
+        ld_row16<true>(A, Np, ri + r, (int64_t)(j + 1) * kNB + hc, tn);
+        share32(zs, wait_vec(v + (int64_t)j * kNB, abort_w, ok), lane);
+        s += dot16(t, zs + hc);
+#pragma unroll
+        for (int m = 0; m < 16; ++m) t[m] = tn[m];
+    }
+    share32(zs, rhs - halves(s), lane);
+    const double y = halves(dot16(w, zs + hc));
+    publish(v + ri, y, lane);
+    return y;
+}
+
+// Backward chain, block i: v_i = W_ii^T (rhs - sum_{j > i} L_ji^T v_j),
+// published to v; every tile is final; w from ld_w16<false>.  kRes: also
+// res += sum_{j > i} S0_ij v_j, S0_ij = S0_ji^T read from the lower triangle
+// of S0 at A0 (the part of the refinement residual from the blocks below).
+template <bool kRes>
+__device__ __forceinline__ double bwd_chain(const double *A, const double *A0, int64_t Np, int T, int i, int r,
+                                            int hc, double rhs, const double (&w)[16], double *v, double *zs,
+                                            int lane, int32_t *abort_w, bool &ok, double &res) {
+    const int64_t ri = (int64_t)i * kNB;
+    double s = 0.0;
+    double t[16], tn[16];
+    // tile (T-1, i) (for i == T-1 the diagonal tile: in bounds, not used)
+    ld_col16<true>(A, Np, (int64_t)(T - 1) * kNB + hc, ri + r, t);
+    for (int j = T - 1; j > i; --j) {
+        double u[16];   // S0 is not written by this kernel: loaded at the step, in flight during the wait
+        if (kRes) ld_col16<false>(A0, Np, (int64_t)j * kNB + hc, ri + r, u);
+        ld_col16<true>(A, Np, (int64_t)(j - 1) * kNB + hc, ri + r, tn);
+        share32(zs, wait_vec(v + (int64_t)j * kNB, abort_w, ok), lane);
+        s += dot16(t, zs + hc);
+        if (kRes) res += dot16(u, zs + hc);
+#pragma unroll
+        for (int m = 0; m < 16; ++m) t[m] = tn[m];
+    }
+    share32(zs, rhs - halves(s), lane);
+    const double x = halves(dot16(w, zs + hc));
+    publish(v + ri, x, lane);
+    return x;
+}
+
+// The rest of the refinement residual of block i once x_i is known:
+// res += S0_ii x_i + sum_{j < i} S0_ij x_j (the x_j awaited as they come).
+__device__ __forceinline__ void resid_rest(const double *A0, int64_t Np, int i, int r, int hc, double x,
+                                           const double *xv, double *zs, int lane, int32_t *abort_w, bool &ok,
+                                           double &res) {
+    const int64_t ri = (int64_t)i * kNB;
+    double u[16], un[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {   // S0_ii from its lower triangle
+        const int c = hc + m;
+        u[m] = c <= r ? A0[ri + r + (ri + c) * Np] : A0[ri + c + (ri + r) * Np];
+    }
+    share32(zs, x, lane);
+    res += dot16(u, zs + hc);
+    ld_row16<false>(A0, Np, ri + r, (int64_t)max(i - 1, 0) * kNB + hc, u);
+    for (int j = i - 1; j >= 0; --j) {
+        ld_row16<false>(A0, Np, ri + r, (int64_t)max(j - 1, 0) * kNB + hc, un);
+        share32(zs, wait_vec(xv + (int64_t)j * kNB, abort_w, ok), lane);
+        res += dot16(u, zs + hc);
+#pragma unroll
+        for (int m = 0; m < 16; ++m) u[m] = un[m];
+    }
+}
+
 // Wavefront roles per cluster (wave w of the cluster's wpc wavefronts):
 //   w = 0, the band worker: the whole diagonal chain.  Step i takes the partial
 //     tiles P_i,i-1 and P_ii (all updates but the last applied), solves the panel
@@ -555,34 +714,29 @@ __device__ inline void load_tile_dev(const double *A, int64_t Np, int64_t ri, in
 //     diagonal tile; no hand-over between wavefronts lies on this chain.
 //   w = 1 + i, row worker i: applies A_ii -= L_ip L_ip^T and
 //     A_i,i-1 -= L_ip L_i-1,p^T for p <= i - 2 as the panels become final,
-//     publishes the partial tiles, then runs the forward chain
-//     y_i = W_ii (b_i - sum_{j < i} L_ij y_j).
+//     publishes the partial tiles, then runs the chains of block i.
 //   w > tmax, one wavefront per tile (i, j), j <= i - 2.
-// Flags per cluster: [tile (i, j) final at i (i + 1) / 2 + j][y_i at tt + i]
-// [partial tiles of row i at tt + tmax + i], tt = tmax (tmax + 1) / 2; diagonal
-// tile flags are 1 (final) or 2 (final, pivot failed).  The word after the last
-// cluster is the abort word.
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_chol_tiles(
-    int32_t wpc, int32_t tmax, int32_t fpc, const int32_t *__restrict__ cl_n, const int32_t *__restrict__ cl_Np,
-    const int64_t *__restrict__ S_off, const int32_t *__restrict__ cl_start, const int32_t *__restrict__ cl_cams,
-    double *__restrict__ S, const double *__restrict__ b, double *__restrict__ dcam, int32_t *__restrict__ cl_status,
-    int32_t *flags, int32_t l, double *yx) {
-    __shared__ double Wi[kNB][kNB + 1];
-    __shared__ double Ls[kNB][kNB + 1];
-    __shared__ __align__(16) double zs[2 * kNB];
+// Flags per cluster (fpc words): [tile (i, j) final at i (i + 1) / 2 + j]
+// [partial tiles of row i at tt + i][error word at tt + tmax][finished
+// wavefronts at tt + tmax + 1], tt = tmax (tmax + 1) / 2; diagonal tile flags
+// are 1 (final) or 2 (final, pivot failed).  After the last cluster: the abort
+// word, then the count of finished clusters.  Block vectors per cluster (yx):
+// y, x, d, e, tmax blocks of 32 each.
+constexpr int kVecSets = 4;
+
+// One wavefront's part; false if one of its waits failed.
+__device__ __forceinline__ bool chol_tiles_wave(int w, int k, int32_t tmax, int32_t fpc, const int32_t *cl_n,
+                                                const int32_t *cl_Np, const int64_t *S_off, const int32_t *cl_start,
+                                                const int32_t *cl_cams, double *S, const double *b, double *dcam,
+                                                int32_t *flags, int32_t l, double *yx, const double *S0,
+                                                double (*Wi)[kNB + 1], double (*Ls)[kNB + 1], double *zs) {
     const int lane = threadIdx.x;
-    const int k = (int)(blockIdx.x / (unsigned)wpc);
-    const int w = (int)(blockIdx.x - (unsigned)k * (unsigned)wpc);
     const int64_t Np = cl_Np[k];
     const int T = (int)(Np / kNB);
-    if (T == 0) {
-        if (w == 0 && lane == 0) cl_status[k] = STBA_OK;
-        return;
-    }
+    if (T == 0) return true;
     const int tt = tmax * (tmax + 1) / 2;
     int32_t *fl = flags + (int64_t)k * fpc;
-    int32_t *fl_y = fl + tt;
-    int32_t *fl_part = fl + tt + tmax;
+    int32_t *fl_part = fl + tt;
     int32_t *abort_w = flags + (int64_t)l * fpc;
     double *A = S + S_off[k];
     const int lr = lane & 15, lk = lane >> 4;
@@ -595,7 +749,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void
         while (i2 * (i2 + 1) / 2 > g) --i2;
         const int j = g - i2 * (i2 + 1) / 2;
         const int i = i2 + 2;
-        if (i >= T) return;
+        if (i >= T) return true;
         const int64_t ri = (int64_t)i * kNB, cj = (int64_t)j * kNB;
         d4 acc[2][2];
         load_tile(A, Np, ri, cj, lr, lk, acc);
@@ -612,8 +766,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void
         panel_solve(acc, A + cj + cj * Np, Np, lr, lk, x);
         store_tile_dev(A, Np, ri, cj, lr, lk, x);
         raise_flag(fl + tile_ix(i, j), 1);
-        if (!ok && lane == 0) cl_status[k] = STBA_EHIP;
-        return;
+        return ok;
     }
     if (w == 0) {
         // band worker
@@ -647,12 +800,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void
             const bool bad = band_factor_invert(A, Np, ri, lane, Ls, Wi, zs);
             raise_flag(fl + tile_ix(i, i), bad ? 2 : 1);
         }
-        if (!ok && lane == 0) cl_status[k] = STBA_EHIP;
-        return;
+        return ok;
     }
     // row worker i
     const int i = w - 1;
-    if (i >= T) return;
+    if (i >= T) return true;
     const int64_t ri = (int64_t)i * kNB;
     {
         d4 accD[2][2], accP[2][2];
@@ -671,46 +823,107 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void
         if (i >= 1) store_tile_dev(A, Np, ri, ri - kNB, lr, lk, accP);
         raise_flag(fl_part + i, 1);
     }
-    // forward: y_i = W_ii (b_i - sum_j L_ij y_j); lane r (and r + 32) holds entry r
     const int r = lane & (kNB - 1);
+    const int hc = 16 * (lane >> 5);
     const int N = 9 * cl_n[k];
     const int c0 = cl_start[k];
-    double *yv = yx + (int64_t)k * tmax * kNB;   // y_0 .. y_{T-1}
+    const int64_t vs = (int64_t)tmax * kNB;
+    double *yv = yx + (int64_t)k * kVecSets * vs;
+    double *xv = yv + vs, *dv = xv + vs, *ev = dv + vs;
     const int64_t row = ri + r;
-    double z = row < N ? b[9 * (int64_t)cl_cams[c0 + row / 9] + row % 9] : 0.0;
-    for (int jj = 0; jj < i; ++jj) {
-        ok &= wait_flag(fl_y + jj, abort_w) != 0;
-        const double *L = A + ri + r + (int64_t)jj * kNB * Np;
-        double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-        for (int c = 0; c < kNB; c += 2) {
-            s0 = fma(ld_dev(L + (int64_t)c * Np), ld_dev(yv + jj * kNB + c), s0);
-            s1 = fma(ld_dev(L + (int64_t)(c + 1) * Np), ld_dev(yv + jj * kNB + c + 1), s1);
-        }
-        z -= s0 + s1;
+    const int64_t drow = row < N ? 9 * (int64_t)cl_cams[c0 + row / 9] + row % 9 : 0;
+    const double bi = row < N ? b[drow] : 0.0;
+    // forward: y_i = W_ii (b_i - sum_{j < i} L_ij y_j).  Tiles (i, j), j <= i - 2,
+    // were awaited above; tile (i, i - 1) is the band worker's panel.
+    double s = 0.0;
+    for (int j = 0; j < i; ++j) {
+        if (j == i - 1) ok &= wait_flag(fl + tile_ix(i, i - 1), abort_w) != 0;
+        double t[16];
+        ld_row16<true>(A, Np, row, (int64_t)j * kNB + hc, t);
+        share32(zs, wait_vec(yv + (int64_t)j * kNB, abort_w, ok), lane);
+        s += dot16(t, zs + hc);
     }
-    share32(zs, z, lane);
     ok &= wait_flag(fl + tile_ix(i, i), abort_w) != 0;
-    // W[r][q] = W^T[q][r], the upper triangle of the final diagonal tile
-    const double *D = A + ri + (ri + r) * Np;
-    double y0 = 0.0, y1 = 0.0;
-#pragma unroll
-    for (int q = 0; q < kNB; q += 2) {
-        const double w0 = ld_dev(D + q), w1 = ld_dev(D + q + 1);
-        y0 = fma(q <= r ? w0 : 0.0, zs[q], y0);
-        y1 = fma(q + 1 <= r ? w1 : 0.0, zs[q + 1], y1);
+    double y;
+    {
+        double wf[16];
+        ld_w16<true>(A, Np, ri, r, hc, wf);
+        share32(zs, bi - halves(s), lane);
+        y = halves(dot16(wf, zs + hc));
     }
-    if (lane < kNB) st_dev(yv + ri + r, y0 + y1);
-    raise_flag(fl_y + i, 1);
-    // y_{T-1} depends on every tile of the cluster: all pivots are known here
-    if (i == T - 1 && lane == 0) {
+    publish(yv + ri, y, lane);
+    // backward: x_i = W_ii^T (y_i - sum_{j > i} L_ji^T x_j); the last diagonal
+    // tile is final only after every other tile
+    ok &= wait_flag(fl + tile_ix(T - 1, T - 1), abort_w) != 0;
+    double wb[16];
+    ld_w16<false>(A, Np, ri, r, hc, wb);
+    double res = 0.0;
+    if (S0 == nullptr) {
+        const double x = bwd_chain<false>(A, nullptr, Np, T, i, r, hc, y, wb, xv, zs, lane, abort_w, ok, res);
+        if (lane < kNB && row < N) dcam[drow] = x;
+        return ok;
+    }
+    // MIXED: r_i = b_i - sum_j S0_ij x_j, then L L^T e = r and dcam = x + e
+    const double *A0 = S0 + S_off[k];
+    const double x = bwd_chain<true>(A, A0, Np, T, i, r, hc, y, wb, xv, zs, lane, abort_w, ok, res);
+    double wf[16];   // loaded again, in flight while the residual completes
+    ld_w16<true>(A, Np, ri, r, hc, wf);
+    resid_rest(A0, Np, i, r, hc, x, xv, zs, lane, abort_w, ok, res);
+    const double d = fwd_chain(A, Np, i, r, hc, bi - halves(res), wf, dv, zs, lane, abort_w, ok);
+    const double e = bwd_chain<false>(A, nullptr, Np, T, i, r, hc, d, wb, ev, zs, lane, abort_w, ok, res);
+    if (lane < kNB && row < N) dcam[drow] = x + e;
+    return ok;
+}
+
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_chol_tiles(
+    int32_t wpc, int32_t tmax, int32_t fpc, const int32_t *__restrict__ cl_n, const int32_t *__restrict__ cl_Np,
+    const int64_t *__restrict__ S_off, const int32_t *__restrict__ cl_start, const int32_t *__restrict__ cl_cams,
+    double *__restrict__ S, const double *__restrict__ b, double *__restrict__ dcam, int32_t *__restrict__ cl_status,
+    int32_t *flags, int32_t l, double *yx, const double *__restrict__ S0) {
+    __shared__ double Wi[kNB][kNB + 1];
+    __shared__ double Ls[kNB][kNB + 1];
+    __shared__ __align__(16) double zs[2 * kNB];
+    const int lane = threadIdx.x;
+    const int k = (int)(blockIdx.x / (unsigned)wpc);
+    const int w = (int)(blockIdx.x - (unsigned)k * (unsigned)wpc);
+    const bool ok = chol_tiles_wave(w, k, tmax, fpc, cl_n, cl_Np, S_off, cl_start, cl_cams, S, b, dcam, flags, l, yx,
+                                    S0, Wi, Ls, zs);
+    // every wavefront of the grid ends here
+    const int tt = tmax * (tmax + 1) / 2;
+    int32_t *fl = flags + (int64_t)k * fpc;
+    int32_t *fl_err = fl + tt + tmax;
+    int32_t *fl_cnt = fl_err + 1;
+    int32_t *abort_w = flags + (int64_t)l * fpc;
+    if (!ok && lane == 0) __hip_atomic_store(fl_err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);   // this wavefront's stores have completed
+    int last = 0;
+    if (lane == 0)
+        last = __hip_atomic_fetch_add(fl_cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == wpc - 1;
+    if (__shfl(last, 0, 64) == 0) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    // the last wavefront of cluster k: status, then the initial state
+    const int T = (int)(cl_Np[k] / kNB);
+    if (lane == 0) {
         bool anybad = false;
         for (int p = 0; p < T; ++p)
             anybad |= __hip_atomic_load(fl + tile_ix(p, p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 2;
-        const bool aborted = __hip_atomic_load(abort_w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
-        cl_status[k] = (!ok || aborted) ? STBA_EHIP : (anybad ? STBA_ENOTPD : STBA_OK);
-    } else if (!ok && lane == 0) {
-        cl_status[k] = STBA_EHIP;
+        const bool failed = __hip_atomic_load(fl_err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                            __hip_atomic_load(abort_w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+        cl_status[k] = failed ? STBA_EHIP : (anybad ? STBA_ENOTPD : STBA_OK);
+    }
+    for (int q = lane; q < fpc - 1; q += 64) fl[q] = 0;
+    const int64_t nv = (int64_t)kVecSets * tmax * kNB;
+    double *vec = yx + (int64_t)k * nv;
+    for (int64_t q = lane; q < nv; q += 64) vec[q] = __longlong_as_double(kEmpty);
+    __builtin_amdgcn_s_waitcnt(0);
+    if (lane == 0) {
+        __hip_atomic_store(fl_cnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // the last cluster clears the abort word and the cluster count
+        if (__hip_atomic_fetch_add(abort_w + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == l - 1) {
+            __hip_atomic_store(abort_w, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(abort_w + 1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
 }
 
@@ -734,26 +947,24 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void
 // Column col of a tile occupies 256 bytes of its slot, its 16-byte part q (rows
 // 2q, 2q + 1) at position (q + col) mod 16: the 32 lanes that read one row of 32
 // columns, or 32 rows of one column, meet at most two to a bank.
-// Modes: kSwFromY: dcam = backward(y), y = the forward solution of the tile
-//   factorisation; kSwRefine (MIXED): dcam += backward(forward(r)) with r the
-//   residual b - S0 x from k_resid (one FP64 refinement step).
+// Used for the MIXED refinement step after the one-workgroup-per-cluster
+// factorisation: dcam += backward(forward(r)), r = b - S0 x from k_resid.
 // ---------------------------------------------------------------------------
 constexpr int kSwThreads = 1024;
 constexpr int kRing = kSwThreads / 64;             // one slot per wavefront
 constexpr int kSeg = 8;
 constexpr int kTileBytes = kNB * kNB * 8;
-constexpr int kSwFromY = 1, kSwRefine = 2;
 constexpr size_t kSwStaticLds = (size_t)kRing * kTileBytes + kNB * 8;
 
 // element (row, col) of a tile in its ring slot
 __device__ inline int sw_at(int row, int col) { return col * 256 + ((((row >> 1) + col) & 15) << 4) + ((row & 1) << 3); }
 
-// tile t of the sweep sequence (T diagonal tiles; forward steps first in
-// refinement mode): block row a, block column b, step, index k in the step
-__device__ inline void sw_tile(int t, int T, bool refine, int *a, int *b, bool *fwd) {
+// tile t of the sweep sequence (the forward steps, then the backward ones):
+// block row a, block column b, step, index k in the step
+__device__ inline void sw_tile(int t, int T, int *a, int *b, bool *fwd) {
     const int n = T * (T + 1) / 2;
-    *fwd = refine && t < n;
-    if (refine && t >= n) t -= n;
+    *fwd = t < n;
+    if (t >= n) t -= n;
     int s = 0, off = 0;
     while (off + (T - s) <= t) {
         off += T - s;
@@ -771,10 +982,10 @@ __device__ inline void sw_tile(int t, int T, bool refine, int *a, int *b, bool *
 }
 
 // wavefront-uniform: issue the eight 1 KB load-to-LDS instructions of tile t
-__device__ inline void sw_issue(const double *A, int64_t Np, int T, bool refine, int t, char *slot, int lane) {
+__device__ inline void sw_issue(const double *A, int64_t Np, int T, int t, char *slot, int lane) {
     int a, b;
     bool fwd;
-    sw_tile(t, T, refine, &a, &b, &fwd);
+    sw_tile(t, T, &a, &b, &fwd);
     const int sl = lane & 15;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -844,27 +1055,20 @@ __device__ __forceinline__ void sw_panel(const char *ring, double *z, const doub
     if (act && qq == 0) z[(kFwd ? p + kk : kk - 1) * kNB + e] -= acc;
 }
 
-__global__ __launch_bounds__(kSwThreads) void k_sweep(int mode, const int32_t *__restrict__ cl_n,
+__global__ __launch_bounds__(kSwThreads) void k_sweep(const int32_t *__restrict__ cl_n,
                                                       const int32_t *__restrict__ cl_Np,
                                                       const int64_t *__restrict__ S_off,
                                                       const int32_t *__restrict__ cl_start,
                                                       const int32_t *__restrict__ cl_cams,
                                                       const double *__restrict__ S,
                                                       const double *__restrict__ rhs, int32_t rstride,
-                                                      double *__restrict__ dcam, int32_t *__restrict__ flags,
-                                                      int32_t fpc) {
+                                                      double *__restrict__ dcam) {
     __shared__ __align__(16) char ring[kRing * kTileBytes];
     __shared__ double xb[kNB];
     extern __shared__ double z[];   // Np
     const int k = blockIdx.x;
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
-    if (flags != nullptr) {
-        // after the tile-parallel factorisation: clear its flag words (cluster k's
-        // and the abort word) so that they are zero when the next one starts
-        for (int i = tid; i < fpc; i += kSwThreads) flags[(int64_t)k * fpc + i] = 0;
-        if (k == 0 && tid == 0) flags[(int64_t)gridDim.x * fpc] = 0;
-    }
     const int nk = cl_n[k];
     if (nk == 0) return;
     const int64_t Np = cl_Np[k];
@@ -872,19 +1076,17 @@ __global__ __launch_bounds__(kSwThreads) void k_sweep(int mode, const int32_t *_
     const int T = (int)(Np / kNB);
     const double *A = S + S_off[k];
     const int c0 = cl_start[k];
-    const bool refine = mode == kSwRefine;
-    const int n1 = T * (T + 1) / 2;
-    const int ntiles = refine ? 2 * n1 : n1;
+    const int ntiles = T * (T + 1);
     char *slot = ring + w * kTileBytes;
     int mine = w;   // the tile this wavefront has in flight (or has landed)
-    if (mine < ntiles) sw_issue(A, Np, T, refine, mine, slot, lane);
+    if (mine < ntiles) sw_issue(A, Np, T, mine, slot, lane);
     for (int i = tid; i < Np; i += kSwThreads) z[i] = rhs[(int64_t)k * rstride + i];
     // segments: (sweep, step s, tiles [k0, k1) of the step).  One barrier between
     // segments: it publishes the previous segment's results and its end of use of
     // the ring slots, and (after the owners' waits) the landing of this one's tiles.
     int t0 = 0, pa = 0, pb = 0;   // the previous segment's tiles [pa, pb)
-    for (int sweep = 0; sweep < (refine ? 2 : 1); ++sweep) {
-        const bool fwd = refine && sweep == 0;
+    for (int sweep = 0; sweep < 2; ++sweep) {
+        const bool fwd = sweep == 0;
         for (int s = 0; s < T; ++s) {
             const int cnt = T - s;
             const int p = fwd ? s : T - 1 - s;   // the diagonal block of the step
@@ -896,7 +1098,7 @@ __global__ __launch_bounds__(kSwThreads) void k_sweep(int mode, const int32_t *_
                 asm volatile("" ::"v"(ring) : "memory");
                 if (mine >= pa && mine < pb) {   // my previous tile is used: load the one kRing further
                     mine += kRing;
-                    if (mine < ntiles) sw_issue(A, Np, T, refine, mine, slot, lane);
+                    if (mine < ntiles) sw_issue(A, Np, T, mine, slot, lane);
                 }
                 if (k0 == 0) {
                     const char *dg = ring + ((t0 % kRing) * kTileBytes);
@@ -917,7 +1119,7 @@ __global__ __launch_bounds__(kSwThreads) void k_sweep(int mode, const int32_t *_
     __syncthreads();
     for (int i = tid; i < N; i += kSwThreads) {
         double *d = dcam + 9 * (int64_t)cl_cams[c0 + i / 9] + i % 9;
-        *d = refine ? *d + z[i] : z[i];
+        *d += z[i];
     }
 }
 
@@ -977,10 +1179,14 @@ __global__ __launch_bounds__(256) void k_resid(int32_t nrb, const int32_t *__res
     }
 }
 
-// S0 = S over the used part (S_off[l] entries)
-__global__ void k_zero_flags(int32_t *flags, int64_t count) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
-        flags[i] = 0;
+// The initial state of the tile-parallel factorisation's flag words (zero)
+// and block vectors (kEmpty).
+__global__ void k_init_chol_sync(int32_t *flags, int64_t nf, double *yx, int64_t nv) {
+    const int64_t n = nf > nv ? nf : nv;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (i < nf) flags[i] = 0;
+        if (i < nv) yx[i] = __longlong_as_double(kEmpty);
+    }
 }
 
 }  // namespace
@@ -1007,8 +1213,8 @@ int chol_tile_layout(int32_t l, int32_t max_Np, int32_t *wpc, int32_t *tmax, int
     if ((int64_t)l * waves > kCholTileWaves) return 0;
     // keep a quarter of the resident capacity in reserve
     if (4 * (int64_t)l * waves > 3 * chol_tile_resident()) return 0;
-    const int64_t words = (int64_t)tm * (tm + 1) / 2 + 2 * tm;
-    if ((int64_t)l * words + 1 > chol_flag_words() || (int64_t)l * tm * kNB > chol_yx_doubles()) return 0;
+    const int64_t words = (int64_t)tm * (tm + 1) / 2 + tm + 2;
+    if ((int64_t)l * words + 2 > chol_flag_words() || (int64_t)l * kVecSets * tm * kNB > chol_yx_doubles()) return 0;
     *tmax = tm;
     *wpc = (int32_t)waves;
     *fpc = (int32_t)words;
@@ -1021,19 +1227,10 @@ hipError_t launch_chol(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, con
                        double *rbuf, hipStream_t st) {
     int32_t wpc = 0, tmax = 0, fpc = 0;
     if (flags && yx && chol_tile_layout(l, max_Np, &wpc, &tmax, &fpc)) {
-        // the flag words are zero here: cleared when the workspace was prepared and
-        // after every factorisation by the solve that follows it
+        // the flag words are zero and the vector entries kEmpty here: set when the
+        // workspace was prepared and again at the end of every factorisation
         k_chol_tiles<<<(unsigned)((int64_t)l * wpc), 64, 0, st>>>(wpc, tmax, fpc, cl_n, cl_Np, S_off, cl_start, cl_cams,
-                                                                 S, b, dcam, cl_status, flags, l, yx);
-        // backward solve by one workgroup per cluster
-        if (kSwStaticLds + sizeof(double) * (size_t)max_Np > 160 * 1024) return hipErrorInvalidConfiguration;
-        k_sweep<<<(unsigned)l, kSwThreads, sizeof(double) * (size_t)max_Np, st>>>(
-            kSwFromY, cl_n, cl_Np, S_off, cl_start, cl_cams, S, yx, tmax * kNB, dcam, flags, fpc);
-        if (S0) {
-            const hipError_t e = hipGetLastError();
-            if (e != hipSuccess) return e;
-            return launch_refine(l, cl_n, cl_Np, S_off, cl_start, cl_cams, S, S0, b, dcam, rbuf, max_Np, st);
-        }
+                                                                 S, b, dcam, cl_status, flags, l, yx, S0);
         return hipGetLastError();
     }
     const size_t shmem = sizeof(double) * (2 * (size_t)kNB * (kNB + 1) + 2 * kNB + (size_t)max_Np + kCholThreads + kNB);
@@ -1047,9 +1244,9 @@ hipError_t launch_chol(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, con
     return hipGetLastError();
 }
 
-hipError_t launch_clear_chol_flags(int32_t *flags, hipStream_t st) {
-    const int64_t n = chol_flag_words();
-    k_zero_flags<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(flags, n);
+hipError_t launch_clear_chol_flags(int32_t *flags, double *yx, hipStream_t st) {
+    const int64_t nf = chol_flag_words(), nv = chol_yx_doubles();
+    k_init_chol_sync<<<(unsigned)(((nf > nv ? nf : nv) + 255) / 256), 256, 0, st>>>(flags, nf, yx, nv);
     return hipGetLastError();
 }
 
@@ -1061,7 +1258,7 @@ hipError_t launch_refine(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, c
         nrb, cl_n, cl_Np, S_off, cl_start, cl_cams, S0, b, dcam, rbuf, max_Np);
     if (kSwStaticLds + sizeof(double) * (size_t)max_Np > 160 * 1024) return hipErrorInvalidConfiguration;
     k_sweep<<<(unsigned)l, kSwThreads, sizeof(double) * (size_t)max_Np, st>>>(
-        kSwRefine, cl_n, cl_Np, S_off, cl_start, cl_cams, S, rbuf, max_Np, dcam, nullptr, 0);
+        cl_n, cl_Np, S_off, cl_start, cl_cams, S, rbuf, max_Np, dcam);
     return hipGetLastError();
 }
 

@@ -97,14 +97,16 @@ hipError_t launch_schur(const int64_t *n_blocks, int64_t n_blocks_cap, const Sch
 // given: one wavefront per tile (tile-parallel dataflow); otherwise one
 // workgroup per cluster.  flags: chol_flag_words() int32; yx: chol_yx_doubles().
 constexpr int kCholTileWaves = 1536;
-// per cluster T (T + 1) / 2 + 2 T flag words <= 3.5 x its wavefronts, plus the abort word
-inline int64_t chol_flag_words() { return 4 * (int64_t)kCholTileWaves + 1; }
-// per cluster T 32 doubles (the forward solution y), T <= its wavefronts
-inline int64_t chol_yx_doubles() { return (int64_t)kCholTileWaves * kNB; }
+// per cluster T (T + 1) / 2 + T + 2 flag words <= 2.5 x its wavefronts, plus the
+// abort word and the count of finished clusters
+inline int64_t chol_flag_words() { return 4 * (int64_t)kCholTileWaves + 2; }
+// per cluster 4 block vectors of T x 32 doubles (y, x and the MIXED refinement's
+// d, e), T <= its wavefronts
+inline int64_t chol_yx_doubles() { return 4 * (int64_t)kCholTileWaves * kNB; }
 int chol_tile_layout(int32_t l, int32_t max_Np, int32_t *wpc, int32_t *tmax, int32_t *fpc);
-// the flag words have to be zero before the first factorisation; every
-// tile-parallel factorisation leaves them zero again
-hipError_t launch_clear_chol_flags(int32_t *flags, hipStream_t st);
+// the flag words and block vectors have to be in their initial state before the
+// first factorisation; every tile-parallel factorisation leaves them so again
+hipError_t launch_clear_chol_flags(int32_t *flags, double *yx, hipStream_t st);
 // S0 (nullable): the assembled S kept for one FP64 refinement step (MIXED),
 // with rbuf (l * max_Np doubles) for its residual.
 hipError_t launch_chol(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, const int64_t *S_off,

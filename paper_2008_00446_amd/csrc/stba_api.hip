@@ -341,7 +341,7 @@ int stba_prepare(const stba_problem *p, const stba_dims *dims, int precision, vo
     b.tmp_bytes = L.tmp_bytes;
     STBA_HIP(launch_reset_status(at<int32_t>(ws, L.status), stream));
     STBA_HIP(launch_prepare(*p, dims->n_pairs, b, at<int32_t>(ws, L.status), stream));
-    STBA_HIP(launch_clear_chol_flags(at<int32_t>(ws, L.chol_flags), stream));
+    STBA_HIP(launch_clear_chol_flags(at<int32_t>(ws, L.chol_flags), at<double>(ws, L.chol_yx), stream));
     if (L.group_size > 0)
         STBA_HIP(launch_point_groups(p->n, b.pt_off, L.group_size, (p->q + L.group_size - 1) / L.group_size,
                                      at<int32_t>(ws, L.grp_first), stream));
