@@ -132,19 +132,28 @@ __device__ __forceinline__ bool diag_factor_invert(double *A, int64_t Np, int64_
     return bad;
 }
 
+// Raise *f = v after all earlier stores of the wavefront have completed.
+__device__ inline void raise_flag(int32_t *f, int v) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);
+    if ((threadIdx.x & 63) == 0) __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Diagonal tile of the tile-parallel factorisation, one wavefront: the tile
 // comes in Ls (row-major).  Lanes 0..31 carry row r of the tile and become row
 // r of L; lanes 32..63 carry column r of the identity and become column r of
 // W = L^-1.  Both updates of a right-looking step have the form
 // v_j -= v_k l_jk (row: l_rk l_jk; column of W: W[k][c] l_jk), so one
 // instruction serves both halves.  At step k the pivot comes from lane k
-// (v_readlane), the scaled column l_.k goes through LDS, and row k of W is final
-// and is written at once: W^T to the upper triangle of the tile in A (device
-// scope, diagonal included, so it holds 1 / L_kk) and W row-major to Wl.
+// (v_readlane) and the scaled column l_.k goes through LDS.  At the end W goes
+// row-major to Wl and W^T to the upper triangle of the tile in A (device scope,
+// diagonal included, so it holds 1 / L_kk).
 // Returns true if a pivot was not positive.
+// panel_flag (nullable): raised a few pivots in, once the stores issued before
+// the call have completed (the loop issues no other global memory operations).
 __device__ __forceinline__ bool band_factor_invert(double *A, int64_t Np, int64_t off, int lane,
                                                    double (*Ls)[kNB + 1], double (*Wl)[kNB + 1],
-                                                   double *col) {
+                                                   double *col, int32_t *panel_flag) {
     const int r = lane & (kNB - 1);
     const bool wl = lane >= kNB;
     double v[kNB];
@@ -161,44 +170,77 @@ __device__ __forceinline__ bool band_factor_invert(double *A, int64_t Np, int64_
         d = 1.0;
     }
     double is = rsqrt_once(d);
+    // Software-pipelined steps.  Step k needs of step k-1's updates only those
+    // of columns k and k+1 (its pivot and the next one); the others (columns
+    // >= k+2) are issued in step k among the dependent operations of the next
+    // pivot's reciprocal square root, whose latencies they fill.  The columns
+    // of L alternate between the two halves of col, so step k reads column
+    // k-1 again for them.
+    double vkp = 0.0;   // this lane's entry of column k-1
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int k = 0; k < kNB; ++k) {
         // an opaque copy of the lane index per step: the lane compares are not
         // hoisted into masks for all 32 steps at once
         asm volatile("" : "+v"(rq));
+        if (k == 4 && panel_flag != nullptr) raise_flag(panel_flag, 1);
+        double *cc = col + (k & 1) * kNB;
+        const double *cp = col + ((k + 1) & 1) * kNB;
         // one scaling for every lane: rows r > k get l_rk, lane k gets d / sqrt(d)
         // = L_kk, W lanes get W[k][c]; rows above k keep don't-care values that
         // only touch entries above the diagonal
         v[k] *= is;
         if (k + 1 < kNB) {
-            if (!wl) col[rq] = v[k];
-            double lc[kNB];
-#pragma unroll
-            for (int j = k + 1; j < kNB; ++j) lc[j] = col[j];
-            __builtin_amdgcn_sched_barrier(0);
+            if (!wl) cc[rq] = v[k];
             const double t = fma(-v[k], v[k], v[k + 1]);
+            __builtin_amdgcn_sched_barrier(0);
+            double lc[kNB], lp[kNB];
+#pragma unroll
+            for (int j = k + 1; j < kNB; ++j) lc[j] = cc[j];
+            if (k >= 1) {
+#pragma unroll
+                for (int j = k + 2; j < kNB; ++j) lp[j] = cp[j];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            // the next pivot (lane k+1's own entries only) while the column
+            // reads are in flight, and step k-1's deferred updates
             double dn = readlane_d(t, k + 1);
             if (!(dn > 0.0) || !isfinite(dn)) {
                 bad = true;
                 dn = 1.0;
             }
             const double is_next = rsqrt_once(dn);
+            if (k >= 1) {
 #pragma unroll
-            for (int j = k + 1; j < kNB; ++j) v[j] = fma(-v[k], lc[j], v[j]);
+                for (int j = k + 2; j < kNB; ++j) v[j] = fma(-vkp, lp[j], v[j]);
 #pragma unroll
-            for (int j = k + 1; j < kNB; ++j) asm volatile("" : "+v"(v[j]));
-            // computed within this step (its chain interleaved with the updates),
-            // not sunk to its use in the next one
+                for (int j = k + 2; j < kNB; ++j) asm volatile("" : "+v"(v[j]));   // not sunk to later steps
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            // the updates of columns k+1 and k+2 (the next step's pivot column
+            // and its next pivot); the rest waits for the next step
+            v[k + 1] = fma(-v[k], lc[k + 1], v[k + 1]);
+            if (k + 2 < kNB) v[k + 2] = fma(-v[k], lc[k + 2], v[k + 2]);
+            vkp = v[k];
+            asm volatile("" : "+v"(v[k + 1]));
+            if (k + 2 < kNB) asm volatile("" : "+v"(v[k + 2]));
+            // computed within this step, not sunk to its use in the next one
             is = is_next;
             asm volatile("" : "+v"(is));
         }
-        if (wl) {   // W[k][r] is final
-            Wl[k][rq] = v[k];
-            if (rq <= k)
-                __hip_atomic_store(A + (off + rq) + (off + k) * Np, v[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
         __builtin_amdgcn_sched_barrier(0);
+    }
+    // W lane c now holds column c of W (v[k] = W[k][c], zero for k < c): W to
+    // Wl (row-major) and W^T to row c of the tile in A, whose upper triangle
+    // then holds W^T with the diagonal.  The zeros land in the lower triangle,
+    // which no reader of a factored diagonal tile uses.
+    if (wl) {
+        double *dst = A + (off + rq) + off * Np;
+#pragma unroll
+        for (int k = 0; k < kNB; ++k) {
+            Wl[k][rq] = v[k];
+            __hip_atomic_store(dst + k * Np, v[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
     __syncwarp();
     return bad;
@@ -436,9 +478,10 @@ __device__ inline int wait_flag(const int32_t *f, int32_t *abort_w) {
     int v = 0;
     if ((threadIdx.x & 63) == 0) {
         for (int it = 0; it < kWaitPolls; ++it) {
+            // both loads in flight together: one round trip per poll
             v = __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (v != 0) break;
-            if (__hip_atomic_load(abort_w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+            const int a = __hip_atomic_load(abort_w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (v != 0 || a != 0) break;
             __builtin_amdgcn_s_sleep(1);
         }
         if (v == 0) __hip_atomic_store(abort_w, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -460,11 +503,11 @@ __device__ inline double wait_vec(const double *v, int32_t *abort_w, bool &ok) {
     const int lane = threadIdx.x & 63;
     const double *p = v + (lane & (kNB - 1));
     for (int it = 0; it < kWaitPolls; ++it) {
+        // both loads in flight together: one round trip per poll
         const double x = ld_dev(p);
+        const int a = __hip_atomic_load(abort_w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (__ballot(__double_as_longlong(x) != kEmpty) == ~0ull) return x;
-        int a = 0;
-        if (lane == 0) a = __hip_atomic_load(abort_w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (__shfl(a, 0, 64) != 0) break;
+        if (a != 0) break;
         __builtin_amdgcn_s_sleep(1);
     }
     if (lane == 0) __hip_atomic_store(abort_w, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -472,12 +515,6 @@ __device__ inline double wait_vec(const double *v, int32_t *abort_w, bool &ok) {
     return 0.0;
 }
 
-// Raise *f = v after all earlier stores of the wavefront have completed.
-__device__ inline void raise_flag(int32_t *f, int v) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_s_waitcnt(0);
-    if ((threadIdx.x & 63) == 0) __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 __device__ inline int tile_ix(int i, int j) { return i * (i + 1) / 2 + j; }
 
@@ -769,15 +806,17 @@ __device__ __forceinline__ bool chol_tiles_wave(int w, int k, int32_t tmax, int3
         return ok;
     }
     if (w == 0) {
-        // band worker
+        // band worker: the critical path, ahead of the other wavefronts on its SIMD
+        __builtin_amdgcn_s_setprio(3);
         for (int i = 0; i < T; ++i) {
-            ok &= wait_flag(fl_part + i, abort_w) != 0;
             const int64_t ri = (int64_t)i * kNB;
-            d4 accD[2][2];
+            d4 accD[2][2], accP[2][2];
+            // rows 0 and 1 have no earlier panels: their tiles are the assembled ones
+            if (i >= 2) ok &= wait_flag(fl_part + i, abort_w) != 0;
             load_tile_dev(A, Np, ri, ri, lr, lk, accD);
+            if (i >= 1) load_tile_dev(A, Np, ri, ri - kNB, lr, lk, accP);
             if (i >= 1) {
-                d4 accP[2][2], x[2][2];
-                load_tile_dev(A, Np, ri, ri - kNB, lr, lk, accP);
+                d4 x[2][2];
                 panel_solve_lds(accP, Wi, lr, lk, x);
                 store_tile_dev(A, Np, ri, ri - kNB, lr, lk, x);
                 double li[2][8];
@@ -794,10 +833,9 @@ __device__ __forceinline__ bool chol_tiles_wave(int w, int k, int32_t tmax, int3
                 for (int C = 0; C < 2; ++C)
 #pragma unroll
                     for (int v = 0; v < 4; ++v) Ls[16 * R + lr][16 * C + 4 * v + lk] = accD[R][C][v];
-            // the panel stores were issued before the update: their flag now waits less
-            if (i >= 1) raise_flag(fl + tile_ix(i, i - 1), 1);
             __syncwarp();
-            const bool bad = band_factor_invert(A, Np, ri, lane, Ls, Wi, zs);
+            // the panel's flag is raised inside, once its stores have completed
+            const bool bad = band_factor_invert(A, Np, ri, lane, Ls, Wi, zs, i >= 1 ? fl + tile_ix(i, i - 1) : nullptr);
             raise_flag(fl + tile_ix(i, i), bad ? 2 : 1);
         }
         return ok;
@@ -806,10 +844,10 @@ __device__ __forceinline__ bool chol_tiles_wave(int w, int k, int32_t tmax, int3
     const int i = w - 1;
     if (i >= T) return true;
     const int64_t ri = (int64_t)i * kNB;
-    {
+    if (i >= 2) {   // rows 0 and 1 have no updates before the band worker's
         d4 accD[2][2], accP[2][2];
         load_tile(A, Np, ri, ri, lr, lk, accD);
-        if (i >= 1) load_tile(A, Np, ri, ri - kNB, lr, lk, accP);
+        load_tile(A, Np, ri, ri - kNB, lr, lk, accP);
         for (int p = 0; p + 1 < i; ++p) {
             ok &= wait_flag(fl + tile_ix(i, p), abort_w) != 0;
             ok &= wait_flag(fl + tile_ix(i - 1, p), abort_w) != 0;
@@ -820,7 +858,7 @@ __device__ __forceinline__ bool chol_tiles_wave(int w, int k, int32_t tmax, int3
             mfma_downdate(accD, li, li);
         }
         store_tile_dev(A, Np, ri, ri, lr, lk, accD);
-        if (i >= 1) store_tile_dev(A, Np, ri, ri - kNB, lr, lk, accP);
+        store_tile_dev(A, Np, ri, ri - kNB, lr, lk, accP);
         raise_flag(fl_part + i, 1);
     }
     const int r = lane & (kNB - 1);
