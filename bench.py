@@ -16,7 +16,7 @@ the library's stream.  `roofline` describes the phase with the largest time per
 iteration.  `mixed_vs_fp64` runs the same iterations in MIXED precision (FP32
 Jacobian and Schur assembly, FP64 Cholesky with one refinement step and FP64
 cost) from the same start and maps and compares the two at equal cost
-reduction as the performance profiles of Sec. 5.1 do: the time each needs to
+reduction as the performance profiles of Sec. 5.2 do: the time each needs to
 reach F_tau = F* + tau (F0 - F*) for tau = 0.1, 0.01, 0.001 (F* the lower of
 their costs after K iterations); the headline speedup is the one at 0.001.  `cpu_baseline` times the
 FP64 oracle on the host for the first iterations of the same run.
@@ -69,7 +69,7 @@ def parse_args():
     ap.add_argument("--pmc-summary", action="store_true",
                     help="write a profiles/pmc_*.txt summary from counter CSVs (no GPU work)")
     ap.add_argument("--phase", default="cluster_cholesky")
-    ap.add_argument("--kernels", default="k_chol_tiles,k_sweep",
+    ap.add_argument("--kernels", default="k_chol_tiles",
                     help="comma-separated kernel name fragments belonging to --phase")
     ap.add_argument("--fetch-csv")
     ap.add_argument("--write-csv")
@@ -340,7 +340,7 @@ TAUS = (0.1, 0.01, 0.001)
 
 def mixed_leg(S, scene, sol64, samples64, samples_maps, args, lam0, cam0, pt0):
     """MIXED against FP64 at equal cost reduction, measured as in the performance
-    profiles of Sec. 5.1: both precisions run from the same x0 with the same
+    profiles of Sec. 5.2: both precisions run from the same x0 with the same
     cluster maps; F0 is the cost at x0, F* the lower of their costs after K
     iterations, F_tau = F* + tau (F0 - F*), and T_tau is the wall time of the
     iterations a precision needs to bring its cost to F_tau or below."""
