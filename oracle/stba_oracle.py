@@ -30,7 +30,9 @@ point update (Eq. 14-15), the correction (Sec. 4.3) and the LM accept rule
 * the draw: key (seed, 0), counter (t, point, camera of the later observation, 0),
   output word 0; keep iff (x0 >> 11) < ceil(alpha * 2^53);
 * accept iff F(x + dx) < F(x) strictly, the step is finite and every cluster
-  system factorises; lambda /= 3 on accept and *= 3 otherwise (Alg. 1).
+  system factorises; lambda /= 3 on accept and *= 3 otherwise (Alg. 1);
+* the robust loss (Sec. 5.1, optional): Huber on each observation's error norm,
+  applied by first-order (IRLS) reweighting of f and J (see `huber_rho`).
 
 Parity pins live in tests/test_oracle_*.py; every function below is pinned.
 """
@@ -45,6 +47,7 @@ import scipy.sparse as sp
 
 __all__ = [
     "rotation_matrix", "project", "residuals", "cost", "jacobian", "jtv", "gradient",
+    "huber_rho", "huber_weight", "robust_cost", "irls",
     "philox4x64_10", "keep_threshold", "link_draws", "segments", "canonical_segments",
     "jc_matrix", "jp_matrix", "damp", "correct_point_gradient", "correction_explicit",
     "StbaStep", "stba_step", "plain_lm_step", "full_normal_step", "relaxed_kkt_step",
@@ -108,6 +111,46 @@ def residuals(cam, pt, obs_cam, obs_pt, obs_uv):
 def cost(f):
     """F = ||f||^2, no 1/2 (Sec. 3)."""
     return float(np.sum(np.asarray(f, dtype=np.float64) ** 2))
+
+
+# ---------------------------------------------------------------------------
+# Robust loss (Sec. 5.1): the experiments put a Huber loss of scale 0.5 on the
+# errors.  Reading: each observation's squared error s = ||f_o||^2 costs
+# rho(s) = s for s <= a^2 and 2 a sqrt(s) - a^2 above (the Huber function of
+# the error norm, continuous with its first derivative), F = sum_o rho(s_o), and
+# LM is applied to the first-order (IRLS) reweighted problem f~ = sqrt(rho') f,
+# J~ = sqrt(rho') J, whose gradient 2 J~^T f~ = 2 sum rho' J^T f is F's.  a = 0
+# is the plain squared loss.
+# ---------------------------------------------------------------------------
+
+
+def huber_rho(s, a):
+    """rho(s) of the Huber loss with scale a on s = ||f_o||^2."""
+    s = np.asarray(s, dtype=np.float64)
+    if a <= 0.0:
+        return s
+    return np.where(s <= a * a, s, 2.0 * a * np.sqrt(s) - a * a)
+
+
+def huber_weight(s, a):
+    """rho'(s): 1 for s <= a^2, a / sqrt(s) above."""
+    s = np.asarray(s, dtype=np.float64)
+    if a <= 0.0:
+        return np.ones_like(s)
+    return np.where(s <= a * a, 1.0, a / np.sqrt(np.maximum(s, a * a)))
+
+
+def robust_cost(f, a):
+    """F = sum_o rho(||f_o||^2) (the squared cost for a = 0)."""
+    f = np.asarray(f, dtype=np.float64).reshape(-1, 2)
+    return float(np.sum(huber_rho(np.sum(f * f, axis=1), a)))
+
+
+def irls(f, Jc, Jp, a):
+    """f~ = sqrt(rho') f, J~_c = sqrt(rho') J_c, J~_p = sqrt(rho') J_p per observation."""
+    f = np.asarray(f, dtype=np.float64).reshape(-1, 2)
+    r = np.sqrt(huber_weight(np.sum(f * f, axis=1), a))
+    return f * r[:, None], Jc * r[:, None, None], Jp * r[:, None, None]
 
 
 # ---------------------------------------------------------------------------
@@ -398,14 +441,17 @@ class StbaStep:
 
 
 def stba_step(cam, pt, obs_cam, obs_pt, obs_uv, cam_cluster, lam, alpha=1.0, seed=0, t=0,
-              lam_corr=0.1, Jc=None, Jp=None, f=None, ids=None):
+              lam_corr=0.1, Jc=None, Jp=None, f=None, ids=None, huber=0.0):
     """One STBA step for a given clustering (Alg. 1, one pass of the while loop
-    up to the point update).  ids: see `segments`."""
+    up to the point update).  ids: see `segments`.  huber > 0: the step of the
+    IRLS-reweighted problem (robust loss of Sec. 5.1, see `irls`)."""
     m, n = cam.shape[0], pt.shape[0]
     if f is None:
         f = residuals(cam, pt, obs_cam, obs_pt, obs_uv)
     if Jc is None or Jp is None:
         Jc, Jp = jacobian(cam, pt, obs_cam, obs_pt)
+    if huber > 0.0:
+        f, Jc, Jp = irls(f, Jc, Jp, huber)
     seg, n_seg, seg_point, _, _, _ = segments(obs_cam, obs_pt, cam_cluster, alpha, seed, t, ids)
     fv = np.asarray(f, dtype=np.float64).reshape(-1)
     Jc_m = jc_matrix(Jc, obs_cam, m)
@@ -543,14 +589,15 @@ class LmResult:
 
 
 def lm_iteration(cam, pt, obs_cam, obs_pt, obs_uv, cam_cluster, lam, alpha=1.0, seed=0, t=0,
-                 lam_corr=0.1, F=None):
-    """One pass of Alg. 1's loop: STBA step, then accept iff F(x + dx) < F(x)."""
+                 lam_corr=0.1, F=None, huber=0.0):
+    """One pass of Alg. 1's loop: STBA step, then accept iff F(x + dx) < F(x)
+    (F the robust cost when huber > 0)."""
     if F is None:
-        F = cost(residuals(cam, pt, obs_cam, obs_pt, obs_uv))
-    st = stba_step(cam, pt, obs_cam, obs_pt, obs_uv, cam_cluster, lam, alpha, seed, t, lam_corr)
+        F = robust_cost(residuals(cam, pt, obs_cam, obs_pt, obs_uv), huber)
+    st = stba_step(cam, pt, obs_cam, obs_pt, obs_uv, cam_cluster, lam, alpha, seed, t, lam_corr, huber=huber)
     cam_new = cam + st.dcam
     pt_new = pt + st.dpt
-    F_new = cost(residuals(cam_new, pt_new, obs_cam, obs_pt, obs_uv)) if st.ok else float("nan")
+    F_new = robust_cost(residuals(cam_new, pt_new, obs_cam, obs_pt, obs_uv), huber) if st.ok else float("nan")
     accepted = bool(st.ok and np.isfinite(F_new) and F_new < F)
     if accepted:
         return LmResult(cam_new, pt_new, lam / 3.0, F_new, F_new, True, st)
