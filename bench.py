@@ -66,6 +66,7 @@ def parse_args():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (to scale HBM counters)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
+    ap.add_argument("--no-huber", action="store_true", help="skip the robust-loss (Huber) leg")
     ap.add_argument("--pmc-summary", action="store_true",
                     help="write a profiles/pmc_*.txt summary from counter CSVs (no GPU work)")
     ap.add_argument("--phase", default="cluster_cholesky")
@@ -328,11 +329,28 @@ def main():
     if not args.no_mixed and precision == S.STBA_FP64:
         out["mixed_vs_fp64"] = mixed_leg(S, scene, sol, samples, samples_maps=maps, args=args, lam0=lam0,
                                          cam0=cam0, pt0=pt0)
+    if not args.no_huber and precision == S.STBA_FP64:
+        out["huber"] = huber_leg(S, scene, maps, args, lam0, cam0, pt0)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, maps, lam0, args.cpu_iters)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out))
+
+
+HUBER_SCALE = 0.5   # the experiments' robust loss (Sec. 5.1)
+
+
+def huber_leg(S, scene, maps, args, lam0, cam0, pt0):
+    """The same K FP64 iterations under the Huber loss of scale 0.5 (IRLS)."""
+    solh = S.StbaSolver(scene.cam0, scene.pt0, scene.obs_cam, scene.obs_pt, scene.obs_uv,
+                        gamma_max=args.gamma, precision=S.STBA_FP64, lambda0=lam0, huber=HUBER_SCALE)
+    samples = [solh.sample(maps[t], alpha=1.0, seed=0, it=t) for t in range(max(args.steps, args.warmup))]
+    run_iterations(solh, samples, cam0, pt0, lam0, args.warmup)
+    t = timed(lambda: run_iterations(solh, samples, cam0, pt0, lam0, args.steps))
+    st = solh.read_state()
+    return {"scale": HUBER_SCALE, "iter_per_s": args.steps / t, "obs_per_s": scene.q * args.steps / t,
+            "F_after_K": st["F"], "accepted": st["n_accept"], "status": st["status"]}
 
 
 TAUS = (0.1, 0.01, 0.001)

@@ -24,7 +24,8 @@
  *    translation, focal length, radial distortion.  A point X projects to
  *    P = R(w) X + t, (x, y) = (P_x, P_y)/P_z, r2 = x^2 + y^2,
  *    pixel = f (1 + k1 r2 + k2 r2^2)(x, y) (image-centred).  The residual is
- *    f_o = pixel - observed and the cost F = sum ||f_o||^2 (Sec. 3, no 1/2).
+ *    f_o = pixel - observed and the cost F = sum ||f_o||^2 (Sec. 3, no 1/2), or
+ *    with the robust loss of stba_problem.huber F = sum rho(||f_o||^2).
  *  - Observations are sorted by (point, camera) with at most one observation
  *    per (camera, point); every point has at least one observation.
  *  - Per-observation Jacobian blocks are stored observation-major:
@@ -68,6 +69,10 @@ typedef struct stba_problem {
     const int32_t *obs_cam;    /* [q] camera of each observation */
     const int32_t *obs_pt;     /* [q] point of each observation, (obs_pt, obs_cam) increasing */
     const double *obs_uv;      /* [q][2] observed pixel, image-centred */
+    double huber;              /* robust loss (Sec. 5.1): Huber scale a > 0 on each observation's
+                                  error norm, rho(s) = s for s = ||f||^2 <= a^2, else 2 a sqrt(s) - a^2,
+                                  applied by IRLS weights sqrt(rho'(s)) on f and J; 0: squared loss.
+                                  Must be finite and >= 0. */
 } stba_problem;
 
 /* Data-dependent sizes, filled by stba_analyze (host struct). */
@@ -155,7 +160,10 @@ int stba_prepare(const stba_problem *p, const stba_dims *dims, int precision, vo
 /* Residuals f and Jacobian blocks J_c, J_p of every observation (Sec. 3, Alg. 1).
  * precision selects the element type of f, Jc, Jp (double or float).  Jc and Jp
  * may both be NULL (residuals only).  cost (nullable, device double) receives
- * F = sum ||f||^2 computed in FP64.  Uses the workspace for partial sums. */
+ * F = sum ||f||^2 computed in FP64.  With p->huber = a > 0 (Sec. 5.1) f and J are
+ * the IRLS-reweighted sqrt(rho'(s)) f, sqrt(rho'(s)) J of each observation
+ * (s = ||f||^2 of the raw residual) and cost is F = sum rho(s); the later calls
+ * then solve the reweighted problem.  Uses the workspace for partial sums. */
 int stba_residual_jacobian(const stba_problem *p, const stba_dims *dims, int precision, void *f, void *Jc,
                            void *Jp, double *cost, void *ws, size_t ws_bytes, hipStream_t stream);
 
@@ -207,7 +215,8 @@ const char *stba_phase_name(int k);
 
 /* J^T v for a cotangent v [q][2] of the residuals (FP32 or FP64 per precision):
  * grad_cam[m][9] = sum_o J_c,o^T v_o, grad_pt[n][3] = sum_o J_p,o^T v_o and
- * grad_uv[q][2] = -v_o.  J is recomputed from cam and pt (nothing stored).
+ * grad_uv[q][2] = -v_o.  J is recomputed from cam and pt (nothing stored); the
+ * residuals differentiated are the raw ones (p->huber is not used).
  * Outputs are written (not accumulated) in the same precision as v; the per-camera
  * and per-point sums use fixed-order segmented reductions.  Requires stba_prepare. */
 int stba_residual_vjp(const stba_problem *p, const stba_dims *dims, int precision, const void *v,

@@ -31,7 +31,7 @@ class StbaError(RuntimeError):
 class StbaProblem(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int32), ("n", ctypes.c_int32), ("q", ctypes.c_int64),
                 ("cam", ctypes.c_void_p), ("pt", ctypes.c_void_p), ("obs_cam", ctypes.c_void_p),
-                ("obs_pt", ctypes.c_void_p), ("obs_uv", ctypes.c_void_p)]
+                ("obs_pt", ctypes.c_void_p), ("obs_uv", ctypes.c_void_p), ("huber", ctypes.c_double)]
 
 
 class StbaDims(ctypes.Structure):
@@ -128,13 +128,14 @@ def _ref(struct):
 # argument structs from tensors
 # ---------------------------------------------------------------------------
 
-def make_problem(cam, pt, obs_cam, obs_pt, obs_uv) -> StbaProblem:
-    """stba_problem from device tensors: cam [m,9] f64, pt [n,3] f64, obs_cam/obs_pt [q] int32, obs_uv [q,2] f64."""
+def make_problem(cam, pt, obs_cam, obs_pt, obs_uv, huber=0.0) -> StbaProblem:
+    """stba_problem from device tensors: cam [m,9] f64, pt [n,3] f64, obs_cam/obs_pt [q] int32, obs_uv [q,2] f64;
+    huber: the robust loss scale (0: squared loss)."""
     assert cam.dtype == torch.float64 and pt.dtype == torch.float64 and obs_uv.dtype == torch.float64
     assert obs_cam.dtype == torch.int32 and obs_pt.dtype == torch.int32
     assert cam.shape[1] == 9 and pt.shape[1] == 3 and obs_uv.shape[1] == 2
     p = StbaProblem(cam.shape[0], pt.shape[0], obs_cam.shape[0], _ptr(cam), _ptr(pt), _ptr(obs_cam),
-                    _ptr(obs_pt), _ptr(obs_uv))
+                    _ptr(obs_pt), _ptr(obs_uv), float(huber))
     p._keep = (cam, pt, obs_cam, obs_pt, obs_uv)
     return p
 

@@ -137,4 +137,12 @@ __device__ inline void camera_project_jac(const double c[9], const double X[3], 
     }
 }
 
+// Robust loss (Sec. 5.1): Huber with scale a on s = ||f_o||^2, rho(s) = s up to
+// a^2 and 2 a sqrt(s) - a^2 above; the IRLS weight on f and J is sqrt(rho'(s)),
+// rho'(s) = a / sqrt(s) above a^2.  a = 0: the squared loss.
+__device__ inline double huber_rho(double s, double a) { return (a > 0.0 && s > a * a) ? 2.0 * a * sqrt(s) - a * a : s; }
+__device__ inline double huber_root_weight(double s, double a) {
+    return (a > 0.0 && s > a * a) ? sqrt(a / sqrt(s)) : 1.0;
+}
+
 }  // namespace stba

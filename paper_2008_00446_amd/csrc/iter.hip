@@ -233,7 +233,7 @@ __global__ __launch_bounds__(256) void k_rj(int64_t q, const double *__restrict_
                                             const int32_t *__restrict__ oc, const int32_t *__restrict__ op,
                                             const double *__restrict__ uv, T *__restrict__ f, T *__restrict__ Jc,
                                             T *__restrict__ Jp, double *__restrict__ partials,
-                                            const int32_t *need_jac, int32_t *jac_ran, ZeroS z) {
+                                            const int32_t *need_jac, int32_t *jac_ran, ZeroS z, double huber) {
     __shared__ double sh[256];
     if (z.S != nullptr) {
         // S and b of this iteration start from zero (the grid runs even when the
@@ -260,22 +260,24 @@ __global__ __launch_bounds__(256) void k_rj(int64_t q, const double *__restrict_
         double pix[2], jc[2][9], jp[2][3];
         camera_project_jac(c, X, pix, jc, jp);
         const double f0 = pix[0] - uv[2 * o], f1 = pix[1] - uv[2 * o + 1];
-        f[2 * o] = (T)f0;
-        f[2 * o + 1] = (T)f1;
-        sq = f0 * f0 + f1 * f1;
+        const double s2 = f0 * f0 + f1 * f1;
+        sq = huber_rho(s2, huber);
+        const double rw = huber_root_weight(s2, huber);   // 1 for the squared loss
+        f[2 * o] = (T)(rw * f0);
+        f[2 * o + 1] = (T)(rw * f1);
         if (Jc != nullptr) {
             T *dc = Jc + 18 * o;
 #pragma unroll
             for (int r = 0; r < 2; ++r)
 #pragma unroll
-                for (int k = 0; k < 9; ++k) dc[9 * r + k] = (T)jc[r][k];
+                for (int k = 0; k < 9; ++k) dc[9 * r + k] = (T)(rw * jc[r][k]);
         }
         if (Jp != nullptr) {
             T *dp = Jp + 6 * o;
 #pragma unroll
             for (int r = 0; r < 2; ++r)
 #pragma unroll
-                for (int k = 0; k < 3; ++k) dp[3 * r + k] = (T)jp[r][k];
+                for (int k = 0; k < 3; ++k) dp[3 * r + k] = (T)(rw * jp[r][k]);
         }
     }
     if (partials != nullptr) {
@@ -1072,7 +1074,7 @@ __global__ __launch_bounds__(256) void k_cost_at(int64_t q, const double *__rest
                                                  const int32_t *__restrict__ op, const double *__restrict__ uv,
                                                  const double *__restrict__ dcam, const double *__restrict__ dpt,
                                                  double *__restrict__ partials, const stba_lm_state *st,
-                                                 double *__restrict__ F_ref) {
+                                                 double *__restrict__ F_ref, double huber) {
     __shared__ double sh[256];
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     // F(x) as it stands before the decision (and whether it is known yet), for
@@ -1092,7 +1094,7 @@ __global__ __launch_bounds__(256) void k_cost_at(int64_t q, const double *__rest
         double pix[2];
         camera_project(c, X, pix);
         const double f0 = pix[0] - uv[2 * o], f1 = pix[1] - uv[2 * o + 1];
-        sq = f0 * f0 + f1 * f1;
+        sq = huber_rho(f0 * f0 + f1 * f1, huber);
     }
     const double s = block_sum_256(sq, sh);
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
@@ -1265,7 +1267,7 @@ template <typename T>
 hipError_t launch_rj(const stba_problem &p, T *f, T *Jc, T *Jp, double *partials, const int32_t *need_jac,
                      int32_t *jac_ran, const ZeroS &z, hipStream_t st) {
     k_rj<T><<<grid_for(p.q), 256, 0, st>>>(p.q, p.cam, p.pt, p.obs_cam, p.obs_pt, p.obs_uv, f, Jc, Jp, partials,
-                                           need_jac, jac_ran, z);
+                                           need_jac, jac_ran, z, p.huber);
     return hipGetLastError();
 }
 template hipError_t launch_rj<double>(const stba_problem &, double *, double *, double *, double *,
@@ -1372,7 +1374,7 @@ template hipError_t launch_backsub<float>(const stba_problem &, const int64_t *,
 hipError_t launch_cost_at(const stba_problem &p, const double *dcam, const double *dpt, double *partials,
                           const stba_lm_state *s, double *F_ref, hipStream_t st) {
     k_cost_at<<<grid_for(p.q), 256, 0, st>>>(p.q, p.cam, p.pt, p.obs_cam, p.obs_pt, p.obs_uv, dcam, dpt, partials, s,
-                                             F_ref);
+                                             F_ref, p.huber);
     return hipGetLastError();
 }
 

@@ -1,6 +1,7 @@
 // C ABI of the STBA hot path: argument checks, the workspace layout and the
 // order in which one LM iteration (Alg. 1) enqueues its kernels.
 #include <math.h>
+#include <cmath>
 #include <string.h>
 
 #include "kernels.h"
@@ -31,6 +32,7 @@ int check_problem(const stba_problem *p) {
     if (!p || p->m < 1 || p->n < 1 || p->q < 1 || p->q >= (int64_t(1) << 31)) return STBA_EINVAL;
     if (!p->cam || !p->pt || !p->obs_cam || !p->obs_pt || !p->obs_uv) return STBA_EINVAL;
     if (p->m > kMaxCamsForClusters) return STBA_EINVAL;
+    if (!(p->huber >= 0.0) || !std::isfinite(p->huber)) return STBA_EINVAL;
     return STBA_OK;
 }
 

@@ -19,10 +19,10 @@ class StbaSolver:
     cam [m,9], pt [n,3] (FP64, copied to the device and updated in place on
     accepted steps), obs_cam / obs_pt [q] int32 sorted by (point, camera),
     obs_uv [q,2] FP64.  gamma_max bounds the cluster sizes of every map later
-    passed to `step`."""
+    passed to `step`.  huber > 0: the robust (Huber) loss of that scale."""
 
     def __init__(self, cam, pt, obs_cam, obs_pt, obs_uv, gamma_max, precision=B.STBA_FP64,
-                 lambda0=1e-4, lambda_corr=0.1, device="cuda"):
+                 lambda0=1e-4, lambda_corr=0.1, device="cuda", huber=0.0):
         as_dev = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(device)  # noqa: E731
         self.cam = as_dev(cam, torch.float64).clone()
         self.pt = as_dev(pt, torch.float64).clone()
@@ -30,7 +30,7 @@ class StbaSolver:
         self.obs_pt = as_dev(obs_pt, torch.int32)
         self.obs_uv = as_dev(obs_uv, torch.float64)
         self.precision = int(precision)
-        self.problem = B.make_problem(self.cam, self.pt, self.obs_cam, self.obs_pt, self.obs_uv)
+        self.problem = B.make_problem(self.cam, self.pt, self.obs_cam, self.obs_pt, self.obs_uv, huber)
         self.dims = B.stba_analyze(self.problem)
         self.dims.gamma_max = int(gamma_max)
         self.ws = B.alloc_workspace(B.stba_workspace_bytes(self.problem, self.dims, self.precision))

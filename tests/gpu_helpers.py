@@ -23,7 +23,7 @@ def ws_view(ws, ptr, dtype, count):
 class GpuProblem:
     """The scene's start values and observations on the device, analysed and prepared."""
 
-    def __init__(self, scene, gamma_max, precision=S.STBA_FP64, cam=None, pt=None):
+    def __init__(self, scene, gamma_max, precision=S.STBA_FP64, cam=None, pt=None, huber=0.0):
         self.scene = scene
         self.precision = precision
         self.T = torch.float64 if precision == S.STBA_FP64 else torch.float32
@@ -32,7 +32,7 @@ class GpuProblem:
         self.obs_cam = dev(scene.obs_cam, torch.int32)
         self.obs_pt = dev(scene.obs_pt, torch.int32)
         self.obs_uv = dev(scene.obs_uv, torch.float64)
-        self.prob = S.make_problem(self.cam, self.pt, self.obs_cam, self.obs_pt, self.obs_uv)
+        self.prob = S.make_problem(self.cam, self.pt, self.obs_cam, self.obs_pt, self.obs_uv, huber)
         self.dims = S.stba_analyze(self.prob)
         self.dims.gamma_max = int(gamma_max)
         self.ws = S.alloc_workspace(S.stba_workspace_bytes(self.prob, self.dims, precision))
