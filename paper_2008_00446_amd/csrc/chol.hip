@@ -917,13 +917,26 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void
     int32_t wpc, int32_t tmax, int32_t fpc, const int32_t *__restrict__ cl_n, const int32_t *__restrict__ cl_Np,
     const int64_t *__restrict__ S_off, const int32_t *__restrict__ cl_start, const int32_t *__restrict__ cl_cams,
     double *__restrict__ S, const double *__restrict__ b, double *__restrict__ dcam, int32_t *__restrict__ cl_status,
-    int32_t *flags, int32_t l, double *yx, const double *__restrict__ S0) {
+    int32_t *flags, int32_t l, double *yx, const double *__restrict__ S0, int32_t xcd_major) {
     __shared__ double Wi[kNB][kNB + 1];
     __shared__ double Ls[kNB][kNB + 1];
     __shared__ __align__(16) double zs[2 * kNB];
     const int lane = threadIdx.x;
-    const int k = (int)(blockIdx.x / (unsigned)wpc);
-    const int w = (int)(blockIdx.x - (unsigned)k * (unsigned)wpc);
+    // xcd_major: workgroups go to the 8 XCDs in turn (block b to XCD b mod 8), so
+    // cluster k is given the blocks of XCD k mod 8 and its hand-overs stay within
+    // one XCD; the grid is padded to 8 ceil(l / 8) wpc blocks and the spare ones
+    // belong to no cluster.  Otherwise cluster k has blocks k wpc .. k wpc + wpc - 1.
+    int k, w;
+    if (xcd_major) {
+        const unsigned sl = blockIdx.x >> 3;
+        const int rk = (int)(sl / (unsigned)wpc);
+        w = (int)(sl - (unsigned)rk * (unsigned)wpc);
+        k = (int)(blockIdx.x & 7u) + 8 * rk;
+        if (k >= l) return;
+    } else {
+        k = (int)(blockIdx.x / (unsigned)wpc);
+        w = (int)(blockIdx.x - (unsigned)k * (unsigned)wpc);
+    }
     const bool ok = chol_tiles_wave(w, k, tmax, fpc, cl_n, cl_Np, S_off, cl_start, cl_cams, S, b, dcam, flags, l, yx,
                                     S0, Wi, Ls, zs);
     // every wavefront of the grid ends here
@@ -1244,7 +1257,7 @@ int64_t chol_tile_resident() {
     return cap;
 }
 
-int chol_tile_layout(int32_t l, int32_t max_Np, int32_t *wpc, int32_t *tmax, int32_t *fpc) {
+int chol_tile_layout(int32_t l, int32_t max_Np, int32_t *wpc, int32_t *tmax, int32_t *fpc, int32_t *xcd_major) {
     const int32_t tm = max_Np / kNB;
     if (tm < 1) return 0;
     const int64_t waves = 1 + (int64_t)tm + (int64_t)(tm - 1) * (tm - 2) / 2;   // band, rows, tiles
@@ -1256,6 +1269,9 @@ int chol_tile_layout(int32_t l, int32_t max_Np, int32_t *wpc, int32_t *tmax, int
     *tmax = tm;
     *wpc = (int32_t)waves;
     *fpc = (int32_t)words;
+    // whole clusters per XCD when one XCD's share of the resident capacity (with
+    // the same reserve) holds ceil(l / 8) clusters
+    *xcd_major = 4 * (((int64_t)l + 7) / 8) * waves <= 3 * (chol_tile_resident() / 8) ? 1 : 0;
     return 1;
 }
 
@@ -1263,12 +1279,13 @@ hipError_t launch_chol(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, con
                        const int32_t *cl_start, const int32_t *cl_cams, double *S, const double *b, double *dcam,
                        int32_t *cl_status, int32_t max_Np, int32_t *flags, double *yx, const double *S0,
                        double *rbuf, hipStream_t st) {
-    int32_t wpc = 0, tmax = 0, fpc = 0;
-    if (flags && yx && chol_tile_layout(l, max_Np, &wpc, &tmax, &fpc)) {
+    int32_t wpc = 0, tmax = 0, fpc = 0, xcd = 0;
+    if (flags && yx && chol_tile_layout(l, max_Np, &wpc, &tmax, &fpc, &xcd)) {
         // the flag words are zero and the vector entries kEmpty here: set when the
         // workspace was prepared and again at the end of every factorisation
-        k_chol_tiles<<<(unsigned)((int64_t)l * wpc), 64, 0, st>>>(wpc, tmax, fpc, cl_n, cl_Np, S_off, cl_start, cl_cams,
-                                                                 S, b, dcam, cl_status, flags, l, yx, S0);
+        const int64_t blocks = xcd ? 8 * (((int64_t)l + 7) / 8) * wpc : (int64_t)l * wpc;
+        k_chol_tiles<<<(unsigned)blocks, 64, 0, st>>>(wpc, tmax, fpc, cl_n, cl_Np, S_off, cl_start, cl_cams, S, b,
+                                                     dcam, cl_status, flags, l, yx, S0, xcd);
         return hipGetLastError();
     }
     const size_t shmem = sizeof(double) * (2 * (size_t)kNB * (kNB + 1) + 2 * kNB + (size_t)max_Np + kCholThreads + kNB);

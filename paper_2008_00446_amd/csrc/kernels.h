@@ -103,7 +103,7 @@ inline int64_t chol_flag_words() { return 4 * (int64_t)kCholTileWaves + 2; }
 // per cluster 4 block vectors of T x 32 doubles (y, x and the MIXED refinement's
 // d, e), T <= its wavefronts
 inline int64_t chol_yx_doubles() { return 4 * (int64_t)kCholTileWaves * kNB; }
-int chol_tile_layout(int32_t l, int32_t max_Np, int32_t *wpc, int32_t *tmax, int32_t *fpc);
+int chol_tile_layout(int32_t l, int32_t max_Np, int32_t *wpc, int32_t *tmax, int32_t *fpc, int32_t *xcd_major);
 // the flag words and block vectors have to be in their initial state before the
 // first factorisation; every tile-parallel factorisation leaves them so again
 hipError_t launch_clear_chol_flags(int32_t *flags, double *yx, hipStream_t st);
