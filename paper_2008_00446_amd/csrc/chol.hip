@@ -674,15 +674,21 @@ __device__ __forceinline__ double fwd_chain(const double *A, int64_t Np, int i, 
                                             int32_t *abort_w, bool &ok) {
     const int64_t ri = (int64_t)i * kNB;
     double s = 0.0;
-    double t[16], tn[16];
-    ld_row16<true>(A, Np, ri + r, hc, t);
-    for (int j = 0; j < i; ++j) {
-        // at j + 1 == i: columns of the diagonal tile (in bounds, not used)
-        ld_row16<true>(A, Np, ri + r, (int64_t)(j + 1) * kNB + hc, tn);
-        share32(zs, wait_vec(v + (int64_t)j * kNB, abort_w, ok), lane);
-        s += dot16(t, zs + hc);
+    if (i > 0) {
+        double t[16];
+        ld_row16<true>(A, Np, ri + r, hc, t);
+        for (int j = 0; j + 1 < i; ++j) {
+            double tn[16];
+            ld_row16<true>(A, Np, ri + r, (int64_t)(j + 1) * kNB + hc, tn);
+            share32(zs, wait_vec(v + (int64_t)j * kNB, abort_w, ok), lane);
+            s += dot16(t, zs + hc);
 #pragma unroll
-        for (int m = 0; m < 16; ++m) t[m] = tn[m];
+            for (int m = 0; m < 16; ++m) t[m] = tn[m];
+        }
+        // the last term (the critical one) with no load in flight: global loads
+        // complete in order, so one issued before the wait would delay it
+        share32(zs, wait_vec(v + (int64_t)(i - 1) * kNB, abort_w, ok), lane);
+        s += dot16(t, zs + hc);
     }
     share32(zs, rhs - halves(s), lane);
     const double y = halves(dot16(w, zs + hc));
@@ -699,23 +705,36 @@ __device__ __forceinline__ double bwd_chain(const double *A, const double *A0, i
                                             int hc, double rhs, const double (&w)[16], double *v, double *zs,
                                             int lane, int32_t *abort_w, bool &ok, double &res) {
     const int64_t ri = (int64_t)i * kNB;
-    double s = 0.0;
-    double t[16], tn[16];
-    // tile (T-1, i) (for i == T-1 the diagonal tile: in bounds, not used)
-    ld_col16<true>(A, Np, (int64_t)(T - 1) * kNB + hc, ri + r, t);
-    for (int j = T - 1; j > i; --j) {
-        double u[16];   // S0 is not written by this kernel: loaded at the step, in flight during the wait
-        if (kRes) ld_col16<false>(A0, Np, (int64_t)j * kNB + hc, ri + r, u);
-        ld_col16<true>(A, Np, (int64_t)(j - 1) * kNB + hc, ri + r, tn);
-        share32(zs, wait_vec(v + (int64_t)j * kNB, abort_w, ok), lane);
-        s += dot16(t, zs + hc);
-        if (kRes) res += dot16(u, zs + hc);
+    double s = 0.0, vlast = 0.0;
+    if (i + 1 < T) {
+        double t[16];
+        ld_col16<true>(A, Np, (int64_t)(T - 1) * kNB + hc, ri + r, t);
+        for (int j = T - 1; j > i + 1; --j) {
+            double u[16], tn[16];   // S0 is not written by this kernel: loaded at the step
+            if (kRes) ld_col16<false>(A0, Np, (int64_t)j * kNB + hc, ri + r, u);
+            ld_col16<true>(A, Np, (int64_t)(j - 1) * kNB + hc, ri + r, tn);
+            share32(zs, wait_vec(v + (int64_t)j * kNB, abort_w, ok), lane);
+            s += dot16(t, zs + hc);
+            if (kRes) res += dot16(u, zs + hc);
 #pragma unroll
-        for (int m = 0; m < 16; ++m) t[m] = tn[m];
+            for (int m = 0; m < 16; ++m) t[m] = tn[m];
+        }
+        // the last term (the critical one) with no load in flight: global loads
+        // complete in order, so one issued before the wait would delay it; its
+        // S0 term follows the publication of v_i
+        vlast = wait_vec(v + (int64_t)(i + 1) * kNB, abort_w, ok);
+        share32(zs, vlast, lane);
+        s += dot16(t, zs + hc);
     }
     share32(zs, rhs - halves(s), lane);
     const double x = halves(dot16(w, zs + hc));
     publish(v + ri, x, lane);
+    if (kRes && i + 1 < T) {
+        double u[16];
+        ld_col16<false>(A0, Np, (int64_t)(i + 1) * kNB + hc, ri + r, u);
+        share32(zs, vlast, lane);
+        res += dot16(u, zs + hc);
+    }
     return x;
 }
 
