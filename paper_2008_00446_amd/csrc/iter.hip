@@ -552,16 +552,27 @@ __global__ __launch_bounds__(64 * kPtWaves) void k_points_obs(
     const int cnt = (int)(o1 - o0);
     const bool act = lane < cnt;
     const int64_t a = o0 + (act ? lane : 0);
-    const double lam = lam2[0];
-    const bool corr = lam >= lam2[1];
+    // every per-observation input requested at once (one round trip), the
+    // camera's cluster after it
     const int32_t j = obs_pt[a];
     const int32_t cam = obs_cam[a];
-    const int32_t cl = act ? cam_cluster[cam] : -1;
-    const int first = act ? (int)(pt_off[j] - o0) : lane;   // first lane of my point
-    const int last = act ? (int)(pt_off[j + 1] - o0) : lane + 1;
     double jp[6];
     load_jp(Jp, a, jp);
     const double f0 = (double)f[2 * a], f1 = (double)f[2 * a + 1];
+    double jc[18];
+#pragma unroll
+    for (int k = 0; k < 18; ++k) jc[k] = (double)Jc[18 * a + k];
+    const double lam = lam2[0];
+    const bool corr = lam >= lam2[1];
+    const int32_t cl = act ? cam_cluster[cam] : -1;
+    // my point's lanes [first, last): observations are sorted by point and the
+    // group starts at a point, so the point starts are where obs_pt changes
+    const int32_t jprev = __shfl(j, lane > 0 ? lane - 1 : 0, 64);
+    const uint64_t starts = __ballot(act && (lane == 0 || j != jprev));
+    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+    const uint64_t after = starts & ~upto & (cnt >= 64 ? ~0ull : ((1ull << cnt) - 1));
+    const int first = act ? 63 - __builtin_clzll(starts & upto) : lane;
+    const int last = act ? (after != 0 ? __builtin_ctzll(after) : cnt) : lane + 1;
     double c[9];
     c[0] = jp[0] * jp[0] + jp[3] * jp[3];
     c[1] = jp[0] * jp[1] + jp[3] * jp[4];
@@ -632,9 +643,6 @@ __global__ __launch_bounds__(64 * kPtWaves) void k_points_obs(
     chol3_inverse(cs, Vi);
     sym3_mul(Vi, ws, u);   // V*_s^-1 w'_s
     seg_head[a] = (int32_t)(o0 + head);
-    double jc[18];
-#pragma unroll
-    for (int k = 0; k < 18; ++k) jc[k] = (double)Jc[18 * a + k];
     T *rec = obsd + (int64_t)kObsRec * a;
 #pragma unroll
     for (int e = 0; e < 9; ++e) {
