@@ -904,15 +904,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                 // batch are the Y_u, 32..63 the Y_w.
                 const int yr = pl % Sh::kRecStep, yp = pl / Sh::kRecStep;
                 const T *src0 = obsd + yp * Sh::kPart;
+                // only Y (elements 0..26) is used here: the lanes of the record's
+                // last parts (M and r) move nothing
+                constexpr int kYParts = (27 + Sh::kPart - 1) / Sh::kPart;
+                const bool ypart = yp < kYParts;
                 auto fetch = [&](int bt) {
 #pragma unroll
                     for (int i = 0; i < Sh::kLoads; ++i) {
                         const int R = i * Sh::kRecStep + yr;
                         const int2 uw = sp[min(bt * 32 + (R & 31), npv - 1)];
                         const int64_t o = R < 32 ? uw.x : uw.y;
-                        __builtin_amdgcn_global_load_lds((const void *)(src0 + (int64_t)kObsRec * o),
-                                                         (void __attribute__((address_space(3))) *)(sb + i * Sh::kBlk),
-                                                         16, 0, 0);
+                        if (ypart)
+                            __builtin_amdgcn_global_load_lds((const void *)(src0 + (int64_t)kObsRec * o),
+                                                             (void __attribute__((address_space(3))) *)(sb + i * Sh::kBlk),
+                                                             16, 0, 0);
                     }
                 };
                 const char *ru = sb + Sh::row_at(pl >> 1) + Sh::elem_at(3 * e0);   // Y_u from row e0
