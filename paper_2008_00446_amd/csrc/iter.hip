@@ -778,8 +778,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     char *sb = s_rec[wv];
     const int64_t nc = ch.n_chunks[0];
     const double lam = lam2[0];
-    const int64_t wstride = (int64_t)gridDim.x * 4;
-    for (int64_t item = (int64_t)blockIdx.x * 4 + wv; item < nc; item += wstride) {
+    // Workgroups go to the 8 XCDs in turn (block b to XCD b mod 8), and each XCD
+    // has its own L2.  XCD x takes the contiguous eighth [x nc / 8, (x + 1) nc / 8)
+    // of the items (chunks in camera-pair order), so the blocks of one camera row,
+    // which read that camera's records again, run on one XCD at about the same time.
+    const unsigned x = blockIdx.x & 7u;
+    const int64_t nwg_x = ((int64_t)gridDim.x - (int64_t)x + 7) / 8;   // workgroups on XCD x
+    const int64_t lo = (int64_t)x * nc / 8, hi = ((int64_t)x + 1) * nc / 8;
+    const int64_t wstride = nwg_x * 4;
+    for (int64_t item = lo + (int64_t)(blockIdx.x >> 3) * 4 + wv; item < hi; item += wstride) {
         const int32_t bk = ch.chunk_blk[item];
         const int2 key = blk_key[bk];
         const int32_t r = key.x, c = key.y;
@@ -1354,7 +1361,7 @@ hipError_t launch_schur(const int64_t *n_blocks, int64_t n_blocks_cap, const Sch
                         double *b, hipStream_t st) {
     int64_t wgs = (ch.chunk_cap + 3) / 4;
     if (wgs > 16384) wgs = 16384;
-    if (wgs < 1) wgs = 1;
+    wgs = ((wgs < 8 ? 8 : wgs) + 7) / 8 * 8;   // every XCD gets its share of workgroups
     k_schur<T><<<(unsigned)wgs, 256, 0, st>>>(ch, blk_key, blk_start, pairs, cam_cluster, l, cam_local, cl_Np,
                                               S_off, seg_head, Jc, obsd, lam2, S, b);
     int64_t rb = n_blocks_cap;
