@@ -1088,6 +1088,70 @@ __global__ __launch_bounds__(256) void k_backsub(int32_t n, const int64_t *__res
     for (int k = 0; k < 3; ++k) dpt[3 * j + k] = d[k];
 }
 
+// a6 with one lane per observation, in the groups of k_points_obs (whole points,
+// at most 64 observations per wavefront): lane o forms J_p,o^T (J_c,o dc) of its
+// camera, and the first lane of each point subtracts its point's terms from w_j
+// in observation order (the order of k_backsub), then dp_j = V*_j^-1 (w_j - ...).
+template <typename T>
+__global__ __launch_bounds__(64 * kPtWaves) void k_backsub_obs(int64_t ngroups, const int32_t *__restrict__ grp_first,
+                                                               const int64_t *__restrict__ pt_off,
+                                                               const int32_t *__restrict__ obs_pt,
+                                                               const int32_t *__restrict__ obs_cam,
+                                                               const T *__restrict__ Jc, const T *__restrict__ Jp,
+                                                               const double *__restrict__ Vinv,
+                                                               const double *__restrict__ wph,
+                                                               const double *__restrict__ dcam, double *__restrict__ dpt) {
+    __shared__ double sT[kPtWaves][3][64];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int64_t g = (int64_t)blockIdx.x * kPtWaves + wv;
+    if (g >= ngroups) return;
+    const int32_t pa = grp_first[g];
+    int32_t pb = grp_first[g + 1];
+    if (pb < 0) pb = grp_first[ngroups];
+    if (pa < 0 || pb < pa) return;
+    const int64_t o0 = pt_off[pa], o1 = pt_off[pb];
+    if (o1 - o0 > 64) return;   // reported by k_points_obs
+    const int cnt = (int)(o1 - o0);
+    const bool act = lane < cnt;
+    const int64_t a = o0 + (act ? lane : 0);
+    const int32_t j = obs_pt[a];
+    const int32_t cam = obs_cam[a];
+    double jc[18], jp[6];
+#pragma unroll
+    for (int k = 0; k < 18; ++k) jc[k] = (double)Jc[18 * a + k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) jp[k] = (double)Jp[6 * a + k];
+    const double *dc = dcam + 9 * (int64_t)cam;
+    double t0 = 0.0, t1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const double d = dc[k];
+        t0 += jc[k] * d;
+        t1 += jc[9 + k] * d;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) sT[wv][k][lane] = act ? jp[k] * t0 + jp[3 + k] * t1 : 0.0;
+    const int32_t jprev = __shfl(j, lane > 0 ? lane - 1 : 0, 64);
+    const bool start = act && (lane == 0 || j != jprev);
+    const uint64_t starts = __ballot(start);
+    __syncwarp();
+    if (!start) return;
+    const uint64_t after = starts & (lane == 63 ? 0ull : ~((2ull << lane) - 1));
+    const int last = after != 0 ? __builtin_ctzll(after) : cnt;
+    double gv[3] = {wph[3 * (int64_t)j], wph[3 * (int64_t)j + 1], wph[3 * (int64_t)j + 2]};
+    for (int b = lane; b < last; ++b)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) gv[k] -= sT[wv][k][b];
+    double Vi[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) Vi[k] = Vinv[6 * (int64_t)j + k];
+    double d[3];
+    sym3_mul(Vi, gv, d);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dpt[3 * (int64_t)j + k] = d[k];
+}
+
 // a7: cost at the candidate x + dx in FP64 (block partial sums).
 __global__ __launch_bounds__(256) void k_cost_at(int64_t q, const double *__restrict__ cam,
                                                  const double *__restrict__ pt, const int32_t *__restrict__ oc,
@@ -1382,14 +1446,23 @@ template hipError_t launch_schur<float>(const int64_t *, int64_t, const SchurChu
 
 template <typename T>
 hipError_t launch_backsub(const stba_problem &p, const int64_t *pt_off, const T *Jc, const T *Jp,
-                          const double *Vinv, const double *wph, const double *dcam, double *dpt, hipStream_t st) {
+                          const double *Vinv, const double *wph, const double *dcam, double *dpt,
+                          int32_t group_size, const int32_t *grp_first, hipStream_t st) {
+    if (group_size > 0) {
+        const int64_t ng = (p.q + group_size - 1) / group_size;
+        k_backsub_obs<T><<<(unsigned)((ng + kPtWaves - 1) / kPtWaves), 64 * kPtWaves, 0, st>>>(
+            ng, grp_first, pt_off, p.obs_pt, p.obs_cam, Jc, Jp, Vinv, wph, dcam, dpt);
+        return hipGetLastError();
+    }
     k_backsub<T><<<grid_for(p.n), 256, 0, st>>>(p.n, pt_off, p.obs_cam, Jc, Jp, Vinv, wph, dcam, dpt);
     return hipGetLastError();
 }
 template hipError_t launch_backsub<double>(const stba_problem &, const int64_t *, const double *, const double *,
-                                           const double *, const double *, const double *, double *, hipStream_t);
+                                           const double *, const double *, const double *, double *, int32_t,
+                                           const int32_t *, hipStream_t);
 template hipError_t launch_backsub<float>(const stba_problem &, const int64_t *, const float *, const float *,
-                                          const double *, const double *, const double *, double *, hipStream_t);
+                                          const double *, const double *, const double *, double *, int32_t,
+                                          const int32_t *, hipStream_t);
 
 hipError_t launch_cost_at(const stba_problem &p, const double *dcam, const double *dpt, double *partials,
                           const stba_lm_state *s, double *F_ref, hipStream_t st) {

@@ -121,8 +121,10 @@ hipError_t launch_refine(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, c
                          const double *b, double *dcam, double *rbuf, int32_t max_Np, hipStream_t st);
 
 template <typename T>
+// group_size > 0: one lane per observation in the groups of launch_points
 hipError_t launch_backsub(const stba_problem &p, const int64_t *pt_off, const T *Jc, const T *Jp,
-                          const double *Vinv, const double *wph, const double *dcam, double *dpt, hipStream_t st);
+                          const double *Vinv, const double *wph, const double *dcam, double *dpt,
+                          int32_t group_size, const int32_t *grp_first, hipStream_t st);
 
 // F_ref (nullable, 2 doubles): receives s->F and s->have_F for launch_accept_update
 hipError_t launch_cost_at(const stba_problem &p, const double *dcam, const double *dpt, double *partials,

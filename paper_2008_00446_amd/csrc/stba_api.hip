@@ -221,7 +221,7 @@ int solve_impl(const stba_problem *p, const stba_dims *d, int32_t l, const T *Jc
     (void)d;
     STBA_TRY(cluster_solve<T>(l, dcam, cl_status, L, ws, st));
     STBA_HIP(launch_backsub<T>(*p, at<int64_t>(ws, L.pt_off), Jc, Jp, at<double>(ws, L.Vinv), at<double>(ws, L.wph),
-                               dcam, dpt, st));
+                               dcam, dpt, L.group_size, at<int32_t>(ws, L.grp_first), st));
     return STBA_OK;
 }
 
@@ -267,7 +267,7 @@ int lm_step_impl(const stba_problem *p, const stba_dims *d, const stba_sample *s
     STBA_TRY(cluster_solve<T>(s->l, dcam, at<int32_t>(ws, L.cl_status), L, ws, st));
     STBA_TRY(mark(6));
     STBA_HIP(launch_backsub<T>(*p, at<int64_t>(ws, L.pt_off), Jc, Jp, at<double>(ws, L.Vinv), at<double>(ws, L.wph),
-                               dcam, dpt, st));
+                               dcam, dpt, L.group_size, at<int32_t>(ws, L.grp_first), st));
     STBA_TRY(mark(7));
     double *rj_part = at<double>(ws, L.partials), *cost_part = rj_part + L.n_partials;
     double *F_ref = cost_part + L.n_partials;
