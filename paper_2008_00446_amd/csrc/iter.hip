@@ -235,6 +235,8 @@ __global__ __launch_bounds__(256) void k_rj(int64_t q, const double *__restrict_
                                             T *__restrict__ Jp, double *__restrict__ partials,
                                             const int32_t *need_jac, int32_t *jac_ran, ZeroS z, double huber) {
     __shared__ double sh[256];
+    __shared__ T sJc[256 * 18];
+    __shared__ T sJp[256 * 6];
     if (z.S != nullptr) {
         // S and b of this iteration start from zero (the grid runs even when the
         // Jacobian is kept)
@@ -265,20 +267,26 @@ __global__ __launch_bounds__(256) void k_rj(int64_t q, const double *__restrict_
         const double rw = huber_root_weight(s2, huber);   // 1 for the squared loss
         f[2 * o] = (T)(rw * f0);
         f[2 * o + 1] = (T)(rw * f1);
-        if (Jc != nullptr) {
-            T *dc = Jc + 18 * o;
+        // the blocks go through LDS: the block's J_c and J_p are contiguous in
+        // memory, written back below with consecutive lanes on consecutive elements
+        const int tl = threadIdx.x;
 #pragma unroll
-            for (int r = 0; r < 2; ++r)
+        for (int r = 0; r < 2; ++r)
 #pragma unroll
-                for (int k = 0; k < 9; ++k) dc[9 * r + k] = (T)(rw * jc[r][k]);
-        }
-        if (Jp != nullptr) {
-            T *dp = Jp + 6 * o;
+            for (int k = 0; k < 9; ++k) sJc[18 * tl + 9 * r + k] = (T)(rw * jc[r][k]);
 #pragma unroll
-            for (int r = 0; r < 2; ++r)
+        for (int r = 0; r < 2; ++r)
 #pragma unroll
-                for (int k = 0; k < 3; ++k) dp[3 * r + k] = (T)(rw * jp[r][k]);
-        }
+            for (int k = 0; k < 3; ++k) sJp[6 * tl + 3 * r + k] = (T)(rw * jp[r][k]);
+    }
+    {
+        const int64_t ob = (int64_t)blockIdx.x * blockDim.x;
+        const int nv = (int)min((int64_t)blockDim.x, q - ob);   // observations of this block
+        __syncthreads();
+        if (Jc != nullptr)
+            for (int i = threadIdx.x; i < 18 * nv; i += blockDim.x) Jc[18 * ob + i] = sJc[i];
+        if (Jp != nullptr)
+            for (int i = threadIdx.x; i < 6 * nv; i += blockDim.x) Jp[6 * ob + i] = sJp[i];
     }
     if (partials != nullptr) {
         const double s = block_sum_256(sq, sh);

@@ -342,3 +342,28 @@ def test_long_tracks_use_thread_per_point_path():
     assert np.all(cs == 0)
     assert rel(dcam, ref.dcam) < 1e-9
     assert rel(dpt, ref.dpt) < 1e-9
+
+
+@pytest.mark.parametrize("path", ["tile", "workgroup"])
+def test_non_positive_definite_cluster_is_reported(path):
+    """A cluster system made indefinite (its first diagonal entry set to -1 after
+    the assembly) reports STBA_ENOTPD from the device, in the tile-parallel and in
+    the one-workgroup-per-cluster factorisation, while every other cluster's step
+    still matches the oracle."""
+    s = _small()
+    lab = _sgc(s, 12, 1) if path == "tile" else np.arange(s.m, dtype=np.int32)
+    g = GpuProblem(s, gamma_max=12 if path == "tile" else s.m)
+    f, Jc, Jp, _ = g.residual_jacobian()
+    rcs = g.build(f, Jc, Jp, lab, 1e-3)
+    torch.cuda.synchronize()
+    S_off = ws_view(g.ws, rcs.S_off, torch.int64, rcs.l + 1).cpu().numpy()
+    Sbuf = ws_view(g.ws, rcs.S, torch.float64, int(S_off[rcs.l]))
+    bad = 1
+    Sbuf[int(S_off[bad])] = -1.0   # entry (0, 0) of cluster 1 (column-major)
+    torch.cuda.synchronize()
+    dcam, dpt, cs = g.solve(rcs, Jc, Jp)
+    assert cs[bad] == -2                                   # STBA_ENOTPD
+    assert np.all(np.delete(cs, bad) == 0)
+    ref = O.stba_step(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv, lab, 1e-3)
+    good = lab != bad
+    assert rel(dcam[good], ref.dcam[good]) < 1e-9
