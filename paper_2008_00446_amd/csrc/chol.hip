@@ -203,13 +203,13 @@ __device__ __forceinline__ bool band_factor_invert(double *A, int64_t Np, int64_
             }
             __builtin_amdgcn_sched_barrier(0);
             // the next pivot (lane k+1's own entries only) while the column
-            // reads are in flight, and step k-1's deferred updates
-            double dn = readlane_d(t, k + 1);
-            if (!(dn > 0.0) || !isfinite(dn)) {
-                bad = true;
-                dn = 1.0;
-            }
-            const double is_next = rsqrt_once(dn);
+            // reads are in flight, and step k-1's deferred updates: every lane
+            // takes the reciprocal square root of its own t and lane k+1's is
+            // broadcast, so the pivot check stays off this chain (a pivot that is
+            // not positive yields NaN, and the tile reports it as failed)
+            const double is_next = readlane_d(rsqrt_once(t), k + 1);
+            const double dn = readlane_d(t, k + 1);
+            bad |= !(dn > 0.0) || !isfinite(dn);
             if (k >= 1) {
 #pragma unroll
                 for (int j = k + 2; j < kNB; ++j) v[j] = fma(-vkp, lp[j], v[j]);
