@@ -836,7 +836,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             int32_t hu[kRounds], hw[kRounds];
 #pragma unroll
             for (int i = 0; i < kRounds; ++i) hu[i] = hw[i] = 0;
-            if (!diag) {
+            if (!diag && !ch.all_links) {
 #pragma unroll
                 for (int i = 0; i < kRounds; ++i) {
                     hu[i] = seg_head[(int64_t)(pr[i] >> 32)];

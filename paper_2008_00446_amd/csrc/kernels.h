@@ -84,6 +84,8 @@ struct SchurChunks {
     int64_t chunk_cap;
     double *part;          // partial sums, kSchurPart doubles per chunk
     double *S0 = nullptr;  // MIXED: every entry written to S is written here too (kept for refinement)
+    int32_t all_links = 0;  // alpha = 1: every same-cluster link is kept, so the pairs of a block
+                            // share their segment and the segment-head check is skipped
 };
 template <typename T>
 hipError_t launch_schur(const int64_t *n_blocks, int64_t n_blocks_cap, const SchurChunks &ch, const int2 *blk_key,

@@ -168,8 +168,9 @@ int front(const stba_problem *p, const stba_dims *d, int precision, void *ws, si
     return check_ws(L, ws, ws_bytes);
 }
 
-SchurChunks chunks_of(const Layout &L, void *ws) {
+SchurChunks chunks_of(const Layout &L, void *ws, const stba_sample *s) {
     SchurChunks c;
+    c.all_links = s->alpha >= 1.0 ? 1 : 0;
     c.n_chunks = at<int64_t>(ws, L.n_chunks);
     c.blk_chunk_off = at<int64_t>(ws, L.blk_chunk_off);
     c.chunk_blk = at<int32_t>(ws, L.chunk_blk);
@@ -192,7 +193,7 @@ int build_rcs_impl(const stba_problem *p, const stba_dims *d, const stba_sample 
                               at<int32_t>(ws, L.grp_first), st));
     STBA_HIP(launch_fill_S(at<double>(ws, L.S), L.mixed ? at<double>(ws, L.S0) : nullptr, at<double>(ws, L.b), p->m,
                            at<int64_t>(ws, L.S_off), s->l, L.S_cap, st));
-    STBA_HIP(launch_schur<T>(at<int64_t>(ws, L.n_blocks), L.blk_cap, chunks_of(L, ws), at<int2>(ws, L.blk_key),
+    STBA_HIP(launch_schur<T>(at<int64_t>(ws, L.n_blocks), L.blk_cap, chunks_of(L, ws, s), at<int2>(ws, L.blk_key),
                              at<int64_t>(ws, L.blk_start), at<uint64_t>(ws, L.pairs), s->cam_cluster, s->l,
                              at<int32_t>(ws, L.cam_local), at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np),
                              at<int64_t>(ws, L.S_off),
@@ -256,7 +257,7 @@ int lm_step_impl(const stba_problem *p, const stba_dims *d, const stba_sample *s
                               at<int32_t>(ws, L.grp_first), st));
     STBA_TRY(mark(3));
     STBA_TRY(mark(4));   // S was zeroed with the residuals: nothing between the marks
-    STBA_HIP(launch_schur<T>(at<int64_t>(ws, L.n_blocks), L.blk_cap, chunks_of(L, ws), at<int2>(ws, L.blk_key),
+    STBA_HIP(launch_schur<T>(at<int64_t>(ws, L.n_blocks), L.blk_cap, chunks_of(L, ws, s), at<int2>(ws, L.blk_key),
                              at<int64_t>(ws, L.blk_start), at<uint64_t>(ws, L.pairs), s->cam_cluster, s->l,
                              at<int32_t>(ws, L.cam_local), at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np),
                              at<int64_t>(ws, L.S_off),
