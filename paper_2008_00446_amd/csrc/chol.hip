@@ -1,7 +1,9 @@
-// a5: independent dense solves S_k dc_k = b_k, one workgroup per cluster
-// (Eq. 13: the decomposed reduced camera systems; the paper uses a dense LL^T
-// per cluster).  Blocked right-looking Cholesky with 32 x 32 FP64 tiles and the
-// forward substitution carried along:
+// a5: independent dense solves S_k dc_k = b_k (Eq. 13: the decomposed reduced
+// camera systems; the paper uses a dense LL^T per cluster), blocked Cholesky
+// with 32 x 32 FP64 tiles.  Matrices are column-major, padded to a multiple of
+// 32 with an identity tail.  Two forms:
+//  - k_chol, one workgroup per cluster (many clusters), right-looking with the
+//    forward substitution carried along:
 //   (a) one wavefront factors and inverts the diagonal tile in registers
 //       (W = L_pp^-1, kept in LDS and transposed in the unused upper triangle)
 //       and forward-solves its slice of the right-hand side,
@@ -10,8 +12,11 @@
 //   (c) trailing update A_ij -= L_ip L_jp^T of the lower tiles with
 //       v_mfma_f64_16x16x4_f64; the next panel's column is updated first so
 //       that its diagonal tile is factored while the other waves finish (c);
-// then the backward solve L^T x = y with the stored W^T.  Matrices are
-// column-major, padded to a multiple of 32 with an identity tail.
+//    then the backward solve L^T x = y with the stored W^T (MIXED: k_resid and
+//    k_sweep add the refinement step);
+//  - k_chol_tiles, one wavefront per tile (few clusters): a dataflow over the
+//    tiles with the substitutions, and the MIXED refinement step, in the same
+//    launch (described where it is defined).
 #include "kernels.h"
 
 namespace stba {
