@@ -32,12 +32,16 @@ point update (Eq. 14-15), the correction (Sec. 4.3) and the LM accept rule
 * accept iff F(x + dx) < F(x) strictly, the step is finite and every cluster
   system factorises; lambda /= 3 on accept and *= 3 otherwise (Alg. 1);
 * the robust loss (Sec. 5.1, optional): Huber on each observation's error norm,
-  applied by first-order (IRLS) reweighting of f and J (see `huber_rho`).
+  applied by first-order (IRLS) reweighting of f and J (see `huber_rho`);
+* stochastic graph clustering (Sec. 4.4, Eq. 16) draws one join at a time from
+  the distribution of Eq. 16 over the neighbouring pairs within the size cap,
+  sampled by competing exponential clocks keyed by Philox (see `sgc_clusters`).
 
 Parity pins live in tests/test_oracle_*.py; every function below is pinned.
 """
 from __future__ import annotations
 
+import heapq
 import math
 from dataclasses import dataclass
 
@@ -52,6 +56,7 @@ __all__ = [
     "jc_matrix", "jp_matrix", "damp", "correct_point_gradient", "correction_explicit",
     "StbaStep", "stba_step", "plain_lm_step", "full_normal_step", "relaxed_kkt_step",
     "LmResult", "lm_iteration", "cluster_layout",
+    "covisibility_graph", "sgc_uniform", "modularity_gain", "sgc_clusters",
 ]
 
 # ---------------------------------------------------------------------------
@@ -602,3 +607,114 @@ def lm_iteration(cam, pt, obs_cam, obs_pt, obs_uv, cam_cluster, lam, alpha=1.0, 
     if accepted:
         return LmResult(cam_new, pt_new, lam / 3.0, F_new, F_new, True, st)
     return LmResult(cam.copy(), pt.copy(), lam * 3.0, F, F_new, False, st)
+
+
+# ---------------------------------------------------------------------------
+# O-14: the camera graph and stochastic graph clustering (Sec. 4.4, Eq. 16)
+# ---------------------------------------------------------------------------
+
+
+def covisibility_graph(obs_cam, obs_pt, m, n):
+    """Camera graph G_c (Sec. 4.4): edge (i, j), i < j, weighted by the number of
+    points both cameras see, i.e. the off-diagonal of V V^T for the m x n
+    visibility matrix V.  Returns (edges [E,2] ascending by (i, j), weights [E])."""
+    obs_cam = np.asarray(obs_cam, dtype=np.int64)
+    obs_pt = np.asarray(obs_pt, dtype=np.int64)
+    V = sp.csr_matrix((np.ones(obs_cam.shape[0]), (obs_cam, obs_pt)), shape=(m, n))
+    W = sp.triu(V @ V.T, k=1).tocoo()
+    order = np.lexsort((W.col, W.row))
+    edges = np.stack([W.row[order], W.col[order]], axis=1).astype(np.int64)
+    return edges, np.rint(W.data[order]).astype(np.int64)
+
+
+def sgc_uniform(seed, t, k, a, b):
+    """Uniforms in (0, 1] for the clocks of cluster pairs (a, b), a < b, set at
+    join step k of LM iteration t: Philox4x64-10 with key (seed, 2) and counter
+    (t, k, a, b), u = ((x0 >> 11) + 1) 2^-53."""
+    a = np.atleast_1d(np.asarray(a, dtype=np.uint64))
+    b = np.atleast_1d(np.asarray(b, dtype=np.uint64))
+    ctr = np.stack([np.full_like(a, np.uint64(t)), np.full_like(a, np.uint64(k)), a, b], axis=1)
+    x0 = philox4x64_10(ctr, (np.uint64(seed), np.uint64(2)))[:, 0] >> np.uint64(11)
+    return (x0.astype(np.float64) + 1.0) * 2.0 ** -53
+
+
+def modularity_gain(w_xy, K_x, K_y, s):
+    """dQ of joining clusters x and y: the change of the modularity of Sec. 4.4,
+    w_xy / s - K_x K_y / (2 s^2) (K: summed incident weight, s: total weight)."""
+    return w_xy / s - (K_x * K_y) / (2.0 * s * s)
+
+
+def sgc_clusters(edges, weights, m, gamma, beta, seed, t):
+    """Stochastic graph clustering (Sec. 4.4): from singletons, repeatedly join
+    two neighbouring clusters x, y with probability exp(beta dQ(x, y)) over the
+    sum of the same over all neighbouring pairs (Eq. 16), where only pairs whose
+    joint size stays within gamma take part; stop when no such pair is left.
+
+    The draw of each join uses competing exponential clocks: every eligible
+    cluster pair holds a clock T = t_now + E / exp(beta dQ), E = -log u with u
+    from `sgc_uniform`; the pair with the smallest clock (ties: smaller a m + b
+    for the pair (a, b), a < b) joins next.  The smallest of independent
+    exponentials with rates r_p is attained at p with probability r_p / sum r,
+    and by memorylessness the clocks of pairs the join does not touch stay
+    valid, so only the pairs of the joined cluster get new clocks (drawn at
+    step k).  A cluster is named by its smallest camera, so joining y into x
+    (x < y) keeps the name x.
+
+    Returns (cam_cluster [m] int32 with clusters numbered 0..l-1 by their
+    smallest camera, l)."""
+    edges = np.asarray(edges, dtype=np.int64).reshape(-1, 2)
+    weights = np.asarray(weights, dtype=np.int64).reshape(-1)
+    adj = [dict() for _ in range(m)]
+    for (i, j), w in zip(edges.tolist(), weights.tolist()):
+        if i == j or w == 0:
+            continue
+        adj[i][j] = adj[i].get(j, 0) + w
+        adj[j][i] = adj[j].get(i, 0) + w
+    K = [sum(a.values()) for a in adj]
+    s = float(sum(K)) / 2.0
+    lab = np.arange(m, dtype=np.int64)
+    size = [1] * m
+    clock = {}
+    heap = []
+    version = [0]
+
+    def set_clocks(pairs, k, t_now):
+        if not pairs:
+            return
+        a = np.array([p[0] for p in pairs], dtype=np.int64)
+        b = np.array([p[1] for p in pairs], dtype=np.int64)
+        u = sgc_uniform(seed, t, k, a, b)
+        for (x, y, w), ui in zip(pairs, u.tolist()):
+            version[0] += 1
+            if size[x] + size[y] > gamma:
+                clock[(x, y)] = (math.inf, version[0])
+                continue
+            rate = math.exp(beta * modularity_gain(float(w), float(K[x]), float(K[y]), s))
+            T = t_now + (-math.log(ui)) / rate
+            clock[(x, y)] = (T, version[0])
+            heapq.heappush(heap, (T, x * m + y, version[0], x, y))
+
+    if s > 0.0 and gamma > 1:
+        set_clocks([(i, j, w) for i in range(m) for j, w in sorted(adj[i].items()) if i < j], 0, 0.0)
+        for k in range(1, m):
+            while heap and clock.get((heap[0][3], heap[0][4]), (None, -1))[1] != heap[0][2]:
+                heapq.heappop(heap)
+            if not heap:
+                break
+            t_now, _, _, x, y = heapq.heappop(heap)
+            # join y into x
+            del clock[(x, y)]
+            del adj[x][y]
+            del adj[y][x]
+            for z, w in adj[y].items():
+                del adj[z][y]
+                del clock[(min(y, z), max(y, z))]
+                adj[x][z] = adj[x].get(z, 0) + w
+                adj[z][x] = adj[x][z]
+            adj[y] = {}
+            size[x] += size[y]
+            K[x] += K[y]
+            lab[lab == y] = x
+            set_clocks([(min(x, z), max(x, z), w) for z, w in sorted(adj[x].items())], k, t_now)
+    names, dense = np.unique(lab, return_inverse=True)
+    return dense.astype(np.int32), int(names.shape[0])
