@@ -18,8 +18,12 @@ Jacobian and Schur assembly, FP64 Cholesky with one refinement step and FP64
 cost) from the same start and maps and compares the two at equal cost
 reduction as the performance profiles of Sec. 5.2 do: the time each needs to
 reach F_tau = F* + tau (F0 - F*) for tau = 0.1, 0.01, 0.001 (F* the lower of
-their costs after K iterations); the headline speedup is the one at 0.001.  `cpu_baseline` times the
-FP64 oracle on the host for the first iterations of the same run.
+their costs after K iterations); the headline speedup is the one at 0.001.
+`huber` runs the same iterations under the robust loss (Sec. 5.1).  `sgc` draws
+the maps on the device instead (stochastic graph clustering, Sec. 4.4): the
+clustering kernel's time per map and the iteration rate with a device map drawn
+before every step.  `cpu_baseline` times the FP64 oracle on the host for the
+first iterations of the same run.
 
 --pmc-summary turns rocprofv3 counter CSVs (FETCH_SIZE and WRITE_SIZE runs of
 this benchmark and of --copy-calibration) into profiles/pmc_<phase>_<workload>.txt,
@@ -67,6 +71,7 @@ def parse_args():
                     help="only run a plain device copy of 1 GiB (to scale HBM counters)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
     ap.add_argument("--no-huber", action="store_true", help="skip the robust-loss (Huber) leg")
+    ap.add_argument("--no-sgc", action="store_true", help="skip the device graph-clustering leg")
     ap.add_argument("--pmc-summary", action="store_true",
                     help="write a profiles/pmc_*.txt summary from counter CSVs (no GPU work)")
     ap.add_argument("--phase", default="cluster_cholesky")
@@ -331,6 +336,8 @@ def main():
                                          cam0=cam0, pt0=pt0)
     if not args.no_huber and precision == S.STBA_FP64:
         out["huber"] = huber_leg(S, scene, maps, args, lam0, cam0, pt0)
+    if not args.no_sgc and precision == S.STBA_FP64:
+        out["sgc"] = sgc_leg(S, scene, e, w, args, lam0, cam0, pt0)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, maps, lam0, args.cpu_iters)
     else:
@@ -351,6 +358,64 @@ def huber_leg(S, scene, maps, args, lam0, cam0, pt0):
     st = solh.read_state()
     return {"scale": HUBER_SCALE, "iter_per_s": args.steps / t, "obs_per_s": scene.q * args.steps / t,
             "F_after_K": st["F"], "accepted": st["n_accept"], "status": st["status"]}
+
+
+SGC_BETA = 10.0   # the clustering's scale beta
+
+
+def sgc_leg(S, scene, e, w, args, lam0, cam0, pt0):
+    """Maps drawn on the device by stochastic graph clustering (Sec. 4.4, Eq. 16):
+    the clustering kernel alone (K maps back to back, HIP events on the stream it
+    runs on), then K FP64 LM iterations each preceded by its own device map (the
+    number of clusters read back before each step), against the host harness's
+    time per map on the same camera graph."""
+    import torch
+    import synth
+    sol = S.StbaSolver(scene.cam0, scene.pt0, scene.obs_cam, scene.obs_pt, scene.obs_uv,
+                       gamma_max=args.gamma, precision=S.STBA_FP64, lambda0=lam0)
+    K = args.steps
+    cc = torch.empty(scene.m, dtype=torch.int32, device="cuda")
+    out = torch.zeros(2, dtype=torch.int32, device="cuda")
+
+    def draw(t):
+        S.stba_sample_clusters(sol.problem, sol.dims, sol.precision, sol.ws, args.gamma, SGC_BETA, 0, t, cc,
+                               out[0:1], out[1:2])
+
+    for t in range(args.warmup):
+        draw(t)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for t in range(K):
+        draw(t)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    kernel_ms = e0.elapsed_time(e1) / K
+
+    def iterations(steps):
+        sol.cam.copy_(cam0)
+        sol.pt.copy_(pt0)
+        S.stba_lm_init(sol.state, lam0, 0.1)
+        ls = []
+        for t in range(steps):
+            smp = sol.sample_clusters(args.gamma, SGC_BETA, alpha=1.0, seed=0, it=t)
+            ls.append(smp.l)
+            sol.step(smp)
+        return ls
+
+    iterations(args.warmup)
+    ls = []
+    t_iter = timed(lambda: ls.extend(iterations(K)))
+    st = sol.read_state()
+    t0 = time.perf_counter()
+    n_host = 3
+    for t in range(n_host):
+        synth.sgc_map(e, w, scene.m, args.gamma, SGC_BETA, 0, t)
+    host_ms = 1e3 * (time.perf_counter() - t0) / n_host
+    return {"beta": SGC_BETA, "cap": args.gamma, "kernel_ms_per_map": kernel_ms,
+            "iter_per_s_with_device_maps": K / t_iter, "clusters_mean": float(np.mean(ls)),
+            "F_after_K": st["F"], "status": st["status"], "host_harness_ms_per_map": host_ms}
 
 
 TAUS = (0.1, 0.01, 0.001)

@@ -3,7 +3,8 @@
  *
  * Method: L. Zhou et al., "Stochastic Bundle Adjustment for Efficient and Scalable
  * 3D Reconstruction", ECCV 2020 (arXiv 2008.00446).  One LM iteration of STBA
- * (Alg. 1) is: residuals and Jacobian (Sec. 3), the sampled constraint set as
+ * (Alg. 1) is: the camera clustering (Sec. 4.4, optionally drawn on the device),
+ * residuals and Jacobian (Sec. 3), the sampled constraint set as
  * point segments (Sec. 4.1-4.2), the optional steepest-descent correction
  * (Sec. 4.3), one reduced camera system per camera cluster from the clustered
  * Schur complement S' = B - E' C'^-1 E'^T (Eq. 10, 13), independent dense
@@ -188,6 +189,31 @@ int stba_build_cluster_rcs(const stba_problem *p, const stba_dims *dims, const s
 int stba_solve_clusters(const stba_problem *p, const stba_dims *dims, const stba_rcs *rcs, int precision,
                         const void *Jc, const void *Jp, double *dcam, double *dpt,
                         int32_t *cluster_status, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Draw the camera clustering {Phi_k} of LM iteration `iter` by stochastic graph
+ * clustering (Sec. 4.4, Eq. 16) on the device.  The camera graph weighs the
+ * edge (i, j) by the number of points both cameras see (read from the plan of
+ * stba_prepare).  From singletons, two neighbouring clusters x, y whose joint
+ * size stays within gamma join with probability exp(beta dQ(x, y)) over the sum
+ * of the same over all such pairs, dQ = w_xy / s - K_x K_y / (2 s^2) the
+ * modularity gain (w_xy: weight between x and y, K: summed incident weight, s:
+ * total weight); joining stops when no such pair is left.  The joins are drawn
+ * by competing exponential clocks (same law): each eligible pair (a, b), a < b
+ * the clusters' smallest cameras, holds T = t + E / exp(beta dQ) with E = -log u,
+ * u = ((x0 >> 11) + 1) 2^-53 and x0 word 0 of Philox4x64-10 with key (seed, 2),
+ * counter (iter, join step, a, b); the smallest T (ties: smaller (a, b)) joins,
+ * and the pairs of the joined cluster draw new clocks at the next step.
+ *   gamma: size cap, 1 <= gamma <= dims->gamma_max (so the map can be passed to
+ *     the per-iteration calls of this workspace); beta >= 0, finite.
+ *   cam_cluster [m] (device int32): cluster of each camera, numbered 0..l-1 in
+ *     order of each cluster's smallest camera.  n_clusters (device int32): l.
+ *   status (device int32): STBA_OK once the map is written.
+ * Requires p->m <= 2048 (the clustering runs in one workgroup) and stba_prepare.
+ * Uses the workspace's plan buffers that only stba_prepare writes; asynchronous
+ * (one kernel).  To fill a stba_sample the caller reads n_clusters back. */
+int stba_sample_clusters(const stba_problem *p, const stba_dims *dims, int precision, void *ws, size_t ws_bytes,
+                         int32_t gamma, double beta, uint64_t seed, uint64_t iter, int32_t *cam_cluster,
+                         int32_t *n_clusters, int32_t *status, hipStream_t stream);
 
 /* Initialise a device stba_lm_state (lambda0, lambda_corr, need_jac = 1). */
 int stba_lm_init(stba_lm_state *st, double lambda0, double lambda_corr, hipStream_t stream);

@@ -75,6 +75,8 @@ _SIGS = {
     "stba_build_cluster_rcs": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, _P, _P, _P, _P, _P,
                                               ctypes.c_size_t, _P]),
     "stba_solve_clusters": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "stba_sample_clusters": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, ctypes.c_size_t, ctypes.c_int32,
+                                            ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64, _P, _P, _P, _P]),
     "stba_lm_init": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double, _P]),
     "stba_lm_step": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, _P, ctypes.c_size_t, _P]),
     "stba_lm_step_profiled": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, _P, ctypes.c_size_t, _P, _P]),
@@ -207,6 +209,14 @@ def stba_solve_clusters(problem, dims, rcs, precision, Jc, Jp, dcam, dpt, cluste
     _check("stba_solve_clusters", load_library().stba_solve_clusters(
         _ref(problem), _ref(dims), _ref(rcs), precision, _ptr(Jc), _ptr(Jp), _ptr(dcam), _ptr(dpt),
         _ptr(cluster_status), _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def stba_sample_clusters(problem, dims, precision, ws, gamma, beta, seed, it, cam_cluster, n_clusters, status,
+                         stream=None):
+    """Device stochastic graph clustering; cam_cluster [m], n_clusters [1], status [1] int32 tensors."""
+    _check("stba_sample_clusters", load_library().stba_sample_clusters(
+        _ref(problem), _ref(dims), precision, _ptr(ws), ws.numel(), int(gamma), float(beta), int(seed), int(it),
+        _ptr(cam_cluster), _ptr(n_clusters), _ptr(status), _stream(stream)))
 
 
 def stba_lm_init(state, lambda0, lambda_corr=0.1, stream=None):

@@ -143,4 +143,11 @@ hipError_t launch_vjp(const stba_problem &p, const int64_t *pt_off, const int64_
                       const int2 *blk_key, const int64_t *blk_start, const uint64_t *pairs, const T *v,
                       T *grad_cam, T *grad_pt, T *grad_uv, hipStream_t st);
 
+// --- camera clustering (sgc.hip) ---------------------------------------------
+// One workgroup; Pg / Tg / Wg hold a pair label, clock and weight per block of
+// the Schur plan (at least n_blocks each) when the graph has more than 4096 blocks.
+hipError_t launch_sgc(int32_t m, const int64_t *n_blocks, const int2 *blk_key, const int64_t *blk_start,
+                      int32_t gamma, double beta, uint64_t seed, uint64_t iter, uint32_t *Pg, double *Tg,
+                      int32_t *Wg, int32_t *cam_cluster, int32_t *n_clusters, int32_t *status, hipStream_t st);
+
 }  // namespace stba

@@ -77,6 +77,8 @@ bool make_layout(const stba_problem *p, const stba_dims *d, int precision, Layou
     L.lam2 = take(2 * sizeof(double));
     L.pt_off = take(8 * (n + 1));
     L.pair_off = take(8 * (n + 1));
+    // scratch_a, keys_in and vals_in serve stba_prepare only; afterwards the
+    // device camera clustering keeps its pair labels, clocks and weights there
     L.scratch_a = take(8 * np);
     L.keys_in = take(8 * (np + 1));
     L.keys_out = take(8 * np);
@@ -407,6 +409,22 @@ int stba_solve_clusters(const stba_problem *p, const stba_dims *dims, const stba
     if (precision == STBA_FP64)
         return solve_impl<double>(p, dims, rcs->l, (const double *)Jc, (const double *)Jp, dcam, dpt, cs, L, ws, stream);
     return solve_impl<float>(p, dims, rcs->l, (const float *)Jc, (const float *)Jp, dcam, dpt, cs, L, ws, stream);
+}
+
+int stba_sample_clusters(const stba_problem *p, const stba_dims *dims, int precision, void *ws, size_t ws_bytes,
+                         int32_t gamma, double beta, uint64_t seed, uint64_t iter, int32_t *cam_cluster,
+                         int32_t *n_clusters, int32_t *status, hipStream_t stream) {
+    Layout L;
+    STBA_TRY(front(p, dims, precision, ws, ws_bytes, L));
+    if (p->m > kSgcMaxCams || gamma < 1 || gamma > dims->gamma_max || !(beta >= 0.0) || !std::isfinite(beta))
+        return STBA_EINVAL;
+    if (!cam_cluster || !n_clusters || !status) return STBA_EINVAL;
+    // pair labels, clocks and weights per block (at most n_pairs blocks) live in
+    // plan buffers that only stba_prepare uses
+    STBA_HIP(launch_sgc(p->m, at<int64_t>(ws, L.n_blocks), at<int2>(ws, L.blk_key), at<int64_t>(ws, L.blk_start),
+                        gamma, beta, seed, iter, at<uint32_t>(ws, L.scratch_a), at<double>(ws, L.keys_in),
+                        at<int32_t>(ws, L.vals_in), cam_cluster, n_clusters, status, stream));
+    return STBA_OK;
 }
 
 int stba_lm_init(stba_lm_state *st, double lambda0, double lambda_corr, hipStream_t stream) {

@@ -38,6 +38,7 @@ class StbaSolver:
         self.state = B.new_state(device)
         B.stba_lm_init(self.state, lambda0, lambda_corr)
         self._events = None
+        self._sgc = None
 
     @property
     def m(self):
@@ -52,6 +53,22 @@ class StbaSolver:
             np.asarray(cam_cluster, dtype=np.int32)).to(self.cam.device)
         if l is None:
             l = int(np.asarray(cam_cluster.cpu() if torch.is_tensor(cam_cluster) else cam_cluster).max()) + 1
+        return B.make_sample(cc, l, alpha, seed, it)
+
+    def sample_clusters(self, gamma, beta=10.0, alpha=1.0, seed=0, it=0, stream=None):
+        """Draw iteration `it`'s camera clustering on the device (stochastic graph
+        clustering, cap gamma) and return the sample for `step`.  The map stays on
+        the device; only l is read back (the call waits for the kernel).  The map
+        buffer is reused by the next call, after the work queued before it."""
+        if self._sgc is None:
+            self._sgc = (torch.empty(self.m, dtype=torch.int32, device=self.cam.device),
+                         torch.zeros(2, dtype=torch.int32, device=self.cam.device))
+        cc, out = self._sgc
+        B.stba_sample_clusters(self.problem, self.dims, self.precision, self.ws, gamma, beta, seed, it, cc,
+                               out[0:1], out[1:2], stream)
+        l, status = (int(v) for v in out.cpu().tolist())
+        if status != 0:
+            raise B.StbaError("stba_sample_clusters", status)
         return B.make_sample(cc, l, alpha, seed, it)
 
     def step(self, sample, events=None):
