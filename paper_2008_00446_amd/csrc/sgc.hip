@@ -34,6 +34,9 @@ constexpr int kSgcThreads = 1024;
 constexpr int kSgcWaves = kSgcThreads / 64;
 constexpr uint32_t kSgcDead = 0xFFFFFFFFu;
 constexpr int kSgcRegSlots = 4;   // pair slots per thread kept in registers (graphs of <= 4096 blocks)
+constexpr int kSgcBatch = 8;      // slots whose labels one round trip reads (larger graphs)
+constexpr int kSgcAffList = 4;    // touched slots a thread remembers between the two phases (larger graphs)
+constexpr int kSgcCompactEvery = 16;   // joins between two packings of the live slots (larger graphs)
 
 struct SgcShared {
     int32_t lab[kSgcMaxCams];      // cluster name of each camera
@@ -90,30 +93,73 @@ __device__ inline void block_argmin(double t, uint32_t p, SgcShared &sh, double 
 
 // The join sequence.  kRegs: at most S pair slots per thread, labels, weights
 // and clocks in registers (loops unrolled); else any number of slots, all three
-// in Pg / Wg / Tg (indexed by block, slot r of thread t is block 1024 r + t).
+// in Pg / Wg / Tg (indexed by block, slot r of thread t is block 1024 r + t),
+// the labels read kSgcBatch slots per round trip.
 template <int S, bool kRegs>
 __device__ void sgc_joins(int32_t m, int64_t nb, const int2 *blk_key, const int64_t *blk_start, int32_t gamma,
                           double beta, uint64_t seed, uint64_t iter, uint32_t *Pg, double *Tg, int32_t *Wg,
                           SgcShared &sh) {
     const int tid = threadIdx.x;
     const int nslots = (int)((nb + kSgcThreads - 1) / kSgcThreads);
-    const int nloop = kRegs ? S : nslots;
-    constexpr int kUnroll = kRegs ? S : 1;
+    int nlive = nslots;   // larger graphs: this thread's slots in use, live ones packed to the front
     uint32_t Pr[kRegs ? S : 1];
     int32_t Wr[kRegs ? S : 1];
     double Tr[kRegs ? S : 1];
-    auto pref = [&](int r) -> uint32_t & { return kRegs ? Pr[kRegs ? r : 0] : Pg[r * kSgcThreads + tid]; };
-    auto wref = [&](int r) -> int32_t & { return kRegs ? Wr[kRegs ? r : 0] : Wg[r * kSgcThreads + tid]; };
-    auto tref = [&](int r) -> double & { return kRegs ? Tr[kRegs ? r : 0] : Tg[r * kSgcThreads + tid]; };
+    auto gidx = [&](int r) { return r * kSgcThreads + tid; };
+    auto wref = [&](int r) -> int32_t & { return kRegs ? Wr[kRegs ? r : 0] : Wg[gidx(r)]; };
+    auto tref = [&](int r) -> double & { return kRegs ? Tr[kRegs ? r : 0] : Tg[gidx(r)]; };
+    // f(r, P) -> the new label of the live slot r (P itself keeps it)
+    auto for_live = [&](auto f) {
+        if constexpr (kRegs) {
+#pragma unroll
+            for (int r = 0; r < S; ++r)
+                if (Pr[r] != kSgcDead) Pr[r] = f(r, Pr[r]);
+        } else {
+            for (int r0 = 0; r0 < nlive; r0 += kSgcBatch) {
+                uint32_t Pb[kSgcBatch];
+#pragma unroll
+                for (int j = 0; j < kSgcBatch; ++j) Pb[j] = r0 + j < nlive ? Pg[gidx(r0 + j)] : kSgcDead;
+#pragma unroll
+                for (int j = 0; j < kSgcBatch; ++j) {
+                    if (Pb[j] == kSgcDead) continue;
+                    const uint32_t Pn = f(r0 + j, Pb[j]);
+                    if (Pn != Pb[j]) Pg[gidx(r0 + j)] = Pn;
+                }
+            }
+        }
+    };
+    // the smallest (clock, label) over the live slots of this thread
+    auto local_min = [&](double &tmin, uint32_t &pmin) {
+        tmin = INFINITY;
+        pmin = kSgcDead;
+        if constexpr (kRegs) {
+#pragma unroll
+            for (int r = 0; r < S; ++r)
+                if (Pr[r] != kSgcDead && clock_less(Tr[r], Pr[r], tmin, pmin)) {
+                    tmin = Tr[r];
+                    pmin = Pr[r];
+                }
+        } else {
+            for (int r0 = 0; r0 < nlive; r0 += kSgcBatch) {
+                uint32_t Pb[kSgcBatch];
+                double Tb[kSgcBatch];
+#pragma unroll
+                for (int j = 0; j < kSgcBatch; ++j) Pb[j] = r0 + j < nlive ? Pg[gidx(r0 + j)] : kSgcDead;
+#pragma unroll
+                for (int j = 0; j < kSgcBatch; ++j) Tb[j] = Pb[j] != kSgcDead ? Tg[gidx(r0 + j)] : INFINITY;
+#pragma unroll
+                for (int j = 0; j < kSgcBatch; ++j)
+                    if (Pb[j] != kSgcDead && clock_less(Tb[j], Pb[j], tmin, pmin)) {
+                        tmin = Tb[j];
+                        pmin = Pb[j];
+                    }
+            }
+        }
+    };
 
     long long my_s = 0;
-#pragma unroll kUnroll
-    for (int r = 0; r < nloop; ++r) {
+    for (int r = 0; r < (kRegs ? S : nslots); ++r) {
         const int64_t b = (int64_t)r * kSgcThreads + tid;
-        if (r >= nslots) {
-            pref(r) = kSgcDead;
-            continue;
-        }
         uint32_t P = kSgcDead;
         if (b < nb) {
             const int2 key = blk_key[b];
@@ -126,7 +172,10 @@ __device__ void sgc_joins(int32_t m, int64_t nb, const int2 *blk_key, const int6
                 my_s += w;
             }
         }
-        pref(r) = P;
+        if constexpr (kRegs)
+            Pr[kRegs ? r : 0] = P;
+        else
+            Pg[gidx(r)] = P;
     }
     for (int off = 32; off > 0; off >>= 1) my_s += __shfl_xor(my_s, off);
     if ((tid & 63) == 0 && my_s) atomicAdd(&sh.s_tot, (unsigned long long)my_s);
@@ -135,31 +184,40 @@ __device__ void sgc_joins(int32_t m, int64_t nb, const int2 *blk_key, const int6
     const bool any = s > 0.0 && gamma > 1;
 
     // initial clocks (join step 0, time 0)
-    double tmin = INFINITY;
-    uint32_t pmin = kSgcDead;
-#pragma unroll kUnroll
-    for (int r = 0; r < nloop; ++r) {
-        const uint32_t P = pref(r);
-        if (P == kSgcDead) continue;
-        if (!any) {
-            pref(r) = kSgcDead;
-            continue;
-        }
+    for_live([&](int r, uint32_t P) -> uint32_t {
+        if (!any) return kSgcDead;
         const int32_t a = (int32_t)(P >> 16), b = (int32_t)(P & 0xFFFFu);
-        const double T = pair_clock(a, b, wref(r), sh.K[a], sh.K[b], s, beta, seed, iter, 0, 0.0);
-        tref(r) = T;
-        if (clock_less(T, P, tmin, pmin)) {
-            tmin = T;
-            pmin = P;
-        }
-    }
-    double gt;
-    uint32_t gp;
+        tref(r) = pair_clock(a, b, wref(r), sh.K[a], sh.K[b], s, beta, seed, iter, 0, 0.0);
+        return P;
+    });
+    double tmin, gt;
+    uint32_t pmin, gp;
+    local_min(tmin, pmin);
     block_argmin(tmin, pmin, sh, gt, gp);
 
     for (int32_t k = 1; k < m && gt < INFINITY; ++k) {
         const int32_t x = (int32_t)(gp >> 16), y = (int32_t)(gp & 0xFFFFu);
         const double t_now = gt;
+        if (!kRegs && (k & (kSgcCompactEvery - 1)) == 0) {
+            // pack this thread's live slots to the front (label, weight and clock move together)
+            int w = 0;
+            for (int r0 = 0; r0 < nlive; r0 += kSgcBatch) {
+                uint32_t Pb[kSgcBatch];
+#pragma unroll
+                for (int j = 0; j < kSgcBatch; ++j) Pb[j] = r0 + j < nlive ? Pg[gidx(r0 + j)] : kSgcDead;
+#pragma unroll
+                for (int j = 0; j < kSgcBatch; ++j) {
+                    if (Pb[j] == kSgcDead) continue;
+                    if (w != r0 + j) {
+                        Pg[gidx(w)] = Pb[j];
+                        Wg[gidx(w)] = Wg[gidx(r0 + j)];
+                        Tg[gidx(w)] = Tg[gidx(r0 + j)];
+                    }
+                    ++w;
+                }
+            }
+            nlive = w;
+        }
         // (A) join y into x; the pairs of x and y meet per neighbour z
         if (tid == 0) {
             sh.csize[x] += sh.csize[y];
@@ -168,47 +226,43 @@ __device__ void sgc_joins(int32_t m, int64_t nb, const int2 *blk_key, const int6
         for (int32_t i = tid; i < m; i += kSgcThreads)
             if (sh.lab[i] == y) sh.lab[i] = x;
         bool rescan = pmin == gp;
-#pragma unroll kUnroll
-        for (int r = 0; r < nloop; ++r) {
-            const uint32_t P = pref(r);
-            if (P == kSgcDead) continue;
+        // the slots of this thread that touch x or y (the first kSgcAffList of them)
+        int naff = 0;
+        int affr[kSgcAffList];
+        for_live([&](int r, uint32_t P) -> uint32_t {
+            if (P == gp) return kSgcDead;
             const int32_t a = (int32_t)(P >> 16), b = (int32_t)(P & 0xFFFFu);
-            if (P == gp) {
-                pref(r) = kSgcDead;
-            } else if (a == x || a == y || b == x || b == y) {
+            if (a == x || a == y || b == x || b == y) {
                 const int32_t z = (a == x || a == y) ? b : a;
                 rescan |= P == pmin;
-                atomicMin(&sh.slot[z], r * kSgcThreads + tid);
+                atomicMin(&sh.slot[z], gidx(r));
                 atomicAdd(&sh.wacc[z], wref(r));
+                if (!kRegs) {
+#pragma unroll
+                    for (int i = 0; i < kSgcAffList; ++i)
+                        if (naff == i) affr[i] = r;
+                    ++naff;
+                }
             }
-        }
+            return P;
+        });
         __syncthreads();
         // (B) one survivor per neighbour takes the summed weight and a new clock
         bool fresh = false;
         double fT = INFINITY;
         uint32_t fP = kSgcDead;
-#pragma unroll kUnroll
-        for (int r = 0; r < nloop; ++r) {
-            const uint32_t P = pref(r);
-            if (P == kSgcDead) continue;
+        auto survive = [&](int r, uint32_t P) -> uint32_t {
             const int32_t a = (int32_t)(P >> 16), b = (int32_t)(P & 0xFFFFu);
-            if (!(a == x || a == y || b == x || b == y)) continue;
+            if (!(a == x || a == y || b == x || b == y)) return P;
             const int32_t z = (a == x || a == y) ? b : a;
-            if (sh.slot[z] != r * kSgcThreads + tid) {
-                pref(r) = kSgcDead;
-                continue;
-            }
+            if (sh.slot[z] != gidx(r)) return kSgcDead;
             const int32_t w = sh.wacc[z];
             sh.slot[z] = INT_MAX;
             sh.wacc[z] = 0;
-            if (sh.csize[x] + sh.csize[z] > gamma) {
-                pref(r) = kSgcDead;
-                continue;
-            }
+            if (sh.csize[x] + sh.csize[z] > gamma) return kSgcDead;
             const int32_t lo = x < z ? x : z, hi = x < z ? z : x;
             const uint32_t Pn = ((uint32_t)lo << 16) | (uint32_t)hi;
             const double T = pair_clock(lo, hi, w, sh.K[lo], sh.K[hi], s, beta, seed, iter, k, t_now);
-            pref(r) = Pn;
             wref(r) = w;
             tref(r) = T;
             fresh = true;
@@ -216,21 +270,24 @@ __device__ void sgc_joins(int32_t m, int64_t nb, const int2 *blk_key, const int6
                 fT = T;
                 fP = Pn;
             }
-        }
-        if (rescan) {
-            tmin = INFINITY;
-            pmin = kSgcDead;
-#pragma unroll kUnroll
-            for (int r = 0; r < nloop; ++r) {
-                const uint32_t P = pref(r);
-                if (P == kSgcDead) continue;
-                const double T = tref(r);
-                if (clock_less(T, P, tmin, pmin)) {
-                    tmin = T;
-                    pmin = P;
+            return Pn;
+        };
+        if (kRegs || naff > kSgcAffList) {
+            for_live(survive);
+        } else {
+#pragma unroll
+            for (int i = 0; i < kSgcAffList; ++i) {
+                if (i < naff) {
+                    const int r = affr[i];
+                    const uint32_t P = Pg[gidx(r)];
+                    const uint32_t Pn = survive(r, P);
+                    if (Pn != P) Pg[gidx(r)] = Pn;
                 }
             }
-        } else if (fresh && clock_less(fT, fP, tmin, pmin)) {
+        }
+        if (rescan)
+            local_min(tmin, pmin);
+        else if (fresh && clock_less(fT, fP, tmin, pmin)) {
             tmin = fT;
             pmin = fP;
         }
