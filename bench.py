@@ -19,7 +19,9 @@ cost) from the same start and maps and compares the two at equal cost
 reduction as the performance profiles of Sec. 5.2 do: the time each needs to
 reach F_tau = F* + tau (F0 - F*) for tau = 0.1, 0.01, 0.001 (F* the lower of
 their costs after K iterations); the headline speedup is the one at 0.001.
-`huber` runs the same iterations under the robust loss (Sec. 5.1).  `sgc` draws
+`huber` runs the same iterations under the robust loss (Sec. 5.1).  `ablations`
+repeats the paper's ablations on this scene (correction, Sec. 5.4; fixed
+clustering, Sec. 5.2; cluster cap, App. B).  `sgc` draws
 the maps on the device instead (stochastic graph clustering, Sec. 4.4): the
 clustering kernel's time per map and the iteration rate with a device map drawn
 before every step.  `cpu_baseline` times the FP64 oracle on the host for the
@@ -72,6 +74,8 @@ def parse_args():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
     ap.add_argument("--no-huber", action="store_true", help="skip the robust-loss (Huber) leg")
     ap.add_argument("--no-sgc", action="store_true", help="skip the device graph-clustering leg")
+    ap.add_argument("--no-ablations", action="store_true", help="skip the synthetic ablations")
+    ap.add_argument("--ablation-iters", type=int, default=20)
     ap.add_argument("--pmc-summary", action="store_true",
                     help="write a profiles/pmc_*.txt summary from counter CSVs (no GPU work)")
     ap.add_argument("--phase", default="cluster_cholesky")
@@ -338,6 +342,8 @@ def main():
         out["huber"] = huber_leg(S, scene, maps, args, lam0, cam0, pt0)
     if not args.no_sgc and precision == S.STBA_FP64:
         out["sgc"] = sgc_leg(S, scene, e, w, args, lam0, cam0, pt0)
+    if not args.no_ablations and precision == S.STBA_FP64:
+        out["ablations"] = ablation_leg(S, scene, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, maps, lam0, args.cpu_iters)
     else:
@@ -416,6 +422,55 @@ def sgc_leg(S, scene, e, w, args, lam0, cam0, pt0):
     return {"beta": SGC_BETA, "cap": args.gamma, "kernel_ms_per_map": kernel_ms,
             "iter_per_s_with_device_maps": K / t_iter, "clusters_mean": float(np.mean(ls)),
             "F_after_K": st["F"], "status": st["status"], "host_harness_ms_per_map": host_ms}
+
+
+def ablation_leg(S, scene, args):
+    """Synthetic versions of the paper's ablations on the same scene, each
+    `--ablation-iters` FP64 LM iterations from the same start, every map drawn
+    on the device (stochastic graph clustering, beta 10, seed 0, redrawn per
+    iteration unless fixed):
+    - correction (Sec. 5.4): lambda kept >= 0.1 (lambda0 0.1), STBA (correction
+      whenever lambda >= 0.1, so at every iteration) against STBA* (none);
+    - fixed clustering (Sec. 5.2): STBA against STBA-fixed (the first map at every
+      iteration), lambda0 1e-4;
+    - cluster cap (App. B): Gamma in {1, 25, 50, 100, m} (m: one cluster, plain
+      LM), final costs normalised by the smallest, as the paper's figure does.
+    Each entry gives the cost after every iteration and the iteration rate."""
+    K = args.ablation_iters
+
+    def run(gamma, lam0, lam_corr=0.1, lam_min=0.0, fixed=False):
+        sol = S.StbaSolver(scene.cam0, scene.pt0, scene.obs_cam, scene.obs_pt, scene.obs_uv, gamma_max=gamma,
+                           precision=S.STBA_FP64, lambda0=lam0, lambda_corr=lam_corr, lambda_min=lam_min)
+        Fs, ls, first = [], [], None
+        t0 = time.perf_counter()
+        for t in range(K):
+            if first is None or not fixed:
+                smp = sol.sample_clusters(gamma, SGC_BETA, alpha=1.0, seed=0, it=t)
+                first = first or smp
+            sol.step(first if fixed else smp)
+            st = sol.read_state()
+            Fs.append(float(st["F"]))
+            ls.append((first if fixed else smp).l)
+        dt = time.perf_counter() - t0
+        return {"F": [float(f"{f:.7g}") for f in Fs], "F_final": Fs[-1], "clusters_mean": float(np.mean(ls)),
+                "iter_per_s": K / dt, "status": int(st["status"])}
+
+    out = {"iterations": K}
+    stba, star = run(args.gamma, 0.1, 0.1, 0.1), run(args.gamma, 0.1, float("inf"), 0.1)
+    out["correction"] = {"lambda_min": 0.1, "stba": stba, "stba_star": star,
+                         "final_ratio_star_over_stba": star["F_final"] / stba["F_final"]}
+    redrawn, fixed = run(args.gamma, 1e-4), run(args.gamma, 1e-4, fixed=True)
+    out["fixed_clustering"] = {"stba": redrawn, "stba_fixed": fixed,
+                               "final_ratio_fixed_over_stba": fixed["F_final"] / redrawn["F_final"]}
+    caps = {}
+    for g in (1, 25, 50, 100, scene.m):
+        caps[str(g)] = run(g, 1e-4)
+    best = min(c["F_final"] for c in caps.values())
+    for c in caps.values():
+        c["normalized_final"] = c["F_final"] / best
+        del c["F"]
+    out["cluster_cap"] = caps
+    return out
 
 
 TAUS = (0.1, 0.01, 0.001)

@@ -114,6 +114,9 @@ typedef struct stba_lm_state {
     int64_t n_jac;              /* Jacobian evaluations */
     int64_t n_rcs;              /* RCS builds / solves */
     int64_t n_accept;           /* accepted steps */
+    double lambda_min;          /* lower bound of lambda after an accepted step (0: none); stba_lm_init
+                                   sets 0, a caller may overwrite it in place (the correction
+                                   ablation of Sec. 5.4 keeps lambda >= 0.1) */
 } stba_lm_state;
 
 /* Views into the workspace written by stba_build_cluster_rcs (read-only for
@@ -215,13 +218,14 @@ int stba_sample_clusters(const stba_problem *p, const stba_dims *dims, int preci
                          int32_t gamma, double beta, uint64_t seed, uint64_t iter, int32_t *cam_cluster,
                          int32_t *n_clusters, int32_t *status, hipStream_t stream);
 
-/* Initialise a device stba_lm_state (lambda0, lambda_corr, need_jac = 1). */
+/* Initialise a device stba_lm_state (lambda0, lambda_corr, need_jac = 1, lambda_min = 0). */
 int stba_lm_init(stba_lm_state *st, double lambda0, double lambda_corr, hipStream_t stream);
 
 /* One full STBA LM iteration (Alg. 1, one pass of the loop) for the given
  * cluster map: residuals/Jacobian (only when x changed), cluster RCS, solves,
  * point update, candidate cost, accept iff F(x+dx) < F(x) strictly, the step is
- * finite and every S_k factorised; then lambda /= 3 and x += dx, else lambda *= 3.
+ * finite and every S_k factorised; then lambda = max(lambda / 3, lambda_min) and
+ * x += dx, else lambda *= 3.
  * Every decision is taken on the device; no host synchronisation. */
 int stba_lm_step(const stba_problem *p, const stba_dims *dims, const stba_sample *s, stba_lm_state *st,
                  int precision, void *ws, size_t ws_bytes, hipStream_t stream);

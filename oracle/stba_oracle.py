@@ -594,9 +594,10 @@ class LmResult:
 
 
 def lm_iteration(cam, pt, obs_cam, obs_pt, obs_uv, cam_cluster, lam, alpha=1.0, seed=0, t=0,
-                 lam_corr=0.1, F=None, huber=0.0):
+                 lam_corr=0.1, F=None, huber=0.0, lam_min=0.0):
     """One pass of Alg. 1's loop: STBA step, then accept iff F(x + dx) < F(x)
-    (F the robust cost when huber > 0)."""
+    (F the robust cost when huber > 0); lambda / 3 on accept but not below
+    lam_min (the lower bound of the correction ablation, Sec. 5.4), x 3 else."""
     if F is None:
         F = robust_cost(residuals(cam, pt, obs_cam, obs_pt, obs_uv), huber)
     st = stba_step(cam, pt, obs_cam, obs_pt, obs_uv, cam_cluster, lam, alpha, seed, t, lam_corr, huber=huber)
@@ -605,7 +606,7 @@ def lm_iteration(cam, pt, obs_cam, obs_pt, obs_uv, cam_cluster, lam, alpha=1.0, 
     F_new = robust_cost(residuals(cam_new, pt_new, obs_cam, obs_pt, obs_uv), huber) if st.ok else float("nan")
     accepted = bool(st.ok and np.isfinite(F_new) and F_new < F)
     if accepted:
-        return LmResult(cam_new, pt_new, lam / 3.0, F_new, F_new, True, st)
+        return LmResult(cam_new, pt_new, max(lam / 3.0, lam_min), F_new, F_new, True, st)
     return LmResult(cam.copy(), pt.copy(), lam * 3.0, F, F_new, False, st)
 
 

@@ -52,7 +52,7 @@ class StbaLmState(ctypes.Structure):
                 ("F_new", ctypes.c_double), ("accepted", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("need_jac", ctypes.c_int32), ("have_F", ctypes.c_int32), ("last_status", ctypes.c_int32),
                 ("pad0", ctypes.c_int32), ("n_jac", ctypes.c_int64), ("n_rcs", ctypes.c_int64),
-                ("n_accept", ctypes.c_int64)]
+                ("n_accept", ctypes.c_int64), ("lambda_min", ctypes.c_double)]
 
 
 class StbaRcs(ctypes.Structure):
@@ -247,6 +247,12 @@ def read_state(state: torch.Tensor) -> dict:
     raw = state.cpu().numpy().tobytes()
     s = StbaLmState.from_buffer_copy(raw[:ctypes.sizeof(StbaLmState)])
     return {name: getattr(s, name) for name, _ in StbaLmState._fields_ if not name.startswith("pad")}
+
+
+def set_lambda_min(state: torch.Tensor, value: float) -> None:
+    """Write stba_lm_state.lambda_min in place (a host-to-device copy on the current stream)."""
+    off = StbaLmState.lambda_min.offset
+    state[off:off + 8].copy_(torch.tensor([float(value)], dtype=torch.float64).view(torch.uint8))
 
 
 def new_state(device="cuda") -> torch.Tensor:

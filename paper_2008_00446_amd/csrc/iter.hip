@@ -223,6 +223,7 @@ __global__ void k_lm_init(stba_lm_state *st, double lambda0, double lambda_corr)
     st->n_jac = 0;
     st->n_rcs = 0;
     st->n_accept = 0;
+    st->lambda_min = 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1193,7 +1194,7 @@ __global__ __launch_bounds__(256) void k_cost_at(int64_t q, const double *__rest
 }
 
 // a7: accept iff F(x + dx) < F(x), the step is finite and every S_k factorised
-// (Alg. 1); lambda /= 3 on accept, *= 3 otherwise; x += dx on accept.  Every
+// (Alg. 1); lambda /= 3 (not below lambda_min) on accept, *= 3 otherwise; x += dx on accept.  Every
 // block sums the per-block partials in the same fixed order and compares with
 // F(x): F_ref[0] (copied by k_cost_at) once the state holds it (F_ref[1] != 0),
 // else the sum of the residual kernel's partials.  So all blocks take the same
@@ -1230,7 +1231,7 @@ __global__ __launch_bounds__(256) void k_accept_update(const double *rj_partials
         st->have_F = 1;
         st->F_new = Fn;
         st->accepted = acc ? 1 : 0;
-        st->lambda = acc ? st->lambda / 3.0 : st->lambda * 3.0;
+        st->lambda = acc ? fmax(st->lambda / 3.0, st->lambda_min) : st->lambda * 3.0;
         if (acc) st->F = Fn;
         st->need_jac = acc ? 1 : 0;
         st->n_rcs += 1;

@@ -19,10 +19,11 @@ class StbaSolver:
     cam [m,9], pt [n,3] (FP64, copied to the device and updated in place on
     accepted steps), obs_cam / obs_pt [q] int32 sorted by (point, camera),
     obs_uv [q,2] FP64.  gamma_max bounds the cluster sizes of every map later
-    passed to `step`.  huber > 0: the robust (Huber) loss of that scale."""
+    passed to `step`.  huber > 0: the robust (Huber) loss of that scale.
+    lambda_min > 0: lambda never drops below it after an accepted step."""
 
     def __init__(self, cam, pt, obs_cam, obs_pt, obs_uv, gamma_max, precision=B.STBA_FP64,
-                 lambda0=1e-4, lambda_corr=0.1, device="cuda", huber=0.0):
+                 lambda0=1e-4, lambda_corr=0.1, device="cuda", huber=0.0, lambda_min=0.0):
         as_dev = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(device)  # noqa: E731
         self.cam = as_dev(cam, torch.float64).clone()
         self.pt = as_dev(pt, torch.float64).clone()
@@ -37,6 +38,8 @@ class StbaSolver:
         B.stba_prepare(self.problem, self.dims, self.precision, self.ws)
         self.state = B.new_state(device)
         B.stba_lm_init(self.state, lambda0, lambda_corr)
+        if lambda_min:
+            B.set_lambda_min(self.state, lambda_min)
         self._events = None
         self._sgc = None
 

@@ -44,3 +44,36 @@ def test_binding_names_match_header_and_host_checks():
     assert lib.stba_workspace_bytes(None, None, 0) == 0
     assert lib.stba_lm_init(None, 1e-4, 0.1, None) == -1
     assert P.stba_phase_name(0) == "clusters" and P.stba_phase_name(99) == ""
+
+
+def test_ctypes_structs_match_the_c_layout(tmp_path):
+    """Every struct the binding mirrors has the header's size and field offsets
+    (the header compiled by the host C compiler)."""
+    import shutil
+    import subprocess
+
+    from paper_2008_00446_amd import binding as B
+
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no host C compiler")
+    structs = {"stba_problem": B.StbaProblem, "stba_dims": B.StbaDims, "stba_sample": B.StbaSample,
+               "stba_damping": B.StbaDamping, "stba_lm_state": B.StbaLmState, "stba_rcs": B.StbaRcs}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "stba.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'    printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            cf = "lambda" if fname == "lambda_" else fname
+            lines.append(f'    printf("{cname} {fname} %zu\\n", offsetof({cname}, {cf}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"), "-I", "/opt/rocm/include",
+                    str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    for line in filter(None, out):
+        cname, what, val = line.split()
+        py = structs[cname]
+        got = ctypes.sizeof(py) if what == "size" else getattr(py, what).offset
+        assert got == int(val), (cname, what, got, val)

@@ -93,6 +93,32 @@ def test_tiny_circle_one_iteration_matches_oracle():
     assert rel(pt - s.pt0, ref.pt - s.pt0) < 1e-9
 
 
+@pytest.mark.parametrize("lam_corr", [0.1, float("inf")], ids=["stba", "stba_star"])
+def test_lambda_floor_and_correction_ablation_match_oracle(lam_corr):
+    # Sec. 5.4: lambda kept >= 0.1 so that the correction (STBA) is active at every
+    # iteration, against the same iterations without it (STBA*)
+    s = _small()
+    lam0, alpha, seed = 0.1, 1.0, 4
+    sol = S.StbaSolver(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv, gamma_max=12, lambda0=lam0,
+                       lambda_corr=lam_corr, lambda_min=0.1)
+    cam, pt, lam = s.cam0.copy(), s.pt0.copy(), lam0
+    F = O.cost(O.residuals(cam, pt, s.obs_cam, s.obs_pt, s.obs_uv))
+    accepted = 0
+    for t in range(4):
+        lab = _sgc(s, 12, t, seed)
+        sol.step(sol.sample(lab, alpha=alpha, seed=seed, it=t))
+        st = sol.read_state()
+        r = O.lm_iteration(cam, pt, s.obs_cam, s.obs_pt, s.obs_uv, lab, lam, alpha, seed, t, lam_corr=lam_corr,
+                           F=F, lam_min=0.1)
+        assert bool(st["accepted"]) == r.accepted, t
+        assert st["lambda_"] == r.lam and r.lam >= 0.1, t
+        assert abs(st["F"] - r.F) <= 1e-9 * r.F, t
+        cam, pt, lam, F = r.cam, r.pt, r.lam, r.F
+        accepted += r.accepted
+        assert rel(sol.cam.cpu().numpy() - s.cam0, cam - s.cam0) < 1e-8, t
+    assert accepted >= 1
+
+
 def test_lm_iterations_with_changing_maps_match_oracle():
     s = _small()
     lam0, alpha, seed = 0.2, 0.8, 11

@@ -148,3 +148,20 @@ def test_lm_iteration_on_a_device_map_matches_oracle():
         assert bool(st["accepted"]) == ref.accepted
         assert st["F_new"] == pytest.approx(ref.F_new, rel=1e-9)
         np.testing.assert_allclose(sol.cam.cpu().numpy(), ref.cam, rtol=0, atol=1e-9 * np.abs(ref.cam).max())
+
+
+def test_uncapped_ring_is_plain_lm_in_one_cluster():
+    # Gamma = m: every camera joins one cluster (the ring's graph is connected), so
+    # the iteration is one dense 1800 x 1800 solve (App. B: STBA equals LM there)
+    s = _scene("ring200")
+    sol = S.StbaSolver(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv, gamma_max=s.m, lambda0=1e-4)
+    samp = sol.sample_clusters(s.m, beta=10.0, seed=0, it=0)
+    assert samp.l == 1
+    sol.step(samp)
+    st = sol.read_state()
+    ref = O.lm_iteration(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv, np.zeros(s.m, dtype=np.int64), 1e-4, 1.0, 0, 0)
+    assert st["status"] == 0 and bool(st["accepted"]) == ref.accepted
+    assert st["F_new"] == pytest.approx(ref.F_new, rel=1e-9)
+    dc = sol.cam.cpu().numpy() - s.cam0
+    assert np.linalg.norm(dc - (ref.cam - s.cam0)) <= 1e-9 * np.linalg.norm(ref.cam - s.cam0)
+
