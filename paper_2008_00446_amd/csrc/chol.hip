@@ -1286,15 +1286,16 @@ int chol_tile_layout(int32_t l, int32_t max_Np, int32_t *wpc, int32_t *tmax, int
     if (tm < 1) return 0;
     const int64_t waves = 1 + (int64_t)tm + (int64_t)(tm - 1) * (tm - 2) / 2;   // band, rows, tiles
     if ((int64_t)l * waves > kCholTileWaves) return 0;
-    // keep a quarter of the resident capacity in reserve
-    if (4 * (int64_t)l * waves > 3 * chol_tile_resident()) return 0;
+    // every wave must be resident at once (they wait on each other); keep a
+    // sixteenth of the capacity in reserve
+    if (16 * (int64_t)l * waves > 15 * chol_tile_resident()) return 0;
     const int64_t words = (int64_t)tm * (tm + 1) / 2 + tm + 2;
     if ((int64_t)l * words + 2 > chol_flag_words() || (int64_t)l * kVecSets * tm * kNB > chol_yx_doubles()) return 0;
     *tmax = tm;
     *wpc = (int32_t)waves;
     *fpc = (int32_t)words;
     // whole clusters per XCD when one XCD's share of the resident capacity (with
-    // the same reserve) holds ceil(l / 8) clusters
+    // a quarter in reserve) holds ceil(l / 8) clusters
     *xcd_major = 4 * (((int64_t)l + 7) / 8) * waves <= 3 * (chol_tile_resident() / 8) ? 1 : 0;
     return 1;
 }

@@ -98,7 +98,7 @@ hipError_t launch_schur(const int64_t *n_blocks, int64_t n_blocks_cap, const Sch
 // T = max_Np / 32, within kCholTileWaves and resident at once) and flags / yx
 // given: one wavefront per tile (tile-parallel dataflow); otherwise one
 // workgroup per cluster.  flags: chol_flag_words() int32; yx: chol_yx_doubles().
-constexpr int kCholTileWaves = 1536;
+constexpr int kCholTileWaves = 2048;   // e.g. one cluster of up to 64 tile rows (Np <= 2048)
 // per cluster T (T + 1) / 2 + T + 2 flag words <= 2.5 x its wavefronts, plus the
 // abort word and the count of finished clusters
 inline int64_t chol_flag_words() { return 4 * (int64_t)kCholTileWaves + 2; }
