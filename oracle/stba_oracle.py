@@ -35,7 +35,10 @@ point update (Eq. 14-15), the correction (Sec. 4.3) and the LM accept rule
   applied by first-order (IRLS) reweighting of f and J (see `huber_rho`);
 * stochastic graph clustering (Sec. 4.4, Eq. 16) draws one join at a time from
   the distribution of Eq. 16 over the neighbouring pairs within the size cap,
-  sampled by competing exponential clocks keyed by Philox (see `sgc_clusters`).
+  sampled by competing exponential clocks keyed by Philox (see `sgc_clusters`);
+* the inexact cluster solve (App. A, Table 3): conjugate gradient with the
+  camera-block (9 x 9) Jacobi preconditioner, from x = 0, stopped at a relative
+  residual (see `pcg`).
 
 Parity pins live in tests/test_oracle_*.py; every function below is pinned.
 """
@@ -57,6 +60,7 @@ __all__ = [
     "StbaStep", "stba_step", "plain_lm_step", "full_normal_step", "relaxed_kkt_step",
     "LmResult", "lm_iteration", "cluster_layout",
     "covisibility_graph", "sgc_uniform", "modularity_gain", "sgc_clusters",
+    "block_jacobi_inverse", "pcg",
 ]
 
 # ---------------------------------------------------------------------------
@@ -719,3 +723,68 @@ def sgc_clusters(edges, weights, m, gamma, beta, seed, t):
             set_clocks([(min(x, z), max(x, z), w) for z, w in sorted(adj[x].items())], k, t_now)
     names, dense = np.unique(lab, return_inverse=True)
     return dense.astype(np.int32), int(names.shape[0])
+
+
+# ---------------------------------------------------------------------------
+# O-15: the inexact cluster solve by preconditioned conjugate gradient (App. A)
+# ---------------------------------------------------------------------------
+
+
+def block_jacobi_inverse(S, bs=9):
+    """M^-1 for the block-Jacobi preconditioner M = blockdiag(S_ii), bs x bs
+    diagonal blocks of S (the camera blocks); raises LinAlgError if a block is not
+    positive definite."""
+    n = S.shape[0] // bs
+    out = np.zeros((n, bs, bs))
+    for a in range(n):
+        blk = S[a * bs:(a + 1) * bs, a * bs:(a + 1) * bs]
+        fac = scipy.linalg.cho_factor(blk, lower=True, check_finite=True)
+        out[a] = scipy.linalg.cho_solve(fac, np.eye(bs))
+    return out
+
+
+def pcg(S, b, tol, max_iters, bs=9):
+    """Preconditioned conjugate gradient on S x = b (App. A: the inexact solver of
+    the split reduced camera systems), S symmetric positive definite, with the
+    block-Jacobi preconditioner of `block_jacobi_inverse`: x = 0, r = b,
+    z = M^-1 r, p = z; each iteration q = S p, alpha = r.z / p.q, x += alpha p,
+    r -= alpha q, stop once ||r|| <= tol ||b||, else z = M^-1 r,
+    beta = (r.z)_new / (r.z)_old, p = z + beta p.  At most max_iters iterations.
+    Returns (x, iterations, ||r|| / ||b||, ok) with ok False when p.q <= 0 or a
+    preconditioner block is not positive definite."""
+    S = np.asarray(S, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    n = b.shape[0] // bs
+    try:
+        Minv = block_jacobi_inverse(S, bs)
+    except (np.linalg.LinAlgError, ValueError):
+        return np.zeros_like(b), 0, float("nan"), False
+
+    def precond(v):
+        return np.einsum("aij,aj->ai", Minv, v.reshape(n, bs)).reshape(-1)
+
+    x = np.zeros_like(b)
+    bn = float(np.linalg.norm(b))
+    if bn == 0.0:
+        return x, 0, 0.0, True
+    r = b.copy()
+    z = precond(r)
+    p = z.copy()
+    rz = float(r @ z)
+    it = 0
+    while it < max_iters:
+        q = S @ p
+        pq = float(p @ q)
+        if not pq > 0.0:
+            return x, it, float(np.linalg.norm(r)) / bn, False
+        alpha = rz / pq
+        x = x + alpha * p
+        r = r - alpha * q
+        it += 1
+        if np.linalg.norm(r) <= tol * bn:
+            break
+        z = precond(r)
+        rz_new = float(r @ z)
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    return x, it, float(np.linalg.norm(r)) / bn, True
