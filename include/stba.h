@@ -193,6 +193,29 @@ int stba_solve_clusters(const stba_problem *p, const stba_dims *dims, const stba
                         const void *Jc, const void *Jp, double *dcam, double *dpt,
                         int32_t *cluster_status, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* The inexact alternative to stba_solve_clusters (App. A, Table 3): every
+ * S_k dc_k = b_k by conjugate gradient with the camera-block Jacobi
+ * preconditioner M = blockdiag(S_ii) (9 x 9 blocks), from dc_k = 0: q = S p,
+ * alpha = r.z / p.q, dc += alpha p, r -= alpha q, stop once ||r|| <= tol ||b_k||
+ * or after max_iters iterations, else z = M^-1 r, beta = (r.z)_new / (r.z)_old,
+ * p = z + beta p.  The product visits only the 9 x 9 blocks of the camera pairs
+ * the plan links, so an iteration costs O(r') in the sampled connections.  Then
+ * the point step of Eq. 15 as in stba_solve_clusters.  Reads S and b as
+ * stba_build_cluster_rcs left them (S is not modified, so stba_solve_clusters
+ * may follow).  Runs in FP64 whatever the precision (which only selects the
+ * type of Jc, Jp).
+ *   max_iters >= 0; tol >= 0, finite (relative residual).
+ *   cluster_iters (device int32 [l], nullable): iterations used per cluster.
+ *   cluster_resid (device double [l], nullable): final ||r|| / ||b_k||.
+ *   cluster_status (device int32 [l], nullable): STBA_OK, or STBA_ENOTPD when a
+ *     camera block is not positive definite or p.q <= 0 (dc_k is then zero).
+ * Requires the LDS of one cluster, 8 (5 Np + 8) + n^2 / 8 bytes for the largest
+ * padded order Np and dims->gamma_max = n, to fit 160 KB (STBA_EINVAL else). */
+int stba_solve_clusters_pcg(const stba_problem *p, const stba_dims *dims, const stba_rcs *rcs, int precision,
+                            const void *Jc, const void *Jp, double *dcam, double *dpt, int32_t max_iters, double tol,
+                            int32_t *cluster_iters, double *cluster_resid, int32_t *cluster_status, void *ws,
+                            size_t ws_bytes, hipStream_t stream);
+
 /* Draw the camera clustering {Phi_k} of LM iteration `iter` by stochastic graph
  * clustering (Sec. 4.4, Eq. 16) on the device.  The camera graph weighs the
  * edge (i, j) by the number of points both cameras see (read from the plan of

@@ -75,6 +75,8 @@ _SIGS = {
     "stba_build_cluster_rcs": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, _P, _P, _P, _P, _P,
                                               ctypes.c_size_t, _P]),
     "stba_solve_clusters": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "stba_solve_clusters_pcg": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P, _P, _P, _P, ctypes.c_int32,
+                                               ctypes.c_double, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "stba_sample_clusters": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, ctypes.c_size_t, ctypes.c_int32,
                                             ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64, _P, _P, _P, _P]),
     "stba_lm_init": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double, _P]),
@@ -209,6 +211,15 @@ def stba_solve_clusters(problem, dims, rcs, precision, Jc, Jp, dcam, dpt, cluste
     _check("stba_solve_clusters", load_library().stba_solve_clusters(
         _ref(problem), _ref(dims), _ref(rcs), precision, _ptr(Jc), _ptr(Jp), _ptr(dcam), _ptr(dpt),
         _ptr(cluster_status), _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def stba_solve_clusters_pcg(problem, dims, rcs, precision, Jc, Jp, dcam, dpt, max_iters, tol, cluster_iters,
+                            cluster_resid, cluster_status, ws, stream=None):
+    """Cluster solves by block-Jacobi preconditioned conjugate gradient, then the point step."""
+    _check("stba_solve_clusters_pcg", load_library().stba_solve_clusters_pcg(
+        _ref(problem), _ref(dims), _ref(rcs), precision, _ptr(Jc), _ptr(Jp), _ptr(dcam), _ptr(dpt), int(max_iters),
+        float(tol), _ptr(cluster_iters), _ptr(cluster_resid), _ptr(cluster_status), _ptr(ws), ws.numel(),
+        _stream(stream)))
 
 
 def stba_sample_clusters(problem, dims, precision, ws, gamma, beta, seed, it, cam_cluster, n_clusters, status,

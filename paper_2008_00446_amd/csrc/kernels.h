@@ -150,4 +150,14 @@ hipError_t launch_sgc(int32_t m, const int64_t *n_blocks, const int2 *blk_key, c
                       int32_t gamma, double beta, uint64_t seed, uint64_t iter, uint32_t *Pg, double *Tg,
                       int32_t *Wg, int32_t *cam_cluster, int32_t *n_clusters, int32_t *status, hipStream_t st);
 
+// --- inexact cluster solves (pcg.hip) ---------------------------------------
+// Dynamic LDS of one cluster's conjugate-gradient workgroup (<= 160 KB required).
+size_t pcg_lds_bytes(int32_t max_np, int32_t max_n);
+// clus [m] and Minv [81 m] are scratch; iters_out, resid_out, cl_status [l].
+hipError_t launch_pcg(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, const int64_t *S_off,
+                      const int32_t *cl_start, const int32_t *cl_cams, const int32_t *cam_local,
+                      const int64_t *n_blocks, const int2 *blk_key, const double *S, const double *b, double *dcam,
+                      int32_t *clus, double *Minv, int32_t max_np, int32_t max_n, int32_t max_iters, double tol,
+                      int32_t *iters_out, double *resid_out, int32_t *cl_status, hipStream_t st);
+
 }  // namespace stba

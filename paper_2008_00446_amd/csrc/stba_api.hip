@@ -18,6 +18,7 @@ struct Layout {
     size_t tmp_bytes;
     // per iteration
     size_t cl_n, cl_Np, cl_start, cl_cams, cam_local, cl_status, S_off;
+    size_t pcg_clus, pcg_minv, pcg_iters, pcg_resid;
     size_t f, Jc, Jp, seg_head, seg_rec, grp_first, obsd, Vinv, wph, S, S0, rres, b, dcam, dpt, partials, chol_flags, chol_yx;
     bool mixed = false;   // S0 and rres exist
     int64_t S_cap, n_partials;
@@ -107,6 +108,10 @@ bool make_layout(const stba_problem *p, const stba_dims *d, int precision, Layou
     L.cam_local = take(4 * m);
     L.cl_status = take(4 * m);
     L.S_off = take(8 * (m + 1));
+    L.pcg_clus = take(4 * m);
+    L.pcg_minv = take(8 * 81 * m);
+    L.pcg_iters = take(4 * m);
+    L.pcg_resid = take(8 * m);
     L.f = take(es * 2 * q);
     L.Jc = take(es * 18 * q);
     L.Jp = take(es * 6 * q);
@@ -424,6 +429,35 @@ int stba_sample_clusters(const stba_problem *p, const stba_dims *dims, int preci
     STBA_HIP(launch_sgc(p->m, at<int64_t>(ws, L.n_blocks), at<int2>(ws, L.blk_key), at<int64_t>(ws, L.blk_start),
                         gamma, beta, seed, iter, at<uint32_t>(ws, L.scratch_a), at<double>(ws, L.keys_in),
                         at<int32_t>(ws, L.vals_in), cam_cluster, n_clusters, status, stream));
+    return STBA_OK;
+}
+
+int stba_solve_clusters_pcg(const stba_problem *p, const stba_dims *dims, const stba_rcs *rcs, int precision,
+                            const void *Jc, const void *Jp, double *dcam, double *dpt, int32_t max_iters, double tol,
+                            int32_t *cluster_iters, double *cluster_resid, int32_t *cluster_status, void *ws,
+                            size_t ws_bytes, hipStream_t stream) {
+    Layout L;
+    STBA_TRY(front(p, dims, precision, ws, ws_bytes, L));
+    if (!rcs || rcs->l < 1 || rcs->l > p->m || rcs->precision != precision || !Jc || !Jp || !dcam || !dpt)
+        return STBA_EINVAL;
+    if (max_iters < 0 || !(tol >= 0.0) || !std::isfinite(tol)) return STBA_EINVAL;
+    if (pcg_lds_bytes(L.max_Np, dims->gamma_max) > 160 * 1024) return STBA_EINVAL;
+    int32_t *cs = cluster_status ? cluster_status : at<int32_t>(ws, L.cl_status);
+    int32_t *its = cluster_iters ? cluster_iters : at<int32_t>(ws, L.pcg_iters);
+    double *res = cluster_resid ? cluster_resid : at<double>(ws, L.pcg_resid);
+    STBA_HIP(launch_pcg(rcs->l, at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np), at<int64_t>(ws, L.S_off),
+                        at<int32_t>(ws, L.cl_start), at<int32_t>(ws, L.cl_cams), at<int32_t>(ws, L.cam_local),
+                        at<int64_t>(ws, L.n_blocks), at<int2>(ws, L.blk_key), at<double>(ws, L.S),
+                        at<double>(ws, L.b), dcam, at<int32_t>(ws, L.pcg_clus), at<double>(ws, L.pcg_minv),
+                        L.max_Np, dims->gamma_max, max_iters, tol, its, res, cs, stream));
+    if (precision == STBA_FP64)
+        STBA_HIP(launch_backsub<double>(*p, at<int64_t>(ws, L.pt_off), (const double *)Jc, (const double *)Jp,
+                                        at<double>(ws, L.Vinv), at<double>(ws, L.wph), dcam, dpt, L.group_size,
+                                        at<int32_t>(ws, L.grp_first), stream));
+    else
+        STBA_HIP(launch_backsub<float>(*p, at<int64_t>(ws, L.pt_off), (const float *)Jc, (const float *)Jp,
+                                       at<double>(ws, L.Vinv), at<double>(ws, L.wph), dcam, dpt, L.group_size,
+                                       at<int32_t>(ws, L.grp_first), stream));
     return STBA_OK;
 }
 

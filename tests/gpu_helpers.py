@@ -99,6 +99,20 @@ class GpuProblem:
         return dcam.cpu().numpy(), dpt.cpu().numpy(), cs.cpu().numpy()
 
 
+def solve_pcg(g, rcs, Jc, Jp, max_iters, tol):
+    """stba_solve_clusters_pcg on a GpuProblem: (dcam, dpt, status, iterations, residuals)."""
+    m, n = g.prob.m, g.prob.n
+    dcam = torch.empty((m, 9), dtype=torch.float64, device="cuda")
+    dpt = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    cs = torch.empty(rcs.l, dtype=torch.int32, device="cuda")
+    its = torch.empty(rcs.l, dtype=torch.int32, device="cuda")
+    res = torch.empty(rcs.l, dtype=torch.float64, device="cuda")
+    S.stba_solve_clusters_pcg(g.prob, g.dims, rcs, g.precision, Jc, Jp, dcam, dpt, max_iters, tol, its, res, cs,
+                              g.ws)
+    torch.cuda.synchronize()
+    return (dcam.cpu().numpy(), dpt.cpu().numpy(), cs.cpu().numpy(), its.cpu().numpy(), res.cpu().numpy())
+
+
 def rel(a, b):
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)

@@ -1,0 +1,113 @@
+"""The inexact cluster solve (App. A, Table 3: conjugate gradient with the
+camera-block Jacobi preconditioner) on the GPU against the oracle: the first
+iterates against the oracle's PCG on the oracle's own S_k and b_k, converged
+steps against the exact (Cholesky) STBA step on a small ring and on the
+200-camera ring, MIXED, a non-positive-definite cluster, and argument errors."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_2008_00446_amd as S
+import synth
+from gpu_helpers import GpuProblem, rel, solve_pcg, ws_view
+
+pytestmark = pytest.mark.gpu
+
+
+def _small():
+    return synth.small_ring(m=40, n=3000, views=8, seed=1)
+
+
+def _map(s, gamma, t, seed=0):
+    e, w = O.covisibility_graph(s.obs_cam, s.obs_pt, s.m, s.n)
+    return O.sgc_clusters(e, w, s.m, gamma, 10.0, seed, t)[0]
+
+
+@pytest.mark.parametrize("k", [1, 2, 5])
+def test_first_iterates_match_oracle_pcg(k):
+    s = _small()
+    lab = _map(s, 12, 0)
+    g = GpuProblem(s, gamma_max=12)
+    f, Jc, Jp, _ = g.residual_jacobian()
+    rcs = g.build(f, Jc, Jp, lab, 1e-3)
+    dcam, _, cs, its, _ = solve_pcg(g, rcs, Jc, Jp, k, 0.0)
+    ref = O.stba_step(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv, lab, 1e-3)
+    assert np.all(cs == 0) and np.all(its == k)
+    for Sk, bk, cams in zip(ref.S_blocks, ref.b_blocks, ref.clusters):
+        x, it, _, ok = O.pcg(Sk, bk, 0.0, k)
+        assert ok and it == k
+        assert rel(dcam[cams].reshape(-1), x) < 1e-9
+
+
+@pytest.mark.parametrize("lam,alpha", [(1e-3, 1.0), (0.3, 0.7)])
+def test_converged_pcg_matches_the_exact_step(lam, alpha):
+    s = _small()
+    lab = _map(s, 12, 2)
+    g = GpuProblem(s, gamma_max=12)
+    f, Jc, Jp, _ = g.residual_jacobian()
+    rcs = g.build(f, Jc, Jp, lab, lam, alpha=alpha, seed=3)
+    dcam, dpt, cs, its, res = solve_pcg(g, rcs, Jc, Jp, 1000, 1e-12)
+    ref = O.stba_step(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv, lab, lam, alpha, 3)
+    print(f"pcg small ring lam={lam} alpha={alpha}: iterations {its.tolist()}", flush=True)
+    assert np.all(cs == 0) and np.all(res <= 1e-12) and np.all(its < 1000)
+    assert rel(dcam, ref.dcam) < 1e-8
+    assert rel(dpt, ref.dpt) < 1e-8
+
+
+def test_ring_pcg_matches_the_exact_step():
+    s = synth.ring(m=200, n=50_000, views=8, seed=0)
+    lab = _map(s, 50, 0)
+    g = GpuProblem(s, gamma_max=50)
+    f, Jc, Jp, _ = g.residual_jacobian()
+    rcs = g.build(f, Jc, Jp, lab, 1e-4)
+    dcam, dpt, cs, its, res = solve_pcg(g, rcs, Jc, Jp, 2000, 1e-12)
+    print(f"pcg ring: iterations {its.tolist()} residuals {res.tolist()}", flush=True)
+    ref = O.stba_step(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv, lab, 1e-4)
+    assert np.all(cs == 0) and np.all(res <= 1e-12)
+    assert rel(dcam, ref.dcam) < 1e-7
+    assert rel(dpt, ref.dpt) < 1e-7
+
+
+def test_mixed_precision_pcg_within_the_mixed_bar():
+    s = _small()
+    lab = _map(s, 12, 1)
+    g = GpuProblem(s, gamma_max=12, precision=S.STBA_MIXED)
+    f, Jc, Jp, _ = g.residual_jacobian()
+    rcs = g.build(f, Jc, Jp, lab, 1e-3)
+    dcam, dpt, cs, its, res = solve_pcg(g, rcs, Jc, Jp, 1000, 1e-12)
+    ref = O.stba_step(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv, lab, 1e-3)
+    assert np.all(cs == 0)
+    assert rel(dcam, ref.dcam) < 1e-4
+    assert rel(dpt, ref.dpt) < 1e-4
+
+
+def test_non_positive_definite_cluster_is_reported():
+    s = _small()
+    lab = _map(s, 12, 1)
+    g = GpuProblem(s, gamma_max=12)
+    f, Jc, Jp, _ = g.residual_jacobian()
+    rcs = g.build(f, Jc, Jp, lab, 1e-3)
+    torch.cuda.synchronize()
+    S_off = ws_view(g.ws, rcs.S_off, torch.int64, rcs.l + 1).cpu().numpy()
+    Sbuf = ws_view(g.ws, rcs.S, torch.float64, int(S_off[rcs.l]))
+    bad = 1
+    Sbuf[int(S_off[bad])] = -1.0   # entry (0, 0) of cluster 1
+    torch.cuda.synchronize()
+    dcam, _, cs, _, _ = solve_pcg(g, rcs, Jc, Jp, 500, 1e-12)
+    assert cs[bad] == -2 and np.all(np.delete(cs, bad) == 0)
+    assert not dcam[lab == bad].any()
+    ref = O.stba_step(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv, lab, 1e-3)
+    good = lab != bad
+    assert rel(dcam[good], ref.dcam[good]) < 1e-8
+
+
+def test_bad_arguments_are_rejected():
+    s = _small()
+    lab = _map(s, 12, 0)
+    g = GpuProblem(s, gamma_max=12)
+    f, Jc, Jp, _ = g.residual_jacobian()
+    rcs = g.build(f, Jc, Jp, lab, 1e-3)
+    for it, tol in [(-1, 1e-6), (10, float("nan")), (10, -1.0), (10, float("inf"))]:
+        with pytest.raises(S.StbaError):
+            solve_pcg(g, rcs, Jc, Jp, it, tol)
