@@ -19,7 +19,8 @@ cost) from the same start and maps and compares the two at equal cost
 reduction as the performance profiles of Sec. 5.2 do: the time each needs to
 reach F_tau = F* + tau (F0 - F*) for tau = 0.1, 0.01, 0.001 (F* the lower of
 their costs after K iterations); the headline speedup is the one at 0.001.
-`huber` runs the same iterations under the robust loss (Sec. 5.1).  `ablations`
+`huber` runs the same iterations under the robust loss (Sec. 5.1).  `pcg` times the inexact
+cluster solve (App. A) against the Cholesky one.  `ablations`
 repeats the paper's ablations on this scene (correction, Sec. 5.4; fixed
 clustering, Sec. 5.2; cluster cap, App. B).  `sgc` draws
 the maps on the device instead (stochastic graph clustering, Sec. 4.4): the
@@ -75,6 +76,7 @@ def parse_args():
     ap.add_argument("--no-huber", action="store_true", help="skip the robust-loss (Huber) leg")
     ap.add_argument("--no-sgc", action="store_true", help="skip the device graph-clustering leg")
     ap.add_argument("--no-ablations", action="store_true", help="skip the synthetic ablations")
+    ap.add_argument("--no-pcg", action="store_true", help="skip the inexact (PCG) cluster-solve leg")
     ap.add_argument("--ablation-iters", type=int, default=20)
     ap.add_argument("--pmc-summary", action="store_true",
                     help="write a profiles/pmc_*.txt summary from counter CSVs (no GPU work)")
@@ -342,6 +344,8 @@ def main():
         out["huber"] = huber_leg(S, scene, maps, args, lam0, cam0, pt0)
     if not args.no_sgc and precision == S.STBA_FP64:
         out["sgc"] = sgc_leg(S, scene, e, w, args, lam0, cam0, pt0)
+    if not args.no_pcg and precision == S.STBA_FP64:
+        out["pcg"] = pcg_leg(S, scene, maps, args, lam0)
     if not args.no_ablations and precision == S.STBA_FP64:
         out["ablations"] = ablation_leg(S, scene, args)
     if not args.no_cpu_baseline:
@@ -422,6 +426,61 @@ def sgc_leg(S, scene, e, w, args, lam0, cam0, pt0):
     return {"beta": SGC_BETA, "cap": args.gamma, "kernel_ms_per_map": kernel_ms,
             "iter_per_s_with_device_maps": K / t_iter, "clusters_mean": float(np.mean(ls)),
             "F_after_K": st["F"], "status": st["status"], "host_harness_ms_per_map": host_ms}
+
+
+PCG_TOLS = (1e-4, 1e-6, 1e-10)
+
+
+def pcg_leg(S, scene, maps, args, lam0):
+    """The inexact cluster solve (App. A, Table 3) against the Cholesky solve on
+    the first iteration's cluster systems: for each tolerance the time of
+    stba_solve_clusters_pcg (conjugate gradient, camera-block Jacobi, then the
+    point step), the largest iteration count over the clusters and the camera
+    step's distance from the Cholesky one; the Cholesky solve's time beside it.
+    Each solve is timed with events on its stream after a fresh assembly."""
+    import torch
+    sol = S.StbaSolver(scene.cam0, scene.pt0, scene.obs_cam, scene.obs_pt, scene.obs_uv, gamma_max=args.gamma,
+                       precision=S.STBA_FP64, lambda0=lam0)
+    m, n, q = scene.m, scene.n, scene.q
+    f = torch.empty((q, 2), dtype=torch.float64, device="cuda")
+    Jc = torch.empty((q, 18), dtype=torch.float64, device="cuda")
+    Jp = torch.empty((q, 6), dtype=torch.float64, device="cuda")
+    S.stba_residual_jacobian(sol.problem, sol.dims, sol.precision, f, Jc, Jp, None, sol.ws)
+    smp = sol.sample(maps[0], alpha=1.0, seed=0, it=0)
+    l = smp.l
+    dcam = torch.empty((m, 9), dtype=torch.float64, device="cuda")
+    dpt = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    cs = torch.empty(l, dtype=torch.int32, device="cuda")
+    its = torch.empty(l, dtype=torch.int32, device="cuda")
+    res = torch.empty(l, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def timed_solve(fn, reps=3):
+        ms = []
+        for _ in range(reps):
+            rcs = S.stba_build_cluster_rcs(sol.problem, sol.dims, smp, S.StbaDamping(lam0, 0.1), sol.precision,
+                                           f, Jc, Jp, sol.ws)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn(rcs)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return float(np.median(ms))
+
+    chol_ms = timed_solve(lambda rcs: S.stba_solve_clusters(sol.problem, sol.dims, rcs, sol.precision, Jc, Jp,
+                                                            dcam, dpt, cs, sol.ws))
+    ref = dcam.cpu().numpy()
+    out = {"clusters": l, "cholesky_ms": chol_ms, "tolerances": {}}
+    for tol in PCG_TOLS:
+        ms = timed_solve(lambda rcs: S.stba_solve_clusters_pcg(sol.problem, sol.dims, rcs, sol.precision, Jc, Jp,
+                                                               dcam, dpt, 5000, tol, its, res, cs, sol.ws))
+        x = dcam.cpu().numpy()
+        out["tolerances"][f"{tol:g}"] = {
+            "ms": ms, "iterations_max": int(its.max().item()), "iterations_mean": float(its.double().mean().item()),
+            "step_rel_diff_vs_cholesky": float(np.linalg.norm(x - ref) / np.linalg.norm(ref)),
+            "status_ok": bool((cs == 0).all().item())}
+    return out
 
 
 def ablation_leg(S, scene, args):

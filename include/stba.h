@@ -209,8 +209,9 @@ int stba_solve_clusters(const stba_problem *p, const stba_dims *dims, const stba
  *   cluster_resid (device double [l], nullable): final ||r|| / ||b_k||.
  *   cluster_status (device int32 [l], nullable): STBA_OK, or STBA_ENOTPD when a
  *     camera block is not positive definite or p.q <= 0 (dc_k is then zero).
- * Requires the LDS of one cluster, 8 (5 Np + 8) + n^2 / 8 bytes for the largest
- * padded order Np and dims->gamma_max = n, to fit 160 KB (STBA_EINVAL else). */
+ * Requires the LDS of one cluster, 8 (5 Np + 9) + n^2 / 8 + 4 (n + 1) + 2 n^2
+ * bytes for the largest padded order Np and dims->gamma_max = n, to fit 160 KB
+ * (STBA_EINVAL else; n <= 200 fits). */
 int stba_solve_clusters_pcg(const stba_problem *p, const stba_dims *dims, const stba_rcs *rcs, int precision,
                             const void *Jc, const void *Jp, double *dcam, double *dpt, int32_t max_iters, double tol,
                             int32_t *cluster_iters, double *cluster_resid, int32_t *cluster_status, void *ws,

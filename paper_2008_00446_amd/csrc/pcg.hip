@@ -5,7 +5,7 @@
 //
 // One 512-thread workgroup per cluster; the five vectors (x, r, z, p, q) live in
 // LDS.  The product S p visits only the 9 x 9 blocks of camera pairs that the
-// plan links (a bitmap over the cluster's camera pairs, built from the plan's
+// plan links (per-camera lists of linked cameras in LDS, built from the plan's
 // block list), so an iteration costs O(r') in the sampled camera connections,
 // reading the lower triangle of the assembled S_k (the upper blocks as
 // transposes of the stored lower ones).  Thread t owns rows t, t + 512, ...;
@@ -40,33 +40,52 @@ __device__ inline bool has_block(const uint32_t *bits, int n, int a, int c) {
     return (bits[e >> 5] >> (e & 31)) & 1u;
 }
 
-// (S p)_row for row = 9 a + i of the cluster matrix A (column-major, lower
-// triangle stored, leading dimension Np).
-__device__ inline double spmv_row(const double *A, int64_t Np, const uint32_t *bits, int n, int a, int i,
-                                  const double *p) {
+// One 9-entry product of row i of block (a, c) with p_c (column-major A, lower
+// triangle stored, leading dimension Np): S_ac itself when c < a, the transpose
+// of the stored S_ca when c > a, the symmetric diagonal block when c == a.
+__device__ inline double block_row_dot(const double *A, int64_t Np, int a, int c, int i, const double *p) {
     const int64_t row = 9 * (int64_t)a + i;
-    double acc = 0.0;
-    for (int c = 0; c < n; ++c) {
-        if (!has_block(bits, n, a, c)) continue;
-        const double *pc = p + 9 * c;
-        if (c < a) {
-            // S_ac is stored: entries (9a + i, 9c + j) in columns 9c + j
-            const double *col = A + 9 * (int64_t)c * Np + row;
+    const double *pc = p + 9 * c;
+    double v[9];
+    if (c < a) {
+        const double *col = A + 9 * (int64_t)c * Np + row;
 #pragma unroll
-            for (int j = 0; j < 9; ++j) acc += col[j * Np] * pc[j];
-        } else if (c > a) {
-            // S_ac = S_ca^T: entry (9c + j, 9a + i) of column 9a + i, nine in a run
-            const double *col = A + row * Np + 9 * (int64_t)c;
+        for (int j = 0; j < 9; ++j) v[j] = col[j * Np];
+    } else if (c > a) {
+        const double *col = A + row * Np + 9 * (int64_t)c;
 #pragma unroll
-            for (int j = 0; j < 9; ++j) acc += col[j] * pc[j];
-        } else {
+        for (int j = 0; j < 9; ++j) v[j] = col[j];
+    } else {
 #pragma unroll
-            for (int j = 0; j < 9; ++j) {
-                const int64_t rr = 9 * (int64_t)a + (i > j ? i : j), cc = 9 * (int64_t)a + (i > j ? j : i);
-                acc += A[cc * Np + rr] * pc[j];
-            }
+        for (int j = 0; j < 9; ++j) {
+            const int64_t rr = 9 * (int64_t)a + (i > j ? i : j), cc = 9 * (int64_t)a + (i > j ? j : i);
+            v[j] = A[cc * Np + rr];
         }
     }
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) acc += v[j] * pc[j];
+    return acc;
+}
+
+// (S p)_row for row = 9 a + i over camera a's linked cameras nbr[0..deg) (in
+// ascending order), four blocks' loads in flight at a time; the partial sums are
+// added in neighbour order.
+__device__ inline double spmv_row(const double *A, int64_t Np, const int16_t *nbr, int deg, int a, int i,
+                                  const double *p) {
+    double acc = 0.0;
+    int t = 0;
+    for (; t + 4 <= deg; t += 4) {
+        const double s0 = block_row_dot(A, Np, a, nbr[t], i, p);
+        const double s1 = block_row_dot(A, Np, a, nbr[t + 1], i, p);
+        const double s2 = block_row_dot(A, Np, a, nbr[t + 2], i, p);
+        const double s3 = block_row_dot(A, Np, a, nbr[t + 3], i, p);
+        acc += s0;
+        acc += s1;
+        acc += s2;
+        acc += s3;
+    }
+    for (; t < deg; ++t) acc += block_row_dot(A, Np, a, nbr[t], i, p);
     return acc;
 }
 
@@ -85,8 +104,8 @@ __global__ __launch_bounds__(kPcgThreads) void k_pcg(
     const int64_t *__restrict__ S_off, const int32_t *__restrict__ cl_start, const int32_t *__restrict__ cl_cams,
     const int32_t *__restrict__ cam_local, const int64_t *__restrict__ n_blocks, const int2 *__restrict__ blk_key,
     const double *__restrict__ S, const double *__restrict__ b, double *__restrict__ dcam, double *__restrict__ Minv,
-    int32_t max_np, int32_t max_iters, double tol, int32_t *__restrict__ iters_out, double *__restrict__ resid_out,
-    int32_t *__restrict__ cl_status) {
+    int32_t max_np, int32_t max_n, int32_t max_iters, double tol, int32_t *__restrict__ iters_out,
+    double *__restrict__ resid_out, int32_t *__restrict__ cl_status) {
     extern __shared__ double lds[];
     const int k = blockIdx.x, tid = threadIdx.x;
     const int n = cl_n[k], N = 9 * n;
@@ -98,9 +117,11 @@ __global__ __launch_bounds__(kPcgThreads) void k_pcg(
     double *red = q + max_np;
     int32_t *flag = reinterpret_cast<int32_t *>(red + kPcgWaves);
     uint32_t *bits = reinterpret_cast<uint32_t *>(flag + 2);
+    const int words = (n * n + 31) / 32;
+    int32_t *nbr_off = reinterpret_cast<int32_t *>(bits + ((max_n * max_n + 31) / 32));   // [max_n + 1]
+    int16_t *nbr = reinterpret_cast<int16_t *>(nbr_off + max_n + 1);                      // [max_n^2]
 
     // camera pairs of this cluster that the plan links (and every diagonal)
-    const int words = (n * n + 31) / 32;
     for (int w = tid; w < words; w += kPcgThreads) bits[w] = 0u;
     if (tid == 0) flag[0] = 0;
     __syncthreads();
@@ -148,6 +169,24 @@ __global__ __launch_bounds__(kPcgThreads) void k_pcg(
             }
         if (!ok) atomicOr(flag, 1);
     }
+    __syncthreads();
+    // neighbour lists: counts, offsets by a scan in camera order, ascending lists
+    for (int a = tid; a < n; a += kPcgThreads) {
+        int cnt = 0;
+        for (int c = 0; c < n; ++c) cnt += has_block(bits, n, a, c) ? 1 : 0;
+        nbr_off[a + 1] = cnt;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        nbr_off[0] = 0;
+        for (int a = 0; a < n; ++a) nbr_off[a + 1] += nbr_off[a];
+    }
+    __syncthreads();
+    for (int a = tid; a < n; a += kPcgThreads) {
+        int o = nbr_off[a];
+        for (int c = 0; c < n; ++c)
+            if (has_block(bits, n, a, c)) nbr[o++] = (int16_t)c;
+    }
     for (int row = tid; row < N; row += kPcgThreads) {
         x[row] = 0.0;
         r[row] = b[9 * (int64_t)cl_cams[c0 + row / 9] + row % 9];
@@ -172,7 +211,8 @@ __global__ __launch_bounds__(kPcgThreads) void k_pcg(
             // p is complete (the sums above end with a barrier)
             double pq_p = 0.0;
             for (int row = tid; row < N; row += kPcgThreads) {
-                const double qq = spmv_row(A, Np, bits, n, row / 9, row % 9, p);
+                const int a = row / 9;
+                const double qq = spmv_row(A, Np, nbr + nbr_off[a], nbr_off[a + 1] - nbr_off[a], a, row % 9, p);
                 q[row] = qq;
                 pq_p += p[row] * qq;
             }
@@ -217,7 +257,8 @@ __global__ __launch_bounds__(kPcgThreads) void k_pcg(
 
 size_t pcg_lds_bytes(int32_t max_np, int32_t max_n) {
     return sizeof(double) * (5 * (size_t)max_np + kPcgWaves) + 2 * sizeof(int32_t) +
-           sizeof(uint32_t) * (((size_t)max_n * max_n + 31) / 32);
+           sizeof(uint32_t) * (((size_t)max_n * max_n + 31) / 32) + sizeof(int32_t) * ((size_t)max_n + 1) +
+           sizeof(int16_t) * (size_t)max_n * max_n;
 }
 
 hipError_t launch_pcg(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, const int64_t *S_off,
@@ -229,7 +270,7 @@ hipError_t launch_pcg(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, cons
     if (shmem > 160 * 1024) return hipErrorInvalidConfiguration;
     k_cluster_of<<<(unsigned)l, 256, 0, st>>>(cl_start, cl_cams, clus);
     k_pcg<<<(unsigned)l, kPcgThreads, shmem, st>>>(clus, cl_n, cl_Np, S_off, cl_start, cl_cams, cam_local, n_blocks,
-                                                   blk_key, S, b, dcam, Minv, max_np, max_iters, tol, iters_out,
+                                                   blk_key, S, b, dcam, Minv, max_np, max_n, max_iters, tol, iters_out,
                                                    resid_out, cl_status);
     return hipGetLastError();
 }
