@@ -480,6 +480,23 @@ def pcg_leg(S, scene, maps, args, lam0):
             "ms": ms, "iterations_max": int(its.max().item()), "iterations_mean": float(its.double().mean().item()),
             "step_rel_diff_vs_cholesky": float(np.linalg.norm(x - ref) / np.linalg.norm(ref)),
             "status_ok": bool((cs == 0).all().item())}
+    # K LM iterations with the PCG solves (tol 1e-6) from x0 on the same maps
+    cam0, pt0 = sol.cam.clone(), sol.pt.clone()
+    samples = [sol.sample(maps[t], alpha=1.0, seed=0, it=t) for t in range(args.steps)]
+
+    def lm(pcg):
+        sol.cam.copy_(cam0)
+        sol.pt.copy_(pt0)
+        S.stba_lm_init(sol.state, lam0, 0.1)
+        for t in range(args.steps):
+            sol.step(samples[t], pcg=pcg)
+
+    lm(None)
+    F_chol = sol.read_state()["F"]
+    dt = timed(lambda: lm((5000, 1e-6)))
+    st = sol.read_state()
+    out["lm_tol_1e-6"] = {"iter_per_s": args.steps / dt, "F_after_K": st["F"], "F_after_K_cholesky": F_chol,
+                          "accepted": st["n_accept"], "status": st["status"]}
     return out
 
 

@@ -262,6 +262,13 @@ int stba_lm_step_profiled(const stba_problem *p, const stba_dims *dims, const st
                           stba_lm_state *st, int precision, void *ws, size_t ws_bytes, hipStream_t stream,
                           hipEvent_t *events);
 
+/* stba_lm_step with every cluster solve done by conjugate gradient as in
+ * stba_solve_clusters_pcg (max_iters, tol as there; an inexact step, App. A);
+ * a cluster reporting STBA_ENOTPD rejects the step as in stba_lm_step.  MIXED
+ * skips the refinement step (the solve is FP64 and iterative). */
+int stba_lm_step_pcg(const stba_problem *p, const stba_dims *dims, const stba_sample *s, stba_lm_state *st,
+                     int precision, int32_t max_iters, double tol, void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* Name of phase k of stba_lm_step_profiled (static string, host). */
 const char *stba_phase_name(int k);
 

@@ -450,10 +450,12 @@ class StbaStep:
 
 
 def stba_step(cam, pt, obs_cam, obs_pt, obs_uv, cam_cluster, lam, alpha=1.0, seed=0, t=0,
-              lam_corr=0.1, Jc=None, Jp=None, f=None, ids=None, huber=0.0):
+              lam_corr=0.1, Jc=None, Jp=None, f=None, ids=None, huber=0.0, pcg_opts=None):
     """One STBA step for a given clustering (Alg. 1, one pass of the while loop
     up to the point update).  ids: see `segments`.  huber > 0: the step of the
-    IRLS-reweighted problem (robust loss of Sec. 5.1, see `irls`)."""
+    IRLS-reweighted problem (robust loss of Sec. 5.1, see `irls`).
+    pcg_opts = (max_iters, tol): each cluster system solved by `pcg` (App. A)
+    instead of Cholesky."""
     m, n = cam.shape[0], pt.shape[0]
     if f is None:
         f = residuals(cam, pt, obs_cam, obs_pt, obs_uv)
@@ -493,6 +495,11 @@ def stba_step(cam, pt, obs_cam, obs_pt, obs_uv, cam_cluster, lam, alpha=1.0, see
         bk = b_full[idx]
         S_blocks.append(Sk)
         b_blocks.append(bk)
+        if pcg_opts is not None:
+            x, _, _, okp = pcg(Sk, bk, pcg_opts[1], pcg_opts[0])
+            dc[idx] = x if okp else 0.0
+            okk.append(bool(okp))
+            continue
         try:
             fac = scipy.linalg.cho_factor(Sk, lower=True, check_finite=True)
             dc[idx] = scipy.linalg.cho_solve(fac, bk)
@@ -598,13 +605,14 @@ class LmResult:
 
 
 def lm_iteration(cam, pt, obs_cam, obs_pt, obs_uv, cam_cluster, lam, alpha=1.0, seed=0, t=0,
-                 lam_corr=0.1, F=None, huber=0.0, lam_min=0.0):
+                 lam_corr=0.1, F=None, huber=0.0, lam_min=0.0, pcg_opts=None):
     """One pass of Alg. 1's loop: STBA step, then accept iff F(x + dx) < F(x)
     (F the robust cost when huber > 0); lambda / 3 on accept but not below
     lam_min (the lower bound of the correction ablation, Sec. 5.4), x 3 else."""
     if F is None:
         F = robust_cost(residuals(cam, pt, obs_cam, obs_pt, obs_uv), huber)
-    st = stba_step(cam, pt, obs_cam, obs_pt, obs_uv, cam_cluster, lam, alpha, seed, t, lam_corr, huber=huber)
+    st = stba_step(cam, pt, obs_cam, obs_pt, obs_uv, cam_cluster, lam, alpha, seed, t, lam_corr, huber=huber,
+                   pcg_opts=pcg_opts)
     cam_new = cam + st.dcam
     pt_new = pt + st.dpt
     F_new = robust_cost(residuals(cam_new, pt_new, obs_cam, obs_pt, obs_uv), huber) if st.ok else float("nan")

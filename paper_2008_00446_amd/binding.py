@@ -81,6 +81,8 @@ _SIGS = {
                                             ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64, _P, _P, _P, _P]),
     "stba_lm_init": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double, _P]),
     "stba_lm_step": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, _P, ctypes.c_size_t, _P]),
+    "stba_lm_step_pcg": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, ctypes.c_int32, ctypes.c_double, _P,
+                                        ctypes.c_size_t, _P]),
     "stba_lm_step_profiled": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, _P, ctypes.c_size_t, _P, _P]),
     "stba_residual_vjp": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
 }
@@ -238,6 +240,12 @@ def stba_lm_init(state, lambda0, lambda_corr=0.1, stream=None):
 def stba_lm_step(problem, dims, sample, state, precision, ws, stream=None):
     _check("stba_lm_step", load_library().stba_lm_step(_ref(problem), _ref(dims), _ref(sample), _ptr(state),
                                                        precision, _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def stba_lm_step_pcg(problem, dims, sample, state, precision, max_iters, tol, ws, stream=None):
+    _check("stba_lm_step_pcg", load_library().stba_lm_step_pcg(
+        _ref(problem), _ref(dims), _ref(sample), _ptr(state), precision, int(max_iters), float(tol), _ptr(ws),
+        ws.numel(), _stream(stream)))
 
 
 def stba_lm_step_profiled(problem, dims, sample, state, precision, ws, events, stream=None):

@@ -233,9 +233,15 @@ int solve_impl(const stba_problem *p, const stba_dims *d, int32_t l, const T *Jc
     return STBA_OK;
 }
 
+// Cluster solves by conjugate gradient instead of Cholesky (App. A).
+struct PcgOpts {
+    int32_t max_iters;
+    double tol;
+};
+
 template <typename T>
 int lm_step_impl(const stba_problem *p, const stba_dims *d, const stba_sample *s, stba_lm_state *stt,
-                 const Layout &L, void *ws, hipStream_t st, hipEvent_t *ev) {
+                 const Layout &L, void *ws, hipStream_t st, hipEvent_t *ev, const PcgOpts *pcg = nullptr) {
     int32_t *status = at<int32_t>(ws, L.status);
     const double *lam2 = &stt->lambda;   // lambda and lambda_corr are adjacent
     T *f = at<T>(ws, L.f), *Jc = at<T>(ws, L.Jc), *Jp = at<T>(ws, L.Jp);
@@ -272,7 +278,15 @@ int lm_step_impl(const stba_problem *p, const stba_dims *d, const stba_sample *s
                              at<double>(ws, L.b), st));
     STBA_TRY(mark(5));
     double *dcam = at<double>(ws, L.dcam), *dpt = at<double>(ws, L.dpt);
-    STBA_TRY(cluster_solve<T>(s->l, dcam, at<int32_t>(ws, L.cl_status), L, ws, st));
+    if (pcg)
+        STBA_HIP(launch_pcg(s->l, at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np), at<int64_t>(ws, L.S_off),
+                            at<int32_t>(ws, L.cl_start), at<int32_t>(ws, L.cl_cams), at<int32_t>(ws, L.cam_local),
+                            at<int64_t>(ws, L.n_blocks), at<int2>(ws, L.blk_key), at<double>(ws, L.S),
+                            at<double>(ws, L.b), dcam, at<int32_t>(ws, L.pcg_clus), at<double>(ws, L.pcg_minv),
+                            L.max_Np, d->gamma_max, pcg->max_iters, pcg->tol, at<int32_t>(ws, L.pcg_iters),
+                            at<double>(ws, L.pcg_resid), at<int32_t>(ws, L.cl_status), st));
+    else
+        STBA_TRY(cluster_solve<T>(s->l, dcam, at<int32_t>(ws, L.cl_status), L, ws, st));
     STBA_TRY(mark(6));
     STBA_HIP(launch_backsub<T>(*p, at<int64_t>(ws, L.pt_off), Jc, Jp, at<double>(ws, L.Vinv), at<double>(ws, L.wph),
                                dcam, dpt, L.group_size, at<int32_t>(ws, L.grp_first), st));
@@ -480,6 +494,18 @@ int stba_lm_step_profiled(const stba_problem *p, const stba_dims *dims, const st
 int stba_lm_step(const stba_problem *p, const stba_dims *dims, const stba_sample *s, stba_lm_state *st, int precision,
                  void *ws, size_t ws_bytes, hipStream_t stream) {
     return stba_lm_step_profiled(p, dims, s, st, precision, ws, ws_bytes, stream, nullptr);
+}
+
+int stba_lm_step_pcg(const stba_problem *p, const stba_dims *dims, const stba_sample *s, stba_lm_state *st,
+                     int precision, int32_t max_iters, double tol, void *ws, size_t ws_bytes, hipStream_t stream) {
+    Layout L;
+    STBA_TRY(front(p, dims, precision, ws, ws_bytes, L));
+    STBA_TRY(check_sample(p, s));
+    if (!st || max_iters < 0 || !(tol >= 0.0) || !std::isfinite(tol)) return STBA_EINVAL;
+    if (pcg_lds_bytes(L.max_Np, dims->gamma_max) > 160 * 1024) return STBA_EINVAL;
+    const PcgOpts o{max_iters, tol};
+    if (precision == STBA_FP64) return lm_step_impl<double>(p, dims, s, st, L, ws, stream, nullptr, &o);
+    return lm_step_impl<float>(p, dims, s, st, L, ws, stream, nullptr, &o);
 }
 
 int stba_residual_vjp(const stba_problem *p, const stba_dims *dims, int precision, const void *v, void *grad_cam,

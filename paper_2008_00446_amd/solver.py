@@ -74,9 +74,12 @@ class StbaSolver:
             raise B.StbaError("stba_sample_clusters", status)
         return B.make_sample(cc, l, alpha, seed, it)
 
-    def step(self, sample, events=None):
-        """One LM iteration (asynchronous)."""
-        if events is None:
+    def step(self, sample, events=None, pcg=None):
+        """One LM iteration (asynchronous); pcg = (max_iters, tol): the cluster
+        solves by conjugate gradient instead of Cholesky."""
+        if pcg is not None:
+            B.stba_lm_step_pcg(self.problem, self.dims, sample, self.state, self.precision, pcg[0], pcg[1], self.ws)
+        elif events is None:
             B.stba_lm_step(self.problem, self.dims, sample, self.state, self.precision, self.ws)
         else:
             B.stba_lm_step_profiled(self.problem, self.dims, sample, self.state, self.precision, self.ws, events)

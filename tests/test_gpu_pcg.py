@@ -111,3 +111,23 @@ def test_bad_arguments_are_rejected():
     for it, tol in [(-1, 1e-6), (10, float("nan")), (10, -1.0), (10, float("inf"))]:
         with pytest.raises(S.StbaError):
             solve_pcg(g, rcs, Jc, Jp, it, tol)
+
+
+@pytest.mark.parametrize("max_iters,tol", [(10, 0.0), (2000, 1e-12)])
+def test_lm_iterations_with_pcg_solves_match_oracle(max_iters, tol):
+    s = _small()
+    lam0 = 1e-3
+    sol = S.StbaSolver(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv, gamma_max=12, lambda0=lam0)
+    cam, pt, lam = s.cam0.copy(), s.pt0.copy(), lam0
+    F = O.cost(O.residuals(cam, pt, s.obs_cam, s.obs_pt, s.obs_uv))
+    for t in range(3):
+        lab = _map(s, 12, t)
+        sol.step(sol.sample(lab, it=t), pcg=(max_iters, tol))
+        st = sol.read_state()
+        r = O.lm_iteration(cam, pt, s.obs_cam, s.obs_pt, s.obs_uv, lab, lam, 1.0, 0, t, F=F,
+                           pcg_opts=(max_iters, tol))
+        assert st["status"] == 0 and bool(st["accepted"]) == r.accepted, t
+        assert st["lambda_"] == r.lam, t
+        assert abs(st["F"] - r.F) <= 1e-9 * r.F, t
+        cam, pt, lam, F = r.cam, r.pt, r.lam, r.F
+        assert rel(sol.cam.cpu().numpy() - s.cam0, cam - s.cam0) < 1e-7, t
