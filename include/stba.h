@@ -235,7 +235,8 @@ int stba_solve_clusters_pcg(const stba_problem *p, const stba_dims *dims, const 
  *   cam_cluster [m] (device int32): cluster of each camera, numbered 0..l-1 in
  *     order of each cluster's smallest camera.  n_clusters (device int32): l.
  *   status (device int32): STBA_OK once the map is written.
- * Requires p->m <= 2048 (the clustering runs in one workgroup) and stba_prepare.
+ * Requires p->m <= 2048 (the clustering runs in one workgroup), dims->n_pairs
+ * < 2^31 (edge weights are 32-bit) and stba_prepare.
  * Uses the workspace's plan buffers that only stba_prepare writes; asynchronous
  * (one kernel).  To fill a stba_sample the caller reads n_clusters back. */
 int stba_sample_clusters(const stba_problem *p, const stba_dims *dims, int precision, void *ws, size_t ws_bytes,

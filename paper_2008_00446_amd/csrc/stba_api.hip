@@ -437,6 +437,8 @@ int stba_sample_clusters(const stba_problem *p, const stba_dims *dims, int preci
     STBA_TRY(front(p, dims, precision, ws, ws_bytes, L));
     if (p->m > kSgcMaxCams || gamma < 1 || gamma > dims->gamma_max || !(beta >= 0.0) || !std::isfinite(beta))
         return STBA_EINVAL;
+    // pair weights and their sums are int32; the total weight is at most n_pairs
+    if (dims->n_pairs >= (int64_t(1) << 31)) return STBA_EINVAL;
     if (!cam_cluster || !n_clusters || !status) return STBA_EINVAL;
     // pair labels, clocks and weights per block (at most n_pairs blocks) live in
     // plan buffers that only stba_prepare uses
