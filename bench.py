@@ -77,6 +77,7 @@ def parse_args():
     ap.add_argument("--no-sgc", action="store_true", help="skip the device graph-clustering leg")
     ap.add_argument("--no-ablations", action="store_true", help="skip the synthetic ablations")
     ap.add_argument("--no-pcg", action="store_true", help="skip the inexact (PCG) cluster-solve leg")
+    ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay of the timed iterations")
     ap.add_argument("--ablation-iters", type=int, default=20)
     ap.add_argument("--pmc-summary", action="store_true",
                     help="write a profiles/pmc_*.txt summary from counter CSVs (no GPU work)")
@@ -285,6 +286,21 @@ def main():
     # timed: K iterations, nothing else on the stream
     elapsed = timed(lambda: run_iterations(sol, samples, cam0, pt0, lam0, args.steps))
     st = sol.read_state()
+    # the same K iterations captured once in a HIP graph and replayed (timed replay)
+    graph_ips = None
+    if not args.no_graph:
+        g = torch.cuda.CUDAGraph()
+        run_iterations(sol, samples, cam0, pt0, lam0, 0)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            for t in range(args.steps):
+                sol.step(samples[t])
+        run_iterations(sol, samples, cam0, pt0, lam0, 0)
+        g.replay()
+        run_iterations(sol, samples, cam0, pt0, lam0, 0)
+        graph_elapsed = timed(g.replay)
+        graph_ips = args.steps / graph_elapsed
+        assert sol.read_state()["F"] == st["F"], "graph replay diverged from the eager iterations"
     # per-phase split: the same iterations again with events between the phases
     P = S.STBA_NUM_PHASES
     evs = [S.hip_events(P + 1) for _ in range(args.steps)]
@@ -330,6 +346,7 @@ def main():
                        np.mean([mp.max() + 1 for mp in maps[:args.steps]])), "lambda0": lam0, "alpha": 1.0,
                    "lm_iterations": args.steps, "precision": args.precision},
         "obs_per_s": scene.q * args.steps / elapsed,
+        "graph_iter_per_s": graph_ips,
         "roofline": roofline,
         "phases": per_phase,
         "lm": {"F_final": st["F"],
