@@ -1,0 +1,45 @@
+"""Host-side checks of the benchmark: it refuses more than one GPU with a
+message, and its algorithmic model (the numerator of the roofline fraction)
+counts what it says, checked against brute force on a small scene."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+import bench
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr and r.stdout.strip() == ""
+
+
+def test_algorithmic_model_counts_pairs_and_flops():
+    s = synth.small_ring(m=20, n=400, views=5, seed=2)
+    e, w = synth.camera_graph(s.obs_cam, s.obs_pt, s.m)
+    maps = [synth.sgc_map(e, w, s.m, 6, 10.0, 0, t) for t in range(2)]
+    model, stats = bench.algorithmic_model(s, maps, 8)
+    pairs, flops, entries = [], [], []
+    for lab in maps:
+        p = 0
+        for j in range(s.n):
+            cams = s.obs_cam[s.obs_pt == j]
+            for a in range(cams.shape[0]):
+                for b in range(a + 1):
+                    p += int(lab[cams[a]] == lab[cams[b]])
+        pairs.append(p)
+        N = [9 * int((lab == k).sum()) for k in range(lab.max() + 1)]
+        flops.append(sum(x ** 3 / 3 + 2 * x ** 2 for x in N))
+        entries.append(sum(x * (x + 1) / 2 for x in N))
+    assert stats["schur_pairs"] == np.mean(pairs)
+    assert np.isclose(stats["chol_flops"], np.mean(flops), rtol=1e-12)
+    assert np.isclose(stats["S_lower_entries"], np.mean(entries), rtol=1e-12)
+    off = np.mean(pairs) - s.q
+    assert np.isclose(model["schur_assembly"]["flops"], 486 * off + 400 * s.q, rtol=1e-12)
+    assert np.isclose(model["cluster_cholesky"]["flops"], np.mean(flops), rtol=1e-12)
