@@ -1,0 +1,90 @@
+"""The differentiation batch: many independent ring problems concatenated into
+one with index offsets (cameras and points renumbered per problem), residuals
+forward and J^T v backward through the autograd function in one launch each,
+FP64 and FP32.  Checked per problem against the oracle's gradient 2 J^T f and
+against central differences of the oracle's FP64 cost on sampled coordinates
+(only the observations a coordinate touches change the cost)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_2008_00446_amd as S
+import synth
+from gpu_helpers import dev, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _concat(batch):
+    cams, pts, oc, op, uv, spans = [], [], [], [], [], []
+    c0 = p0 = 0
+    for s in batch:
+        cams.append(s.cam0)
+        pts.append(s.pt0)
+        oc.append(s.obs_cam + c0)
+        op.append(s.obs_pt + p0)
+        uv.append(s.obs_uv)
+        spans.append((c0, c0 + s.m, p0, p0 + s.n))
+        c0 += s.m
+        p0 += s.n
+    return (np.vstack(cams), np.vstack(pts), np.concatenate(oc).astype(np.int32),
+            np.concatenate(op).astype(np.int32), np.vstack(uv), spans)
+
+
+def _local_cost(s, cam, pt, obs):
+    f = O.residuals(cam, pt, s.obs_cam[obs], s.obs_pt[obs], s.obs_uv[obs])
+    return float(np.sum(f * f))
+
+
+@pytest.mark.parametrize("precision,tol", [(S.STBA_FP64, 1e-12), (S.STBA_MIXED, 1e-5)], ids=["fp64", "fp32"])
+def test_batched_gradient_matches_oracle_per_problem(precision, tol):
+    batch = synth.diff_batch(seeds=range(6))
+    cam, pt, oc, op, uv, spans = _concat(batch)
+    plan = S.ResidualPlan(oc, op, cam.shape[0], pt.shape[0], precision)
+    tc = dev(cam, torch.float64).requires_grad_(True)
+    tp = dev(pt, torch.float64).requires_grad_(True)
+    tu = dev(uv, torch.float64).requires_grad_(True)
+    f = S.residuals(tc, tp, tu, plan)
+    loss = (f.double() ** 2).sum()
+    loss.backward()
+    gc, gp, gu = tc.grad.cpu().numpy(), tp.grad.cpu().numpy(), tu.grad.cpu().numpy()
+    q0 = 0
+    F_all = 0.0
+    for s, (c0, c1, p0, p1) in zip(batch, spans):
+        rc, rp, ru = O.gradient(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv)
+        assert rel(gc[c0:c1], rc) < tol and rel(gp[p0:p1], rp) < tol
+        assert rel(gu[q0:q0 + s.q], ru) < tol
+        q0 += s.q
+        F_all += O.cost(O.residuals(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv))
+    assert abs(loss.item() - F_all) <= tol * F_all
+
+
+def test_batched_gradient_matches_central_differences():
+    batch = synth.diff_batch(seeds=range(3))
+    cam, pt, oc, op, uv, spans = _concat(batch)
+    plan = S.ResidualPlan(oc, op, cam.shape[0], pt.shape[0], S.STBA_FP64)
+    tc = dev(cam, torch.float64).requires_grad_(True)
+    tp = dev(pt, torch.float64).requires_grad_(True)
+    f = S.residuals(tc, tp, dev(uv, torch.float64), plan)
+    (f ** 2).sum().backward()
+    gc, gp = tc.grad.cpu().numpy(), tp.grad.cpu().numpy()
+    rng = np.random.default_rng(5)
+    h = 1e-4
+    for s, (c0, c1, p0, p1) in zip(batch, spans):
+        for _ in range(20):
+            i, k = int(rng.integers(s.m)), int(rng.integers(9))
+            obs = np.flatnonzero(s.obs_cam == i)
+            cp, cm = s.cam0.copy(), s.cam0.copy()
+            cp[i, k] += h
+            cm[i, k] -= h
+            fd = (_local_cost(s, cp, s.pt0, obs) - _local_cost(s, cm, s.pt0, obs)) / (2 * h)
+            assert abs(gc[c0 + i, k] - fd) <= 1e-5 * max(1.0, abs(fd)) + 1e-4 * abs(fd), (i, k)
+        for _ in range(20):
+            j, k = int(rng.integers(s.n)), int(rng.integers(3))
+            obs = np.flatnonzero(s.obs_pt == j)
+            pp, pm = s.pt0.copy(), s.pt0.copy()
+            pp[j, k] += h
+            pm[j, k] -= h
+            fd = (_local_cost(s, s.cam0, pp, obs) - _local_cost(s, s.cam0, pm, obs)) / (2 * h)
+            assert abs(gp[p0 + j, k] - fd) <= 1e-5 * max(1.0, abs(fd)) + 1e-4 * abs(fd), (j, k)
