@@ -229,7 +229,8 @@ int stba_solve_clusters_pcg(const stba_problem *p, const stba_dims *dims, const 
  * the clusters' smallest cameras, holds T = t + E / exp(beta dQ) with E = -log u,
  * u = ((x0 >> 11) + 1) 2^-53 and x0 word 0 of Philox4x64-10 with key (seed, 2),
  * counter (iter, join step, a, b); the smallest T (ties: smaller (a, b)) joins,
- * and the pairs of the joined cluster draw new clocks at the next step.
+ * and the pairs of the joined cluster draw new clocks with that join's step
+ * number (the initial clocks are step 0, the first join step 1).
  *   gamma: size cap, 1 <= gamma <= dims->gamma_max (so the map can be passed to
  *     the per-iteration calls of this workspace); beta >= 0, finite.
  *   cam_cluster [m] (device int32): cluster of each camera, numbered 0..l-1 in
@@ -237,8 +238,10 @@ int stba_solve_clusters_pcg(const stba_problem *p, const stba_dims *dims, const 
  *   status (device int32): STBA_OK once the map is written.
  * Requires p->m <= 2048 (the clustering runs in one workgroup), dims->n_pairs
  * < 2^31 (edge weights are 32-bit) and stba_prepare.
- * Uses the workspace's plan buffers that only stba_prepare writes; asynchronous
- * (one kernel).  To fill a stba_sample the caller reads n_clusters back. */
+ * Keeps its pair labels, clocks and weights in workspace buffers that only
+ * stba_prepare otherwise uses (a later stba_prepare rewrites them);
+ * asynchronous (one kernel).  To fill a stba_sample the caller reads n_clusters
+ * back. */
 int stba_sample_clusters(const stba_problem *p, const stba_dims *dims, int precision, void *ws, size_t ws_bytes,
                          int32_t gamma, double beta, uint64_t seed, uint64_t iter, int32_t *cam_cluster,
                          int32_t *n_clusters, int32_t *status, hipStream_t stream);
