@@ -77,3 +77,33 @@ def test_ctypes_structs_match_the_c_layout(tmp_path):
         py = structs[cname]
         got = ctypes.sizeof(py) if what == "size" else getattr(py, what).offset
         assert got == int(val), (cname, what, got, val)
+
+
+def test_product_path_never_imports_the_oracle_and_has_no_fallback(tmp_path):
+    """Importing and using the package's host side loads no oracle module, and a
+    missing library is an error, not a switch to some other path."""
+    import subprocess
+    import sys
+
+    code = (
+        "import sys\n"
+        f"sys.path.insert(0, {ROOT!r})\n"
+        "import paper_2008_00446_amd as P\n"
+        "from paper_2008_00446_amd import binding as B, solver\n"
+        "assert not any(m == 'oracle' or m.startswith('oracle.') for m in sys.modules), 'oracle imported'\n"
+        "try:\n"
+        f"    B._lib = None\n"
+        f"    B.load_library({str(tmp_path / 'missing.so')!r})\n"
+        "except ImportError:\n"
+        "    print('raised')\n"
+    )
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.strip() == "raised"
+    # and the package's sources do not name the oracle at all
+    pkg = os.path.join(ROOT, "paper_2008_00446_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
