@@ -58,3 +58,27 @@ def test_captured_iterations_replay_the_eager_ones(precision):
         assert torch.equal(sol.cam, ref_cam) and torch.equal(sol.pt, ref_pt), rep
         for key in ("F", "lambda_", "n_accept", "n_jac", "status"):
             assert st[key] == ref_state[key], (rep, key)
+
+
+def test_profiled_step_matches_the_plain_step():
+    """stba_lm_step_profiled records events between the phases and otherwise
+    runs the same iteration: identical results, ordered events, named phases."""
+    s = synth.small_ring(m=40, n=3000, views=8, seed=1)
+    K = 3
+    maps = _maps(s, 12, K)
+    out = []
+    for profiled in (False, True):
+        sol = S.StbaSolver(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv, gamma_max=12, lambda0=1e-3)
+        evs = [S.hip_events(S.STBA_NUM_PHASES + 1) for _ in range(K)] if profiled else None
+        for t in range(K):
+            sol.step(sol.sample(maps[t], it=t), events=None if evs is None else evs[t])
+        torch.cuda.synchronize()
+        out.append((sol.cam.cpu().numpy(), sol.pt.cpu().numpy(), sol.read_state()))
+        if profiled:
+            for ev in evs:
+                ms = [S.event_ms(ev[k], ev[k + 1]) for k in range(S.STBA_NUM_PHASES)]
+                assert all(v >= 0.0 for v in ms) and sum(ms) > 0.0
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    assert out[0][2]["F"] == out[1][2]["F"] and out[0][2]["lambda_"] == out[1][2]["lambda_"]
+    names = [S.stba_phase_name(k) for k in range(S.STBA_NUM_PHASES)]
+    assert len(set(names)) == S.STBA_NUM_PHASES and all(names)
