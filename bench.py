@@ -78,6 +78,8 @@ def parse_args():
     ap.add_argument("--no-ablations", action="store_true", help="skip the synthetic ablations")
     ap.add_argument("--no-pcg", action="store_true", help="skip the inexact (PCG) cluster-solve leg")
     ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay of the timed iterations")
+    ap.add_argument("--diff-batch", action="store_true",
+                    help="also time residuals + J^T v on the 64-problem differentiation batch (FP32)")
     ap.add_argument("--ablation-iters", type=int, default=20)
     ap.add_argument("--pmc-summary", action="store_true",
                     help="write a profiles/pmc_*.txt summary from counter CSVs (no GPU work)")
@@ -365,6 +367,8 @@ def main():
         out["pcg"] = pcg_leg(S, scene, maps, args, lam0)
     if not args.no_ablations and precision == S.STBA_FP64:
         out["ablations"] = ablation_leg(S, scene, args)
+    if args.diff_batch:
+        out["diff_batch"] = diff_batch_leg(S, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, maps, lam0, args.cpu_iters)
     else:
@@ -385,6 +389,52 @@ def huber_leg(S, scene, maps, args, lam0, cam0, pt0):
     st = solh.read_state()
     return {"scale": HUBER_SCALE, "iter_per_s": args.steps / t, "obs_per_s": scene.q * args.steps / t,
             "F_after_K": st["F"], "accepted": st["n_accept"], "status": st["status"]}
+
+
+def diff_batch_leg(S, args):
+    """The differentiation batch: 64 ring problems (m ~ U{30..120}, n ~ U{5k..30k},
+    7 views per point, seeds 0-63) concatenated with index offsets into one
+    problem; one forward (residuals, stba_residual_jacobian without J) and one
+    backward (stba_residual_vjp of v = 2 f, the gradient of sum ||f||^2 with the
+    Jacobian recomputed) per pass, in FP32, timed over K passes.  Algorithmic
+    bytes per pass: forward ids, pixel and f (24 + 2 es per observation),
+    backward ids, v and the pixel gradient (8 + 4 es per observation), plus the
+    gathered and reduced camera and point rows."""
+    import torch
+    import synth
+    batch = synth.diff_batch(seeds=range(64))
+    cam = np.vstack([b.cam0 for b in batch])
+    pt = np.vstack([b.pt0 for b in batch])
+    co = np.cumsum([0] + [b.m for b in batch])
+    po = np.cumsum([0] + [b.n for b in batch])
+    oc = np.concatenate([b.obs_cam + co[i] for i, b in enumerate(batch)]).astype(np.int32)
+    op = np.concatenate([b.obs_pt + po[i] for i, b in enumerate(batch)]).astype(np.int32)
+    uv = np.vstack([b.obs_uv for b in batch])
+    m, n, q = cam.shape[0], pt.shape[0], oc.shape[0]
+    plan = S.ResidualPlan(oc, op, m, n, S.STBA_MIXED)
+    dev = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to("cuda", dt)  # noqa: E731
+    tc, tp, tu = dev(cam, torch.float64), dev(pt, torch.float64), dev(uv, torch.float64)
+    prob = plan.problem(tc, tp, tu)
+    f = torch.empty((q, 2), dtype=torch.float32, device="cuda")
+    v = torch.empty_like(f)
+    gc = torch.empty((m, 9), dtype=torch.float32, device="cuda")
+    gp = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+    gu = torch.empty((q, 2), dtype=torch.float32, device="cuda")
+
+    def one():
+        S.stba_residual_jacobian(prob, plan.dims, S.STBA_MIXED, f, None, None, None, plan.ws)
+        torch.mul(f, 2.0, out=v)
+        S.stba_residual_vjp(prob, plan.dims, S.STBA_MIXED, v, gc, gp, gu, plan.ws)
+
+    for _ in range(args.warmup):
+        one()
+    K = args.steps
+    dt = timed(lambda: [one() for _ in range(K)])
+    es = 4
+    algo = q * ((24 + 2 * es) + (8 + 4 * es) + 2 * es) + (m * 72 + n * 24) + (m * 9 + n * 3) * es
+    return {"problems": len(batch), "observations": q, "cameras": m, "points": n,
+            "us_per_fwd_bwd": 1e6 * dt / K, "GB_per_s_algorithmic": algo * K / dt / 1e9,
+            "algorithmic_bytes_per_pass": algo}
 
 
 SGC_BETA = 10.0   # the clustering's scale beta
