@@ -14,105 +14,8 @@ inline unsigned grid_for(int64_t count, int bs = 256) { return (unsigned)((count
 // ---------------------------------------------------------------------------
 // cluster layout: cameras grouped by cluster (ascending id inside a cluster),
 // per-cluster sizes, padded orders and offsets of S_k (Eq. 13).
-// One workgroup of up to 1024 threads; bitonic sort of (cluster, camera) keys in LDS.
 // As the first kernel of an iteration it also clears the status words.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_clusters(const int32_t *cam_cluster, int32_t m, int32_t l,
-                                                   int32_t gamma_max, int32_t *cl_n, int32_t *cl_Np,
-                                                   int32_t *cl_start, int32_t *cl_cams, int32_t *cam_local,
-                                                   int64_t *S_off, int32_t *status) {
-    __shared__ uint32_t keys[kMaxCamsForClusters];
-    __shared__ int64_t part[1024];
-    __shared__ int bad;
-    const int tid = threadIdx.x;
-    const int nt = blockDim.x;
-    int P = 1;
-    while (P < m) P <<= 1;
-    if (tid < kStCount) status[tid] = 0;
-    if (tid == 0) bad = 0;
-    __syncthreads();
-    for (int i = tid; i < P; i += nt) {
-        uint32_t key = 0xFFFFFFFFu;
-        if (i < m) {
-            int k = cam_cluster[i];
-            if (k < 0 || k >= l) {
-                bad = 1;
-                k = 0;
-            }
-            key = ((uint32_t)k << 15) | (uint32_t)i;
-        }
-        keys[i] = key;
-    }
-    __syncthreads();
-    for (int size = 2; size <= P; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int i = tid; i < (P >> 1); i += nt) {
-                const int lo = 2 * stride * (i / stride) + (i % stride);
-                const int hi = lo + stride;
-                const bool up = (lo & size) == 0;
-                const uint32_t a = keys[lo], b = keys[hi];
-                if ((a > b) == up) {
-                    keys[lo] = b;
-                    keys[hi] = a;
-                }
-            }
-            __syncthreads();
-        }
-    }
-    for (int k = tid; k <= l; k += nt) {
-        int lo = 0, hi = m;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if ((int)(keys[mid] >> 15) < k) lo = mid + 1; else hi = mid;
-        }
-        cl_start[k] = lo;
-    }
-    for (int p = tid; p < m; p += nt) cl_cams[p] = (int32_t)(keys[p] & 0x7FFFu);
-    __syncthreads();
-    for (int p = tid; p < m; p += nt) {
-        const int32_t cam = (int32_t)(keys[p] & 0x7FFFu);
-        cam_local[cam] = p - cl_start[keys[p] >> 15];
-    }
-    for (int k = tid; k < l; k += nt) {
-        const int nk = cl_start[k + 1] - cl_start[k];
-        if (nk > gamma_max) bad = 2;
-        cl_n[k] = nk;
-        cl_Np[k] = (int32_t)round_up(9 * (int64_t)nk, kNB);
-    }
-    __syncthreads();
-    if (bad) {
-        // nothing is assembled or solved for an invalid map; the step is rejected
-        for (int k = tid; k < l; k += nt) {
-            cl_n[k] = 0;
-            cl_Np[k] = 0;
-        }
-        if (tid == 0) set_status(status + kStSticky, STBA_EINVAL);
-    }
-    __syncthreads();
-    // exclusive scan of Np^2 over clusters
-    const int chunk = (l + nt - 1) / nt;
-    const int k0 = tid * chunk, k1 = min(l, k0 + chunk);
-    int64_t s = 0;
-    for (int k = k0; k < k1; ++k) s += (int64_t)cl_Np[k] * cl_Np[k];
-    part[tid] = s;
-    __syncthreads();
-    if (tid == 0) {
-        int64_t run = 0;
-        for (int t = 0; t < nt; ++t) {
-            const int64_t v = part[t];
-            part[t] = run;
-            run += v;
-        }
-    }
-    __syncthreads();
-    s = part[tid];
-    for (int k = k0; k < k1; ++k) {
-        S_off[k] = s;
-        s += (int64_t)cl_Np[k] * cl_Np[k];
-    }
-    if (k0 < l && k1 == l) S_off[l] = s;
-}
-
 // Exclusive scan over the block (at most 1024 threads, whole wavefronts): wave
 // scans by shuffles, then a scan of the wave totals.  *total gets the sum.
 template <typename V>
@@ -203,6 +106,101 @@ __global__ __launch_bounds__(1024) void k_clusters_small(const int32_t *cam_clus
     const int64_t off = block_exclusive_scan<int64_t>(t < l ? (int64_t)np_out * np_out : 0, ws64, &tot64);
     if (t < l) S_off[t] = off;
     if (t == 0) S_off[l] = tot64;
+}
+
+// The same layout for any m (up to kMaxCamsForClusters): ceil(m / 256)
+// workgroups, each holding every camera's cluster id in LDS.  Every workgroup
+// counts the cameras per cluster and scans the counts (the same result in
+// each), then gives each of its 256 cameras its rank among the lower-numbered
+// cameras of its cluster, from vectorised LDS reads of the ids.  Workgroup 0
+// alone clears the status words and writes the per-cluster arrays and S_off,
+// so a bad map is reported after the clearing.
+constexpr int kClusterLargeThreads = 256;
+__global__ __launch_bounds__(kClusterLargeThreads) void k_clusters_large(
+    const int32_t *cam_cluster, int32_t m, int32_t l, int32_t gamma_max, int32_t *cl_n, int32_t *cl_Np,
+    int32_t *cl_start, int32_t *cl_cams, int32_t *cam_local, int64_t *S_off, int32_t *status) {
+    extern __shared__ __align__(16) int32_t dyn[];
+    const int32_t m4 = (int32_t)round_up(m, 4);
+    int32_t *ids = dyn;          // [m4], -1 for a bad id, -2 in the padding
+    int32_t *cnt = dyn + m4;     // [l] cameras per cluster, then the first slot of each cluster
+    __shared__ int32_t ws32[16];
+    __shared__ int64_t ws64[16];
+    __shared__ int bad;
+    const int t = threadIdx.x;
+    const bool lead = blockIdx.x == 0;
+    if (lead && t < kStCount) status[t] = 0;
+    if (t == 0) bad = 0;
+    for (int i = t; i < l; i += kClusterLargeThreads) cnt[i] = 0;
+    for (int i = t; i < m4; i += kClusterLargeThreads) {
+        int32_t k = -2;
+        if (i < m) {
+            k = cam_cluster[i];
+            if (k < 0 || k >= l) {
+                bad = 1;
+                k = -1;
+            }
+        }
+        ids[i] = k;
+    }
+    __syncthreads();
+    for (int i = t; i < m; i += kClusterLargeThreads)
+        if (ids[i] >= 0) atomicAdd(&cnt[ids[i]], 1);
+    __syncthreads();
+    // each thread scans a contiguous chunk of clusters
+    const int chunk = (l + kClusterLargeThreads - 1) / kClusterLargeThreads;
+    const int k0 = min(l, t * chunk), k1 = min(l, k0 + chunk);
+    int32_t loc = 0;
+    for (int k = k0; k < k1; ++k) {
+        loc += cnt[k];
+        if (cnt[k] > gamma_max) bad = 2;
+    }
+    int32_t tot32;
+    int32_t run = block_exclusive_scan<int32_t>(loc, ws32, &tot32);   // its barriers publish bad
+    const bool ok = bad == 0;
+    int64_t loc2 = 0;
+    for (int k = k0; k < k1; ++k) {
+        const int32_t nk = cnt[k];
+        const int32_t np_out = ok ? (int32_t)round_up(9 * (int64_t)nk, kNB) : 0;
+        if (lead) {
+            cl_n[k] = ok ? nk : 0;
+            cl_Np[k] = np_out;
+            cl_start[k] = run;
+        }
+        loc2 += (int64_t)np_out * np_out;
+        cnt[k] = run;
+        run += nk;
+    }
+    if (lead && t == 0) {
+        cl_start[l] = tot32;
+        if (!ok) set_status(status + kStSticky, STBA_EINVAL);
+    }
+    int64_t tot64;
+    int64_t off = block_exclusive_scan<int64_t>(loc2, ws64, &tot64);   // its barriers publish the cnt writes
+    if (lead) {
+        for (int k = k0; k < k1; ++k) {
+            S_off[k] = off;
+            const int32_t nk = (k + 1 < l ? cnt[k + 1] : tot32) - cnt[k];
+            const int64_t np = ok ? round_up(9 * (int64_t)nk, kNB) : 0;
+            off += np * np;
+        }
+        if (t == 0) S_off[l] = tot64;
+    }
+    // rank of camera i among the lower-numbered cameras of its cluster
+    const int32_t i = (int32_t)blockIdx.x * kClusterLargeThreads + t;
+    const int32_t k = i < m ? ids[i] : -1;
+    int32_t rank = 0;
+    const int4 *ids4 = reinterpret_cast<const int4 *>(ids);
+    const int32_t lim = i < m ? (i + 3) / 4 : 0;   // j4 < m4 / 4: inside ids
+#pragma unroll 4
+    for (int j4 = 0; j4 < lim; ++j4) {
+        const int4 v = ids4[j4];
+        const int j = 4 * j4;
+        rank += (j < i && v.x == k) + (j + 1 < i && v.y == k) + (j + 2 < i && v.z == k) + (j + 3 < i && v.w == k);
+    }
+    if (k >= 0) {
+        cl_cams[cnt[k] + rank] = i;
+        cam_local[i] = rank;
+    }
 }
 
 __global__ void k_reset_status(int32_t *status) {
@@ -1205,14 +1203,17 @@ __global__ __launch_bounds__(256) void k_accept_update(const double *rj_partials
                                                        stba_lm_state *st, int32_t m, int32_t n, double *cam,
                                                        double *pt, const double *dcam, const double *dpt) {
     __shared__ double sh[256];
-    __shared__ int bad_pd;
-    if (threadIdx.x == 0) bad_pd = 0;
+    __shared__ int bad_pd, bad_hip;
+    if (threadIdx.x == 0) bad_pd = bad_hip = 0;
     __syncthreads();
     double s = 0.0;
     for (int64_t i = threadIdx.x; i < count; i += 256) s += partials[i];
-    for (int k = threadIdx.x; k < l; k += 256)
-        if (cl_status[k] != STBA_OK) bad_pd = 1;
-    s = block_sum_256(s, sh);   // its barriers also publish bad_pd
+    for (int k = threadIdx.x; k < l; k += 256) {
+        const int32_t c = cl_status[k];
+        if (c == STBA_EHIP) bad_hip = 1;       // a factorisation wait timed out
+        else if (c != STBA_OK) bad_pd = 1;
+    }
+    s = block_sum_256(s, sh);   // its barriers also publish bad_pd and bad_hip
     const double Fn = s;
     const bool have_F = F_ref[1] != 0.0;
     double F0 = F_ref[0];
@@ -1221,7 +1222,7 @@ __global__ __launch_bounds__(256) void k_accept_update(const double *rj_partials
         for (int64_t i = threadIdx.x; i < count; i += 256) s0 += rj_partials[i];
         F0 = block_sum_256(s0, sh);
     }
-    const int32_t sticky = status[kStSticky];
+    const int32_t sticky = bad_hip ? STBA_EHIP : status[kStSticky];
     const bool pd = !bad_pd && status[kStPointBad] == 0;
     const bool fin = isfinite(Fn);
     const bool valid = pd && fin && sticky == 0;
@@ -1237,7 +1238,7 @@ __global__ __launch_bounds__(256) void k_accept_update(const double *rj_partials
         st->n_rcs += 1;
         st->n_accept += acc ? 1 : 0;
         st->n_jac += status[kStJacRan] ? 1 : 0;
-        st->last_status = !pd ? STBA_ENOTPD : (!fin ? STBA_ENONFINITE : sticky);
+        st->last_status = bad_hip ? STBA_EHIP : (!pd ? STBA_ENOTPD : (!fin ? STBA_ENONFINITE : sticky));
         if (st->status == 0 && sticky != 0) st->status = sticky;
     }
     if (!acc) return;
@@ -1342,15 +1343,9 @@ hipError_t launch_clusters(const int32_t *cam_cluster, int32_t m, int32_t l, int
                                                                   cl_cams, cam_local, S_off, status);
         return hipGetLastError();
     }
-    // one thread per compare-exchange of the bitonic sort, so a small map uses a
-    // small block (cheaper barriers)
-    int P = 1;
-    while (P < m) P <<= 1;
-    int threads = P / 2;
-    if (threads < 64) threads = 64;
-    if (threads > 1024) threads = 1024;
-    k_clusters<<<1, threads, 0, st>>>(cam_cluster, m, l, gamma_max, cl_n, cl_Np, cl_start, cl_cams, cam_local, S_off,
-                                      status);
+    const size_t lds = sizeof(int32_t) * ((size_t)round_up(m, 4) + (size_t)l);
+    k_clusters_large<<<(unsigned)((m + kClusterLargeThreads - 1) / kClusterLargeThreads), kClusterLargeThreads, lds,
+                       st>>>(cam_cluster, m, l, gamma_max, cl_n, cl_Np, cl_start, cl_cams, cam_local, S_off, status);
     return hipGetLastError();
 }
 
