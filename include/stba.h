@@ -57,7 +57,8 @@ extern "C" {
 #define STBA_ENOTPD     -2   /* a cluster matrix S_k is not positive definite */
 #define STBA_ENONFINITE -3   /* NaN / Inf in a step or cost */
 #define STBA_EWORKSPACE -4   /* workspace too small */
-#define STBA_EHIP       -5   /* a HIP runtime call failed */
+#define STBA_EHIP       -5   /* a HIP runtime call failed, or a wait inside a cluster factorisation
+                                timed out (device) */
 #define STBA_EDATA      -6   /* observations not sorted / duplicated / point unseen */
 
 /* Bundle-adjustment problem: the visibility graph and x = [c; p] (Sec. 3). */
@@ -109,7 +110,8 @@ typedef struct stba_lm_state {
     int32_t status;             /* sticky: first device-side error (STBA_* code), 0 if none */
     int32_t need_jac;           /* 1 if f and J must be evaluated at the current x */
     int32_t have_F;             /* 1 once F holds the cost at x */
-    int32_t last_status;        /* status of the last step only (0, STBA_ENOTPD, STBA_ENONFINITE) */
+    int32_t last_status;        /* status of the last step only (0, STBA_ENOTPD, STBA_ENONFINITE, STBA_EHIP,
+                                   or the sticky data error) */
     int32_t pad0;
     int64_t n_jac;              /* Jacobian evaluations */
     int64_t n_rcs;              /* RCS builds / solves */
@@ -188,7 +190,10 @@ int stba_build_cluster_rcs(const stba_problem *p, const stba_dims *dims, const s
  * dp_j = C_j^-1 (w_j - sum_o W_o^T dc) with the physical blocks (Eq. 15).
  * Jc, Jp: the Jacobian passed to stba_build_cluster_rcs.  dcam [m][9], dpt [n][3]
  * (device, FP64).  cluster_status (device int32 [l], nullable): STBA_OK or
- * STBA_ENOTPD per cluster.  The factorisation overwrites S in the workspace. */
+ * STBA_ENOTPD per cluster, or STBA_EHIP if a wait between the wavefronts that
+ * factor the cluster timed out (the step is then invalid; stba_lm_step rejects
+ * it and records STBA_EHIP in the sticky status).  The factorisation overwrites
+ * S in the workspace. */
 int stba_solve_clusters(const stba_problem *p, const stba_dims *dims, const stba_rcs *rcs, int precision,
                         const void *Jc, const void *Jp, double *dcam, double *dpt,
                         int32_t *cluster_status, void *ws, size_t ws_bytes, hipStream_t stream);

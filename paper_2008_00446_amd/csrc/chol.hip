@@ -1266,19 +1266,18 @@ __global__ void k_init_chol_sync(int32_t *flags, int64_t nf, double *yx, int64_t
 
 }  // namespace
 
-// Wavefronts of k_chol_tiles that the device holds at once (its dataflow waits
-// need every wavefront of the grid resident); 0 if the query fails.
+// Wavefronts of k_chol_tiles that the current device holds at once (its
+// dataflow waits need every wavefront of the grid resident); 0 if the query
+// fails.  Asked on every call (no cached state), so a change of the current
+// device is seen.
 int64_t chol_tile_resident() {
-    static const int64_t cap = [] {
-        int dev = 0, cus = 0, per_cu = 0;
-        if (hipGetDevice(&dev) != hipSuccess) return (int64_t)0;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return (int64_t)0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(k_chol_tiles), 64,
-                                                         0) != hipSuccess)
-            return (int64_t)0;
-        return (int64_t)cus * per_cu;
-    }();
-    return cap;
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(k_chol_tiles), 64, 0) !=
+        hipSuccess)
+        return 0;
+    return (int64_t)cus * per_cu;
 }
 
 int chol_tile_layout(int32_t l, int32_t max_Np, int32_t *wpc, int32_t *tmax, int32_t *fpc, int32_t *xcd_major) {
