@@ -123,3 +123,11 @@ def rel_max(a, b):
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def kappa_scaled(Sk):
+    """kappa(D^-1 S_k D^-1), D = diag(S_k)^(1/2): the condition number that bounds
+    how much FP64 rounding in S_k or b_k (about 1e-16 relative) can move the step."""
+    Sk = np.asarray(Sk, dtype=np.float64)
+    d = np.sqrt(np.diag(Sk))
+    return float(np.linalg.cond(Sk / np.outer(d, d)))

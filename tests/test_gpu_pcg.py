@@ -10,7 +10,25 @@ import torch
 import oracle as O
 import paper_2008_00446_amd as S
 import synth
-from gpu_helpers import GpuProblem, rel, solve_pcg, ws_view
+from gpu_helpers import GpuProblem, kappa_scaled, rel, solve_pcg, ws_view
+
+
+def _kappas(ref):
+    """kappa(S_k) and kappa(D^-1 S_k D^-1) of every cluster system of the oracle's step."""
+    return [(float(np.linalg.cond(Sk)), kappa_scaled(Sk)) for Sk in ref.S_blocks]
+
+
+def _report(tag, kap, dc_err, dp_err, tol):
+    k_max = max(k for k, _ in kap)
+    ks_max = max(k for _, k in kap)
+    # stopping at ||r|| <= tol ||b|| bounds the relative error of each cluster's
+    # step by kappa(S_k) tol; with FP64 rounding of S_k alone the bound is
+    # about kappa_scaled 1e-16
+    print(f"{tag}: max kappa(S_k) {k_max:.2e}, max kappa(D^-1 S_k D^-1) {ks_max:.2e}, "
+          f"kappa tol {k_max * tol:.1e}, kappa_scaled eps {ks_max * 1e-16:.1e}; "
+          f"errors dcam {dc_err:.2e} dpt {dp_err:.2e}", flush=True)
+    return k_max, ks_max
+
 
 pytestmark = pytest.mark.gpu
 
@@ -50,9 +68,12 @@ def test_converged_pcg_matches_the_exact_step(lam, alpha):
     dcam, dpt, cs, its, res = solve_pcg(g, rcs, Jc, Jp, 1000, 1e-12)
     ref = O.stba_step(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv, lab, lam, alpha, 3)
     print(f"pcg small ring lam={lam} alpha={alpha}: iterations {its.tolist()}", flush=True)
+    k_max, _ = _report("small ring", _kappas(ref), rel(dcam, ref.dcam), rel(dpt, ref.dpt), 1e-12)
     assert np.all(cs == 0) and np.all(res <= 1e-12) and np.all(its < 1000)
-    assert rel(dcam, ref.dcam) < 1e-8
-    assert rel(dpt, ref.dpt) < 1e-8
+    # the stopping rule's bound, not below the FP64 bar
+    bar = max(1e-9, 10.0 * k_max * 1e-12)
+    assert rel(dcam, ref.dcam) < bar
+    assert rel(dpt, ref.dpt) < bar
 
 
 def test_ring_pcg_matches_the_exact_step():
@@ -64,9 +85,11 @@ def test_ring_pcg_matches_the_exact_step():
     dcam, dpt, cs, its, res = solve_pcg(g, rcs, Jc, Jp, 2000, 1e-12)
     print(f"pcg ring: iterations {its.tolist()} residuals {res.tolist()}", flush=True)
     ref = O.stba_step(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv, lab, 1e-4)
+    k_max, _ = _report("ring", _kappas(ref), rel(dcam, ref.dcam), rel(dpt, ref.dpt), 1e-12)
     assert np.all(cs == 0) and np.all(res <= 1e-12)
-    assert rel(dcam, ref.dcam) < 1e-7
-    assert rel(dpt, ref.dpt) < 1e-7
+    bar = max(1e-9, 10.0 * k_max * 1e-12)
+    assert rel(dcam, ref.dcam) < bar
+    assert rel(dpt, ref.dpt) < bar
 
 
 def test_mixed_precision_pcg_within_the_mixed_bar():
@@ -99,7 +122,8 @@ def test_non_positive_definite_cluster_is_reported():
     assert not dcam[lab == bad].any()
     ref = O.stba_step(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv, lab, 1e-3)
     good = lab != bad
-    assert rel(dcam[good], ref.dcam[good]) < 1e-8
+    k_max, _ = _report("non-PD cluster", _kappas(ref), rel(dcam[good], ref.dcam[good]), 0.0, 1e-12)
+    assert rel(dcam[good], ref.dcam[good]) < max(1e-9, 10.0 * k_max * 1e-12)
 
 
 def test_bad_arguments_are_rejected():
@@ -130,4 +154,14 @@ def test_lm_iterations_with_pcg_solves_match_oracle(max_iters, tol):
         assert st["lambda_"] == r.lam, t
         assert abs(st["F"] - r.F) <= 1e-9 * r.F, t
         cam, pt, lam, F = r.cam, r.pt, r.lam, r.F
-        assert rel(sol.cam.cpu().numpy() - s.cam0, cam - s.cam0) < 1e-7, t
+        err = rel(sol.cam.cpu().numpy() - s.cam0, cam - s.cam0)
+        kap = _kappas(r.step)
+        _report(f"LM iteration {t}, {max_iters} iterations tol {tol:g}", kap, err, 0.0, tol)
+        # both sides run the same recurrence on S_k that differ by FP64 assembly
+        # rounding; conjugate gradient passes such differences on to its
+        # iterates scaled by up to kappa(D^-1 S_k D^-1), and a converged solve
+        # is bounded by the stopping rule
+        ks_max = max(k for _, k in kap)
+        k_max = max(k for k, _ in kap)
+        bar = max(1e-9, 1e3 * ks_max * 1e-16, 10.0 * k_max * tol if tol > 0 else 0.0)
+        assert err < bar, t

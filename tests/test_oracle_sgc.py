@@ -170,6 +170,36 @@ def test_final_maps_follow_the_exact_law(gamma):
             assert _chi2_pvalue(bad, counts, n) < 1e-6
 
 
+# a second graph: two dense triangles joined through camera 6 by weak edges, with
+# one heavy edge across, so that the cap decides which communities can form
+G7_EDGES = np.array([[0, 1], [1, 2], [0, 2], [3, 4], [4, 5], [3, 5], [2, 6], [6, 3], [1, 4], [0, 6]])
+G7_W = np.array([9, 7, 8, 6, 9, 5, 1, 2, 12, 1])
+
+
+@pytest.mark.parametrize("gamma,beta", [(5, 25.0), (6, 4.0)])
+def test_final_maps_follow_the_exact_law_second_graph(gamma, beta):
+    m, n = 7, 3000
+    law = _exact_law(G7_EDGES, G7_W, m, gamma, beta)
+    assert abs(sum(law.values()) - 1.0) < 1e-12
+    assert len(law) > 3
+    counts = {}
+    for t in range(n):
+        lab, l = oracle.sgc_clusters(G7_EDGES, G7_W, m, gamma, beta, seed=13, t=t)
+        key = _canonical(lab)
+        assert l == max(key) + 1 and np.bincount(lab).max() <= gamma
+        counts[key] = counts.get(key, 0) + 1
+    assert _chi2_pvalue(law, counts, n) > 1e-3
+    wrong = [
+        lambda A, lab, x, y: A[np.ix_(lab == x, lab == y)].sum() / (A.sum() / 2),
+        lambda A, lab, x, y: -(_modularity(A, np.where(lab == y, x, lab)) - _modularity(A, lab)),
+        lambda A, lab, x, y: 0.0,
+    ]
+    for g in wrong:
+        bad = _exact_law(G7_EDGES, G7_W, m, gamma, beta, gain=g)
+        if max(abs(bad.get(k, 0.0) - law.get(k, 0.0)) for k in set(bad) | set(law)) > 0.05:
+            assert _chi2_pvalue(bad, counts, n) < 1e-6
+
+
 def test_host_harness_draws_the_same_law():
     m, gamma, beta, n = 6, 3, 10.0, 3000
     law = _exact_law(G6_EDGES, G6_W, m, gamma, beta)
