@@ -16,7 +16,7 @@ import torch
 import oracle as O
 import paper_2008_00446_amd as S
 import synth
-from cluster_cut import cut_args, cut_cluster
+from synth.cluster_cut import cut_args, cut_cluster
 from gpu_helpers import GpuProblem, rel, rel_max
 
 pytestmark = pytest.mark.gpu

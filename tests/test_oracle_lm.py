@@ -19,7 +19,7 @@ import pytest
 
 import oracle as O
 import synth
-from cluster_cut import cut_args, cut_cluster
+from synth.cluster_cut import cut_args, cut_cluster
 
 
 def _tiny(seed=3, m=5, n=12, views=3):
