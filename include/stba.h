@@ -14,7 +14,8 @@
  * Conventions shared by every entry point
  *  - Pointers are DEVICE pointers unless the comment says (host).  The caller
  *    owns all memory; the library never allocates or frees and keeps no global
- *    state.  Everything it needs between calls lives in the caller's workspace.
+ *    state.  Everything it needs between calls lives in the caller's workspace
+ *    (the one exception: the scratch of stba_residual_jacobian_static).
  *  - Calls that take a stream only enqueue work on it and return; they do not
  *    synchronise (stba_analyze is the one exception and says so).
  *  - Host-detectable argument errors return an error code before anything is
@@ -172,6 +173,22 @@ int stba_prepare(const stba_problem *p, const stba_dims *dims, int precision, vo
  * then solve the reweighted problem.  Uses the workspace for partial sums. */
 int stba_residual_jacobian(const stba_problem *p, const stba_dims *dims, int precision, void *f, void *Jc,
                            void *Jp, double *cost, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* For callers that cannot allocate (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): stba_residual_jacobian without a
+ * workspace, dims or stba_prepare.  Same kernels and results (bit for bit) as
+ * stba_residual_jacobian with the same arguments.  The cost's per-workgroup
+ * partial sums go to a scratch array of 65536 doubles (512 KiB) that the
+ * library keeps in device memory, one copy per GPU it runs on, held until the
+ * process ends; nothing is allocated or freed by the call.  The first call on a
+ * device looks that device's copy up (hipGetSymbolAddress) with the device
+ * current.  Limits: with cost != NULL, q <= 2^24 (65536 partials of 256
+ * observations), else STBA_EWORKSPACE before anything is enqueued; other
+ * argument errors as stba_residual_jacobian.  Calls that overlap on one GPU
+ * (other streams, or other host threads before the first call finishes) share
+ * that GPU's scratch and race on the cost: serialise them. */
+int stba_residual_jacobian_static(const stba_problem *p, int precision, void *f, void *Jc, void *Jp, double *cost,
+                                  hipStream_t stream);
 
 /* Assemble one reduced camera system per cluster (Eq. 10, 13; Alg. 1): draw the
  * sampled constraints as point segments, form the segment blocks C', E', the

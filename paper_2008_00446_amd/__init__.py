@@ -8,7 +8,8 @@ from .binding import (  # noqa: F401
     STBA_FP64, STBA_MIXED, STBA_NUM_PHASES, StbaError, load_library, make_problem, make_sample,
     alloc_workspace, new_state, read_state, set_lambda_min, StbaDamping, StbaDims,
     stba_version, stba_phase_name, stba_analyze_scratch_bytes, stba_analyze, stba_workspace_bytes, stba_prepare,
-    stba_residual_jacobian, stba_build_cluster_rcs, stba_solve_clusters, stba_solve_clusters_pcg,
+    stba_residual_jacobian, stba_residual_jacobian_static, stba_build_cluster_rcs, stba_solve_clusters,
+    stba_solve_clusters_pcg,
     stba_sample_clusters, stba_lm_step_pcg, stba_lm_init,
     stba_lm_step,
     stba_lm_step_profiled, stba_residual_vjp,

@@ -72,6 +72,7 @@ _SIGS = {
     "stba_workspace_bytes": (ctypes.c_size_t, [_P, _P, ctypes.c_int]),
     "stba_prepare": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, ctypes.c_size_t, _P]),
     "stba_residual_jacobian": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "stba_residual_jacobian_static": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P, _P]),
     "stba_build_cluster_rcs": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, _P, _P, _P, _P, _P,
                                               ctypes.c_size_t, _P]),
     "stba_solve_clusters": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
@@ -199,6 +200,12 @@ def stba_residual_jacobian(problem, dims, precision, f, Jc, Jp, cost, ws, stream
     _check("stba_residual_jacobian", load_library().stba_residual_jacobian(
         _ref(problem), _ref(dims), precision, _ptr(f), _ptr(Jc), _ptr(Jp), _ptr(cost), _ptr(ws), ws.numel(),
         _stream(stream)))
+
+
+def stba_residual_jacobian_static(problem, precision, f, Jc, Jp, cost, stream=None):
+    """stba_residual_jacobian without a workspace (the library's own scratch, no allocation)."""
+    _check("stba_residual_jacobian_static", load_library().stba_residual_jacobian_static(
+        _ref(problem), precision, _ptr(f), _ptr(Jc), _ptr(Jp), _ptr(cost), _stream(stream)))
 
 
 def stba_build_cluster_rcs(problem, dims, sample, damping, precision, f, Jc, Jp, ws, stream=None) -> StbaRcs:

@@ -2,6 +2,7 @@
 // order in which one LM iteration (Alg. 1) enqueues its kernels.
 #include <math.h>
 #include <cmath>
+#include <mutex>
 #include <string.h>
 
 #include "kernels.h"
@@ -301,6 +302,37 @@ int lm_step_impl(const stba_problem *p, const stba_dims *d, const stba_sample *s
     return STBA_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of the entry point that allocates nothing (stba_residual_jacobian_static):
+// the per-workgroup cost partials of the residual kernel, one double per 256
+// observations, in a file-scope device array of kStaticPartials entries that
+// every GPU the library runs on holds until the process ends.  Host code never
+// uses the array's name as an address: each device's copy is found once, with
+// that device current, by hipGetSymbolAddress, and that pointer is what the
+// kernels are given.
+// ---------------------------------------------------------------------------
+constexpr int64_t kStaticPartials = 65536;           // 512 KiB: up to 2^24 observations
+constexpr int kStaticMaxDevices = 64;
+static __device__ __align__(256) double scratch[kStaticPartials];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kStaticMaxDevices] = {};
+
+// This device's copy of `scratch` (found on the first call on the device).
+int static_scratch(double **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return STBA_EHIP;
+    if (dev < 0 || dev >= kStaticMaxDevices) return STBA_EINVAL;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr) return STBA_EHIP;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = static_cast<double *>(g_scratch_ptr[dev]);
+    return STBA_OK;
+}
+
 const char *const kPhaseNames[STBA_NUM_PHASES] = {
     "clusters", "residual_jacobian", "points_segments", "fill_S", "schur_assembly",
     "cluster_cholesky", "point_backsub", "candidate_cost", "accept_update"};
@@ -385,6 +417,25 @@ int stba_residual_jacobian(const stba_problem *p, const stba_dims *dims, int pre
         STBA_HIP(launch_rj<float>(*p, (float *)f, (float *)Jc, (float *)Jp, partials, nullptr, nullptr, ZeroS(),
                                   stream));
     if (cost) STBA_HIP(launch_sum_partials(partials, L.n_partials, cost, stream));
+    return STBA_OK;
+}
+
+int stba_residual_jacobian_static(const stba_problem *p, int precision, void *f, void *Jc, void *Jp, double *cost,
+                                  hipStream_t stream) {
+    STBA_TRY(check_problem(p));
+    STBA_TRY(check_precision(precision));
+    if (!f || ((Jc == nullptr) != (Jp == nullptr))) return STBA_EINVAL;
+    const int64_t nb = rj_blocks(p->q);
+    if (cost && nb > kStaticPartials) return STBA_EWORKSPACE;   // more observations than the scratch holds
+    double *partials = nullptr;
+    if (cost) STBA_TRY(static_scratch(&partials));
+    if (precision == STBA_FP64)
+        STBA_HIP(launch_rj<double>(*p, (double *)f, (double *)Jc, (double *)Jp, partials, nullptr, nullptr, ZeroS(),
+                                   stream));
+    else
+        STBA_HIP(launch_rj<float>(*p, (float *)f, (float *)Jc, (float *)Jp, partials, nullptr, nullptr, ZeroS(),
+                                  stream));
+    if (cost) STBA_HIP(launch_sum_partials(partials, nb, cost, stream));
     return STBA_OK;
 }
 
