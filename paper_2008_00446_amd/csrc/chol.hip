@@ -1254,6 +1254,490 @@ __global__ __launch_bounds__(256) void k_resid(int32_t nrb, const int32_t *__res
     }
 }
 
+// ---------------------------------------------------------------------------
+// Team factorisation for maps with many clusters (when one wavefront per tile
+// of every cluster would not be resident at once).  One launch of G
+// one-wavefront workgroups; every wavefront works out its cluster and role
+// from the clusters' padded orders (the same arithmetic in every wavefront):
+// cluster k gets a band wavefront and W_k workers, W_k proportional to T_k^3
+// (its share of the factorisation's work), at least one when there are tiles
+// below the first subdiagonal.  The tiles stay in memory; every hand-over
+// goes through device-scope stores, flags raised after the stores complete,
+// and device-scope loads.
+//   band: the diagonal chain as in the tile-parallel form (partial tiles P_ii
+//     and P_i,i-1 -> panel L_i,i-1 with W_i-1 in LDS, last update of the
+//     diagonal tile, factor and inverse) with the forward substitution folded
+//     in: y_i = W_ii (b_i - sum_{j <= i-2} c_ij - L_i,i-1 y_i-1), where the
+//     workers publish c_ij = L_ij y_j; after the last diagonal tile the
+//     backward substitution x_i = W_ii^T (y_i - sum_{j >= i+2} d_ji -
+//     L_i+1,i^T x_i+1) with d_ji = L_ji^T x_j from the workers.
+//   workers: own a share of the tasks (round robin over the task list in
+//     column order): R(i), 2 <= i < T, applies A_ii -= L_ip L_ip^T and
+//     A_i,i-1 -= L_ip L_i-1,p^T for p <= i - 2 and publishes the partial tiles;
+//     F(i, j), j <= i - 2, applies A_ij -= L_ip L_jp^T for p < j, solves the
+//     panel L_ij = A_ij W_jj^T, then publishes c_ij and, once x_i is known,
+//     d_ij.  A worker never waits on one task: each pass checks every pending
+//     task's inputs at once (one flag load per lane) and advances the ready
+//     ones, applying all the consecutive updates whose panels are final in one
+//     visit of the tile.
+// Flags of cluster k start at 2 S_off[k] / 1024 + 8 k: F(i, j) final at
+// i (i + 1) / 2 + j (2 on a failed pivot of a diagonal tile), then per block
+// row the partial tiles, y_i and x_i published, then the error word and the
+// count of finished wavefronts.  Block vectors (c, d per tile, y, x per block
+// row) start at S_off[k] / 32 in their buffers and hold kEmpty between uses.
+// ---------------------------------------------------------------------------
+constexpr int kTeamLook = 4;   // updates a worker checks ahead per task and pass
+
+struct TeamBufs {
+    int32_t *flags;      // cluster flag words, then the abort word and the finished-cluster count
+    int64_t abort_at;    // index of the abort word
+    double *cv, *dv, *yv, *xv;
+};
+
+__device__ inline int64_t team_fbase(const int64_t *S_off, int k) { return 2 * (S_off[k] >> 10) + 8 * (int64_t)k; }
+__device__ inline int64_t team_vbase(const int64_t *S_off, int k) { return S_off[k] >> 5; }
+
+// Non-blocking flag test (lane-local).
+__device__ inline bool flag_set(const int32_t *f) {
+    return __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+
+__host__ __device__ inline int team_ntasks(int T) { return T < 3 ? 0 : (T - 2) + (T - 1) * (T - 2) / 2; }
+
+// Task g of a cluster with T block rows, column-major groups: column j holds
+// R(j + 2) and then F(j + 2 .. T - 1, j).  Packed as kind << 30 | i << 15 | j
+// (kind 0: F, 1: R).
+__device__ inline int32_t team_task(int g, int T) {
+    int j = 0;
+    while (true) {
+        const int n = T - 1 - j;   // tasks of column j
+        if (g < n) break;
+        g -= n;
+        ++j;
+    }
+    if (g == 0) return (1 << 30) | ((j + 2) << 15) | (j + 1);   // R(j + 2): its tiles are (i, i), (i, i - 1)
+    return ((j + 1 + g) << 15) | j;
+}
+
+// This wavefront's cluster k, its index r in the team (0: band) and the
+// number of workers W (every wavefront computes the same layout).
+__device__ inline bool team_role(int wave, int G, int l, const int32_t *cl_Np, int &k_out, int &r_out, int &W_out) {
+    const int lane = threadIdx.x & 63;
+    int64_t sw = 0;
+    int n3 = 0;
+    for (int k = lane; k < l; k += 64) {
+        const int T = cl_Np[k] / kNB;
+        if (T >= 3) {
+            sw += (int64_t)T * T * T;
+            ++n3;
+        }
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        sw += __shfl_xor(sw, d, 64);
+        n3 += __shfl_xor(n3, d, 64);
+    }
+    const int64_t wtot = (int64_t)G - l - n3;
+    if (wtot < 0) return false;
+    int64_t base = 0;
+    for (int c0 = 0; c0 < l; c0 += 64) {
+        const int k = c0 + lane;
+        int64_t size = 0, W = 0;
+        if (k < l) {
+            const int T = cl_Np[k] / kNB;
+            if (T >= 3) {
+                W = sw > 0 ? wtot * ((int64_t)T * T * T) / sw : 0;
+                if (W < 1) W = 1;
+                if (W > team_ntasks(T)) W = team_ntasks(T);
+            }
+            size = 1 + W;
+        }
+        int64_t inc = size;   // inclusive scan over the 64 clusters of this chunk
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int64_t n = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += n;
+        }
+        const int64_t start = base + inc - size;
+        const unsigned long long hit = __ballot(k < l && wave >= start && wave < start + size);
+        if (hit) {
+            const int src = __ffsll(hit) - 1;
+            k_out = c0 + src;
+            r_out = wave - __shfl((int)start, src, 64);
+            W_out = __shfl((int)W, src, 64);
+            return true;
+        }
+        base += __shfl((int)inc, 63, 64);
+    }
+    return false;
+}
+
+// y[r] = sum_c M[r][c] z[c] over a 32 x 32 row-major LDS matrix, lanes (r, half);
+// the sum of both halves lands in lanes r and r + 32.
+__device__ inline double lds_matvec(const double (*M)[kNB + 1], const double *z, int lane) {
+    const int r = lane & (kNB - 1), hc = 16 * (lane >> 5);
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int m = 0; m < 16; ++m) a[m & 3] = fma(M[r][hc + m], z[hc + m], a[m & 3]);
+    return halves((a[0] + a[1]) + (a[2] + a[3]));
+}
+
+// Wait for a published block vector, take it and return its slot to kEmpty.
+__device__ inline double take_vec(double *v, int32_t *abort_w, bool &ok, int lane) {
+    const double x = wait_vec(v, abort_w, ok);
+    if (lane < kNB) st_dev(v + lane, __longlong_as_double(kEmpty));
+    return x;
+}
+
+__device__ __forceinline__ bool team_band(int k, const int64_t *S_off, const int32_t *cl_n, const int32_t *cl_Np,
+                                          const int32_t *cl_start, const int32_t *cl_cams, double *S, const double *b,
+                                          double *dcam, const TeamBufs &tb, double (*Wi)[kNB + 1],
+                                          double (*Ls)[kNB + 1], double *zs, double *ys) {
+    const int lane = threadIdx.x;
+    const int64_t Np = cl_Np[k];
+    const int T = (int)(Np / kNB);
+    if (T == 0) return true;
+    const int tt = T * (T + 1) / 2;
+    int32_t *fl = tb.flags + team_fbase(S_off, k);
+    int32_t *fl_part = fl + tt, *fl_y = fl_part + T, *fl_x = fl_y + T;
+    int32_t *abort_w = tb.flags + tb.abort_at;
+    const int64_t vb = team_vbase(S_off, k);
+    double *cv = tb.cv + vb, *dv = tb.dv + vb, *yv = tb.yv + vb, *xv = tb.xv + vb;
+    double *A = S + S_off[k];
+    const int lr = lane & 15, lk = lane >> 4;
+    const int r = lane & (kNB - 1), hc = 16 * (lane >> 5);
+    const int N = 9 * cl_n[k];
+    const int c0 = cl_start[k];
+    bool ok = true;
+    __builtin_amdgcn_s_setprio(3);
+    for (int i = 0; i < T; ++i) {
+        const int64_t ri = (int64_t)i * kNB;
+        const int64_t row = ri + r;
+        const double bi = row < N ? b[9 * (int64_t)cl_cams[c0 + row / 9] + row % 9] : 0.0;
+        d4 accD[2][2], accP[2][2];
+        if (i >= 2) ok &= wait_flag(fl_part + i, abort_w) != 0;
+        load_tile_dev(A, Np, ri, ri, lr, lk, accD);
+        double clast = 0.0;
+        if (i >= 1) {
+            load_tile_dev(A, Np, ri, ri - kNB, lr, lk, accP);
+            d4 x[2][2];
+            panel_solve_lds(accP, Wi, lr, lk, x);
+            store_tile_dev(A, Np, ri, ri - kNB, lr, lk, x);
+            double li[2][8];
+#pragma unroll
+            for (int R = 0; R < 2; ++R)
+#pragma unroll
+                for (int kk = 0; kk < 8; ++kk) li[R][kk] = x[R][kk >> 2][kk & 3];
+            mfma_downdate(accD, li, li);
+            // c_i,i-1 = L_i,i-1 y_i-1 from the registers (rows 16 R + lr)
+            double s[2];
+#pragma unroll
+            for (int R = 0; R < 2; ++R) {
+                s[R] = 0.0;
+#pragma unroll
+                for (int C = 0; C < 2; ++C)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) s[R] = fma(x[R][C][v], ys[16 * C + 4 * v + lk], s[R]);
+                s[R] += __shfl_xor(s[R], 16, 64);
+                s[R] += __shfl_xor(s[R], 32, 64);
+            }
+            // lane r takes row r: rows r < 16 from lane r (R = 0), rows 16.. from lane r - 16 (R = 1)
+            const double s0 = __shfl(s[0], r & 15, 64), s1 = __shfl(s[1], r & 15, 64);
+            clast = r < 16 ? s0 : s1;
+        }
+        __syncwarp();   // the previous step's W and y have been read
+#pragma unroll
+        for (int R = 0; R < 2; ++R)
+#pragma unroll
+            for (int C = 0; C < 2; ++C)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) Ls[16 * R + lr][16 * C + 4 * v + lk] = accD[R][C][v];
+        __syncwarp();
+        const bool bad = band_factor_invert(A, Np, ri, lane, Ls, Wi, zs, i >= 1 ? fl + tile_ix(i, i - 1) : nullptr);
+        raise_flag(fl + tile_ix(i, i), bad ? 2 : 1);
+        // forward substitution of block i
+        double z = bi - clast;
+        for (int j = 0; j + 2 <= i; ++j) z -= take_vec(cv + 32 * (int64_t)tile_ix(i, j), abort_w, ok, lane);
+        share32(zs, z, lane);
+        const double y = lds_matvec(Wi, zs, lane);
+        __syncwarp();
+        if (lane < kNB) ys[lane] = y;
+        publish(yv + ri, y, lane);
+        raise_flag(fl_y + i, 1);
+        __syncwarp();
+    }
+    // backward substitution; W_T-1 is still in Wi (row-major W)
+    double x;
+    {
+        share32(zs, ys[r], lane);
+        // x_r = sum_q W[q][r] z_q
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int m = 0; m < 16; ++m) a[m & 3] = fma(Wi[hc + m][r], zs[hc + m], a[m & 3]);
+        x = halves((a[0] + a[1]) + (a[2] + a[3]));
+    }
+    for (int i = T - 1; i >= 0; --i) {
+        const int64_t ri = (int64_t)i * kNB;
+        if (i < T - 1) {
+            // z = y_i - sum_{j >= i+2} d_ji - L_i+1,i^T x_i+1, x_i = W_ii^T z
+            double t[16], w[16];
+            ld_col16<true>(A, Np, ri + kNB + hc, ri + r, t);   // column r of L_i+1,i, rows hc..hc+15
+            ld_w16<false>(A, Np, ri, r, hc, w);
+            const double yi = ld_dev(yv + ri + r);
+            share32(zs, x, lane);   // x_i+1
+            double z = yi - halves(dot16(t, zs + hc));
+            for (int j = i + 2; j < T; ++j) z -= take_vec(dv + 32 * (int64_t)tile_ix(j, i), abort_w, ok, lane);
+            share32(zs, z, lane);
+            x = halves(dot16(w, zs + hc));
+        }
+        publish(xv + ri, x, lane);
+        raise_flag(fl_x + i, 1);
+        const int64_t row = ri + r;
+        if (lane < kNB && row < N) dcam[9 * (int64_t)cl_cams[c0 + row / 9] + row % 9] = x;
+    }
+    return ok;
+}
+
+// Worker r (1 <= r <= W) of cluster k.  tasks / st: LDS lists of this
+// wavefront's tasks and their states (phase << 16 | next update).
+__device__ __forceinline__ bool team_worker(int k, int r, int W, const int64_t *S_off, const int32_t *cl_Np, double *S,
+                                            const TeamBufs &tb, int32_t *tasks, int32_t *st, int32_t *rdy,
+                                            double *zs) {
+    const int lane = threadIdx.x;
+    const int64_t Np = cl_Np[k];
+    const int T = (int)(Np / kNB);
+    const int nt = team_ntasks(T);
+    const int own = r - 1 < nt ? (nt - (r - 1) + W - 1) / W : 0;
+    if (own == 0) return true;
+    const int tt = T * (T + 1) / 2;
+    int32_t *fl = tb.flags + team_fbase(S_off, k);
+    int32_t *fl_part = fl + tt, *fl_y = fl_part + T, *fl_x = fl_y + T;
+    int32_t *abort_w = tb.flags + tb.abort_at;
+    const int64_t vb = team_vbase(S_off, k);
+    double *cv = tb.cv + vb, *dv = tb.dv + vb, *yv = tb.yv + vb, *xv = tb.xv + vb;
+    double *A = S + S_off[k];
+    const int lr = lane & 15, lk = lane >> 4;
+    const int rr = lane & (kNB - 1), hc = 16 * (lane >> 5);
+    for (int s = lane; s < own; s += 64) {
+        const int32_t tk = team_task((r - 1) + W * s, T);
+        tasks[s] = tk;
+        // a panel of the first block column has no updates: it starts at its solve
+        st[s] = ((tk >> 30) == 0 && (tk & 0x7FFF) == 0) ? (1 << 16) : 0;
+    }
+    __syncwarp();
+    int left = own, idle = 0;
+    while (left > 0) {
+        // readiness of every pending task, one lane per task: rdy = number of
+        // consecutive updates ready (phase 0) or 1 (other phases), 0 if none
+        for (int s = lane; s < own; s += 64) {
+            const int32_t tk = tasks[s], sv = st[s];
+            const int ph = sv >> 16, pn = sv & 0xFFFF;
+            const int i = (tk >> 15) & 0x7FFF, j = tk & 0x7FFF;
+            const bool isR = (tk >> 30) != 0;
+            int n = 0;
+            if (ph == 0) {
+                const int lim = isR ? i - 1 : j;   // updates p < lim
+                const int i2 = isR ? i - 1 : j;
+#pragma unroll
+                for (int q = 0; q < kTeamLook; ++q) {
+                    const int p = pn + q;
+                    if (p >= lim || n < q) break;
+                    if (flag_set(fl + tile_ix(i, p)) && flag_set(fl + tile_ix(i2, p))) n = q + 1;
+                }
+            } else if (ph == 1) {
+                n = flag_set(fl + tile_ix(j, j)) ? 1 : 0;
+            } else if (ph == 2) {
+                n = flag_set(fl_y + j) ? 1 : 0;
+            } else if (ph == 3) {
+                n = flag_set(fl_x + i) ? 1 : 0;
+            }
+            rdy[s] = n;
+        }
+        __syncwarp();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        bool progress = false;
+        for (int s = 0; s < own; ++s) {
+            const int cnt = rdy[s];
+            if (cnt == 0) continue;   // inputs not ready, or done
+            const int32_t tk = tasks[s], sv = st[s];
+            const int i = (tk >> 15) & 0x7FFF, j = tk & 0x7FFF;
+            const bool isR = (tk >> 30) != 0;
+            int ph = sv >> 16, pn = sv & 0xFFFF;
+            const int64_t ri = (int64_t)i * kNB, cj = (int64_t)j * kNB;
+            progress = true;
+            if (isR) {
+                // R(i): tiles (i, i) and (i, i - 1), updates p = pn .. pn + cnt - 1 (<= i - 2)
+                d4 accD[2][2], accP[2][2];
+                load_tile_dev(A, Np, ri, ri, lr, lk, accD);
+                load_tile_dev(A, Np, ri, ri - kNB, lr, lk, accP);
+                for (int q = 0; q < cnt; ++q) {
+                    const int64_t off = (int64_t)(pn + q) * kNB;
+                    double li[2][8], lj[2][8];
+                    load_panel(A, Np, ri, off, lr, lk, li);
+                    load_panel(A, Np, ri - kNB, off, lr, lk, lj);
+                    mfma_downdate(accP, li, lj);
+                    mfma_downdate(accD, li, li);
+                }
+                store_tile_dev(A, Np, ri, ri, lr, lk, accD);
+                store_tile_dev(A, Np, ri, ri - kNB, lr, lk, accP);
+                pn += cnt;
+                if (pn >= i - 1) {
+                    raise_flag(fl_part + i, 1);
+                    ph = 4;
+                    --left;
+                }
+            } else if (ph == 0) {
+                d4 acc[2][2];
+                load_tile_dev(A, Np, ri, cj, lr, lk, acc);
+                for (int q = 0; q < cnt; ++q) {
+                    const int64_t off = (int64_t)(pn + q) * kNB;
+                    double li[2][8], lj[2][8];
+                    load_panel(A, Np, ri, off, lr, lk, li);
+                    load_panel(A, Np, cj, off, lr, lk, lj);
+                    mfma_downdate(acc, li, lj);
+                }
+                pn += cnt;
+                bool solved = false;
+                if (pn == j) {
+                    ph = 1;
+                    // the diagonal tile may already be final: solve in this visit
+                    int fin = 0;
+                    if (lane == 0) fin = flag_set(fl + tile_ix(j, j)) ? 1 : 0;
+                    if (__shfl(fin, 0, 64)) {
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                        d4 x[2][2];
+                        panel_solve(acc, A + cj + cj * Np, Np, lr, lk, x);
+                        store_tile_dev(A, Np, ri, cj, lr, lk, x);
+                        raise_flag(fl + tile_ix(i, j), 1);
+                        ph = 2;
+                        solved = true;
+                    }
+                }
+                if (!solved) store_tile_dev(A, Np, ri, cj, lr, lk, acc);
+            } else if (ph == 1) {
+                d4 acc[2][2], x[2][2];
+                load_tile_dev(A, Np, ri, cj, lr, lk, acc);
+                panel_solve(acc, A + cj + cj * Np, Np, lr, lk, x);
+                store_tile_dev(A, Np, ri, cj, lr, lk, x);
+                raise_flag(fl + tile_ix(i, j), 1);
+                ph = 2;
+            } else if (ph == 2) {
+                // c_ij = L_ij y_j
+                double t[16];
+                ld_row16<true>(A, Np, ri + rr, cj + hc, t);
+                share32(zs, ld_dev(yv + cj + rr), lane);
+                const double c = halves(dot16(t, zs + hc));
+                publish(cv + 32 * (int64_t)tile_ix(i, j), c, lane);
+                ph = 3;
+            } else if (ph == 3) {
+                // d_ij = L_ij^T x_i: column rr of the tile, rows hc .. hc + 15
+                double t[16];
+                ld_col16<true>(A, Np, ri + hc, cj + rr, t);
+                share32(zs, ld_dev(xv + ri + rr), lane);
+                const double d = halves(dot16(t, zs + hc));
+                publish(dv + 32 * (int64_t)tile_ix(i, j), d, lane);
+                ph = 4;
+                --left;
+            }
+            __syncwarp();
+            if (lane == 0) st[s] = (ph << 16) | pn;
+            __syncwarp();
+        }
+        if (!progress) {
+            if (++idle >= kWaitPolls) {
+                if (lane == 0) __hip_atomic_store(abort_w, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return false;
+            }
+            int a = 0;
+            if (lane == 0) a = __hip_atomic_load(abort_w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (__shfl(a, 0, 64)) return false;
+            __builtin_amdgcn_s_sleep(1);
+        } else {
+            idle = 0;
+        }
+    }
+    return true;
+}
+
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_chol_team(
+    int32_t G, int32_t l, const int32_t *__restrict__ cl_n, const int32_t *__restrict__ cl_Np,
+    const int64_t *__restrict__ S_off, const int32_t *__restrict__ cl_start, const int32_t *__restrict__ cl_cams,
+    double *__restrict__ S, const double *__restrict__ b, double *__restrict__ dcam, int32_t *__restrict__ cl_status,
+    TeamBufs tb) {
+    // dynamic LDS, team_lds_bytes(): the band's W, staged tile, column and y,
+    // or a worker's column buffer and task lists
+    extern __shared__ __align__(16) double team_lds[];
+    double *zs = team_lds;                      // 2 kNB
+    double *ys = zs + 2 * kNB;                  // kNB
+    double(*Wi)[kNB + 1] = reinterpret_cast<double(*)[kNB + 1]>(ys + kNB);
+    double(*Ls)[kNB + 1] = Wi + kNB;
+    int32_t *lists = reinterpret_cast<int32_t *>(ys + kNB);
+    const int lane = threadIdx.x;
+    int k = 0, r = 0, W = 0;
+    if (!team_role((int)blockIdx.x, G, l, cl_Np, k, r, W)) return;   // spare wavefront
+    bool ok;
+    if (r == 0)
+        ok = team_band(k, S_off, cl_n, cl_Np, cl_start, cl_cams, S, b, dcam, tb, Wi, Ls, zs, ys);
+    else {
+        const int T = cl_Np[k] / kNB;
+        const int cap = (team_ntasks(T) + W - 1) / (W > 0 ? W : 1);
+        ok = team_worker(k, r, W, S_off, cl_Np, S, tb, lists, lists + cap, lists + 2 * cap, zs);
+    }
+    // every wavefront of the team ends here; the last one writes the status
+    // and returns the cluster's flags and vectors to their initial state
+    const int T = cl_Np[k] / kNB;
+    const int tt = T * (T + 1) / 2;
+    int32_t *fl = tb.flags + team_fbase(S_off, k);
+    int32_t *fl_err = fl + tt + 3 * T;
+    int32_t *fl_cnt = fl_err + 1;
+    int32_t *abort_w = tb.flags + tb.abort_at;
+    if (!ok && lane == 0) __hip_atomic_store(fl_err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);
+    int last = 0;
+    if (lane == 0) last = __hip_atomic_fetch_add(fl_cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == W;
+    if (__shfl(last, 0, 64) == 0) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    bool failed = false;
+    if (lane == 0) {
+        bool anybad = false;
+        for (int p = 0; p < T; ++p)
+            anybad |= __hip_atomic_load(fl + tile_ix(p, p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 2;
+        failed = __hip_atomic_load(fl_err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                 __hip_atomic_load(abort_w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+        cl_status[k] = failed ? STBA_EHIP : (anybad ? STBA_ENOTPD : STBA_OK);
+    }
+    failed = __shfl((int)failed, 0, 64) != 0;
+    for (int q = lane; q < tt + 3 * T + 1; q += 64) fl[q] = 0;
+    const int64_t vb = team_vbase(S_off, k);
+    for (int q = lane; q < T * kNB; q += 64) {
+        tb.yv[vb + q] = __longlong_as_double(kEmpty);
+        tb.xv[vb + q] = __longlong_as_double(kEmpty);
+    }
+    if (failed)   // after an abort the tile vectors may still hold values
+        for (int64_t q = lane; q < (int64_t)tt * kNB; q += 64) {
+            tb.cv[vb + q] = __longlong_as_double(kEmpty);
+            tb.dv[vb + q] = __longlong_as_double(kEmpty);
+        }
+    __builtin_amdgcn_s_waitcnt(0);
+    if (lane == 0) {
+        __hip_atomic_store(fl_cnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (__hip_atomic_fetch_add(abort_w + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == l - 1) {
+            __hip_atomic_store(abort_w, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(abort_w + 1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// Dynamic LDS of k_chol_team for clusters of at most max_Np: the band's part,
+// or a worker's lists for the most tasks one wavefront can own (one worker).
+size_t team_lds_bytes(int32_t max_Np) {
+    const int T = max_Np / kNB;
+    const size_t band = sizeof(double) * (3 * kNB + 2 * kNB * (kNB + 1));
+    const size_t worker = sizeof(double) * 3 * kNB + 12 * (size_t)team_ntasks(T);
+    return band > worker ? band : worker;
+}
+
 // The initial state of the tile-parallel factorisation's flag words (zero)
 // and block vectors (kEmpty).
 __global__ void k_init_chol_sync(int32_t *flags, int64_t nf, double *yx, int64_t nv) {
@@ -1280,6 +1764,18 @@ int64_t chol_tile_resident() {
     return (int64_t)cus * per_cu;
 }
 
+// Wavefronts of k_chol_team the current device holds at once with the LDS a
+// cluster of order max_Np needs; 0 if the query fails.
+int64_t chol_team_resident(int32_t max_Np) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(k_chol_team), 64,
+                                                     team_lds_bytes(max_Np)) != hipSuccess)
+        return 0;
+    return (int64_t)cus * per_cu;
+}
+
 int chol_tile_layout(int32_t l, int32_t max_Np, int32_t *wpc, int32_t *tmax, int32_t *fpc, int32_t *xcd_major) {
     const int32_t tm = max_Np / kNB;
     if (tm < 1) return 0;
@@ -1302,8 +1798,9 @@ int chol_tile_layout(int32_t l, int32_t max_Np, int32_t *wpc, int32_t *tmax, int
 hipError_t launch_chol(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, const int64_t *S_off,
                        const int32_t *cl_start, const int32_t *cl_cams, double *S, const double *b, double *dcam,
                        int32_t *cl_status, int32_t max_Np, int32_t *flags, double *yx, const double *S0,
-                       double *rbuf, hipStream_t st) {
+                       double *rbuf, const CholTeam *team, hipStream_t st) {
     int32_t wpc = 0, tmax = 0, fpc = 0, xcd = 0;
+    if (team != nullptr && team->force) goto team_path;
     if (flags && yx && chol_tile_layout(l, max_Np, &wpc, &tmax, &fpc, &xcd)) {
         // the flag words are zero and the vector entries kEmpty here: set when the
         // workspace was prepared and again at the end of every factorisation
@@ -1311,6 +1808,29 @@ hipError_t launch_chol(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, con
         k_chol_tiles<<<(unsigned)blocks, 64, 0, st>>>(wpc, tmax, fpc, cl_n, cl_Np, S_off, cl_start, cl_cams, S, b,
                                                      dcam, cl_status, flags, l, yx, S0, xcd);
         return hipGetLastError();
+    }
+team_path:
+    if (team != nullptr && team->flags != nullptr && max_Np <= kTeamMaxNp) {
+        // every wavefront of a team waits on the others: all must be resident,
+        // with a sixteenth of the capacity in reserve; a band and a worker per cluster
+        const int64_t G = 15 * chol_team_resident(max_Np) / 16;
+        if (G >= 2 * (int64_t)l) {
+            TeamBufs tb;
+            tb.flags = team->flags;
+            tb.abort_at = team->abort_at;
+            tb.cv = team->vec;
+            tb.dv = team->vec + team->vec_len;
+            tb.yv = team->vec + 2 * team->vec_len;
+            tb.xv = team->vec + 3 * team->vec_len;
+            k_chol_team<<<(unsigned)G, 64, team_lds_bytes(max_Np), st>>>((int32_t)G, l, cl_n, cl_Np, S_off, cl_start,
+                                                                         cl_cams, S, b, dcam, cl_status, tb);
+            if (S0) {
+                const hipError_t e = hipGetLastError();
+                if (e != hipSuccess) return e;
+                return launch_refine(l, cl_n, cl_Np, S_off, cl_start, cl_cams, S, S0, b, dcam, rbuf, max_Np, st);
+            }
+            return hipGetLastError();
+        }
     }
     const size_t shmem = sizeof(double) * (2 * (size_t)kNB * (kNB + 1) + 2 * kNB + (size_t)max_Np + kCholThreads + kNB);
     k_chol<<<(unsigned)l, kCholThreads, shmem, st>>>(l, cl_n, cl_Np, S_off, cl_start, cl_cams, S, b, dcam, cl_status,
@@ -1323,9 +1843,15 @@ hipError_t launch_chol(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, con
     return hipGetLastError();
 }
 
-hipError_t launch_clear_chol_flags(int32_t *flags, double *yx, hipStream_t st) {
+hipError_t launch_clear_chol_flags(int32_t *flags, double *yx, const CholTeam *team, hipStream_t st) {
     const int64_t nf = chol_flag_words(), nv = chol_yx_doubles();
     k_init_chol_sync<<<(unsigned)(((nf > nv ? nf : nv) + 255) / 256), 256, 0, st>>>(flags, nf, yx, nv);
+    if (team != nullptr && team->flags != nullptr) {
+        const int64_t tf = team->abort_at + 2, tv = 4 * team->vec_len;
+        int64_t blocks = ((tf > tv ? tf : tv) + 255) / 256;
+        if (blocks > 65536) blocks = 65536;
+        k_init_chol_sync<<<(unsigned)blocks, 256, 0, st>>>(team->flags, tf, team->vec, tv);
+    }
     return hipGetLastError();
 }
 

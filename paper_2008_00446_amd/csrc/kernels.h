@@ -106,15 +106,30 @@ inline int64_t chol_flag_words() { return 4 * (int64_t)kCholTileWaves + 2; }
 // d, e), T <= its wavefronts
 inline int64_t chol_yx_doubles() { return 4 * (int64_t)kCholTileWaves * kNB; }
 int chol_tile_layout(int32_t l, int32_t max_Np, int32_t *wpc, int32_t *tmax, int32_t *fpc, int32_t *xcd_major);
+// Buffers of the team factorisation (many clusters, tiles in memory): flag
+// words (per cluster 2 T^2 + 8 from 2 S_off / 1024 + 8 k, then the abort word
+// at abort_at and the finished-cluster count) and four block-vector buffers of
+// vec_len doubles each (c, d per tile, y, x per block row, from S_off / 32).
+// force: take the team form even when the tile-parallel one would fit.
+struct CholTeam {
+    int32_t *flags = nullptr;
+    int64_t abort_at = 0;
+    double *vec = nullptr;
+    int64_t vec_len = 0;
+    bool force = false;
+};
+constexpr int32_t kTeamMaxNp = 2048;
+inline int64_t chol_team_flag_words(int64_t S_cap, int32_t m) { return 2 * (S_cap / 1024) + 8 * (int64_t)m + 2; }
+inline int64_t chol_team_vec_len(int64_t S_cap) { return S_cap / 32; }
 // the flag words and block vectors have to be in their initial state before the
-// first factorisation; every tile-parallel factorisation leaves them so again
-hipError_t launch_clear_chol_flags(int32_t *flags, double *yx, hipStream_t st);
+// first factorisation; every tile-parallel or team factorisation leaves them so again
+hipError_t launch_clear_chol_flags(int32_t *flags, double *yx, const CholTeam *team, hipStream_t st);
 // S0 (nullable): the assembled S kept for one FP64 refinement step (MIXED),
 // with rbuf (l * max_Np doubles) for its residual.
 hipError_t launch_chol(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, const int64_t *S_off,
                        const int32_t *cl_start, const int32_t *cl_cams, double *S, const double *b,
                        double *dcam, int32_t *cl_status, int32_t max_Np, int32_t *flags, double *yx,
-                       const double *S0, double *rbuf, hipStream_t st);
+                       const double *S0, double *rbuf, const CholTeam *team, hipStream_t st);
 
 // MIXED precision: one FP64 refinement step of dcam against S0 (the assembled
 // S, written alongside it by the assembly) with the factors.

@@ -3,6 +3,7 @@
 #include <math.h>
 #include <cmath>
 #include <mutex>
+#include <stdlib.h>
 #include <string.h>
 
 #include "kernels.h"
@@ -21,6 +22,8 @@ struct Layout {
     size_t cl_n, cl_Np, cl_start, cl_cams, cam_local, cl_status, S_off;
     size_t pcg_clus, pcg_minv, pcg_iters, pcg_resid;
     size_t f, Jc, Jp, seg_head, seg_rec, grp_first, obsd, Vinv, wph, S, S0, rres, b, dcam, dpt, partials, chol_flags, chol_yx;
+    size_t team_flags, team_vec;
+    int64_t team_abort_at, team_vec_len;
     bool mixed = false;   // S0 and rres exist
     int64_t S_cap, n_partials;
     int32_t group_size;
@@ -129,6 +132,11 @@ bool make_layout(const stba_problem *p, const stba_dims *d, int precision, Layou
     L.max_Np = (int32_t)round_up(9 * (int64_t)d->gamma_max, kNB);
     L.S_cap = s_capacity(p->m, d->gamma_max);
     L.S = take(8 * (size_t)L.S_cap);
+    // flags and block vectors of the team factorisation (many clusters)
+    L.team_abort_at = chol_team_flag_words(L.S_cap, p->m) - 2;
+    L.team_flags = take(4 * (size_t)(L.team_abort_at + 2));
+    L.team_vec_len = chol_team_vec_len(L.S_cap);
+    L.team_vec = take(8 * 4 * (size_t)L.team_vec_len);
     // MIXED keeps the assembled S for the refinement step
     L.mixed = precision == STBA_MIXED;
     L.S0 = L.mixed ? take(8 * (size_t)L.S_cap) : 0;
@@ -210,17 +218,30 @@ int build_rcs_impl(const stba_problem *p, const stba_dims *d, const stba_sample 
     return STBA_OK;
 }
 
+CholTeam team_of(const Layout &L, void *ws) {
+    CholTeam t;
+    t.flags = at<int32_t>(ws, L.team_flags);
+    t.abort_at = L.team_abort_at;
+    t.vec = at<double>(ws, L.team_vec);
+    t.vec_len = L.team_vec_len;
+    // STBA_CHOL=team takes the team form whenever it fits (for tests and tuning)
+    const char *e = getenv("STBA_CHOL");
+    t.force = e != nullptr && strcmp(e, "team") == 0;
+    return t;
+}
+
 // The cluster solves of Eq. 13; in MIXED precision with one FP64 refinement
 // step against the assembled S.
 template <typename T>
 int cluster_solve(int32_t l, double *dcam, int32_t *cl_status, const Layout &L, void *ws, hipStream_t st) {
     // MIXED: S0, the copy of S kept for the refinement step, was written by the assembly
     const bool mixed = sizeof(T) == sizeof(float);
+    const CholTeam team = team_of(L, ws);
     STBA_HIP(launch_chol(l, at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np), at<int64_t>(ws, L.S_off),
                          at<int32_t>(ws, L.cl_start), at<int32_t>(ws, L.cl_cams), at<double>(ws, L.S),
                          at<double>(ws, L.b), dcam, cl_status, L.max_Np, at<int32_t>(ws, L.chol_flags),
                          at<double>(ws, L.chol_yx), mixed ? at<double>(ws, L.S0) : nullptr,
-                         mixed ? at<double>(ws, L.rres) : nullptr, st));
+                         mixed ? at<double>(ws, L.rres) : nullptr, &team, st));
     return STBA_OK;
 }
 
@@ -397,7 +418,8 @@ int stba_prepare(const stba_problem *p, const stba_dims *dims, int precision, vo
     b.tmp_bytes = L.tmp_bytes;
     STBA_HIP(launch_reset_status(at<int32_t>(ws, L.status), stream));
     STBA_HIP(launch_prepare(*p, dims->n_pairs, b, at<int32_t>(ws, L.status), stream));
-    STBA_HIP(launch_clear_chol_flags(at<int32_t>(ws, L.chol_flags), at<double>(ws, L.chol_yx), stream));
+    const CholTeam team = team_of(L, ws);
+    STBA_HIP(launch_clear_chol_flags(at<int32_t>(ws, L.chol_flags), at<double>(ws, L.chol_yx), &team, stream));
     if (L.group_size > 0)
         STBA_HIP(launch_point_groups(p->n, b.pt_off, L.group_size, (p->q + L.group_size - 1) / L.group_size,
                                      at<int32_t>(ws, L.grp_first), stream));
