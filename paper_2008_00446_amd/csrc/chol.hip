@@ -1306,7 +1306,7 @@ __host__ __device__ inline int team_ntasks(int T) { return T < 3 ? 0 : (T - 2) +
 
 // Task g of a cluster with T block rows, column-major groups: column j holds
 // R(j + 2) and then F(j + 2 .. T - 1, j).  Packed as kind << 30 | i << 15 | j
-// (kind 0: F, 1: R).
+// (kind 0: F, 1: R, whose j field is i - 1).
 __device__ inline int32_t team_task(int g, int T) {
     int j = 0;
     while (true) {
@@ -1315,8 +1315,15 @@ __device__ inline int32_t team_task(int g, int T) {
         g -= n;
         ++j;
     }
-    if (g == 0) return (1 << 30) | ((j + 2) << 15) | (j + 1);   // R(j + 2): its tiles are (i, i), (i, i - 1)
+    if (g == 0) return (1 << 30) | ((j + 2) << 15) | (j + 1);
     return ((j + 1 + g) << 15) | j;
+}
+
+// Tasks of worker w0 (0 .. W - 1) of a team with W workers: every W-th task
+// of the list, from task w0.
+__device__ inline int team_own(int T, int W, int w0) {
+    const int nt = team_ntasks(T);
+    return w0 < nt ? (nt - w0 + W - 1) / W : 0;
 }
 
 // This wavefront's cluster k, its index r in the team (0: band) and the
@@ -1337,7 +1344,7 @@ __device__ inline bool team_role(int wave, int G, int l, const int32_t *cl_Np, i
         sw += __shfl_xor(sw, d, 64);
         n3 += __shfl_xor(n3, d, 64);
     }
-    const int64_t wtot = (int64_t)G - l - n3;
+    const int64_t wtot = (int64_t)G - 2 * (int64_t)l - n3;
     if (wtot < 0) return false;
     int64_t base = 0;
     for (int c0 = 0; c0 < l; c0 += 64) {
@@ -1350,7 +1357,7 @@ __device__ inline bool team_role(int wave, int G, int l, const int32_t *cl_Np, i
                 if (W < 1) W = 1;
                 if (W > team_ntasks(T)) W = team_ntasks(T);
             }
-            size = 1 + W;
+            size = 2 + W;
         }
         int64_t inc = size;   // inclusive scan over the 64 clusters of this chunk
 #pragma unroll
@@ -1382,17 +1389,58 @@ __device__ inline double lds_matvec(const double (*M)[kNB + 1], const double *z,
     return halves((a[0] + a[1]) + (a[2] + a[3]));
 }
 
-// Wait for a published block vector, take it and return its slot to kEmpty.
-__device__ inline double take_vec(double *v, int32_t *abort_w, bool &ok, int lane) {
-    const double x = wait_vec(v, abort_w, ok);
-    if (lane < kNB) st_dev(v + lane, __longlong_as_double(kEmpty));
-    return x;
+// Sum of cnt published 32-vectors at base + 32 slot(q), q = 0 .. cnt - 1, entry
+// (lane mod 32) in every lane, each returned to kEmpty after use.  Sixteen
+// vectors per round trip (half h of the wavefront loads q = h, h + 2, ...);
+// an entry still kEmpty is polled again (bounded).  The order of the sum is
+// fixed: each half adds its vectors in increasing q, then the two halves.
+template <class Slot>
+__device__ inline double take_sum(double *base, int cnt, Slot slot, int32_t *abort_w, bool &ok) {
+    const int lane = threadIdx.x & 63, r = lane & (kNB - 1), h = lane >> 5;
+    double acc = 0.0;
+    for (int q0 = 0; q0 < cnt; q0 += 16) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int q = q0 + 2 * u + h;
+            v[u] = q < cnt ? ld_dev(base + 32 * (int64_t)slot(q) + r) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int q = q0 + 2 * u + h;
+            double *p = base + 32 * (int64_t)slot(q < cnt ? q : 0) + r;
+            for (int it = 0; it < kWaitPolls; ++it) {
+                const bool empty = q < cnt && __double_as_longlong(v[u]) == kEmpty;
+                if (__ballot(empty) == 0ull) break;
+                const int a = __hip_atomic_load(abort_w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (a != 0 || it + 1 == kWaitPolls) {
+                    if (lane == 0) __hip_atomic_store(abort_w, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = false;
+                    v[u] = 0.0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                if (empty) v[u] = ld_dev(p);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int q = q0 + 2 * u + h;
+            if (q < cnt) {
+                acc += v[u];
+                st_dev(base + 32 * (int64_t)slot(q) + r, __longlong_as_double(kEmpty));
+            }
+        }
+    }
+    return acc + __shfl_xor(acc, 32, 64);
 }
 
+// The band wavefront of cluster k: the diagonal chain, then the backward
+// substitution.
 __device__ __forceinline__ bool team_band(int k, const int64_t *S_off, const int32_t *cl_n, const int32_t *cl_Np,
-                                          const int32_t *cl_start, const int32_t *cl_cams, double *S, const double *b,
-                                          double *dcam, const TeamBufs &tb, double (*Wi)[kNB + 1],
-                                          double (*Ls)[kNB + 1], double *zs, double *ys) {
+                                          const int32_t *cl_start, const int32_t *cl_cams, double *S, double *dcam,
+                                          const TeamBufs &tb, double (*Wi)[kNB + 1], double (*Ls)[kNB + 1],
+                                          double *zs) {
     const int lane = threadIdx.x;
     const int64_t Np = cl_Np[k];
     const int T = (int)(Np / kNB);
@@ -1402,7 +1450,7 @@ __device__ __forceinline__ bool team_band(int k, const int64_t *S_off, const int
     int32_t *fl_part = fl + tt, *fl_y = fl_part + T, *fl_x = fl_y + T;
     int32_t *abort_w = tb.flags + tb.abort_at;
     const int64_t vb = team_vbase(S_off, k);
-    double *cv = tb.cv + vb, *dv = tb.dv + vb, *yv = tb.yv + vb, *xv = tb.xv + vb;
+    double *dv = tb.dv + vb, *yv = tb.yv + vb, *xv = tb.xv + vb;
     double *A = S + S_off[k];
     const int lr = lane & 15, lk = lane >> 4;
     const int r = lane & (kNB - 1), hc = 16 * (lane >> 5);
@@ -1412,12 +1460,9 @@ __device__ __forceinline__ bool team_band(int k, const int64_t *S_off, const int
     __builtin_amdgcn_s_setprio(3);
     for (int i = 0; i < T; ++i) {
         const int64_t ri = (int64_t)i * kNB;
-        const int64_t row = ri + r;
-        const double bi = row < N ? b[9 * (int64_t)cl_cams[c0 + row / 9] + row % 9] : 0.0;
         d4 accD[2][2], accP[2][2];
         if (i >= 2) ok &= wait_flag(fl_part + i, abort_w) != 0;
         load_tile_dev(A, Np, ri, ri, lr, lk, accD);
-        double clast = 0.0;
         if (i >= 1) {
             load_tile_dev(A, Np, ri, ri - kNB, lr, lk, accP);
             d4 x[2][2];
@@ -1429,23 +1474,8 @@ __device__ __forceinline__ bool team_band(int k, const int64_t *S_off, const int
 #pragma unroll
                 for (int kk = 0; kk < 8; ++kk) li[R][kk] = x[R][kk >> 2][kk & 3];
             mfma_downdate(accD, li, li);
-            // c_i,i-1 = L_i,i-1 y_i-1 from the registers (rows 16 R + lr)
-            double s[2];
-#pragma unroll
-            for (int R = 0; R < 2; ++R) {
-                s[R] = 0.0;
-#pragma unroll
-                for (int C = 0; C < 2; ++C)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) s[R] = fma(x[R][C][v], ys[16 * C + 4 * v + lk], s[R]);
-                s[R] += __shfl_xor(s[R], 16, 64);
-                s[R] += __shfl_xor(s[R], 32, 64);
-            }
-            // lane r takes row r: rows r < 16 from lane r (R = 0), rows 16.. from lane r - 16 (R = 1)
-            const double s0 = __shfl(s[0], r & 15, 64), s1 = __shfl(s[1], r & 15, 64);
-            clast = r < 16 ? s0 : s1;
         }
-        __syncwarp();   // the previous step's W and y have been read
+        __syncwarp();   // the previous step's W has been read
 #pragma unroll
         for (int R = 0; R < 2; ++R)
 #pragma unroll
@@ -1455,38 +1485,42 @@ __device__ __forceinline__ bool team_band(int k, const int64_t *S_off, const int
         __syncwarp();
         const bool bad = band_factor_invert(A, Np, ri, lane, Ls, Wi, zs, i >= 1 ? fl + tile_ix(i, i - 1) : nullptr);
         raise_flag(fl + tile_ix(i, i), bad ? 2 : 1);
-        // forward substitution of block i
-        double z = bi - clast;
-        for (int j = 0; j + 2 <= i; ++j) z -= take_vec(cv + 32 * (int64_t)tile_ix(i, j), abort_w, ok, lane);
-        share32(zs, z, lane);
-        const double y = lds_matvec(Wi, zs, lane);
-        __syncwarp();
-        if (lane < kNB) ys[lane] = y;
-        publish(yv + ri, y, lane);
-        raise_flag(fl_y + i, 1);
-        __syncwarp();
     }
-    // backward substitution; W_T-1 is still in Wi (row-major W)
+    // backward substitution once the forward one is complete; W_T-1 is still
+    // in Wi (row-major W): x_T-1 = W^T y_T-1
+    ok &= wait_flag(fl_y + (T - 1), abort_w) != 0;
     double x;
     {
-        share32(zs, ys[r], lane);
-        // x_r = sum_q W[q][r] z_q
+        share32(zs, ld_dev(yv + (int64_t)(T - 1) * kNB + r), lane);
         double a[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int m = 0; m < 16; ++m) a[m & 3] = fma(Wi[hc + m][r], zs[hc + m], a[m & 3]);
         x = halves((a[0] + a[1]) + (a[2] + a[3]));
     }
+    double x2 = 0.0;   // x_i+2
     for (int i = T - 1; i >= 0; --i) {
         const int64_t ri = (int64_t)i * kNB;
         if (i < T - 1) {
-            // z = y_i - sum_{j >= i+2} d_ji - L_i+1,i^T x_i+1, x_i = W_ii^T z
-            double t[16], w[16];
-            ld_col16<true>(A, Np, ri + kNB + hc, ri + r, t);   // column r of L_i+1,i, rows hc..hc+15
+            // x_i = W_ii^T (y_i - L_i+1,i^T x_i+1 - L_i+2,i^T x_i+2 - sum_{j >= i+3} d_ji):
+            // the two nearest terms here, the others from the workers (published
+            // at least three steps ago); every load is issued before the sums
+            double t1[16], t2[16], w[16];
+            ld_col16<true>(A, Np, ri + kNB + hc, ri + r, t1);   // column r of L_i+1,i, rows hc..hc+15
+            if (i + 2 < T) ld_col16<true>(A, Np, ri + 2 * kNB + hc, ri + r, t2);
             ld_w16<false>(A, Np, ri, r, hc, w);
             const double yi = ld_dev(yv + ri + r);
-            share32(zs, x, lane);   // x_i+1
-            double z = yi - halves(dot16(t, zs + hc));
-            for (int j = i + 2; j < T; ++j) z -= take_vec(dv + 32 * (int64_t)tile_ix(j, i), abort_w, ok, lane);
+            const double dsum =
+                take_sum(dv, i + 3 < T ? T - i - 3 : 0, [&](int q) { return tile_ix(i + 3 + q, i); }, abort_w, ok);
+            __syncwarp();
+            if (lane < kNB) {
+                zs[lane] = x;            // x_i+1
+                zs[kNB + lane] = x2;     // x_i+2
+            }
+            __syncwarp();
+            double z = yi - halves(dot16(t1, zs + hc));
+            if (i + 2 < T) z -= halves(dot16(t2, zs + kNB + hc));
+            z -= dsum;
+            x2 = x;
             share32(zs, z, lane);
             x = halves(dot16(w, zs + hc));
         }
@@ -1494,6 +1528,52 @@ __device__ __forceinline__ bool team_band(int k, const int64_t *S_off, const int
         raise_flag(fl_x + i, 1);
         const int64_t row = ri + r;
         if (lane < kNB && row < N) dcam[9 * (int64_t)cl_cams[c0 + row / 9] + row % 9] = x;
+    }
+    return ok;
+}
+
+// The forward substitution of cluster k, one wavefront behind the band:
+// y_i = W_ii (b_i - L_i,i-1 y_i-1 - sum_{j <= i-2} c_ij) once tile (i, i) is
+// final, published with its flag.
+__device__ __forceinline__ bool team_forward(int k, const int64_t *S_off, const int32_t *cl_n, const int32_t *cl_Np,
+                                             const int32_t *cl_start, const int32_t *cl_cams, const double *S,
+                                             const double *b, const TeamBufs &tb, double *zs, double *ys) {
+    const int lane = threadIdx.x;
+    const int64_t Np = cl_Np[k];
+    const int T = (int)(Np / kNB);
+    if (T == 0) return true;
+    const int tt = T * (T + 1) / 2;
+    int32_t *fl = tb.flags + team_fbase(S_off, k);
+    int32_t *fl_y = fl + tt + T;
+    int32_t *abort_w = tb.flags + tb.abort_at;
+    const int64_t vb = team_vbase(S_off, k);
+    double *cv = tb.cv + vb, *yv = tb.yv + vb;
+    const double *A = S + S_off[k];
+    const int r = lane & (kNB - 1), hc = 16 * (lane >> 5);
+    const int N = 9 * cl_n[k];
+    const int c0 = cl_start[k];
+    bool ok = true;
+    for (int i = 0; i < T; ++i) {
+        const int64_t ri = (int64_t)i * kNB;
+        const int64_t row = ri + r;
+        const double bi = row < N ? b[9 * (int64_t)cl_cams[c0 + row / 9] + row % 9] : 0.0;
+        const double csum = take_sum(cv, i >= 2 ? i - 1 : 0, [&](int q) { return tile_ix(i, q); }, abort_w, ok);
+        ok &= wait_flag(fl + tile_ix(i, i), abort_w) != 0;   // also orders tile (i, i - 1)
+        double w[16];
+        ld_w16<true>(A, Np, ri, r, hc, w);
+        double z = bi - csum;
+        if (i >= 1) {
+            double t[16];
+            ld_row16<true>(A, Np, row, ri - kNB + hc, t);
+            z -= halves(dot16(t, ys + hc));   // L_i,i-1 y_i-1
+        }
+        share32(zs, z, lane);
+        const double y = halves(dot16(w, zs + hc));
+        __syncwarp();
+        if (lane < kNB) ys[lane] = y;
+        __syncwarp();
+        publish(yv + ri, y, lane);
+        raise_flag(fl_y + i, 1);
     }
     return ok;
 }
@@ -1506,8 +1586,8 @@ __device__ __forceinline__ bool team_worker(int k, int r, int W, const int64_t *
     const int lane = threadIdx.x;
     const int64_t Np = cl_Np[k];
     const int T = (int)(Np / kNB);
-    const int nt = team_ntasks(T);
-    const int own = r - 1 < nt ? (nt - (r - 1) + W - 1) / W : 0;
+    const int w0 = r - 1;
+    const int own = team_own(T, W, w0);
     if (own == 0) return true;
     const int tt = T * (T + 1) / 2;
     int32_t *fl = tb.flags + team_fbase(S_off, k);
@@ -1519,7 +1599,7 @@ __device__ __forceinline__ bool team_worker(int k, int r, int W, const int64_t *
     const int lr = lane & 15, lk = lane >> 4;
     const int rr = lane & (kNB - 1), hc = 16 * (lane >> 5);
     for (int s = lane; s < own; s += 64) {
-        const int32_t tk = team_task((r - 1) + W * s, T);
+        const int32_t tk = team_task(w0 + W * s, T);
         tasks[s] = tk;
         // a panel of the first block column has no updates: it starts at its solve
         st[s] = ((tk >> 30) == 0 && (tk & 0x7FFF) == 0) ? (1 << 16) : 0;
@@ -1544,6 +1624,10 @@ __device__ __forceinline__ bool team_worker(int k, int r, int W, const int64_t *
                     if (p >= lim || n < q) break;
                     if (flag_set(fl + tile_ix(i, p)) && flag_set(fl + tile_ix(i2, p))) n = q + 1;
                 }
+                // a tile far from the diagonal is visited once several updates
+                // are ready (each visit loads and stores the tile), the
+                // partial tiles and the tiles next to the band at once
+                if (!isR && i - j >= 3 && n < min(kTeamLook, lim - pn)) n = 0;
             } else if (ph == 1) {
                 n = flag_set(fl + tile_ix(j, j)) ? 1 : 0;
             } else if (ph == 2) {
@@ -1628,7 +1712,13 @@ __device__ __forceinline__ bool team_worker(int k, int r, int W, const int64_t *
                 share32(zs, ld_dev(yv + cj + rr), lane);
                 const double c = halves(dot16(t, zs + hc));
                 publish(cv + 32 * (int64_t)tile_ix(i, j), c, lane);
-                ph = 3;
+                // the band takes L_ij^T x_i itself for the two nearest blocks
+                if (i - j >= 3) {
+                    ph = 3;
+                } else {
+                    ph = 4;
+                    --left;
+                }
             } else if (ph == 3) {
                 // d_ij = L_ij^T x_i: column rr of the tile, rows hc .. hc + 15
                 double t[16];
@@ -1677,11 +1767,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void
     if (!team_role((int)blockIdx.x, G, l, cl_Np, k, r, W)) return;   // spare wavefront
     bool ok;
     if (r == 0)
-        ok = team_band(k, S_off, cl_n, cl_Np, cl_start, cl_cams, S, b, dcam, tb, Wi, Ls, zs, ys);
+        ok = team_band(k, S_off, cl_n, cl_Np, cl_start, cl_cams, S, dcam, tb, Wi, Ls, zs);
+    else if (r == 1)
+        ok = team_forward(k, S_off, cl_n, cl_Np, cl_start, cl_cams, S, b, tb, zs, ys);
     else {
+        // list capacity: the most tasks any worker of this team owns (at most
+        // all of them, which the launch's LDS holds for the largest cluster)
         const int T = cl_Np[k] / kNB;
-        const int cap = (team_ntasks(T) + W - 1) / (W > 0 ? W : 1);
-        ok = team_worker(k, r, W, S_off, cl_Np, S, tb, lists, lists + cap, lists + 2 * cap, zs);
+        const int cap = team_own(T, W, 0);
+        ok = team_worker(k, r - 1, W, S_off, cl_Np, S, tb, lists, lists + cap, lists + 2 * cap, zs);
     }
     // every wavefront of the team ends here; the last one writes the status
     // and returns the cluster's flags and vectors to their initial state
@@ -1695,7 +1789,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_s_waitcnt(0);
     int last = 0;
-    if (lane == 0) last = __hip_atomic_fetch_add(fl_cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == W;
+    if (lane == 0) last = __hip_atomic_fetch_add(fl_cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == W + 1;
     if (__shfl(last, 0, 64) == 0) return;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     bool failed = false;
@@ -1812,9 +1906,10 @@ hipError_t launch_chol(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, con
 team_path:
     if (team != nullptr && team->flags != nullptr && max_Np <= kTeamMaxNp) {
         // every wavefront of a team waits on the others: all must be resident,
-        // with a sixteenth of the capacity in reserve; a band and a worker per cluster
+        // with a sixteenth of the capacity in reserve; a band, a forward wavefront
+        // and a worker per cluster
         const int64_t G = 15 * chol_team_resident(max_Np) / 16;
-        if (G >= 2 * (int64_t)l) {
+        if (G >= 3 * (int64_t)l) {
             TeamBufs tb;
             tb.flags = team->flags;
             tb.abort_at = team->abort_at;

@@ -109,42 +109,55 @@ __global__ __launch_bounds__(1024) void k_clusters_small(const int32_t *cam_clus
 }
 
 // The same layout for any m (up to kMaxCamsForClusters): ceil(m / 256)
-// workgroups, each holding every camera's cluster id in LDS.  Every workgroup
-// counts the cameras per cluster and scans the counts (the same result in
-// each), then gives each of its 256 cameras its rank among the lower-numbered
-// cameras of its cluster, from vectorised LDS reads of the ids.  Workgroup 0
-// alone clears the status words and writes the per-cluster arrays and S_off,
-// so a bad map is reported after the clearing.
+// workgroups.  Every workgroup counts the cameras of each cluster over all
+// cameras and over those before its own chunk of 256 (the lanes of a
+// wavefront that share a cluster add their number at once), scans the counts
+// (the same result in each workgroup), then one wavefront ranks the chunk's
+// cameras in four rounds of 64 by the same ballots, so each camera's position
+// is its cluster's start plus the number of lower-numbered cameras of that
+// cluster.  Workgroup 0 alone clears the status words and writes the
+// per-cluster arrays and S_off, so a bad map is reported after the clearing.
 constexpr int kClusterLargeThreads = 256;
 __global__ __launch_bounds__(kClusterLargeThreads) void k_clusters_large(
     const int32_t *cam_cluster, int32_t m, int32_t l, int32_t gamma_max, int32_t *cl_n, int32_t *cl_Np,
     int32_t *cl_start, int32_t *cl_cams, int32_t *cam_local, int64_t *S_off, int32_t *status) {
     extern __shared__ __align__(16) int32_t dyn[];
-    const int32_t m4 = (int32_t)round_up(m, 4);
-    int32_t *ids = dyn;          // [m4], -1 for a bad id, -2 in the padding
-    int32_t *cnt = dyn + m4;     // [l] cameras per cluster, then the first slot of each cluster
+    int32_t *cnt = dyn;          // [l] cameras per cluster, then the first slot of each cluster
+    int32_t *base = dyn + l;     // [l] cameras of each cluster before this workgroup's chunk
     __shared__ int32_t ws32[16];
     __shared__ int64_t ws64[16];
     __shared__ int bad;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63;
     const bool lead = blockIdx.x == 0;
+    const int32_t chunk0 = (int32_t)blockIdx.x * kClusterLargeThreads;
     if (lead && t < kStCount) status[t] = 0;
     if (t == 0) bad = 0;
-    for (int i = t; i < l; i += kClusterLargeThreads) cnt[i] = 0;
-    for (int i = t; i < m4; i += kClusterLargeThreads) {
-        int32_t k = -2;
-        if (i < m) {
-            k = cam_cluster[i];
-            if (k < 0 || k >= l) {
-                bad = 1;
-                k = -1;
-            }
-        }
-        ids[i] = k;
+    for (int i = t; i < l; i += kClusterLargeThreads) {
+        cnt[i] = 0;
+        base[i] = 0;
     }
     __syncthreads();
-    for (int i = t; i < m; i += kClusterLargeThreads)
-        if (ids[i] >= 0) atomicAdd(&cnt[ids[i]], 1);
+    bool bad_id = false;
+    for (int i0 = t - lane; i0 < m; i0 += kClusterLargeThreads) {   // wavefront-uniform
+        const int i = i0 + lane;
+        int32_t k = i < m ? cam_cluster[i] : -1;
+        if (i < m && (k < 0 || k >= l)) {
+            bad_id = true;
+            k = -1;
+        }
+        unsigned long long todo = __ballot(k >= 0);
+        while (todo) {
+            const int ld = __ffsll(todo) - 1;
+            const int32_t key = __shfl(k, ld, 64);
+            const unsigned long long same = __ballot(k == key);
+            if (lane == ld) {
+                atomicAdd(&cnt[key], __popcll(same));
+                if (i0 < chunk0) atomicAdd(&base[key], __popcll(same));
+            }
+            todo &= ~same;
+        }
+    }
+    if (bad_id) bad = 1;
     __syncthreads();
     // each thread scans a contiguous chunk of clusters
     const int chunk = (l + kClusterLargeThreads - 1) / kClusterLargeThreads;
@@ -185,21 +198,28 @@ __global__ __launch_bounds__(kClusterLargeThreads) void k_clusters_large(
         }
         if (t == 0) S_off[l] = tot64;
     }
-    // rank of camera i among the lower-numbered cameras of its cluster
-    const int32_t i = (int32_t)blockIdx.x * kClusterLargeThreads + t;
-    const int32_t k = i < m ? ids[i] : -1;
-    int32_t rank = 0;
-    const int4 *ids4 = reinterpret_cast<const int4 *>(ids);
-    const int32_t lim = i < m ? (i + 3) / 4 : 0;   // j4 < m4 / 4: inside ids
-#pragma unroll 4
-    for (int j4 = 0; j4 < lim; ++j4) {
-        const int4 v = ids4[j4];
-        const int j = 4 * j4;
-        rank += (j < i && v.x == k) + (j + 1 < i && v.y == k) + (j + 2 < i && v.z == k) + (j + 3 < i && v.w == k);
-    }
-    if (k >= 0) {
-        cl_cams[cnt[k] + rank] = i;
-        cam_local[i] = rank;
+    // ranks of this chunk's cameras, 64 at a time in camera order
+    if (t < 64) {
+        for (int sub = 0; sub < kClusterLargeThreads / 64; ++sub) {
+            const int i = chunk0 + 64 * sub + lane;
+            int32_t k = i < m ? cam_cluster[i] : -1;
+            if (k >= l) k = -1;
+            unsigned long long todo = __ballot(k >= 0);
+            while (todo) {
+                const int ld = __ffsll(todo) - 1;
+                const int32_t key = __shfl(k, ld, 64);
+                const unsigned long long same = __ballot(k == key);
+                if (k == key) {
+                    const int32_t rank = base[key] + __popcll(same & ((1ull << lane) - 1ull));
+                    cl_cams[cnt[key] + rank] = i;
+                    cam_local[i] = rank;
+                }
+                __syncwarp();
+                if (lane == ld) base[key] += __popcll(same);
+                __syncwarp();
+                todo &= ~same;
+            }
+        }
     }
 }
 
@@ -1343,7 +1363,7 @@ hipError_t launch_clusters(const int32_t *cam_cluster, int32_t m, int32_t l, int
                                                                   cl_cams, cam_local, S_off, status);
         return hipGetLastError();
     }
-    const size_t lds = sizeof(int32_t) * ((size_t)round_up(m, 4) + (size_t)l);
+    const size_t lds = sizeof(int32_t) * 2 * (size_t)l;
     k_clusters_large<<<(unsigned)((m + kClusterLargeThreads - 1) / kClusterLargeThreads), kClusterLargeThreads, lds,
                        st>>>(cam_cluster, m, l, gamma_max, cl_n, cl_Np, cl_start, cl_cams, cam_local, S_off, status);
     return hipGetLastError();
