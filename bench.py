@@ -147,7 +147,7 @@ def draw_maps(S, wl, total):
         return [np.asarray(wl.map_of(t), dtype=np.int32) for t in range(total)]
     s = wl.scene
     sol = S.StbaSolver(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv, gamma_max=wl.gamma, precision=S.STBA_FP64)
-    out = [sol.sample_clusters(wl.gamma, SGC_BETA, alpha=1.0, seed=0, it=t)._keep.cpu().numpy().copy()
+    out = [sol.sample_clusters(wl.gamma, SGC_BETA, alpha=1.0, seed=0, it=t)._keep[0].cpu().numpy().copy()
            for t in range(total)]
     del sol
     return out
@@ -792,7 +792,9 @@ def sgc_leg(S, wl, warmup):
     the clustering kernel alone (K maps back to back, HIP events on the stream it
     runs on), then K FP64 LM iterations each preceded by its own device map (the
     number of clusters read back before each step), against the host harness's
-    time per map on the same camera graph."""
+    time per map on the same camera graph; then the same K iterations with the
+    number of clusters left on the device (no read-back), eager and as one
+    captured HIP graph, whose final state must equal the eager one's."""
     import torch
     import synth
     s = wl.scene
@@ -818,10 +820,13 @@ def sgc_leg(S, wl, warmup):
     kernel_ms = e0.elapsed_time(e1) / K
     cam0, pt0 = sol.cam.clone(), sol.pt.clone()
 
-    def iterations(steps):
+    def reset():
         sol.cam.copy_(cam0)
         sol.pt.copy_(pt0)
         S.stba_lm_init(sol.state, wl.lam0, 0.1)
+
+    def iterations(steps):
+        reset()
         ls = []
         for t in range(steps):
             smp = sol.sample_clusters(wl.gamma, SGC_BETA, alpha=1.0, seed=0, it=t)
@@ -829,19 +834,44 @@ def sgc_leg(S, wl, warmup):
             sol.step(smp)
         return ls
 
+    def device_iterations(steps):
+        # the number of clusters stays on the device: nothing is read back
+        for t in range(steps):
+            sol.step(sol.sample_clusters_device(wl.gamma, SGC_BETA, alpha=1.0, seed=0, it=t))
+
     iterations(warmup)
     ls = []
     t_iter = timed(lambda: ls.extend(iterations(K)))
     st = sol.read_state()
+    reset()
+    device_iterations(warmup)
+    reset()
+    t_dev = timed(lambda: device_iterations(K))
+    st_dev = sol.read_state()
+    g = torch.cuda.CUDAGraph()
+    reset()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        device_iterations(K)
+    reset()
+    g.replay()
+    torch.cuda.synchronize()
+    st_cap = sol.read_state()
+    reset()
+    t_cap = timed(g.replay)
+    del g
     e, w = synth.camera_graph(s.obs_cam, s.obs_pt, s.m)
     t0 = time.perf_counter()
     n_host = 3
     for t in range(n_host):
         synth.sgc_map(e, w, s.m, wl.gamma, SGC_BETA, 0, t)
     host_ms = 1e3 * (time.perf_counter() - t0) / n_host
+    same = all(st_dev[k] == st[k] and st_cap[k] == st[k] for k in ("F", "lambda_", "accepted", "status"))
     return {"workload": wl.name, "beta": SGC_BETA, "cap": wl.gamma, "kernel_ms_per_map": kernel_ms,
-            "iter_per_s_with_device_maps": K / t_iter, "clusters_mean": float(np.mean(ls)),
-            "F_after_K": st["F"], "status": st["status"], "host_harness_ms_per_map": host_ms}
+            "iter_per_s_with_device_maps": K / t_iter, "iter_per_s_device_count": K / t_dev,
+            "iter_per_s_captured_device_maps": K / t_cap, "captured_equals_eager": bool(same),
+            "clusters_mean": float(np.mean(ls)), "F_after_K": st["F"], "status": st["status"],
+            "host_harness_ms_per_map": host_ms}
 
 
 PCG_TOLS = (1e-4, 1e-6, 1e-10)
@@ -947,7 +977,7 @@ def ablation_leg(S, wl, K):
                 first = first or smp
             use = first if fixed else smp
             if fixed:
-                use = S.make_sample(first._keep, first.l, 1.0, 0, t)
+                use = S.make_sample(first._keep[0], first.l, 1.0, 0, t)
             sol.step(use)
             st = sol.read_state()
             Fs.append(float(st["F"]))

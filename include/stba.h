@@ -88,11 +88,16 @@ typedef struct stba_dims {
 /* One draw of the constraint sampler Theta(alpha) (Sec. 4.2). */
 typedef struct stba_sample {
     const int32_t *cam_cluster; /* [m] cluster of each camera, values in [0, l) */
-    int32_t l;                  /* number of clusters, 1 <= l <= m */
+    int32_t l;                  /* number of clusters, 1 <= l <= m; with l_dev: an upper bound */
     int32_t pad0;
     double alpha;               /* confidence level in (0, 1]; 1 keeps every intra-cluster link */
     uint64_t seed;              /* Philox4x64-10 key word 0 */
     uint64_t iter;              /* LM iteration t, Philox counter word 0 */
+    const int32_t *l_dev;       /* (device, nullable) the number of clusters, read on the device, so a
+                                   map drawn on the device (stba_sample_clusters) needs no read-back:
+                                   ids must lie in [0, *l_dev), 1 <= *l_dev <= l, and the launches are
+                                   sized for the bound l (clusters *l_dev .. l - 1 are empty).  A value
+                                   outside [1, l] rejects the step as an invalid map. */
 } stba_sample;
 
 /* Damping for the standalone assembly call (Eq. 1-4, Sec. 4.3). */
@@ -135,8 +140,9 @@ typedef struct stba_rcs {
     const double *b;            /* [m][9] right-hand side b' = v' - E' C'^-1 w' (Eq. 13) */
     const int32_t *seg_head;    /* [q] sampled segment of each observation, named by its first
                                    observation (smallest camera) - the bound virtual point */
-    int32_t l;
+    int32_t l;                  /* the sample's l (a bound when l_dev is set) */
     int32_t precision;
+    const int32_t *l_dev;       /* the sample's l_dev (nullable) */
 } stba_rcs;
 
 /* ---- set-up ------------------------------------------------------------ */
@@ -258,12 +264,14 @@ int stba_solve_clusters_pcg(const stba_problem *p, const stba_dims *dims, const 
  *   cam_cluster [m] (device int32): cluster of each camera, numbered 0..l-1 in
  *     order of each cluster's smallest camera.  n_clusters (device int32): l.
  *   status (device int32): STBA_OK once the map is written.
- * Requires p->m <= 2048 (the clustering runs in one workgroup), dims->n_pairs
- * < 2^31 (edge weights are 32-bit) and stba_prepare.
+ * Requires p->m <= 6144 (the clustering runs in one workgroup whose LDS holds
+ * 24 bytes per camera), dims->n_pairs < 2^31 (edge weights are 32-bit) and
+ * stba_prepare.
  * Keeps its pair labels, clocks and weights in workspace buffers that only
  * stba_prepare otherwise uses (a later stba_prepare rewrites them);
- * asynchronous (one kernel).  To fill a stba_sample the caller reads n_clusters
- * back. */
+ * asynchronous (one kernel).  A stba_sample can take the map as it stands on the
+ * device: cam_cluster, l = m (the bound) and l_dev = n_clusters, with no
+ * read-back, so the clustering and the LM step can be captured together. */
 int stba_sample_clusters(const stba_problem *p, const stba_dims *dims, int precision, void *ws, size_t ws_bytes,
                          int32_t gamma, double beta, uint64_t seed, uint64_t iter, int32_t *cam_cluster,
                          int32_t *n_clusters, int32_t *status, hipStream_t stream);

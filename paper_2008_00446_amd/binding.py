@@ -40,7 +40,8 @@ class StbaDims(ctypes.Structure):
 
 class StbaSample(ctypes.Structure):
     _fields_ = [("cam_cluster", ctypes.c_void_p), ("l", ctypes.c_int32), ("pad0", ctypes.c_int32),
-                ("alpha", ctypes.c_double), ("seed", ctypes.c_uint64), ("iter", ctypes.c_uint64)]
+                ("alpha", ctypes.c_double), ("seed", ctypes.c_uint64), ("iter", ctypes.c_uint64),
+                ("l_dev", ctypes.c_void_p)]
 
 
 class StbaDamping(ctypes.Structure):
@@ -60,7 +61,7 @@ class StbaRcs(ctypes.Structure):
                 ("cl_Np", ctypes.c_void_p), ("cl_start", ctypes.c_void_p), ("cl_cams", ctypes.c_void_p),
                 ("cam_local", ctypes.c_void_p), ("b", ctypes.c_void_p), ("seg_head", ctypes.c_void_p),
                 ("l", ctypes.c_int32),
-                ("precision", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("l_dev", ctypes.c_void_p)]
 
 
 _P = ctypes.c_void_p
@@ -147,10 +148,13 @@ def make_problem(cam, pt, obs_cam, obs_pt, obs_uv, huber=0.0) -> StbaProblem:
     return p
 
 
-def make_sample(cam_cluster, l, alpha=1.0, seed=0, it=0) -> StbaSample:
+def make_sample(cam_cluster, l, alpha=1.0, seed=0, it=0, l_dev=None) -> StbaSample:
+    """l_dev (device int32 tensor of one element, optional): the number of clusters on the
+    device; l is then an upper bound."""
     assert cam_cluster.dtype == torch.int32
-    s = StbaSample(_ptr(cam_cluster), int(l), 0, float(alpha), int(seed), int(it))
-    s._keep = cam_cluster
+    assert l_dev is None or (l_dev.dtype == torch.int32 and l_dev.numel() >= 1)
+    s = StbaSample(_ptr(cam_cluster), int(l), 0, float(alpha), int(seed), int(it), _ptr(l_dev))
+    s._keep = (cam_cluster, l_dev)
     return s
 
 

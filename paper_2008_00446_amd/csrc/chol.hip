@@ -368,7 +368,10 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(int32_t l, const int32_t 
                                                        const int32_t *__restrict__ cl_start,
                                                        const int32_t *__restrict__ cl_cams, double *__restrict__ S,
                                                        const double *__restrict__ b, double *__restrict__ dcam,
-                                                       int32_t *__restrict__ cl_status, int32_t max_Np) {
+                                                       int32_t *__restrict__ cl_status, int32_t max_Np,
+                                                       const int32_t *skip) {
+    // skip (nullable): 1 when the team form has already solved every cluster
+    if (skip != nullptr && skip[0] == 1) return;
     extern __shared__ double smem[];
     double(*Wi)[kNB + 1] = reinterpret_cast<double(*)[kNB + 1]>(smem);
     double(*Ls)[kNB + 1] = reinterpret_cast<double(*)[kNB + 1]>(smem + kNB * (kNB + 1));
@@ -1328,12 +1331,17 @@ __device__ inline int team_own(int T, int W, int w0) {
 
 // This wavefront's cluster k, its index r in the team (0: band) and the
 // number of workers W (every wavefront computes the same layout).
-__device__ inline bool team_role(int wave, int G, int l, const int32_t *cl_Np, int &k_out, int &r_out, int &W_out) {
+// Empty clusters get no wavefront; n_act receives the number of the others.
+// False for a spare wavefront, and for every wavefront when the teams would
+// not fit in G (fits = false).
+__device__ inline bool team_role(int wave, int G, int l, const int32_t *cl_Np, int &k_out, int &r_out, int &W_out,
+                                 int &n_act, bool &fits) {
     const int lane = threadIdx.x & 63;
     int64_t sw = 0;
-    int n3 = 0;
+    int n3 = 0, n1 = 0;
     for (int k = lane; k < l; k += 64) {
         const int T = cl_Np[k] / kNB;
+        if (T >= 1) ++n1;
         if (T >= 3) {
             sw += (int64_t)T * T * T;
             ++n3;
@@ -1343,9 +1351,12 @@ __device__ inline bool team_role(int wave, int G, int l, const int32_t *cl_Np, i
     for (int d = 32; d > 0; d >>= 1) {
         sw += __shfl_xor(sw, d, 64);
         n3 += __shfl_xor(n3, d, 64);
+        n1 += __shfl_xor(n1, d, 64);
     }
-    const int64_t wtot = (int64_t)G - 2 * (int64_t)l - n3;
-    if (wtot < 0) return false;
+    n_act = n1;
+    const int64_t wtot = (int64_t)G - 2 * (int64_t)n1 - n3;
+    fits = wtot >= 0;
+    if (!fits) return false;
     int64_t base = 0;
     for (int c0 = 0; c0 < l; c0 += 64) {
         const int k = c0 + lane;
@@ -1357,7 +1368,7 @@ __device__ inline bool team_role(int wave, int G, int l, const int32_t *cl_Np, i
                 if (W < 1) W = 1;
                 if (W > team_ntasks(T)) W = team_ntasks(T);
             }
-            size = 2 + W;
+            size = T >= 1 ? 2 + W : 0;
         }
         int64_t inc = size;   // inclusive scan over the 64 clusters of this chunk
 #pragma unroll
@@ -1763,8 +1774,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void
     double(*Ls)[kNB + 1] = Wi + kNB;
     int32_t *lists = reinterpret_cast<int32_t *>(ys + kNB);
     const int lane = threadIdx.x;
-    int k = 0, r = 0, W = 0;
-    if (!team_role((int)blockIdx.x, G, l, cl_Np, k, r, W)) return;   // spare wavefront
+    int k = 0, r = 0, W = 0, n_act = 0;
+    bool fits = false;
+    const bool found = team_role((int)blockIdx.x, G, l, cl_Np, k, r, W, n_act, fits);
+    if (blockIdx.x == 0) {
+        // the empty clusters' status, and whether the workgroup form must still run
+        for (int q = lane; q < l; q += 64)
+            if (cl_Np[q] == 0) cl_status[q] = STBA_OK;
+        if (lane == 0) tb.flags[tb.abort_at + 2] = fits ? 1 : 0;
+    }
+    if (!found) return;   // spare wavefront, or the teams do not fit
     bool ok;
     if (r == 0)
         ok = team_band(k, S_off, cl_n, cl_Np, cl_start, cl_cams, S, dcam, tb, Wi, Ls, zs);
@@ -1816,7 +1835,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void
     __builtin_amdgcn_s_waitcnt(0);
     if (lane == 0) {
         __hip_atomic_store(fl_cnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (__hip_atomic_fetch_add(abort_w + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == l - 1) {
+        if (__hip_atomic_fetch_add(abort_w + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == n_act - 1) {
             __hip_atomic_store(abort_w, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(abort_w + 1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -1894,7 +1913,8 @@ hipError_t launch_chol(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, con
                        int32_t *cl_status, int32_t max_Np, int32_t *flags, double *yx, const double *S0,
                        double *rbuf, const CholTeam *team, hipStream_t st) {
     int32_t wpc = 0, tmax = 0, fpc = 0, xcd = 0;
-    if (team != nullptr && team->force) goto team_path;
+    // with the number of clusters on the device the tile grid cannot be sized
+    if (team != nullptr && (team->force || team->l_on_device)) goto team_path;
     if (flags && yx && chol_tile_layout(l, max_Np, &wpc, &tmax, &fpc, &xcd)) {
         // the flag words are zero and the vector entries kEmpty here: set when the
         // workspace was prepared and again at the end of every factorisation
@@ -1908,8 +1928,11 @@ team_path:
         // every wavefront of a team waits on the others: all must be resident,
         // with a sixteenth of the capacity in reserve; a band, a forward wavefront
         // and a worker per cluster
+        // With the number of clusters on the device the team form is tried
+        // first and the workgroup form runs after it only if the teams did not
+        // fit (a word the team launch writes).
         const int64_t G = 15 * chol_team_resident(max_Np) / 16;
-        if (G >= 3 * (int64_t)l) {
+        if (G >= 3 * (int64_t)l || (team->l_on_device && G >= 3)) {
             TeamBufs tb;
             tb.flags = team->flags;
             tb.abort_at = team->abort_at;
@@ -1919,6 +1942,14 @@ team_path:
             tb.xv = team->vec + 3 * team->vec_len;
             k_chol_team<<<(unsigned)G, 64, team_lds_bytes(max_Np), st>>>((int32_t)G, l, cl_n, cl_Np, S_off, cl_start,
                                                                          cl_cams, S, b, dcam, cl_status, tb);
+            if (team->l_on_device) {
+                const hipError_t e = hipGetLastError();
+                if (e != hipSuccess) return e;
+                const size_t shmem = sizeof(double) * (2 * (size_t)kNB * (kNB + 1) + 2 * kNB + (size_t)max_Np +
+                                                       kCholThreads + kNB);
+                k_chol<<<(unsigned)l, kCholThreads, shmem, st>>>(l, cl_n, cl_Np, S_off, cl_start, cl_cams, S, b, dcam,
+                                                                 cl_status, max_Np, team->flags + team->abort_at + 2);
+            }
             if (S0) {
                 const hipError_t e = hipGetLastError();
                 if (e != hipSuccess) return e;
@@ -1929,7 +1960,7 @@ team_path:
     }
     const size_t shmem = sizeof(double) * (2 * (size_t)kNB * (kNB + 1) + 2 * kNB + (size_t)max_Np + kCholThreads + kNB);
     k_chol<<<(unsigned)l, kCholThreads, shmem, st>>>(l, cl_n, cl_Np, S_off, cl_start, cl_cams, S, b, dcam, cl_status,
-                                                     max_Np);
+                                                     max_Np, nullptr);
     if (S0) {
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -1942,7 +1973,7 @@ hipError_t launch_clear_chol_flags(int32_t *flags, double *yx, const CholTeam *t
     const int64_t nf = chol_flag_words(), nv = chol_yx_doubles();
     k_init_chol_sync<<<(unsigned)(((nf > nv ? nf : nv) + 255) / 256), 256, 0, st>>>(flags, nf, yx, nv);
     if (team != nullptr && team->flags != nullptr) {
-        const int64_t tf = team->abort_at + 2, tv = 4 * team->vec_len;
+        const int64_t tf = team->abort_at + 3, tv = 4 * team->vec_len;
         int64_t blocks = ((tf > tv ? tf : tv) + 255) / 256;
         if (blocks > 65536) blocks = 65536;
         k_init_chol_sync<<<(unsigned)blocks, 256, 0, st>>>(team->flags, tf, team->vec, tv);

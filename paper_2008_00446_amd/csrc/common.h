@@ -15,7 +15,7 @@ constexpr int kSegRec = 16;        // per-segment record at the head observation
 constexpr int kSchurChunk = 512;   // observation pairs per Schur work item (16 rounds of 32 pair slots)
 constexpr int kSchurPart = 100;    // doubles per partial sum: 81 block entries, 9 diag(U), 9 rhs, pad
 constexpr int kMaxCamsForClusters = 16384;   // cluster layout: every camera id and cluster count held in LDS
-constexpr int kSgcMaxCams = 2048;          // graph clustering: cameras held in one workgroup's LDS
+constexpr int kSgcMaxCams = 6144;          // graph clustering: cameras held in one workgroup's LDS (24 B each)
 
 // Status words kept in the workspace (int32[16]).
 enum StatusWord : int {

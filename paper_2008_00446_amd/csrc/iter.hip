@@ -49,9 +49,10 @@ __device__ inline V block_exclusive_scan(V v, V *wsum, V *total) {
 // and per cluster (l <= m), per-cluster counts in LDS, the position of a camera
 // in its cluster = the number of lower-numbered cameras of that cluster.
 __global__ __launch_bounds__(1024) void k_clusters_small(const int32_t *cam_cluster, int32_t m, int32_t l,
-                                                         int32_t gamma_max, int32_t *cl_n, int32_t *cl_Np,
-                                                         int32_t *cl_start, int32_t *cl_cams, int32_t *cam_local,
-                                                         int64_t *S_off, int32_t *status) {
+                                                         const int32_t *l_dev, int32_t gamma_max, int32_t *cl_n,
+                                                         int32_t *cl_Np, int32_t *cl_start, int32_t *cl_cams,
+                                                         int32_t *cam_local, int64_t *S_off, int32_t *cl_status,
+                                                         int32_t *status) {
     __shared__ __align__(16) int32_t cl[1024];
     __shared__ int32_t cnt[1024];
     __shared__ int32_t ws32[16];
@@ -60,10 +61,14 @@ __global__ __launch_bounds__(1024) void k_clusters_small(const int32_t *cam_clus
     const int t = threadIdx.x;
     if (t < kStCount) status[t] = 0;
     if (t == 0) bad = 0;
+    // ids are checked against the device count when there is one (clusters up to l stay empty)
+    const int32_t lv = l_dev != nullptr ? l_dev[0] : l;
+    const int32_t lid = (lv >= 1 && lv <= l) ? lv : 0;
+    if (t < l) cl_status[t] = STBA_OK;
     int32_t k = -1;
     if (t < m) {
         k = cam_cluster[t];
-        if (k < 0 || k >= l) {
+        if (k < 0 || k >= lid) {
             bad = 1;
             k = -1;
         }
@@ -119,8 +124,9 @@ __global__ __launch_bounds__(1024) void k_clusters_small(const int32_t *cam_clus
 // per-cluster arrays and S_off, so a bad map is reported after the clearing.
 constexpr int kClusterLargeThreads = 256;
 __global__ __launch_bounds__(kClusterLargeThreads) void k_clusters_large(
-    const int32_t *cam_cluster, int32_t m, int32_t l, int32_t gamma_max, int32_t *cl_n, int32_t *cl_Np,
-    int32_t *cl_start, int32_t *cl_cams, int32_t *cam_local, int64_t *S_off, int32_t *status) {
+    const int32_t *cam_cluster, int32_t m, int32_t l, const int32_t *l_dev, int32_t gamma_max, int32_t *cl_n,
+    int32_t *cl_Np, int32_t *cl_start, int32_t *cl_cams, int32_t *cam_local, int64_t *S_off, int32_t *cl_status,
+    int32_t *status) {
     extern __shared__ __align__(16) int32_t dyn[];
     int32_t *cnt = dyn;          // [l] cameras per cluster, then the first slot of each cluster
     int32_t *base = dyn + l;     // [l] cameras of each cluster before this workgroup's chunk
@@ -132,16 +138,20 @@ __global__ __launch_bounds__(kClusterLargeThreads) void k_clusters_large(
     const int32_t chunk0 = (int32_t)blockIdx.x * kClusterLargeThreads;
     if (lead && t < kStCount) status[t] = 0;
     if (t == 0) bad = 0;
+    // ids are checked against the device count when there is one (clusters up to l stay empty)
+    const int32_t lv = l_dev != nullptr ? l_dev[0] : l;
+    const int32_t lid = (lv >= 1 && lv <= l) ? lv : 0;
     for (int i = t; i < l; i += kClusterLargeThreads) {
         cnt[i] = 0;
         base[i] = 0;
+        if (lead) cl_status[i] = STBA_OK;
     }
     __syncthreads();
     bool bad_id = false;
     for (int i0 = t - lane; i0 < m; i0 += kClusterLargeThreads) {   // wavefront-uniform
         const int i = i0 + lane;
         int32_t k = i < m ? cam_cluster[i] : -1;
-        if (i < m && (k < 0 || k >= l)) {
+        if (i < m && (k < 0 || k >= lid)) {
             bad_id = true;
             k = -1;
         }
@@ -203,7 +213,7 @@ __global__ __launch_bounds__(kClusterLargeThreads) void k_clusters_large(
         for (int sub = 0; sub < kClusterLargeThreads / 64; ++sub) {
             const int i = chunk0 + 64 * sub + lane;
             int32_t k = i < m ? cam_cluster[i] : -1;
-            if (k >= l) k = -1;
+            if (k >= lid) k = -1;
             unsigned long long todo = __ballot(k >= 0);
             while (todo) {
                 const int ld = __ffsll(todo) - 1;
@@ -1355,17 +1365,24 @@ hipError_t launch_lm_init(stba_lm_state *s, double lambda0, double lambda_corr, 
     return hipGetLastError();
 }
 
-hipError_t launch_clusters(const int32_t *cam_cluster, int32_t m, int32_t l, int32_t gamma_max, int32_t *cl_n,
-                           int32_t *cl_Np, int32_t *cl_start, int32_t *cl_cams, int32_t *cam_local,
-                           int64_t *S_off, int32_t *status, hipStream_t st) {
+hipError_t launch_clusters(const int32_t *cam_cluster, int32_t m, int32_t l, const int32_t *l_dev, int32_t gamma_max,
+                           int32_t *cl_n, int32_t *cl_Np, int32_t *cl_start, int32_t *cl_cams, int32_t *cam_local,
+                           int64_t *S_off, int32_t *cl_status, int32_t *status, hipStream_t st) {
     if (m <= 1024) {
-        k_clusters_small<<<1, (unsigned)round_up(m, 64), 0, st>>>(cam_cluster, m, l, gamma_max, cl_n, cl_Np, cl_start,
-                                                                  cl_cams, cam_local, S_off, status);
+        k_clusters_small<<<1, (unsigned)round_up(m, 64), 0, st>>>(cam_cluster, m, l, l_dev, gamma_max, cl_n, cl_Np,
+                                                                  cl_start, cl_cams, cam_local, S_off, cl_status,
+                                                                  status);
         return hipGetLastError();
     }
     const size_t lds = sizeof(int32_t) * 2 * (size_t)l;
+    if (lds > 64 * 1024) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_clusters_large),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
     k_clusters_large<<<(unsigned)((m + kClusterLargeThreads - 1) / kClusterLargeThreads), kClusterLargeThreads, lds,
-                       st>>>(cam_cluster, m, l, gamma_max, cl_n, cl_Np, cl_start, cl_cams, cam_local, S_off, status);
+                       st>>>(cam_cluster, m, l, l_dev, gamma_max, cl_n, cl_Np, cl_start, cl_cams, cam_local, S_off,
+                             cl_status, status);
     return hipGetLastError();
 }
 

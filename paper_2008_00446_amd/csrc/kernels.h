@@ -35,10 +35,11 @@ hipError_t launch_prepare(const stba_problem &p, int64_t n_pairs, const PrepBufs
 // --- per iteration ----------------------------------------------------------
 hipError_t launch_reset_status(int32_t *status, hipStream_t st);
 hipError_t launch_lm_init(stba_lm_state *s, double lambda0, double lambda_corr, hipStream_t st);
-// also clears the status words
-hipError_t launch_clusters(const int32_t *cam_cluster, int32_t m, int32_t l, int32_t gamma_max,
+// also clears the status words and sets every cluster's status (l of them) to
+// STBA_OK; l_dev (nullable): the number of clusters on the device, l a bound
+hipError_t launch_clusters(const int32_t *cam_cluster, int32_t m, int32_t l, const int32_t *l_dev, int32_t gamma_max,
                            int32_t *cl_n, int32_t *cl_Np, int32_t *cl_start, int32_t *cl_cams,
-                           int32_t *cam_local, int64_t *S_off, int32_t *status, hipStream_t st);
+                           int32_t *cam_local, int64_t *S_off, int32_t *cl_status, int32_t *status, hipStream_t st);
 
 // S (nullable): also zero S (the first min(S_off[l], S_cap) doubles), S0 (if
 // given, the same extent) and b (nb doubles)
@@ -117,9 +118,11 @@ struct CholTeam {
     double *vec = nullptr;
     int64_t vec_len = 0;
     bool force = false;
+    bool l_on_device = false;   // l is a bound: the number of clusters is known only on the device
 };
 constexpr int32_t kTeamMaxNp = 2048;
-inline int64_t chol_team_flag_words(int64_t S_cap, int32_t m) { return 2 * (S_cap / 1024) + 8 * (int64_t)m + 2; }
+// ... then the abort word, the finished-cluster count and whether the teams ran
+inline int64_t chol_team_flag_words(int64_t S_cap, int32_t m) { return 2 * (S_cap / 1024) + 8 * (int64_t)m + 3; }
 inline int64_t chol_team_vec_len(int64_t S_cap) { return S_cap / 32; }
 // the flag words and block vectors have to be in their initial state before the
 // first factorisation; every tile-parallel or team factorisation leaves them so again

@@ -38,16 +38,24 @@ constexpr int kSgcBatch = 8;      // slots whose labels one round trip reads (la
 constexpr int kSgcAffList = 4;    // touched slots a thread remembers between the two phases (larger graphs)
 constexpr int kSgcCompactEvery = 16;   // joins between two packings of the live slots (larger graphs)
 
-struct SgcShared {
-    int32_t lab[kSgcMaxCams];      // cluster name of each camera
-    int32_t csize[kSgcMaxCams];    // cameras in the cluster named i
-    int32_t slot[kSgcMaxCams];     // smallest block index of the renamed pairs (x, z), per z
-    int32_t wacc[kSgcMaxCams];     // their summed weight, per z; the cluster ranks at the end
-    unsigned long long K[kSgcMaxCams];   // summed incident weight of the cluster named i
+// Per-camera state in dynamic LDS (24 bytes per camera, sgc_lds_bytes), the
+// reductions in static LDS; the struct holds the pointers.
+struct SgcSmall {
     double redT[kSgcWaves];
     uint32_t redP[kSgcWaves];
     int32_t redC[kSgcWaves];
     unsigned long long s_tot;
+};
+struct SgcShared {
+    unsigned long long *K;   // summed incident weight of the cluster named i
+    int32_t *lab;            // cluster name of each camera
+    int32_t *csize;          // cameras in the cluster named i
+    int32_t *slot;           // smallest block index of the renamed pairs (x, z), per z
+    int32_t *wacc;           // their summed weight, per z; the cluster ranks at the end
+    double *redT;
+    uint32_t *redP;
+    int32_t *redC;
+    unsigned long long *s_tot;
 };
 
 __device__ inline bool clock_less(double t1, uint32_t p1, double t2, uint32_t p2) {
@@ -178,9 +186,9 @@ __device__ void sgc_joins(int32_t m, int64_t nb, const int2 *blk_key, const int6
             Pg[gidx(r)] = P;
     }
     for (int off = 32; off > 0; off >>= 1) my_s += __shfl_xor(my_s, off);
-    if ((tid & 63) == 0 && my_s) atomicAdd(&sh.s_tot, (unsigned long long)my_s);
+    if ((tid & 63) == 0 && my_s) atomicAdd(sh.s_tot, (unsigned long long)my_s);
     __syncthreads();
-    const double s = (double)sh.s_tot;
+    const double s = (double)*sh.s_tot;
     const bool any = s > 0.0 && gamma > 1;
 
     // initial clocks (join step 0, time 0)
@@ -300,7 +308,18 @@ __global__ __launch_bounds__(kSgcThreads) void k_sgc(int32_t m, const int64_t *n
                                                      uint64_t seed, uint64_t iter, uint32_t *Pg, double *Tg,
                                                      int32_t *Wg, int32_t *cam_cluster, int32_t *n_clusters,
                                                      int32_t *status) {
-    __shared__ SgcShared sh;
+    extern __shared__ __align__(16) unsigned long long sgc_lds[];
+    __shared__ SgcSmall small;
+    SgcShared sh;
+    sh.K = sgc_lds;
+    sh.lab = reinterpret_cast<int32_t *>(sgc_lds + m);
+    sh.csize = sh.lab + m;
+    sh.slot = sh.csize + m;
+    sh.wacc = sh.slot + m;
+    sh.redT = small.redT;
+    sh.redP = small.redP;
+    sh.redC = small.redC;
+    sh.s_tot = &small.s_tot;
     const int tid = threadIdx.x;
     const int64_t nb = n_blocks[0];
     for (int32_t i = tid; i < m; i += kSgcThreads) {
@@ -310,7 +329,7 @@ __global__ __launch_bounds__(kSgcThreads) void k_sgc(int32_t m, const int64_t *n
         sh.wacc[i] = 0;
         sh.K[i] = 0;
     }
-    if (tid == 0) sh.s_tot = 0;
+    if (tid == 0) *sh.s_tot = 0;
     __syncthreads();
     if (nb <= kSgcRegSlots * kSgcThreads)
         sgc_joins<kSgcRegSlots, true>(m, nb, blk_key, blk_start, gamma, beta, seed, iter, Pg, Tg, Wg, sh);
@@ -359,8 +378,15 @@ __global__ __launch_bounds__(kSgcThreads) void k_sgc(int32_t m, const int64_t *n
 hipError_t launch_sgc(int32_t m, const int64_t *n_blocks, const int2 *blk_key, const int64_t *blk_start,
                       int32_t gamma, double beta, uint64_t seed, uint64_t iter, uint32_t *Pg, double *Tg,
                       int32_t *Wg, int32_t *cam_cluster, int32_t *n_clusters, int32_t *status, hipStream_t st) {
-    k_sgc<<<1, kSgcThreads, 0, st>>>(m, n_blocks, blk_key, blk_start, gamma, beta, seed, iter, Pg, Tg, Wg,
-                                     cam_cluster, n_clusters, status);
+    // 8 bytes of K and 4 x 4 of the int32 arrays per camera
+    const size_t lds = 24 * (size_t)m;
+    if (lds > 64 * 1024) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_sgc),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    k_sgc<<<1, kSgcThreads, lds, st>>>(m, n_blocks, blk_key, blk_start, gamma, beta, seed, iter, Pg, Tg, Wg,
+                                       cam_cluster, n_clusters, status);
     return hipGetLastError();
 }
 

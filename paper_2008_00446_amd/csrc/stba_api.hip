@@ -133,8 +133,8 @@ bool make_layout(const stba_problem *p, const stba_dims *d, int precision, Layou
     L.S_cap = s_capacity(p->m, d->gamma_max);
     L.S = take(8 * (size_t)L.S_cap);
     // flags and block vectors of the team factorisation (many clusters)
-    L.team_abort_at = chol_team_flag_words(L.S_cap, p->m) - 2;
-    L.team_flags = take(4 * (size_t)(L.team_abort_at + 2));
+    L.team_abort_at = chol_team_flag_words(L.S_cap, p->m) - 3;
+    L.team_flags = take(4 * (size_t)(L.team_abort_at + 3));
     L.team_vec_len = chol_team_vec_len(L.S_cap);
     L.team_vec = take(8 * 4 * (size_t)L.team_vec_len);
     // MIXED keeps the assembled S for the refinement step
@@ -200,9 +200,10 @@ template <typename T>
 int build_rcs_impl(const stba_problem *p, const stba_dims *d, const stba_sample *s, const double *lam2,
                    const T *f, const T *Jc, const T *Jp, const Layout &L, void *ws, hipStream_t st) {
     int32_t *status = at<int32_t>(ws, L.status);
-    STBA_HIP(launch_clusters(s->cam_cluster, p->m, s->l, d->gamma_max, at<int32_t>(ws, L.cl_n),
+    STBA_HIP(launch_clusters(s->cam_cluster, p->m, s->l, s->l_dev, d->gamma_max, at<int32_t>(ws, L.cl_n),
                              at<int32_t>(ws, L.cl_Np), at<int32_t>(ws, L.cl_start), at<int32_t>(ws, L.cl_cams),
-                             at<int32_t>(ws, L.cam_local), at<int64_t>(ws, L.S_off), status, st));
+                             at<int32_t>(ws, L.cam_local), at<int64_t>(ws, L.S_off), at<int32_t>(ws, L.cl_status),
+                             status, st));
     STBA_HIP(launch_points<T>(*p, at<int64_t>(ws, L.pt_off), s->cam_cluster, s->l, f, Jc, Jp, lam2, s->seed, s->iter,
                               keep_threshold(s->alpha), at<int32_t>(ws, L.seg_head), at<double>(ws, L.seg_rec), at<T>(ws, L.obsd),
                               at<double>(ws, L.Vinv), at<double>(ws, L.wph), status, L.group_size,
@@ -233,10 +234,12 @@ CholTeam team_of(const Layout &L, void *ws) {
 // The cluster solves of Eq. 13; in MIXED precision with one FP64 refinement
 // step against the assembled S.
 template <typename T>
-int cluster_solve(int32_t l, double *dcam, int32_t *cl_status, const Layout &L, void *ws, hipStream_t st) {
+int cluster_solve(int32_t l, bool l_on_device, double *dcam, int32_t *cl_status, const Layout &L, void *ws,
+                  hipStream_t st) {
     // MIXED: S0, the copy of S kept for the refinement step, was written by the assembly
     const bool mixed = sizeof(T) == sizeof(float);
-    const CholTeam team = team_of(L, ws);
+    CholTeam team = team_of(L, ws);
+    team.l_on_device = l_on_device;
     STBA_HIP(launch_chol(l, at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np), at<int64_t>(ws, L.S_off),
                          at<int32_t>(ws, L.cl_start), at<int32_t>(ws, L.cl_cams), at<double>(ws, L.S),
                          at<double>(ws, L.b), dcam, cl_status, L.max_Np, at<int32_t>(ws, L.chol_flags),
@@ -246,10 +249,11 @@ int cluster_solve(int32_t l, double *dcam, int32_t *cl_status, const Layout &L, 
 }
 
 template <typename T>
-int solve_impl(const stba_problem *p, const stba_dims *d, int32_t l, const T *Jc, const T *Jp, double *dcam,
+int solve_impl(const stba_problem *p, const stba_dims *d, int32_t l, bool l_on_device, const T *Jc, const T *Jp,
+               double *dcam,
                double *dpt, int32_t *cl_status, const Layout &L, void *ws, hipStream_t st) {
     (void)d;
-    STBA_TRY(cluster_solve<T>(l, dcam, cl_status, L, ws, st));
+    STBA_TRY(cluster_solve<T>(l, l_on_device, dcam, cl_status, L, ws, st));
     STBA_HIP(launch_backsub<T>(*p, at<int64_t>(ws, L.pt_off), Jc, Jp, at<double>(ws, L.Vinv), at<double>(ws, L.wph),
                                dcam, dpt, L.group_size, at<int32_t>(ws, L.grp_first), st));
     return STBA_OK;
@@ -272,9 +276,10 @@ int lm_step_impl(const stba_problem *p, const stba_dims *d, const stba_sample *s
         return STBA_OK;
     };
     STBA_TRY(mark(0));
-    STBA_HIP(launch_clusters(s->cam_cluster, p->m, s->l, d->gamma_max, at<int32_t>(ws, L.cl_n),
+    STBA_HIP(launch_clusters(s->cam_cluster, p->m, s->l, s->l_dev, d->gamma_max, at<int32_t>(ws, L.cl_n),
                              at<int32_t>(ws, L.cl_Np), at<int32_t>(ws, L.cl_start), at<int32_t>(ws, L.cl_cams),
-                             at<int32_t>(ws, L.cam_local), at<int64_t>(ws, L.S_off), status, st));
+                             at<int32_t>(ws, L.cam_local), at<int64_t>(ws, L.S_off), at<int32_t>(ws, L.cl_status),
+                             status, st));
     STBA_TRY(mark(1));
     ZeroS z;   // S and b are zeroed by the residual kernel's grid
     z.S = at<double>(ws, L.S);
@@ -308,7 +313,7 @@ int lm_step_impl(const stba_problem *p, const stba_dims *d, const stba_sample *s
                             L.max_Np, d->gamma_max, pcg->max_iters, pcg->tol, at<int32_t>(ws, L.pcg_iters),
                             at<double>(ws, L.pcg_resid), at<int32_t>(ws, L.cl_status), st));
     else
-        STBA_TRY(cluster_solve<T>(s->l, dcam, at<int32_t>(ws, L.cl_status), L, ws, st));
+        STBA_TRY(cluster_solve<T>(s->l, s->l_dev != nullptr, dcam, at<int32_t>(ws, L.cl_status), L, ws, st));
     STBA_TRY(mark(6));
     STBA_HIP(launch_backsub<T>(*p, at<int64_t>(ws, L.pt_off), Jc, Jp, at<double>(ws, L.Vinv), at<double>(ws, L.wph),
                                dcam, dpt, L.group_size, at<int32_t>(ws, L.grp_first), st));
@@ -486,6 +491,7 @@ int stba_build_cluster_rcs(const stba_problem *p, const stba_dims *dims, const s
     out->b = at<double>(ws, L.b);
     out->seg_head = at<int32_t>(ws, L.seg_head);
     out->l = s->l;
+    out->l_dev = s->l_dev;
     out->precision = precision;
     return STBA_OK;
 }
@@ -499,8 +505,10 @@ int stba_solve_clusters(const stba_problem *p, const stba_dims *dims, const stba
         return STBA_EINVAL;
     int32_t *cs = cluster_status ? cluster_status : at<int32_t>(ws, L.cl_status);
     if (precision == STBA_FP64)
-        return solve_impl<double>(p, dims, rcs->l, (const double *)Jc, (const double *)Jp, dcam, dpt, cs, L, ws, stream);
-    return solve_impl<float>(p, dims, rcs->l, (const float *)Jc, (const float *)Jp, dcam, dpt, cs, L, ws, stream);
+        return solve_impl<double>(p, dims, rcs->l, rcs->l_dev != nullptr, (const double *)Jc, (const double *)Jp,
+                                  dcam, dpt, cs, L, ws, stream);
+    return solve_impl<float>(p, dims, rcs->l, rcs->l_dev != nullptr, (const float *)Jc, (const float *)Jp, dcam, dpt,
+                             cs, L, ws, stream);
 }
 
 int stba_sample_clusters(const stba_problem *p, const stba_dims *dims, int precision, void *ws, size_t ws_bytes,

@@ -74,6 +74,19 @@ class StbaSolver:
             raise B.StbaError("stba_sample_clusters", status)
         return B.make_sample(cc, l, alpha, seed, it)
 
+    def sample_clusters_device(self, gamma, beta=10.0, alpha=1.0, seed=0, it=0, stream=None):
+        """Draw iteration `it`'s camera clustering on the device and return a sample
+        that reads the number of clusters on the device (l = m as the bound), so
+        nothing is read back and the draw can be captured with the step.  The map
+        buffer is reused by the next call, after the work queued before it."""
+        if self._sgc is None:
+            self._sgc = (torch.empty(self.m, dtype=torch.int32, device=self.cam.device),
+                         torch.zeros(2, dtype=torch.int32, device=self.cam.device))
+        cc, out = self._sgc
+        B.stba_sample_clusters(self.problem, self.dims, self.precision, self.ws, gamma, beta, seed, it, cc,
+                               out[0:1], out[1:2], stream)
+        return B.make_sample(cc, self.m, alpha, seed, it, l_dev=out[0:1])
+
     def step(self, sample, events=None, pcg=None):
         """One LM iteration (asynchronous); pcg = (max_iters, tol): the cluster
         solves by conjugate gradient instead of Cholesky."""

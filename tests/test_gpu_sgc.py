@@ -111,7 +111,7 @@ def test_bad_arguments_are_rejected():
 
 
 def test_more_cameras_than_one_workgroup_holds_is_rejected():
-    m = 2100
+    m = 6145   # one workgroup's LDS holds the clustering of up to 6144 cameras
     obs_pt = np.repeat(np.arange(m - 1), 2).astype(np.int32)
     obs_cam = np.stack([np.arange(m - 1), np.arange(1, m)], axis=1).reshape(-1).astype(np.int32)
     cam = np.zeros((m, 9))
