@@ -72,7 +72,7 @@ def parse_args():
     ap.add_argument("--steps", type=int, default=None, help="LM iterations timed (default: 20 slam, 10 others)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=["slam", "ring", "internet"], default="slam")
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "mixed", "mixed_norefine"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work in cpu_baseline")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -231,18 +231,18 @@ def load_traffic(phase: str, workload: str):
 # the algorithmic work of each phase
 # ---------------------------------------------------------------------------
 
-def algorithmic_model(scene, maps, es):
+def algorithmic_model(scene, maps, es, refine=False):
     """Algorithmic bytes / flops per launch of each phase, averaged over `maps`
     (alpha = 1: one segment per point and cluster).  es: bytes per element of
-    f, J and the Schur data (8 FP64, 4 MIXED).
+    f, J and the Schur data (8 FP64, 4 MIXED); refine: STBA_MIXED's refinement
+    step runs (and the point update takes J in FP64 at x).
 
     Per unit (the method's own inputs and outputs of each step, not this
     implementation's intermediate records):
       residual_jacobian  24 + 26 es bytes per observation (ids and pixel in,
                          f, J_c, J_p out) + the camera and point rows, per
                          Jacobian evaluation; every launch also clears the
-                         padded cluster matrices (8 bytes per entry, and the
-                         MIXED copy) and b
+                         padded cluster matrices (8 bytes per entry) and b
       points_segments    8 + 26 es bytes per observation (ids, f, J in) +
                          72 per segment (V_s, w'_s) + 72 per point (V*_j, w_j)
                          + 432 per camera (U, v)
@@ -251,7 +251,12 @@ def algorithmic_model(scene, maps, es):
                          per pair of distinct observations of one segment
       cluster_cholesky   sum_k N_k^3 / 3 + 4 N_k^2 flop (N_k = 9 n_k),
                          16 bytes per lower entry
-      point_backsub      8 + 24 es bytes per observation + 72 per point
+      refinement         (MIXED) 48 bytes per observation (ids, pixel, point)
+                         + the parameters, 72 per camera out, and the factor
+                         of S_k twice (forward and backward): 16 per lower entry
+      point_backsub      72 per point + 48 per observation (ids, pixel, point:
+                         J formed in FP64 at x; FP64 and MIXED) or 8 + 24 es
+                         (the FP32 J read; MIXED_NOREFINE)
       candidate_cost     24 bytes per observation + the parameters twice"""
     q, n, m = scene.q, scene.n, scene.m
     acc = {k: [] for k in ("chol_flops", "S_lower", "S_padded", "n_seg", "off_pairs", "clusters")}
@@ -272,15 +277,18 @@ def algorithmic_model(scene, maps, es):
     params = m * 72 + n * 24
     model = {
         "residual_jacobian": dict(bound="hbm", bytes=q * (24 + 26 * es) + params,
-                                  clear_bytes=8 * st["S_padded"] * (2 if es == 4 else 1) + 72 * m),
+                                  clear_bytes=8 * st["S_padded"] + 72 * m),
         "points_segments": dict(bound="hbm", bytes=q * (8 + 26 * es) + 72 * st["n_seg"] + 72 * n + 432 * m,
                                 record_bytes=q * 32 * es),
         "schur_assembly": dict(bound="alu", flops=576 * q + 486 * st["off_pairs"],
                                bytes=q * (8 + 26 * es) + 8 * st["S_lower"]),
         "cluster_cholesky": dict(bound="mfma", flops=st["chol_flops"], bytes=16 * st["S_lower"]),
-        "point_backsub": dict(bound="hbm", bytes=q * (8 + 24 * es) + 72 * n),
+        "point_backsub": dict(bound="hbm", bytes=(q * 48 + params if (refine or es == 8) else q * (8 + 24 * es))
+                              + 72 * n),
         "candidate_cost": dict(bound="hbm", bytes=q * 24 + 2 * params),
     }
+    if refine:
+        model["refinement"] = dict(bound="hbm", bytes=q * 48 + params + 72 * m + 16 * st["S_lower"])
     return model, st
 
 
@@ -429,7 +437,7 @@ def main():
     import torch
     import paper_2008_00446_amd as S
 
-    precision = S.STBA_FP64 if args.precision == "fp64" else S.STBA_MIXED
+    precision = {"fp64": S.STBA_FP64, "mixed": S.STBA_MIXED, "mixed_norefine": S.STBA_MIXED_NOREFINE}[args.precision]
     es = 8 if precision == S.STBA_FP64 else 4
     wl = make_workload(args.workload)
     scene = wl.scene
@@ -457,7 +465,7 @@ def main():
     if args.only_timed:
         print(json.dumps(out))
         return
-    model, stats = algorithmic_model(scene, maps[:steps], es)
+    model, stats = algorithmic_model(scene, maps[:steps], es, refine=precision == S.STBA_MIXED)
     phases, names, _, _ = phase_split(S, sol, samples, cam0, pt0, wl.lam0, steps, model)
     out["roofline"] = roofline_of(phases, model, precision == S.STBA_FP64, wl.name)
     out["phases"] = phases
@@ -507,16 +515,19 @@ TAUS = (0.1, 0.01, 0.001)
 
 
 def mixed_leg(S, wl, sol64, samples64, maps, K, warmup, cam0, pt0):
-    """MIXED against FP64 from the same x0 with the same maps.  The target is the
-    FP64 cost after K iterations; MIXED is run until its cost reaches it (up to
-    3K iterations) and the wall time of each to reach it is compared.  The
-    profile at tau = 0.1, 0.01, 0.001 (F_tau = F* + tau (F0 - F*), F* the lower of
-    the two costs after K iterations) is reported beside it."""
+    """The two mixed-precision modes against FP64 from the same x0 with the same
+    maps: STBA_MIXED (FP32 assembly, FP64 factorisation and one FP64 refinement
+    step) and STBA_MIXED_NOREFINE (the same without the refinement).  The target
+    is the FP64 cost after K iterations; each mode is run until its cost reaches
+    it (up to 3K iterations) and the wall times to reach it are compared.  The
+    profile at tau = 0.1, 0.01, 0.001 (F_tau = F* + tau (F0 - F*), F* the lowest
+    of the costs after K iterations) is reported beside it."""
     import torch
-    solm = make_solver(S, wl, S.STBA_MIXED)
     kmax = 3 * K
-    samplesm = [solm.sample(maps[t], alpha=1.0, seed=0, it=t) for t in range(kmax)]
-    runs = {"fp64": (sol64, samples64), "mixed": (solm, samplesm)}
+    runs = {"fp64": (sol64, samples64)}
+    for name, prec in (("mixed", S.STBA_MIXED), ("mixed_norefine", S.STBA_MIXED_NOREFINE)):
+        sol = make_solver(S, wl, prec)
+        runs[name] = (sol, [sol.sample(maps[t], alpha=1.0, seed=0, it=t) for t in range(kmax)])
     hist = {}
     for name, (sol, smp) in runs.items():
         run_iterations(sol, smp, cam0, pt0, wl.lam0, warmup)
@@ -541,9 +552,8 @@ def mixed_leg(S, wl, sol64, samples64, maps, K, warmup, cam0, pt0):
         return int(hit[0]) + 1 if hit.size else None
 
     F_target = float(hist["fp64"][K - 1])
-    n_mixed = first_at_or_below("mixed", F_target)
     t64 = seconds("fp64", K)
-    F_star = float(min(hist["fp64"][K - 1], hist["mixed"][K - 1]))
+    F_star = float(min(h[K - 1] for h in hist.values()))
     profile = []
     for tau in TAUS:
         F_tau = F_star + tau * (F0 - F_star)
@@ -552,22 +562,31 @@ def mixed_leg(S, wl, sol64, samples64, maps, K, warmup, cam0, pt0):
             n = first_at_or_below(name, F_tau)
             row[f"{name}_iterations"] = n
             row[f"{name}_seconds"] = None if n is None else seconds(name, n)
-        row["speedup"] = (row["fp64_seconds"] / row["mixed_seconds"]
-                          if row["fp64_seconds"] and row["mixed_seconds"] else None)
+        for name in ("mixed", "mixed_norefine"):
+            row[f"{name}_speedup"] = (row["fp64_seconds"] / row[f"{name}_seconds"]
+                                      if row["fp64_seconds"] and row[f"{name}_seconds"] else None)
         profile.append(row)
-    tmx = seconds("mixed", K)
+    variants = {}
+    for name in ("mixed", "mixed_norefine"):
+        n = first_at_or_below(name, F_target)
+        tk = seconds(name, K)
+        variants[name] = {
+            "iterations_to_target": n,
+            "seconds_to_target": None if n is None else seconds(name, n),
+            "speedup_at_equal_cost_reduction": None if n is None else t64 / seconds(name, n),
+            "F_after_K": float(hist[name][K - 1]),
+            "minus_fp64_F_after_K_rel": float((hist[name][K - 1] - hist["fp64"][K - 1]) / hist["fp64"][K - 1]),
+            "iter_per_s": K / tk, "obs_per_s": s.q * K / tk,
+        }
     out = {
         "F0": F0, "iterations": K, "F_target": F_target,
-        "mixed_iterations_to_target": n_mixed,
-        "fp64_seconds_to_target": t64,
-        "mixed_seconds_to_target": None if n_mixed is None else seconds("mixed", n_mixed),
-        "speedup_at_equal_cost_reduction": None if n_mixed is None else t64 / seconds("mixed", n_mixed),
-        "fp64_F_after_K": float(hist["fp64"][K - 1]), "mixed_F_after_K": float(hist["mixed"][K - 1]),
-        "mixed_minus_fp64_F_after_K_rel": float((hist["mixed"][K - 1] - hist["fp64"][K - 1]) / hist["fp64"][K - 1]),
-        "fp64_iter_per_s": K / t64, "mixed_iter_per_s": K / tmx, "mixed_obs_per_s": s.q * K / tmx,
-        "profile_tau": profile,
+        "fp64_seconds_to_target": t64, "fp64_iter_per_s": K / t64, "fp64_F_after_K": float(hist["fp64"][K - 1]),
+        # the headline: STBA_MIXED (with its refinement step)
+        "speedup_at_equal_cost_reduction": variants["mixed"]["speedup_at_equal_cost_reduction"],
+        "variants": variants, "profile_tau": profile,
     }
-    del solm
+    for name in ("mixed", "mixed_norefine"):
+        del runs[name]
     return out
 
 
@@ -631,7 +650,7 @@ def cpu_baseline(S, wl, lab, budget_s):
     smallest and median first and then alternating, until about `budget_s`
     seconds.  The per-iteration time is scaled to the whole problem by
     observations (every observation belongs to exactly one cluster).  The
-    GPU's FP64 and MIXED results on the same clusters (S_k, b_k, camera steps,
+    GPU's FP64, MIXED and MIXED_NOREFINE results on the same clusters (S_k, b_k, camera steps,
     steps of points seen only inside the cluster) and the cost F(x0) are
     compared with the oracle's."""
     import psutil
@@ -676,7 +695,7 @@ def cpu_baseline(S, wl, lab, budget_s):
         d = np.sqrt(np.diag(Sk))
         kap.append(float(np.linalg.cond(Sk / np.outer(d, d))))
     errors = {"kappa_scaled_max": max(kap), "kappa_scaled_median": float(np.median(kap))}
-    for name, prec in (("fp64", S.STBA_FP64), ("mixed", S.STBA_MIXED)):
+    for name, prec in (("fp64", S.STBA_FP64), ("mixed", S.STBA_MIXED), ("mixed_norefine", S.STBA_MIXED_NOREFINE)):
         g = _gpu_cluster_results(S, wl, prec, lab, list(refs))
         e = {"S_maxabs_rel": 0.0, "b_rel": 0.0, "dcam_rel": 0.0, "dpt_interior_rel": 0.0,
              "F_x0_rel": abs(g["F"] - F_ref) / F_ref, "status_ok": g["status_ok"]}
@@ -708,13 +727,13 @@ def _rel(a, b):
 
 
 def secondary_leg(S, wl, warmup):
-    """A secondary workload: FP64 and MIXED iterations/s (eager and graph replay)."""
+    """A secondary workload: FP64, MIXED and MIXED_NOREFINE iterations/s (eager and graph replay)."""
     import torch
     K = wl.steps
     maps = draw_maps(S, wl, max(K, warmup))
     out = {"workload": wl.name, "iterations": K, "maps": wl.maps_desc, "cluster_cap": wl.gamma,
            "clusters_mean": float(np.mean([mp.max() + 1 for mp in maps[:K]]))}
-    for name, prec in (("fp64", S.STBA_FP64), ("mixed", S.STBA_MIXED)):
+    for name, prec in (("fp64", S.STBA_FP64), ("mixed", S.STBA_MIXED), ("mixed_norefine", S.STBA_MIXED_NOREFINE)):
         sol, _, _, _, el, st, gips = timed_run(S, wl, prec, maps, K, warmup, graph=True)
         out[name] = {"iter_per_s": K / el, "obs_per_s": wl.scene.q * K / el, "graph_iter_per_s": gips,
                      "F_after_K": st["F"], "accepted": st["n_accept"], "status": st["status"]}

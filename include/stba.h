@@ -49,8 +49,15 @@ extern "C" {
 /* precision of residuals, Jacobians and Schur assembly */
 #define STBA_FP64  0   /* everything in FP64 */
 #define STBA_MIXED 1   /* f, J, Hessian blocks and Schur assembly in FP32 with FP32
-                          accumulation; Cholesky, one refinement step of every
-                          cluster solve, point update and cost in FP64 */
+                          accumulation; Cholesky, point update and cost in FP64,
+                          and one FP64 refinement step of every cluster solve:
+                          dc += S_k^-1 (b - S x) with b - S x formed from J
+                          recomputed in FP64 at x (the FP64 method's S and b,
+                          never the FP32-assembled S_k), the factor that of the
+                          FP32-assembled S_k; the point update (Eq. 15) then
+                          also takes J and its blocks in FP64 */
+#define STBA_MIXED_NOREFINE 2  /* STBA_MIXED without the refinement step: the point
+                          update with the FP32 J */
 
 /* status codes (int32) */
 #define STBA_OK          0
@@ -207,10 +214,11 @@ int stba_build_cluster_rcs(const stba_problem *p, const stba_dims *dims, const s
                            const stba_damping *d, int precision, const void *f, const void *Jc, const void *Jp,
                            stba_rcs *out, void *ws, size_t ws_bytes, hipStream_t stream);
 
-/* Solve every S_k dc_k = b_k by dense FP64 Cholesky (Eq. 13; plus one FP64
- * refinement step in STBA_MIXED, against the copy of S_k that the last
- * stba_build_cluster_rcs wrote beside it in the workspace), then the point step
- * dp_j = C_j^-1 (w_j - sum_o W_o^T dc) with the physical blocks (Eq. 15).
+/* Solve every S_k dc_k = b_k by dense FP64 Cholesky (Eq. 13; plus, in
+ * STBA_MIXED, one FP64 refinement step whose residual is formed from J
+ * recomputed in FP64 at x, with the damping and the segments of the last
+ * stba_build_cluster_rcs), then the point step dp_j = C_j^-1 (w_j - sum_o W_o^T dc)
+ * with the physical blocks (Eq. 15).
  * Jc, Jp: the Jacobian passed to stba_build_cluster_rcs.  dcam [m][9], dpt [n][3]
  * (device, FP64).  cluster_status (device int32 [l], nullable): STBA_OK or
  * STBA_ENOTPD per cluster, or STBA_EHIP if a wait between the wavefronts that
@@ -291,7 +299,10 @@ int stba_lm_step(const stba_problem *p, const stba_dims *dims, const stba_sample
 /* Same as stba_lm_step, recording events[k] before phase k and events[STBA_NUM_PHASES]
  * after the last (host array of STBA_NUM_PHASES + 1 created hipEvent_t) so that a
  * caller can time each kernel of the iteration on `stream`. */
-#define STBA_NUM_PHASES 9
+#define STBA_NUM_PHASES 10   /* clusters, residual_jacobian, points_segments, fill_S,
+                                schur_assembly, cluster_cholesky, refinement (STBA_MIXED
+                                only; empty otherwise), point_backsub, candidate_cost,
+                                accept_update */
 int stba_lm_step_profiled(const stba_problem *p, const stba_dims *dims, const stba_sample *s,
                           stba_lm_state *st, int precision, void *ws, size_t ws_bytes, hipStream_t stream,
                           hipEvent_t *events);

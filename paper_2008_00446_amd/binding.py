@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(PKG, "libstba.so")
 
 STBA_FP64 = 0
 STBA_MIXED = 1
-STBA_NUM_PHASES = 9
+STBA_MIXED_NOREFINE = 2
+STBA_NUM_PHASES = 10
 STATUS_NAMES = {0: "STBA_OK", -1: "STBA_EINVAL", -2: "STBA_ENOTPD", -3: "STBA_ENONFINITE",
                 -4: "STBA_EWORKSPACE", -5: "STBA_EHIP", -6: "STBA_EDATA"}
 

@@ -63,20 +63,51 @@ __device__ inline void camera_project(const double c[9], const double X[3], doub
     pix[1] = c[6] * d * y;
 }
 
-// Pixel plus Jacobian blocks Jc [2][9] and Jp [2][3] (row-major).
-__device__ inline void camera_project_jac(const double c[9], const double X[3], double pix[2],
-                                          double Jc[2][9], double Jp[2][3]) {
+// The camera's part of the projection, independent of the point: R(w) (row-
+// major, 9), the right Jacobian J_r(w) (row-major, 9), t (3), f, k1, k2: 24
+// doubles, formed once per camera where many observations share it.
+constexpr int kCamPre = 24;
+
+__device__ inline void camera_pre(const double c[9], double cp[kCamPre]) {
     const double w[3] = {c[0], c[1], c[2]};
     const double th2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
     const RodCoef k = rodrigues_coefficients(th2);
     double R[3][3];
     rotation_from_vector(w, th2, k, R);
+    // J_r = I - b K + c K^2 = (1 - c th2) I - b K + c w w^T
+    const double bb = k.b, cc = k.c;
+    double Jr[3][3];
+    Jr[0][0] = 1.0 + cc * (w[0] * w[0] - th2);
+    Jr[0][1] = bb * w[2] + cc * w[0] * w[1];
+    Jr[0][2] = -bb * w[1] + cc * w[0] * w[2];
+    Jr[1][0] = -bb * w[2] + cc * w[1] * w[0];
+    Jr[1][1] = 1.0 + cc * (w[1] * w[1] - th2);
+    Jr[1][2] = bb * w[0] + cc * w[1] * w[2];
+    Jr[2][0] = bb * w[1] + cc * w[2] * w[0];
+    Jr[2][1] = -bb * w[0] + cc * w[2] * w[1];
+    Jr[2][2] = 1.0 + cc * (w[2] * w[2] - th2);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            cp[3 * i + j] = R[i][j];
+            cp[9 + 3 * i + j] = Jr[i][j];
+        }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) cp[18 + i] = c[3 + i];
+}
+
+// Pixel plus Jacobian blocks Jc [2][9] and Jp [2][3] (row-major) from the
+// camera's part cp and the point X.
+__device__ inline void project_jac_pre(const double cp[kCamPre], const double X[3], double pix[2], double Jc[2][9],
+                                       double Jp[2][3]) {
+    const double *R = cp, *Jr = cp + 9;
     double P[3];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) P[i] = R[i][0] * X[0] + R[i][1] * X[1] + R[i][2] * X[2] + c[3 + i];
+    for (int i = 0; i < 3; ++i) P[i] = R[3 * i] * X[0] + R[3 * i + 1] * X[1] + R[3 * i + 2] * X[2] + cp[18 + i];
     const double iz = 1.0 / P[2];
     const double x = P[0] * iz, y = P[1] * iz;
-    const double fl = c[6], k1 = c[7], k2 = c[8];
+    const double fl = cp[21], k1 = cp[22], k2 = cp[23];
     const double r2 = x * x + y * y;
     const double d = 1.0 + k1 * r2 + k2 * r2 * r2;
     pix[0] = fl * d * x;
@@ -93,27 +124,13 @@ __device__ inline void camera_project_jac(const double c[9], const double X[3], 
     B[1][0] = A01 * iz;
     B[1][1] = A11 * iz;
     B[1][2] = -(A01 * x + A11 * y) * iz;
-    // J_r = I - b K + c K^2 = (1 - c th2) I - b K + c w w^T
-    double Jr[3][3];
-    {
-        const double bb = k.b, cc = k.c;
-        Jr[0][0] = 1.0 + cc * (w[0] * w[0] - th2);
-        Jr[0][1] = bb * w[2] + cc * w[0] * w[1];
-        Jr[0][2] = -bb * w[1] + cc * w[0] * w[2];
-        Jr[1][0] = -bb * w[2] + cc * w[1] * w[0];
-        Jr[1][1] = 1.0 + cc * (w[1] * w[1] - th2);
-        Jr[1][2] = bb * w[0] + cc * w[1] * w[2];
-        Jr[2][0] = bb * w[1] + cc * w[2] * w[0];
-        Jr[2][1] = -bb * w[0] + cc * w[2] * w[1];
-        Jr[2][2] = 1.0 + cc * (w[2] * w[2] - th2);
-    }
     // [X]x J_r
     double XJ[3][3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        XJ[0][j] = -X[2] * Jr[1][j] + X[1] * Jr[2][j];
-        XJ[1][j] = X[2] * Jr[0][j] - X[0] * Jr[2][j];
-        XJ[2][j] = -X[1] * Jr[0][j] + X[0] * Jr[1][j];
+        XJ[0][j] = -X[2] * Jr[3 + j] + X[1] * Jr[6 + j];
+        XJ[1][j] = X[2] * Jr[j] - X[0] * Jr[6 + j];
+        XJ[2][j] = -X[1] * Jr[j] + X[0] * Jr[3 + j];
     }
     // dP/dw = -R [X]x J_r
     double dPdw[3][3];
@@ -121,7 +138,7 @@ __device__ inline void camera_project_jac(const double c[9], const double X[3], 
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j)
-            dPdw[i][j] = -(R[i][0] * XJ[0][j] + R[i][1] * XJ[1][j] + R[i][2] * XJ[2][j]);
+            dPdw[i][j] = -(R[3 * i] * XJ[0][j] + R[3 * i + 1] * XJ[1][j] + R[3 * i + 2] * XJ[2][j]);
     const double xy[2] = {x, y};
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
@@ -129,12 +146,20 @@ __device__ inline void camera_project_jac(const double c[9], const double X[3], 
         for (int j = 0; j < 3; ++j) {
             Jc[i][j] = B[i][0] * dPdw[0][j] + B[i][1] * dPdw[1][j] + B[i][2] * dPdw[2][j];
             Jc[i][3 + j] = B[i][j];
-            Jp[i][j] = B[i][0] * R[0][j] + B[i][1] * R[1][j] + B[i][2] * R[2][j];
+            Jp[i][j] = B[i][0] * R[j] + B[i][1] * R[3 + j] + B[i][2] * R[6 + j];
         }
         Jc[i][6] = d * xy[i];
         Jc[i][7] = fl * r2 * xy[i];
         Jc[i][8] = fl * r2 * r2 * xy[i];
     }
+}
+
+// Pixel plus Jacobian blocks Jc [2][9] and Jp [2][3] (row-major).
+__device__ inline void camera_project_jac(const double c[9], const double X[3], double pix[2],
+                                          double Jc[2][9], double Jp[2][3]) {
+    double cp[kCamPre];
+    camera_pre(c, cp);
+    project_jac_pre(cp, X, pix, Jc, Jp);
 }
 
 // Robust loss (Sec. 5.1): Huber with scale a on s = ||f_o||^2, rho(s) = s up to

@@ -12,11 +12,13 @@
 //   (c) trailing update A_ij -= L_ip L_jp^T of the lower tiles with
 //       v_mfma_f64_16x16x4_f64; the next panel's column is updated first so
 //       that its diagonal tile is factored while the other waves finish (c);
-//    then the backward solve L^T x = y with the stored W^T (MIXED: k_resid and
-//    k_sweep add the refinement step);
+//    then the backward solve L^T x = y with the stored W^T;
 //  - k_chol_tiles, one wavefront per tile (few clusters): a dataflow over the
-//    tiles with the substitutions, and the MIXED refinement step, in the same
-//    launch (described where it is defined).
+//    tiles with the substitutions in the same launch (described where it is
+//    defined);
+//  - k_chol_team, teams of wavefronts per cluster for maps with many clusters.
+// k_sweep repeats both substitutions with a stored factor (the MIXED
+// refinement step).
 #include "kernels.h"
 
 namespace stba {
@@ -462,9 +464,6 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(int32_t l, const int32_t 
 // blocks, each block vector handed on as soon as it is known:
 //   forward   y_i = W_ii (b_i - sum_{j < i} L_ij y_j),
 //   backward  x_i = W_ii^T (y_i - sum_{j > i} L_ji^T x_j),
-// and with S0 (MIXED) one FP64 refinement step against the assembled matrix:
-//   r_i = b_i - sum_j S0_ij x_j (summed while the x_j arrive),
-//   forward d from r, backward e from d, and dcam = x + e.
 // A block vector goes to the other row workers through memory: its entries
 // start as kEmpty and a reader polls the 32 entries themselves, so a hand-over
 // costs one store and the reader's next poll.  The last wavefront of a cluster
@@ -674,20 +673,19 @@ __device__ inline void publish(double *v, double x, int lane) {
     if (lane < kNB) st_dev(v + lane, x);
 }
 
-// Forward chain, block i: v_i = W_ii (rhs - sum_{j < i} L_ij v_j), published
-// to v (blocks of 32).  Every tile of block row i is final; w from ld_w16<true>.
-// The tile of the next step is loaded while the current v_j is awaited.
-__device__ __forceinline__ double fwd_chain(const double *A, int64_t Np, int i, int r, int hc, double rhs,
+// Backward chain, block i: v_i = W_ii^T (rhs - sum_{j > i} L_ji^T v_j),
+// published to v; every tile is final; w from ld_w16<false>.
+__device__ __forceinline__ double bwd_chain(const double *A, int64_t Np, int T, int i, int r, int hc, double rhs,
                                             const double (&w)[16], double *v, double *zs, int lane,
                                             int32_t *abort_w, bool &ok) {
     const int64_t ri = (int64_t)i * kNB;
     double s = 0.0;
-    if (i > 0) {
+    if (i + 1 < T) {
         double t[16];
-        ld_row16<true>(A, Np, ri + r, hc, t);
-        for (int j = 0; j + 1 < i; ++j) {
+        ld_col16<true>(A, Np, (int64_t)(T - 1) * kNB + hc, ri + r, t);
+        for (int j = T - 1; j > i + 1; --j) {
             double tn[16];
-            ld_row16<true>(A, Np, ri + r, (int64_t)(j + 1) * kNB + hc, tn);
+            ld_col16<true>(A, Np, (int64_t)(j - 1) * kNB + hc, ri + r, tn);
             share32(zs, wait_vec(v + (int64_t)j * kNB, abort_w, ok), lane);
             s += dot16(t, zs + hc);
 #pragma unroll
@@ -695,79 +693,13 @@ __device__ __forceinline__ double fwd_chain(const double *A, int64_t Np, int i, 
         }
         // the last term (the critical one) with no load in flight: global loads
         // complete in order, so one issued before the wait would delay it
-        share32(zs, wait_vec(v + (int64_t)(i - 1) * kNB, abort_w, ok), lane);
-        s += dot16(t, zs + hc);
-    }
-    share32(zs, rhs - halves(s), lane);
-    const double y = halves(dot16(w, zs + hc));
-    publish(v + ri, y, lane);
-    return y;
-}
-
-// Backward chain, block i: v_i = W_ii^T (rhs - sum_{j > i} L_ji^T v_j),
-// published to v; every tile is final; w from ld_w16<false>.  kRes: also
-// res += sum_{j > i} S0_ij v_j, S0_ij = S0_ji^T read from the lower triangle
-// of S0 at A0 (the part of the refinement residual from the blocks below).
-template <bool kRes>
-__device__ __forceinline__ double bwd_chain(const double *A, const double *A0, int64_t Np, int T, int i, int r,
-                                            int hc, double rhs, const double (&w)[16], double *v, double *zs,
-                                            int lane, int32_t *abort_w, bool &ok, double &res) {
-    const int64_t ri = (int64_t)i * kNB;
-    double s = 0.0, vlast = 0.0;
-    if (i + 1 < T) {
-        double t[16];
-        ld_col16<true>(A, Np, (int64_t)(T - 1) * kNB + hc, ri + r, t);
-        for (int j = T - 1; j > i + 1; --j) {
-            double u[16], tn[16];   // S0 is not written by this kernel: loaded at the step
-            if (kRes) ld_col16<false>(A0, Np, (int64_t)j * kNB + hc, ri + r, u);
-            ld_col16<true>(A, Np, (int64_t)(j - 1) * kNB + hc, ri + r, tn);
-            share32(zs, wait_vec(v + (int64_t)j * kNB, abort_w, ok), lane);
-            s += dot16(t, zs + hc);
-            if (kRes) res += dot16(u, zs + hc);
-#pragma unroll
-            for (int m = 0; m < 16; ++m) t[m] = tn[m];
-        }
-        // the last term (the critical one) with no load in flight: global loads
-        // complete in order, so one issued before the wait would delay it; its
-        // S0 term follows the publication of v_i
-        vlast = wait_vec(v + (int64_t)(i + 1) * kNB, abort_w, ok);
-        share32(zs, vlast, lane);
+        share32(zs, wait_vec(v + (int64_t)(i + 1) * kNB, abort_w, ok), lane);
         s += dot16(t, zs + hc);
     }
     share32(zs, rhs - halves(s), lane);
     const double x = halves(dot16(w, zs + hc));
     publish(v + ri, x, lane);
-    if (kRes && i + 1 < T) {
-        double u[16];
-        ld_col16<false>(A0, Np, (int64_t)(i + 1) * kNB + hc, ri + r, u);
-        share32(zs, vlast, lane);
-        res += dot16(u, zs + hc);
-    }
     return x;
-}
-
-// The rest of the refinement residual of block i once x_i is known:
-// res += S0_ii x_i + sum_{j < i} S0_ij x_j (the x_j awaited as they come).
-__device__ __forceinline__ void resid_rest(const double *A0, int64_t Np, int i, int r, int hc, double x,
-                                           const double *xv, double *zs, int lane, int32_t *abort_w, bool &ok,
-                                           double &res) {
-    const int64_t ri = (int64_t)i * kNB;
-    double u[16], un[16];
-#pragma unroll
-    for (int m = 0; m < 16; ++m) {   // S0_ii from its lower triangle
-        const int c = hc + m;
-        u[m] = c <= r ? A0[ri + r + (ri + c) * Np] : A0[ri + c + (ri + r) * Np];
-    }
-    share32(zs, x, lane);
-    res += dot16(u, zs + hc);
-    ld_row16<false>(A0, Np, ri + r, (int64_t)max(i - 1, 0) * kNB + hc, u);
-    for (int j = i - 1; j >= 0; --j) {
-        ld_row16<false>(A0, Np, ri + r, (int64_t)max(j - 1, 0) * kNB + hc, un);
-        share32(zs, wait_vec(xv + (int64_t)j * kNB, abort_w, ok), lane);
-        res += dot16(u, zs + hc);
-#pragma unroll
-        for (int m = 0; m < 16; ++m) u[m] = un[m];
-    }
 }
 
 // Wavefront roles per cluster (wave w of the cluster's wpc wavefronts):
@@ -785,14 +717,14 @@ __device__ __forceinline__ void resid_rest(const double *A0, int64_t Np, int i, 
 // wavefronts at tt + tmax + 1], tt = tmax (tmax + 1) / 2; diagonal tile flags
 // are 1 (final) or 2 (final, pivot failed).  After the last cluster: the abort
 // word, then the count of finished clusters.  Block vectors per cluster (yx):
-// y, x, d, e, tmax blocks of 32 each.
-constexpr int kVecSets = 4;
+// y and x, tmax blocks of 32 each.
+constexpr int kVecSets = 2;
 
 // One wavefront's part; false if one of its waits failed.
 __device__ __forceinline__ bool chol_tiles_wave(int w, int k, int32_t tmax, int32_t fpc, const int32_t *cl_n,
                                                 const int32_t *cl_Np, const int64_t *S_off, const int32_t *cl_start,
                                                 const int32_t *cl_cams, double *S, const double *b, double *dcam,
-                                                int32_t *flags, int32_t l, double *yx, const double *S0,
+                                                int32_t *flags, int32_t l, double *yx,
                                                 double (*Wi)[kNB + 1], double (*Ls)[kNB + 1], double *zs) {
     const int lane = threadIdx.x;
     const int64_t Np = cl_Np[k];
@@ -894,7 +826,7 @@ __device__ __forceinline__ bool chol_tiles_wave(int w, int k, int32_t tmax, int3
     const int c0 = cl_start[k];
     const int64_t vs = (int64_t)tmax * kNB;
     double *yv = yx + (int64_t)k * kVecSets * vs;
-    double *xv = yv + vs, *dv = xv + vs, *ev = dv + vs;
+    double *xv = yv + vs;
     const int64_t row = ri + r;
     const int64_t drow = row < N ? 9 * (int64_t)cl_cams[c0 + row / 9] + row % 9 : 0;
     const double bi = row < N ? b[drow] : 0.0;
@@ -922,21 +854,8 @@ __device__ __forceinline__ bool chol_tiles_wave(int w, int k, int32_t tmax, int3
     ok &= wait_flag(fl + tile_ix(T - 1, T - 1), abort_w) != 0;
     double wb[16];
     ld_w16<false>(A, Np, ri, r, hc, wb);
-    double res = 0.0;
-    if (S0 == nullptr) {
-        const double x = bwd_chain<false>(A, nullptr, Np, T, i, r, hc, y, wb, xv, zs, lane, abort_w, ok, res);
-        if (lane < kNB && row < N) dcam[drow] = x;
-        return ok;
-    }
-    // MIXED: r_i = b_i - sum_j S0_ij x_j, then L L^T e = r and dcam = x + e
-    const double *A0 = S0 + S_off[k];
-    const double x = bwd_chain<true>(A, A0, Np, T, i, r, hc, y, wb, xv, zs, lane, abort_w, ok, res);
-    double wf[16];   // loaded again, in flight while the residual completes
-    ld_w16<true>(A, Np, ri, r, hc, wf);
-    resid_rest(A0, Np, i, r, hc, x, xv, zs, lane, abort_w, ok, res);
-    const double d = fwd_chain(A, Np, i, r, hc, bi - halves(res), wf, dv, zs, lane, abort_w, ok);
-    const double e = bwd_chain<false>(A, nullptr, Np, T, i, r, hc, d, wb, ev, zs, lane, abort_w, ok, res);
-    if (lane < kNB && row < N) dcam[drow] = x + e;
+    const double x = bwd_chain(A, Np, T, i, r, hc, y, wb, xv, zs, lane, abort_w, ok);
+    if (lane < kNB && row < N) dcam[drow] = x;
     return ok;
 }
 
@@ -944,7 +863,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void
     int32_t wpc, int32_t tmax, int32_t fpc, const int32_t *__restrict__ cl_n, const int32_t *__restrict__ cl_Np,
     const int64_t *__restrict__ S_off, const int32_t *__restrict__ cl_start, const int32_t *__restrict__ cl_cams,
     double *__restrict__ S, const double *__restrict__ b, double *__restrict__ dcam, int32_t *__restrict__ cl_status,
-    int32_t *flags, int32_t l, double *yx, const double *__restrict__ S0, int32_t xcd_major) {
+    int32_t *flags, int32_t l, double *yx, int32_t xcd_major) {
     __shared__ double Wi[kNB][kNB + 1];
     __shared__ double Ls[kNB][kNB + 1];
     __shared__ __align__(16) double zs[2 * kNB];
@@ -965,7 +884,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void
         w = (int)(blockIdx.x - (unsigned)k * (unsigned)wpc);
     }
     const bool ok = chol_tiles_wave(w, k, tmax, fpc, cl_n, cl_Np, S_off, cl_start, cl_cams, S, b, dcam, flags, l, yx,
-                                    S0, Wi, Ls, zs);
+                                    Wi, Ls, zs);
     // every wavefront of the grid ends here
     const int tt = tmax * (tmax + 1) / 2;
     int32_t *fl = flags + (int64_t)k * fpc;
@@ -1025,8 +944,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void
 // Column col of a tile occupies 256 bytes of its slot, its 16-byte part q (rows
 // 2q, 2q + 1) at position (q + col) mod 16: the 32 lanes that read one row of 32
 // columns, or 32 rows of one column, meet at most two to a bank.
-// Used for the MIXED refinement step after the one-workgroup-per-cluster
-// factorisation: dcam += backward(forward(r)), r = b - S0 x from k_resid.
+// Used for the MIXED refinement step after any of the factorisations:
+// dcam += backward(forward(r)) with the residual r in camera order.
 // ---------------------------------------------------------------------------
 constexpr int kSwThreads = 1024;
 constexpr int kRing = kSwThreads / 64;             // one slot per wavefront
@@ -1139,8 +1058,7 @@ __global__ __launch_bounds__(kSwThreads) void k_sweep(const int32_t *__restrict_
                                                       const int32_t *__restrict__ cl_start,
                                                       const int32_t *__restrict__ cl_cams,
                                                       const double *__restrict__ S,
-                                                      const double *__restrict__ rhs, int32_t rstride,
-                                                      double *__restrict__ dcam) {
+                                                      const double *__restrict__ rhs, double *__restrict__ dcam) {
     __shared__ __align__(16) char ring[kRing * kTileBytes];
     __shared__ double xb[kNB];
     extern __shared__ double z[];   // Np
@@ -1158,7 +1076,8 @@ __global__ __launch_bounds__(kSwThreads) void k_sweep(const int32_t *__restrict_
     char *slot = ring + w * kTileBytes;
     int mine = w;   // the tile this wavefront has in flight (or has landed)
     if (mine < ntiles) sw_issue(A, Np, T, mine, slot, lane);
-    for (int i = tid; i < Np; i += kSwThreads) z[i] = rhs[(int64_t)k * rstride + i];
+    for (int i = tid; i < Np; i += kSwThreads)
+        z[i] = i < N ? rhs[9 * (int64_t)cl_cams[c0 + i / 9] + i % 9] : 0.0;
     // segments: (sweep, step s, tiles [k0, k1) of the step).  One barrier between
     // segments: it publishes the previous segment's results and its end of use of
     // the ring slots, and (after the owners' waits) the landing of this one's tiles.
@@ -1201,61 +1120,6 @@ __global__ __launch_bounds__(kSwThreads) void k_sweep(const int32_t *__restrict_
     }
 }
 
-
-// MIXED refinement residual r = b - S0 x for 32 rows of one cluster per
-// workgroup (x = the current dcam); S0 is symmetric with its lower triangle
-// stored.  Row i takes sum_{j <= i} S0(i, j) x_j along row i (32 rows of one
-// column at a time: consecutive addresses) plus sum_{j > i} S0(j, i) x_j down
-// column i (one wavefront per 8 columns, lanes down the column); every sum in
-// a fixed order.
-__global__ __launch_bounds__(256) void k_resid(int32_t nrb, const int32_t *__restrict__ cl_n,
-                                               const int32_t *__restrict__ cl_Np,
-                                               const int64_t *__restrict__ S_off,
-                                               const int32_t *__restrict__ cl_start,
-                                               const int32_t *__restrict__ cl_cams,
-                                               const double *__restrict__ S0, const double *__restrict__ b,
-                                               const double *__restrict__ dcam, double *__restrict__ r,
-                                               int32_t rstride) {
-    extern __shared__ double smem[];
-    double *x = smem;                // Np
-    __shared__ double red[8][kNB];
-    const int k = (int)(blockIdx.x / (unsigned)nrb);
-    const int rb = (int)(blockIdx.x - (unsigned)k * (unsigned)nrb);
-    const int nk = cl_n[k];
-    const int64_t Np = cl_Np[k];
-    if (nk == 0 || (int64_t)rb * kNB >= Np) return;
-    const int N = 9 * nk;
-    const int c0 = cl_start[k];
-    const int tid = threadIdx.x;
-    for (int i = tid; i < Np; i += 256) x[i] = (i < N) ? dcam[9 * (int64_t)cl_cams[c0 + i / 9] + i % 9] : 0.0;
-    __syncthreads();
-    const double *A0 = S0 + S_off[k];
-    const int rr = tid & (kNB - 1), g = tid >> 5;
-    const int64_t i = (int64_t)rb * kNB + rr;
-    double s0 = 0.0;
-    for (int64_t j = g; j <= i; j += 8) s0 = fma(A0[i + j * Np], x[j], s0);   // row i, columns j <= i
-    red[g][rr] = s0;
-    // column part: wavefront v takes columns rb*32 + 8v .. + 7
-    __shared__ double colp[kNB];
-    const int v = tid >> 6, lane = tid & 63;
-    for (int cc = 0; cc < 8; ++cc) {
-        const int64_t ic = (int64_t)rb * kNB + 8 * v + cc;
-        double s1 = 0.0;
-        for (int64_t j = ic + 1 + lane; j < Np; j += 64) s1 = fma(A0[j + ic * Np], x[j], s1);
-#pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) s1 += __shfl_xor(s1, d, 64);
-        if (lane == 0) colp[8 * v + cc] = s1;
-    }
-    __syncthreads();
-    if (tid < kNB) {
-        double s = colp[tid];
-#pragma unroll
-        for (int gg = 0; gg < 8; ++gg) s += red[gg][tid];
-        const int64_t row = (int64_t)rb * kNB + tid;
-        const double bi = row < N ? b[9 * (int64_t)cl_cams[c0 + row / 9] + row % 9] : 0.0;
-        r[(int64_t)k * rstride + row] = bi - s;
-    }
-}
 
 // ---------------------------------------------------------------------------
 // Team factorisation for maps with many clusters (when one wavefront per tile
@@ -1910,8 +1774,8 @@ int chol_tile_layout(int32_t l, int32_t max_Np, int32_t *wpc, int32_t *tmax, int
 
 hipError_t launch_chol(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, const int64_t *S_off,
                        const int32_t *cl_start, const int32_t *cl_cams, double *S, const double *b, double *dcam,
-                       int32_t *cl_status, int32_t max_Np, int32_t *flags, double *yx, const double *S0,
-                       double *rbuf, const CholTeam *team, hipStream_t st) {
+                       int32_t *cl_status, int32_t max_Np, int32_t *flags, double *yx, const CholTeam *team,
+                       hipStream_t st) {
     int32_t wpc = 0, tmax = 0, fpc = 0, xcd = 0;
     // with the number of clusters on the device the tile grid cannot be sized
     if (team != nullptr && (team->force || team->l_on_device)) goto team_path;
@@ -1920,7 +1784,7 @@ hipError_t launch_chol(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, con
         // workspace was prepared and again at the end of every factorisation
         const int64_t blocks = xcd ? 8 * (((int64_t)l + 7) / 8) * wpc : (int64_t)l * wpc;
         k_chol_tiles<<<(unsigned)blocks, 64, 0, st>>>(wpc, tmax, fpc, cl_n, cl_Np, S_off, cl_start, cl_cams, S, b,
-                                                     dcam, cl_status, flags, l, yx, S0, xcd);
+                                                     dcam, cl_status, flags, l, yx, xcd);
         return hipGetLastError();
     }
 team_path:
@@ -1950,22 +1814,12 @@ team_path:
                 k_chol<<<(unsigned)l, kCholThreads, shmem, st>>>(l, cl_n, cl_Np, S_off, cl_start, cl_cams, S, b, dcam,
                                                                  cl_status, max_Np, team->flags + team->abort_at + 2);
             }
-            if (S0) {
-                const hipError_t e = hipGetLastError();
-                if (e != hipSuccess) return e;
-                return launch_refine(l, cl_n, cl_Np, S_off, cl_start, cl_cams, S, S0, b, dcam, rbuf, max_Np, st);
-            }
             return hipGetLastError();
         }
     }
     const size_t shmem = sizeof(double) * (2 * (size_t)kNB * (kNB + 1) + 2 * kNB + (size_t)max_Np + kCholThreads + kNB);
     k_chol<<<(unsigned)l, kCholThreads, shmem, st>>>(l, cl_n, cl_Np, S_off, cl_start, cl_cams, S, b, dcam, cl_status,
                                                      max_Np, nullptr);
-    if (S0) {
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        return launch_refine(l, cl_n, cl_Np, S_off, cl_start, cl_cams, S, S0, b, dcam, rbuf, max_Np, st);
-    }
     return hipGetLastError();
 }
 
@@ -1981,15 +1835,12 @@ hipError_t launch_clear_chol_flags(int32_t *flags, double *yx, const CholTeam *t
     return hipGetLastError();
 }
 
-hipError_t launch_refine(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, const int64_t *S_off,
-                         const int32_t *cl_start, const int32_t *cl_cams, const double *S, const double *S0,
-                         const double *b, double *dcam, double *rbuf, int32_t max_Np, hipStream_t st) {
-    const int32_t nrb = max_Np / kNB;
-    k_resid<<<(unsigned)((int64_t)l * nrb), 256, sizeof(double) * (size_t)max_Np, st>>>(
-        nrb, cl_n, cl_Np, S_off, cl_start, cl_cams, S0, b, dcam, rbuf, max_Np);
+hipError_t launch_sweep(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, const int64_t *S_off,
+                        const int32_t *cl_start, const int32_t *cl_cams, const double *S, const double *r,
+                        double *dcam, int32_t max_Np, hipStream_t st) {
     if (kSwStaticLds + sizeof(double) * (size_t)max_Np > 160 * 1024) return hipErrorInvalidConfiguration;
-    k_sweep<<<(unsigned)l, kSwThreads, sizeof(double) * (size_t)max_Np, st>>>(
-        cl_n, cl_Np, S_off, cl_start, cl_cams, S, rbuf, max_Np, dcam);
+    k_sweep<<<(unsigned)l, kSwThreads, sizeof(double) * (size_t)max_Np, st>>>(cl_n, cl_Np, S_off, cl_start, cl_cams,
+                                                                               S, r, dcam);
     return hipGetLastError();
 }
 

@@ -272,10 +272,7 @@ __global__ __launch_bounds__(256) void k_rj(int64_t q, const double *__restrict_
         int64_t total = z.S_off[z.l];
         if (total > z.S_cap) total = z.S_cap;
         const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
-            z.S[i] = 0.0;
-            if (z.S0 != nullptr) z.S0[i] = 0.0;
-        }
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) z.S[i] = 0.0;
         for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < z.nb; i += stride) z.b[i] = 0.0;
     }
     if (need_jac != nullptr && need_jac[0] == 0) return;
@@ -392,6 +389,41 @@ template <typename T>
 __device__ inline void load_jp(const T *Jp, int64_t o, double jp[6]) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) jp[k] = (double)Jp[6 * o + k];
+}
+
+// FP64 residual and Jacobian rows of observation o (camera part cp of
+// camera_pre, point j) at x, weighted as the residual kernel weights them
+// (Huber when huber > 0): f [2], jc [2][9] row-major as J_c is stored, jp
+// [2][3] as J_p.
+__device__ inline void obs_fj64(const double cp[kCamPre], const double *__restrict__ pt,
+                                const double *__restrict__ uv, double huber, int32_t j, int64_t o, double f[2],
+                                double jc[18], double jp[6]) {
+    const double X[3] = {pt[3 * (int64_t)j], pt[3 * (int64_t)j + 1], pt[3 * (int64_t)j + 2]};
+    double pix[2], a[2][9], b[2][3];
+    project_jac_pre(cp, X, pix, a, b);
+    const double f0 = pix[0] - uv[2 * o], f1 = pix[1] - uv[2 * o + 1];
+    const double rw = huber_root_weight(f0 * f0 + f1 * f1, huber);
+    f[0] = rw * f0;
+    f[1] = rw * f1;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) jc[9 * r + k] = rw * a[r][k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) jp[3 * r + k] = rw * b[r][k];
+    }
+}
+
+// the same from camera i's parameters (9 loads; forming the camera part again
+// costs less than gathering it from memory per observation)
+__device__ inline void obs_fj64(const double *__restrict__ cam, const double *__restrict__ pt,
+                                const double *__restrict__ uv, double huber, int32_t i, int32_t j, int64_t o,
+                                double f[2], double jc[18], double jp[6]) {
+    double c[9], cp[kCamPre];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) c[k] = cam[9 * (int64_t)i + k];
+    camera_pre(c, cp);
+    obs_fj64(cp, pt, uv, huber, j, o, f, jc, jp);
 }
 
 // ---------------------------------------------------------------------------
@@ -714,16 +746,13 @@ __global__ void k_point_groups(int32_t n, const int64_t *__restrict__ pt_off, in
     if (jj == 0) grp_first[ngroups] = n;
 }
 
-// zero S (all clusters), S0 (if given) and b
-__global__ __launch_bounds__(256) void k_zero_S(double *S, double *S0, double *b, int32_t m, const int64_t *S_off,
-                                                int32_t l, int64_t S_cap) {
+// zero S (all clusters) and b
+__global__ __launch_bounds__(256) void k_zero_S(double *S, double *b, int32_t m, const int64_t *S_off, int32_t l,
+                                                int64_t S_cap) {
     int64_t total = S_off[l];
     if (total > S_cap) total = S_cap;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
-        S[i] = 0.0;
-        if (S0 != nullptr) S0[i] = 0.0;
-    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) S[i] = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 9 * (int64_t)m; i += stride) b[i] = 0.0;
 }
 
@@ -1007,7 +1036,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         if (nch == 1) {
             const int64_t at0 = S_off[kr] + 9 * (int64_t)cam_local[r] + (9 * (int64_t)cam_local[c] + slot) * Np;
             double *colp = S + at0;
-            double *colp0 = ch.S0 != nullptr ? ch.S0 + at0 : nullptr;   // MIXED: the copy kept for refinement
             for (int i = i0; i < 5; ++i) {
                 const int e = e0 + i;
                 double v = (double)col[i];
@@ -1017,7 +1045,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                     v = -v;
                 }
                 colp[e] = v;
-                if (colp0 != nullptr) colp0[e] = v;
             }
             if (diag && slot == 0)
                 for (int i = i0; i < 5; ++i) b[9 * (int64_t)r + e0 + i] = -(double)rb[i];
@@ -1051,11 +1078,7 @@ __global__ __launch_bounds__(128) void k_schur_reduce(SchurChunks ch, const int6
     for (int32_t k = blockIdx.x; k < l; k += gridDim.x) {
         const int64_t Np = cl_Np[k];
         double *A = S + S_off[k];
-        double *A0 = ch.S0 != nullptr ? ch.S0 + S_off[k] : nullptr;
-        for (int64_t i = 9 * (int64_t)cl_n[k] + t; i < Np; i += blockDim.x) {
-            A[i + i * Np] = 1.0;
-            if (A0 != nullptr) A0[i + i * Np] = 1.0;
-        }
+        for (int64_t i = 9 * (int64_t)cl_n[k] + t; i < Np; i += blockDim.x) A[i + i * Np] = 1.0;
     }
     for (int64_t bk = blockIdx.x; bk < nb; bk += gridDim.x) {
         const int64_t c0 = ch.blk_chunk_off[bk];
@@ -1080,7 +1103,6 @@ __global__ __launch_bounds__(128) void k_schur_reduce(SchurChunks ch, const int6
             }
             const int64_t at0 = S_off[kr] + 9 * cam_local[r] + e + (9 * (int64_t)cam_local[c] + k) * Np;
             S[at0] = diag ? v : -v;
-            if (ch.S0 != nullptr) ch.S0[at0] = diag ? v : -v;
         } else {
             const int e = t - 81;
             double v = 0.0;
@@ -1094,27 +1116,42 @@ __global__ __launch_bounds__(128) void k_schur_reduce(SchurChunks ch, const int6
 // a6: point update with the physical blocks (Eq. 15):
 //   dp_j = V*_j^-1 (w_j - sum_o J_p,o^T J_c,o dc_{i_o}).  One thread per point.
 // ---------------------------------------------------------------------------
-template <typename T>
+// kFp64J: J_c, J_p formed in FP64 at x (X: cam, pt, uv, huber) instead of
+// read from Jc / Jp.
+struct AtX {
+    const double *cam, *pt, *uv;
+    double huber;
+};
+
+template <typename T, bool kFp64J>
 __global__ __launch_bounds__(256) void k_backsub(int32_t n, const int64_t *__restrict__ pt_off,
                                                  const int32_t *__restrict__ obs_cam, const T *__restrict__ Jc,
                                                  const T *__restrict__ Jp, const double *__restrict__ Vinv,
                                                  const double *__restrict__ wph, const double *__restrict__ dcam,
-                                                 double *__restrict__ dpt) {
+                                                 double *__restrict__ dpt, AtX X) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     double g[3] = {wph[3 * j], wph[3 * j + 1], wph[3 * j + 2]};
     for (int64_t o = pt_off[j]; o < pt_off[j + 1]; ++o) {
         const double *dc = dcam + 9 * (int64_t)obs_cam[o];
-        const T *jc = Jc + 18 * o;
+        double jc[18], jp[6];
+        if (kFp64J) {
+            double f[2];
+            obs_fj64(X.cam, X.pt, X.uv, X.huber, obs_cam[o], (int32_t)j, o, f, jc, jp);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 18; ++k) jc[k] = (double)Jc[18 * o + k];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) jp[k] = (double)Jp[6 * o + k];
+        }
         double t0 = 0.0, t1 = 0.0;
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            t0 += (double)jc[k] * dc[k];
-            t1 += (double)jc[9 + k] * dc[k];
+            t0 += jc[k] * dc[k];
+            t1 += jc[9 + k] * dc[k];
         }
-        const T *jp = Jp + 6 * o;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) g[k] -= (double)jp[k] * t0 + (double)jp[3 + k] * t1;
+        for (int k = 0; k < 3; ++k) g[k] -= jp[k] * t0 + jp[3 + k] * t1;
     }
     double Vi[6];
 #pragma unroll
@@ -1129,7 +1166,7 @@ __global__ __launch_bounds__(256) void k_backsub(int32_t n, const int64_t *__res
 // at most 64 observations per wavefront): lane o forms J_p,o^T (J_c,o dc) of its
 // camera, and the first lane of each point subtracts its point's terms from w_j
 // in observation order (the order of k_backsub), then dp_j = V*_j^-1 (w_j - ...).
-template <typename T>
+template <typename T, bool kFp64J>
 __global__ __launch_bounds__(64 * kPtWaves) void k_backsub_obs(int64_t ngroups, const int32_t *__restrict__ grp_first,
                                                                const int64_t *__restrict__ pt_off,
                                                                const int32_t *__restrict__ obs_pt,
@@ -1137,7 +1174,8 @@ __global__ __launch_bounds__(64 * kPtWaves) void k_backsub_obs(int64_t ngroups, 
                                                                const T *__restrict__ Jc, const T *__restrict__ Jp,
                                                                const double *__restrict__ Vinv,
                                                                const double *__restrict__ wph,
-                                                               const double *__restrict__ dcam, double *__restrict__ dpt) {
+                                                               const double *__restrict__ dcam, double *__restrict__ dpt,
+                                                               AtX X) {
     __shared__ double sT[kPtWaves][3][64];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -1155,10 +1193,15 @@ __global__ __launch_bounds__(64 * kPtWaves) void k_backsub_obs(int64_t ngroups, 
     const int32_t j = obs_pt[a];
     const int32_t cam = obs_cam[a];
     double jc[18], jp[6];
+    if (kFp64J) {
+        double f[2];
+        obs_fj64(X.cam, X.pt, X.uv, X.huber, cam, j, a, f, jc, jp);
+    } else {
 #pragma unroll
-    for (int k = 0; k < 18; ++k) jc[k] = (double)Jc[18 * a + k];
+        for (int k = 0; k < 18; ++k) jc[k] = (double)Jc[18 * a + k];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) jp[k] = (double)Jp[6 * a + k];
+        for (int k = 0; k < 6; ++k) jp[k] = (double)Jp[6 * a + k];
+    }
     const double *dc = dcam + 9 * (int64_t)cam;
     double t0 = 0.0, t1 = 0.0;
 #pragma unroll
@@ -1187,6 +1230,256 @@ __global__ __launch_bounds__(64 * kPtWaves) void k_backsub_obs(int64_t ngroups, 
     sym3_mul(Vi, gv, d);
 #pragma unroll
     for (int k = 0; k < 3; ++k) dpt[3 * (int64_t)j + k] = d[k];
+}
+
+// ---------------------------------------------------------------------------
+// MIXED: the residual of one FP64 refinement step of every cluster solve
+// (Eq. 13), r = b - S x with the S and b of the FP64 method, taken from J
+// recomputed in FP64 at x and never from the FP32-assembled S.  With the
+// virtual-point blocks C_s = V_s + lambda diag(V_s), the point gradient w'_s
+// (corrected when lambda >= lambda_corr, Sec. 4.3), B = U + lambda diag(U) and
+// E the camera / virtual-point coupling (Eq. 10),
+//   b - S x = (v - B x) - E C^-1 (w' - E^T x) = J_c^T e - lambda diag(U) x,
+//   y_s = C_s^-1 (w'_s - sum_{o in s} J_p,o^T J_c,o x_{i_o}),
+//   e_o = -(f_o + J_c,o x_{i_o} + J_p,o y_{s_o}),
+// i.e. e is the linearised residual of the step with every virtual point at
+// its own optimum y.  Part 1 (per point, segments from seg_head): y_s and e_o;
+// the point's first lane also writes the FP64 V*_j^-1 and w_j that the point
+// update (Eq. 15) then uses.  Part 2 (one wavefront per camera over the
+// camera's observations, fixed order): r_i.
+// ---------------------------------------------------------------------------
+__device__ inline void refine_contrib(const double f[2], const double jc[18], const double jp[6], const double *dc,
+                                      double &t0, double &t1, double cv[12]) {
+    t0 = 0.0;
+    t1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        t0 += jc[k] * dc[k];
+        t1 += jc[9 + k] * dc[k];
+    }
+    cv[0] = jp[0] * jp[0] + jp[3] * jp[3];
+    cv[1] = jp[0] * jp[1] + jp[3] * jp[4];
+    cv[2] = jp[0] * jp[2] + jp[3] * jp[5];
+    cv[3] = jp[1] * jp[1] + jp[4] * jp[4];
+    cv[4] = jp[1] * jp[2] + jp[4] * jp[5];
+    cv[5] = jp[2] * jp[2] + jp[5] * jp[5];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        cv[6 + k] = -(jp[k] * f[0] + jp[3 + k] * f[1]);   // -J_p^T f
+        cv[9 + k] = jp[k] * t0 + jp[3 + k] * t1;          // J_p^T J_c x
+    }
+}
+
+// y_s from the segment sums (Vs, ws, zs) and, for the correction, the point's (V, w)
+__device__ inline void refine_segment_step(const double V[6], const double w[3], const double Vs[6],
+                                           const double ws_in[3], const double zs[3], double lam, bool corr,
+                                           double y[3]) {
+    double ws[3] = {ws_in[0], ws_in[1], ws_in[2]};
+    if (corr) {
+        ws[0] = Vs[0] * w[0] / V[0];
+        ws[1] = Vs[3] * w[1] / V[3];
+        ws[2] = Vs[5] * w[2] / V[5];
+    }
+    const double Vd[6] = {Vs[0] * (1.0 + lam), Vs[1], Vs[2], Vs[3] * (1.0 + lam), Vs[4], Vs[5] * (1.0 + lam)};
+    const Chol3 c = chol3(Vd);
+    double Vi[6];
+    chol3_inverse(c, Vi);
+    const double g[3] = {ws[0] - zs[0], ws[1] - zs[1], ws[2] - zs[2]};
+    sym3_mul(Vi, g, y);
+}
+
+__device__ inline void refine_point_blocks(const double V[6], const double w[3], double lam, double *Vinv_j,
+                                           double *wph_j) {
+    const double Vd[6] = {V[0] * (1.0 + lam), V[1], V[2], V[3] * (1.0 + lam), V[4], V[5] * (1.0 + lam)};
+    const Chol3 c = chol3(Vd);
+    double Vi[6];
+    chol3_inverse(c, Vi);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) Vinv_j[k] = Vi[k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) wph_j[k] = w[k];
+}
+
+__device__ inline void refine_write_e(const double f[2], double t0, double t1, const double jp[6], const double y[3],
+                                      double *e_o) {
+    e_o[0] = -(f[0] + t0 + (jp[0] * y[0] + jp[1] * y[1] + jp[2] * y[2]));
+    e_o[1] = -(f[1] + t1 + (jp[3] * y[0] + jp[4] * y[1] + jp[5] * y[2]));
+}
+
+// Part 1, one lane per observation in the groups of k_points_obs.
+__global__ __launch_bounds__(64 * kPtWaves) void k_refine_obs(
+    int64_t ngroups, const int32_t *__restrict__ grp_first, const int64_t *__restrict__ pt_off,
+    const int32_t *__restrict__ obs_pt, const int32_t *__restrict__ obs_cam, const double *__restrict__ cam,
+    const double *__restrict__ pt, const double *__restrict__ uv, double huber, const int32_t *__restrict__ seg_head,
+    const double *__restrict__ lam2, const double *__restrict__ dcam, double *__restrict__ e,
+    double *__restrict__ Vinv, double *__restrict__ wph) {
+    __shared__ double sV[kPtWaves][12][64];
+    __shared__ int32_t sHead[kPtWaves][64];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int64_t g = (int64_t)blockIdx.x * kPtWaves + wv;
+    if (g >= ngroups) return;
+    const int32_t pa = grp_first[g];
+    int32_t pb = grp_first[g + 1];
+    if (pb < 0) pb = grp_first[ngroups];
+    if (pa < 0 || pb <= pa) return;
+    const int64_t o0 = pt_off[pa], o1 = pt_off[pb];
+    if (o1 - o0 > 64 || o1 <= o0) return;   // reported by k_points_obs
+    const int cnt = (int)(o1 - o0);
+    const bool act = lane < cnt;
+    const int64_t a = o0 + (act ? lane : 0);
+    const int32_t j = obs_pt[a];
+    const int32_t ci = obs_cam[a];
+    double f[2], jc[18], jp[6];
+    obs_fj64(cam, pt, uv, huber, ci, j, a, f, jc, jp);
+    double t0, t1, cv[12];
+    refine_contrib(f, jc, jp, dcam + 9 * (int64_t)ci, t0, t1, cv);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) sV[wv][k][lane] = act ? cv[k] : 0.0;
+    // the segment's head is its first observation, in this point and so in this group
+    int head = act ? (int)(seg_head[a] - o0) : lane;
+    if (head < 0 || head > lane) head = lane;
+    sHead[wv][lane] = head;
+    const int32_t jprev = __shfl(j, lane > 0 ? lane - 1 : 0, 64);
+    const uint64_t starts = __ballot(act && (lane == 0 || j != jprev));
+    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+    const uint64_t after = starts & ~upto & (cnt >= 64 ? ~0ull : ((1ull << cnt) - 1));
+    const int first = act ? 63 - __builtin_clzll(starts & upto) : lane;
+    const int last = act ? (after != 0 ? __builtin_ctzll(after) : cnt) : lane + 1;
+    __syncwarp();
+    // point sums (V_j, w_j) and segment sums in observation order
+    double V[6] = {0, 0, 0, 0, 0, 0}, w[3] = {0, 0, 0}, Vs[6] = {0, 0, 0, 0, 0, 0}, ws[3] = {0, 0, 0},
+           zs[3] = {0, 0, 0};
+    for (int b = first; b < last; ++b) {
+        const bool mine = sHead[wv][b] == head;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const double x = sV[wv][k][b];
+            V[k] += x;
+            if (mine) Vs[k] += x;
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double x = sV[wv][6 + k][b];
+            w[k] += x;
+            if (mine) {
+                ws[k] += x;
+                zs[k] += sV[wv][9 + k][b];
+            }
+        }
+    }
+    if (!act) return;
+    const double lam = lam2[0];
+    const bool corr = lam >= lam2[1];
+    if (lane == first) refine_point_blocks(V, w, lam, Vinv + 6 * (int64_t)j, wph + 3 * (int64_t)j);
+    double y[3];
+    refine_segment_step(V, w, Vs, ws, zs, lam, corr, y);
+    refine_write_e(f, t0, t1, jp, y, e + 2 * a);
+}
+
+// Part 1, one thread per point (points too long for the groups); J recomputed
+// on each pass over the point's observations.
+__global__ __launch_bounds__(64) void k_refine_pt(int32_t n, const int64_t *__restrict__ pt_off,
+                                                  const int32_t *__restrict__ obs_cam, const double *__restrict__ cam,
+                                                  const double *__restrict__ pt, const double *__restrict__ uv,
+                                                  double huber, const int32_t *__restrict__ seg_head,
+                                                  const double *__restrict__ lam2, const double *__restrict__ dcam,
+                                                  double *__restrict__ e, double *__restrict__ Vinv,
+                                                  double *__restrict__ wph) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const double lam = lam2[0];
+    const bool corr = lam >= lam2[1];
+    const int64_t p0 = pt_off[j], p1 = pt_off[j + 1];
+    double V[6] = {0, 0, 0, 0, 0, 0}, w[3] = {0, 0, 0};
+    for (int64_t a = p0; a < p1; ++a) {
+        double f[2], jc[18], jp[6], t0, t1, cv[12];
+        const int32_t ci = obs_cam[a];
+        obs_fj64(cam, pt, uv, huber, ci, (int32_t)j, a, f, jc, jp);
+        refine_contrib(f, jc, jp, dcam + 9 * (int64_t)ci, t0, t1, cv);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) V[k] += cv[k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) w[k] += cv[6 + k];
+    }
+    refine_point_blocks(V, w, lam, Vinv + 6 * j, wph + 3 * j);
+    for (int64_t h = p0; h < p1; ++h) {
+        if (seg_head[h] != (int32_t)h) continue;
+        double Vs[6] = {0, 0, 0, 0, 0, 0}, ws[3] = {0, 0, 0}, zs[3] = {0, 0, 0};
+        for (int64_t a = h; a < p1; ++a) {
+            if (seg_head[a] != (int32_t)h) continue;
+            double f[2], jc[18], jp[6], t0, t1, cv[12];
+            const int32_t ci = obs_cam[a];
+            obs_fj64(cam, pt, uv, huber, ci, (int32_t)j, a, f, jc, jp);
+            refine_contrib(f, jc, jp, dcam + 9 * (int64_t)ci, t0, t1, cv);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) Vs[k] += cv[k];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                ws[k] += cv[6 + k];
+                zs[k] += cv[9 + k];
+            }
+        }
+        double y[3];
+        refine_segment_step(V, w, Vs, ws, zs, lam, corr, y);
+        for (int64_t a = h; a < p1; ++a) {
+            if (seg_head[a] != (int32_t)h) continue;
+            double f[2], jc[18], jp[6], t0, t1, cv[12];
+            const int32_t ci = obs_cam[a];
+            obs_fj64(cam, pt, uv, huber, ci, (int32_t)j, a, f, jc, jp);
+            refine_contrib(f, jc, jp, dcam + 9 * (int64_t)ci, t0, t1, cv);
+            refine_write_e(f, t0, t1, jp, y, e + 2 * a);
+        }
+    }
+}
+
+// Part 2: r_i = sum_{o of camera i} J_c,o^T e_o - lambda diag(U_i) x_i, U_i =
+// sum J_c,o^T J_c,o; one wavefront per camera over the diagonal block's pair
+// list (every observation of the camera once), the camera's part of the
+// projection formed once per lane, then a fixed-order butterfly.
+__global__ __launch_bounds__(256) void k_refine_cam(int32_t m, const double *__restrict__ cam,
+                                                    const double *__restrict__ pt, const int32_t *__restrict__ op,
+                                                    const double *__restrict__ uv, double huber,
+                                                    const int64_t *__restrict__ diag_blk,
+                                                    const int64_t *__restrict__ blk_start,
+                                                    const uint64_t *__restrict__ pairs,
+                                                    const double *__restrict__ lam2, const double *__restrict__ dcam,
+                                                    const double *__restrict__ e, double *__restrict__ r) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= m) return;
+    double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, dg[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const int64_t kb = diag_blk[i];
+    if (kb >= 0) {
+        double c[9], cp[kCamPre];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) c[k] = cam[9 * i + k];
+        camera_pre(c, cp);
+        for (int64_t p = blk_start[kb] + lane; p < blk_start[kb + 1]; p += 64) {
+            const int64_t o = (int64_t)(pairs[p] >> 32);
+            double f[2], jc[18], jp[6];
+            obs_fj64(cp, pt, uv, huber, op[o], o, f, jc, jp);
+            const double e0 = e[2 * o], e1 = e[2 * o + 1];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                acc[k] += jc[k] * e0 + jc[9 + k] * e1;
+                dg[k] += jc[k] * jc[k] + jc[9 + k] * jc[9 + k];
+            }
+        }
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1)
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            acc[k] += __shfl_xor(acc[k], d, 64);
+            dg[k] += __shfl_xor(dg[k], d, 64);
+        }
+    const double lam = lam2[0];
+    double v = 0.0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+        if (lane == k) v = acc[k] - lam * dg[k] * dcam[9 * i + k];
+    if (lane < 9) r[9 * i + lane] = v;
 }
 
 // a7: cost at the candidate x + dx in FP64 (block partial sums).
@@ -1449,12 +1742,12 @@ hipError_t launch_point_groups(int32_t n, const int64_t *pt_off, int32_t group_s
     return hipGetLastError();
 }
 
-hipError_t launch_fill_S(double *S, double *S0, double *b, int32_t m, const int64_t *S_off, int32_t l, int64_t S_cap,
+hipError_t launch_fill_S(double *S, double *b, int32_t m, const int64_t *S_off, int32_t l, int64_t S_cap,
                          hipStream_t st) {
     int64_t blocks = (S_cap + 1023) / 1024;
     if (blocks > 8192) blocks = 8192;
     if (blocks < 1) blocks = 1;
-    k_zero_S<<<(unsigned)blocks, 256, 0, st>>>(S, S0, b, m, S_off, l, S_cap);
+    k_zero_S<<<(unsigned)blocks, 256, 0, st>>>(S, b, m, S_off, l, S_cap);
     return hipGetLastError();
 }
 
@@ -1485,25 +1778,54 @@ template hipError_t launch_schur<float>(const int64_t *, int64_t, const SchurChu
                                         const int32_t *, const int64_t *, const int32_t *, const float *, const float *,
                                         const double *, double *, double *, hipStream_t);
 
+template <typename T, bool kFp64J>
+hipError_t backsub_as(const stba_problem &p, const int64_t *pt_off, const T *Jc, const T *Jp, const double *Vinv,
+                      const double *wph, const double *dcam, double *dpt, int32_t group_size,
+                      const int32_t *grp_first, hipStream_t st) {
+    const AtX X{p.cam, p.pt, p.obs_uv, p.huber};
+    if (group_size > 0) {
+        const int64_t ng = (p.q + group_size - 1) / group_size;
+        k_backsub_obs<T, kFp64J><<<(unsigned)((ng + kPtWaves - 1) / kPtWaves), 64 * kPtWaves, 0, st>>>(
+            ng, grp_first, pt_off, p.obs_pt, p.obs_cam, Jc, Jp, Vinv, wph, dcam, dpt, X);
+        return hipGetLastError();
+    }
+    k_backsub<T, kFp64J><<<grid_for(p.n), 256, 0, st>>>(p.n, pt_off, p.obs_cam, Jc, Jp, Vinv, wph, dcam, dpt, X);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_backsub(const stba_problem &p, const int64_t *pt_off, const T *Jc, const T *Jp,
                           const double *Vinv, const double *wph, const double *dcam, double *dpt,
-                          int32_t group_size, const int32_t *grp_first, hipStream_t st) {
-    if (group_size > 0) {
-        const int64_t ng = (p.q + group_size - 1) / group_size;
-        k_backsub_obs<T><<<(unsigned)((ng + kPtWaves - 1) / kPtWaves), 64 * kPtWaves, 0, st>>>(
-            ng, grp_first, pt_off, p.obs_pt, p.obs_cam, Jc, Jp, Vinv, wph, dcam, dpt);
-        return hipGetLastError();
-    }
-    k_backsub<T><<<grid_for(p.n), 256, 0, st>>>(p.n, pt_off, p.obs_cam, Jc, Jp, Vinv, wph, dcam, dpt);
-    return hipGetLastError();
+                          int32_t group_size, const int32_t *grp_first, bool fp64_j, hipStream_t st) {
+    if (fp64_j) return backsub_as<T, true>(p, pt_off, Jc, Jp, Vinv, wph, dcam, dpt, group_size, grp_first, st);
+    return backsub_as<T, false>(p, pt_off, Jc, Jp, Vinv, wph, dcam, dpt, group_size, grp_first, st);
 }
 template hipError_t launch_backsub<double>(const stba_problem &, const int64_t *, const double *, const double *,
                                            const double *, const double *, const double *, double *, int32_t,
-                                           const int32_t *, hipStream_t);
+                                           const int32_t *, bool, hipStream_t);
 template hipError_t launch_backsub<float>(const stba_problem &, const int64_t *, const float *, const float *,
                                           const double *, const double *, const double *, double *, int32_t,
-                                          const int32_t *, hipStream_t);
+                                          const int32_t *, bool, hipStream_t);
+
+hipError_t launch_refine_residual(const stba_problem &p, const int64_t *pt_off, const int32_t *seg_head,
+                                  int32_t group_size, const int32_t *grp_first, const double *lam2,
+                                  const double *dcam, double *e, double *Vinv, double *wph, const int64_t *diag_blk,
+                                  const int64_t *blk_start, const uint64_t *pairs, double *r, hipStream_t st) {
+    if (group_size > 0) {
+        const int64_t ng = (p.q + group_size - 1) / group_size;
+        k_refine_obs<<<(unsigned)((ng + kPtWaves - 1) / kPtWaves), 64 * kPtWaves, 0, st>>>(
+            ng, grp_first, pt_off, p.obs_pt, p.obs_cam, p.cam, p.pt, p.obs_uv, p.huber, seg_head, lam2, dcam, e, Vinv,
+            wph);
+    } else {
+        k_refine_pt<<<grid_for(p.n, 64), 64, 0, st>>>(p.n, pt_off, p.obs_cam, p.cam, p.pt, p.obs_uv, p.huber,
+                                                      seg_head, lam2, dcam, e, Vinv, wph);
+    }
+    const hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    k_refine_cam<<<(unsigned)(((int64_t)p.m + 3) / 4), 256, 0, st>>>(p.m, p.cam, p.pt, p.obs_pt, p.obs_uv, p.huber,
+                                                                     diag_blk, blk_start, pairs, lam2, dcam, e, r);
+    return hipGetLastError();
+}
 
 hipError_t launch_cost_at(const stba_problem &p, const double *dcam, const double *dpt, double *partials,
                           const stba_lm_state *s, double *F_ref, hipStream_t st) {

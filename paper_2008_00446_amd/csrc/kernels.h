@@ -41,11 +41,10 @@ hipError_t launch_clusters(const int32_t *cam_cluster, int32_t m, int32_t l, con
                            int32_t *cl_n, int32_t *cl_Np, int32_t *cl_start, int32_t *cl_cams,
                            int32_t *cam_local, int64_t *S_off, int32_t *cl_status, int32_t *status, hipStream_t st);
 
-// S (nullable): also zero S (the first min(S_off[l], S_cap) doubles), S0 (if
-// given, the same extent) and b (nb doubles)
+// S (nullable): also zero S (the first min(S_off[l], S_cap) doubles) and b
+// (nb doubles)
 struct ZeroS {
     double *S = nullptr;
-    double *S0 = nullptr;
     const int64_t *S_off = nullptr;
     int32_t l = 0;
     int64_t S_cap = 0;
@@ -74,8 +73,8 @@ hipError_t launch_point_groups(int32_t n, const int64_t *pt_off, int32_t group_s
                                int32_t *grp_first, hipStream_t st);
 inline int32_t point_group_size(int32_t max_track) { return max_track <= 32 ? 65 - max_track : 0; }
 
-// zero S, S0 (nullable) and b
-hipError_t launch_fill_S(double *S, double *S0, double *b, int32_t m, const int64_t *S_off, int32_t l, int64_t S_cap,
+// zero S and b
+hipError_t launch_fill_S(double *S, double *b, int32_t m, const int64_t *S_off, int32_t l, int64_t S_cap,
                          hipStream_t st);
 
 struct SchurChunks {
@@ -84,7 +83,6 @@ struct SchurChunks {
     const int32_t *chunk_blk;
     int64_t chunk_cap;
     double *part;          // partial sums, kSchurPart doubles per chunk
-    double *S0 = nullptr;  // MIXED: every entry written to S is written here too (kept for refinement)
     int32_t all_links = 0;  // alpha = 1: every same-cluster link is kept, so the pairs of a block
                             // share their segment and the segment-head check is skipped
 };
@@ -103,9 +101,8 @@ constexpr int kCholTileWaves = 2048;   // e.g. one cluster of up to 64 tile rows
 // per cluster T (T + 1) / 2 + T + 2 flag words <= 2.5 x its wavefronts, plus the
 // abort word and the count of finished clusters
 inline int64_t chol_flag_words() { return 4 * (int64_t)kCholTileWaves + 2; }
-// per cluster 4 block vectors of T x 32 doubles (y, x and the MIXED refinement's
-// d, e), T <= its wavefronts
-inline int64_t chol_yx_doubles() { return 4 * (int64_t)kCholTileWaves * kNB; }
+// per cluster 2 block vectors of T x 32 doubles (y, x), T <= its wavefronts
+inline int64_t chol_yx_doubles() { return 2 * (int64_t)kCholTileWaves * kNB; }
 int chol_tile_layout(int32_t l, int32_t max_Np, int32_t *wpc, int32_t *tmax, int32_t *fpc, int32_t *xcd_major);
 // Buffers of the team factorisation (many clusters, tiles in memory): flag
 // words (per cluster 2 T^2 + 8 from 2 S_off / 1024 + 8 k, then the abort word
@@ -127,24 +124,32 @@ inline int64_t chol_team_vec_len(int64_t S_cap) { return S_cap / 32; }
 // the flag words and block vectors have to be in their initial state before the
 // first factorisation; every tile-parallel or team factorisation leaves them so again
 hipError_t launch_clear_chol_flags(int32_t *flags, double *yx, const CholTeam *team, hipStream_t st);
-// S0 (nullable): the assembled S kept for one FP64 refinement step (MIXED),
-// with rbuf (l * max_Np doubles) for its residual.
+// The factorisation leaves L in S's lower tiles and W_pp^T = (L_pp^-1)^T in the
+// upper triangle of each diagonal tile.
 hipError_t launch_chol(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, const int64_t *S_off,
                        const int32_t *cl_start, const int32_t *cl_cams, double *S, const double *b,
                        double *dcam, int32_t *cl_status, int32_t max_Np, int32_t *flags, double *yx,
-                       const double *S0, double *rbuf, const CholTeam *team, hipStream_t st);
+                       const CholTeam *team, hipStream_t st);
 
-// MIXED precision: one FP64 refinement step of dcam against S0 (the assembled
-// S, written alongside it by the assembly) with the factors.
-hipError_t launch_refine(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, const int64_t *S_off,
-                         const int32_t *cl_start, const int32_t *cl_cams, const double *S, const double *S0,
-                         const double *b, double *dcam, double *rbuf, int32_t max_Np, hipStream_t st);
+// MIXED refinement residual r = b - S x of the FP64 method's S and b, formed
+// from J recomputed in FP64 at x (never from the FP32-assembled S): e [2 q]
+// receives the linearised residuals, r [9 m] the residual in camera order;
+// Vinv / wph are overwritten with the FP64 physical point blocks.
+hipError_t launch_refine_residual(const stba_problem &p, const int64_t *pt_off, const int32_t *seg_head,
+                                  int32_t group_size, const int32_t *grp_first, const double *lam2,
+                                  const double *dcam, double *e, double *Vinv, double *wph, const int64_t *diag_blk,
+                                  const int64_t *blk_start, const uint64_t *pairs, double *r, hipStream_t st);
+// dcam += S^-1 r with the factors left in S by launch_chol (r in camera order)
+hipError_t launch_sweep(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, const int64_t *S_off,
+                        const int32_t *cl_start, const int32_t *cl_cams, const double *S, const double *r,
+                        double *dcam, int32_t max_Np, hipStream_t st);
 
 template <typename T>
-// group_size > 0: one lane per observation in the groups of launch_points
+// group_size > 0: one lane per observation in the groups of launch_points.
+// fp64_j: J_c, J_p formed in FP64 at x instead of read from Jc / Jp.
 hipError_t launch_backsub(const stba_problem &p, const int64_t *pt_off, const T *Jc, const T *Jp,
                           const double *Vinv, const double *wph, const double *dcam, double *dpt,
-                          int32_t group_size, const int32_t *grp_first, hipStream_t st);
+                          int32_t group_size, const int32_t *grp_first, bool fp64_j, hipStream_t st);
 
 // F_ref (nullable, 2 doubles): receives s->F and s->have_F for launch_accept_update
 hipError_t launch_cost_at(const stba_problem &p, const double *dcam, const double *dpt, double *partials,

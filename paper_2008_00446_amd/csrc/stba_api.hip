@@ -21,10 +21,11 @@ struct Layout {
     // per iteration
     size_t cl_n, cl_Np, cl_start, cl_cams, cam_local, cl_status, S_off;
     size_t pcg_clus, pcg_minv, pcg_iters, pcg_resid;
-    size_t f, Jc, Jp, seg_head, seg_rec, grp_first, obsd, Vinv, wph, S, S0, rres, b, dcam, dpt, partials, chol_flags, chol_yx;
+    size_t f, Jc, Jp, seg_head, seg_rec, grp_first, obsd, Vinv, wph, S, eref, rres, b, dcam, dpt, partials, chol_flags,
+        chol_yx;
     size_t team_flags, team_vec;
     int64_t team_abort_at, team_vec_len;
-    bool mixed = false;   // S0 and rres exist
+    bool refine = false;   // STBA_MIXED: eref and rres exist
     int64_t S_cap, n_partials;
     int32_t group_size;
     int32_t max_Np;
@@ -49,7 +50,8 @@ int check_dims(const stba_problem *p, const stba_dims *d) {
 }
 
 int check_precision(int precision) {
-    return (precision == STBA_FP64 || precision == STBA_MIXED) ? STBA_OK : STBA_EINVAL;
+    return (precision == STBA_FP64 || precision == STBA_MIXED || precision == STBA_MIXED_NOREFINE) ? STBA_OK
+                                                                                                     : STBA_EINVAL;
 }
 
 int check_sample(const stba_problem *p, const stba_sample *s) {
@@ -70,7 +72,7 @@ int64_t s_capacity(int32_t m, int32_t gamma) {
 }
 
 bool make_layout(const stba_problem *p, const stba_dims *d, int precision, Layout &L) {
-    const size_t es = precision == STBA_MIXED ? sizeof(float) : sizeof(double);
+    const size_t es = precision == STBA_FP64 ? sizeof(double) : sizeof(float);
     const size_t m = (size_t)p->m, n = (size_t)p->n, q = (size_t)p->q, np = (size_t)d->n_pairs;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -137,10 +139,10 @@ bool make_layout(const stba_problem *p, const stba_dims *d, int precision, Layou
     L.team_flags = take(4 * (size_t)(L.team_abort_at + 3));
     L.team_vec_len = chol_team_vec_len(L.S_cap);
     L.team_vec = take(8 * 4 * (size_t)L.team_vec_len);
-    // MIXED keeps the assembled S for the refinement step
-    L.mixed = precision == STBA_MIXED;
-    L.S0 = L.mixed ? take(8 * (size_t)L.S_cap) : 0;
-    L.rres = precision == STBA_MIXED ? take(8 * m * (size_t)L.max_Np) : 0;
+    // MIXED's refinement step: linearised residuals per observation, residual per camera
+    L.refine = precision == STBA_MIXED;
+    L.eref = L.refine ? take(8 * 2 * q) : 0;
+    L.rres = L.refine ? take(8 * 9 * m) : 0;
     L.b = take(8 * 9 * m);
     L.dcam = take(8 * 9 * m);
     L.dpt = take(8 * 3 * n);
@@ -192,7 +194,6 @@ SchurChunks chunks_of(const Layout &L, void *ws, const stba_sample *s) {
     c.chunk_blk = at<int32_t>(ws, L.chunk_blk);
     c.chunk_cap = L.chunk_cap;
     c.part = at<double>(ws, L.part);
-    c.S0 = L.mixed ? at<double>(ws, L.S0) : nullptr;
     return c;
 }
 
@@ -208,8 +209,8 @@ int build_rcs_impl(const stba_problem *p, const stba_dims *d, const stba_sample 
                               keep_threshold(s->alpha), at<int32_t>(ws, L.seg_head), at<double>(ws, L.seg_rec), at<T>(ws, L.obsd),
                               at<double>(ws, L.Vinv), at<double>(ws, L.wph), status, L.group_size,
                               at<int32_t>(ws, L.grp_first), st));
-    STBA_HIP(launch_fill_S(at<double>(ws, L.S), L.mixed ? at<double>(ws, L.S0) : nullptr, at<double>(ws, L.b), p->m,
-                           at<int64_t>(ws, L.S_off), s->l, L.S_cap, st));
+    STBA_HIP(launch_fill_S(at<double>(ws, L.S), at<double>(ws, L.b), p->m, at<int64_t>(ws, L.S_off), s->l, L.S_cap,
+                           st));
     STBA_HIP(launch_schur<T>(at<int64_t>(ws, L.n_blocks), L.blk_cap, chunks_of(L, ws, s), at<int2>(ws, L.blk_key),
                              at<int64_t>(ws, L.blk_start), at<uint64_t>(ws, L.pairs), s->cam_cluster, s->l,
                              at<int32_t>(ws, L.cam_local), at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np),
@@ -231,31 +232,42 @@ CholTeam team_of(const Layout &L, void *ws) {
     return t;
 }
 
-// The cluster solves of Eq. 13; in MIXED precision with one FP64 refinement
-// step against the assembled S.
-template <typename T>
+// The cluster solves of Eq. 13 (FP64 Cholesky of every S_k).
 int cluster_solve(int32_t l, bool l_on_device, double *dcam, int32_t *cl_status, const Layout &L, void *ws,
                   hipStream_t st) {
-    // MIXED: S0, the copy of S kept for the refinement step, was written by the assembly
-    const bool mixed = sizeof(T) == sizeof(float);
     CholTeam team = team_of(L, ws);
     team.l_on_device = l_on_device;
     STBA_HIP(launch_chol(l, at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np), at<int64_t>(ws, L.S_off),
                          at<int32_t>(ws, L.cl_start), at<int32_t>(ws, L.cl_cams), at<double>(ws, L.S),
                          at<double>(ws, L.b), dcam, cl_status, L.max_Np, at<int32_t>(ws, L.chol_flags),
-                         at<double>(ws, L.chol_yx), mixed ? at<double>(ws, L.S0) : nullptr,
-                         mixed ? at<double>(ws, L.rres) : nullptr, &team, st));
+                         at<double>(ws, L.chol_yx), &team, st));
+    return STBA_OK;
+}
+
+// MIXED: one FP64 refinement step of every cluster solve, dcam += S_k^-1 (b - S x)
+// with the residual of the FP64 method's S and b (J recomputed in FP64 at x)
+// and the factors of the FP32-assembled S_k.
+int refine_solve(const stba_problem *p, int32_t l, const double *lam2, double *dcam, const Layout &L, void *ws,
+                 hipStream_t st) {
+    double *r = at<double>(ws, L.rres);
+    STBA_HIP(launch_refine_residual(*p, at<int64_t>(ws, L.pt_off), at<int32_t>(ws, L.seg_head), L.group_size,
+                                    at<int32_t>(ws, L.grp_first), lam2, dcam, at<double>(ws, L.eref),
+                                    at<double>(ws, L.Vinv), at<double>(ws, L.wph), at<int64_t>(ws, L.diag_blk),
+                                    at<int64_t>(ws, L.blk_start), at<uint64_t>(ws, L.pairs), r, st));
+    STBA_HIP(launch_sweep(l, at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np), at<int64_t>(ws, L.S_off),
+                          at<int32_t>(ws, L.cl_start), at<int32_t>(ws, L.cl_cams), at<double>(ws, L.S), r, dcam,
+                          L.max_Np, st));
     return STBA_OK;
 }
 
 template <typename T>
 int solve_impl(const stba_problem *p, const stba_dims *d, int32_t l, bool l_on_device, const T *Jc, const T *Jp,
-               double *dcam,
-               double *dpt, int32_t *cl_status, const Layout &L, void *ws, hipStream_t st) {
+               double *dcam, double *dpt, int32_t *cl_status, const Layout &L, void *ws, hipStream_t st) {
     (void)d;
-    STBA_TRY(cluster_solve<T>(l, l_on_device, dcam, cl_status, L, ws, st));
+    STBA_TRY(cluster_solve(l, l_on_device, dcam, cl_status, L, ws, st));
+    if (L.refine) STBA_TRY(refine_solve(p, l, at<double>(ws, L.lam2), dcam, L, ws, st));
     STBA_HIP(launch_backsub<T>(*p, at<int64_t>(ws, L.pt_off), Jc, Jp, at<double>(ws, L.Vinv), at<double>(ws, L.wph),
-                               dcam, dpt, L.group_size, at<int32_t>(ws, L.grp_first), st));
+                               dcam, dpt, L.group_size, at<int32_t>(ws, L.grp_first), L.refine, st));
     return STBA_OK;
 }
 
@@ -283,7 +295,6 @@ int lm_step_impl(const stba_problem *p, const stba_dims *d, const stba_sample *s
     STBA_TRY(mark(1));
     ZeroS z;   // S and b are zeroed by the residual kernel's grid
     z.S = at<double>(ws, L.S);
-    z.S0 = L.mixed ? at<double>(ws, L.S0) : nullptr;
     z.S_off = at<int64_t>(ws, L.S_off);
     z.l = s->l;
     z.S_cap = L.S_cap;
@@ -313,18 +324,26 @@ int lm_step_impl(const stba_problem *p, const stba_dims *d, const stba_sample *s
                             L.max_Np, d->gamma_max, pcg->max_iters, pcg->tol, at<int32_t>(ws, L.pcg_iters),
                             at<double>(ws, L.pcg_resid), at<int32_t>(ws, L.cl_status), st));
     else
-        STBA_TRY(cluster_solve<T>(s->l, s->l_dev != nullptr, dcam, at<int32_t>(ws, L.cl_status), L, ws, st));
+        STBA_TRY(cluster_solve(s->l, s->l_dev != nullptr, dcam, at<int32_t>(ws, L.cl_status), L, ws, st));
     STBA_TRY(mark(6));
-    STBA_HIP(launch_backsub<T>(*p, at<int64_t>(ws, L.pt_off), Jc, Jp, at<double>(ws, L.Vinv), at<double>(ws, L.wph),
-                               dcam, dpt, L.group_size, at<int32_t>(ws, L.grp_first), st));
+    // the conjugate-gradient solves take no refinement step (FP64 and iterative)
+    const bool refine = L.refine && pcg == nullptr;
+    if (refine) STBA_TRY(refine_solve(p, s->l, lam2, dcam, L, ws, st));
     STBA_TRY(mark(7));
+    // The point update takes J in FP64 at x: recomputed from x (48 bytes per
+    // observation in) rather than read (200 bytes per observation in FP64).  x
+    // is where the residual kernel last evaluated J, so in FP64 the two agree.
+    const bool fp64_j = refine || sizeof(T) == sizeof(double);
+    STBA_HIP(launch_backsub<T>(*p, at<int64_t>(ws, L.pt_off), Jc, Jp, at<double>(ws, L.Vinv), at<double>(ws, L.wph),
+                               dcam, dpt, L.group_size, at<int32_t>(ws, L.grp_first), fp64_j, st));
+    STBA_TRY(mark(8));
     double *rj_part = at<double>(ws, L.partials), *cost_part = rj_part + L.n_partials;
     double *F_ref = cost_part + L.n_partials;
     STBA_HIP(launch_cost_at(*p, dcam, dpt, cost_part, stt, F_ref, st));
-    STBA_TRY(mark(8));
+    STBA_TRY(mark(9));
     STBA_HIP(launch_accept_update(*p, rj_part, cost_part, L.n_partials, F_ref, at<int32_t>(ws, L.cl_status), s->l,
                                   status, stt, dcam, dpt, st));
-    STBA_TRY(mark(9));
+    STBA_TRY(mark(10));
     return STBA_OK;
 }
 
@@ -361,7 +380,7 @@ int static_scratch(double **out) {
 
 const char *const kPhaseNames[STBA_NUM_PHASES] = {
     "clusters", "residual_jacobian", "points_segments", "fill_S", "schur_assembly",
-    "cluster_cholesky", "point_backsub", "candidate_cost", "accept_update"};
+    "cluster_cholesky", "refinement", "point_backsub", "candidate_cost", "accept_update"};
 
 }  // namespace
 }  // namespace stba
@@ -550,11 +569,11 @@ int stba_solve_clusters_pcg(const stba_problem *p, const stba_dims *dims, const 
     if (precision == STBA_FP64)
         STBA_HIP(launch_backsub<double>(*p, at<int64_t>(ws, L.pt_off), (const double *)Jc, (const double *)Jp,
                                         at<double>(ws, L.Vinv), at<double>(ws, L.wph), dcam, dpt, L.group_size,
-                                        at<int32_t>(ws, L.grp_first), stream));
+                                        at<int32_t>(ws, L.grp_first), false, stream));
     else
         STBA_HIP(launch_backsub<float>(*p, at<int64_t>(ws, L.pt_off), (const float *)Jc, (const float *)Jp,
                                        at<double>(ws, L.Vinv), at<double>(ws, L.wph), dcam, dpt, L.group_size,
-                                       at<int32_t>(ws, L.grp_first), stream));
+                                       at<int32_t>(ws, L.grp_first), false, stream));
     return STBA_OK;
 }
 

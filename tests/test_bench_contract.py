@@ -49,6 +49,14 @@ def test_algorithmic_model_counts_pairs_and_flops():
     assert np.isclose(model["schur_assembly"]["flops"], 486 * np.mean(off_pairs) + 576 * s.q, rtol=1e-12)
     assert np.isclose(model["schur_assembly"]["bytes"], s.q * 216 + 8 * np.mean(entries), rtol=1e-12)
     assert np.isclose(model["cluster_cholesky"]["flops"], np.mean(flops), rtol=1e-12)
-    assert np.isclose(model["point_backsub"]["bytes"], s.q * 200 + 72 * s.n, rtol=1e-12)
+    assert np.isclose(model["point_backsub"]["bytes"], s.q * 48 + 72 * s.m + 24 * s.n + 72 * s.n, rtol=1e-12)
     m4, _ = bench.algorithmic_model(s, maps, 4)
     assert np.isclose(m4["schur_assembly"]["bytes"], s.q * 112 + 8 * np.mean(entries), rtol=1e-12)
+    assert "refinement" not in m4
+    assert np.isclose(m4["point_backsub"]["bytes"], s.q * 104 + 72 * s.n, rtol=1e-12)
+    # STBA_MIXED: the refinement's inputs once, the factor twice; the point
+    # update reads ids, pixel and point to form J in FP64
+    mr, _ = bench.algorithmic_model(s, maps, 4, refine=True)
+    params = 72 * s.m + 24 * s.n
+    assert np.isclose(mr["refinement"]["bytes"], 48 * s.q + params + 72 * s.m + 16 * np.mean(entries), rtol=1e-12)
+    assert np.isclose(mr["point_backsub"]["bytes"], 48 * s.q + params + 72 * s.n, rtol=1e-12)

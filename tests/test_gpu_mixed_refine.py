@@ -1,0 +1,107 @@
+"""MIXED precision's refinement step.  STBA_MIXED assembles every S_k from the
+FP32 Jacobian, factors it in FP64 and then takes one FP64 refinement step whose
+residual b - S x belongs to the FP64 method (J recomputed in FP64 at x, never
+the FP32-assembled S_k); the point update then uses the FP64 J as well.
+STBA_MIXED_NOREFINE stops after the first solve.  Against the FP64 oracle's
+exact step (Eq. 13 and 15), the refined steps must be far closer than the
+unrefined ones: on every factorisation form (tile dataflow, one workgroup per
+cluster, teams), on both point paths (one lane per observation; one thread per
+point for tracks above 32), with the correction (lambda >= 0.1) and a random
+constraint draw, and with the Huber loss."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_2008_00446_amd as S
+import synth
+from gpu_helpers import GpuProblem, kappa_scaled, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _sgc(scene, gamma, t, seed=0):
+    e, w = synth.camera_graph(scene.obs_cam, scene.obs_pt, scene.m)
+    return synth.sgc_map(e, w, scene.m, gamma, 10.0, seed, t)
+
+
+CASES = {
+    # name: (scene, map, gamma_max, lambda, alpha, seed, t, huber, team)
+    "tile": (lambda: synth.small_ring(m=40, n=3000, views=8, seed=1), ("sgc", 12, 2), 12, 1e-3, 1.0, 5, 2, 0.0, False),
+    "correction_draw": (lambda: synth.small_ring(m=40, n=3000, views=8, seed=1), ("sgc", 12, 1), 12, 0.3, 0.7, 4, 1,
+                        0.0, False),
+    "workgroup": (lambda: synth.small_ring(m=40, n=3000, views=8, seed=1), ("single",), 40, 1e-2, 1.0, 0, 0, 0.0,
+                  False),
+    "team": (lambda: synth.small_ring(m=40, n=3000, views=8, seed=1), ("sgc", 40, 3), 40, 1e-4, 1.0, 0, 3, 0.0, True),
+    "long_tracks": (lambda: synth.small_ring(m=50, n=400, views=40, seed=3), ("sgc", 20, 0), 20, 0.2, 0.7, 4, 0, 0.0,
+                    False),
+    "huber": (lambda: synth.small_ring(m=40, n=3000, views=8, seed=1), ("sgc", 12, 2), 12, 1e-3, 1.0, 5, 2, 0.5,
+              False),
+}
+
+
+def _step(s, lab, gamma_max, precision, lam, alpha, seed, t, huber):
+    g = GpuProblem(s, gamma_max=gamma_max, precision=precision, huber=huber)
+    f, Jc, Jp, _ = g.residual_jacobian()
+    rcs = g.build(f, Jc, Jp, lab, lam, alpha, seed, t)
+    dcam, dpt, cs = g.solve(rcs, Jc, Jp)
+    assert np.all(cs == 0)
+    return g, dcam, dpt
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_refinement_brings_mixed_steps_to_the_fp64_step(case, monkeypatch):
+    make, mp, gamma_max, lam, alpha, seed, t, huber, team = CASES[case]
+    if team:
+        monkeypatch.setenv("STBA_CHOL", "team")
+    s = make()
+    lab = _sgc(s, mp[1], mp[2]) if mp[0] == "sgc" else np.arange(s.m, dtype=np.int32)
+    ref = O.stba_step(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv, lab, lam, alpha, seed, t, huber=huber)
+    g, dc1, dp1 = _step(s, lab, gamma_max, S.STBA_MIXED_NOREFINE, lam, alpha, seed, t, huber)
+    if case == "long_tracks":
+        assert g.dims.max_track > 32
+    _, dc2, dp2 = _step(s, lab, gamma_max, S.STBA_MIXED, lam, alpha, seed, t, huber)
+    kap = max(kappa_scaled(Sk) for Sk in ref.S_blocks)
+    e1c, e1p = rel(dc1, ref.dcam), rel(dp1, ref.dpt)
+    e2c, e2p = rel(dc2, ref.dcam), rel(dp2, ref.dpt)
+    print(f"{case}: kappa {kap:.2e}; unrefined dcam {e1c:.2e} dpt {e1p:.2e}; refined dcam {e2c:.2e} dpt {e2p:.2e}",
+          flush=True)
+    # the unrefined step carries the FP32 assembly's error; one refinement step
+    # leaves that error times about kappa * 2^-24, plus FP64 rounding
+    assert e1c < 1e-4 and e1p < 1e-4
+    assert e2c < max(1e-9, 1e-2 * e1c)
+    assert e2p < max(1e-9, 1e-2 * e1p)
+
+
+@pytest.mark.parametrize("precision", [S.STBA_MIXED, S.STBA_MIXED_NOREFINE])
+def test_full_size_ring_iteration_mixed(precision):
+    """One LM iteration of the 200-camera ring (400k observations, Gamma 50)."""
+    s = synth.ring(m=200, n=50000, views=8, seed=0)
+    lab = _sgc(s, 50, 0)
+    sol = S.StbaSolver(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv, gamma_max=50, lambda0=1e-4,
+                       precision=precision)
+    sol.step(sol.sample(lab, alpha=1.0, seed=0, it=0))
+    st = sol.read_state()
+    ref = O.lm_iteration(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv, lab, 1e-4, 1.0, 0, 0)
+    dc = rel(sol.cam.cpu().numpy() - s.cam0, ref.cam - s.cam0)
+    dp = rel(sol.pt.cpu().numpy() - s.pt0, ref.pt - s.pt0)
+    dF = abs(st["F_new"] - ref.F_new) / ref.F_new
+    print(f"ring precision {precision}: accepted {st['accepted']} F_new rel {dF:.2e} dcam {dc:.2e} dpt {dp:.2e}",
+          flush=True)
+    assert st["status"] == 0 and st["last_status"] == 0
+    assert bool(st["accepted"]) == ref.accepted
+    bar = 1e-7 if precision == S.STBA_MIXED else 1e-4
+    assert dF <= bar and dc < bar and dp < bar
+
+
+def test_refined_lm_iterations_repeat_bit_for_bit():
+    s = synth.small_ring(m=40, n=3000, views=8, seed=1)
+    out = []
+    for _ in range(2):
+        sol = S.StbaSolver(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv, gamma_max=12, lambda0=1e-3,
+                           precision=S.STBA_MIXED)
+        for t in range(3):
+            sol.step(sol.sample(_sgc(s, 12, t), it=t))
+        torch.cuda.synchronize()
+        out.append((sol.cam.cpu().numpy(), sol.pt.cpu().numpy(), sol.read_state()["F"]))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1]) and out[0][2] == out[1][2]
