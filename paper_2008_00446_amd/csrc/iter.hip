@@ -321,6 +321,38 @@ __global__ __launch_bounds__(256) void k_rj(int64_t q, const double *__restrict_
     if (jac_ran != nullptr && blockIdx.x == 0 && threadIdx.x == 0) jac_ran[0] = 1;
 }
 
+// Residuals alone (no Jacobian requested, nothing to clear): the pixel only,
+// with the same weighting and cost partials as k_rj.
+template <typename T>
+__global__ __launch_bounds__(256) void k_resid_only(int64_t q, const double *__restrict__ cam,
+                                                    const double *__restrict__ pt, const int32_t *__restrict__ oc,
+                                                    const int32_t *__restrict__ op, const double *__restrict__ uv,
+                                                    T *__restrict__ f, double *__restrict__ partials, double huber) {
+    __shared__ double sh[256];
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double sq = 0.0;
+    if (o < q) {
+        const int32_t i = oc[o], j = op[o];
+        double c[9], X[3];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) c[k] = cam[9 * (int64_t)i + k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) X[k] = pt[3 * (int64_t)j + k];
+        double pix[2];
+        camera_project(c, X, pix);
+        const double f0 = pix[0] - uv[2 * o], f1 = pix[1] - uv[2 * o + 1];
+        const double s2 = f0 * f0 + f1 * f1;
+        sq = huber_rho(s2, huber);
+        const double rw = huber_root_weight(s2, huber);
+        f[2 * o] = (T)(rw * f0);
+        f[2 * o + 1] = (T)(rw * f1);
+    }
+    if (partials != nullptr) {
+        const double sum = block_sum_256(sq, sh);
+        if (threadIdx.x == 0) partials[blockIdx.x] = sum;
+    }
+}
+
 // Fixed-order sum of per-block partials (one 256-thread block).
 __global__ __launch_bounds__(256) void k_sum_partials(const double *partials, int64_t count, double *out) {
     __shared__ double sh[256];
@@ -1232,6 +1264,18 @@ __global__ __launch_bounds__(64 * kPtWaves) void k_backsub_obs(int64_t ngroups, 
     for (int k = 0; k < 3; ++k) dpt[3 * (int64_t)j + k] = d[k];
 }
 
+// Workgroups go to the 8 XCDs in turn (workgroup b to XCD b mod 8), each with
+// its own L2.  Camera-major kernels with one wavefront per camera hand each XCD
+// a contiguous range of cameras, so that what neighbouring cameras share (the
+// points they see, those points' observations) is read through one L2:
+// wavefront w of workgroup b (4 per workgroup, nb workgroups, nb a multiple of
+// 8) takes camera 4 ((b mod 8) nb / 8 + b / 8) + w.
+__device__ inline int64_t xcd_contiguous_item(unsigned b, unsigned nb, int w) {
+    const unsigned per = nb >> 3;
+    return 4 * ((int64_t)(b & 7u) * per + (b >> 3)) + w;
+}
+inline unsigned xcd_contiguous_grid(int64_t m) { return (grid_for(m, 4) + 7u) & ~7u; }
+
 // ---------------------------------------------------------------------------
 // MIXED: the residual of one FP64 refinement step of every cluster solve
 // (Eq. 13), r = b - S x with the S and b of the FP64 method, taken from J
@@ -1434,7 +1478,7 @@ __global__ __launch_bounds__(64) void k_refine_pt(int32_t n, const int64_t *__re
 }
 
 // Part 2: r_i = sum_{o of camera i} J_c,o^T e_o - lambda diag(U_i) x_i, U_i =
-// sum J_c,o^T J_c,o; one wavefront per camera over the diagonal block's pair
+// sum J_c,o^T J_c,o; one wavefront per camera (XCD-contiguous) over the diagonal block's pair
 // list (every observation of the camera once), the camera's part of the
 // projection formed once per lane, then a fixed-order butterfly.
 __global__ __launch_bounds__(256) void k_refine_cam(int32_t m, const double *__restrict__ cam,
@@ -1446,7 +1490,7 @@ __global__ __launch_bounds__(256) void k_refine_cam(int32_t m, const double *__r
                                                     const double *__restrict__ lam2, const double *__restrict__ dcam,
                                                     const double *__restrict__ e, double *__restrict__ r) {
     const int lane = threadIdx.x & 63;
-    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t i = xcd_contiguous_item(blockIdx.x, gridDim.x, threadIdx.x >> 6);
     if (i >= m) return;
     double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, dg[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int64_t kb = diag_blk[i];
@@ -1575,7 +1619,8 @@ __global__ __launch_bounds__(256) void k_accept_update(const double *rj_partials
 
 // ---------------------------------------------------------------------------
 // J^T v (differentiation of the residuals): the Jacobian is recomputed.
-// Cameras: one wavefront per camera over its observations (fixed order);
+// Cameras: one wavefront per camera (XCD-contiguous) over its observations
+// (fixed order), the camera's part of the projection formed once per lane;
 // points: one thread per point; observed pixels: -v.
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -1586,20 +1631,21 @@ __global__ __launch_bounds__(256) void k_vjp_cam(int32_t m, const double *__rest
                                                  const uint64_t *__restrict__ pairs, const T *__restrict__ v,
                                                  T *__restrict__ grad_cam) {
     const int lane = threadIdx.x & 63;
-    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t r = xcd_contiguous_item(blockIdx.x, gridDim.x, threadIdx.x >> 6);
     if (r >= m) return;
     double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int64_t kb = diag_blk[r];
     if (kb >= 0) {
-        double c[9];
+        double c[9], cp[kCamPre];
 #pragma unroll
         for (int k = 0; k < 9; ++k) c[k] = cam[9 * r + k];
+        camera_pre(c, cp);
         for (int64_t p = blk_start[kb] + lane; p < blk_start[kb + 1]; p += 64) {
             const int64_t o = (int64_t)(pairs[p] >> 32);
             const int64_t j = op[o];
             const double X[3] = {pt[3 * j], pt[3 * j + 1], pt[3 * j + 2]};
             double pix[2], jc[2][9], jp[2][3];
-            camera_project_jac(c, X, pix, jc, jp);
+            project_jac_pre(cp, X, pix, jc, jp);
             const double v0 = (double)v[2 * o], v1 = (double)v[2 * o + 1];
 #pragma unroll
             for (int k = 0; k < 9; ++k) acc[k] += jc[0][k] * v0 + jc[1][k] * v1;
@@ -1609,7 +1655,11 @@ __global__ __launch_bounds__(256) void k_vjp_cam(int32_t m, const double *__rest
     for (int d = 32; d >= 1; d >>= 1)
 #pragma unroll
         for (int k = 0; k < 9; ++k) acc[k] += __shfl_xor(acc[k], d, 64);
-    if (lane < 9) grad_cam[9 * r + lane] = (T)acc[lane];
+    double g = 0.0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+        if (lane == k) g = acc[k];
+    if (lane < 9) grad_cam[9 * r + lane] = (T)g;
 }
 
 template <typename T>
@@ -1684,6 +1734,11 @@ int64_t rj_blocks(int64_t q) { return (q + 255) / 256; }
 template <typename T>
 hipError_t launch_rj(const stba_problem &p, T *f, T *Jc, T *Jp, double *partials, const int32_t *need_jac,
                      int32_t *jac_ran, const ZeroS &z, hipStream_t st) {
+    if (Jc == nullptr && Jp == nullptr && z.S == nullptr && need_jac == nullptr && jac_ran == nullptr) {
+        k_resid_only<T><<<grid_for(p.q), 256, 0, st>>>(p.q, p.cam, p.pt, p.obs_cam, p.obs_pt, p.obs_uv, f, partials,
+                                                       p.huber);
+        return hipGetLastError();
+    }
     k_rj<T><<<grid_for(p.q), 256, 0, st>>>(p.q, p.cam, p.pt, p.obs_cam, p.obs_pt, p.obs_uv, f, Jc, Jp, partials,
                                            need_jac, jac_ran, z, p.huber);
     return hipGetLastError();
@@ -1822,8 +1877,8 @@ hipError_t launch_refine_residual(const stba_problem &p, const int64_t *pt_off, 
     }
     const hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    k_refine_cam<<<(unsigned)(((int64_t)p.m + 3) / 4), 256, 0, st>>>(p.m, p.cam, p.pt, p.obs_pt, p.obs_uv, p.huber,
-                                                                     diag_blk, blk_start, pairs, lam2, dcam, e, r);
+    k_refine_cam<<<xcd_contiguous_grid(p.m), 256, 0, st>>>(p.m, p.cam, p.pt, p.obs_pt, p.obs_uv, p.huber, diag_blk,
+                                                           blk_start, pairs, lam2, dcam, e, r);
     return hipGetLastError();
 }
 
@@ -1852,8 +1907,8 @@ hipError_t launch_vjp(const stba_problem &p, const int64_t *pt_off, const int64_
                       const int64_t *blk_start, const uint64_t *pairs, const T *v, T *grad_cam, T *grad_pt,
                       T *grad_uv, hipStream_t st) {
     (void)blk_key;
-    k_vjp_cam<T><<<grid_for(p.m, 4), 256, 0, st>>>(p.m, p.cam, p.pt, p.obs_pt, diag_blk, blk_start, pairs, v,
-                                                   grad_cam);
+    k_vjp_cam<T><<<xcd_contiguous_grid(p.m), 256, 0, st>>>(p.m, p.cam, p.pt, p.obs_pt, diag_blk, blk_start, pairs, v,
+                                                           grad_cam);
     k_vjp_pt<T><<<grid_for(p.n), 256, 0, st>>>(p.n, p.q, p.cam, p.pt, p.obs_cam, pt_off, v, grad_pt);
     k_neg<T><<<grid_for(2 * p.q), 256, 0, st>>>(2 * p.q, v, grad_uv);
     return hipGetLastError();

@@ -88,3 +88,61 @@ def test_batched_gradient_matches_central_differences():
             pm[j, k] -= h
             fd = (_local_cost(s, s.cam0, pp, obs) - _local_cost(s, s.cam0, pm, obs)) / (2 * h)
             assert abs(gp[p0 + j, k] - fd) <= 1e-5 * max(1.0, abs(fd)) + 1e-4 * abs(fd), (j, k)
+
+
+def _richardson(cost_at, h):
+    """d/dt of cost_at(t) at 0 by central differences at h and h / 2 combined
+    by Richardson extrapolation (truncation O(h^4))."""
+    d1 = (cost_at(h) - cost_at(-h)) / (2 * h)
+    d2 = (cost_at(h / 2) - cost_at(-h / 2)) / h
+    return (4 * d2 - d1) / 3
+
+
+@pytest.mark.parametrize("precision,rtol", [(S.STBA_FP64, 1e-7), (S.STBA_MIXED, 1e-4)], ids=["fp64", "fp32"])
+def test_64_problem_batch_gradient_against_central_differences(precision, rtol):
+    """The full 64-problem batch in one launch each way; on every problem 200
+    coordinates (100 camera, 100 point, drawn at random) against central
+    differences of the oracle's FP64 cost over the observations the coordinate
+    touches (h = 1e-3 and 5e-4, Richardson-extrapolated: truncation near
+    1e-12 relative, rounding near 1e-9).  FP32 stores f and the gradients in
+    FP32."""
+    batch = synth.diff_batch(seeds=range(64))
+    cam, pt, oc, op, uv, spans = _concat(batch)
+    plan = S.ResidualPlan(oc, op, cam.shape[0], pt.shape[0], precision)
+    tc = dev(cam, torch.float64).requires_grad_(True)
+    tp = dev(pt, torch.float64).requires_grad_(True)
+    f = S.residuals(tc, tp, dev(uv, torch.float64), plan)
+    (f.double() ** 2).sum().backward()
+    gc, gp = tc.grad.cpu().numpy(), tp.grad.cpu().numpy()
+    rng = np.random.default_rng(11)
+    h = 1e-3
+    worst = 0.0
+    for s, (c0, c1, p0, p1) in zip(batch, spans):
+        by_cam = np.argsort(s.obs_cam, kind="stable")
+        cam_start = np.searchsorted(s.obs_cam[by_cam], np.arange(s.m + 1))
+        pt_start = np.searchsorted(s.obs_pt, np.arange(s.n + 1))
+        for _ in range(100):
+            i, k = int(rng.integers(s.m)), int(rng.integers(9))
+            obs = by_cam[cam_start[i]:cam_start[i + 1]]
+
+            def at(t):
+                c = s.cam0.copy()
+                c[i, k] += t
+                return _local_cost(s, c, s.pt0, obs)
+            fd = _richardson(at, h)
+            err = abs(gc[c0 + i, k] - fd) / max(1.0, abs(fd))
+            worst = max(worst, err)
+            assert err <= rtol, (s.m, i, k, gc[c0 + i, k], fd)
+        for _ in range(100):
+            j, k = int(rng.integers(s.n)), int(rng.integers(3))
+            obs = np.arange(pt_start[j], pt_start[j + 1])
+
+            def at(t):
+                p = s.pt0.copy()
+                p[j, k] += t
+                return _local_cost(s, s.cam0, p, obs)
+            fd = _richardson(at, h)
+            err = abs(gp[p0 + j, k] - fd) / max(1.0, abs(fd))
+            worst = max(worst, err)
+            assert err <= rtol, (s.n, j, k, gp[p0 + j, k], fd)
+    print(f"64 problems x 200 coordinates: worst |g - fd| / max(1, |fd|) = {worst:.2e}", flush=True)
