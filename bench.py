@@ -86,6 +86,8 @@ def parse_args():
     ap.add_argument("--no-ablations", action="store_true", help="skip the synthetic ablations")
     ap.add_argument("--no-pcg", action="store_true", help="skip the inexact (PCG) cluster-solve leg")
     ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay of the timed iterations")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the built-in launch settings instead of measuring them (stba_autotune) first")
     ap.add_argument("--no-diff-batch", action="store_true", help="skip the 64-problem differentiation batch")
     ap.add_argument("--ablation-iters", type=int, default=20)
     ap.add_argument("--pmc-summary", action="store_true",
@@ -392,11 +394,22 @@ def roofline_of(phases, model, precision_fp64, workload):
             "frac": achieved / peak, "traffic": load_traffic(dom, workload), "duration_ms": dur * 1e3}
 
 
+TUNE = True   # measure the launch settings (stba_autotune) on the first map before timing
+
+
+def tune(sol, sample):
+    """stba_autotune on a representative sample (the first map); the choices
+    and what was measured, or None when tuning is off."""
+    return sol.autotune(sample) if TUNE else None
+
+
 def timed_run(S, wl, precision, maps, steps, warmup, graph=True):
-    """Warm-up, the timed K iterations and (optionally) their HIP-graph replay."""
+    """Warm-up, the timed K iterations and (optionally) their HIP-graph replay;
+    the launch settings tuned on the first map first (sol.tuning)."""
     import torch
     sol = make_solver(S, wl, precision)
     samples = [sol.sample(maps[t], alpha=1.0, seed=0, it=t) for t in range(len(maps))]
+    sol.tuning = tune(sol, samples[0])
     cam0, pt0 = sol.cam.clone(), sol.pt.clone()
     run_iterations(sol, samples, cam0, pt0, wl.lam0, warmup)
     elapsed = timed(lambda: run_iterations(sol, samples, cam0, pt0, wl.lam0, steps))
@@ -421,6 +434,8 @@ def timed_run(S, wl, precision, maps, steps, warmup, graph=True):
 
 def main():
     args = parse_args()
+    global TUNE
+    TUNE = not args.no_tune
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is not built",
               file=sys.stderr)
@@ -461,6 +476,7 @@ def main():
         "lm": {"F_final": st["F"], "accepted": st["n_accept"], "jacobian_evals": st["n_jac"],
                "rcs_builds": st["n_rcs"], "lambda_final": st["lambda_"], "status": st["status"]},
         "source_hash": source_hash(),
+        "tuning": sol.tuning,
     }
     if args.only_timed:
         print(json.dumps(out))
@@ -528,6 +544,7 @@ def mixed_leg(S, wl, sol64, samples64, maps, K, warmup, cam0, pt0):
     for name, prec in (("mixed", S.STBA_MIXED), ("mixed_norefine", S.STBA_MIXED_NOREFINE)):
         sol = make_solver(S, wl, prec)
         runs[name] = (sol, [sol.sample(maps[t], alpha=1.0, seed=0, it=t) for t in range(kmax)])
+        tune(sol, runs[name][1][0])
     hist = {}
     for name, (sol, smp) in runs.items():
         run_iterations(sol, smp, cam0, pt0, wl.lam0, warmup)
@@ -569,11 +586,15 @@ def mixed_leg(S, wl, sol64, samples64, maps, K, warmup, cam0, pt0):
     variants = {}
     for name in ("mixed", "mixed_norefine"):
         n = first_at_or_below(name, F_target)
+        # the same target up to FP64 rounding of the cost sum (1e-9 relative)
+        n9 = first_at_or_below(name, F_target * (1.0 + 1e-9))
         tk = seconds(name, K)
         variants[name] = {
             "iterations_to_target": n,
             "seconds_to_target": None if n is None else seconds(name, n),
             "speedup_at_equal_cost_reduction": None if n is None else t64 / seconds(name, n),
+            "iterations_to_target_rel_1e-9": n9,
+            "speedup_at_target_rel_1e-9": None if n9 is None else t64 / seconds(name, n9),
             "F_after_K": float(hist[name][K - 1]),
             "minus_fp64_F_after_K_rel": float((hist[name][K - 1] - hist["fp64"][K - 1]) / hist["fp64"][K - 1]),
             "iter_per_s": K / tk, "obs_per_s": s.q * K / tk,
@@ -736,7 +757,8 @@ def secondary_leg(S, wl, warmup):
     for name, prec in (("fp64", S.STBA_FP64), ("mixed", S.STBA_MIXED), ("mixed_norefine", S.STBA_MIXED_NOREFINE)):
         sol, _, _, _, el, st, gips = timed_run(S, wl, prec, maps, K, warmup, graph=True)
         out[name] = {"iter_per_s": K / el, "obs_per_s": wl.scene.q * K / el, "graph_iter_per_s": gips,
-                     "F_after_K": st["F"], "accepted": st["n_accept"], "status": st["status"]}
+                     "F_after_K": st["F"], "accepted": st["n_accept"], "status": st["status"],
+                     "tuning": sol.tuning}
         del sol
         torch.cuda.empty_cache()
     return out

@@ -85,11 +85,21 @@ typedef struct stba_problem {
                                   Must be finite and >= 0. */
 } stba_problem;
 
-/* Data-dependent sizes, filled by stba_analyze (host struct). */
+/* forms of the cluster factorisation (stba_dims.chol_form) */
+#define STBA_CHOL_AUTO      0   /* the built-in choice: tiles when they fit, else teams, else workgroups */
+#define STBA_CHOL_TILES     1   /* one wavefront per tile, all clusters' tiles resident at once */
+#define STBA_CHOL_TEAM      2   /* per cluster a band, a forward and worker wavefronts, tiles in memory */
+#define STBA_CHOL_WORKGROUP 3   /* one workgroup per cluster */
+
+/* Data-dependent sizes, filled by stba_analyze (host struct), and the launch
+ * settings stba_autotune chooses (stba_analyze sets them to 0, the built-in
+ * choices; a caller may also set them). */
 typedef struct stba_dims {
     int64_t n_pairs;           /* sum over points of v (v + 1) / 2, v = observations of the point */
     int32_t max_track;         /* largest v */
     int32_t gamma_max;         /* largest cluster (cameras) the workspace must hold */
+    int32_t chol_form;         /* STBA_CHOL_*; a form that does not fit falls back to the built-in order */
+    int32_t schur_blocks;      /* workgroups of the Schur assembly, 0 or 8..65536 */
 } stba_dims;
 
 /* One draw of the constraint sampler Theta(alpha) (Sec. 4.2). */
@@ -316,6 +326,30 @@ int stba_lm_step_pcg(const stba_problem *p, const stba_dims *dims, const stba_sa
 
 /* Name of phase k of stba_lm_step_profiled (static string, host). */
 const char *stba_phase_name(int k);
+
+/* ---- autotuning ---------------------------------------------------------- */
+
+/* What stba_autotune measured (host struct).  Times in ms, the best of three
+ * runs each; 0 where a candidate was not run (a form that does not fit). */
+#define STBA_TUNE_SCHUR_CANDIDATES 6
+typedef struct stba_tune_report {
+    int32_t chol_form;                                 /* chosen */
+    int32_t schur_blocks;                              /* chosen */
+    float chol_ms[4];                                  /* by form: [STBA_CHOL_TILES .. STBA_CHOL_WORKGROUP] */
+    int32_t schur_candidates[STBA_TUNE_SCHUR_CANDIDATES];
+    float schur_ms[STBA_TUNE_SCHUR_CANDIDATES];        /* the assembly (cluster layout to b) per candidate */
+} stba_tune_report;
+
+/* Choose dims->chol_form and dims->schur_blocks for this problem and a
+ * representative sample: the residual kernel fills the workspace's f and J,
+ * then the assembly (stba_build_cluster_rcs) runs with each Schur workgroup
+ * count and the cluster solves with each factorisation form that fits, each
+ * timed with HIP events on `stream`; the fastest of each is written to dims.
+ * A set-up call: it SYNCHRONISES the stream and creates (and destroys) HIP
+ * events; x is not changed.  report (host, nullable) receives the times.
+ * Errors as stba_build_cluster_rcs; STBA_EHIP if an event call fails. */
+int stba_autotune(const stba_problem *p, stba_dims *dims, const stba_sample *s, const stba_damping *d,
+                  int precision, void *ws, size_t ws_bytes, hipStream_t stream, stba_tune_report *report);
 
 /* ---- differentiation (residuals as a differentiable function) ----------- */
 

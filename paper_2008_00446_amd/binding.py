@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(PKG, "libstba.so")
 STBA_FP64 = 0
 STBA_MIXED = 1
 STBA_MIXED_NOREFINE = 2
+STBA_CHOL_AUTO, STBA_CHOL_TILES, STBA_CHOL_TEAM, STBA_CHOL_WORKGROUP = 0, 1, 2, 3
+STBA_TUNE_SCHUR_CANDIDATES = 6
 STBA_NUM_PHASES = 10
 STATUS_NAMES = {0: "STBA_OK", -1: "STBA_EINVAL", -2: "STBA_ENOTPD", -3: "STBA_ENONFINITE",
                 -4: "STBA_EWORKSPACE", -5: "STBA_EHIP", -6: "STBA_EDATA"}
@@ -36,7 +38,14 @@ class StbaProblem(ctypes.Structure):
 
 
 class StbaDims(ctypes.Structure):
-    _fields_ = [("n_pairs", ctypes.c_int64), ("max_track", ctypes.c_int32), ("gamma_max", ctypes.c_int32)]
+    _fields_ = [("n_pairs", ctypes.c_int64), ("max_track", ctypes.c_int32), ("gamma_max", ctypes.c_int32),
+                ("chol_form", ctypes.c_int32), ("schur_blocks", ctypes.c_int32)]
+
+
+class StbaTuneReport(ctypes.Structure):
+    _fields_ = [("chol_form", ctypes.c_int32), ("schur_blocks", ctypes.c_int32), ("chol_ms", ctypes.c_float * 4),
+                ("schur_candidates", ctypes.c_int32 * STBA_TUNE_SCHUR_CANDIDATES),
+                ("schur_ms", ctypes.c_float * STBA_TUNE_SCHUR_CANDIDATES)]
 
 
 class StbaSample(ctypes.Structure):
@@ -88,6 +97,7 @@ _SIGS = {
                                         ctypes.c_size_t, _P]),
     "stba_lm_step_profiled": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, _P, ctypes.c_size_t, _P, _P]),
     "stba_residual_vjp": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "stba_autotune": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, _P, ctypes.c_size_t, _P, _P]),
 }
 
 _lib = None
@@ -219,6 +229,20 @@ def stba_build_cluster_rcs(problem, dims, sample, damping, precision, f, Jc, Jp,
         _ref(problem), _ref(dims), _ref(sample), _ref(damping), precision, _ptr(f), _ptr(Jc), _ptr(Jp),
         _ref(out), _ptr(ws), ws.numel(), _stream(stream)))
     return out
+
+
+def stba_autotune(problem, dims, sample, damping, precision, ws, stream=None) -> dict:
+    """Fill dims.chol_form and dims.schur_blocks with the fastest settings for this
+    problem and sample (synchronises); returns what was measured."""
+    rep = StbaTuneReport()
+    _check("stba_autotune", load_library().stba_autotune(
+        _ref(problem), _ref(dims), _ref(sample), _ref(damping), precision, _ptr(ws), ws.numel(), _stream(stream),
+        _ref(rep)))
+    names = {STBA_CHOL_TILES: "tiles", STBA_CHOL_TEAM: "team", STBA_CHOL_WORKGROUP: "workgroup"}
+    return {"chol_form": names.get(rep.chol_form, "auto"), "schur_blocks": int(rep.schur_blocks),
+            "chol_ms": {names[f]: float(rep.chol_ms[f - 1]) for f in names if rep.chol_ms[f - 1] > 0},
+            "schur_ms": {int(rep.schur_candidates[i]): float(rep.schur_ms[i])
+                         for i in range(STBA_TUNE_SCHUR_CANDIDATES)}}
 
 
 def stba_solve_clusters(problem, dims, rcs, precision, Jc, Jp, dcam, dpt, cluster_status, ws, stream=None):

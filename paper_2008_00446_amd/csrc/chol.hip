@@ -1772,13 +1772,29 @@ int chol_tile_layout(int32_t l, int32_t max_Np, int32_t *wpc, int32_t *tmax, int
     return 1;
 }
 
+int chol_form_fits(int32_t form, int32_t l, int32_t max_Np, bool l_on_device, const CholTeam *team) {
+    if (form == STBA_CHOL_WORKGROUP) return 1;
+    if (form == STBA_CHOL_TILES) {
+        int32_t wpc, tmax, fpc, xcd;
+        return !l_on_device && chol_tile_layout(l, max_Np, &wpc, &tmax, &fpc, &xcd);
+    }
+    if (form == STBA_CHOL_TEAM) {
+        if (team == nullptr || team->flags == nullptr || max_Np > kTeamMaxNp) return 0;
+        const int64_t G = 15 * chol_team_resident(max_Np) / 16;
+        return G >= 3 * (int64_t)l || (l_on_device && G >= 3);
+    }
+    return 0;
+}
+
 hipError_t launch_chol(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, const int64_t *S_off,
                        const int32_t *cl_start, const int32_t *cl_cams, double *S, const double *b, double *dcam,
                        int32_t *cl_status, int32_t max_Np, int32_t *flags, double *yx, const CholTeam *team,
                        hipStream_t st) {
     int32_t wpc = 0, tmax = 0, fpc = 0, xcd = 0;
+    const int32_t form = team != nullptr ? team->form : STBA_CHOL_AUTO;
+    if (form == STBA_CHOL_WORKGROUP) goto workgroup_path;
     // with the number of clusters on the device the tile grid cannot be sized
-    if (team != nullptr && (team->force || team->l_on_device)) goto team_path;
+    if (team != nullptr && (form == STBA_CHOL_TEAM || team->l_on_device)) goto team_path;
     if (flags && yx && chol_tile_layout(l, max_Np, &wpc, &tmax, &fpc, &xcd)) {
         // the flag words are zero and the vector entries kEmpty here: set when the
         // workspace was prepared and again at the end of every factorisation
@@ -1817,6 +1833,7 @@ team_path:
             return hipGetLastError();
         }
     }
+workgroup_path:
     const size_t shmem = sizeof(double) * (2 * (size_t)kNB * (kNB + 1) + 2 * kNB + (size_t)max_Np + kCholThreads + kNB);
     k_chol<<<(unsigned)l, kCholThreads, shmem, st>>>(l, cl_n, cl_Np, S_off, cl_start, cl_cams, S, b, dcam, cl_status,
                                                      max_Np, nullptr);

@@ -1814,6 +1814,7 @@ hipError_t launch_schur(const int64_t *n_blocks, int64_t n_blocks_cap, const Sch
                         double *b, hipStream_t st) {
     int64_t wgs = (ch.chunk_cap + 3) / 4;
     if (wgs > 16384) wgs = 16384;
+    if (ch.blocks > 0) wgs = ch.blocks;
     wgs = ((wgs < 8 ? 8 : wgs) + 7) / 8 * 8;   // every XCD gets its share of workgroups
     k_schur<T><<<(unsigned)wgs, 256, 0, st>>>(ch, blk_key, blk_start, pairs, cam_cluster, l, cam_local, cl_Np,
                                               S_off, seg_head, Jc, obsd, lam2, S, b);

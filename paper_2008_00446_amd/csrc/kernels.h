@@ -83,6 +83,7 @@ struct SchurChunks {
     const int32_t *chunk_blk;
     int64_t chunk_cap;
     double *part;          // partial sums, kSchurPart doubles per chunk
+    int32_t blocks = 0;    // workgroups of k_schur (0: from the chunk count)
     int32_t all_links = 0;  // alpha = 1: every same-cluster link is kept, so the pairs of a block
                             // share their segment and the segment-head check is skipped
 };
@@ -108,13 +109,13 @@ int chol_tile_layout(int32_t l, int32_t max_Np, int32_t *wpc, int32_t *tmax, int
 // words (per cluster 2 T^2 + 8 from 2 S_off / 1024 + 8 k, then the abort word
 // at abort_at and the finished-cluster count) and four block-vector buffers of
 // vec_len doubles each (c, d per tile, y, x per block row, from S_off / 32).
-// force: take the team form even when the tile-parallel one would fit.
+// form: STBA_CHOL_* (a form that does not fit falls back to the built-in order).
 struct CholTeam {
     int32_t *flags = nullptr;
     int64_t abort_at = 0;
     double *vec = nullptr;
     int64_t vec_len = 0;
-    bool force = false;
+    int32_t form = STBA_CHOL_AUTO;
     bool l_on_device = false;   // l is a bound: the number of clusters is known only on the device
 };
 constexpr int32_t kTeamMaxNp = 2048;
@@ -124,6 +125,8 @@ inline int64_t chol_team_vec_len(int64_t S_cap) { return S_cap / 32; }
 // the flag words and block vectors have to be in their initial state before the
 // first factorisation; every tile-parallel or team factorisation leaves them so again
 hipError_t launch_clear_chol_flags(int32_t *flags, double *yx, const CholTeam *team, hipStream_t st);
+// whether launch_chol would run `form` itself (rather than fall back) for l clusters
+int chol_form_fits(int32_t form, int32_t l, int32_t max_Np, bool l_on_device, const CholTeam *team);
 // The factorisation leaves L in S's lower tiles and W_pp^T = (L_pp^-1)^T in the
 // upper triangle of each diagonal tile.
 hipError_t launch_chol(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, const int64_t *S_off,

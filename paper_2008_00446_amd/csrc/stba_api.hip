@@ -46,6 +46,8 @@ int check_dims(const stba_problem *p, const stba_dims *d) {
     if (!d || d->n_pairs < p->n || d->n_pairs < p->q || d->gamma_max < 1 || d->gamma_max > p->m)
         return STBA_EINVAL;
     if (d->max_track < 1 || d->max_track > p->q) return STBA_EINVAL;
+    if (d->chol_form < STBA_CHOL_AUTO || d->chol_form > STBA_CHOL_WORKGROUP) return STBA_EINVAL;
+    if (d->schur_blocks != 0 && (d->schur_blocks < 8 || d->schur_blocks > 65536)) return STBA_EINVAL;
     return STBA_OK;
 }
 
@@ -186,7 +188,7 @@ int front(const stba_problem *p, const stba_dims *d, int precision, void *ws, si
     return check_ws(L, ws, ws_bytes);
 }
 
-SchurChunks chunks_of(const Layout &L, void *ws, const stba_sample *s) {
+SchurChunks chunks_of(const Layout &L, void *ws, const stba_sample *s, const stba_dims *d) {
     SchurChunks c;
     c.all_links = s->alpha >= 1.0 ? 1 : 0;
     c.n_chunks = at<int64_t>(ws, L.n_chunks);
@@ -194,6 +196,7 @@ SchurChunks chunks_of(const Layout &L, void *ws, const stba_sample *s) {
     c.chunk_blk = at<int32_t>(ws, L.chunk_blk);
     c.chunk_cap = L.chunk_cap;
     c.part = at<double>(ws, L.part);
+    c.blocks = d->schur_blocks;
     return c;
 }
 
@@ -211,7 +214,7 @@ int build_rcs_impl(const stba_problem *p, const stba_dims *d, const stba_sample 
                               at<int32_t>(ws, L.grp_first), st));
     STBA_HIP(launch_fill_S(at<double>(ws, L.S), at<double>(ws, L.b), p->m, at<int64_t>(ws, L.S_off), s->l, L.S_cap,
                            st));
-    STBA_HIP(launch_schur<T>(at<int64_t>(ws, L.n_blocks), L.blk_cap, chunks_of(L, ws, s), at<int2>(ws, L.blk_key),
+    STBA_HIP(launch_schur<T>(at<int64_t>(ws, L.n_blocks), L.blk_cap, chunks_of(L, ws, s, d), at<int2>(ws, L.blk_key),
                              at<int64_t>(ws, L.blk_start), at<uint64_t>(ws, L.pairs), s->cam_cluster, s->l,
                              at<int32_t>(ws, L.cam_local), at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np),
                              at<int64_t>(ws, L.S_off),
@@ -220,22 +223,20 @@ int build_rcs_impl(const stba_problem *p, const stba_dims *d, const stba_sample 
     return STBA_OK;
 }
 
-CholTeam team_of(const Layout &L, void *ws) {
+CholTeam team_of(const Layout &L, void *ws, const stba_dims *d) {
     CholTeam t;
     t.flags = at<int32_t>(ws, L.team_flags);
     t.abort_at = L.team_abort_at;
     t.vec = at<double>(ws, L.team_vec);
     t.vec_len = L.team_vec_len;
-    // STBA_CHOL=team takes the team form whenever it fits (for tests and tuning)
-    const char *e = getenv("STBA_CHOL");
-    t.force = e != nullptr && strcmp(e, "team") == 0;
+    t.form = d != nullptr ? d->chol_form : STBA_CHOL_AUTO;
     return t;
 }
 
 // The cluster solves of Eq. 13 (FP64 Cholesky of every S_k).
-int cluster_solve(int32_t l, bool l_on_device, double *dcam, int32_t *cl_status, const Layout &L, void *ws,
-                  hipStream_t st) {
-    CholTeam team = team_of(L, ws);
+int cluster_solve(const stba_dims *d, int32_t l, bool l_on_device, double *dcam, int32_t *cl_status, const Layout &L,
+                  void *ws, hipStream_t st) {
+    CholTeam team = team_of(L, ws, d);
     team.l_on_device = l_on_device;
     STBA_HIP(launch_chol(l, at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np), at<int64_t>(ws, L.S_off),
                          at<int32_t>(ws, L.cl_start), at<int32_t>(ws, L.cl_cams), at<double>(ws, L.S),
@@ -263,11 +264,84 @@ int refine_solve(const stba_problem *p, int32_t l, const double *lam2, double *d
 template <typename T>
 int solve_impl(const stba_problem *p, const stba_dims *d, int32_t l, bool l_on_device, const T *Jc, const T *Jp,
                double *dcam, double *dpt, int32_t *cl_status, const Layout &L, void *ws, hipStream_t st) {
-    (void)d;
-    STBA_TRY(cluster_solve(l, l_on_device, dcam, cl_status, L, ws, st));
+    STBA_TRY(cluster_solve(d, l, l_on_device, dcam, cl_status, L, ws, st));
     if (L.refine) STBA_TRY(refine_solve(p, l, at<double>(ws, L.lam2), dcam, L, ws, st));
     STBA_HIP(launch_backsub<T>(*p, at<int64_t>(ws, L.pt_off), Jc, Jp, at<double>(ws, L.Vinv), at<double>(ws, L.wph),
                                dcam, dpt, L.group_size, at<int32_t>(ws, L.grp_first), L.refine, st));
+    return STBA_OK;
+}
+
+// Autotuning: best of three event-timed runs of the assembly for each Schur
+// workgroup count and of the cluster solves for each factorisation form.
+constexpr int32_t kSchurCandidates[STBA_TUNE_SCHUR_CANDIDATES] = {1024, 2048, 4096, 8192, 16384, 32768};
+
+template <typename T>
+int autotune_impl(const stba_problem *p, stba_dims *dims, const stba_sample *s, const Layout &L, void *ws,
+                  hipStream_t st, stba_tune_report *rep) {
+    T *f = at<T>(ws, L.f), *Jc = at<T>(ws, L.Jc), *Jp = at<T>(ws, L.Jp);
+    const double *lam2 = at<double>(ws, L.lam2);
+    STBA_HIP(launch_rj<T>(*p, f, Jc, Jp, nullptr, nullptr, nullptr, ZeroS(), st));
+    hipEvent_t e[2];
+    if (hipEventCreate(&e[0]) != hipSuccess) return STBA_EHIP;
+    if (hipEventCreate(&e[1]) != hipSuccess) {
+        hipEventDestroy(e[0]);
+        return STBA_EHIP;
+    }
+    int rc = STBA_OK;
+    // best of three runs of fn (with prep before each run, untimed)
+    auto best_ms = [&](auto &&prep, auto &&fn, float *out) -> int {
+        float best = 0.0f;
+        for (int r = 0; r < 3; ++r) {
+            STBA_TRY(prep());
+            if (hipEventRecord(e[0], st) != hipSuccess) return STBA_EHIP;
+            STBA_TRY(fn());
+            if (hipEventRecord(e[1], st) != hipSuccess || hipEventSynchronize(e[1]) != hipSuccess) return STBA_EHIP;
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, e[0], e[1]) != hipSuccess) return STBA_EHIP;
+            if (r == 0 || ms < best) best = ms;
+        }
+        *out = best;
+        return STBA_OK;
+    };
+    auto nothing = []() -> int { return STBA_OK; };
+    stba_dims trial = *dims;
+    auto build = [&]() -> int { return build_rcs_impl<T>(p, &trial, s, lam2, f, Jc, Jp, L, ws, st); };
+    int32_t best_blocks = 0;
+    float best = 0.0f;
+    for (int i = 0; i < STBA_TUNE_SCHUR_CANDIDATES && rc == STBA_OK; ++i) {
+        trial.schur_blocks = kSchurCandidates[i];
+        rep->schur_candidates[i] = kSchurCandidates[i];
+        rc = best_ms(nothing, build, &rep->schur_ms[i]);
+        if (rc == STBA_OK && (best_blocks == 0 || rep->schur_ms[i] < best)) {
+            best = rep->schur_ms[i];
+            best_blocks = kSchurCandidates[i];
+        }
+    }
+    trial.schur_blocks = best_blocks;
+    CholTeam team = team_of(L, ws, &trial);
+    team.l_on_device = s->l_dev != nullptr;
+    int32_t best_form = STBA_CHOL_AUTO;
+    double *dcam = at<double>(ws, L.dcam);
+    for (int32_t form = STBA_CHOL_TILES; form <= STBA_CHOL_WORKGROUP && rc == STBA_OK; ++form) {
+        rep->chol_ms[form - 1] = 0.0f;
+        if (!chol_form_fits(form, s->l, L.max_Np, team.l_on_device, &team)) continue;
+        trial.chol_form = form;
+        auto solve = [&]() -> int {
+            return cluster_solve(&trial, s->l, team.l_on_device, dcam, at<int32_t>(ws, L.cl_status), L, ws, st);
+        };
+        rc = best_ms(build, solve, &rep->chol_ms[form - 1]);   // the factorisation overwrites S: build first
+        if (rc == STBA_OK && (best_form == STBA_CHOL_AUTO || rep->chol_ms[form - 1] < best)) {
+            best = rep->chol_ms[form - 1];
+            best_form = form;
+        }
+    }
+    hipEventDestroy(e[0]);
+    hipEventDestroy(e[1]);
+    if (rc != STBA_OK) return rc;
+    dims->schur_blocks = best_blocks;
+    dims->chol_form = best_form;
+    rep->schur_blocks = best_blocks;
+    rep->chol_form = best_form;
     return STBA_OK;
 }
 
@@ -308,7 +382,7 @@ int lm_step_impl(const stba_problem *p, const stba_dims *d, const stba_sample *s
                               at<int32_t>(ws, L.grp_first), st));
     STBA_TRY(mark(3));
     STBA_TRY(mark(4));   // S was zeroed with the residuals: nothing between the marks
-    STBA_HIP(launch_schur<T>(at<int64_t>(ws, L.n_blocks), L.blk_cap, chunks_of(L, ws, s), at<int2>(ws, L.blk_key),
+    STBA_HIP(launch_schur<T>(at<int64_t>(ws, L.n_blocks), L.blk_cap, chunks_of(L, ws, s, d), at<int2>(ws, L.blk_key),
                              at<int64_t>(ws, L.blk_start), at<uint64_t>(ws, L.pairs), s->cam_cluster, s->l,
                              at<int32_t>(ws, L.cam_local), at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np),
                              at<int64_t>(ws, L.S_off),
@@ -324,7 +398,7 @@ int lm_step_impl(const stba_problem *p, const stba_dims *d, const stba_sample *s
                             L.max_Np, d->gamma_max, pcg->max_iters, pcg->tol, at<int32_t>(ws, L.pcg_iters),
                             at<double>(ws, L.pcg_resid), at<int32_t>(ws, L.cl_status), st));
     else
-        STBA_TRY(cluster_solve(s->l, s->l_dev != nullptr, dcam, at<int32_t>(ws, L.cl_status), L, ws, st));
+        STBA_TRY(cluster_solve(d, s->l, s->l_dev != nullptr, dcam, at<int32_t>(ws, L.cl_status), L, ws, st));
     STBA_TRY(mark(6));
     // the conjugate-gradient solves take no refinement step (FP64 and iterative)
     const bool refine = L.refine && pcg == nullptr;
@@ -405,6 +479,8 @@ int stba_analyze(const stba_problem *p, void *d_scratch, stba_dims *dims, hipStr
     if (h[2] != 0) return STBA_EDATA;
     dims->n_pairs = h[0];
     dims->max_track = (int32_t)h[1];
+    dims->chol_form = STBA_CHOL_AUTO;
+    dims->schur_blocks = 0;
     return STBA_OK;
 }
 
@@ -442,7 +518,7 @@ int stba_prepare(const stba_problem *p, const stba_dims *dims, int precision, vo
     b.tmp_bytes = L.tmp_bytes;
     STBA_HIP(launch_reset_status(at<int32_t>(ws, L.status), stream));
     STBA_HIP(launch_prepare(*p, dims->n_pairs, b, at<int32_t>(ws, L.status), stream));
-    const CholTeam team = team_of(L, ws);
+    const CholTeam team = team_of(L, ws, dims);
     STBA_HIP(launch_clear_chol_flags(at<int32_t>(ws, L.chol_flags), at<double>(ws, L.chol_yx), &team, stream));
     if (L.group_size > 0)
         STBA_HIP(launch_point_groups(p->n, b.pt_off, L.group_size, (p->q + L.group_size - 1) / L.group_size,
@@ -608,6 +684,20 @@ int stba_lm_step_pcg(const stba_problem *p, const stba_dims *dims, const stba_sa
     const PcgOpts o{max_iters, tol};
     if (precision == STBA_FP64) return lm_step_impl<double>(p, dims, s, st, L, ws, stream, nullptr, &o);
     return lm_step_impl<float>(p, dims, s, st, L, ws, stream, nullptr, &o);
+}
+
+int stba_autotune(const stba_problem *p, stba_dims *dims, const stba_sample *s, const stba_damping *d,
+                  int precision, void *ws, size_t ws_bytes, hipStream_t stream, stba_tune_report *report) {
+    Layout L;
+    STBA_TRY(front(p, dims, precision, ws, ws_bytes, L));
+    STBA_TRY(check_sample(p, s));
+    if (!d || !(d->lambda > 0.0) || !(d->lambda_corr >= 0.0)) return STBA_EINVAL;
+    STBA_HIP(launch_set_damping(at<double>(ws, L.lam2), d->lambda, d->lambda_corr, stream));
+    stba_tune_report local = {};
+    stba_tune_report *rep = report ? report : &local;
+    *rep = stba_tune_report{};
+    if (precision == STBA_FP64) return autotune_impl<double>(p, dims, s, L, ws, stream, rep);
+    return autotune_impl<float>(p, dims, s, L, ws, stream, rep);
 }
 
 int stba_residual_vjp(const stba_problem *p, const stba_dims *dims, int precision, const void *v, void *grad_cam,

@@ -87,6 +87,12 @@ class StbaSolver:
                                out[0:1], out[1:2], stream)
         return B.make_sample(cc, self.m, alpha, seed, it, l_dev=out[0:1])
 
+    def autotune(self, sample, cache_path=None):
+        """Choose the Schur workgroup count and the factorisation form for this
+        problem's shape class (measured once per class; see tuning.py)."""
+        from .tuning import autotune_solver
+        return autotune_solver(self, sample, cache_path)
+
     def step(self, sample, events=None, pcg=None):
         """One LM iteration (asynchronous); pcg = (max_iters, tol): the cluster
         solves by conjugate gradient instead of Cholesky."""

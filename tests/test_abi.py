@@ -107,3 +107,20 @@ def test_product_path_never_imports_the_oracle_and_has_no_fallback(tmp_path):
             if f.endswith((".py", ".hip", ".h")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
+
+
+def test_launch_settings_are_checked_on_the_host():
+    """stba_workspace_bytes (host, pure) returns 0 for dims whose factorisation
+    form or Schur workgroup count is out of range."""
+    import ctypes
+    import paper_2008_00446_amd as S
+    from paper_2008_00446_amd import binding as B
+    lib = S.load_library()
+    prob = B.StbaProblem(10, 10, 40, ctypes.c_void_p(256), ctypes.c_void_p(256), ctypes.c_void_p(256),
+                         ctypes.c_void_p(256), ctypes.c_void_p(256), 0.0)
+    ok = B.StbaDims(100, 4, 5, 0, 0)
+    assert lib.stba_workspace_bytes(ctypes.byref(prob), ctypes.byref(ok), 0) > 0
+    for form, blocks in [(4, 0), (-1, 0), (0, 7), (0, 65537)]:
+        bad = B.StbaDims(100, 4, 5, form, blocks)
+        assert lib.stba_workspace_bytes(ctypes.byref(prob), ctypes.byref(bad), 0) == 0
+    assert lib.stba_workspace_bytes(ctypes.byref(prob), ctypes.byref(B.StbaDims(100, 4, 5, 3, 8)), 0) > 0

@@ -20,17 +20,18 @@ def _state_equal(a, b):
 
 
 @pytest.mark.parametrize("which,gamma", [("ring", 50), ("slam3000", 60)])
-def test_device_count_step_matches_host_count_step(which, gamma, monkeypatch):
+def test_device_count_step_matches_host_count_step(which, gamma):
     """With the count on the device the cluster factorisation takes the team
-    form (its tile grid cannot be sized on the host); forcing that form on the
-    host-count run as well, the two runs agree bit for bit."""
-    monkeypatch.setenv("STBA_CHOL", "team")
+    form (its tile grid cannot be sized on the host); choosing that form for
+    the host-count run as well, the two runs agree bit for bit."""
     if which == "ring":
         s = synth.ring(m=200, n=50000, views=8, seed=0)
     else:
         s = synth.slam(seed=1, m=3000, n=150000)
     sols = [S.StbaSolver(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv, gamma_max=gamma, lambda0=1e-4)
             for _ in range(2)]
+    for sol in sols:
+        sol.dims.chol_form = S.STBA_CHOL_TEAM
     for t in range(3):
         host = sols[0].sample_clusters(gamma, 10.0, alpha=1.0, seed=0, it=t)   # count read back
         sols[0].step(host)

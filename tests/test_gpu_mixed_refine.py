@@ -40,8 +40,10 @@ CASES = {
 }
 
 
-def _step(s, lab, gamma_max, precision, lam, alpha, seed, t, huber):
+def _step(s, lab, gamma_max, precision, lam, alpha, seed, t, huber, team=False):
     g = GpuProblem(s, gamma_max=gamma_max, precision=precision, huber=huber)
+    if team:
+        g.dims.chol_form = S.STBA_CHOL_TEAM
     f, Jc, Jp, _ = g.residual_jacobian()
     rcs = g.build(f, Jc, Jp, lab, lam, alpha, seed, t)
     dcam, dpt, cs = g.solve(rcs, Jc, Jp)
@@ -50,17 +52,15 @@ def _step(s, lab, gamma_max, precision, lam, alpha, seed, t, huber):
 
 
 @pytest.mark.parametrize("case", list(CASES))
-def test_refinement_brings_mixed_steps_to_the_fp64_step(case, monkeypatch):
+def test_refinement_brings_mixed_steps_to_the_fp64_step(case):
     make, mp, gamma_max, lam, alpha, seed, t, huber, team = CASES[case]
-    if team:
-        monkeypatch.setenv("STBA_CHOL", "team")
     s = make()
     lab = _sgc(s, mp[1], mp[2]) if mp[0] == "sgc" else np.arange(s.m, dtype=np.int32)
     ref = O.stba_step(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv, lab, lam, alpha, seed, t, huber=huber)
-    g, dc1, dp1 = _step(s, lab, gamma_max, S.STBA_MIXED_NOREFINE, lam, alpha, seed, t, huber)
+    g, dc1, dp1 = _step(s, lab, gamma_max, S.STBA_MIXED_NOREFINE, lam, alpha, seed, t, huber, team)
     if case == "long_tracks":
         assert g.dims.max_track > 32
-    _, dc2, dp2 = _step(s, lab, gamma_max, S.STBA_MIXED, lam, alpha, seed, t, huber)
+    _, dc2, dp2 = _step(s, lab, gamma_max, S.STBA_MIXED, lam, alpha, seed, t, huber, team)
     kap = max(kappa_scaled(Sk) for Sk in ref.S_blocks)
     e1c, e1p = rel(dc1, ref.dcam), rel(dp1, ref.dpt)
     e2c, e2p = rel(dc2, ref.dcam), rel(dp2, ref.dpt)

@@ -1,6 +1,6 @@
 """The team form of the cluster factorisation (many clusters, tiles in memory,
-a band wavefront per cluster and workers sized by the cluster's work), forced
-with STBA_CHOL=team on scenes the oracle solves whole, against the oracle's
+a band wavefront per cluster and workers sized by the cluster's work), chosen
+with stba_dims.chol_form = STBA_CHOL_TEAM on scenes the oracle solves whole, against the oracle's
 steps: clusters of 1 to 15 block rows (the band alone below three), FP64 and
 MIXED, a cluster made indefinite, one cluster per camera, repeated runs bit
 for bit.  The SLAM-like workload, where the form is the default, is checked
@@ -17,9 +17,10 @@ from gpu_helpers import GpuProblem, kappa_scaled, rel, ws_view
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(autouse=True)
-def _team(monkeypatch):
-    monkeypatch.setenv("STBA_CHOL", "team")
+def _team(obj):
+    """the team form for a GpuProblem or a StbaSolver"""
+    obj.dims.chol_form = S.STBA_CHOL_TEAM
+    return obj
 
 
 def _sgc(scene, gamma, t, seed=0):
@@ -31,7 +32,7 @@ def _sgc(scene, gamma, t, seed=0):
 def test_team_steps_match_oracle(gamma, lam, alpha):
     s = synth.small_ring(m=40, n=3000, views=8, seed=1)
     lab = _sgc(s, gamma, 2)
-    g = GpuProblem(s, gamma_max=gamma)
+    g = _team(GpuProblem(s, gamma_max=gamma))
     f, Jc, Jp, _ = g.residual_jacobian()
     rcs = g.build(f, Jc, Jp, lab, lam, alpha, 5, 2)
     dcam, dpt, cs = g.solve(rcs, Jc, Jp)
@@ -49,8 +50,8 @@ def test_team_full_size_ring_iteration(precision, bar):
     """One LM iteration of the 200-camera ring (Gamma 50: up to 15 block rows)."""
     s = synth.ring(m=200, n=50000, views=8, seed=0)
     lab = _sgc(s, 50, 0)
-    sol = S.StbaSolver(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv, gamma_max=50, lambda0=1e-4,
-                       precision=precision)
+    sol = _team(S.StbaSolver(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv, gamma_max=50, lambda0=1e-4,
+                             precision=precision))
     sol.step(sol.sample(lab, alpha=1.0, seed=0, it=0))
     st = sol.read_state()
     ref = O.lm_iteration(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv, lab, 1e-4, 1.0, 0, 0)
@@ -67,7 +68,7 @@ def test_team_full_size_ring_iteration(precision, bar):
 def test_team_reports_a_cluster_that_is_not_positive_definite():
     s = synth.small_ring(m=40, n=3000, views=8, seed=1)
     lab = _sgc(s, 40, 1)
-    g = GpuProblem(s, gamma_max=40)
+    g = _team(GpuProblem(s, gamma_max=40))
     f, Jc, Jp, _ = g.residual_jacobian()
     rcs = g.build(f, Jc, Jp, lab, 1e-3)
     torch.cuda.synchronize()
@@ -92,7 +93,7 @@ def test_team_reports_a_cluster_that_is_not_positive_definite():
 def test_team_solves_are_bit_for_bit_repeatable():
     s = synth.ring(m=200, n=50000, views=8, seed=0)
     lab = _sgc(s, 50, 3)
-    g = GpuProblem(s, gamma_max=50)
+    g = _team(GpuProblem(s, gamma_max=50))
     f, Jc, Jp, _ = g.residual_jacobian()
     out = []
     for _ in range(3):
