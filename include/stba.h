@@ -218,8 +218,10 @@ int stba_residual_jacobian_static(const stba_problem *p, int precision, void *f,
  * corrected gradient when lambda >= lambda_corr (Sec. 4.3), then
  * S_k = B_k - E'_k C'^-1 E'_k^T (lower triangle, FP64 storage) and
  * b' = v' - E' C'^-1 w'.  f, Jc, Jp are the outputs of stba_residual_jacobian in
- * the same precision.  out (host) receives views into the workspace.  The
- * per-point blocks needed by stba_solve_clusters are kept in the workspace. */
+ * the same precision (in FP64 Jc must be 16-byte aligned: the assembly moves it
+ * in 16-byte parts; STBA_EINVAL else).  out (host) receives views into the
+ * workspace.  The per-point blocks needed by stba_solve_clusters are kept in
+ * the workspace. */
 int stba_build_cluster_rcs(const stba_problem *p, const stba_dims *dims, const stba_sample *s,
                            const stba_damping *d, int precision, const void *f, const void *Jc, const void *Jp,
                            stba_rcs *out, void *ws, size_t ws_bytes, hipStream_t stream);

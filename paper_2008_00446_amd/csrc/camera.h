@@ -46,22 +46,6 @@ __device__ inline void rotation_from_vector(const double w[3], double th2, const
     R[2][2] = 1.0 + b * (w[2] * w[2] - th2);
 }
 
-// Pixel of point X in camera c.
-__device__ inline void camera_project(const double c[9], const double X[3], double pix[2]) {
-    const double w[3] = {c[0], c[1], c[2]};
-    const double th2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
-    const RodCoef k = rodrigues_coefficients(th2);
-    double R[3][3];
-    rotation_from_vector(w, th2, k, R);
-    double P[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) P[i] = R[i][0] * X[0] + R[i][1] * X[1] + R[i][2] * X[2] + c[3 + i];
-    const double x = P[0] / P[2], y = P[1] / P[2];
-    const double r2 = x * x + y * y;
-    const double d = 1.0 + c[7] * r2 + c[8] * r2 * r2;
-    pix[0] = c[6] * d * x;
-    pix[1] = c[6] * d * y;
-}
 
 // The camera's part of the projection, independent of the point: R(w) (row-
 // major, 9), the right Jacobian J_r(w) (row-major, 9), t (3), f, k1, k2: 24
@@ -95,6 +79,30 @@ __device__ inline void camera_pre(const double c[9], double cp[kCamPre]) {
         }
 #pragma unroll
     for (int i = 0; i < 6; ++i) cp[18 + i] = c[3 + i];
+}
+
+// Pixel of point X from the camera's part cp: the same operations as the
+// pixel of project_jac_pre, so residuals with and without the Jacobian agree
+// bit for bit.
+__device__ inline void project_pre(const double cp[kCamPre], const double X[3], double pix[2]) {
+    const double *R = cp;
+    double P[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) P[i] = R[3 * i] * X[0] + R[3 * i + 1] * X[1] + R[3 * i + 2] * X[2] + cp[18 + i];
+    const double iz = 1.0 / P[2];
+    const double x = P[0] * iz, y = P[1] * iz;
+    const double fl = cp[21], k1 = cp[22], k2 = cp[23];
+    const double r2 = x * x + y * y;
+    const double d = 1.0 + k1 * r2 + k2 * r2 * r2;
+    pix[0] = fl * d * x;
+    pix[1] = fl * d * y;
+}
+
+// Pixel of point X in camera c.
+__device__ inline void camera_project(const double c[9], const double X[3], double pix[2]) {
+    double cp[kCamPre];
+    camera_pre(c, cp);
+    project_pre(cp, X, pix);
 }
 
 // Pixel plus Jacobian blocks Jc [2][9] and Jp [2][3] (row-major) from the

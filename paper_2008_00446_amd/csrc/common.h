@@ -9,8 +9,14 @@
 namespace stba {
 
 constexpr int kNB = 32;            // Cholesky tile order (FP64)
-constexpr int kObsRec = 32;        // per-observation record written by the point kernel:
-                                   //   Y[9][3] (27), M (m00 m01 m11), r (2)
+// Per-observation record written by the point kernel for the Schur assembly:
+// G = J_p R_s^-1 (2x3 row-major, R_s^T R_s = V*_s), M = I - J_p V*_s^-1 J_p^T
+// (m00 m01 m11), r = f + J_p V*_s^-1 w'_s (2), so that Y = J_c^T G and
+// W V*^-1 W'^T = J_c^T (G G'^T) J_c'.  FP64: [G M r pad] (12 doubles), the
+// assembly reading J_c from the Jacobian itself; FP32: [J_c G M r pad] (32
+// floats), J_c copied in (FP32 J_c rows are only 8-byte aligned).
+template <typename T> constexpr int obs_rec_elems() { return sizeof(T) == 8 ? 12 : 32; }
+inline size_t obs_rec_bytes(bool fp64) { return fp64 ? 12 * 8 : 32 * 4; }
 constexpr int kSegRec = 16;        // per-segment record at the head observation: R^-1 (6), V*^-1 (6), V*^-1 w' (3)
 constexpr int kSchurChunk = 512;   // observation pairs per Schur work item (16 rounds of 32 pair slots)
 constexpr int kSchurPart = 100;    // doubles per partial sum: 81 block entries, 9 diag(U), 9 rhs, pad

@@ -573,8 +573,40 @@ __global__ __launch_bounds__(64) void k_points(int32_t n, const int64_t *__restr
     if (!ok) set_status(status + kStPointBad, STBA_ENOTPD);
 }
 
-// Per observation o of segment s: Y_o = W_o R_s^-1, M_o = I - J_p,o V*_s^-1 J_p,o^T,
-// r_o = f_o + J_p,o V*_s^-1 w'_s (see k_points).  One thread per observation.
+// The assembly record of observation a (layout at obs_rec_elems): G = J_p R^-1
+// with R^-1 = I (upper, I00 I01 I02 I11 I12 I22), M = I - J_p V*^-1 J_p^T and
+// r = f + J_p u, u = V*^-1 w'; jc is read only for FP32.
+template <typename T>
+__device__ inline void write_obs_rec(T *__restrict__ obsd, int64_t a, const double jc[18], const double jp[6],
+                                     const Chol3 &c, const double Vi[6], const double u[3], double f0, double f1) {
+    T *rec = obsd + (int64_t)obs_rec_elems<T>() * a;
+    constexpr int kG = sizeof(T) == 8 ? 0 : 18;   // where G starts
+    if (sizeof(T) != 8) {
+#pragma unroll
+        for (int k = 0; k < 18; ++k) rec[k] = (T)jc[k];
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const double p0 = jp[3 * r], p1 = jp[3 * r + 1], p2 = jp[3 * r + 2];
+        rec[kG + 3 * r + 0] = (T)(p0 * c.I00);
+        rec[kG + 3 * r + 1] = (T)(p0 * c.I01 + p1 * c.I11);
+        rec[kG + 3 * r + 2] = (T)(p0 * c.I02 + p1 * c.I12 + p2 * c.I22);
+    }
+    double G0[3], G1[3];
+    const double r0v[3] = {jp[0], jp[1], jp[2]}, r1v[3] = {jp[3], jp[4], jp[5]};
+    sym3_mul(Vi, r0v, G0);
+    sym3_mul(Vi, r1v, G1);
+    rec[kG + 6] = (T)(1.0 - (G0[0] * jp[0] + G0[1] * jp[1] + G0[2] * jp[2]));
+    rec[kG + 7] = (T)(-(G0[0] * jp[3] + G0[1] * jp[4] + G0[2] * jp[5]));
+    rec[kG + 8] = (T)(1.0 - (G1[0] * jp[3] + G1[1] * jp[4] + G1[2] * jp[5]));
+    rec[kG + 9] = (T)(f0 + jp[0] * u[0] + jp[1] * u[1] + jp[2] * u[2]);
+    rec[kG + 10] = (T)(f1 + jp[3] * u[0] + jp[4] * u[1] + jp[5] * u[2]);
+#pragma unroll
+    for (int k = kG + 11; k < obs_rec_elems<T>(); ++k) rec[k] = (T)0;
+}
+
+// Per observation of segment s, the assembly record (see write_obs_rec) from
+// the segment record of k_points.  One thread per observation.
 template <typename T>
 __global__ __launch_bounds__(256) void k_obs_rec(int64_t q, const int32_t *__restrict__ seg_head,
                                                  const double *__restrict__ seg_rec, const T *__restrict__ f,
@@ -583,7 +615,13 @@ __global__ __launch_bounds__(256) void k_obs_rec(int64_t q, const int32_t *__res
     const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= q) return;
     const double *sr = seg_rec + (int64_t)kSegRec * seg_head[a];
-    const double I00 = sr[0], I01 = sr[1], I02 = sr[2], I11 = sr[3], I12 = sr[4], I22 = sr[5];
+    Chol3 c;
+    c.I00 = sr[0];
+    c.I01 = sr[1];
+    c.I02 = sr[2];
+    c.I11 = sr[3];
+    c.I12 = sr[4];
+    c.I22 = sr[5];
     double Vi[6], u[3];
 #pragma unroll
     for (int k = 0; k < 6; ++k) Vi[k] = sr[6 + k];
@@ -591,27 +629,11 @@ __global__ __launch_bounds__(256) void k_obs_rec(int64_t q, const int32_t *__res
     for (int k = 0; k < 3; ++k) u[k] = sr[12 + k];
     double jp[6], jc[18];
     load_jp(Jp, a, jp);
+    if (sizeof(T) != 8) {
 #pragma unroll
-    for (int k = 0; k < 18; ++k) jc[k] = (double)Jc[18 * a + k];
-    T *rec = obsd + (int64_t)kObsRec * a;
-#pragma unroll
-    for (int e = 0; e < 9; ++e) {
-        const double W0 = jc[e] * jp[0] + jc[9 + e] * jp[3];
-        const double W1 = jc[e] * jp[1] + jc[9 + e] * jp[4];
-        const double W2 = jc[e] * jp[2] + jc[9 + e] * jp[5];
-        rec[3 * e + 0] = (T)(W0 * I00);
-        rec[3 * e + 1] = (T)(W0 * I01 + W1 * I11);
-        rec[3 * e + 2] = (T)(W0 * I02 + W1 * I12 + W2 * I22);
+        for (int k = 0; k < 18; ++k) jc[k] = (double)Jc[18 * a + k];
     }
-    double G0[3], G1[3];
-    const double r0v[3] = {jp[0], jp[1], jp[2]}, r1v[3] = {jp[3], jp[4], jp[5]};
-    sym3_mul(Vi, r0v, G0);
-    sym3_mul(Vi, r1v, G1);
-    rec[27] = (T)(1.0 - (G0[0] * jp[0] + G0[1] * jp[1] + G0[2] * jp[2]));
-    rec[28] = (T)(-(G0[0] * jp[3] + G0[1] * jp[4] + G0[2] * jp[5]));
-    rec[29] = (T)(1.0 - (G1[0] * jp[3] + G1[1] * jp[4] + G1[2] * jp[5]));
-    rec[30] = (T)((double)f[2 * a] + jp[0] * u[0] + jp[1] * u[1] + jp[2] * u[2]);
-    rec[31] = (T)((double)f[2 * a + 1] + jp[3] * u[0] + jp[4] * u[1] + jp[5] * u[2]);
+    write_obs_rec<T>(obsd, a, jc, jp, c, Vi, u, (double)f[2 * a], (double)f[2 * a + 1]);
 }
 
 // ---------------------------------------------------------------------------
@@ -660,9 +682,12 @@ __global__ __launch_bounds__(64 * kPtWaves) void k_points_obs(
     double jp[6];
     load_jp(Jp, a, jp);
     const double f0 = (double)f[2 * a], f1 = (double)f[2 * a + 1];
+    // J_c goes into the record only in FP32 (the FP64 assembly reads it from Jc)
     double jc[18];
+    if (sizeof(T) != 8) {
 #pragma unroll
-    for (int k = 0; k < 18; ++k) jc[k] = (double)Jc[18 * a + k];
+        for (int k = 0; k < 18; ++k) jc[k] = (double)Jc[18 * a + k];
+    }
     const double lam = lam2[0];
     const bool corr = lam >= lam2[1];
     const int32_t cl = act ? cam_cluster[cam] : -1;
@@ -744,25 +769,7 @@ __global__ __launch_bounds__(64 * kPtWaves) void k_points_obs(
     chol3_inverse(cs, Vi);
     sym3_mul(Vi, ws, u);   // V*_s^-1 w'_s
     seg_head[a] = (int32_t)(o0 + head);
-    T *rec = obsd + (int64_t)kObsRec * a;
-#pragma unroll
-    for (int e = 0; e < 9; ++e) {
-        const double W0 = jc[e] * jp[0] + jc[9 + e] * jp[3];
-        const double W1 = jc[e] * jp[1] + jc[9 + e] * jp[4];
-        const double W2 = jc[e] * jp[2] + jc[9 + e] * jp[5];
-        rec[3 * e + 0] = (T)(W0 * cs.I00);
-        rec[3 * e + 1] = (T)(W0 * cs.I01 + W1 * cs.I11);
-        rec[3 * e + 2] = (T)(W0 * cs.I02 + W1 * cs.I12 + W2 * cs.I22);
-    }
-    double G0[3], G1[3];
-    const double r0v[3] = {jp[0], jp[1], jp[2]}, r1v[3] = {jp[3], jp[4], jp[5]};
-    sym3_mul(Vi, r0v, G0);
-    sym3_mul(Vi, r1v, G1);
-    rec[27] = (T)(1.0 - (G0[0] * jp[0] + G0[1] * jp[1] + G0[2] * jp[2]));
-    rec[28] = (T)(-(G0[0] * jp[3] + G0[1] * jp[4] + G0[2] * jp[5]));
-    rec[29] = (T)(1.0 - (G1[0] * jp[3] + G1[1] * jp[4] + G1[2] * jp[5]));
-    rec[30] = (T)(f0 + jp[0] * u[0] + jp[1] * u[1] + jp[2] * u[2]);
-    rec[31] = (T)(f1 + jp[3] * u[0] + jp[4] * u[1] + jp[5] * u[2]);
+    write_obs_rec<T>(obsd, a, jc, jp, cs, Vi, u, f0, f1);
     if (!ok) set_status(status + kStPointBad, STBA_ENOTPD);
 }
 
@@ -824,37 +831,46 @@ __device__ inline void schur_butterfly(T (&acc)[5][9], T (&du)[5], T (&rb)[5], b
     }
 }
 
-// Staging of one wavefront's work in LDS.  A batch is 32 pairs: 64 records
-// (off-diagonal) or 32 sets of J_c and record elements 26..31 (diagonal), moved
-// from memory straight into LDS by load-to-LDS instructions (no registers hold
-// them in flight), whole cache lines per instruction.
+// Staging of one wavefront's work in LDS.  A batch is 32 pairs.  An
+// observation's inputs form a virtual record of 32 elements: J_c (0..17, 2x9
+// row-major), G = J_p R^-1 (18..23), M (24..26), r (27, 28), pad; in FP64
+// J_c comes from the Jacobian and the rest from the assembly record, in FP32
+// the record holds all of it (obs_rec_elems).  Batches move from memory
+// straight into LDS by load-to-LDS instructions in 16-byte parts, whole cache
+// lines per instruction, no registers holding them in flight.
 template <typename T> struct SchurShape {
-    static constexpr int kPart = 16 / (int)sizeof(T);      // elements per 16-byte part
-    static constexpr int kLanesRec = kObsRec / kPart;        // lanes per record (16 | 8)
+    static constexpr int kPart = 16 / (int)sizeof(T);      // elements per 16-byte part (2 | 4)
+    static constexpr int kLanesRec = 32 / kPart;             // parts of a virtual record (16 | 8)
     static constexpr int kRecStep = 64 / kLanesRec;          // records per load instruction
     static constexpr int kLoads = 64 / kRecStep;             // loads per lane for 64 records
+    static constexpr int kOffParts = 24 / kPart;             // parts of J_c and G (an off-diagonal pair's use)
+    static constexpr int kDiagParts = 28 / kPart + 1;        // parts up to r (a diagonal pair's use)
     static constexpr int kStage = 256;                       // pairs compacted at a time
-    // Off-diagonal batches go from memory to LDS without passing through
-    // registers.  Load instruction i fills its own block of 64 x 16 bytes (lane j
-    // writes bytes [16 j, 16 j + 16)) with part j / kRecStep of record kRecStep i
-    // + j % kRecStep; blocks are kBlk bytes apart.  So record R starts at
-    // row_at(R), its parts kRecStep * 16 bytes apart, and the slack of kBlk over
-    // 1 KB puts the 32 records that the slots read together on 16 bank groups.
+    // part p of observation o's virtual record
+    __device__ static const T *src(const T *Jc, const T *obsd, int64_t o, int p) {
+        if (sizeof(T) == 8)
+            return p < 9 ? Jc + 18 * o + 2 * p : obsd + (int64_t)obs_rec_elems<T>() * o + 2 * (p - 9);
+        return obsd + (int64_t)obs_rec_elems<T>() * o + kPart * p;
+    }
+    // Off-diagonal batches (64 records: the 32 u, then the 32 w): load
+    // instruction i fills its own block of 64 x 16 bytes (lane j writes bytes
+    // [16 j, 16 j + 16)) with part j / kRecStep of record kRecStep i + j %
+    // kRecStep; blocks are kBlk bytes apart.  So record R starts at row_at(R), its
+    // parts kRecStep * 16 bytes apart, and the slack of kBlk over 1 KB puts the 32
+    // records that the slots read together on 16 bank groups.
     static constexpr int kBlk = 1024 + (sizeof(T) == 8 ? 64 : 128);
     static constexpr int kDmaBytes = kLoads * kBlk;
     __device__ static int row_at(int R) { return (R / kRecStep) * kBlk + (R % kRecStep) * 16; }
     __device__ static constexpr int elem_at(int k) { return (k / kPart) * kRecStep * 16 + (k % kPart) * (int)sizeof(T); }
-    // Diagonal batches: 24 elements per pair in units of kDU bytes, kDStep pairs
-    // per load instruction, blocks kDBlk bytes apart (32 pairs on 16 or 32 bank groups).
-    static constexpr int kDU = sizeof(T) == 8 ? 16 : 4;
-    static constexpr int kDUE = kDU / (int)sizeof(T);        // elements per unit
-    static constexpr int kDUnits = 24 / kDUE;                // units per pair (12 | 24)
-    static constexpr int kDStep = kDUnits > 16 ? 2 : 4;      // pairs per load instruction
-    static constexpr int kDLoads = 32 / kDStep;              // load instructions per batch
-    static constexpr int kDBlk = 64 * kDU + (sizeof(T) == 8 ? 64 : 8);
+    // Diagonal batches (32 records): kDiagParts parts per pair, kDStep pairs per
+    // load instruction (lane kDStep p + q takes part p of pair q), blocks kDBlk
+    // bytes apart; parts past kDiagParts repeat the last one into the pad.
+    static constexpr int kDStep = 4;
+    static constexpr int kDLoads = 32 / kDStep;
+    static constexpr int kDBlk = 64 * 16 + 64;
     static constexpr int kDBytes = kDLoads * kDBlk;
-    __device__ static int drow_at(int q) { return (q / kDStep) * kDBlk + (q % kDStep) * kDU; }
-    __device__ static constexpr int delem_at(int k) { return (k / kDUE) * kDStep * kDU + (k % kDUE) * (int)sizeof(T); }
+    __device__ static int drow_at(int q) { return (q / kDStep) * kDBlk + (q % kDStep) * 16; }
+    __device__ static constexpr int delem_at(int k) { return (k / kPart) * kDStep * 16 + (k % kPart) * (int)sizeof(T); }
 };
 
 template <typename T>
@@ -952,29 +968,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             int pl = lane;   // again opaque: nothing of a path is hoisted out of the stage loop
             asm volatile("" : "+v"(pl));
             if (diag) {
-                // pairs (a, a): J_c^T M J_c, diag(J_c^T J_c), J_c^T r from J_c (18
-                // elements) and record elements 26..31, straight from memory to LDS
-                // in units of kDU bytes (J_c rows of FP32 are only 8-byte aligned).
-                // Unit p of pair kDStep i + dq comes from lane kDStep p + dq of load
-                // instruction i; units past kDUnits repeat the last one into the pad.
-                const int dq = pl % Sh::kDStep, dp = min(pl / Sh::kDStep, Sh::kDUnits - 1);
-                const int el = dp * Sh::kDUE;
-                const bool from_jc = el < 18;
-                const T *src_base = (from_jc ? Jc : obsd) + (from_jc ? el : 8 + el);
-                const int64_t src_stride = from_jc ? 18 : kObsRec;
+                // pairs (a, a): J_c^T M J_c, diag(J_c^T J_c), J_c^T r
+                const int dq = pl % Sh::kDStep, dp = min(pl / Sh::kDStep, Sh::kDiagParts - 1);
                 auto fetch = [&](int bt) {
 #pragma unroll
                     for (int i = 0; i < Sh::kDLoads; ++i) {
                         const int64_t a = sp[min(bt * 32 + i * Sh::kDStep + dq, npv - 1)].x;
-                        const void *g = (const void *)(src_base + a * src_stride);
-                        auto *l = (void __attribute__((address_space(3))) *)(sb + i * Sh::kDBlk);
-                        // the unit size has to be a literal for the builtin
-                        if constexpr (Sh::kDU == 16) __builtin_amdgcn_global_load_lds(g, l, 16, 0, 0);
-                        else __builtin_amdgcn_global_load_lds(g, l, 4, 0, 0);
+                        __builtin_amdgcn_global_load_lds((const void *)Sh::src(Jc, obsd, a, dp),
+                                                         (void __attribute__((address_space(3))) *)(sb + i * Sh::kDBlk),
+                                                         16, 0, 0);
                     }
                 };
                 const char *dd = sb + Sh::drow_at(pl >> 1);
-                const char *de = dd + Sh::delem_at(e0);   // row e0 (e0 is a whole number of units)
+                const char *de = dd + Sh::delem_at(e0);   // row e0 (e0 is a whole number of parts)
                 auto d = [&](int k) -> T { return *reinterpret_cast<const T *>(dd + Sh::delem_at(k)); };
                 auto dr = [&](int k) -> T { return *reinterpret_cast<const T *>(de + Sh::delem_at(k)); };
                 for (int bt = 0; bt < nbat; ++bt) {
@@ -984,8 +990,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                     __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the batch is in LDS
                     asm volatile("" ::"v"(sb) : "memory");
                     if (bt * 32 + slot < npv) {
-                        // J_c (0..17), record 26..31 (18..23)
-                        const T m00 = d(19), m01 = d(20), m11 = d(21), r0 = d(22), r1 = d(23);
+                        const T m00 = d(24), m01 = d(25), m11 = d(26), r0 = d(27), r1 = d(28);
                         // rows e of J_c^T M, then one column of J_c at a time
                         T p0[5], p1[5];
 #pragma unroll
@@ -1005,14 +1010,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                     }
                 }
             } else {
-                // off-diagonal pairs (u, w): S_rc -= Y_u Y_w^T.  Records 0..31 of a
-                // batch are the Y_u, 32..63 the Y_w.
+                // off-diagonal pairs (u, w): S_rc -= Y_u Y_w^T = J_c,u^T (G_u G_w^T) J_c,w.
+                // Records 0..31 of a batch are the u, 32..63 the w.
                 const int yr = pl % Sh::kRecStep, yp = pl / Sh::kRecStep;
-                const T *src0 = obsd + yp * Sh::kPart;
-                // only Y (elements 0..26) is used here: the lanes of the record's
-                // last parts (M and r) move nothing
-                constexpr int kYParts = (27 + Sh::kPart - 1) / Sh::kPart;
-                const bool ypart = yp < kYParts;
+                const bool ypart = yp < Sh::kOffParts;   // the lanes of M and r move nothing
                 auto fetch = [&](int bt) {
 #pragma unroll
                     for (int i = 0; i < Sh::kLoads; ++i) {
@@ -1020,13 +1021,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                         const int2 uw = sp[min(bt * 32 + (R & 31), npv - 1)];
                         const int64_t o = R < 32 ? uw.x : uw.y;
                         if (ypart)
-                            __builtin_amdgcn_global_load_lds((const void *)(src0 + (int64_t)kObsRec * o),
+                            __builtin_amdgcn_global_load_lds((const void *)Sh::src(Jc, obsd, o, yp),
                                                              (void __attribute__((address_space(3))) *)(sb + i * Sh::kBlk),
                                                              16, 0, 0);
                     }
                 };
-                const char *ru = sb + Sh::row_at(pl >> 1) + Sh::elem_at(3 * e0);   // Y_u from row e0
+                const char *ru = sb + Sh::row_at(pl >> 1);
+                const char *rue = ru + Sh::elem_at(e0);   // J_c,u from row e0 (a whole number of parts)
                 const char *rw = sb + Sh::row_at(32 + (pl >> 1));
+                auto eu = [&](int k) -> T { return *reinterpret_cast<const T *>(ru + Sh::elem_at(k)); };
+                auto eue = [&](int k) -> T { return *reinterpret_cast<const T *>(rue + Sh::elem_at(k)); };
+                auto ew = [&](int k) -> T { return *reinterpret_cast<const T *>(rw + Sh::elem_at(k)); };
                 for (int bt = 0; bt < nbat; ++bt) {
                     // the previous batch has been read before the next one lands
                     __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0)
@@ -1035,20 +1040,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                     __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the batch is in LDS
                     asm volatile("" ::"v"(sb) : "memory");
                     if (bt * 32 + slot < npv) {
-                        T a[5][3];
+                        // m = G_u G_w^T (2 x 2)
+                        T m[2][2];
 #pragma unroll
-                        for (int i = 0; i < 5; ++i)
+                        for (int a2 = 0; a2 < 2; ++a2)
 #pragma unroll
-                            for (int t = 0; t < 3; ++t)
-                                a[i][t] = *reinterpret_cast<const T *>(ru + Sh::elem_at(3 * i + t));
+                            for (int b2 = 0; b2 < 2; ++b2)
+                                m[a2][b2] = fma(eu(18 + 3 * a2 + 2), ew(18 + 3 * b2 + 2),
+                                                fma(eu(18 + 3 * a2 + 1), ew(18 + 3 * b2 + 1),
+                                                    eu(18 + 3 * a2) * ew(18 + 3 * b2)));
+                        // rows e of J_c,u^T m, then one column of J_c,w at a time
+                        T p0[5], p1[5];
+#pragma unroll
+                        for (int i = 0; i < 5; ++i) {
+                            const T je0 = eue(i), je1 = eue(9 + i);
+                            p0[i] = fma(je1, m[1][0], je0 * m[0][0]);
+                            p1[i] = fma(je1, m[1][1], je0 * m[0][1]);
+                        }
 #pragma unroll
                         for (int k = 0; k < 9; ++k) {
-                            const T y0 = *reinterpret_cast<const T *>(rw + Sh::elem_at(3 * k));
-                            const T y1 = *reinterpret_cast<const T *>(rw + Sh::elem_at(3 * k + 1));
-                            const T y2 = *reinterpret_cast<const T *>(rw + Sh::elem_at(3 * k + 2));
+                            const T j0 = ew(k), j1 = ew(9 + k);
 #pragma unroll
-                            for (int i = 0; i < 5; ++i)
-                                acc[i][k] = fma(a[i][2], y2, fma(a[i][1], y1, fma(a[i][0], y0, acc[i][k])));
+                            for (int i = 0; i < 5; ++i) acc[i][k] = fma(p1[i], j1, fma(p0[i], j0, acc[i][k]));
                         }
                     }
                 }

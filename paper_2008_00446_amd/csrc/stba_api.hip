@@ -130,7 +130,7 @@ bool make_layout(const stba_problem *p, const stba_dims *d, int precision, Layou
     L.group_size = point_group_size(d->max_track);
     // the staged segment records are used only when the one-lane-per-observation path is off
     L.seg_rec = take(L.group_size > 0 ? 8 : 8 * (size_t)kSegRec * q);
-    L.obsd = take(es * kObsRec * q);
+    L.obsd = take(obs_rec_bytes(precision == STBA_FP64) * q);
     L.Vinv = take(8 * 6 * n);
     L.wph = take(8 * 3 * n);
     L.max_Np = (int32_t)round_up(9 * (int64_t)d->gamma_max, kNB);
@@ -568,6 +568,7 @@ int stba_build_cluster_rcs(const stba_problem *p, const stba_dims *dims, const s
     STBA_TRY(front(p, dims, precision, ws, ws_bytes, L));
     STBA_TRY(check_sample(p, s));
     if (!d || !(d->lambda > 0.0) || !(d->lambda_corr >= 0.0) || !f || !Jc || !Jp || !out) return STBA_EINVAL;
+    if (precision == STBA_FP64 && (reinterpret_cast<uintptr_t>(Jc) & 15) != 0) return STBA_EINVAL;
     double *lam2 = at<double>(ws, L.lam2);
     STBA_HIP(launch_set_damping(lam2, d->lambda, d->lambda_corr, stream));
     if (precision == STBA_FP64)
