@@ -852,25 +852,27 @@ template <typename T> struct SchurShape {
             return p < 9 ? Jc + 18 * o + 2 * p : obsd + (int64_t)obs_rec_elems<T>() * o + 2 * (p - 9);
         return obsd + (int64_t)obs_rec_elems<T>() * o + kPart * p;
     }
-    // Off-diagonal batches (64 records: the 32 u, then the 32 w): load
+    // Batches: the 32 u records (side 0), then the 32 w (side 1) of an
+    // off-diagonal batch, or the 32 records of a diagonal one (side 0).  Load
     // instruction i fills its own block of 64 x 16 bytes (lane j writes bytes
-    // [16 j, 16 j + 16)) with part j / kRecStep of record kRecStep i + j %
-    // kRecStep; blocks are kBlk bytes apart.  So record R starts at row_at(R), its
-    // parts kRecStep * 16 bytes apart, and the slack of kBlk over 1 KB puts the 32
-    // records that the slots read together on 16 bank groups.
-    static constexpr int kBlk = 1024 + (sizeof(T) == 8 ? 64 : 128);
+    // [16 j, 16 j + 16)) record by record: lanes kLanesRec q .. kLanesRec q +
+    // kLanesRec - 1 take the parts of one record, so every four lanes read 64
+    // contiguous bytes (the address unit serves them as one access instead of
+    // four).  Instruction i of a side holds the records of slots i, i + kNI, ..,
+    // so the four slots that eight consecutive lanes read together sit in
+    // blocks kBlk bytes apart, on four different bank groups.
+    static constexpr int kNI = 32 / kRecStep;                // load instructions per side
+    static constexpr int kBlk = 1024 + 64;
     static constexpr int kDmaBytes = kLoads * kBlk;
-    __device__ static int row_at(int R) { return (R / kRecStep) * kBlk + (R % kRecStep) * 16; }
-    __device__ static constexpr int elem_at(int k) { return (k / kPart) * kRecStep * 16 + (k % kPart) * (int)sizeof(T); }
-    // Diagonal batches (32 records): kDiagParts parts per pair, kDStep pairs per
-    // load instruction (lane kDStep p + q takes part p of pair q), blocks kDBlk
-    // bytes apart; parts past kDiagParts repeat the last one into the pad.
-    static constexpr int kDStep = 4;
-    static constexpr int kDLoads = 32 / kDStep;
-    static constexpr int kDBlk = 64 * 16 + 64;
-    static constexpr int kDBytes = kDLoads * kDBlk;
-    __device__ static int drow_at(int q) { return (q / kDStep) * kDBlk + (q % kDStep) * 16; }
-    __device__ static constexpr int delem_at(int k) { return (k / kPart) * kDStep * 16 + (k % kPart) * (int)sizeof(T); }
+    __device__ static int row_at(int R) {
+        const int s = R & 31;
+        return ((R >> 5) * kNI + s % kNI) * kBlk + (s / kNI) * kLanesRec * 16;
+    }
+    __device__ static constexpr int elem_at(int k) { return (k / kPart) * 16 + (k % kPart) * (int)sizeof(T); }
+    // diagonal batches: side 0 only, kDiagParts parts per record (lanes past
+    // them repeat the last one into the pad)
+    static constexpr int kDLoads = kNI;
+    static constexpr int kDBytes = kDLoads * kBlk;
 };
 
 template <typename T>
@@ -969,20 +971,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             asm volatile("" : "+v"(pl));
             if (diag) {
                 // pairs (a, a): J_c^T M J_c, diag(J_c^T J_c), J_c^T r
-                const int dq = pl % Sh::kDStep, dp = min(pl / Sh::kDStep, Sh::kDiagParts - 1);
+                const int dq = pl / Sh::kLanesRec, dp = min(pl % Sh::kLanesRec, Sh::kDiagParts - 1);
                 auto fetch = [&](int bt) {
+                    int64_t a[Sh::kDLoads];
 #pragma unroll
-                    for (int i = 0; i < Sh::kDLoads; ++i) {
-                        const int64_t a = sp[min(bt * 32 + i * Sh::kDStep + dq, npv - 1)].x;
-                        __builtin_amdgcn_global_load_lds((const void *)Sh::src(Jc, obsd, a, dp),
-                                                         (void __attribute__((address_space(3))) *)(sb + i * Sh::kDBlk),
+                    for (int i = 0; i < Sh::kDLoads; ++i) a[i] = sp[min(bt * 32 + dq * Sh::kNI + i, npv - 1)].x;
+#pragma unroll
+                    for (int i = 0; i < Sh::kDLoads; ++i)
+                        __builtin_amdgcn_global_load_lds((const void *)Sh::src(Jc, obsd, a[i], dp),
+                                                         (void __attribute__((address_space(3))) *)(sb + i * Sh::kBlk),
                                                          16, 0, 0);
-                    }
                 };
-                const char *dd = sb + Sh::drow_at(pl >> 1);
-                const char *de = dd + Sh::delem_at(e0);   // row e0 (e0 is a whole number of parts)
-                auto d = [&](int k) -> T { return *reinterpret_cast<const T *>(dd + Sh::delem_at(k)); };
-                auto dr = [&](int k) -> T { return *reinterpret_cast<const T *>(de + Sh::delem_at(k)); };
+                const char *dd = sb + Sh::row_at(pl >> 1);
+                const char *de = dd + Sh::elem_at(e0);   // row e0 (e0 is a whole number of parts)
+                auto d = [&](int k) -> T { return *reinterpret_cast<const T *>(dd + Sh::elem_at(k)); };
+                auto dr = [&](int k) -> T { return *reinterpret_cast<const T *>(de + Sh::elem_at(k)); };
                 for (int bt = 0; bt < nbat; ++bt) {
                     __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): the previous batch has been read
                     asm volatile("" ::: "memory");
@@ -1012,19 +1015,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             } else {
                 // off-diagonal pairs (u, w): S_rc -= Y_u Y_w^T = J_c,u^T (G_u G_w^T) J_c,w.
                 // Records 0..31 of a batch are the u, 32..63 the w.
-                const int yr = pl % Sh::kRecStep, yp = pl / Sh::kRecStep;
+                const int yr = pl / Sh::kLanesRec, yp = pl % Sh::kLanesRec;
                 const bool ypart = yp < Sh::kOffParts;   // the lanes of M and r move nothing
                 auto fetch = [&](int bt) {
+                    // every record index first, then the loads
+                    int64_t o[Sh::kLoads];
 #pragma unroll
-                    for (int i = 0; i < Sh::kLoads; ++i) {
-                        const int R = i * Sh::kRecStep + yr;
-                        const int2 uw = sp[min(bt * 32 + (R & 31), npv - 1)];
-                        const int64_t o = R < 32 ? uw.x : uw.y;
+                    for (int i = 0; i < Sh::kNI; ++i) {
+                        const int2 uw = sp[min(bt * 32 + yr * Sh::kNI + i, npv - 1)];
+                        o[i] = uw.x;
+                        o[Sh::kNI + i] = uw.y;
+                    }
+#pragma unroll
+                    for (int i = 0; i < Sh::kLoads; ++i)
                         if (ypart)
-                            __builtin_amdgcn_global_load_lds((const void *)Sh::src(Jc, obsd, o, yp),
+                            __builtin_amdgcn_global_load_lds((const void *)Sh::src(Jc, obsd, o[i], yp),
                                                              (void __attribute__((address_space(3))) *)(sb + i * Sh::kBlk),
                                                              16, 0, 0);
-                    }
                 };
                 const char *ru = sb + Sh::row_at(pl >> 1);
                 const char *rue = ru + Sh::elem_at(e0);   // J_c,u from row e0 (a whole number of parts)

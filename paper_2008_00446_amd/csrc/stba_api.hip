@@ -284,7 +284,7 @@ int autotune_impl(const stba_problem *p, stba_dims *dims, const stba_sample *s, 
     hipEvent_t e[2];
     if (hipEventCreate(&e[0]) != hipSuccess) return STBA_EHIP;
     if (hipEventCreate(&e[1]) != hipSuccess) {
-        hipEventDestroy(e[0]);
+        (void)hipEventDestroy(e[0]);
         return STBA_EHIP;
     }
     int rc = STBA_OK;
@@ -335,8 +335,8 @@ int autotune_impl(const stba_problem *p, stba_dims *dims, const stba_sample *s, 
             best_form = form;
         }
     }
-    hipEventDestroy(e[0]);
-    hipEventDestroy(e[1]);
+    (void)hipEventDestroy(e[0]);
+    (void)hipEventDestroy(e[1]);
     if (rc != STBA_OK) return rc;
     dims->schur_blocks = best_blocks;
     dims->chol_form = best_form;
