@@ -791,7 +791,9 @@ def diff_batch_leg(S, args):
     Jacobian recomputed) per pass, in FP32, timed over K passes.  Algorithmic
     bytes per pass: forward ids, pixel and f (24 + 2 es per observation),
     backward ids, v and the pixel gradient (8 + 4 es per observation), plus the
-    gathered and reduced camera and point rows."""
+    gathered and reduced camera and point rows.  The same with the Jacobian
+    stored: the forward pass also writes J and the backward pass reads it
+    (stba_residual_vjp_stored), 48 es more per observation."""
     import torch
     import synth
     batch = synth.diff_batch(seeds=range(64))
@@ -813,20 +815,36 @@ def diff_batch_leg(S, args):
     gp = torch.empty((n, 3), dtype=torch.float32, device="cuda")
     gu = torch.empty((q, 2), dtype=torch.float32, device="cuda")
 
+    Jc = torch.empty((q, 18), dtype=torch.float32, device="cuda")
+    Jp = torch.empty((q, 6), dtype=torch.float32, device="cuda")
+
     def one():
         S.stba_residual_jacobian(prob, plan.dims, S.STBA_MIXED, f, None, None, None, plan.ws)
         torch.mul(f, 2.0, out=v)
         S.stba_residual_vjp(prob, plan.dims, S.STBA_MIXED, v, gc, gp, gu, plan.ws)
 
-    for _ in range(args.warmup):
-        one()
+    def one_stored():
+        # J kept from the forward pass (24 values per observation) and read back
+        S.stba_residual_jacobian(prob, plan.dims, S.STBA_MIXED, f, Jc, Jp, None, plan.ws)
+        torch.mul(f, 2.0, out=v)
+        S.stba_residual_vjp_stored(prob, plan.dims, S.STBA_MIXED, v, Jc, Jp, gc, gp, gu, plan.ws)
+
     K = 20
-    dt = timed(lambda: [one() for _ in range(K)])
     es = 4
     algo = q * ((24 + 2 * es) + (8 + 4 * es) + 2 * es) + (m * 72 + n * 24) + (m * 9 + n * 3) * es
-    return {"problems": len(batch), "observations": q, "cameras": m, "points": n, "passes": K,
-            "us_per_fwd_bwd": 1e6 * dt / K, "GB_per_s_algorithmic": algo * K / dt / 1e9,
-            "hbm_frac": algo * K / dt / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes_per_pass": algo}
+    algo_st = algo + q * 2 * 24 * es   # the blocks written forward and read back
+    res = {"problems": len(batch), "observations": q, "cameras": m, "points": n, "passes": K}
+    for name, fn, a in (("recompute", one, algo), ("stored", one_stored, algo_st)):
+        for _ in range(args.warmup):
+            fn()
+        dt = timed(lambda: [fn() for _ in range(K)])
+        leg = {"us_per_fwd_bwd": 1e6 * dt / K, "GB_per_s_algorithmic": a * K / dt / 1e9,
+               "hbm_frac": a * K / dt / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes_per_pass": a}
+        if name == "recompute":
+            res.update(leg)
+        else:
+            res["stored_jacobian"] = leg
+    return res
 
 
 SGC_BETA = 10.0   # the clustering's scale beta

@@ -364,6 +364,17 @@ int stba_autotune(const stba_problem *p, stba_dims *dims, const stba_sample *s, 
 int stba_residual_vjp(const stba_problem *p, const stba_dims *dims, int precision, const void *v,
                       void *grad_cam, void *grad_pt, void *grad_uv, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* The same products with J read instead of recomputed: Jc [q][18] and Jp
+ * [q][6] (device, same precision as v, row-major as stba_residual_jacobian
+ * writes them) must hold the blocks at the x of p (the caller keeps them from
+ * the forward evaluation; the memory-for-time choice of the differentiable
+ * residual).  Same sums in the same order as stba_residual_vjp (in FP64 the
+ * two agree to rounding).  Errors as stba_residual_vjp (STBA_EINVAL also for a
+ * null Jc or Jp). */
+int stba_residual_vjp_stored(const stba_problem *p, const stba_dims *dims, int precision, const void *v,
+                             const void *Jc, const void *Jp, void *grad_cam, void *grad_pt, void *grad_uv, void *ws,
+                             size_t ws_bytes, hipStream_t stream);
+
 /* Library version string (host). */
 const char *stba_version(void);
 

@@ -97,6 +97,7 @@ _SIGS = {
                                         ctypes.c_size_t, _P]),
     "stba_lm_step_profiled": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, _P, ctypes.c_size_t, _P, _P]),
     "stba_residual_vjp": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "stba_residual_vjp_stored": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "stba_autotune": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, _P, ctypes.c_size_t, _P, _P]),
 }
 
@@ -295,6 +296,12 @@ def stba_residual_vjp(problem, dims, precision, v, grad_cam, grad_pt, grad_uv, w
     _check("stba_residual_vjp", load_library().stba_residual_vjp(
         _ref(problem), _ref(dims), precision, _ptr(v), _ptr(grad_cam), _ptr(grad_pt), _ptr(grad_uv), _ptr(ws),
         ws.numel(), _stream(stream)))
+
+
+def stba_residual_vjp_stored(problem, dims, precision, v, Jc, Jp, grad_cam, grad_pt, grad_uv, ws, stream=None):
+    _check("stba_residual_vjp_stored", load_library().stba_residual_vjp_stored(
+        _ref(problem), _ref(dims), precision, _ptr(v), _ptr(Jc), _ptr(Jp), _ptr(grad_cam), _ptr(grad_pt),
+        _ptr(grad_uv), _ptr(ws), ws.numel(), _stream(stream)))
 
 
 def read_state(state: torch.Tensor) -> dict:

@@ -1706,6 +1706,56 @@ __global__ __launch_bounds__(256) void k_vjp_pt(int32_t n, int64_t q, const doub
     for (int k = 0; k < 3; ++k) grad_pt[3 * j + k] = (T)acc[k];
 }
 
+// J^T v from the stored blocks (J_c, J_p as the residual kernel wrote them for
+// this x): the same sums as k_vjp_cam / k_vjp_pt, in the same order, with each
+// block read instead of recomputed.
+template <typename T>
+__global__ __launch_bounds__(256) void k_vjp_cam_stored(int32_t m, const int64_t *__restrict__ diag_blk,
+                                                        const int64_t *__restrict__ blk_start,
+                                                        const uint64_t *__restrict__ pairs, const T *__restrict__ Jc,
+                                                        const T *__restrict__ v, T *__restrict__ grad_cam) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r = xcd_contiguous_item(blockIdx.x, gridDim.x, threadIdx.x >> 6);
+    if (r >= m) return;
+    double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const int64_t kb = diag_blk[r];
+    if (kb >= 0) {
+        for (int64_t p = blk_start[kb] + lane; p < blk_start[kb + 1]; p += 64) {
+            const int64_t o = (int64_t)(pairs[p] >> 32);
+            const T *jc = Jc + 18 * o;
+            const double v0 = (double)v[2 * o], v1 = (double)v[2 * o + 1];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) acc[k] += (double)jc[k] * v0 + (double)jc[9 + k] * v1;
+        }
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1)
+#pragma unroll
+        for (int k = 0; k < 9; ++k) acc[k] += __shfl_xor(acc[k], d, 64);
+    double g = 0.0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+        if (lane == k) g = acc[k];
+    if (lane < 9) grad_cam[9 * r + lane] = (T)g;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_vjp_pt_stored(int32_t n, const int64_t *__restrict__ pt_off,
+                                                       const T *__restrict__ Jp, const T *__restrict__ v,
+                                                       T *__restrict__ grad_pt) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double acc[3] = {0, 0, 0};
+    for (int64_t o = pt_off[j]; o < pt_off[j + 1]; ++o) {
+        const T *jp = Jp + 6 * o;
+        const double v0 = (double)v[2 * o], v1 = (double)v[2 * o + 1];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) acc[k] += (double)jp[k] * v0 + (double)jp[3 + k] * v1;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) grad_pt[3 * j + k] = (T)acc[k];
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_neg(int64_t len, const T *v, T *out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1934,6 +1984,21 @@ hipError_t launch_vjp(const stba_problem &p, const int64_t *pt_off, const int64_
     k_neg<T><<<grid_for(2 * p.q), 256, 0, st>>>(2 * p.q, v, grad_uv);
     return hipGetLastError();
 }
+template <typename T>
+hipError_t launch_vjp_stored(const stba_problem &p, const int64_t *pt_off, const int64_t *diag_blk,
+                             const int64_t *blk_start, const uint64_t *pairs, const T *v, const T *Jc, const T *Jp,
+                             T *grad_cam, T *grad_pt, T *grad_uv, hipStream_t st) {
+    k_vjp_cam_stored<T><<<xcd_contiguous_grid(p.m), 256, 0, st>>>(p.m, diag_blk, blk_start, pairs, Jc, v, grad_cam);
+    k_vjp_pt_stored<T><<<grid_for(p.n), 256, 0, st>>>(p.n, pt_off, Jp, v, grad_pt);
+    k_neg<T><<<grid_for(2 * p.q), 256, 0, st>>>(2 * p.q, v, grad_uv);
+    return hipGetLastError();
+}
+template hipError_t launch_vjp_stored<double>(const stba_problem &, const int64_t *, const int64_t *, const int64_t *,
+                                              const uint64_t *, const double *, const double *, const double *,
+                                              double *, double *, double *, hipStream_t);
+template hipError_t launch_vjp_stored<float>(const stba_problem &, const int64_t *, const int64_t *, const int64_t *,
+                                             const uint64_t *, const float *, const float *, const float *, float *,
+                                             float *, float *, hipStream_t);
 template hipError_t launch_vjp<double>(const stba_problem &, const int64_t *, const int64_t *, const int2 *,
                                        const int64_t *, const uint64_t *, const double *, double *, double *,
                                        double *, hipStream_t);

@@ -168,6 +168,11 @@ template <typename T>
 hipError_t launch_vjp(const stba_problem &p, const int64_t *pt_off, const int64_t *diag_blk,
                       const int2 *blk_key, const int64_t *blk_start, const uint64_t *pairs, const T *v,
                       T *grad_cam, T *grad_pt, T *grad_uv, hipStream_t st);
+// The same products from stored blocks Jc [q][18], Jp [q][6] (precision T).
+template <typename T>
+hipError_t launch_vjp_stored(const stba_problem &p, const int64_t *pt_off, const int64_t *diag_blk,
+                             const int64_t *blk_start, const uint64_t *pairs, const T *v, const T *Jc, const T *Jp,
+                             T *grad_cam, T *grad_pt, T *grad_uv, hipStream_t st);
 
 // --- camera clustering (sgc.hip) ---------------------------------------------
 // One workgroup; Pg / Tg / Wg hold a pair label, clock and weight per block of

@@ -717,4 +717,23 @@ int stba_residual_vjp(const stba_problem *p, const stba_dims *dims, int precisio
     return STBA_OK;
 }
 
+int stba_residual_vjp_stored(const stba_problem *p, const stba_dims *dims, int precision, const void *v,
+                             const void *Jc, const void *Jp, void *grad_cam, void *grad_pt, void *grad_uv, void *ws,
+                             size_t ws_bytes, hipStream_t stream) {
+    Layout L;
+    STBA_TRY(front(p, dims, precision, ws, ws_bytes, L));
+    if (!v || !Jc || !Jp || !grad_cam || !grad_pt || !grad_uv) return STBA_EINVAL;
+    if (precision == STBA_FP64)
+        STBA_HIP(launch_vjp_stored<double>(*p, at<int64_t>(ws, L.pt_off), at<int64_t>(ws, L.diag_blk),
+                                           at<int64_t>(ws, L.blk_start), at<uint64_t>(ws, L.pairs), (const double *)v,
+                                           (const double *)Jc, (const double *)Jp, (double *)grad_cam,
+                                           (double *)grad_pt, (double *)grad_uv, stream));
+    else
+        STBA_HIP(launch_vjp_stored<float>(*p, at<int64_t>(ws, L.pt_off), at<int64_t>(ws, L.diag_blk),
+                                          at<int64_t>(ws, L.blk_start), at<uint64_t>(ws, L.pairs), (const float *)v,
+                                          (const float *)Jc, (const float *)Jp, (float *)grad_cam, (float *)grad_pt,
+                                          (float *)grad_uv, stream));
+    return STBA_OK;
+}
+
 }  // extern "C"

@@ -108,9 +108,14 @@ class StbaSolver:
 
 
 class ResidualPlan:
-    """Static structure (visibility graph) for repeated residual / J^T v calls."""
+    """Static structure (visibility graph) for repeated residual / J^T v calls.
 
-    def __init__(self, obs_cam, obs_pt, m, n, precision=B.STBA_FP64, device="cuda"):
+    store_jacobian: keep J (24 values per observation) from the forward pass and
+    read it in the backward pass, instead of recomputing it (the default, for
+    when memory is short)."""
+
+    def __init__(self, obs_cam, obs_pt, m, n, precision=B.STBA_FP64, device="cuda", store_jacobian=False):
+        self.store_jacobian = bool(store_jacobian)
         self.obs_cam = torch.as_tensor(obs_cam, dtype=torch.int32).to(device).contiguous()
         self.obs_pt = torch.as_tensor(obs_pt, dtype=torch.int32).to(device).contiguous()
         self.m, self.n, self.q = int(m), int(n), int(self.obs_cam.shape[0])
@@ -135,27 +140,38 @@ class _Residuals(torch.autograd.Function):
         cam_d, pt_d, uv_d = cam.detach(), pt.detach(), obs_uv.detach()
         prob = plan.problem(cam_d, pt_d, uv_d)
         f = torch.empty((plan.q, 2), dtype=plan.dtype, device=cam.device)
-        B.stba_residual_jacobian(prob, plan.dims, plan.precision, f, None, None, None, plan.ws)
-        ctx.save_for_backward(cam_d, pt_d, uv_d)
+        if plan.store_jacobian:
+            Jc = torch.empty((plan.q, 18), dtype=plan.dtype, device=cam.device)
+            Jp = torch.empty((plan.q, 6), dtype=plan.dtype, device=cam.device)
+            B.stba_residual_jacobian(prob, plan.dims, plan.precision, f, Jc, Jp, None, plan.ws)
+            ctx.save_for_backward(cam_d, pt_d, uv_d, Jc, Jp)
+        else:
+            B.stba_residual_jacobian(prob, plan.dims, plan.precision, f, None, None, None, plan.ws)
+            ctx.save_for_backward(cam_d, pt_d, uv_d)
         ctx.plan = plan
         return f
 
     @staticmethod
     def backward(ctx, grad_f):
-        cam, pt, uv = ctx.saved_tensors
         plan = ctx.plan
+        cam, pt, uv = ctx.saved_tensors[:3]
         prob = plan.problem(cam, pt, uv)
         v = grad_f.to(plan.dtype).contiguous()
         gc = torch.empty((plan.m, 9), dtype=plan.dtype, device=cam.device)
         gp = torch.empty((plan.n, 3), dtype=plan.dtype, device=cam.device)
         gu = torch.empty((plan.q, 2), dtype=plan.dtype, device=cam.device)
-        B.stba_residual_vjp(prob, plan.dims, plan.precision, v, gc, gp, gu, plan.ws)
+        if plan.store_jacobian:
+            Jc, Jp = ctx.saved_tensors[3:]
+            B.stba_residual_vjp_stored(prob, plan.dims, plan.precision, v, Jc, Jp, gc, gp, gu, plan.ws)
+        else:
+            B.stba_residual_vjp(prob, plan.dims, plan.precision, v, gc, gp, gu, plan.ws)
         return gc.to(cam.dtype), gp.to(pt.dtype), gu.to(uv.dtype), None
 
 
 def residuals(cam, pt, obs_uv, plan: ResidualPlan):
     """Reprojection residuals f (pixel - observed) as a differentiable function of
-    cam, pt and obs_uv; the backward pass is J^T v with J recomputed on the GPU."""
+    cam, pt and obs_uv; the backward pass is J^T v on the GPU, with J recomputed
+    or, for a plan made with store_jacobian=True, kept from the forward pass."""
     return _Residuals.apply(cam, pt, obs_uv, plan)
 
 

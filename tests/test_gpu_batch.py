@@ -146,3 +146,46 @@ def test_64_problem_batch_gradient_against_central_differences(precision, rtol):
             worst = max(worst, err)
             assert err <= rtol, (s.n, j, k, gp[p0 + j, k], fd)
     print(f"64 problems x 200 coordinates: worst |g - fd| / max(1, |fd|) = {worst:.2e}", flush=True)
+
+
+@pytest.mark.parametrize("precision", [S.STBA_FP64, S.STBA_MIXED], ids=["fp64", "fp32"])
+def test_stored_jacobian_vjp_matches_recompute_and_oracle(precision):
+    """The stored-Jacobian backward pass (J kept from the forward evaluation)
+    against the recomputing one: the same sums in the same order, so FP64 agrees
+    to rounding (the compiler fuses the block's last products into the sums
+    differently in the two kernels); FP32 stores rounded blocks and agrees to
+    FP32 rounding.  Both against the oracle's gradient 2 J^T f per problem."""
+    batch = synth.diff_batch(seeds=range(6))
+    cam, pt, oc, op, uv, spans = _concat(batch)
+    grads = {}
+    for store in (False, True):
+        plan = S.ResidualPlan(oc, op, cam.shape[0], pt.shape[0], precision, store_jacobian=store)
+        tc = dev(cam, torch.float64).requires_grad_(True)
+        tp = dev(pt, torch.float64).requires_grad_(True)
+        tu = dev(uv, torch.float64).requires_grad_(True)
+        f = S.residuals(tc, tp, tu, plan)
+        (f.double() ** 2).sum().backward()
+        grads[store] = [t.grad.cpu().numpy() for t in (tc, tp, tu)]
+    for a, b in zip(grads[False], grads[True]):
+        assert rel(b, a) < (1e-13 if precision == S.STBA_FP64 else 1e-5)
+    tol = 1e-12 if precision == S.STBA_FP64 else 1e-5
+    gc, gp, gu = grads[True]
+    q0 = 0
+    for s, (c0, c1, p0, p1) in zip(batch, spans):
+        rc, rp, ru = O.gradient(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv)
+        assert rel(gc[c0:c1], rc) < tol and rel(gp[p0:p1], rp) < tol
+        assert rel(gu[q0:q0 + s.q], ru) < tol
+        q0 += s.q
+
+
+def test_stored_jacobian_vjp_rejects_missing_blocks():
+    batch = synth.diff_batch(seeds=range(1))
+    cam, pt, oc, op, uv, _ = _concat(batch)
+    plan = S.ResidualPlan(oc, op, cam.shape[0], pt.shape[0], S.STBA_FP64, store_jacobian=True)
+    prob = plan.problem(dev(cam, torch.float64), dev(pt, torch.float64), dev(uv, torch.float64))
+    v = torch.zeros((plan.q, 2), dtype=torch.float64, device="cuda")
+    gc = torch.empty((plan.m, 9), dtype=torch.float64, device="cuda")
+    gp = torch.empty((plan.n, 3), dtype=torch.float64, device="cuda")
+    gu = torch.empty((plan.q, 2), dtype=torch.float64, device="cuda")
+    with pytest.raises(S.StbaError):
+        S.stba_residual_vjp_stored(prob, plan.dims, S.STBA_FP64, v, None, None, gc, gp, gu, plan.ws)
