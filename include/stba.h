@@ -308,6 +308,30 @@ int stba_lm_init(stba_lm_state *st, double lambda0, double lambda_corr, hipStrea
 int stba_lm_step(const stba_problem *p, const stba_dims *dims, const stba_sample *s, stba_lm_state *st,
                  int precision, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* One LM iteration of many independent problems at once (Alg. 1 per problem):
+ * p holds the problems concatenated, with n_prob (1 <= n_prob <= m) problems
+ * whose cameras, points and observations lie in contiguous index ranges.
+ *   states [n_prob] (device): one stba_lm_state per problem (stba_lm_init each);
+ *     each problem keeps its own lambda, cost, accept decision and counters.
+ *   prob_cam [m], prob_pt [n] (device int32): the problem of each camera / point.
+ *   prob_obs_off [n_prob + 1] (device int64): problem b's observations are
+ *     [prob_obs_off[b], prob_obs_off[b + 1]).
+ * The cluster map must keep each cluster inside one problem, and each point's
+ * observations must see cameras of the point's problem (checked on the device:
+ * STBA_EINVAL in every state's status otherwise).  Per problem the step is the
+ * one of stba_lm_step: its segments, point blocks and S_k blocks damped with
+ * its own lambda, its cost at x and at x + dx summed over its observations in
+ * a fixed order, accept iff F(x + dx) < F(x), finite and its clusters
+ * factorised; x += dx for its cameras and points only.  f and J are evaluated
+ * when any problem accepted its last step.  A non-positive-definite point
+ * block, and a sticky data error, reject the step of every problem (they are
+ * tracked for the batch as a whole).  Asynchronous, no host synchronisation;
+ * errors as stba_lm_step (STBA_EINVAL also for null batch arrays or n_prob out
+ * of range). */
+int stba_lm_step_batched(const stba_problem *p, const stba_dims *dims, const stba_sample *s, stba_lm_state *states,
+                         int32_t n_prob, const int32_t *prob_cam, const int32_t *prob_pt, const int64_t *prob_obs_off,
+                         int precision, void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* Same as stba_lm_step, recording events[k] before phase k and events[STBA_NUM_PHASES]
  * after the last (host array of STBA_NUM_PHASES + 1 created hipEvent_t) so that a
  * caller can time each kernel of the iteration on `stream`. */

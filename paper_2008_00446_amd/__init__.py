@@ -12,8 +12,8 @@ from .binding import (  # noqa: F401
     stba_residual_jacobian, stba_residual_jacobian_static, stba_build_cluster_rcs, stba_solve_clusters,
     stba_solve_clusters_pcg,
     stba_sample_clusters, stba_lm_step_pcg, stba_lm_init,
-    stba_lm_step,
+    stba_lm_step, stba_lm_step_batched, new_states,
     stba_lm_step_profiled, stba_residual_vjp, stba_residual_vjp_stored, stba_autotune,
 )
 from .tuning import shape_class, autotune_solver  # noqa: F401
-from .solver import StbaSolver, ResidualPlan, residuals, hip_events, event_ms  # noqa: F401
+from .solver import StbaSolver, BatchSolver, ResidualPlan, residuals, hip_events, event_ms  # noqa: F401

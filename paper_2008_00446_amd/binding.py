@@ -93,6 +93,8 @@ _SIGS = {
                                             ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64, _P, _P, _P, _P]),
     "stba_lm_init": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double, _P]),
     "stba_lm_step": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, _P, ctypes.c_size_t, _P]),
+    "stba_lm_step_batched": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, _P, _P, _P, ctypes.c_int, _P,
+                                            ctypes.c_size_t, _P]),
     "stba_lm_step_pcg": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, ctypes.c_int32, ctypes.c_double, _P,
                                         ctypes.c_size_t, _P]),
     "stba_lm_step_profiled": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, _P, ctypes.c_size_t, _P, _P]),
@@ -279,6 +281,14 @@ def stba_lm_step(problem, dims, sample, state, precision, ws, stream=None):
                                                        precision, _ptr(ws), ws.numel(), _stream(stream)))
 
 
+def stba_lm_step_batched(problem, dims, sample, states, n_prob, prob_cam, prob_pt, prob_obs_off, precision, ws,
+                         stream=None):
+    """states: n_prob stba_lm_state structs back to back in one device tensor."""
+    _check("stba_lm_step_batched", load_library().stba_lm_step_batched(
+        _ref(problem), _ref(dims), _ref(sample), _ptr(states), int(n_prob), _ptr(prob_cam), _ptr(prob_pt),
+        _ptr(prob_obs_off), precision, _ptr(ws), ws.numel(), _stream(stream)))
+
+
 def stba_lm_step_pcg(problem, dims, sample, state, precision, max_iters, tol, ws, stream=None):
     _check("stba_lm_step_pcg", load_library().stba_lm_step_pcg(
         _ref(problem), _ref(dims), _ref(sample), _ptr(state), precision, int(max_iters), float(tol), _ptr(ws),
@@ -319,3 +329,8 @@ def set_lambda_min(state: torch.Tensor, value: float) -> None:
 
 def new_state(device="cuda") -> torch.Tensor:
     return torch.zeros(ctypes.sizeof(StbaLmState), dtype=torch.uint8, device=device)
+
+
+def new_states(count, device="cuda") -> torch.Tensor:
+    """count device stba_lm_state structs back to back ([count, size] bytes)."""
+    return torch.zeros((count, ctypes.sizeof(StbaLmState)), dtype=torch.uint8, device=device)

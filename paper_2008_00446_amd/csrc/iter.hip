@@ -474,14 +474,15 @@ template <typename T>
 __global__ __launch_bounds__(64) void k_points(int32_t n, const int64_t *__restrict__ pt_off,
                                                const int32_t *__restrict__ obs_cam,
                                                const int32_t *__restrict__ cam_cluster, const T *__restrict__ f,
-                                               const T *__restrict__ Jp, const double *__restrict__ lam2,
+                                               const T *__restrict__ Jp, Damp dm,
                                                uint64_t seed, uint64_t t, uint64_t thr, int32_t *__restrict__ seg_head,
                                                double *__restrict__ seg_rec, double *__restrict__ Vinv,
                                                double *__restrict__ wph, int32_t *status) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
-    const double lam = lam2[0];
-    const bool corr = lam >= lam2[1];
+    const double *lp = dm.at_pt(j);
+    const double lam = lp[0];
+    const bool corr = lam >= lp[1];
     const int64_t p0 = pt_off[j], p1 = pt_off[j + 1];
     // segment heads: the chain of a cluster follows camera order, which is storage order
     for (int64_t a = p0; a < p1; ++a) {
@@ -652,7 +653,7 @@ template <typename T>
 __global__ __launch_bounds__(64 * kPtWaves) void k_points_obs(
     int64_t ngroups, const int32_t *__restrict__ grp_first, const int64_t *__restrict__ pt_off,
     const int32_t *__restrict__ obs_pt, const int32_t *__restrict__ obs_cam, const int32_t *__restrict__ cam_cluster,
-    const T *__restrict__ f, const T *__restrict__ Jc, const T *__restrict__ Jp, const double *__restrict__ lam2,
+    const T *__restrict__ f, const T *__restrict__ Jc, const T *__restrict__ Jp, Damp dm,
     uint64_t seed, uint64_t t, uint64_t thr, int32_t *__restrict__ seg_head, T *__restrict__ obsd,
     double *__restrict__ Vinv, double *__restrict__ wph, int32_t *status) {
     __shared__ double sV[kPtWaves][9][64];   // J_p^T J_p (6) and -J_p^T f (3) of each lane
@@ -688,8 +689,9 @@ __global__ __launch_bounds__(64 * kPtWaves) void k_points_obs(
 #pragma unroll
         for (int k = 0; k < 18; ++k) jc[k] = (double)Jc[18 * a + k];
     }
-    const double lam = lam2[0];
-    const bool corr = lam >= lam2[1];
+    const double *lp = dm.at_pt(j);
+    const double lam = lp[0];
+    const bool corr = lam >= lp[1];
     const int32_t cl = act ? cam_cluster[cam] : -1;
     // my point's lanes [first, last): observations are sorted by point and the
     // group starts at a point, so the point starts are where obs_pt changes
@@ -883,7 +885,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                                                const int32_t *__restrict__ cam_local,
                                                const int32_t *__restrict__ cl_Np, const int64_t *__restrict__ S_off,
                                                const int32_t *__restrict__ seg_head, const T *__restrict__ Jc,
-                                               const T *__restrict__ obsd, const double *__restrict__ lam2,
+                                               const T *__restrict__ obsd, Damp dm,
                                                double *__restrict__ S, double *__restrict__ b) {
     using Sh = SchurShape<T>;
     constexpr int kBuf = Sh::kDmaBytes > Sh::kDBytes ? Sh::kDmaBytes : Sh::kDBytes;
@@ -893,7 +895,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     int2 *sp = s_pairs[wv];
     char *sb = s_rec[wv];
     const int64_t nc = ch.n_chunks[0];
-    const double lam = lam2[0];
     // Workgroups go to the 8 XCDs in turn (block b to XCD b mod 8), and each XCD
     // has its own L2.  XCD x takes the contiguous eighth [x nc / 8, (x + 1) nc / 8)
     // of the items (chunks in camera-pair order), so the blocks of one camera row,
@@ -910,6 +911,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         if (kr < 0 || kr >= l || cam_cluster[c] != kr) continue;
         const int64_t Np = cl_Np[kr];
         if (Np == 0) continue;   // the map was rejected by the cluster layout
+        const double lam = dm.at_cam(r)[0];
         const int64_t c0 = ch.blk_chunk_off[bk];
         const int64_t nch = ch.blk_chunk_off[bk + 1] - c0;
         const int64_t s0 = blk_start[bk] + (item - c0) * kSchurChunk;
@@ -1122,11 +1124,10 @@ __global__ __launch_bounds__(128) void k_schur_reduce(SchurChunks ch, const int6
                                                       const int32_t *__restrict__ cl_n,
                                                       const int32_t *__restrict__ cl_Np,
                                                       const int64_t *__restrict__ S_off,
-                                                      const double *__restrict__ lam2, double *__restrict__ S,
+                                                      Damp dm, double *__restrict__ S,
                                                       double *__restrict__ b) {
     const int64_t nb = n_blocks_p[0];
     const int t = threadIdx.x;
-    const double lam = lam2[0];
     for (int32_t k = blockIdx.x; k < l; k += gridDim.x) {
         const int64_t Np = cl_Np[k];
         double *A = S + S_off[k];
@@ -1144,6 +1145,7 @@ __global__ __launch_bounds__(128) void k_schur_reduce(SchurChunks ch, const int6
         if (Np == 0) continue;
         const bool diag = r == c;
         if (t >= 90 || (!diag && t >= 81)) continue;
+        const double lam = dm.at_cam(r)[0];
         const double *q = ch.part + c0 * kSchurPart;
         if (t < 81) {
             const int e = t / 9, k = t - 9 * (t / 9);
@@ -1375,7 +1377,7 @@ __global__ __launch_bounds__(64 * kPtWaves) void k_refine_obs(
     int64_t ngroups, const int32_t *__restrict__ grp_first, const int64_t *__restrict__ pt_off,
     const int32_t *__restrict__ obs_pt, const int32_t *__restrict__ obs_cam, const double *__restrict__ cam,
     const double *__restrict__ pt, const double *__restrict__ uv, double huber, const int32_t *__restrict__ seg_head,
-    const double *__restrict__ lam2, const double *__restrict__ dcam, double *__restrict__ e,
+    Damp dm, const double *__restrict__ dcam, double *__restrict__ e,
     double *__restrict__ Vinv, double *__restrict__ wph) {
     __shared__ double sV[kPtWaves][12][64];
     __shared__ int32_t sHead[kPtWaves][64];
@@ -1433,8 +1435,9 @@ __global__ __launch_bounds__(64 * kPtWaves) void k_refine_obs(
         }
     }
     if (!act) return;
-    const double lam = lam2[0];
-    const bool corr = lam >= lam2[1];
+    const double *lp = dm.at_pt(j);
+    const double lam = lp[0];
+    const bool corr = lam >= lp[1];
     if (lane == first) refine_point_blocks(V, w, lam, Vinv + 6 * (int64_t)j, wph + 3 * (int64_t)j);
     double y[3];
     refine_segment_step(V, w, Vs, ws, zs, lam, corr, y);
@@ -1447,13 +1450,14 @@ __global__ __launch_bounds__(64) void k_refine_pt(int32_t n, const int64_t *__re
                                                   const int32_t *__restrict__ obs_cam, const double *__restrict__ cam,
                                                   const double *__restrict__ pt, const double *__restrict__ uv,
                                                   double huber, const int32_t *__restrict__ seg_head,
-                                                  const double *__restrict__ lam2, const double *__restrict__ dcam,
+                                                  Damp dm, const double *__restrict__ dcam,
                                                   double *__restrict__ e, double *__restrict__ Vinv,
                                                   double *__restrict__ wph) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
-    const double lam = lam2[0];
-    const bool corr = lam >= lam2[1];
+    const double *lp = dm.at_pt(j);
+    const double lam = lp[0];
+    const bool corr = lam >= lp[1];
     const int64_t p0 = pt_off[j], p1 = pt_off[j + 1];
     double V[6] = {0, 0, 0, 0, 0, 0}, w[3] = {0, 0, 0};
     for (int64_t a = p0; a < p1; ++a) {
@@ -1507,7 +1511,7 @@ __global__ __launch_bounds__(256) void k_refine_cam(int32_t m, const double *__r
                                                     const int64_t *__restrict__ diag_blk,
                                                     const int64_t *__restrict__ blk_start,
                                                     const uint64_t *__restrict__ pairs,
-                                                    const double *__restrict__ lam2, const double *__restrict__ dcam,
+                                                    Damp dm, const double *__restrict__ dcam,
                                                     const double *__restrict__ e, double *__restrict__ r) {
     const int lane = threadIdx.x & 63;
     const int64_t i = xcd_contiguous_item(blockIdx.x, gridDim.x, threadIdx.x >> 6);
@@ -1538,7 +1542,7 @@ __global__ __launch_bounds__(256) void k_refine_cam(int32_t m, const double *__r
             acc[k] += __shfl_xor(acc[k], d, 64);
             dg[k] += __shfl_xor(dg[k], d, 64);
         }
-    const double lam = lam2[0];
+    const double lam = dm.at_cam(i)[0];
     double v = 0.0;
 #pragma unroll
     for (int k = 0; k < 9; ++k)
@@ -1830,28 +1834,28 @@ hipError_t launch_set_damping(double *slot, double lambda, double lambda_corr, h
 
 template <typename T>
 hipError_t launch_points(const stba_problem &p, const int64_t *pt_off, const int32_t *cam_cluster, int32_t l,
-                         const T *f, const T *Jc, const T *Jp, const double *lam2, uint64_t seed, uint64_t t,
+                         const T *f, const T *Jc, const T *Jp, const Damp &dm, uint64_t seed, uint64_t t,
                          uint64_t thr, int32_t *seg_head, double *seg_rec, T *obsd, double *Vinv, double *wph,
                          int32_t *status, int32_t group_size, const int32_t *grp_first, hipStream_t st) {
     (void)l;
     if (group_size > 0) {
         const int64_t ng = (p.q + group_size - 1) / group_size;
         k_points_obs<T><<<(unsigned)((ng + kPtWaves - 1) / kPtWaves), 64 * kPtWaves, 0, st>>>(
-            ng, grp_first, pt_off, p.obs_pt, p.obs_cam, cam_cluster, f, Jc, Jp, lam2, seed, t, thr, seg_head, obsd,
+            ng, grp_first, pt_off, p.obs_pt, p.obs_cam, cam_cluster, f, Jc, Jp, dm, seed, t, thr, seg_head, obsd,
             Vinv, wph, status);
         return hipGetLastError();
     }
-    k_points<T><<<grid_for(p.n, 64), 64, 0, st>>>(p.n, pt_off, p.obs_cam, cam_cluster, f, Jp, lam2, seed, t, thr,
+    k_points<T><<<grid_for(p.n, 64), 64, 0, st>>>(p.n, pt_off, p.obs_cam, cam_cluster, f, Jp, dm, seed, t, thr,
                                                   seg_head, seg_rec, Vinv, wph, status);
     k_obs_rec<T><<<grid_for(p.q), 256, 0, st>>>(p.q, seg_head, seg_rec, f, Jc, Jp, obsd);
     return hipGetLastError();
 }
 template hipError_t launch_points<double>(const stba_problem &, const int64_t *, const int32_t *, int32_t,
-                                          const double *, const double *, const double *, const double *, uint64_t,
+                                          const double *, const double *, const double *, const Damp &, uint64_t,
                                           uint64_t, uint64_t, int32_t *, double *, double *, double *, double *,
                                           int32_t *, int32_t, const int32_t *, hipStream_t);
 template hipError_t launch_points<float>(const stba_problem &, const int64_t *, const int32_t *, int32_t,
-                                         const float *, const float *, const float *, const double *, uint64_t,
+                                         const float *, const float *, const float *, const Damp &, uint64_t,
                                          uint64_t, uint64_t, int32_t *, double *, float *, double *, double *,
                                          int32_t *, int32_t, const int32_t *, hipStream_t);
 
@@ -1880,29 +1884,29 @@ template <typename T>
 hipError_t launch_schur(const int64_t *n_blocks, int64_t n_blocks_cap, const SchurChunks &ch, const int2 *blk_key,
                         const int64_t *blk_start, const uint64_t *pairs, const int32_t *cam_cluster, int32_t l,
                         const int32_t *cam_local, const int32_t *cl_n, const int32_t *cl_Np, const int64_t *S_off,
-                        const int32_t *seg_head, const T *Jc, const T *obsd, const double *lam2, double *S,
+                        const int32_t *seg_head, const T *Jc, const T *obsd, const Damp &dm, double *S,
                         double *b, hipStream_t st) {
     int64_t wgs = (ch.chunk_cap + 3) / 4;
     if (wgs > 16384) wgs = 16384;
     if (ch.blocks > 0) wgs = ch.blocks;
     wgs = ((wgs < 8 ? 8 : wgs) + 7) / 8 * 8;   // every XCD gets its share of workgroups
     k_schur<T><<<(unsigned)wgs, 256, 0, st>>>(ch, blk_key, blk_start, pairs, cam_cluster, l, cam_local, cl_Np,
-                                              S_off, seg_head, Jc, obsd, lam2, S, b);
+                                              S_off, seg_head, Jc, obsd, dm, S, b);
     int64_t rb = n_blocks_cap;
     if (rb > 8192) rb = 8192;
     if (rb < 1) rb = 1;
     k_schur_reduce<<<(unsigned)rb, 128, 0, st>>>(ch, n_blocks, blk_key, cam_cluster, l, cam_local, cl_n, cl_Np, S_off,
-                                                 lam2, S, b);
+                                                 dm, S, b);
     return hipGetLastError();
 }
 template hipError_t launch_schur<double>(const int64_t *, int64_t, const SchurChunks &, const int2 *, const int64_t *,
                                          const uint64_t *, const int32_t *, int32_t, const int32_t *, const int32_t *,
                                          const int32_t *, const int64_t *, const int32_t *, const double *,
-                                         const double *, const double *, double *, double *, hipStream_t);
+                                         const double *, const Damp &, double *, double *, hipStream_t);
 template hipError_t launch_schur<float>(const int64_t *, int64_t, const SchurChunks &, const int2 *, const int64_t *,
                                         const uint64_t *, const int32_t *, int32_t, const int32_t *, const int32_t *,
                                         const int32_t *, const int64_t *, const int32_t *, const float *, const float *,
-                                        const double *, double *, double *, hipStream_t);
+                                        const Damp &, double *, double *, hipStream_t);
 
 template <typename T, bool kFp64J>
 hipError_t backsub_as(const stba_problem &p, const int64_t *pt_off, const T *Jc, const T *Jp, const double *Vinv,
@@ -1934,22 +1938,22 @@ template hipError_t launch_backsub<float>(const stba_problem &, const int64_t *,
                                           const int32_t *, bool, hipStream_t);
 
 hipError_t launch_refine_residual(const stba_problem &p, const int64_t *pt_off, const int32_t *seg_head,
-                                  int32_t group_size, const int32_t *grp_first, const double *lam2,
+                                  int32_t group_size, const int32_t *grp_first, const Damp &dm,
                                   const double *dcam, double *e, double *Vinv, double *wph, const int64_t *diag_blk,
                                   const int64_t *blk_start, const uint64_t *pairs, double *r, hipStream_t st) {
     if (group_size > 0) {
         const int64_t ng = (p.q + group_size - 1) / group_size;
         k_refine_obs<<<(unsigned)((ng + kPtWaves - 1) / kPtWaves), 64 * kPtWaves, 0, st>>>(
-            ng, grp_first, pt_off, p.obs_pt, p.obs_cam, p.cam, p.pt, p.obs_uv, p.huber, seg_head, lam2, dcam, e, Vinv,
+            ng, grp_first, pt_off, p.obs_pt, p.obs_cam, p.cam, p.pt, p.obs_uv, p.huber, seg_head, dm, dcam, e, Vinv,
             wph);
     } else {
         k_refine_pt<<<grid_for(p.n, 64), 64, 0, st>>>(p.n, pt_off, p.obs_cam, p.cam, p.pt, p.obs_uv, p.huber,
-                                                      seg_head, lam2, dcam, e, Vinv, wph);
+                                                      seg_head, dm, dcam, e, Vinv, wph);
     }
     const hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     k_refine_cam<<<xcd_contiguous_grid(p.m), 256, 0, st>>>(p.m, p.cam, p.pt, p.obs_pt, p.obs_uv, p.huber, diag_blk,
-                                                           blk_start, pairs, lam2, dcam, e, r);
+                                                           blk_start, pairs, dm, dcam, e, r);
     return hipGetLastError();
 }
 
@@ -1970,6 +1974,149 @@ hipError_t launch_accept_update(const stba_problem &p, const double *rj_partials
     if (blocks < 1) blocks = 1;
     k_accept_update<<<blocks, 256, 0, st>>>(rj_partials, partials, count, F_ref, cl_status, l, status, s, p.m, p.n,
                                             p.cam, p.pt, dcam, dpt);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Many problems in one LM step (Alg. 1 per problem): the problems are
+// concatenated (cameras, points and observations in contiguous ranges, each
+// point's observations and each cluster's cameras inside one problem) and
+// every problem keeps its own damping, cost and accept decision.
+// ---------------------------------------------------------------------------
+// Cost of each problem at x (dcam = dpt = null) or at x + dx, one workgroup
+// per problem over its observation range in a fixed order; also checks that
+// every observation's camera and point belong to the range's problem.
+__global__ __launch_bounds__(256) void k_cost_problems(int32_t n_prob, const int64_t *__restrict__ obs_off,
+                                                       const double *__restrict__ cam, const double *__restrict__ pt,
+                                                       const int32_t *__restrict__ oc, const int32_t *__restrict__ op,
+                                                       const double *__restrict__ uv, const double *__restrict__ dcam,
+                                                       const double *__restrict__ dpt, double huber,
+                                                       const int32_t *__restrict__ prob_cam,
+                                                       const int32_t *__restrict__ prob_pt, double *__restrict__ F,
+                                                       int32_t *status) {
+    __shared__ double sh[256];
+    for (int32_t pb = blockIdx.x; pb < n_prob; pb += gridDim.x) {
+        double s = 0.0;
+        for (int64_t o = obs_off[pb] + threadIdx.x; o < obs_off[pb + 1]; o += 256) {
+            const int64_t i = oc[o], j = op[o];
+            if (prob_cam[i] != pb || prob_pt[j] != pb) set_status(status + kStSticky, STBA_EINVAL);
+            double c[9], X[3];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) c[k] = cam[9 * i + k] + (dcam ? dcam[9 * i + k] : 0.0);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) X[k] = pt[3 * j + k] + (dpt ? dpt[3 * j + k] : 0.0);
+            double pix[2];
+            camera_project(c, X, pix);
+            const double f0 = pix[0] - uv[2 * o], f1 = pix[1] - uv[2 * o + 1];
+            s += huber_rho(f0 * f0 + f1 * f1, huber);
+        }
+        s = block_sum_256(s, sh);
+        if (threadIdx.x == 0) F[pb] = s;
+    }
+}
+
+// The problems whose clusters did not all factorise (bad[p] = 1: a non-PD S_k,
+// 2: a factorisation wait that timed out); a cluster whose cameras span two
+// problems is a data error.  bad is cleared by the caller.
+__global__ __launch_bounds__(256) void k_batch_clusters(int32_t l, const int32_t *__restrict__ cl_start,
+                                                        const int32_t *__restrict__ cl_cams,
+                                                        const int32_t *__restrict__ cl_status,
+                                                        const int32_t *__restrict__ prob_cam, int32_t *__restrict__ bad,
+                                                        int32_t *status) {
+    for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < l; k += gridDim.x * blockDim.x) {
+        const int32_t a = cl_start[k], e = cl_start[k + 1];
+        if (e <= a) continue;
+        const int32_t pb = prob_cam[cl_cams[a]];
+        for (int32_t u = a + 1; u < e; ++u)
+            if (prob_cam[cl_cams[u]] != pb) set_status(status + kStSticky, STBA_EINVAL);
+        const int32_t cs = cl_status[k];
+        if (cs == STBA_EHIP) atomicMax(bad + pb, 2);
+        else if (cs != STBA_OK) atomicMax(bad + pb, 1);
+    }
+}
+
+// Per problem: accept iff F(x + dx) < F(x), finite, and every cluster of the
+// problem factorised; the damping rule and counters of k_accept_update.  The
+// point blocks' status and the sticky data error are shared by the batch.
+__global__ __launch_bounds__(256) void k_batch_accept(int32_t n_prob, const double *__restrict__ F_x,
+                                                      const double *__restrict__ F_c, const int32_t *__restrict__ bad,
+                                                      const int32_t *status, stba_lm_state *states) {
+    const int32_t pb = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pb >= n_prob) return;
+    stba_lm_state *st = states + pb;
+    const double F0 = F_x[pb], Fn = F_c[pb];
+    const int32_t sticky = bad[pb] == 2 ? STBA_EHIP : status[kStSticky];
+    const bool pd = bad[pb] == 0 && status[kStPointBad] == 0;
+    const bool fin = isfinite(Fn);
+    const bool acc = pd && fin && sticky == 0 && (Fn < F0);
+    st->F = acc ? Fn : F0;
+    st->have_F = 1;
+    st->F_new = Fn;
+    st->accepted = acc ? 1 : 0;
+    st->lambda = acc ? fmax(st->lambda / 3.0, st->lambda_min) : st->lambda * 3.0;
+    st->need_jac = acc ? 1 : 0;
+    st->n_rcs += 1;
+    st->n_accept += acc ? 1 : 0;
+    st->n_jac += status[kStJacRan] ? 1 : 0;
+    st->last_status = bad[pb] == 2 ? STBA_EHIP : (!pd ? STBA_ENOTPD : (!fin ? STBA_ENONFINITE : sticky));
+    if (st->status == 0 && sticky != 0) st->status = sticky;
+}
+
+// x += dx for the cameras and points of the problems that accepted.
+__global__ __launch_bounds__(256) void k_batch_apply(int32_t m, int32_t n, const int32_t *__restrict__ prob_cam,
+                                                     const int32_t *__restrict__ prob_pt,
+                                                     const stba_lm_state *__restrict__ states, double *cam,
+                                                     double *pt, const double *__restrict__ dcam,
+                                                     const double *__restrict__ dpt) {
+    const int64_t nc = 9 * (int64_t)m, total = nc + 3 * (int64_t)n;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        if (i < nc) {
+            if (states[prob_cam[i / 9]].accepted) cam[i] += dcam[i];
+        } else {
+            const int64_t k = i - nc;
+            if (states[prob_pt[k / 3]].accepted) pt[k] += dpt[k];
+        }
+    }
+}
+
+// flag = 1 if any problem of the batch needs f and J at its x.
+__global__ __launch_bounds__(256) void k_batch_need_jac(int32_t n_prob, const stba_lm_state *__restrict__ states,
+                                                        int32_t *flag) {
+    __shared__ int any;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    for (int32_t pb = threadIdx.x; pb < n_prob; pb += blockDim.x)
+        if (states[pb].need_jac) any = 1;
+    __syncthreads();
+    if (threadIdx.x == 0) flag[0] = any;
+}
+
+hipError_t launch_batch_need_jac(int32_t n_prob, const stba_lm_state *states, int32_t *flag, hipStream_t st) {
+    k_batch_need_jac<<<1, 256, 0, st>>>(n_prob, states, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_cost_problems(const stba_problem &p, int32_t n_prob, const int64_t *obs_off,
+                                const int32_t *prob_cam, const int32_t *prob_pt, const double *dcam,
+                                const double *dpt, double *F, int32_t *status, hipStream_t st) {
+    const unsigned blocks = (unsigned)(n_prob < 4096 ? n_prob : 4096);
+    k_cost_problems<<<blocks, 256, 0, st>>>(n_prob, obs_off, p.cam, p.pt, p.obs_cam, p.obs_pt, p.obs_uv, dcam, dpt,
+                                            p.huber, prob_cam, prob_pt, F, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_accept(const stba_problem &p, int32_t n_prob, int32_t l, const int32_t *cl_start,
+                               const int32_t *cl_cams, const int32_t *cl_status, const int32_t *prob_cam,
+                               const int32_t *prob_pt, const double *F_x, const double *F_c, int32_t *bad,
+                               int32_t *status, stba_lm_state *states, const double *dcam, const double *dpt,
+                               hipStream_t st) {
+    k_fill_i32<<<grid_for(n_prob), 256, 0, st>>>(bad, n_prob, 0);
+    k_batch_clusters<<<grid_for(l), 256, 0, st>>>(l, cl_start, cl_cams, cl_status, prob_cam, bad, status);
+    k_batch_accept<<<grid_for(n_prob), 256, 0, st>>>(n_prob, F_x, F_c, bad, status, states);
+    unsigned blocks = grid_for(9 * (int64_t)p.m + 3 * (int64_t)p.n);
+    if (blocks > 2048) blocks = 2048;
+    k_batch_apply<<<blocks, 256, 0, st>>>(p.m, p.n, prob_cam, prob_pt, states, p.cam, p.pt, dcam, dpt);
     return hipGetLastError();
 }
 

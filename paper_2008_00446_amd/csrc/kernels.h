@@ -59,12 +59,26 @@ int64_t rj_blocks(int64_t q);
 hipError_t launch_sum_partials(const double *partials, int64_t count, double *out, hipStream_t st);
 hipError_t launch_set_damping(double *slot, double lambda, double lambda_corr, hipStream_t st);
 
+// Damping of the step: lambda and lambda_corr of one problem (lam2[0], lam2[1]),
+// or of each problem of a batch: problem p's pair at lam2 + stride p, where p
+// is prob_cam[i] for camera i and prob_pt[j] for point j.
+struct Damp {
+    const double *lam2 = nullptr;
+    const int32_t *prob_cam = nullptr, *prob_pt = nullptr;   // null: one problem
+    int64_t stride = 0;
+    Damp() = default;
+    Damp(const double *l) : lam2(l) {}
+    __device__ const double *at_cam(int64_t i) const { return prob_cam ? lam2 + stride * prob_cam[i] : lam2; }
+    __device__ const double *at_pt(int64_t j) const { return prob_pt ? lam2 + stride * prob_pt[j] : lam2; }
+};
+
 // Segments, point blocks and per-observation records.  group_size > 0: one
 // lane per observation (groups from launch_point_groups, max_track <= 32);
 // otherwise one thread per point and one per observation (seg_rec staging).
+
 template <typename T>
 hipError_t launch_points(const stba_problem &p, const int64_t *pt_off, const int32_t *cam_cluster, int32_t l,
-                         const T *f, const T *Jc, const T *Jp, const double *lam2, uint64_t seed, uint64_t t,
+                         const T *f, const T *Jc, const T *Jp, const Damp &dm, uint64_t seed, uint64_t t,
                          uint64_t thr, int32_t *seg_head, double *seg_rec, T *obsd, double *Vinv, double *wph,
                          int32_t *status, int32_t group_size, const int32_t *grp_first, hipStream_t st);
 // group g of the one-lane-per-observation path starts at grp_first[g]
@@ -91,7 +105,7 @@ template <typename T>
 hipError_t launch_schur(const int64_t *n_blocks, int64_t n_blocks_cap, const SchurChunks &ch, const int2 *blk_key,
                         const int64_t *blk_start, const uint64_t *pairs, const int32_t *cam_cluster, int32_t l,
                         const int32_t *cam_local, const int32_t *cl_n, const int32_t *cl_Np, const int64_t *S_off,
-                        const int32_t *seg_head, const T *Jc, const T *obsd, const double *lam2, double *S,
+                        const int32_t *seg_head, const T *Jc, const T *obsd, const Damp &dm, double *S,
                         double *b, hipStream_t st);
 
 // Cluster solves.  With few clusters (l wavefront sets of T + (T-1)(T-2)/2,
@@ -139,7 +153,7 @@ hipError_t launch_chol(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, con
 // receives the linearised residuals, r [9 m] the residual in camera order;
 // Vinv / wph are overwritten with the FP64 physical point blocks.
 hipError_t launch_refine_residual(const stba_problem &p, const int64_t *pt_off, const int32_t *seg_head,
-                                  int32_t group_size, const int32_t *grp_first, const double *lam2,
+                                  int32_t group_size, const int32_t *grp_first, const Damp &dm,
                                   const double *dcam, double *e, double *Vinv, double *wph, const int64_t *diag_blk,
                                   const int64_t *blk_start, const uint64_t *pairs, double *r, hipStream_t st);
 // dcam += S^-1 r with the factors left in S by launch_chol (r in camera order)
@@ -163,6 +177,19 @@ hipError_t launch_accept_update(const stba_problem &p, const double *rj_partials
                                 int64_t count, const double *F_ref, const int32_t *cl_status, int32_t l,
                                 const int32_t *status, stba_lm_state *s, const double *dcam, const double *dpt,
                                 hipStream_t st);
+
+// Batched LM (many problems, one step): per-problem cost (at x when dcam and
+// dpt are null), then the per-problem decisions and x += dx where accepted.
+// bad: n_prob int32 of scratch.
+hipError_t launch_batch_need_jac(int32_t n_prob, const stba_lm_state *states, int32_t *flag, hipStream_t st);
+hipError_t launch_cost_problems(const stba_problem &p, int32_t n_prob, const int64_t *obs_off,
+                                const int32_t *prob_cam, const int32_t *prob_pt, const double *dcam,
+                                const double *dpt, double *F, int32_t *status, hipStream_t st);
+hipError_t launch_batch_accept(const stba_problem &p, int32_t n_prob, int32_t l, const int32_t *cl_start,
+                               const int32_t *cl_cams, const int32_t *cl_status, const int32_t *prob_cam,
+                               const int32_t *prob_pt, const double *F_x, const double *F_c, int32_t *bad,
+                               int32_t *status, stba_lm_state *states, const double *dcam, const double *dpt,
+                               hipStream_t st);
 
 template <typename T>
 hipError_t launch_vjp(const stba_problem &p, const int64_t *pt_off, const int64_t *diag_blk,

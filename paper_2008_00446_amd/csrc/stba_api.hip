@@ -23,7 +23,7 @@ struct Layout {
     size_t pcg_clus, pcg_minv, pcg_iters, pcg_resid;
     size_t f, Jc, Jp, seg_head, seg_rec, grp_first, obsd, Vinv, wph, S, eref, rres, b, dcam, dpt, partials, chol_flags,
         chol_yx;
-    size_t team_flags, team_vec;
+    size_t team_flags, team_vec, batch;
     int64_t team_abort_at, team_vec_len;
     bool refine = false;   // STBA_MIXED: eref and rres exist
     int64_t S_cap, n_partials;
@@ -136,6 +136,8 @@ bool make_layout(const stba_problem *p, const stba_dims *d, int precision, Layou
     L.max_Np = (int32_t)round_up(9 * (int64_t)d->gamma_max, kNB);
     L.S_cap = s_capacity(p->m, d->gamma_max);
     L.S = take(8 * (size_t)L.S_cap);
+    // batched LM: the costs at x and at x + dx and a scratch word per problem (at most m problems), and a flag
+    L.batch = take(8 * 2 * m + 4 * m + 4);
     // flags and block vectors of the team factorisation (many clusters)
     L.team_abort_at = chol_team_flag_words(L.S_cap, p->m) - 3;
     L.team_flags = take(4 * (size_t)(L.team_abort_at + 3));
@@ -248,11 +250,11 @@ int cluster_solve(const stba_dims *d, int32_t l, bool l_on_device, double *dcam,
 // MIXED: one FP64 refinement step of every cluster solve, dcam += S_k^-1 (b - S x)
 // with the residual of the FP64 method's S and b (J recomputed in FP64 at x)
 // and the factors of the FP32-assembled S_k.
-int refine_solve(const stba_problem *p, int32_t l, const double *lam2, double *dcam, const Layout &L, void *ws,
+int refine_solve(const stba_problem *p, int32_t l, const Damp &dm, double *dcam, const Layout &L, void *ws,
                  hipStream_t st) {
     double *r = at<double>(ws, L.rres);
     STBA_HIP(launch_refine_residual(*p, at<int64_t>(ws, L.pt_off), at<int32_t>(ws, L.seg_head), L.group_size,
-                                    at<int32_t>(ws, L.grp_first), lam2, dcam, at<double>(ws, L.eref),
+                                    at<int32_t>(ws, L.grp_first), dm, dcam, at<double>(ws, L.eref),
                                     at<double>(ws, L.Vinv), at<double>(ws, L.wph), at<int64_t>(ws, L.diag_blk),
                                     at<int64_t>(ws, L.blk_start), at<uint64_t>(ws, L.pairs), r, st));
     STBA_HIP(launch_sweep(l, at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np), at<int64_t>(ws, L.S_off),
@@ -418,6 +420,60 @@ int lm_step_impl(const stba_problem *p, const stba_dims *d, const stba_sample *s
     STBA_HIP(launch_accept_update(*p, rj_part, cost_part, L.n_partials, F_ref, at<int32_t>(ws, L.cl_status), s->l,
                                   status, stt, dcam, dpt, st));
     STBA_TRY(mark(10));
+    return STBA_OK;
+}
+
+// One LM step of many problems at once (see stba_lm_step_batched): the
+// iteration of lm_step_impl with each problem's damping (Damp over the states'
+// lambda and lambda_corr, stba_lm_state apart), f and J evaluated when any
+// problem needs them, the cost of each problem summed over its observation
+// range, and the decisions taken per problem.
+template <typename T>
+int lm_step_batched_impl(const stba_problem *p, const stba_dims *d, const stba_sample *s, stba_lm_state *states,
+                         int32_t n_prob, const int32_t *prob_cam, const int32_t *prob_pt, const int64_t *obs_off,
+                         const Layout &L, void *ws, hipStream_t st) {
+    int32_t *status = at<int32_t>(ws, L.status);
+    Damp dm;
+    dm.lam2 = &states[0].lambda;
+    dm.prob_cam = prob_cam;
+    dm.prob_pt = prob_pt;
+    dm.stride = (int64_t)(sizeof(stba_lm_state) / sizeof(double));
+    T *f = at<T>(ws, L.f), *Jc = at<T>(ws, L.Jc), *Jp = at<T>(ws, L.Jp);
+    double *F_x = at<double>(ws, L.batch), *F_c = F_x + p->m;
+    int32_t *bad = reinterpret_cast<int32_t *>(F_c + p->m), *need = bad + p->m;
+    STBA_HIP(launch_clusters(s->cam_cluster, p->m, s->l, s->l_dev, d->gamma_max, at<int32_t>(ws, L.cl_n),
+                             at<int32_t>(ws, L.cl_Np), at<int32_t>(ws, L.cl_start), at<int32_t>(ws, L.cl_cams),
+                             at<int32_t>(ws, L.cam_local), at<int64_t>(ws, L.S_off), at<int32_t>(ws, L.cl_status),
+                             status, st));
+    ZeroS z;
+    z.S = at<double>(ws, L.S);
+    z.S_off = at<int64_t>(ws, L.S_off);
+    z.l = s->l;
+    z.S_cap = L.S_cap;
+    z.b = at<double>(ws, L.b);
+    z.nb = 9 * (int64_t)p->m;
+    STBA_HIP(launch_batch_need_jac(n_prob, states, need, st));
+    STBA_HIP(launch_rj<T>(*p, f, Jc, Jp, at<double>(ws, L.partials), need, status + kStJacRan, z, st));
+    STBA_HIP(launch_points<T>(*p, at<int64_t>(ws, L.pt_off), s->cam_cluster, s->l, f, Jc, Jp, dm, s->seed, s->iter,
+                              keep_threshold(s->alpha), at<int32_t>(ws, L.seg_head), at<double>(ws, L.seg_rec),
+                              at<T>(ws, L.obsd), at<double>(ws, L.Vinv), at<double>(ws, L.wph), status, L.group_size,
+                              at<int32_t>(ws, L.grp_first), st));
+    STBA_HIP(launch_schur<T>(at<int64_t>(ws, L.n_blocks), L.blk_cap, chunks_of(L, ws, s, d), at<int2>(ws, L.blk_key),
+                             at<int64_t>(ws, L.blk_start), at<uint64_t>(ws, L.pairs), s->cam_cluster, s->l,
+                             at<int32_t>(ws, L.cam_local), at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np),
+                             at<int64_t>(ws, L.S_off), at<int32_t>(ws, L.seg_head), Jc, at<T>(ws, L.obsd), dm,
+                             at<double>(ws, L.S), at<double>(ws, L.b), st));
+    double *dcam = at<double>(ws, L.dcam), *dpt = at<double>(ws, L.dpt);
+    STBA_TRY(cluster_solve(d, s->l, s->l_dev != nullptr, dcam, at<int32_t>(ws, L.cl_status), L, ws, st));
+    if (L.refine) STBA_TRY(refine_solve(p, s->l, dm, dcam, L, ws, st));
+    const bool fp64_j = L.refine || sizeof(T) == sizeof(double);
+    STBA_HIP(launch_backsub<T>(*p, at<int64_t>(ws, L.pt_off), Jc, Jp, at<double>(ws, L.Vinv), at<double>(ws, L.wph),
+                               dcam, dpt, L.group_size, at<int32_t>(ws, L.grp_first), fp64_j, st));
+    STBA_HIP(launch_cost_problems(*p, n_prob, obs_off, prob_cam, prob_pt, nullptr, nullptr, F_x, status, st));
+    STBA_HIP(launch_cost_problems(*p, n_prob, obs_off, prob_cam, prob_pt, dcam, dpt, F_c, status, st));
+    STBA_HIP(launch_batch_accept(*p, n_prob, s->l, at<int32_t>(ws, L.cl_start), at<int32_t>(ws, L.cl_cams),
+                                 at<int32_t>(ws, L.cl_status), prob_cam, prob_pt, F_x, F_c, bad, status, states, dcam,
+                                 dpt, st));
     return STBA_OK;
 }
 
@@ -715,6 +771,19 @@ int stba_residual_vjp(const stba_problem *p, const stba_dims *dims, int precisio
                                    at<int64_t>(ws, L.blk_start), at<uint64_t>(ws, L.pairs), (const float *)v,
                                    (float *)grad_cam, (float *)grad_pt, (float *)grad_uv, stream));
     return STBA_OK;
+}
+
+int stba_lm_step_batched(const stba_problem *p, const stba_dims *dims, const stba_sample *s, stba_lm_state *states,
+                         int32_t n_prob, const int32_t *prob_cam, const int32_t *prob_pt, const int64_t *prob_obs_off,
+                         int precision, void *ws, size_t ws_bytes, hipStream_t stream) {
+    Layout L;
+    STBA_TRY(front(p, dims, precision, ws, ws_bytes, L));
+    STBA_TRY(check_sample(p, s));
+    if (!states || !prob_cam || !prob_pt || !prob_obs_off || n_prob < 1 || n_prob > p->m) return STBA_EINVAL;
+    if (precision == STBA_FP64)
+        return lm_step_batched_impl<double>(p, dims, s, states, n_prob, prob_cam, prob_pt, prob_obs_off, L, ws,
+                                            stream);
+    return lm_step_batched_impl<float>(p, dims, s, states, n_prob, prob_cam, prob_pt, prob_obs_off, L, ws, stream);
 }
 
 int stba_residual_vjp_stored(const stba_problem *p, const stba_dims *dims, int precision, const void *v,

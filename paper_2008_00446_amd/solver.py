@@ -107,6 +107,74 @@ class StbaSolver:
         return B.read_state(self.state)
 
 
+class BatchSolver:
+    """Many independent bundle-adjustment problems stepped by one LM iteration
+    (stba_lm_step_batched): the problems are concatenated with index offsets,
+    and each keeps its own damping, cost and accept decision.
+
+    problems: a list of (cam [m_b,9], pt [n_b,3], obs_cam [q_b], obs_pt [q_b],
+    obs_uv [q_b,2]) with local indices, each sorted by (point, camera)."""
+
+    def __init__(self, problems, gamma_max, precision=B.STBA_FP64, lambda0=1e-4, lambda_corr=0.1, device="cuda",
+                 huber=0.0):
+        cams, pts, oc, op, uv = [], [], [], [], []
+        self.cam_off, self.pt_off, self.obs_off = [0], [0], [0]
+        for cam, pt, c_, p_, u_ in problems:
+            cams.append(np.asarray(cam, dtype=np.float64))
+            pts.append(np.asarray(pt, dtype=np.float64))
+            oc.append(np.asarray(c_, dtype=np.int64) + self.cam_off[-1])
+            op.append(np.asarray(p_, dtype=np.int64) + self.pt_off[-1])
+            uv.append(np.asarray(u_, dtype=np.float64))
+            self.cam_off.append(self.cam_off[-1] + len(cams[-1]))
+            self.pt_off.append(self.pt_off[-1] + len(pts[-1]))
+            self.obs_off.append(self.obs_off[-1] + len(oc[-1]))
+        self.n_prob = len(problems)
+        as_dev = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(device)  # noqa: E731
+        self.cam = as_dev(np.vstack(cams), torch.float64).clone()
+        self.pt = as_dev(np.vstack(pts), torch.float64).clone()
+        self.obs_cam = as_dev(np.concatenate(oc), torch.int32)
+        self.obs_pt = as_dev(np.concatenate(op), torch.int32)
+        self.obs_uv = as_dev(np.vstack(uv), torch.float64)
+        sizes = np.diff(self.cam_off)
+        self.prob_cam = as_dev(np.repeat(np.arange(self.n_prob), sizes), torch.int32)
+        self.prob_pt = as_dev(np.repeat(np.arange(self.n_prob), np.diff(self.pt_off)), torch.int32)
+        self.prob_obs_off = as_dev(np.asarray(self.obs_off), torch.int64)
+        self.precision = int(precision)
+        self.problem = B.make_problem(self.cam, self.pt, self.obs_cam, self.obs_pt, self.obs_uv, huber)
+        self.dims = B.stba_analyze(self.problem)
+        self.dims.gamma_max = int(gamma_max)
+        self.ws = B.alloc_workspace(B.stba_workspace_bytes(self.problem, self.dims, self.precision))
+        B.stba_prepare(self.problem, self.dims, self.precision, self.ws)
+        self.states = B.new_states(self.n_prob, device)
+        for b in range(self.n_prob):
+            B.stba_lm_init(self.states[b], lambda0, lambda_corr)
+
+    def sample(self, maps, alpha=1.0, seed=0, it=0):
+        """maps: one cluster map per problem (local cluster ids); the clusters are
+        numbered across the batch in problem order."""
+        full, base = [], 0
+        for mp in maps:
+            mp = np.asarray(mp, dtype=np.int64)
+            full.append(mp + base)
+            base += int(mp.max()) + 1
+        cc = torch.as_tensor(np.concatenate(full).astype(np.int32)).to(self.cam.device)
+        return B.make_sample(cc, base, alpha, seed, it)
+
+    def step(self, sample):
+        """One LM iteration of every problem (asynchronous)."""
+        B.stba_lm_step_batched(self.problem, self.dims, sample, self.states, self.n_prob, self.prob_cam,
+                               self.prob_pt, self.prob_obs_off, self.precision, self.ws)
+
+    def read_states(self):
+        return [B.read_state(self.states[b]) for b in range(self.n_prob)]
+
+    def cam_of(self, b):
+        return self.cam[self.cam_off[b]:self.cam_off[b + 1]]
+
+    def pt_of(self, b):
+        return self.pt[self.pt_off[b]:self.pt_off[b + 1]]
+
+
 class ResidualPlan:
     """Static structure (visibility graph) for repeated residual / J^T v calls.
 
