@@ -27,7 +27,8 @@ first iteration (whole clusters cut out of the problem, scaled to the full
 iteration by observations) and reports the GPU's FP64 and MIXED results on the
 same clusters against it.  `secondary` times the 200-camera ring and the
 Internet-like workloads; `diff_batch` the 64-problem differentiation batch;
-`ablations` the paper's ablations on the SLAM-like and Internet-like scenes;
+`batched_lm` the same 64 problems through one LM iteration against stepping
+them one by one; `ablations` the paper's ablations on the SLAM-like and Internet-like scenes;
 `huber`, `pcg` and `sgc` the robust loss, the inexact cluster solve and the
 device graph clustering.
 
@@ -89,6 +90,7 @@ def parse_args():
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the built-in launch settings instead of measuring them (stba_autotune) first")
     ap.add_argument("--no-diff-batch", action="store_true", help="skip the 64-problem differentiation batch")
+    ap.add_argument("--no-batched-lm", action="store_true", help="skip the many-problem LM iteration leg")
     ap.add_argument("--ablation-iters", type=int, default=20)
     ap.add_argument("--pmc-summary", action="store_true",
                     help="write a profiles/pmc_*.txt summary from counter CSVs (no GPU work)")
@@ -524,6 +526,9 @@ def main():
         out["secondary"] = sec
     if not args.no_diff_batch:
         out["diff_batch"] = diff_batch_leg(S, args)
+        torch.cuda.empty_cache()
+    if not args.no_batched_lm:
+        out["batched_lm"] = batched_lm_leg(S, args)
     print(json.dumps(out))
 
 
@@ -845,6 +850,62 @@ def diff_batch_leg(S, args):
         else:
             res["stored_jacobian"] = leg
     return res
+
+
+def batched_lm_leg(S, args, P=64, K=10):
+    """Many problems through one LM iteration (stba_lm_step_batched): the 64
+    ring problems of the differentiation batch (m_b ~ U{30..120}, n_b ~
+    U{5k..30k}, 7 views per point), cameras perturbed, each with its own map of
+    runs of U{10..40} cameras per iteration and its own damping and accept
+    decisions; FP64, K iterations of the whole batch against the same K
+    iterations taken problem by problem with stba_lm_step."""
+    import torch
+    import synth
+    scenes = synth.diff_batch(seeds=range(P))
+    probs = []
+    for b, s in enumerate(scenes):
+        rng = np.random.default_rng(100 + b)
+        cam = s.cam0.copy()
+        cam[:, :6] += rng.normal(0.0, 1e-3, size=(s.m, 6))
+        probs.append((cam, s.pt0.copy(), s.obs_cam, s.obs_pt, s.obs_uv))
+    gamma = 40
+    maps = [[synth.sequential_map(s.m, 10, gamma, b, t) for b, s in enumerate(scenes)] for t in range(K)]
+    bs = S.BatchSolver(probs, gamma, precision=S.STBA_FP64, lambda0=1e-3)
+    samples = [bs.sample(maps[t], alpha=1.0, seed=0, it=t) for t in range(K)]
+    cam0, pt0, st0 = bs.cam.clone(), bs.pt.clone(), bs.states.clone()
+
+    def batch_run(n):
+        bs.cam.copy_(cam0)
+        bs.pt.copy_(pt0)
+        bs.states.copy_(st0)
+        for t in range(n):
+            bs.step(samples[t])
+
+    batch_run(min(args.warmup, K))
+    t_batch = timed(lambda: batch_run(K))
+    got = bs.read_states()
+    sols = [S.StbaSolver(*pr, min(gamma, s.m), precision=S.STBA_FP64, lambda0=1e-3) for pr, s in zip(probs, scenes)]
+    one = [[sol.sample(maps[t][b], alpha=1.0, seed=0, it=t) for t in range(K)] for b, sol in enumerate(sols)]
+    c0 = [(sol.cam.clone(), sol.pt.clone()) for sol in sols]
+
+    def single_run(n):
+        for b, sol in enumerate(sols):
+            sol.cam.copy_(c0[b][0])
+            sol.pt.copy_(c0[b][1])
+            S.stba_lm_init(sol.state, 1e-3, 0.1)
+            for t in range(n):
+                sol.step(one[b][t])
+
+    single_run(min(args.warmup, K))
+    t_single = timed(lambda: single_run(K))
+    ref = [sol.read_state() for sol in sols]
+    same = all(g["n_accept"] == r["n_accept"] and g["lambda_"] == r["lambda_"] for g, r in zip(got, ref))
+    q = sum(s.q for s in scenes)
+    return {"problems": P, "observations": q, "cameras": sum(s.m for s in scenes), "iterations": K,
+            "batch_iter_per_s": K / t_batch, "problem_iter_per_s": P * K / t_batch,
+            "obs_per_s": q * K / t_batch, "one_by_one_problem_iter_per_s": P * K / t_single,
+            "speedup_over_one_by_one": t_single / t_batch, "same_decisions_as_one_by_one": bool(same),
+            "accepted_total": int(sum(g["n_accept"] for g in got))}
 
 
 SGC_BETA = 10.0   # the clustering's scale beta

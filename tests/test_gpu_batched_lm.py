@@ -41,7 +41,7 @@ def test_batched_step_matches_each_problem_alone(precision):
     torch.cuda.synchronize()
     got = bs.read_states()
     for b, (cam, pt, oc, op, uv) in enumerate(probs):
-        sol = S.StbaSolver(cam, pt, oc, op, uv, gamma, precision=precision, lambda0=1e-3)
+        sol = S.StbaSolver(cam, pt, oc, op, uv, min(gamma, cam.shape[0]), precision=precision, lambda0=1e-3)
         for t in range(K):
             sol.step(sol.sample(maps[t][b], alpha=1.0, seed=0, it=t))
         ref = sol.read_state()
