@@ -20,6 +20,7 @@ inline size_t obs_rec_bytes(bool fp64) { return fp64 ? 12 * 8 : 32 * 4; }
 constexpr int kSegRec = 16;        // per-segment record at the head observation: R^-1 (6), V*^-1 (6), V*^-1 w' (3)
 constexpr int kSchurChunk = 512;   // observation pairs per Schur work item (16 rounds of 32 pair slots)
 constexpr int kSchurPart = 100;    // doubles per partial sum: 81 block entries, 9 diag(U), 9 rhs, pad
+constexpr int kVjpPart = 1792;     // observations per wavefront in the camera sums of J^T v (28 rounds of 64)
 constexpr int kMaxCamsForClusters = 16384;   // cluster layout: every camera id and cluster count held in LDS
 constexpr int kSgcMaxCams = 6144;          // graph clustering: cameras held in one workgroup's LDS (24 B each)
 

@@ -1298,6 +1298,17 @@ __device__ inline int64_t xcd_contiguous_item(unsigned b, unsigned nb, int w) {
 }
 inline unsigned xcd_contiguous_grid(int64_t m) { return (grid_for(m, 4) + 7u) & ~7u; }
 
+// The same hand-out for a count known only on the device: XCD x takes items
+// [x per, (x + 1) per), per = ceil(count / 8), wavefront w of workgroup b the
+// item x per + 4 (b / 8) + w; -1 past the count.  The grid is sized for a
+// bound on the count (xcd_contiguous_grid(bound)).
+__device__ inline int64_t xcd_split_item(unsigned b, int w, int64_t count) {
+    const int64_t per = (count + 7) / 8;
+    const int64_t u = 4 * (int64_t)(b >> 3) + w;
+    const int64_t it = (int64_t)(b & 7u) * per + u;
+    return (u < per && it < count) ? it : -1;
+}
+
 // ---------------------------------------------------------------------------
 // MIXED: the residual of one FP64 refinement step of every cluster solve
 // (Eq. 13), r = b - S x with the S and b of the FP64 method, taken from J
@@ -1643,28 +1654,77 @@ __global__ __launch_bounds__(256) void k_accept_update(const double *rj_partials
 
 // ---------------------------------------------------------------------------
 // J^T v (differentiation of the residuals): the Jacobian is recomputed.
-// Cameras: one wavefront per camera (XCD-contiguous) over its observations
-// (fixed order), the camera's part of the projection formed once per lane;
-// points: one thread per point; observed pixels: -v.
+// Cameras: one wavefront per part of a camera's observations (at most
+// kVjpPart of them, in list order; the parts spread evenly over the XCDs, a
+// camera's parts next to each other), the camera's part of the projection
+// formed once per lane; a camera of one part writes its sum, the parts of the
+// others are added in part order by k_vjp_cam_sum.  Points: one thread per
+// point; observed pixels: -v (its own pass: written from the point loops the
+// stores scatter and cost more than a second read of v).
 // ---------------------------------------------------------------------------
+
+// Part `it` of the camera sums: its camera r, and the pair range [p0, p1) of
+// camera r's diagonal block it covers (empty for a camera without one).
+struct VjpPart {
+    int64_t r, p0, p1;
+    bool alone;   // the camera's only part
+};
+__device__ inline VjpPart vjp_part(int64_t it, const int64_t *part_off, const int32_t *part_cam,
+                                   const int64_t *diag_blk, const int64_t *blk_start) {
+    VjpPart q;
+    q.r = part_cam[it];
+    const int64_t first = part_off[q.r];
+    q.alone = part_off[q.r + 1] - first == 1;
+    const int64_t kb = diag_blk[q.r];
+    q.p0 = q.p1 = 0;
+    if (kb >= 0) {
+        const int64_t end = blk_start[kb + 1];
+        q.p0 = blk_start[kb] + (it - first) * kVjpPart;
+        q.p1 = q.p0 + kVjpPart < end ? q.p0 + kVjpPart : end;
+    }
+    return q;
+}
+
+// The wavefront's nine sums (every lane holds all of them after the
+// butterfly) to grad_cam, or to the part's slot of part_sum.
 template <typename T>
-__global__ __launch_bounds__(256) void k_vjp_cam(int32_t m, const double *__restrict__ cam,
+__device__ inline void vjp_part_out(double (&acc)[9], const VjpPart &q, int64_t it, double *part_sum, T *grad_cam) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1)
+#pragma unroll
+        for (int k = 0; k < 9; ++k) acc[k] += __shfl_xor(acc[k], d, 64);
+    double g = 0.0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+        if (lane == k) g = acc[k];
+    if (lane < 9) {
+        if (q.alone)
+            grad_cam[9 * q.r + lane] = (T)g;
+        else
+            part_sum[9 * it + lane] = g;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_vjp_cam(int32_t m, const int64_t *__restrict__ part_off,
+                                                 const int32_t *__restrict__ part_cam, const double *__restrict__ cam,
                                                  const double *__restrict__ pt, const int32_t *__restrict__ op,
                                                  const int64_t *__restrict__ diag_blk,
                                                  const int64_t *__restrict__ blk_start,
                                                  const uint64_t *__restrict__ pairs, const T *__restrict__ v,
-                                                 T *__restrict__ grad_cam) {
+                                                 double *__restrict__ part_sum, T *__restrict__ grad_cam) {
     const int lane = threadIdx.x & 63;
-    const int64_t r = xcd_contiguous_item(blockIdx.x, gridDim.x, threadIdx.x >> 6);
-    if (r >= m) return;
+    const int64_t it = xcd_split_item(blockIdx.x, threadIdx.x >> 6, part_off[m]);
+    if (it < 0) return;
+    const VjpPart q = vjp_part(it, part_off, part_cam, diag_blk, blk_start);
     double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    const int64_t kb = diag_blk[r];
-    if (kb >= 0) {
+    if (q.p0 < q.p1) {
         double c[9], cp[kCamPre];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) c[k] = cam[9 * r + k];
+        for (int k = 0; k < 9; ++k) c[k] = cam[9 * q.r + k];
         camera_pre(c, cp);
-        for (int64_t p = blk_start[kb] + lane; p < blk_start[kb + 1]; p += 64) {
+        for (int64_t p = q.p0 + lane; p < q.p1; p += 64) {
             const int64_t o = (int64_t)(pairs[p] >> 32);
             const int64_t j = op[o];
             const double X[3] = {pt[3 * j], pt[3 * j + 1], pt[3 * j + 2]};
@@ -1675,15 +1735,21 @@ __global__ __launch_bounds__(256) void k_vjp_cam(int32_t m, const double *__rest
             for (int k = 0; k < 9; ++k) acc[k] += jc[0][k] * v0 + jc[1][k] * v1;
         }
     }
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1)
-#pragma unroll
-        for (int k = 0; k < 9; ++k) acc[k] += __shfl_xor(acc[k], d, 64);
-    double g = 0.0;
-#pragma unroll
-    for (int k = 0; k < 9; ++k)
-        if (lane == k) g = acc[k];
-    if (lane < 9) grad_cam[9 * r + lane] = (T)g;
+    vjp_part_out(acc, q, it, part_sum, grad_cam);
+}
+
+// grad_cam of the cameras cut in several parts: their part sums in part order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_vjp_cam_sum(int32_t m, const int64_t *__restrict__ part_off,
+                                                     const double *__restrict__ part_sum, T *__restrict__ grad_cam) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 9 * (int64_t)m) return;
+    const int64_t r = i / 9, k = i % 9;
+    const int64_t a = part_off[r], b = part_off[r + 1];
+    if (b - a < 2) return;
+    double s = 0.0;
+    for (int64_t u = a; u < b; ++u) s += part_sum[9 * u + k];
+    grad_cam[i] = (T)s;
 }
 
 template <typename T>
@@ -1714,33 +1780,26 @@ __global__ __launch_bounds__(256) void k_vjp_pt(int32_t n, int64_t q, const doub
 // this x): the same sums as k_vjp_cam / k_vjp_pt, in the same order, with each
 // block read instead of recomputed.
 template <typename T>
-__global__ __launch_bounds__(256) void k_vjp_cam_stored(int32_t m, const int64_t *__restrict__ diag_blk,
+__global__ __launch_bounds__(256) void k_vjp_cam_stored(int32_t m, const int64_t *__restrict__ part_off,
+                                                        const int32_t *__restrict__ part_cam,
+                                                        const int64_t *__restrict__ diag_blk,
                                                         const int64_t *__restrict__ blk_start,
                                                         const uint64_t *__restrict__ pairs, const T *__restrict__ Jc,
-                                                        const T *__restrict__ v, T *__restrict__ grad_cam) {
+                                                        const T *__restrict__ v, double *__restrict__ part_sum,
+                                                        T *__restrict__ grad_cam) {
     const int lane = threadIdx.x & 63;
-    const int64_t r = xcd_contiguous_item(blockIdx.x, gridDim.x, threadIdx.x >> 6);
-    if (r >= m) return;
+    const int64_t it = xcd_split_item(blockIdx.x, threadIdx.x >> 6, part_off[m]);
+    if (it < 0) return;
+    const VjpPart q = vjp_part(it, part_off, part_cam, diag_blk, blk_start);
     double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    const int64_t kb = diag_blk[r];
-    if (kb >= 0) {
-        for (int64_t p = blk_start[kb] + lane; p < blk_start[kb + 1]; p += 64) {
-            const int64_t o = (int64_t)(pairs[p] >> 32);
-            const T *jc = Jc + 18 * o;
-            const double v0 = (double)v[2 * o], v1 = (double)v[2 * o + 1];
+    for (int64_t p = q.p0 + lane; p < q.p1; p += 64) {
+        const int64_t o = (int64_t)(pairs[p] >> 32);
+        const T *jc = Jc + 18 * o;
+        const double v0 = (double)v[2 * o], v1 = (double)v[2 * o + 1];
 #pragma unroll
-            for (int k = 0; k < 9; ++k) acc[k] += (double)jc[k] * v0 + (double)jc[9 + k] * v1;
-        }
+        for (int k = 0; k < 9; ++k) acc[k] += (double)jc[k] * v0 + (double)jc[9 + k] * v1;
     }
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1)
-#pragma unroll
-        for (int k = 0; k < 9; ++k) acc[k] += __shfl_xor(acc[k], d, 64);
-    double g = 0.0;
-#pragma unroll
-    for (int k = 0; k < 9; ++k)
-        if (lane == k) g = acc[k];
-    if (lane < 9) grad_cam[9 * r + lane] = (T)g;
+    vjp_part_out(acc, q, it, part_sum, grad_cam);
 }
 
 template <typename T>
@@ -2121,36 +2180,38 @@ hipError_t launch_batch_accept(const stba_problem &p, int32_t n_prob, int32_t l,
 }
 
 template <typename T>
-hipError_t launch_vjp(const stba_problem &p, const int64_t *pt_off, const int64_t *diag_blk, const int2 *blk_key,
-                      const int64_t *blk_start, const uint64_t *pairs, const T *v, T *grad_cam, T *grad_pt,
-                      T *grad_uv, hipStream_t st) {
-    (void)blk_key;
-    k_vjp_cam<T><<<xcd_contiguous_grid(p.m), 256, 0, st>>>(p.m, p.cam, p.pt, p.obs_pt, diag_blk, blk_start, pairs, v,
-                                                           grad_cam);
+hipError_t launch_vjp(const stba_problem &p, const int64_t *pt_off, const int64_t *diag_blk, const int64_t *blk_start,
+                      const uint64_t *pairs, const VjpParts &parts, const T *v, T *grad_cam, T *grad_pt, T *grad_uv,
+                      hipStream_t st) {
+    k_vjp_cam<T><<<xcd_contiguous_grid(parts.cap), 256, 0, st>>>(p.m, parts.off, parts.cam, p.cam, p.pt, p.obs_pt,
+                                                                 diag_blk, blk_start, pairs, v, parts.sum, grad_cam);
+    k_vjp_cam_sum<T><<<grid_for(9 * (int64_t)p.m), 256, 0, st>>>(p.m, parts.off, parts.sum, grad_cam);
     k_vjp_pt<T><<<grid_for(p.n), 256, 0, st>>>(p.n, p.q, p.cam, p.pt, p.obs_cam, pt_off, v, grad_pt);
     k_neg<T><<<grid_for(2 * p.q), 256, 0, st>>>(2 * p.q, v, grad_uv);
     return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_vjp_stored(const stba_problem &p, const int64_t *pt_off, const int64_t *diag_blk,
-                             const int64_t *blk_start, const uint64_t *pairs, const T *v, const T *Jc, const T *Jp,
-                             T *grad_cam, T *grad_pt, T *grad_uv, hipStream_t st) {
-    k_vjp_cam_stored<T><<<xcd_contiguous_grid(p.m), 256, 0, st>>>(p.m, diag_blk, blk_start, pairs, Jc, v, grad_cam);
+                             const int64_t *blk_start, const uint64_t *pairs, const VjpParts &parts, const T *v,
+                             const T *Jc, const T *Jp, T *grad_cam, T *grad_pt, T *grad_uv, hipStream_t st) {
+    k_vjp_cam_stored<T><<<xcd_contiguous_grid(parts.cap), 256, 0, st>>>(p.m, parts.off, parts.cam, diag_blk,
+                                                                        blk_start, pairs, Jc, v, parts.sum, grad_cam);
+    k_vjp_cam_sum<T><<<grid_for(9 * (int64_t)p.m), 256, 0, st>>>(p.m, parts.off, parts.sum, grad_cam);
     k_vjp_pt_stored<T><<<grid_for(p.n), 256, 0, st>>>(p.n, pt_off, Jp, v, grad_pt);
     k_neg<T><<<grid_for(2 * p.q), 256, 0, st>>>(2 * p.q, v, grad_uv);
     return hipGetLastError();
 }
 template hipError_t launch_vjp_stored<double>(const stba_problem &, const int64_t *, const int64_t *, const int64_t *,
-                                              const uint64_t *, const double *, const double *, const double *,
-                                              double *, double *, double *, hipStream_t);
+                                              const uint64_t *, const VjpParts &, const double *, const double *,
+                                              const double *, double *, double *, double *, hipStream_t);
 template hipError_t launch_vjp_stored<float>(const stba_problem &, const int64_t *, const int64_t *, const int64_t *,
-                                             const uint64_t *, const float *, const float *, const float *, float *,
-                                             float *, float *, hipStream_t);
-template hipError_t launch_vjp<double>(const stba_problem &, const int64_t *, const int64_t *, const int2 *,
-                                       const int64_t *, const uint64_t *, const double *, double *, double *,
+                                             const uint64_t *, const VjpParts &, const float *, const float *,
+                                             const float *, float *, float *, float *, hipStream_t);
+template hipError_t launch_vjp<double>(const stba_problem &, const int64_t *, const int64_t *, const int64_t *,
+                                       const uint64_t *, const VjpParts &, const double *, double *, double *,
                                        double *, hipStream_t);
-template hipError_t launch_vjp<float>(const stba_problem &, const int64_t *, const int64_t *, const int2 *,
-                                      const int64_t *, const uint64_t *, const float *, float *, float *, float *,
+template hipError_t launch_vjp<float>(const stba_problem &, const int64_t *, const int64_t *, const int64_t *,
+                                      const uint64_t *, const VjpParts &, const float *, float *, float *, float *,
                                       hipStream_t);
 
 }  // namespace stba

@@ -25,6 +25,11 @@ struct PrepBufs {
     int32_t *chunk_blk;      // [chunk_cap] block of each chunk
     int64_t chunk_cap;       // blk_cap + n_pairs / kSchurChunk + 1
     int64_t *n_chunks;       // [1]
+    // camera sums of J^T v: camera r's observations (its diagonal block) cut
+    // into parts of at most kVjpPart, one wavefront each
+    int64_t *vjp_part_off;   // [m + 1] first part of each camera; [m]: the number of parts
+    int32_t *vjp_part_cam;   // [vjp_part_cap] camera of each part
+    int64_t vjp_part_cap;    // m + n_pairs / kVjpPart + 1
     void *tmp;            // rocPRIM temporary storage
     size_t tmp_bytes;
 };
@@ -191,15 +196,24 @@ hipError_t launch_batch_accept(const stba_problem &p, int32_t n_prob, int32_t l,
                                int32_t *status, stba_lm_state *states, const double *dcam, const double *dpt,
                                hipStream_t st);
 
+// The camera parts of stba_prepare (vjp_part_off, vjp_part_cam, part_cap of
+// them at most) and part_sum, 9 doubles per part, for the cameras cut in
+// several.
+struct VjpParts {
+    const int64_t *off;
+    const int32_t *cam;
+    int64_t cap;
+    double *sum;
+};
 template <typename T>
 hipError_t launch_vjp(const stba_problem &p, const int64_t *pt_off, const int64_t *diag_blk,
-                      const int2 *blk_key, const int64_t *blk_start, const uint64_t *pairs, const T *v,
+                      const int64_t *blk_start, const uint64_t *pairs, const VjpParts &parts, const T *v,
                       T *grad_cam, T *grad_pt, T *grad_uv, hipStream_t st);
 // The same products from stored blocks Jc [q][18], Jp [q][6] (precision T).
 template <typename T>
 hipError_t launch_vjp_stored(const stba_problem &p, const int64_t *pt_off, const int64_t *diag_blk,
-                             const int64_t *blk_start, const uint64_t *pairs, const T *v, const T *Jc, const T *Jp,
-                             T *grad_cam, T *grad_pt, T *grad_uv, hipStream_t st);
+                             const int64_t *blk_start, const uint64_t *pairs, const VjpParts &parts, const T *v,
+                             const T *Jc, const T *Jp, T *grad_cam, T *grad_pt, T *grad_uv, hipStream_t st);
 
 // --- camera clustering (sgc.hip) ---------------------------------------------
 // One workgroup; Pg / Tg / Wg hold a pair label, clock and weight per block of

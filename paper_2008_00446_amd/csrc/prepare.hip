@@ -134,6 +134,48 @@ __global__ void k_total_chunks(const int64_t *n_blocks, const int64_t *blk_chunk
     n_chunks[0] = blk_chunk_off[n_blocks[0]];
 }
 
+// Camera parts of the J^T v camera sums: camera r's diagonal-block list of
+// len_r observations in ceil(len_r / kVjpPart) parts (one for a camera with
+// none); part_off by an exclusive scan over the cameras in order, part_off[m]
+// the total (at most m + q / kVjpPart).  One workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void k_vjp_parts(int32_t m, const int64_t *diag_blk, const int64_t *blk_start,
+                                                    int64_t *part_off, int32_t *part_cam, int64_t cap) {
+    __shared__ int64_t wsum[16];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int64_t carry = 0;
+    for (int32_t base = 0; base < m; base += 1024) {
+        const int32_t r = base + (int32_t)threadIdx.x;
+        int64_t s = 0;
+        if (r < m) {
+            const int64_t kb = diag_blk[r];
+            const int64_t len = kb >= 0 ? blk_start[kb + 1] - blk_start[kb] : 0;
+            s = len > 0 ? (len + kVjpPart - 1) / kVjpPart : 1;
+        }
+        int64_t inc = s;   // inclusive scan within the wavefront, then over the 16 wavefronts
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int64_t t = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += t;
+        }
+        if (lane == 63) wsum[wv] = inc;
+        __syncthreads();
+        int64_t before = 0, total = 0;
+        for (int w = 0; w < 16; ++w) {
+            if (w < wv) before += wsum[w];
+            total += wsum[w];
+        }
+        const int64_t first = carry + before + inc - s;
+        if (r < m) {
+            part_off[r] = first;
+            for (int64_t i = 0; i < s; ++i)
+                if (first + i < cap) part_cam[first + i] = r;
+        }
+        carry += total;
+        __syncthreads();   // wsum is rewritten in the next round
+    }
+    if (threadIdx.x == 0) part_off[m] = carry < cap ? carry : cap;
+}
+
 __global__ void k_fill_i64(int64_t *a, int64_t len, int64_t v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < len) a[i] = v;
@@ -198,6 +240,7 @@ hipError_t launch_prepare(const stba_problem &p, int64_t np, const PrepBufs &b, 
     if (e != hipSuccess) return e;
     k_chunk_blk<<<grid_for(b.blk_cap), 256, 0, st>>>(b.n_blocks, b.blk_chunk_off, b.chunk_blk);
     k_total_chunks<<<1, 1, 0, st>>>(b.n_blocks, b.blk_chunk_off, b.n_chunks);
+    k_vjp_parts<<<1, 1024, 0, st>>>(p.m, b.diag_blk, b.blk_start, b.vjp_part_off, b.vjp_part_cam, b.vjp_part_cap);
     return hipGetLastError();
 }
 

@@ -15,8 +15,8 @@ struct Layout {
     size_t status, lam2;
     // static plan (stba_prepare)
     size_t pt_off, pair_off, scratch_a, keys_in, keys_out, vals_in, pairs, blk_of, blk_key, blk_start, n_blocks,
-        diag_blk, blk_chunk_off, chunk_blk, n_chunks, part, tmp;
-    int64_t blk_cap, chunk_cap;
+        diag_blk, blk_chunk_off, chunk_blk, n_chunks, part, vjp_part_off, vjp_part_cam, vjp_part_sum, tmp;
+    int64_t blk_cap, chunk_cap, vjp_part_cap;
     size_t tmp_bytes;
     // per iteration
     size_t cl_n, cl_Np, cl_start, cl_cams, cam_local, cl_status, S_off;
@@ -107,6 +107,11 @@ bool make_layout(const stba_problem *p, const stba_dims *d, int precision, Layou
     L.chunk_blk = take(4 * (size_t)L.chunk_cap);
     L.n_chunks = take(8);
     L.part = take(8 * (size_t)kSchurPart * (size_t)L.chunk_cap);
+    // camera parts of the J^T v sums: ceil(len / kVjpPart) <= 1 + len / kVjpPart per camera
+    L.vjp_part_cap = (int64_t)m + (int64_t)np / kVjpPart + 1;
+    L.vjp_part_off = take(8 * (m + 1));
+    L.vjp_part_cam = take(4 * (size_t)L.vjp_part_cap);
+    L.vjp_part_sum = take(8 * 9 * (size_t)L.vjp_part_cap);
     L.tmp_bytes = prepare_tmp_bytes(d->n_pairs, p->m, 0);
     L.tmp = take(L.tmp_bytes);
     L.cl_n = take(4 * m);
@@ -223,6 +228,16 @@ int build_rcs_impl(const stba_problem *p, const stba_dims *d, const stba_sample 
                              at<int32_t>(ws, L.seg_head), Jc, at<T>(ws, L.obsd), lam2, at<double>(ws, L.S),
                              at<double>(ws, L.b), st));
     return STBA_OK;
+}
+
+// The camera parts stba_prepare left for the J^T v camera sums.
+VjpParts vjp_parts_of(const Layout &L, void *ws) {
+    VjpParts v;
+    v.off = at<int64_t>(ws, L.vjp_part_off);
+    v.cam = at<int32_t>(ws, L.vjp_part_cam);
+    v.cap = L.vjp_part_cap;
+    v.sum = at<double>(ws, L.vjp_part_sum);
+    return v;
 }
 
 CholTeam team_of(const Layout &L, void *ws, const stba_dims *d) {
@@ -570,6 +585,9 @@ int stba_prepare(const stba_problem *p, const stba_dims *dims, int precision, vo
     b.chunk_blk = at<int32_t>(ws, L.chunk_blk);
     b.chunk_cap = L.chunk_cap;
     b.n_chunks = at<int64_t>(ws, L.n_chunks);
+    b.vjp_part_off = at<int64_t>(ws, L.vjp_part_off);
+    b.vjp_part_cam = at<int32_t>(ws, L.vjp_part_cam);
+    b.vjp_part_cap = L.vjp_part_cap;
     b.tmp = at<void>(ws, L.tmp);
     b.tmp_bytes = L.tmp_bytes;
     STBA_HIP(launch_reset_status(at<int32_t>(ws, L.status), stream));
@@ -762,13 +780,14 @@ int stba_residual_vjp(const stba_problem *p, const stba_dims *dims, int precisio
     Layout L;
     STBA_TRY(front(p, dims, precision, ws, ws_bytes, L));
     if (!v || !grad_cam || !grad_pt || !grad_uv) return STBA_EINVAL;
+    const VjpParts parts = vjp_parts_of(L, ws);
     if (precision == STBA_FP64)
-        STBA_HIP(launch_vjp<double>(*p, at<int64_t>(ws, L.pt_off), at<int64_t>(ws, L.diag_blk), at<int2>(ws, L.blk_key),
-                                    at<int64_t>(ws, L.blk_start), at<uint64_t>(ws, L.pairs), (const double *)v,
+        STBA_HIP(launch_vjp<double>(*p, at<int64_t>(ws, L.pt_off), at<int64_t>(ws, L.diag_blk),
+                                    at<int64_t>(ws, L.blk_start), at<uint64_t>(ws, L.pairs), parts, (const double *)v,
                                     (double *)grad_cam, (double *)grad_pt, (double *)grad_uv, stream));
     else
-        STBA_HIP(launch_vjp<float>(*p, at<int64_t>(ws, L.pt_off), at<int64_t>(ws, L.diag_blk), at<int2>(ws, L.blk_key),
-                                   at<int64_t>(ws, L.blk_start), at<uint64_t>(ws, L.pairs), (const float *)v,
+        STBA_HIP(launch_vjp<float>(*p, at<int64_t>(ws, L.pt_off), at<int64_t>(ws, L.diag_blk),
+                                   at<int64_t>(ws, L.blk_start), at<uint64_t>(ws, L.pairs), parts, (const float *)v,
                                    (float *)grad_cam, (float *)grad_pt, (float *)grad_uv, stream));
     return STBA_OK;
 }
@@ -792,16 +811,17 @@ int stba_residual_vjp_stored(const stba_problem *p, const stba_dims *dims, int p
     Layout L;
     STBA_TRY(front(p, dims, precision, ws, ws_bytes, L));
     if (!v || !Jc || !Jp || !grad_cam || !grad_pt || !grad_uv) return STBA_EINVAL;
+    const VjpParts parts = vjp_parts_of(L, ws);
     if (precision == STBA_FP64)
         STBA_HIP(launch_vjp_stored<double>(*p, at<int64_t>(ws, L.pt_off), at<int64_t>(ws, L.diag_blk),
-                                           at<int64_t>(ws, L.blk_start), at<uint64_t>(ws, L.pairs), (const double *)v,
-                                           (const double *)Jc, (const double *)Jp, (double *)grad_cam,
-                                           (double *)grad_pt, (double *)grad_uv, stream));
+                                           at<int64_t>(ws, L.blk_start), at<uint64_t>(ws, L.pairs), parts,
+                                           (const double *)v, (const double *)Jc, (const double *)Jp,
+                                           (double *)grad_cam, (double *)grad_pt, (double *)grad_uv, stream));
     else
         STBA_HIP(launch_vjp_stored<float>(*p, at<int64_t>(ws, L.pt_off), at<int64_t>(ws, L.diag_blk),
-                                          at<int64_t>(ws, L.blk_start), at<uint64_t>(ws, L.pairs), (const float *)v,
-                                          (const float *)Jc, (const float *)Jp, (float *)grad_cam, (float *)grad_pt,
-                                          (float *)grad_uv, stream));
+                                          at<int64_t>(ws, L.blk_start), at<uint64_t>(ws, L.pairs), parts,
+                                          (const float *)v, (const float *)Jc, (const float *)Jp, (float *)grad_cam,
+                                          (float *)grad_pt, (float *)grad_uv, stream));
     return STBA_OK;
 }
 

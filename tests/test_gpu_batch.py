@@ -51,12 +51,19 @@ def test_batched_gradient_matches_oracle_per_problem(precision, tol):
     gc, gp, gu = tc.grad.cpu().numpy(), tp.grad.cpu().numpy(), tu.grad.cpu().numpy()
     q0 = 0
     F_all = 0.0
+    heavy = 0
     for s, (c0, c1, p0, p1) in zip(batch, spans):
         rc, rp, ru = O.gradient(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv)
         assert rel(gc[c0:c1], rc) < tol and rel(gp[p0:p1], rp) < tol
         assert rel(gu[q0:q0 + s.q], ru) < tol
+        # cameras with more observations than one wavefront takes (1792): their
+        # sums come from several parts, each row checked on its own
+        for i in np.flatnonzero(np.bincount(s.obs_cam, minlength=s.m) > 1792):
+            assert rel(gc[c0 + i], rc[i]) < tol, (s.m, i)
+            heavy += 1
         q0 += s.q
         F_all += O.cost(O.residuals(s.cam0, s.pt0, s.obs_cam, s.obs_pt, s.obs_uv))
+    assert heavy > 0
     assert abs(loss.item() - F_all) <= tol * F_all
 
 
