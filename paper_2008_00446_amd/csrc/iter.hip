@@ -1663,24 +1663,33 @@ __global__ __launch_bounds__(256) void k_accept_update(const double *rj_partials
 // stores scatter and cost more than a second read of v).
 // ---------------------------------------------------------------------------
 
-// Part `it` of the camera sums: its camera r, and the pair range [p0, p1) of
-// camera r's diagonal block it covers (empty for a camera without one).
+// Part `it` of the camera sums: its camera r, the pair range [p0, p1) of
+// camera r's diagonal block it covers (empty for a camera without one), and
+// the same entries' range [d0, d1) of the camera-major (observation, point)
+// list (at most q entries; with obs_off null, left empty).
 struct VjpPart {
-    int64_t r, p0, p1;
+    int64_t r, p0, p1, d0, d1;
     bool alone;   // the camera's only part
 };
 __device__ inline VjpPart vjp_part(int64_t it, const int64_t *part_off, const int32_t *part_cam,
-                                   const int64_t *diag_blk, const int64_t *blk_start) {
+                                   const int64_t *diag_blk, const int64_t *blk_start, const int64_t *obs_off,
+                                   int64_t q_obs) {
     VjpPart q;
     q.r = part_cam[it];
     const int64_t first = part_off[q.r];
     q.alone = part_off[q.r + 1] - first == 1;
     const int64_t kb = diag_blk[q.r];
-    q.p0 = q.p1 = 0;
+    q.p0 = q.p1 = q.d0 = q.d1 = 0;
     if (kb >= 0) {
         const int64_t end = blk_start[kb + 1];
         q.p0 = blk_start[kb] + (it - first) * kVjpPart;
         q.p1 = q.p0 + kVjpPart < end ? q.p0 + kVjpPart : end;
+        if (obs_off != nullptr) {
+            q.d0 = obs_off[q.r] + (q.p0 - blk_start[kb]);
+            q.d1 = q.d0 + (q.p1 - q.p0);
+            if (q.d1 > q_obs) q.d1 = q_obs;
+            if (q.d0 > q.d1) q.d0 = q.d1;
+        }
     }
     return q;
 }
@@ -1706,33 +1715,76 @@ __device__ inline void vjp_part_out(double (&acc)[9], const VjpPart &q, int64_t 
     }
 }
 
+// The gathers of one round of k_vjp_cam: the point and the cotangent of
+// entry e, the cotangent zero for a lane past the part's end.
 template <typename T>
-__global__ __launch_bounds__(256) void k_vjp_cam(int32_t m, const int64_t *__restrict__ part_off,
-                                                 const int32_t *__restrict__ part_cam, const double *__restrict__ cam,
-                                                 const double *__restrict__ pt, const int32_t *__restrict__ op,
+struct VjpRound {
+    double X[3], v0, v1;
+};
+template <typename T>
+__device__ inline void vjp_gather(int2 e, bool on, const double *__restrict__ pt, const T *__restrict__ v,
+                                  VjpRound<T> &g) {
+    const int64_t o = e.x, j = e.y;
+    g.X[0] = pt[3 * j];
+    g.X[1] = pt[3 * j + 1];
+    g.X[2] = pt[3 * j + 2];
+    g.v0 = on ? (double)v[2 * o] : 0.0;
+    g.v1 = on ? (double)v[2 * o + 1] : 0.0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_vjp_cam(int32_t m, int64_t q_obs, const int64_t *__restrict__ part_off,
+                                                 const int32_t *__restrict__ part_cam,
+                                                 const int64_t *__restrict__ obs_off, const int2 *__restrict__ oj,
+                                                 const double *__restrict__ cam, const double *__restrict__ pt,
                                                  const int64_t *__restrict__ diag_blk,
-                                                 const int64_t *__restrict__ blk_start,
-                                                 const uint64_t *__restrict__ pairs, const T *__restrict__ v,
+                                                 const int64_t *__restrict__ blk_start, const T *__restrict__ v,
                                                  double *__restrict__ part_sum, T *__restrict__ grad_cam) {
+    // the camera's part of the projection in LDS (read in every round, not
+    // held in 48 registers: the occupancy stays at four wavefronts)
+    __shared__ double cps[4][kCamPre];
     const int lane = threadIdx.x & 63;
     const int64_t it = xcd_split_item(blockIdx.x, threadIdx.x >> 6, part_off[m]);
     if (it < 0) return;
-    const VjpPart q = vjp_part(it, part_off, part_cam, diag_blk, blk_start);
+    const VjpPart q = vjp_part(it, part_off, part_cam, diag_blk, blk_start, obs_off, q_obs);
     double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    if (q.p0 < q.p1) {
-        double c[9], cp[kCamPre];
+    if (q.d0 < q.d1) {
+        double *cp = cps[threadIdx.x >> 6];
+        {
+            double c[9], cr[kCamPre];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) c[k] = cam[9 * q.r + k];
-        camera_pre(c, cp);
-        for (int64_t p = q.p0 + lane; p < q.p1; p += 64) {
-            const int64_t o = (int64_t)(pairs[p] >> 32);
-            const int64_t j = op[o];
-            const double X[3] = {pt[3 * j], pt[3 * j + 1], pt[3 * j + 2]};
+            for (int k = 0; k < 9; ++k) c[k] = cam[9 * q.r + k];
+            camera_pre(c, cr);
+            if (lane == 0) {
+#pragma unroll
+                for (int k = 0; k < kCamPre; ++k) cp[k] = cr[k];
+            }
+            __syncwarp();
+        }
+        // Rounds of 64 entries in list order, lane l taking entry d0 + 64 t + l
+        // in round t.  The list entries are read two rounds ahead and the
+        // gathers they address one round ahead, so a round's arithmetic runs
+        // while the next round's loads are in flight.  A lane past the end
+        // reads the part's first entry and adds zero.
+        const int rounds = (int)((q.d1 - q.d0 + 63) / 64);
+        auto entry = [&](int t) {
+            const int64_t d = q.d0 + 64 * (int64_t)t + lane;
+            return oj[d < q.d1 ? d : q.d0];
+        };
+        int2 e1 = rounds > 1 ? entry(1) : make_int2(0, 0);
+        VjpRound<T> g;
+        vjp_gather(entry(0), q.d0 + lane < q.d1, pt, v, g);
+        for (int t = 0; t < rounds; ++t) {
+            int2 e2 = t + 2 < rounds ? entry(t + 2) : e1;
+            asm volatile("" ::: "memory");   // cp is read from LDS in this round
+            VjpRound<T> gn = g;
+            if (t + 1 < rounds) vjp_gather(e1, q.d0 + 64 * (int64_t)(t + 1) + lane < q.d1, pt, v, gn);
             double pix[2], jc[2][9], jp[2][3];
-            project_jac_pre(cp, X, pix, jc, jp);
-            const double v0 = (double)v[2 * o], v1 = (double)v[2 * o + 1];
+            project_jac_pre(cp, g.X, pix, jc, jp);
 #pragma unroll
-            for (int k = 0; k < 9; ++k) acc[k] += jc[0][k] * v0 + jc[1][k] * v1;
+            for (int k = 0; k < 9; ++k) acc[k] += jc[0][k] * g.v0 + jc[1][k] * g.v1;
+            g = gn;
+            e1 = e2;
         }
     }
     vjp_part_out(acc, q, it, part_sum, grad_cam);
@@ -1790,7 +1842,7 @@ __global__ __launch_bounds__(256) void k_vjp_cam_stored(int32_t m, const int64_t
     const int lane = threadIdx.x & 63;
     const int64_t it = xcd_split_item(blockIdx.x, threadIdx.x >> 6, part_off[m]);
     if (it < 0) return;
-    const VjpPart q = vjp_part(it, part_off, part_cam, diag_blk, blk_start);
+    const VjpPart q = vjp_part(it, part_off, part_cam, diag_blk, blk_start, nullptr, 0);
     double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int64_t p = q.p0 + lane; p < q.p1; p += 64) {
         const int64_t o = (int64_t)(pairs[p] >> 32);
@@ -2183,8 +2235,10 @@ template <typename T>
 hipError_t launch_vjp(const stba_problem &p, const int64_t *pt_off, const int64_t *diag_blk, const int64_t *blk_start,
                       const uint64_t *pairs, const VjpParts &parts, const T *v, T *grad_cam, T *grad_pt, T *grad_uv,
                       hipStream_t st) {
-    k_vjp_cam<T><<<xcd_contiguous_grid(parts.cap), 256, 0, st>>>(p.m, parts.off, parts.cam, p.cam, p.pt, p.obs_pt,
-                                                                 diag_blk, blk_start, pairs, v, parts.sum, grad_cam);
+    (void)pairs;
+    k_vjp_cam<T><<<xcd_contiguous_grid(parts.cap), 256, 0, st>>>(p.m, p.q, parts.off, parts.cam, parts.obs_off,
+                                                                 parts.oj, p.cam, p.pt, diag_blk, blk_start, v,
+                                                                 parts.sum, grad_cam);
     k_vjp_cam_sum<T><<<grid_for(9 * (int64_t)p.m), 256, 0, st>>>(p.m, parts.off, parts.sum, grad_cam);
     k_vjp_pt<T><<<grid_for(p.n), 256, 0, st>>>(p.n, p.q, p.cam, p.pt, p.obs_cam, pt_off, v, grad_pt);
     k_neg<T><<<grid_for(2 * p.q), 256, 0, st>>>(2 * p.q, v, grad_uv);

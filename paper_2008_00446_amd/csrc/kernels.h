@@ -30,6 +30,8 @@ struct PrepBufs {
     int64_t *vjp_part_off;   // [m + 1] first part of each camera; [m]: the number of parts
     int32_t *vjp_part_cam;   // [vjp_part_cap] camera of each part
     int64_t vjp_part_cap;    // m + n_pairs / kVjpPart + 1
+    int64_t *vjp_obs_off;    // [m + 1] first entry of each camera in vjp_oj
+    int2 *vjp_oj;            // [q] (observation, point) of each camera's observations, camera-major
     void *tmp;            // rocPRIM temporary storage
     size_t tmp_bytes;
 };
@@ -204,6 +206,8 @@ struct VjpParts {
     const int32_t *cam;
     int64_t cap;
     double *sum;
+    const int64_t *obs_off;   // [m + 1] first entry of each camera in oj
+    const int2 *oj;           // [q] (observation, point), camera-major in diagonal-block order
 };
 template <typename T>
 hipError_t launch_vjp(const stba_problem &p, const int64_t *pt_off, const int64_t *diag_blk,

@@ -134,46 +134,83 @@ __global__ void k_total_chunks(const int64_t *n_blocks, const int64_t *blk_chunk
     n_chunks[0] = blk_chunk_off[n_blocks[0]];
 }
 
+// Exclusive scan of one value per camera by one workgroup of 1024 threads:
+// returns the sum of the values of the cameras before this thread's, the
+// round's total in `total`.  Every thread of the workgroup calls it.
+__device__ inline int64_t block_scan_excl(int64_t s, int64_t *wsum, int64_t &total) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int64_t inc = s;   // inclusive scan within the wavefront, then over the 16 wavefronts
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int64_t t = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += t;
+    }
+    if (lane == 63) wsum[wv] = inc;
+    __syncthreads();
+    int64_t before = 0;
+    total = 0;
+    for (int w = 0; w < 16; ++w) {
+        if (w < wv) before += wsum[w];
+        total += wsum[w];
+    }
+    __syncthreads();   // wsum is rewritten by the next call
+    return before + inc - s;
+}
+
 // Camera parts of the J^T v camera sums: camera r's diagonal-block list of
 // len_r observations in ceil(len_r / kVjpPart) parts (one for a camera with
 // none); part_off by an exclusive scan over the cameras in order, part_off[m]
-// the total (at most m + q / kVjpPart).  One workgroup of 1024 threads.
+// the total (at most m + q / kVjpPart); obs_off the exclusive scan of len_r
+// (obs_off[m] = q).  One workgroup of 1024 threads.
 __global__ __launch_bounds__(1024) void k_vjp_parts(int32_t m, const int64_t *diag_blk, const int64_t *blk_start,
-                                                    int64_t *part_off, int32_t *part_cam, int64_t cap) {
+                                                    int64_t *part_off, int32_t *part_cam, int64_t cap,
+                                                    int64_t *obs_off) {
     __shared__ int64_t wsum[16];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    int64_t carry = 0;
+    int64_t carry = 0, carry_o = 0;
     for (int32_t base = 0; base < m; base += 1024) {
         const int32_t r = base + (int32_t)threadIdx.x;
-        int64_t s = 0;
+        int64_t s = 0, len = 0;
         if (r < m) {
             const int64_t kb = diag_blk[r];
-            const int64_t len = kb >= 0 ? blk_start[kb + 1] - blk_start[kb] : 0;
+            len = kb >= 0 ? blk_start[kb + 1] - blk_start[kb] : 0;
             s = len > 0 ? (len + kVjpPart - 1) / kVjpPart : 1;
         }
-        int64_t inc = s;   // inclusive scan within the wavefront, then over the 16 wavefronts
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const int64_t t = __shfl_up(inc, d, 64);
-            if (lane >= d) inc += t;
-        }
-        if (lane == 63) wsum[wv] = inc;
-        __syncthreads();
-        int64_t before = 0, total = 0;
-        for (int w = 0; w < 16; ++w) {
-            if (w < wv) before += wsum[w];
-            total += wsum[w];
-        }
-        const int64_t first = carry + before + inc - s;
+        int64_t total = 0, total_o = 0;
+        const int64_t first = carry + block_scan_excl(s, wsum, total);
+        const int64_t first_o = carry_o + block_scan_excl(len, wsum, total_o);
         if (r < m) {
             part_off[r] = first;
+            obs_off[r] = first_o;
             for (int64_t i = 0; i < s; ++i)
                 if (first + i < cap) part_cam[first + i] = r;
         }
         carry += total;
-        __syncthreads();   // wsum is rewritten in the next round
+        carry_o += total_o;
     }
-    if (threadIdx.x == 0) part_off[m] = carry < cap ? carry : cap;
+    if (threadIdx.x == 0) {
+        part_off[m] = carry < cap ? carry : cap;
+        obs_off[m] = carry_o;
+    }
+}
+
+// (observation, point) of camera r's diagonal-block pairs in list order at
+// oj[obs_off[r] ..]: one wavefront per camera.  Without duplicated
+// observations (which stba_analyze reports) there are q entries; past q
+// nothing is written.
+__global__ __launch_bounds__(256) void k_vjp_oj(int32_t m, int64_t q, const int64_t *diag_blk,
+                                                const int64_t *blk_start, const uint64_t *pairs,
+                                                const int32_t *obs_pt, const int64_t *obs_off, int2 *oj) {
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= m) return;
+    const int64_t kb = diag_blk[r];
+    if (kb < 0) return;
+    const int64_t p0 = blk_start[kb], d0 = obs_off[r];
+    int64_t len = blk_start[kb + 1] - p0;
+    if (d0 + len > q) len = q > d0 ? q - d0 : 0;
+    for (int64_t t = threadIdx.x & 63; t < len; t += 64) {
+        const int32_t o = (int32_t)(pairs[p0 + t] >> 32);
+        oj[d0 + t] = make_int2(o, obs_pt[o]);
+    }
 }
 
 __global__ void k_fill_i64(int64_t *a, int64_t len, int64_t v) {
@@ -240,7 +277,10 @@ hipError_t launch_prepare(const stba_problem &p, int64_t np, const PrepBufs &b, 
     if (e != hipSuccess) return e;
     k_chunk_blk<<<grid_for(b.blk_cap), 256, 0, st>>>(b.n_blocks, b.blk_chunk_off, b.chunk_blk);
     k_total_chunks<<<1, 1, 0, st>>>(b.n_blocks, b.blk_chunk_off, b.n_chunks);
-    k_vjp_parts<<<1, 1024, 0, st>>>(p.m, b.diag_blk, b.blk_start, b.vjp_part_off, b.vjp_part_cam, b.vjp_part_cap);
+    k_vjp_parts<<<1, 1024, 0, st>>>(p.m, b.diag_blk, b.blk_start, b.vjp_part_off, b.vjp_part_cam, b.vjp_part_cap,
+                                    b.vjp_obs_off);
+    k_vjp_oj<<<grid_for(p.m, 4), 256, 0, st>>>(p.m, p.q, b.diag_blk, b.blk_start, b.pairs, p.obs_pt, b.vjp_obs_off,
+                                               b.vjp_oj);
     return hipGetLastError();
 }
 

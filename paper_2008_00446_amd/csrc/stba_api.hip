@@ -15,7 +15,8 @@ struct Layout {
     size_t status, lam2;
     // static plan (stba_prepare)
     size_t pt_off, pair_off, scratch_a, keys_in, keys_out, vals_in, pairs, blk_of, blk_key, blk_start, n_blocks,
-        diag_blk, blk_chunk_off, chunk_blk, n_chunks, part, vjp_part_off, vjp_part_cam, vjp_part_sum, tmp;
+        diag_blk, blk_chunk_off, chunk_blk, n_chunks, part, vjp_part_off, vjp_part_cam, vjp_part_sum, vjp_obs_off,
+        vjp_oj, tmp;
     int64_t blk_cap, chunk_cap, vjp_part_cap;
     size_t tmp_bytes;
     // per iteration
@@ -112,6 +113,8 @@ bool make_layout(const stba_problem *p, const stba_dims *d, int precision, Layou
     L.vjp_part_off = take(8 * (m + 1));
     L.vjp_part_cam = take(4 * (size_t)L.vjp_part_cap);
     L.vjp_part_sum = take(8 * 9 * (size_t)L.vjp_part_cap);
+    L.vjp_obs_off = take(8 * (m + 1));
+    L.vjp_oj = take(8 * q);
     L.tmp_bytes = prepare_tmp_bytes(d->n_pairs, p->m, 0);
     L.tmp = take(L.tmp_bytes);
     L.cl_n = take(4 * m);
@@ -237,6 +240,8 @@ VjpParts vjp_parts_of(const Layout &L, void *ws) {
     v.cam = at<int32_t>(ws, L.vjp_part_cam);
     v.cap = L.vjp_part_cap;
     v.sum = at<double>(ws, L.vjp_part_sum);
+    v.obs_off = at<int64_t>(ws, L.vjp_obs_off);
+    v.oj = at<int2>(ws, L.vjp_oj);
     return v;
 }
 
@@ -588,6 +593,8 @@ int stba_prepare(const stba_problem *p, const stba_dims *dims, int precision, vo
     b.vjp_part_off = at<int64_t>(ws, L.vjp_part_off);
     b.vjp_part_cam = at<int32_t>(ws, L.vjp_part_cam);
     b.vjp_part_cap = L.vjp_part_cap;
+    b.vjp_obs_off = at<int64_t>(ws, L.vjp_obs_off);
+    b.vjp_oj = at<int2>(ws, L.vjp_oj);
     b.tmp = at<void>(ws, L.tmp);
     b.tmp_bytes = L.tmp_bytes;
     STBA_HIP(launch_reset_status(at<int32_t>(ws, L.status), stream));
