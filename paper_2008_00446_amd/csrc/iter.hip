@@ -263,9 +263,11 @@ __global__ __launch_bounds__(256) void k_rj(int64_t q, const double *__restrict_
                                             const double *__restrict__ uv, T *__restrict__ f, T *__restrict__ Jc,
                                             T *__restrict__ Jp, double *__restrict__ partials,
                                             const int32_t *need_jac, int32_t *jac_ran, ZeroS z, double huber) {
+    // the blocks go out through LDS half a workgroup at a time (128
+    // observations, 24.6 KB in FP64), so that more workgroups fit on a CU
     __shared__ double sh[256];
-    __shared__ T sJc[256 * 18];
-    __shared__ T sJp[256 * 6];
+    __shared__ T sJc[128 * 18];
+    __shared__ T sJp[128 * 6];
     if (z.S != nullptr) {
         // S and b of this iteration start from zero (the grid runs even when the
         // Jacobian is kept)
@@ -278,6 +280,7 @@ __global__ __launch_bounds__(256) void k_rj(int64_t q, const double *__restrict_
     if (need_jac != nullptr && need_jac[0] == 0) return;
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double sq = 0.0;
+    T bc[18], bp[6];
     if (o < q) {
         const int32_t i = oc[o], j = op[o];
         double c[9], X[3];
@@ -293,26 +296,36 @@ __global__ __launch_bounds__(256) void k_rj(int64_t q, const double *__restrict_
         const double rw = huber_root_weight(s2, huber);   // 1 for the squared loss
         f[2 * o] = (T)(rw * f0);
         f[2 * o + 1] = (T)(rw * f1);
-        // the blocks go through LDS: the block's J_c and J_p are contiguous in
-        // memory, written back below with consecutive lanes on consecutive elements
-        const int tl = threadIdx.x;
 #pragma unroll
         for (int r = 0; r < 2; ++r)
 #pragma unroll
-            for (int k = 0; k < 9; ++k) sJc[18 * tl + 9 * r + k] = (T)(rw * jc[r][k]);
+            for (int k = 0; k < 9; ++k) bc[9 * r + k] = (T)(rw * jc[r][k]);
 #pragma unroll
         for (int r = 0; r < 2; ++r)
 #pragma unroll
-            for (int k = 0; k < 3; ++k) sJp[6 * tl + 3 * r + k] = (T)(rw * jp[r][k]);
+            for (int k = 0; k < 3; ++k) bp[3 * r + k] = (T)(rw * jp[r][k]);
     }
-    {
-        const int64_t ob = (int64_t)blockIdx.x * blockDim.x;
-        const int nv = (int)min((int64_t)blockDim.x, q - ob);   // observations of this block
+    // the block's J_c and J_p rows are contiguous in memory: each half is
+    // written back with consecutive lanes on consecutive elements
+    const int tl = threadIdx.x;
+    for (int h = 0; h < 2; ++h) {
+        const int lo = 128 * h;
+        if (o < q && tl >= lo && tl < lo + 128) {
+            const int u = tl - lo;
+#pragma unroll
+            for (int k = 0; k < 18; ++k) sJc[18 * u + k] = bc[k];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) sJp[6 * u + k] = bp[k];
+        }
+        const int64_t ob = (int64_t)blockIdx.x * blockDim.x + lo;
+        const int64_t left = q - ob;
+        const int nv = left <= 0 ? 0 : (int)min((int64_t)128, left);   // observations of this half
         __syncthreads();
         if (Jc != nullptr)
-            for (int i = threadIdx.x; i < 18 * nv; i += blockDim.x) Jc[18 * ob + i] = sJc[i];
+            for (int i = tl; i < 18 * nv; i += blockDim.x) Jc[18 * ob + i] = sJc[i];
         if (Jp != nullptr)
-            for (int i = threadIdx.x; i < 6 * nv; i += blockDim.x) Jp[6 * ob + i] = sJp[i];
+            for (int i = tl; i < 6 * nv; i += blockDim.x) Jp[6 * ob + i] = sJp[i];
+        __syncthreads();   // the next half reuses sJc, sJp
     }
     if (partials != nullptr) {
         const double s = block_sum_256(sq, sh);
