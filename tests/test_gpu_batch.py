@@ -196,3 +196,38 @@ def test_stored_jacobian_vjp_rejects_missing_blocks():
     gu = torch.empty((plan.q, 2), dtype=torch.float64, device="cuda")
     with pytest.raises(S.StbaError):
         S.stba_residual_vjp_stored(prob, plan.dims, S.STBA_FP64, v, None, None, gc, gp, gu, plan.ws)
+
+
+@pytest.mark.parametrize("precision,tol", [(S.STBA_FP64, 1e-12), (S.STBA_MIXED, 1e-5)], ids=["fp64", "fp32"])
+def test_camera_sums_at_the_part_boundaries(precision, tol):
+    """The camera sums of J^T v run over each camera's observations in parts
+    of at most 1792 (one wavefront each) added in part order: cameras of
+    exactly one part (1792), one past it (1793), exactly two parts (3584), a
+    small one (100) and one that sees nothing, each camera's gradient row
+    against the oracle's."""
+    rng = np.random.default_rng(5)
+    sizes = [1792, 1793, 3584, 100, 0]
+    m, n = len(sizes), max(sizes)
+    pt = np.column_stack([rng.uniform(-1, 1, n), rng.uniform(-1, 1, n), rng.uniform(6, 9, n)])
+    cam = np.zeros((m, 9))
+    cam[:, :3] = rng.normal(0, 0.02, (m, 3))
+    cam[:, 3:6] = rng.normal(0, 0.1, (m, 3))
+    cam[:, 6], cam[:, 7], cam[:, 8] = 500.0, 1e-3, -1e-4
+    # observations sorted by point, then camera: camera i sees points 0 .. sizes[i] - 1
+    pairs = sorted((j, i) for i, k in enumerate(sizes) for j in range(k))
+    op = np.array([j for j, _ in pairs], dtype=np.int32)
+    oc = np.array([i for _, i in pairs], dtype=np.int32)
+    uv = O.residuals(cam, pt, oc, op, np.zeros((len(op), 2))) + rng.normal(0, 1.0, (len(op), 2))
+    plan = S.ResidualPlan(oc, op, m, n, precision)
+    tc = dev(cam, torch.float64).requires_grad_(True)
+    tp = dev(pt, torch.float64).requires_grad_(True)
+    f = S.residuals(tc, tp, dev(uv, torch.float64), plan)
+    (f.double() ** 2).sum().backward()
+    gc = tc.grad.cpu().numpy()
+    rc, rp, _ = O.gradient(cam, pt, oc, op, uv)
+    for i, k in enumerate(sizes):
+        if k == 0:
+            assert np.all(gc[i] == 0.0)
+        else:
+            assert rel(gc[i], rc[i]) < tol, (i, k)
+    assert rel(tp.grad.cpu().numpy(), rp) < tol
