@@ -1322,6 +1322,38 @@ __device__ inline int64_t xcd_split_item(unsigned b, int w, int64_t count) {
     return (u < per && it < count) ? it : -1;
 }
 
+// Part `it` of the camera sums: its camera r, the pair range [p0, p1) of
+// camera r's diagonal block it covers (empty for a camera without one), and
+// the same entries' range [d0, d1) of the camera-major (observation, point)
+// list (at most q entries; with obs_off null, left empty).
+struct VjpPart {
+    int64_t r, p0, p1, d0, d1;
+    bool alone;   // the camera's only part
+};
+__device__ inline VjpPart vjp_part(int64_t it, const int64_t *part_off, const int32_t *part_cam,
+                                   const int64_t *diag_blk, const int64_t *blk_start, const int64_t *obs_off,
+                                   int64_t q_obs) {
+    VjpPart q;
+    q.r = part_cam[it];
+    const int64_t first = part_off[q.r];
+    q.alone = part_off[q.r + 1] - first == 1;
+    const int64_t kb = diag_blk[q.r];
+    q.p0 = q.p1 = q.d0 = q.d1 = 0;
+    if (kb >= 0) {
+        const int64_t end = blk_start[kb + 1];
+        q.p0 = blk_start[kb] + (it - first) * kVjpPart;
+        q.p1 = q.p0 + kVjpPart < end ? q.p0 + kVjpPart : end;
+        if (obs_off != nullptr) {
+            q.d0 = obs_off[q.r] + (q.p0 - blk_start[kb]);
+            q.d1 = q.d0 + (q.p1 - q.p0);
+            if (q.d1 > q_obs) q.d1 = q_obs;
+            if (q.d0 > q.d1) q.d0 = q.d1;
+        }
+    }
+    return q;
+}
+
+
 // ---------------------------------------------------------------------------
 // MIXED: the residual of one FP64 refinement step of every cluster solve
 // (Eq. 13), r = b - S x with the S and b of the FP64 method, taken from J
@@ -1526,37 +1558,88 @@ __global__ __launch_bounds__(64) void k_refine_pt(int32_t n, const int64_t *__re
 }
 
 // Part 2: r_i = sum_{o of camera i} J_c,o^T e_o - lambda diag(U_i) x_i, U_i =
-// sum J_c,o^T J_c,o; one wavefront per camera (XCD-contiguous) over the diagonal block's pair
-// list (every observation of the camera once), the camera's part of the
-// projection formed once per lane, then a fixed-order butterfly.
-__global__ __launch_bounds__(256) void k_refine_cam(int32_t m, const double *__restrict__ cam,
-                                                    const double *__restrict__ pt, const int32_t *__restrict__ op,
+// sum J_c,o^T J_c,o, over camera i's observations (its diagonal block's list)
+// in the parts of the J^T v camera sums: one wavefront per part, the parts
+// spread evenly over the XCDs, the camera's part of the projection formed
+// once per wavefront and kept in LDS, the camera-major (observation, point)
+// entries read two rounds ahead and the point, pixel and e gathers one round
+// ahead; a fixed-order butterfly per part, a camera of one part writes r_i,
+// the parts of the others are added in part order by k_refine_cam_sum.
+__device__ inline void refine_cam_round(const double cp[kCamPre], const double X[3], double u0, double u1, double e0,
+                                        double e1, double on, double huber, double (&acc)[9], double (&dg)[9]) {
+    // obs_fj64's operations on the gathered values
+    double pix[2], a[2][9], b[2][3];
+    project_jac_pre(cp, X, pix, a, b);
+    const double f0 = pix[0] - u0, f1 = pix[1] - u1;
+    const double rw = huber_root_weight(f0 * f0 + f1 * f1, huber);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const double j0 = rw * a[0][k], j1 = rw * a[1][k];
+        acc[k] += j0 * e0 + j1 * e1;
+        dg[k] += on * (j0 * j0 + j1 * j1);   // on = 0 for a lane past the part's end
+    }
+}
+
+struct RefineRound {
+    double X[3], u0, u1, e0, e1, on;
+};
+__device__ inline void refine_gather(int2 en, bool on, const double *__restrict__ pt, const double *__restrict__ uv,
+                                     const double *__restrict__ e, RefineRound &g) {
+    const int64_t o = en.x, j = en.y;
+    g.X[0] = pt[3 * j];
+    g.X[1] = pt[3 * j + 1];
+    g.X[2] = pt[3 * j + 2];
+    g.u0 = uv[2 * o];
+    g.u1 = uv[2 * o + 1];
+    g.e0 = on ? e[2 * o] : 0.0;   // a lane past the part's end adds zero
+    g.e1 = on ? e[2 * o + 1] : 0.0;
+    g.on = on ? 1.0 : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_refine_cam(int32_t m, int64_t q_obs, const int64_t *__restrict__ part_off,
+                                                    const int32_t *__restrict__ part_cam,
+                                                    const int64_t *__restrict__ obs_off, const int2 *__restrict__ oj,
+                                                    const double *__restrict__ cam, const double *__restrict__ pt,
                                                     const double *__restrict__ uv, double huber,
                                                     const int64_t *__restrict__ diag_blk,
-                                                    const int64_t *__restrict__ blk_start,
-                                                    const uint64_t *__restrict__ pairs,
-                                                    Damp dm, const double *__restrict__ dcam,
-                                                    const double *__restrict__ e, double *__restrict__ r) {
+                                                    const int64_t *__restrict__ blk_start, Damp dm,
+                                                    const double *__restrict__ dcam, const double *__restrict__ e,
+                                                    double *__restrict__ part_sum, double *__restrict__ r) {
+    __shared__ double cps[4][kCamPre];
     const int lane = threadIdx.x & 63;
-    const int64_t i = xcd_contiguous_item(blockIdx.x, gridDim.x, threadIdx.x >> 6);
-    if (i >= m) return;
+    const int64_t it = xcd_split_item(blockIdx.x, threadIdx.x >> 6, part_off[m]);
+    if (it < 0) return;
+    const VjpPart q = vjp_part(it, part_off, part_cam, diag_blk, blk_start, obs_off, q_obs);
     double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, dg[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    const int64_t kb = diag_blk[i];
-    if (kb >= 0) {
-        double c[9], cp[kCamPre];
+    if (q.d0 < q.d1) {
+        double *cp = cps[threadIdx.x >> 6];
+        {
+            double c[9], cr[kCamPre];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) c[k] = cam[9 * i + k];
-        camera_pre(c, cp);
-        for (int64_t p = blk_start[kb] + lane; p < blk_start[kb + 1]; p += 64) {
-            const int64_t o = (int64_t)(pairs[p] >> 32);
-            double f[2], jc[18], jp[6];
-            obs_fj64(cp, pt, uv, huber, op[o], o, f, jc, jp);
-            const double e0 = e[2 * o], e1 = e[2 * o + 1];
+            for (int k = 0; k < 9; ++k) c[k] = cam[9 * q.r + k];
+            camera_pre(c, cr);
+            if (lane == 0) {
 #pragma unroll
-            for (int k = 0; k < 9; ++k) {
-                acc[k] += jc[k] * e0 + jc[9 + k] * e1;
-                dg[k] += jc[k] * jc[k] + jc[9 + k] * jc[9 + k];
+                for (int k = 0; k < kCamPre; ++k) cp[k] = cr[k];
             }
+            __syncwarp();
+        }
+        const int rounds = (int)((q.d1 - q.d0 + 63) / 64);
+        auto entry = [&](int t) {
+            const int64_t d = q.d0 + 64 * (int64_t)t + lane;
+            return oj[d < q.d1 ? d : q.d0];
+        };
+        int2 e1 = rounds > 1 ? entry(1) : make_int2(0, 0);
+        RefineRound g;
+        refine_gather(entry(0), q.d0 + lane < q.d1, pt, uv, e, g);
+        for (int t = 0; t < rounds; ++t) {
+            int2 e2 = t + 2 < rounds ? entry(t + 2) : e1;
+            asm volatile("" ::: "memory");   // cp is read from LDS in this round
+            RefineRound gn = g;
+            if (t + 1 < rounds) refine_gather(e1, q.d0 + 64 * (int64_t)(t + 1) + lane < q.d1, pt, uv, e, gn);
+            refine_cam_round(cp, g.X, g.u0, g.u1, g.e0, g.e1, g.on, huber, acc, dg);
+            g = gn;
+            e1 = e2;
         }
     }
 #pragma unroll
@@ -1566,12 +1649,40 @@ __global__ __launch_bounds__(256) void k_refine_cam(int32_t m, const double *__r
             acc[k] += __shfl_xor(acc[k], d, 64);
             dg[k] += __shfl_xor(dg[k], d, 64);
         }
-    const double lam = dm.at_cam(i)[0];
-    double v = 0.0;
+    double va = 0.0, vg = 0.0;
 #pragma unroll
     for (int k = 0; k < 9; ++k)
-        if (lane == k) v = acc[k] - lam * dg[k] * dcam[9 * i + k];
-    if (lane < 9) r[9 * i + lane] = v;
+        if (lane == k) {
+            va = acc[k];
+            vg = dg[k];
+        }
+    if (lane < 9) {
+        if (q.alone) {
+            const double lam = dm.at_cam(q.r)[0];
+            r[9 * q.r + lane] = va - lam * vg * dcam[9 * q.r + lane];
+        } else {
+            part_sum[18 * it + lane] = va;
+            part_sum[18 * it + 9 + lane] = vg;
+        }
+    }
+}
+
+// r of the cameras cut in several parts: their sums in part order.
+__global__ __launch_bounds__(256) void k_refine_cam_sum(int32_t m, const int64_t *__restrict__ part_off,
+                                                        const double *__restrict__ part_sum, Damp dm,
+                                                        const double *__restrict__ dcam, double *__restrict__ r) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 9 * (int64_t)m) return;
+    const int64_t c = i / 9, k = i % 9;
+    const int64_t a = part_off[c], b = part_off[c + 1];
+    if (b - a < 2) return;
+    double sa = 0.0, sg = 0.0;
+    for (int64_t u = a; u < b; ++u) {
+        sa += part_sum[18 * u + k];
+        sg += part_sum[18 * u + 9 + k];
+    }
+    const double lam = dm.at_cam(c)[0];
+    r[i] = sa - lam * sg * dcam[i];
 }
 
 // a7: cost at the candidate x + dx in FP64 (block partial sums).
@@ -1675,37 +1786,6 @@ __global__ __launch_bounds__(256) void k_accept_update(const double *rj_partials
 // point; observed pixels: -v (its own pass: written from the point loops the
 // stores scatter and cost more than a second read of v).
 // ---------------------------------------------------------------------------
-
-// Part `it` of the camera sums: its camera r, the pair range [p0, p1) of
-// camera r's diagonal block it covers (empty for a camera without one), and
-// the same entries' range [d0, d1) of the camera-major (observation, point)
-// list (at most q entries; with obs_off null, left empty).
-struct VjpPart {
-    int64_t r, p0, p1, d0, d1;
-    bool alone;   // the camera's only part
-};
-__device__ inline VjpPart vjp_part(int64_t it, const int64_t *part_off, const int32_t *part_cam,
-                                   const int64_t *diag_blk, const int64_t *blk_start, const int64_t *obs_off,
-                                   int64_t q_obs) {
-    VjpPart q;
-    q.r = part_cam[it];
-    const int64_t first = part_off[q.r];
-    q.alone = part_off[q.r + 1] - first == 1;
-    const int64_t kb = diag_blk[q.r];
-    q.p0 = q.p1 = q.d0 = q.d1 = 0;
-    if (kb >= 0) {
-        const int64_t end = blk_start[kb + 1];
-        q.p0 = blk_start[kb] + (it - first) * kVjpPart;
-        q.p1 = q.p0 + kVjpPart < end ? q.p0 + kVjpPart : end;
-        if (obs_off != nullptr) {
-            q.d0 = obs_off[q.r] + (q.p0 - blk_start[kb]);
-            q.d1 = q.d0 + (q.p1 - q.p0);
-            if (q.d1 > q_obs) q.d1 = q_obs;
-            if (q.d0 > q.d1) q.d0 = q.d1;
-        }
-    }
-    return q;
-}
 
 // The wavefront's nine sums (every lane holds all of them after the
 // butterfly) to grad_cam, or to the part's slot of part_sum.
@@ -2064,7 +2144,7 @@ template hipError_t launch_backsub<float>(const stba_problem &, const int64_t *,
 hipError_t launch_refine_residual(const stba_problem &p, const int64_t *pt_off, const int32_t *seg_head,
                                   int32_t group_size, const int32_t *grp_first, const Damp &dm,
                                   const double *dcam, double *e, double *Vinv, double *wph, const int64_t *diag_blk,
-                                  const int64_t *blk_start, const uint64_t *pairs, double *r, hipStream_t st) {
+                                  const int64_t *blk_start, const VjpParts &parts, double *r, hipStream_t st) {
     if (group_size > 0) {
         const int64_t ng = (p.q + group_size - 1) / group_size;
         k_refine_obs<<<(unsigned)((ng + kPtWaves - 1) / kPtWaves), 64 * kPtWaves, 0, st>>>(
@@ -2076,8 +2156,10 @@ hipError_t launch_refine_residual(const stba_problem &p, const int64_t *pt_off, 
     }
     const hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    k_refine_cam<<<xcd_contiguous_grid(p.m), 256, 0, st>>>(p.m, p.cam, p.pt, p.obs_pt, p.obs_uv, p.huber, diag_blk,
-                                                           blk_start, pairs, dm, dcam, e, r);
+    k_refine_cam<<<xcd_contiguous_grid(parts.cap), 256, 0, st>>>(p.m, p.q, parts.off, parts.cam, parts.obs_off,
+                                                                    parts.oj, p.cam, p.pt, p.obs_uv, p.huber,
+                                                                    diag_blk, blk_start, dm, dcam, e, parts.sum, r);
+    k_refine_cam_sum<<<grid_for(9 * (int64_t)p.m), 256, 0, st>>>(p.m, parts.off, parts.sum, dm, dcam, r);
     return hipGetLastError();
 }
 

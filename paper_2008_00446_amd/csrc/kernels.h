@@ -155,6 +155,18 @@ hipError_t launch_chol(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, con
                        double *dcam, int32_t *cl_status, int32_t max_Np, int32_t *flags, double *yx,
                        const CholTeam *team, hipStream_t st);
 
+// The camera parts of stba_prepare (vjp_part_off, vjp_part_cam, part_cap of
+// them at most) and part_sum, 18 doubles per part (the camera sums of J^T v
+// use 9), for the cameras cut in several; the camera-major observation list.
+struct VjpParts {
+    const int64_t *off;
+    const int32_t *cam;
+    int64_t cap;
+    double *sum;
+    const int64_t *obs_off;   // [m + 1] first entry of each camera in oj
+    const int2 *oj;           // [q] (observation, point), camera-major in diagonal-block order
+};
+
 // MIXED refinement residual r = b - S x of the FP64 method's S and b, formed
 // from J recomputed in FP64 at x (never from the FP32-assembled S): e [2 q]
 // receives the linearised residuals, r [9 m] the residual in camera order;
@@ -162,7 +174,7 @@ hipError_t launch_chol(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, con
 hipError_t launch_refine_residual(const stba_problem &p, const int64_t *pt_off, const int32_t *seg_head,
                                   int32_t group_size, const int32_t *grp_first, const Damp &dm,
                                   const double *dcam, double *e, double *Vinv, double *wph, const int64_t *diag_blk,
-                                  const int64_t *blk_start, const uint64_t *pairs, double *r, hipStream_t st);
+                                  const int64_t *blk_start, const VjpParts &parts, double *r, hipStream_t st);
 // dcam += S^-1 r with the factors left in S by launch_chol (r in camera order)
 hipError_t launch_sweep(int32_t l, const int32_t *cl_n, const int32_t *cl_Np, const int64_t *S_off,
                         const int32_t *cl_start, const int32_t *cl_cams, const double *S, const double *r,
@@ -198,17 +210,6 @@ hipError_t launch_batch_accept(const stba_problem &p, int32_t n_prob, int32_t l,
                                int32_t *status, stba_lm_state *states, const double *dcam, const double *dpt,
                                hipStream_t st);
 
-// The camera parts of stba_prepare (vjp_part_off, vjp_part_cam, part_cap of
-// them at most) and part_sum, 9 doubles per part, for the cameras cut in
-// several.
-struct VjpParts {
-    const int64_t *off;
-    const int32_t *cam;
-    int64_t cap;
-    double *sum;
-    const int64_t *obs_off;   // [m + 1] first entry of each camera in oj
-    const int2 *oj;           // [q] (observation, point), camera-major in diagonal-block order
-};
 template <typename T>
 hipError_t launch_vjp(const stba_problem &p, const int64_t *pt_off, const int64_t *diag_blk,
                       const int64_t *blk_start, const uint64_t *pairs, const VjpParts &parts, const T *v,

@@ -112,7 +112,7 @@ bool make_layout(const stba_problem *p, const stba_dims *d, int precision, Layou
     L.vjp_part_cap = (int64_t)m + (int64_t)np / kVjpPart + 1;
     L.vjp_part_off = take(8 * (m + 1));
     L.vjp_part_cam = take(4 * (size_t)L.vjp_part_cap);
-    L.vjp_part_sum = take(8 * 9 * (size_t)L.vjp_part_cap);
+    L.vjp_part_sum = take(8 * 18 * (size_t)L.vjp_part_cap);
     L.vjp_obs_off = take(8 * (m + 1));
     L.vjp_oj = take(8 * q);
     L.tmp_bytes = prepare_tmp_bytes(d->n_pairs, p->m, 0);
@@ -276,7 +276,7 @@ int refine_solve(const stba_problem *p, int32_t l, const Damp &dm, double *dcam,
     STBA_HIP(launch_refine_residual(*p, at<int64_t>(ws, L.pt_off), at<int32_t>(ws, L.seg_head), L.group_size,
                                     at<int32_t>(ws, L.grp_first), dm, dcam, at<double>(ws, L.eref),
                                     at<double>(ws, L.Vinv), at<double>(ws, L.wph), at<int64_t>(ws, L.diag_blk),
-                                    at<int64_t>(ws, L.blk_start), at<uint64_t>(ws, L.pairs), r, st));
+                                    at<int64_t>(ws, L.blk_start), vjp_parts_of(L, ws), r, st));
     STBA_HIP(launch_sweep(l, at<int32_t>(ws, L.cl_n), at<int32_t>(ws, L.cl_Np), at<int64_t>(ws, L.S_off),
                           at<int32_t>(ws, L.cl_start), at<int32_t>(ws, L.cl_cams), at<double>(ws, L.S), r, dcam,
                           L.max_Np, st));
