@@ -369,9 +369,7 @@ __global__ __launch_bounds__(256) void k_resid_only(int64_t q, const double *__r
 // Fixed-order sum of per-block partials (one 256-thread block).
 __global__ __launch_bounds__(256) void k_sum_partials(const double *partials, int64_t count, double *out) {
     __shared__ double sh[256];
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < count; i += 256) s += partials[i];
-    s = block_sum_256(s, sh);
+    const double s = block_sum_256(strided_sum_256(partials, count), sh);
     if (threadIdx.x == 0) out[0] = s;
 }
 
@@ -888,7 +886,57 @@ template <typename T> struct SchurShape {
     // them repeat the last one into the pad)
     static constexpr int kDLoads = kNI;
     static constexpr int kDBytes = kDLoads * kBlk;
+    // FP64 batches use a layout of their own: the 12 parts a pair uses (J_c:
+    // parts 0..8 from the Jacobian; G, or M and r in a diagonal batch: parts
+    // 9..11 from the assembly record) of the 64 (32) records in 6 groups of
+    // two parts.  Group t
+    // holds parts 2t and 2t + 1 of every record, 32 bytes per record in record
+    // order, so in a load instruction (one group, one side) two consecutive
+    // lanes take one record and each lane keeps its record for all six groups:
+    // two record indices and a few address operations per lane and batch.
+    // Groups are kGS bytes apart (2 KB and one part): element k + 4 of a J_c
+    // row lies exactly one group after element k (two parts on), so the lanes
+    // of rows 4..8 read at a fixed distance from those of rows 0..4 and on
+    // other banks.
+    static constexpr int kGS = 2048 + 16;
+    static constexpr int kOff64Bytes = 5 * kGS + 2048;
+    // part of element k: J_c 0..8; G (18..23, off-diagonal batches) or M and r
+    // (24..28, diagonal batches) 9..11
+    __device__ static constexpr int part64(int k) { return k < 18 ? k / 2 : (k < 24 ? 9 + (k - 18) / 2 : 9 + (k - 24) / 2); }
+    __device__ static constexpr int off64(int k) {   // element k of a record, record 0
+        return (part64(k) / 2) * kGS + (part64(k) % 2) * 16 + (k % 2) * 8;
+    }
 };
+
+// One off-diagonal pair of a lane's batch slot: rows e0..e0 + 4 of
+// J_c,u^T (G_u G_w^T) J_c,w added to acc.  eu(k) / ew(k) read element k of
+// the u / w virtual record (G at 18..23), eue(k) element k of J_c,u moved on
+// to row e0.
+template <typename T, typename EU, typename EUE, typename EW>
+__device__ __forceinline__ void schur_pair(const EU &eu, const EUE &eue, const EW &ew, T (&acc)[5][9]) {
+    // m = G_u G_w^T (2 x 2)
+    T m[2][2];
+#pragma unroll
+    for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+        for (int b2 = 0; b2 < 2; ++b2)
+            m[a2][b2] = fma(eu(18 + 3 * a2 + 2), ew(18 + 3 * b2 + 2),
+                            fma(eu(18 + 3 * a2 + 1), ew(18 + 3 * b2 + 1), eu(18 + 3 * a2) * ew(18 + 3 * b2)));
+    // rows e of J_c,u^T m, then one column of J_c,w at a time
+    T p0[5], p1[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        const T je0 = eue(i), je1 = eue(9 + i);
+        p0[i] = fma(je1, m[1][0], je0 * m[0][0]);
+        p1[i] = fma(je1, m[1][1], je0 * m[0][1]);
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const T j0 = ew(k), j1 = ew(9 + k);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) acc[i][k] = fma(p1[i], j1, fma(p0[i], j0, acc[i][k]));
+    }
+}
 
 template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_schur(SchurChunks ch, const int2 *__restrict__ blk_key,
@@ -901,7 +949,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                                                const T *__restrict__ obsd, Damp dm,
                                                double *__restrict__ S, double *__restrict__ b) {
     using Sh = SchurShape<T>;
-    constexpr int kBuf = Sh::kDmaBytes > Sh::kDBytes ? Sh::kDmaBytes : Sh::kDBytes;
+    constexpr int kOffB = sizeof(T) == 8 ? Sh::kOff64Bytes : Sh::kDmaBytes;
+    constexpr int kBuf = kOffB > Sh::kDBytes ? kOffB : Sh::kDBytes;
     __shared__ int2 s_pairs[4][Sh::kStage];
     __shared__ __align__(16) char s_rec[4][kBuf];
     const int wv = threadIdx.x >> 6;
@@ -988,19 +1037,44 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                 // pairs (a, a): J_c^T M J_c, diag(J_c^T J_c), J_c^T r
                 const int dq = pl / Sh::kLanesRec, dp = min(pl % Sh::kLanesRec, Sh::kDiagParts - 1);
                 auto fetch = [&](int bt) {
-                    int64_t a[Sh::kDLoads];
+                    if constexpr (sizeof(T) == 8) {
+                        // the grouped layout, one side: J_c (parts 0..8), then M and r
+                        // (parts 3..5 of the assembly record) as parts 9..11; all slots of
+                        // sp hold pairs of this item
+                        int ln = pl;
+                        asm volatile("" : "+v"(ln));
+                        const int jh = ln & 1, jr = ln >> 1;
+                        const uint32_t o = (uint32_t)reinterpret_cast<const int *>(sp)[2 * (bt * 32 + jr)];
+                        const char *a = reinterpret_cast<const char *>(Jc) + (uint64_t)o * 144u + 16 * jh;
+                        const char *g = reinterpret_cast<const char *>(obsd) + (uint64_t)o * 96u;
 #pragma unroll
-                    for (int i = 0; i < Sh::kDLoads; ++i) a[i] = sp[min(bt * 32 + dq * Sh::kNI + i, npv - 1)].x;
-#pragma unroll
-                    for (int i = 0; i < Sh::kDLoads; ++i)
-                        __builtin_amdgcn_global_load_lds((const void *)Sh::src(Jc, obsd, a[i], dp),
-                                                         (void __attribute__((address_space(3))) *)(sb + i * Sh::kBlk),
+                        for (int t = 0; t < 4; ++t)
+                            __builtin_amdgcn_global_load_lds((const void *)(a + 32 * t),
+                                                             (void __attribute__((address_space(3))) *)(sb + t * Sh::kGS),
+                                                             16, 0, 0);
+                        __builtin_amdgcn_global_load_lds((const void *)(jh ? g + 48 : a + 128),
+                                                         (void __attribute__((address_space(3))) *)(sb + 4 * Sh::kGS),
                                                          16, 0, 0);
+                        __builtin_amdgcn_global_load_lds((const void *)(g + 64 + 16 * jh),
+                                                         (void __attribute__((address_space(3))) *)(sb + 5 * Sh::kGS),
+                                                         16, 0, 0);
+                    } else {
+                        int64_t a[Sh::kDLoads];
+#pragma unroll
+                        for (int i = 0; i < Sh::kDLoads; ++i) a[i] = sp[min(bt * 32 + dq * Sh::kNI + i, npv - 1)].x;
+#pragma unroll
+                        for (int i = 0; i < Sh::kDLoads; ++i)
+                            __builtin_amdgcn_global_load_lds((const void *)Sh::src(Jc, obsd, a[i], dp),
+                                                             (void __attribute__((address_space(3))) *)(sb + i * Sh::kBlk),
+                                                             16, 0, 0);
+                    }
                 };
-                const char *dd = sb + Sh::row_at(pl >> 1);
-                const char *de = dd + Sh::elem_at(e0);   // row e0 (e0 is a whole number of parts)
-                auto d = [&](int k) -> T { return *reinterpret_cast<const T *>(dd + Sh::elem_at(k)); };
-                auto dr = [&](int k) -> T { return *reinterpret_cast<const T *>(de + Sh::elem_at(k)); };
+                // element k of the lane's record, and of its J_c moved on to row e0
+                auto eoff = [](int k) { return sizeof(T) == 8 ? Sh::off64(k) : Sh::elem_at(k); };
+                const char *dd = sizeof(T) == 8 ? sb + 32 * (pl >> 1) : sb + Sh::row_at(pl >> 1);
+                const char *de = sizeof(T) == 8 ? dd + (e0 / 4) * Sh::kGS : dd + Sh::elem_at(e0);
+                auto d = [&](int k) -> T { return *reinterpret_cast<const T *>(dd + eoff(k)); };
+                auto dr = [&](int k) -> T { return *reinterpret_cast<const T *>(de + eoff(k)); };
                 for (int bt = 0; bt < nbat; ++bt) {
                     __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): the previous batch has been read
                     asm volatile("" ::: "memory");
@@ -1026,6 +1100,53 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                             for (int i = 0; i < 5; ++i) acc[i][k] = fma(p1[i], j1, fma(p0[i], j0, acc[i][k]));
                         }
                     }
+                }
+            } else if constexpr (sizeof(T) == 8) {
+                // off-diagonal pairs (u, w), FP64: S_rc -= J_c,u^T (G_u G_w^T) J_c,w as
+                // below, batches in the grouped layout.  Every slot of sp holds a pair
+                // of this item (the compaction writes all kStage of them), so the
+                // records of slots past npv are valid ones that no lane uses.
+                const int *spi = reinterpret_cast<const int *>(sp);
+                auto fetch = [&](int bt) {
+                    // lane (slot jr, part jh of each group); an opaque copy of the lane
+                    // index, so that nothing of it is held across batches
+                    int ln = pl;
+                    asm volatile("" : "+v"(ln));
+                    const int jh = ln & 1, jr = ln >> 1;
+                    uint32_t o[2];
+#pragma unroll
+                    for (int b2 = 0; b2 < 2; ++b2) o[b2] = (uint32_t)spi[2 * (bt * 32 + jr) + b2];
+#pragma unroll
+                    for (int b2 = 0; b2 < 2; ++b2) {
+                        const char *a = reinterpret_cast<const char *>(Jc) + (uint64_t)o[b2] * 144u + 16 * jh;
+                        const char *g = reinterpret_cast<const char *>(obsd) + (uint64_t)o[b2] * 96u;
+                        char *dst = sb + 1024 * b2;
+#pragma unroll
+                        for (int t = 0; t < 4; ++t)   // parts 0..7 of J_c
+                            __builtin_amdgcn_global_load_lds((const void *)(a + 32 * t),
+                                                             (void __attribute__((address_space(3))) *)(dst + t * Sh::kGS),
+                                                             16, 0, 0);
+                        // part 8 (the last of J_c) and part 9 (the first of G), then G's 10, 11
+                        __builtin_amdgcn_global_load_lds((const void *)(jh ? g : a + 128),
+                                                         (void __attribute__((address_space(3))) *)(dst + 4 * Sh::kGS),
+                                                         16, 0, 0);
+                        __builtin_amdgcn_global_load_lds((const void *)(g + 16 + 16 * jh),
+                                                         (void __attribute__((address_space(3))) *)(dst + 5 * Sh::kGS),
+                                                         16, 0, 0);
+                    }
+                };
+                const char *ju = sb + 32 * (pl >> 1), *jw = sb + 32 * (32 + (pl >> 1));
+                const char *jue = ju + (e0 / 4) * Sh::kGS;   // rows e0.. of J_c,u: 4 elements on
+                auto eu = [&](int k) -> T { return *reinterpret_cast<const T *>(ju + Sh::off64(k)); };
+                auto eue = [&](int k) -> T { return *reinterpret_cast<const T *>(jue + Sh::off64(k)); };
+                auto ew = [&](int k) -> T { return *reinterpret_cast<const T *>(jw + Sh::off64(k)); };
+                for (int bt = 0; bt < nbat; ++bt) {
+                    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): the previous batch has been read
+                    asm volatile("" ::: "memory");
+                    fetch(bt);
+                    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the batch is in LDS
+                    asm volatile("" ::"v"(sb) : "memory");
+                    if (bt * 32 + slot < npv) schur_pair(eu, eue, ew, acc);
                 }
             } else {
                 // off-diagonal pairs (u, w): S_rc -= Y_u Y_w^T = J_c,u^T (G_u G_w^T) J_c,w.
@@ -1061,31 +1182,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                     fetch(bt);
                     __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the batch is in LDS
                     asm volatile("" ::"v"(sb) : "memory");
-                    if (bt * 32 + slot < npv) {
-                        // m = G_u G_w^T (2 x 2)
-                        T m[2][2];
-#pragma unroll
-                        for (int a2 = 0; a2 < 2; ++a2)
-#pragma unroll
-                            for (int b2 = 0; b2 < 2; ++b2)
-                                m[a2][b2] = fma(eu(18 + 3 * a2 + 2), ew(18 + 3 * b2 + 2),
-                                                fma(eu(18 + 3 * a2 + 1), ew(18 + 3 * b2 + 1),
-                                                    eu(18 + 3 * a2) * ew(18 + 3 * b2)));
-                        // rows e of J_c,u^T m, then one column of J_c,w at a time
-                        T p0[5], p1[5];
-#pragma unroll
-                        for (int i = 0; i < 5; ++i) {
-                            const T je0 = eue(i), je1 = eue(9 + i);
-                            p0[i] = fma(je1, m[1][0], je0 * m[0][0]);
-                            p1[i] = fma(je1, m[1][1], je0 * m[0][1]);
-                        }
-#pragma unroll
-                        for (int k = 0; k < 9; ++k) {
-                            const T j0 = ew(k), j1 = ew(9 + k);
-#pragma unroll
-                            for (int i = 0; i < 5; ++i) acc[i][k] = fma(p1[i], j1, fma(p0[i], j0, acc[i][k]));
-                        }
-                    }
+                    if (bt * 32 + slot < npv) schur_pair(eu, eue, ew, acc);
                 }
             }
         }
@@ -1732,8 +1829,7 @@ __global__ __launch_bounds__(256) void k_accept_update(const double *rj_partials
     __shared__ int bad_pd, bad_hip;
     if (threadIdx.x == 0) bad_pd = bad_hip = 0;
     __syncthreads();
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < count; i += 256) s += partials[i];
+    double s = strided_sum_256(partials, count);
     for (int k = threadIdx.x; k < l; k += 256) {
         const int32_t c = cl_status[k];
         if (c == STBA_EHIP) bad_hip = 1;       // a factorisation wait timed out
@@ -1744,9 +1840,7 @@ __global__ __launch_bounds__(256) void k_accept_update(const double *rj_partials
     const bool have_F = F_ref[1] != 0.0;
     double F0 = F_ref[0];
     if (!have_F) {
-        double s0 = 0.0;
-        for (int64_t i = threadIdx.x; i < count; i += 256) s0 += rj_partials[i];
-        F0 = block_sum_256(s0, sh);
+        F0 = block_sum_256(strided_sum_256(rj_partials, count), sh);
     }
     const int32_t sticky = bad_hip ? STBA_EHIP : status[kStSticky];
     const bool pd = !bad_pd && status[kStPointBad] == 0;
@@ -1768,11 +1862,30 @@ __global__ __launch_bounds__(256) void k_accept_update(const double *rj_partials
         if (st->status == 0 && sticky != 0) st->status = sticky;
     }
     if (!acc) return;
+    // x += dx, four elements per thread and round with all their loads issued
+    // before any store
     const int64_t nc = 9 * (int64_t)m, total = nc + 3 * (int64_t)n;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
-        if (i < nc) cam[i] += dcam[i];
-        else pt[i - nc] += dpt[i - nc];
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < total; i0 += 4 * stride) {
+        double xv[4], dv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t i = i0 + u * stride;
+            xv[u] = dv[u] = 0.0;
+            if (i < nc) {
+                xv[u] = cam[i];
+                dv[u] = dcam[i];
+            } else if (i < total) {
+                xv[u] = pt[i - nc];
+                dv[u] = dpt[i - nc];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t i = i0 + u * stride;
+            if (i < nc) cam[i] = xv[u] + dv[u];
+            else if (i < total) pt[i - nc] = xv[u] + dv[u];
+        }
     }
 }
 
@@ -2174,9 +2287,10 @@ hipError_t launch_accept_update(const stba_problem &p, const double *rj_partials
                                 int64_t count, const double *F_ref, const int32_t *cl_status, int32_t l,
                                 const int32_t *status, stba_lm_state *s, const double *dcam, const double *dpt,
                                 hipStream_t st) {
-    // few blocks: each one re-sums the candidate partials before its share of x += dx
+    // one block per CU at most: each one re-sums the candidate partials before
+    // its share of x += dx
     unsigned blocks = grid_for(9 * (int64_t)p.m + 3 * (int64_t)p.n);
-    if (blocks > 128) blocks = 128;
+    if (blocks > 256) blocks = 256;
     if (blocks < 1) blocks = 1;
     k_accept_update<<<blocks, 256, 0, st>>>(rj_partials, partials, count, F_ref, cl_status, l, status, s, p.m, p.n,
                                             p.cam, p.pt, dcam, dpt);
