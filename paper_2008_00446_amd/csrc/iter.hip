@@ -724,12 +724,24 @@ __global__ __launch_bounds__(64 * kPtWaves) void k_points_obs(
     c[8] = -(jp[2] * f0 + jp[5] * f1);
 #pragma unroll
     for (int k = 0; k < 9; ++k) sV[wv][k][lane] = act ? c[k] : 0.0;
-    // chain predecessor: nearest earlier lane of the same point in the same cluster
+    // chain predecessor: nearest earlier lane of the same point in the same
+    // cluster; the search ends as soon as no lane has one left to look at (the
+    // longest track of the group, not 63 steps), four distances per round with
+    // their exchanges in flight together
     int pred = -1;
-    for (int d = 1; d < 64; ++d) {
-        const int src = lane - d;
-        const int32_t cl_o = __shfl(cl, src < 0 ? 0 : src, 64);
-        if (pred < 0 && src >= first && cl_o == cl) pred = src;
+    for (int d0 = 1; d0 < 64; d0 += 4) {
+        int32_t clo[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int src = lane - d0 - u;
+            clo[u] = __shfl(cl, src < 0 ? 0 : src, 64);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int src = lane - d0 - u;
+            if (pred < 0 && src >= first && clo[u] == cl) pred = src;
+        }
+        if (__ballot(pred < 0 && lane - d0 - 4 >= first) == 0) break;
     }
     int head = lane;
     if (act && pred >= 0 && keep_link(seed, t, (uint64_t)j, (uint64_t)cam, thr)) head = pred;
