@@ -321,10 +321,24 @@ __global__ __launch_bounds__(256) void k_rj(int64_t q, const double *__restrict_
         const int64_t left = q - ob;
         const int nv = left <= 0 ? 0 : (int)min((int64_t)128, left);   // observations of this half
         __syncthreads();
-        if (Jc != nullptr)
-            for (int i = tl; i < 18 * nv; i += blockDim.x) Jc[18 * ob + i] = sJc[i];
-        if (Jp != nullptr)
-            for (int i = tl; i < 6 * nv; i += blockDim.x) Jp[6 * ob + i] = sJp[i];
+        // every LDS read of the half first, then the stores (256 threads: at
+        // most 9 elements of J_c and 3 of J_p each)
+        if (Jc != nullptr) {
+            T v[9];
+#pragma unroll
+            for (int u = 0; u < 9; ++u) v[u] = tl + 256 * u < 18 * nv ? sJc[tl + 256 * u] : (T)0;
+#pragma unroll
+            for (int u = 0; u < 9; ++u)
+                if (tl + 256 * u < 18 * nv) Jc[18 * ob + tl + 256 * u] = v[u];
+        }
+        if (Jp != nullptr) {
+            T v[3];
+#pragma unroll
+            for (int u = 0; u < 3; ++u) v[u] = tl + 256 * u < 6 * nv ? sJp[tl + 256 * u] : (T)0;
+#pragma unroll
+            for (int u = 0; u < 3; ++u)
+                if (tl + 256 * u < 6 * nv) Jp[6 * ob + tl + 256 * u] = v[u];
+        }
         __syncthreads();   // the next half reuses sJc, sJp
     }
     if (partials != nullptr) {
