@@ -1410,6 +1410,8 @@ __global__ __launch_bounds__(64 * kPtWaves) void k_backsub_obs(int64_t ngroups, 
     const uint64_t after = starts & (lane == 63 ? 0ull : ~((2ull << lane) - 1));
     const int last = after != 0 ? __builtin_ctzll(after) : cnt;
     double gv[3] = {wph[3 * (int64_t)j], wph[3 * (int64_t)j + 1], wph[3 * (int64_t)j + 2]};
+    // (unrolled: reads in flight together, subtractions in order)
+#pragma unroll 4
     for (int b = lane; b < last; ++b)
 #pragma unroll
         for (int k = 0; k < 3; ++k) gv[k] -= sT[wv][k][b];
