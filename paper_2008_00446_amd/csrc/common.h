@@ -15,8 +15,8 @@ constexpr int kNB = 32;            // Cholesky tile order (FP64)
 // W V*^-1 W'^T = J_c^T (G G'^T) J_c'.  FP64: [G M r pad] (12 doubles), the
 // assembly reading J_c from the Jacobian itself; FP32: [J_c G M r pad] (32
 // floats), J_c copied in (FP32 J_c rows are only 8-byte aligned).
-template <typename T> constexpr int obs_rec_elems() { return sizeof(T) == 8 ? 12 : 32; }
-inline size_t obs_rec_bytes(bool fp64) { return fp64 ? 12 * 8 : 32 * 4; }
+template <typename T> constexpr int obs_rec_elems() { return sizeof(T) == 8 ? 16 : 32; }
+inline size_t obs_rec_bytes(bool fp64) { return fp64 ? 16 * 8 : 32 * 4; }
 constexpr int kSegRec = 16;        // per-segment record at the head observation: R^-1 (6), V*^-1 (6), V*^-1 w' (3)
 constexpr int kSchurChunk = 512;   // observation pairs per Schur work item (16 rounds of 32 pair slots)
 constexpr int kSchurPart = 100;    // doubles per partial sum: 81 block entries, 9 diag(U), 9 rhs, pad

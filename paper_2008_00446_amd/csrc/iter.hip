@@ -601,12 +601,16 @@ __global__ __launch_bounds__(64) void k_points(int32_t n, const int64_t *__restr
 
 // The assembly record of observation a (layout at obs_rec_elems): G = J_p R^-1
 // with R^-1 = I (upper, I00 I01 I02 I11 I12 I22), M = I - J_p V*^-1 J_p^T and
-// r = f + J_p u, u = V*^-1 w'; jc is read only for FP32.
+// r = f + J_p u, u = V*^-1 w'; jc is read only for FP32.  FP64: G (0..5), pad,
+// M (8..10), r (11, 12), pad, 128 bytes; FP32: J_c (0..17), G, M, r, pad.
 template <typename T>
 __device__ inline void write_obs_rec(T *__restrict__ obsd, int64_t a, const double jc[18], const double jp[6],
                                      const Chol3 &c, const double Vi[6], const double u[3], double f0, double f1) {
     T *rec = obsd + (int64_t)obs_rec_elems<T>() * a;
     constexpr int kG = sizeof(T) == 8 ? 0 : 18;   // where G starts
+    // where M and r start: in FP64 at the record's second 64 bytes, so that the
+    // assembly's reads of G and of M, r each touch one 64-byte segment
+    constexpr int kM = sizeof(T) == 8 ? 8 : kG + 6;
     if (sizeof(T) != 8) {
 #pragma unroll
         for (int k = 0; k < 18; ++k) rec[k] = (T)jc[k];
@@ -622,13 +626,15 @@ __device__ inline void write_obs_rec(T *__restrict__ obsd, int64_t a, const doub
     const double r0v[3] = {jp[0], jp[1], jp[2]}, r1v[3] = {jp[3], jp[4], jp[5]};
     sym3_mul(Vi, r0v, G0);
     sym3_mul(Vi, r1v, G1);
-    rec[kG + 6] = (T)(1.0 - (G0[0] * jp[0] + G0[1] * jp[1] + G0[2] * jp[2]));
-    rec[kG + 7] = (T)(-(G0[0] * jp[3] + G0[1] * jp[4] + G0[2] * jp[5]));
-    rec[kG + 8] = (T)(1.0 - (G1[0] * jp[3] + G1[1] * jp[4] + G1[2] * jp[5]));
-    rec[kG + 9] = (T)(f0 + jp[0] * u[0] + jp[1] * u[1] + jp[2] * u[2]);
-    rec[kG + 10] = (T)(f1 + jp[3] * u[0] + jp[4] * u[1] + jp[5] * u[2]);
+    rec[kM + 0] = (T)(1.0 - (G0[0] * jp[0] + G0[1] * jp[1] + G0[2] * jp[2]));
+    rec[kM + 1] = (T)(-(G0[0] * jp[3] + G0[1] * jp[4] + G0[2] * jp[5]));
+    rec[kM + 2] = (T)(1.0 - (G1[0] * jp[3] + G1[1] * jp[4] + G1[2] * jp[5]));
+    rec[kM + 3] = (T)(f0 + jp[0] * u[0] + jp[1] * u[1] + jp[2] * u[2]);
+    rec[kM + 4] = (T)(f1 + jp[3] * u[0] + jp[4] * u[1] + jp[5] * u[2]);
 #pragma unroll
-    for (int k = kG + 11; k < obs_rec_elems<T>(); ++k) rec[k] = (T)0;
+    for (int k = kG + 6; k < kM; ++k) rec[k] = (T)0;
+#pragma unroll
+    for (int k = kM + 5; k < obs_rec_elems<T>(); ++k) rec[k] = (T)0;
 }
 
 // Per observation of segment s, the assembly record (see write_obs_rec) from
@@ -681,10 +687,15 @@ __global__ __launch_bounds__(64 * kPtWaves) void k_points_obs(
     const T *__restrict__ f, const T *__restrict__ Jc, const T *__restrict__ Jp, Damp dm,
     uint64_t seed, uint64_t t, uint64_t thr, int32_t *__restrict__ seg_head, T *__restrict__ obsd,
     double *__restrict__ Vinv, double *__restrict__ wph, int32_t *status) {
-    __shared__ double sV[kPtWaves][9][64];   // J_p^T J_p (6) and -J_p^T f (3) of each lane
+    // per wavefront: J_p^T J_p (6) and -J_p^T f (3) of each lane, later the
+    // wavefront's assembly records on their way out
+    constexpr int kRecB = 64 * obs_rec_elems<T>() * (int)sizeof(T);
+    constexpr int kBufB = kRecB > 9 * 64 * 8 ? kRecB : 9 * 64 * 8;
+    __shared__ __align__(16) char sBuf[kPtWaves][kBufB];
     __shared__ int32_t sHead[kPtWaves][64];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
+    double(&sVw)[9][64] = *reinterpret_cast<double(*)[9][64]>(sBuf[wv]);
     const int64_t g = (int64_t)blockIdx.x * kPtWaves + wv;
     if (g >= ngroups) return;
     // every window of G observations inside [0, q) holds a point start (G > max_track);
@@ -737,7 +748,7 @@ __global__ __launch_bounds__(64 * kPtWaves) void k_points_obs(
     c[7] = -(jp[1] * f0 + jp[4] * f1);
     c[8] = -(jp[2] * f0 + jp[5] * f1);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) sV[wv][k][lane] = act ? c[k] : 0.0;
+    for (int k = 0; k < 9; ++k) sVw[k][lane] = act ? c[k] : 0.0;
     // chain predecessor: nearest earlier lane of the same point in the same
     // cluster; the search ends as soon as no lane has one left to look at (the
     // longest track of the group, not 63 steps), four distances per round with
@@ -770,45 +781,54 @@ __global__ __launch_bounds__(64 * kPtWaves) void k_points_obs(
         const bool mine = sHead[wv][b] == head;
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            const double x = sV[wv][k][b];
+            const double x = sVw[k][b];
             V[k] += x;
             if (mine) Vs[k] += x;
         }
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const double x = sV[wv][6 + k][b];
+            const double x = sVw[6 + k][b];
             w[k] += x;
             if (mine) ws[k] += x;
         }
     }
-    if (!act) return;
+    __syncwarp();   // every read of sVw is done before the records overwrite it
     bool ok = true;
-    if (lane == first) {
-        double Vd[6] = {V[0] * (1.0 + lam), V[1], V[2], V[3] * (1.0 + lam), V[4], V[5] * (1.0 + lam)};
-        const Chol3 cj = chol3(Vd);
-        ok &= cj.ok;
-        double Vi[6];
-        chol3_inverse(cj, Vi);
+    if (act) {
+        if (lane == first) {
+            double Vd[6] = {V[0] * (1.0 + lam), V[1], V[2], V[3] * (1.0 + lam), V[4], V[5] * (1.0 + lam)};
+            const Chol3 cj = chol3(Vd);
+            ok &= cj.ok;
+            double Vi[6];
+            chol3_inverse(cj, Vi);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) Vinv[6 * (int64_t)j + k] = Vi[k];
+            for (int k = 0; k < 6; ++k) Vinv[6 * (int64_t)j + k] = Vi[k];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) wph[3 * (int64_t)j + k] = w[k];
+            for (int k = 0; k < 3; ++k) wph[3 * (int64_t)j + k] = w[k];
+        }
+        if (corr) {
+            // g'_s = h_s (sum_s g_s) / (sum_s h_s), h_s = (1 + lambda) diag(V_s);
+            // sum_s g_s = w_j and sum_s diag(V_s) = diag(V_j)
+            ws[0] = Vs[0] * w[0] / V[0];
+            ws[1] = Vs[3] * w[1] / V[3];
+            ws[2] = Vs[5] * w[2] / V[5];
+        }
+        const double Vd[6] = {Vs[0] * (1.0 + lam), Vs[1], Vs[2], Vs[3] * (1.0 + lam), Vs[4], Vs[5] * (1.0 + lam)};
+        const Chol3 cs = chol3(Vd);
+        ok &= cs.ok;
+        double Vi[6], u[3];
+        chol3_inverse(cs, Vi);
+        sym3_mul(Vi, ws, u);   // V*_s^-1 w'_s
+        seg_head[a] = (int32_t)(o0 + head);
+        write_obs_rec<T>(reinterpret_cast<T *>(sBuf[wv]), lane, jc, jp, cs, Vi, u, f0, f1);
     }
-    if (corr) {
-        // g'_s = h_s (sum_s g_s) / (sum_s h_s), h_s = (1 + lambda) diag(V_s);
-        // sum_s g_s = w_j and sum_s diag(V_s) = diag(V_j)
-        ws[0] = Vs[0] * w[0] / V[0];
-        ws[1] = Vs[3] * w[1] / V[3];
-        ws[2] = Vs[5] * w[2] / V[5];
-    }
-    const double Vd[6] = {Vs[0] * (1.0 + lam), Vs[1], Vs[2], Vs[3] * (1.0 + lam), Vs[4], Vs[5] * (1.0 + lam)};
-    const Chol3 cs = chol3(Vd);
-    ok &= cs.ok;
-    double Vi[6], u[3];
-    chol3_inverse(cs, Vi);
-    sym3_mul(Vi, ws, u);   // V*_s^-1 w'_s
-    seg_head[a] = (int32_t)(o0 + head);
-    write_obs_rec<T>(obsd, a, jc, jp, cs, Vi, u, f0, f1);
+    __syncwarp();
+    // the group's records are contiguous in memory: consecutive lanes store
+    // consecutive elements
+    constexpr int E = obs_rec_elems<T>();
+    const T *srec = reinterpret_cast<const T *>(sBuf[wv]);
+#pragma unroll 4
+    for (int i = lane; i < cnt * E; i += 64) obsd[o0 * E + i] = srec[i];
     if (!ok) set_status(status + kStPointBad, STBA_ENOTPD);
 }
 
@@ -885,10 +905,10 @@ template <typename T> struct SchurShape {
     static constexpr int kOffParts = 24 / kPart;             // parts of J_c and G (an off-diagonal pair's use)
     static constexpr int kDiagParts = 28 / kPart + 1;        // parts up to r (a diagonal pair's use)
     static constexpr int kStage = 256;                       // pairs compacted at a time
-    // part p of observation o's virtual record
-    __device__ static const T *src(const T *Jc, const T *obsd, int64_t o, int p) {
-        if (sizeof(T) == 8)
-            return p < 9 ? Jc + 18 * o + 2 * p : obsd + (int64_t)obs_rec_elems<T>() * o + 2 * (p - 9);
+    // part p of observation o's virtual record (FP32: the assembly record is
+    // the virtual record; FP64 batches use the grouped layout below)
+    __device__ static const T *src(const T *, const T *obsd, int64_t o, int p) {
+        static_assert(sizeof(T) == 4, "FP64 batches are staged in the grouped layout");
         return obsd + (int64_t)obs_rec_elems<T>() * o + kPart * p;
     }
     // Batches: the 32 u records (side 0), then the 32 w (side 1) of an
@@ -1065,23 +1085,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                 auto fetch = [&](int bt) {
                     if constexpr (sizeof(T) == 8) {
                         // the grouped layout, one side: J_c (parts 0..8), then M and r
-                        // (parts 3..5 of the assembly record) as parts 9..11; all slots of
+                        // (parts 4..6 of the assembly record) as parts 9..11; all slots of
                         // sp hold pairs of this item
                         int ln = pl;
                         asm volatile("" : "+v"(ln));
                         const int jh = ln & 1, jr = ln >> 1;
                         const uint32_t o = (uint32_t)reinterpret_cast<const int *>(sp)[2 * (bt * 32 + jr)];
                         const char *a = reinterpret_cast<const char *>(Jc) + (uint64_t)o * 144u + 16 * jh;
-                        const char *g = reinterpret_cast<const char *>(obsd) + (uint64_t)o * 96u;
+                        const char *g = reinterpret_cast<const char *>(obsd) + (uint64_t)o * 128u;
 #pragma unroll
                         for (int t = 0; t < 4; ++t)
                             __builtin_amdgcn_global_load_lds((const void *)(a + 32 * t),
                                                              (void __attribute__((address_space(3))) *)(sb + t * Sh::kGS),
                                                              16, 0, 0);
-                        __builtin_amdgcn_global_load_lds((const void *)(jh ? g + 48 : a + 128),
+                        __builtin_amdgcn_global_load_lds((const void *)(jh ? g + 64 : a + 128),
                                                          (void __attribute__((address_space(3))) *)(sb + 4 * Sh::kGS),
                                                          16, 0, 0);
-                        __builtin_amdgcn_global_load_lds((const void *)(g + 64 + 16 * jh),
+                        __builtin_amdgcn_global_load_lds((const void *)(g + 80 + 16 * jh),
                                                          (void __attribute__((address_space(3))) *)(sb + 5 * Sh::kGS),
                                                          16, 0, 0);
                     } else {
@@ -1145,7 +1165,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
                     for (int b2 = 0; b2 < 2; ++b2) {
                         const char *a = reinterpret_cast<const char *>(Jc) + (uint64_t)o[b2] * 144u + 16 * jh;
-                        const char *g = reinterpret_cast<const char *>(obsd) + (uint64_t)o[b2] * 96u;
+                        const char *g = reinterpret_cast<const char *>(obsd) + (uint64_t)o[b2] * 128u;
                         char *dst = sb + 1024 * b2;
 #pragma unroll
                         for (int t = 0; t < 4; ++t)   // parts 0..7 of J_c
