@@ -12,9 +12,10 @@ constexpr int kNB = 32;            // Cholesky tile order (FP64)
 // Per-observation record written by the point kernel for the Schur assembly:
 // G = J_p R_s^-1 (2x3 row-major, R_s^T R_s = V*_s), M = I - J_p V*_s^-1 J_p^T
 // (m00 m01 m11), r = f + J_p V*_s^-1 w'_s (2), so that Y = J_c^T G and
-// W V*^-1 W'^T = J_c^T (G G'^T) J_c'.  FP64: [G M r pad] (12 doubles), the
-// assembly reading J_c from the Jacobian itself; FP32: [J_c G M r pad] (32
-// floats), J_c copied in (FP32 J_c rows are only 8-byte aligned).
+// W V*^-1 W'^T = J_c^T (G G'^T) J_c'.  FP64: [G pad M r pad] (16 doubles: G
+// in the first 64 bytes, M and r in the second), the assembly reading J_c from
+// the Jacobian itself; FP32: [J_c G M r pad] (32 floats), J_c copied in (FP32
+// J_c rows are only 8-byte aligned).
 template <typename T> constexpr int obs_rec_elems() { return sizeof(T) == 8 ? 16 : 32; }
 inline size_t obs_rec_bytes(bool fp64) { return fp64 ? 16 * 8 : 32 * 4; }
 constexpr int kSegRec = 16;        // per-segment record at the head observation: R^-1 (6), V*^-1 (6), V*^-1 w' (3)
